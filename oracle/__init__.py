@@ -1,0 +1,231 @@
+"""FP64 CPU oracle of the NEP-PIMD hot path (ctypes wrapper over plain C).
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, `__graft_entry__.smoke()` and the
+CPU-baseline leg of `bench.py` may import this package.  The product path
+(the HIP library and its Python binding) never imports, links or runs it, and
+the oracle shares no code with it.
+
+Functions follow paper Sec. II.A (ring polymer, normal modes, Cayley step,
+Langevin thermostat, forces and virial) and Sec. II.C (NEP site energies);
+the C sources state each formula and every reading taken where the paper is
+silent.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_SRC = [os.path.join(_HERE, f) for f in ("nep_oracle.c", "pimd_oracle.c")]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP64, no FMA contraction, OpenMP)."""
+    if (not force and os.path.exists(_SO) and
+            all(os.path.getmtime(_SO) >= os.path.getmtime(s) for s in _SRC)):
+        return _SO
+    tmp = _SO + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-D_DEFAULT_SOURCE", "-o", tmp] + _SRC + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_SO)
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int)
+        vp = C.c_void_p
+        L.or_model_load.argtypes = [C.c_char_p, C.POINTER(vp)]
+        L.or_model_free.argtypes = [vp]
+        L.or_model_dims.argtypes = [vp, ip, dp]
+        L.or_neighbors.argtypes = [dp, C.c_int, dp, C.c_double, C.c_int, ip, ip]
+        L.or_neighbors.restype = C.c_int
+        L.or_nep_config.argtypes = [vp, dp, ip, C.c_int, dp, C.c_int, dp, dp, dp, dp, dp, dp]
+        L.or_nep_beads.argtypes = [vp, dp, ip, C.c_int, C.c_int, dp, C.c_int, dp, dp, dp, dp, dp]
+        L.or_num_threads.restype = C.c_int
+        u32p = C.POINTER(C.c_uint32)
+        u64p = C.POINTER(C.c_uint64)
+        L.or_philox4x32.argtypes = [u32p, u32p, u32p]
+        L.or_philox4x64.argtypes = [u64p, u64p, u64p]
+        L.or_normals.argtypes = [C.c_uint64, C.c_int64, C.c_int, C.c_int, C.c_int, dp]
+        L.or_nm_matrix.argtypes = [C.c_int, dp]
+        L.or_nm_freqs.argtypes = [C.c_int, C.c_double, dp]
+        L.or_nm_transform.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp]
+        L.or_trpmd_stage.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                                     C.c_uint64, dp, dp, dp, dp, C.c_int64, C.c_int]
+        L.or_cayley_coeffs.argtypes = [C.c_int, C.c_double, C.c_double, dp]
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _i(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def num_threads() -> int:
+    return lib().or_num_threads()
+
+
+# ---------------------------------------------------------------- NEP ---
+
+class Model:
+    """A NEP model file loaded into the oracle."""
+
+    def __init__(self, path: str):
+        self._h = C.c_void_p()
+        rc = lib().or_model_load(path.encode(), C.byref(self._h))
+        if rc:
+            raise ValueError(f"oracle: cannot load model file {path} (code {rc})")
+        dims = np.zeros(9, np.int32)
+        rcs = np.zeros(2)
+        lib().or_model_dims(self._h, _i(dims), _d(rcs))
+        (self.S, self.n_radial, self.n_angular, self.k_radial, self.k_angular,
+         self.l_max, self.four_body, self.hidden, self.dim) = [int(x) for x in dims]
+        self.rc_radial, self.rc_angular = float(rcs[0]), float(rcs[1])
+
+    def __del__(self):
+        if getattr(self, "_h", None) and lib is not None:
+            try:
+                lib().or_model_free(self._h)
+            except Exception:
+                pass
+            self._h = None
+
+    def config(self, pos, types, box, cap: int = 512, want_q: bool = False):
+        """Energy, forces, virial of one configuration pos [N,3].
+
+        Returns dict(E, F [N,3], W [3,3], U [N], Wat [N,3,3], q [N,D]?)."""
+        pos = _f64(pos); types = _i32(types); box = _f64(box)
+        N = len(pos)
+        E = np.zeros(1); F = np.zeros((N, 3)); W = np.zeros(9)
+        U = np.zeros(N); Wat = np.zeros((N, 9))
+        q = np.zeros((N, self.dim)) if want_q else None
+        rc = lib().or_nep_config(self._h, _d(pos), _i(types), N, _d(box), cap, _d(E), _d(F), _d(W),
+                                 _d(U), _d(Wat), _d(q) if want_q else None)
+        if rc:
+            raise RuntimeError(f"oracle: neighbour capacity {cap} too small")
+        out = dict(E=float(E[0]), F=F, W=W.reshape(3, 3), U=U, Wat=Wat.reshape(N, 3, 3))
+        if want_q:
+            out["q"] = q
+        return out
+
+    def beads(self, pos, types, box, cap: int = 512):
+        """All beads: pos [P,N,3] -> E [P], F [P,N,3], W [P,3,3], U [P,N]."""
+        pos = _f64(pos); types = _i32(types); box = _f64(box)
+        P, N = pos.shape[:2]
+        E = np.zeros(P); F = np.zeros((P, N, 3)); W = np.zeros((P, 9)); U = np.zeros((P, N))
+        Wat = np.zeros((P, N, 9))
+        rc = lib().or_nep_beads(self._h, _d(pos), _i(types), P, N, _d(box), cap, _d(E), _d(F), _d(W),
+                                _d(U), _d(Wat))
+        if rc:
+            raise RuntimeError(f"oracle: neighbour capacity {cap} too small")
+        return dict(E=E, F=F, W=W.reshape(P, 3, 3), U=U, Wat=Wat.reshape(P, N, 3, 3))
+
+
+def neighbors(pos, box, rc: float, cap: int = 512):
+    """Brute-force minimum-image neighbour lists of one configuration.
+
+    Returns (cnt [N], idx [N,cap] with ascending indices, -1 padded)."""
+    pos = _f64(pos); box = _f64(box)
+    N = len(pos)
+    cnt = np.zeros(N, np.int32)
+    idx = np.full((N, cap), -1, np.int32)
+    mx = lib().or_neighbors(_d(pos), N, _d(box), float(rc), cap, _i(cnt), _i(idx))
+    if mx > cap:
+        raise RuntimeError(f"oracle: neighbour capacity {cap} < {mx}")
+    return cnt, idx
+
+
+# --------------------------------------------------------- ring polymer ---
+
+PIMD, TRPMD, RPMD = 0, 1, 2
+PRE, POST, FUSED = 0, 1, 2
+MODES = {"pimd": PIMD, "trpmd": TRPMD, "rpmd": RPMD}
+
+
+def philox4x32(key, ctr):
+    k = np.ascontiguousarray(key, np.uint32); c = np.ascontiguousarray(ctr, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().or_philox4x32(k.ctypes.data_as(C.POINTER(C.c_uint32)), c.ctypes.data_as(C.POINTER(C.c_uint32)),
+                        out.ctypes.data_as(C.POINTER(C.c_uint32)))
+    return out
+
+
+def philox4x64(key, ctr):
+    k = np.ascontiguousarray(key, np.uint64); c = np.ascontiguousarray(ctr, np.uint64)
+    out = np.zeros(4, np.uint64)
+    lib().or_philox4x64(k.ctypes.data_as(C.POINTER(C.c_uint64)), c.ctypes.data_as(C.POINTER(C.c_uint64)),
+                        out.ctypes.data_as(C.POINTER(C.c_uint64)))
+    return out
+
+
+def normals(seed: int, step: int, stage: int, atom: int, count: int):
+    out = np.zeros(count)
+    lib().or_normals(seed, step, stage, atom, count, _d(out))
+    return out
+
+
+def nm_matrix(P: int) -> np.ndarray:
+    Cm = np.zeros((P, P))
+    lib().or_nm_matrix(P, _d(Cm))
+    return Cm
+
+
+def nm_freqs(P: int, T: float) -> np.ndarray:
+    w = np.zeros(P)
+    lib().or_nm_freqs(P, float(T), _d(w))
+    return w
+
+
+def nm_transform(x, direction: int) -> np.ndarray:
+    """x [P, ...] -> normal modes (direction=+1) or beads (direction=-1)."""
+    x = _f64(x)
+    P = x.shape[0]
+    M = x.size // P
+    y = np.zeros_like(x)
+    lib().or_nm_transform(P, M, int(direction), _d(x), _d(y))
+    return y
+
+
+def cayley_coeffs(P: int, T: float, dt: float) -> np.ndarray:
+    out = np.zeros((P, 3))
+    lib().or_cayley_coeffs(P, float(T), float(dt), _d(out))
+    return out
+
+
+def trpmd_stage(pos, vel, F, mass, *, dt, T, tau, mode, seed, step, stage):
+    """Apply one integrator stage in place to pos/vel [P,N,3] (float64)."""
+    assert pos.dtype == np.float64 and pos.flags.c_contiguous
+    assert vel.dtype == np.float64 and vel.flags.c_contiguous
+    F = _f64(F); mass = _f64(mass)
+    P, N = pos.shape[:2]
+    m = MODES[mode] if isinstance(mode, str) else int(mode)
+    rc = lib().or_trpmd_stage(P, N, m, float(dt), float(T), float(tau), int(seed), _d(mass),
+                              _d(pos), _d(vel), _d(F), int(step), int(stage))
+    if rc:
+        raise ValueError("oracle: bad trpmd_stage arguments")

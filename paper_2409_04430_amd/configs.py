@@ -1,0 +1,100 @@
+"""The five synthetic workloads of the hot path (sizes, seeds, model shapes).
+
+Each workload is a stand-in for one of the paper's production systems
+(Sec. II.D): FCC aluminium, a rocksalt binary like LiH, liquid water, a
+metal-organic framework and a large FCC crystal used for the learned student.
+Everything is generated from a seed by `inputs`; no dataset is read.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List, Optional
+
+import numpy as np
+
+from . import inputs as I
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    seed: int
+    P: int
+    T: float            # K
+    dt: float           # fs
+    mode: str           # "pimd" | "trpmd" | "rpmd"
+    steps: int
+    tau_T: float        # fs, centroid thermostat time (PILE only)
+    hyper: I.NepHyper
+    species_masses: List[float]
+    e_scale: float = 30.0
+    student: Optional[I.NepHyper] = None
+
+    def systems(self, P: Optional[int] = None, scale: int = 1) -> List[I.System]:
+        """Build the periodic system(s) for this workload (list, one per box)."""
+        P = self.P if P is None else P
+        rng = np.random.default_rng(self.seed)
+        out = []
+        for pos0, types, box, sigma in self._structures(rng, scale):
+            out.append(I.make_system(pos0, types, box, self.species_masses, P, self.T, sigma, rng))
+        return out
+
+    def _structures(self, rng, scale):
+        n = self.name
+        if n == "fcc108":
+            p, t, b = I.fcc(3 * scale, 4.05)
+            return [(p, t, b, 0.05)]
+        if n == "rocksalt4096":
+            p, t, b = I.rocksalt(8 * scale, 4.2)
+            return [(p, t, b, 0.03)]
+        if n == "water16":
+            res = []
+            for k in range(1, 17):
+                p, t, b = I.water_box(64 * k, rng)
+                res.append((p, t, b, 0.0))
+            return res
+        if n == "porous13824":
+            p, t, b = I.porous_framework(8 * scale, 12.9)
+            return [(p, t, b, 0.0)]
+        if n == "fcc32000":
+            p, t, b = I.fcc(20 * scale, 4.05)
+            return [(p, t, b, 0.05)]
+        raise KeyError(n)
+
+    def model(self, student: bool = False) -> dict:
+        """Seeded random NEP-form model for this workload."""
+        h = self.student if student else self.hyper
+        rng = np.random.default_rng(self.seed + (1000 if student else 0))
+        dens = self.density()
+        return I.random_model(h, rng, dens, self.e_scale)
+
+    def density(self) -> float:
+        s = self.systems(P=1)
+        n = sum(x.N for x in s)
+        v = sum(float(np.prod(x.box)) for x in s)
+        return n / v
+
+
+WORKLOADS = {
+    # Tiny FCC aluminium: 3x3x3 cubic cells, 4 beads, TRPMD at 300 K.
+    "fcc108": Workload("fcc108", 4431, P=4, T=300.0, dt=1.0, mode="trpmd", steps=100, tau_T=100.0,
+                       hyper=I.NepHyper(1, 5.0, 4.0, 4, 4, 8, 8, 4, False, 30),
+                       species_masses=[26.98]),
+    # Rocksalt binary (LiH-like shape, Mg/O-like masses): 8x8x8 cells, 32 beads at 100 K.
+    "rocksalt4096": Workload("rocksalt4096", 4432, P=32, T=100.0, dt=0.5, mode="trpmd", steps=1000,
+                             tau_T=100.0, hyper=I.NepHyper(2, 6.0, 4.0, 6, 4, 8, 8, 4, False, 50),
+                             species_masses=[24.3, 16.0]),
+    # Sixteen water boxes of 64..1024 molecules, 32 beads at 300 K.
+    "water16": Workload("water16", 4433, P=32, T=300.0, dt=0.5, mode="trpmd", steps=100, tau_T=100.0,
+                        hyper=I.NepHyper(2, 6.0, 4.0, 4, 4, 8, 8, 4, False, 50),
+                        species_masses=[16.0, 1.008]),
+    # Porous four-species framework, 13,824 atoms, 64 beads at 300 K.
+    "porous13824": Workload("porous13824", 4434, P=64, T=300.0, dt=0.5, mode="trpmd", steps=50,
+                            tau_T=100.0, hyper=I.NepHyper(4, 6.0, 4.0, 8, 6, 8, 8, 4, False, 80),
+                            species_masses=[65.38, 16.0, 12.011, 1.008]),
+    # Large FCC crystal: teacher with four-body terms and a small student.
+    "fcc32000": Workload("fcc32000", 4435, P=32, T=300.0, dt=1.0, mode="trpmd", steps=100, tau_T=100.0,
+                         hyper=I.NepHyper(1, 6.0, 5.0, 8, 8, 8, 8, 4, True, 100),
+                         species_masses=[26.98],
+                         student=I.NepHyper(1, 6.0, 5.0, 4, 4, 8, 8, 4, False, 30)),
+}

@@ -1,0 +1,314 @@
+"""Pins of the FP64 NEP oracle against closed forms, independent library
+routines and the invariances the energy must have (paper Sec. II.A force and
+virial definitions; Sec. II.C site-energy model).  CPU only."""
+import copy
+import math
+
+import numpy as np
+import pytest
+from scipy import special
+from scipy.spatial import cKDTree
+
+from conftest import write_model, cluster_box
+from paper_2409_04430_amd import inputs as I
+from paper_2409_04430_amd import configs
+
+
+# ------------------------------------------------------------- helpers ---
+
+def g_trig(c, r, rc):
+    """g_n(r) with Chebyshev polynomials in trigonometric form
+    T_k(x) = cos(k arccos x): an evaluation path the oracle does not use."""
+    x = 2.0 * (r / rc - 1.0) ** 2 - 1.0
+    k = np.arange(c.shape[-1])
+    T = np.cos(k * np.arccos(np.clip(x, -1.0, 1.0)))
+    fc = 0.5 * (1.0 + np.cos(np.pi * r / rc)) if r < rc else 0.0
+    return c @ (0.5 * (T + 1.0) * fc)
+
+
+def sph_harm(l, m, u):
+    """Complex orthonormal Y_lm at unit vector u, from scipy."""
+    theta = math.acos(max(-1.0, min(1.0, u[2])))
+    phi = math.atan2(u[1], u[0])
+    if hasattr(special, "sph_harm_y"):
+        return complex(special.sph_harm_y(l, m, theta, phi))
+    return complex(special.sph_harm(m, l, phi, theta))
+
+
+def wigner3j_222():
+    from sympy.physics.wigner import wigner_3j
+    out = []
+    for m1 in range(-2, 3):
+        for m2 in range(-2, 3):
+            m3 = -m1 - m2
+            if abs(m3) <= 2:
+                out.append((m1, m2, m3, float(wigner_3j(2, 2, 2, m1, m2, m3))))
+    return out
+
+
+def small_model(tmpdir, name, S=1, four=False, nR=4, nA=4, rcR=5.0, rcA=4.0, H=12, seed=7, e_scale=3.0):
+    h = I.NepHyper(S, rcR, rcA, nR, nA, 8, 8, 4, four, H)
+    m = I.random_model(h, np.random.default_rng(seed), 0.06, e_scale)
+    return write_model(tmpdir, name, m), m
+
+
+def random_cluster(rng, n, rmax=3.5, rmin=1.2):
+    pts = [np.zeros(3)]
+    while len(pts) < n:
+        p = rng.uniform(-rmax, rmax, 3)
+        if np.linalg.norm(p) > rmax:
+            continue
+        if min(np.linalg.norm(p - q) for q in pts) < rmin:
+            continue
+        pts.append(p)
+    return np.array(pts) + 30.0
+
+
+# ------------------------------------------------------- neighbour lists ---
+
+def test_neighbors_match_periodic_kdtree(orc):
+    rng = np.random.default_rng(1)
+    box = np.array([13.0, 14.5, 12.2])
+    pos = rng.uniform(-20, 40, (300, 3))                # unwrapped on purpose
+    rc = 5.0
+    cnt, idx = orc.neighbors(pos, box, rc, cap=256)
+    tree = cKDTree(np.mod(pos, box), boxsize=box)
+    pairs = tree.query_pairs(rc, output_type="ndarray")
+    ref = [set() for _ in range(len(pos))]
+    for a, b in pairs:
+        ref[a].add(b); ref[b].add(a)
+    for i in range(len(pos)):
+        got = idx[i, :cnt[i]]
+        assert list(got) == sorted(ref[i])
+    assert np.all(np.diff(idx[0, :cnt[0]]) > 0)
+
+
+def test_neighbor_capacity_reported(orc):
+    pos = I.fcc(3, 4.05)[0]
+    with pytest.raises(RuntimeError):
+        orc.neighbors(pos, np.full(3, 12.15), 5.0, cap=10)
+
+
+# ------------------------------------------------------- closed forms ---
+
+def test_dimer_descriptors_closed_form(orc, tmpdir_session):
+    path, m = small_model(tmpdir_session, "dimer", S=2, four=True)
+    M = orc.Model(path)
+    u = np.array([0.3, -0.5, 0.8]); u /= np.linalg.norm(u)
+    r = 3.1
+    pos = np.array([[30.0, 30.0, 30.0], [30.0, 30.0, 30.0] + r * u])
+    types = np.array([0, 1])
+    out = M.config(pos, types, cluster_box(), want_q=True)
+    q = out["q"][0]
+    h = m["hyper"]
+    nR1, nA1 = h.n_max_radial + 1, h.n_max_angular + 1
+    gR = g_trig(m["c_radial"][0, 1], r, h.rc_radial)
+    gA = g_trig(m["c_angular"][0, 1], r, h.rc_angular)
+    np.testing.assert_allclose(q[:nR1], gR, rtol=1e-12, atol=1e-14)
+    for l in range(1, h.l_max + 1):
+        # P_l(1) = 1: one neighbour gives (2l+1)/(4 pi) g_n^2
+        np.testing.assert_allclose(q[nR1 + (l - 1) * nA1: nR1 + l * nA1],
+                                   (2 * l + 1) / (4 * np.pi) * gA ** 2, rtol=1e-12, atol=1e-15)
+    # four-body through the (2 2 2) Wigner-3j contraction of complex Y_2m
+    Y = {mm: sph_harm(2, mm, u) for mm in range(-2, 3)}
+    t3 = wigner3j_222()
+    for n in range(nA1):
+        A = {mm: gA[n] * Y[mm] for mm in Y}
+        ref = sum(w * A[a] * A[b] * A[c] for a, b, c, w in t3).real
+        np.testing.assert_allclose(q[nR1 + h.l_max * nA1 + n], ref, rtol=1e-11, atol=1e-15)
+    # the second atom sees the first with the (1, 0) coefficients
+    gR10 = g_trig(m["c_radial"][1, 0], r, h.rc_radial)
+    np.testing.assert_allclose(out["q"][1][:nR1], gR10, rtol=1e-12, atol=1e-14)
+
+
+def test_trimer_angular_legendre(orc, tmpdir_session):
+    path, m = small_model(tmpdir_session, "trimer")
+    M = orc.Model(path)
+    theta = 1.1
+    r1, r2 = 2.7, 3.3
+    c0 = np.full(3, 30.0)
+    pos = np.array([c0, c0 + [r1, 0, 0], c0 + r2 * np.array([math.cos(theta), math.sin(theta), 0])])
+    out = M.config(pos, np.zeros(3, int), cluster_box(), want_q=True)
+    h = m["hyper"]
+    nR1, nA1 = h.n_max_radial + 1, h.n_max_angular + 1
+    g1 = g_trig(m["c_angular"][0, 0], r1, h.rc_angular)
+    g2 = g_trig(m["c_angular"][0, 0], r2, h.rc_angular)
+    for l in range(1, h.l_max + 1):
+        ref = (2 * l + 1) / (4 * np.pi) * (g1 ** 2 + g2 ** 2 + 2 * g1 * g2 * special.eval_legendre(l, math.cos(theta)))
+        np.testing.assert_allclose(out["q"][0][nR1 + (l - 1) * nA1: nR1 + l * nA1], ref, rtol=1e-12, atol=1e-15)
+
+
+def test_angular_equals_spherical_harmonic_sums(orc, tmpdir_session):
+    """Legendre double sum == sum_m |A_nlm|^2 (addition theorem), with
+    A_nlm = sum_j g_n(r_ij) Y_lm(r_ij) from scipy's spherical harmonics."""
+    path, m = small_model(tmpdir_session, "sph2", S=2, four=True, seed=11)
+    M = orc.Model(path)
+    rng = np.random.default_rng(5)
+    pos = random_cluster(rng, 9)
+    types = rng.integers(0, 2, len(pos))
+    out = M.config(pos, types, cluster_box(), want_q=True)
+    h = m["hyper"]
+    nR1, nA1 = h.n_max_radial + 1, h.n_max_angular + 1
+    d = pos[1:] - pos[0]
+    rr = np.linalg.norm(d, axis=1)
+    sel = rr < h.rc_angular
+    g = np.array([g_trig(m["c_angular"][types[0], types[j + 1]], rr[j], h.rc_angular) for j in range(len(d))])
+    t3 = wigner3j_222()
+    for l in range(1, h.l_max + 1):
+        for n in range(nA1):
+            A = [sum(g[j, n] * sph_harm(l, mm, d[j] / rr[j]) for j in range(len(d)) if sel[j])
+                 for mm in range(-l, l + 1)]
+            ref = sum(abs(a) ** 2 for a in A)
+            np.testing.assert_allclose(out["q"][0][nR1 + (l - 1) * nA1 + n], ref, rtol=1e-11)
+    for n in range(nA1):
+        A = {mm: sum(g[j, n] * sph_harm(2, mm, d[j] / rr[j]) for j in range(len(d)) if sel[j])
+             for mm in range(-2, 3)}
+        ref = sum(w * A[a] * A[b] * A[c] for a, b, c, w in t3).real
+        np.testing.assert_allclose(out["q"][0][nR1 + h.l_max * nA1 + n], ref, rtol=1e-10, atol=1e-14)
+
+
+def test_site_energy_network(orc, tmpdir_session):
+    """U_i equals the one-hidden-layer tanh network of the scaled descriptors."""
+    path, m = small_model(tmpdir_session, "ann", S=2)
+    M = orc.Model(path)
+    rng = np.random.default_rng(3)
+    pos = random_cluster(rng, 7)
+    types = rng.integers(0, 2, len(pos))
+    out = M.config(pos, types, cluster_box(), want_q=True)
+    for i in range(len(pos)):
+        t = types[i]
+        h = np.tanh(m["W0"][t] @ (m["q_scale"] * out["q"][i]) - m["b0"][t])
+        np.testing.assert_allclose(out["U"][i], m["w1"][t] @ h - m["b1"], rtol=1e-12, atol=1e-14)
+    assert abs(out["E"] - out["U"].sum()) < 1e-12 * max(1.0, abs(out["E"]))
+
+
+# ---------------------------------------------------------- forces ---
+
+def _fd_force(M, pos, types, box, i, a, h=1e-5):
+    p = pos.copy(); p[i, a] += h
+    ep = M.config(p, types, box)["E"]
+    p[i, a] -= 2 * h
+    em = M.config(p, types, box)["E"]
+    return -(ep - em) / (2 * h)
+
+
+@pytest.mark.parametrize("kind", ["fcc1", "rocksalt2", "fourbody"])
+def test_forces_central_difference(orc, tmpdir_session, kind):
+    rng = np.random.default_rng(17)
+    if kind == "fcc1":
+        w = configs.WORKLOADS["fcc108"]
+        path = write_model(tmpdir_session, kind, w.model())
+        s = w.systems(P=1)[0]
+        pos, types, box = s.pos[0], s.types, s.box
+    elif kind == "rocksalt2":
+        w = configs.WORKLOADS["rocksalt4096"]
+        path = write_model(tmpdir_session, kind, w.model())
+        p0, types, box = I.rocksalt(3, 4.2)
+        pos = I.displace(p0, 0.05, rng)
+    else:
+        path, _ = small_model(tmpdir_session, kind, four=True, e_scale=30.0)
+        p0, types, box = I.fcc(3, 4.05)
+        pos = I.displace(p0, 0.08, rng)
+    M = orc.Model(path)
+    out = M.config(pos, types, box)
+    F = out["F"]
+    fmax = np.abs(F).max()
+    assert fmax > 1e-3
+    for i in rng.choice(len(pos), 5, replace=False):
+        for a in range(3):
+            fd = _fd_force(M, pos, types, box, i, a)
+            assert abs(fd - F[i, a]) <= 1e-7 * fmax + 1e-10, (i, a, fd, F[i, a])
+    # Newton's third law for the total: sum of forces vanishes
+    assert np.abs(F.sum(axis=0)).max() <= 1e-12 * len(pos) * fmax
+    # a small step along F lowers the energy
+    e2 = M.config(pos + 1e-4 * F / fmax, types, box)["E"]
+    assert e2 < out["E"]
+
+
+# ------------------------------------------------------ invariances ---
+
+def test_translation_rotation_permutation(orc, tmpdir_session):
+    path, m = small_model(tmpdir_session, "inv", S=2, four=True, seed=21, e_scale=10.0)
+    M = orc.Model(path)
+    rng = np.random.default_rng(8)
+    pos = random_cluster(rng, 14, rmax=5.0)
+    types = np.sort(rng.integers(0, 2, len(pos)))
+    box = cluster_box()
+    ref = M.config(pos, types, box)
+    # translation (also across the periodic boundary)
+    t = M.config(pos + np.array([17.3, -41.2, 5.5]), types, box)
+    assert abs(t["E"] - ref["E"]) <= 1e-12 * abs(ref["E"])
+    np.testing.assert_allclose(t["F"], ref["F"], atol=1e-11 * np.abs(ref["F"]).max())
+    # rotation about the cluster centre
+    from scipy.spatial.transform import Rotation
+    R = Rotation.random(random_state=4).as_matrix()
+    c = pos.mean(axis=0)
+    r = M.config((pos - c) @ R.T + c, types, box)
+    assert abs(r["E"] - ref["E"]) <= 1e-12 * abs(ref["E"])
+    np.testing.assert_allclose(r["F"], ref["F"] @ R.T, atol=1e-10 * np.abs(ref["F"]).max())
+    np.testing.assert_allclose(r["W"], R @ ref["W"] @ R.T, atol=1e-10 * np.abs(ref["W"]).max())
+    # permutation of atoms of the same species
+    perm = np.arange(len(pos))
+    same = np.where(types == types[0])[0]
+    perm[same] = rng.permutation(same)
+    p = M.config(pos[perm], types[perm], box)
+    assert abs(p["E"] - ref["E"]) <= 1e-12 * abs(ref["E"])
+    np.testing.assert_allclose(p["F"], ref["F"][perm], atol=1e-11 * np.abs(ref["F"]).max())
+
+
+# ----------------------------------------------------------- virial ---
+
+def test_virial_diagonal_strain_periodic(orc, tmpdir_session):
+    """W_aa = -dE/d(eps_aa) under a homogeneous strain of box and positions."""
+    w = configs.WORKLOADS["fcc108"]
+    path = write_model(tmpdir_session, "vir", w.model())
+    M = orc.Model(path)
+    s = w.systems(P=1)[0]
+    out = M.config(s.pos[0], s.types, s.box)
+    h = 1e-6
+    for a in range(3):
+        sc = np.ones(3); sc[a] += h
+        ep = M.config(s.pos[0] * sc, s.types, s.box * sc)["E"]
+        sc[a] -= 2 * h
+        em = M.config(s.pos[0] * sc, s.types, s.box * sc)["E"]
+        fd = -(ep - em) / (2 * h)
+        assert abs(fd - out["W"][a, a]) <= 1e-6 * np.abs(out["W"]).max(), (a, fd, out["W"][a, a])
+    np.testing.assert_allclose(out["Wat"].sum(axis=0), out["W"], atol=1e-12 * np.abs(out["W"]).max())
+    np.testing.assert_allclose(out["W"], out["W"].T, atol=1e-10 * np.abs(out["W"]).max())
+
+
+def test_virial_shear_strain_cluster(orc, tmpdir_session):
+    """Off-diagonal W_ab = -dE/d(eps_ba) for an isolated cluster."""
+    path, _ = small_model(tmpdir_session, "shear", S=2, four=True, seed=31, e_scale=10.0)
+    M = orc.Model(path)
+    rng = np.random.default_rng(9)
+    pos = random_cluster(rng, 12, rmax=4.5)
+    types = rng.integers(0, 2, len(pos))
+    box = cluster_box()
+    W = M.config(pos, types, box)["W"]
+    c = pos.mean(axis=0)
+    h = 1e-6
+    for a in range(3):
+        for b in range(3):
+            eps = np.zeros((3, 3)); eps[a, b] = h
+            ep = M.config((pos - c) @ (np.eye(3) + eps).T + c, types, box)["E"]
+            em = M.config((pos - c) @ (np.eye(3) - eps).T + c, types, box)["E"]
+            fd = -(ep - em) / (2 * h)
+            assert abs(fd - W[b, a]) <= 1e-6 * np.abs(W).max() + 1e-12, (a, b, fd, W[b, a])
+
+
+def test_repulsive_dimer_virial_sign(orc, tmpdir_session):
+    """A pair whose energy falls with distance has a positive virial."""
+    h = I.NepHyper(1, 5.0, 4.0, 0, 0, 1, 1, 1, False, 1)
+    m = dict(hyper=h, c_radial=np.array([[[[1.0, 0.0]]]]), c_angular=np.zeros((1, 1, 1, 2)),
+             q_scale=np.array([1.0, 0.0]), W0=np.array([[[1.0, 0.0]]]), b0=np.zeros((1, 1)),
+             w1=np.array([[1.0]]), b1=0.0)
+    path = write_model(tmpdir_session, "rep", m)
+    M = orc.Model(path)
+    pos = np.array([[30.0, 30.0, 30.0], [32.0, 30.0, 30.0]])
+    out = M.config(pos, np.zeros(2, int), cluster_box())
+    # U_i = tanh(f_0(r)), f_0 = f_c decreasing: repulsive
+    assert out["F"][0, 0] < 0 < out["F"][1, 0]
+    assert out["W"][0, 0] > 0
+    fc = 0.5 * (1 + math.cos(math.pi * 2.0 / 5.0))
+    assert abs(out["E"] - 2 * math.tanh(fc)) < 1e-14
