@@ -1,0 +1,245 @@
+/*
+ * neppimd.h - C ABI of the MI355X (gfx950) NEP path-integral MD hot path.
+ *
+ * What is computed (citations are to arXiv:2409.04430):
+ *   - the NEP site-energy model of Sec. II.C: U = sum_i U_i, each U_i a
+ *     one-hidden-layer tanh network of radial (Chebyshev x cutoff) and
+ *     angular (Legendre / spherical-harmonic) descriptors, NEP4 style
+ *     per-species networks;
+ *   - bead forces F_j^(i) = -dU/dr_j^(i) and the virial of Sec. II.A;
+ *   - the ring-polymer normal-mode transform (Eqs. (3)-(4), (7)-(8)), the
+ *     Cayley free ring-polymer step (Eqs. (5)-(6)), the half kick (Eq. (9))
+ *     and the Langevin thermostat on normal-mode momenta (Eqs. (10)-(12))
+ *     in its PILE (all modes), TRPMD (k > 0) and RPMD (none) forms.
+ *
+ * Conventions
+ *   Units: eV, Angstrom, amu, fs, K.  Velocities in A/fs.
+ *   Every function returns int32_t status: NEP_OK (0) or an error code > 0;
+ *   nep_last_error() then returns a message for the calling thread.  No C++
+ *   exception and no abort crosses this ABI.
+ *   Array arguments marked "dev" are device pointers owned by the caller;
+ *   the library never frees them.  Arrays marked "host" are host pointers.
+ *   Opaque handles are owned by the library and released by *_destroy.
+ *   Functions that take a hipStream_t enqueue work on that stream and return
+ *   before it finishes.  Argument errors are found on the host before any
+ *   launch; conditions found on the device (neighbour-list overflow,
+ *   non-finite forces, out-of-range species) set sticky flag bits that the
+ *   *_poll functions read (those functions synchronise the stream).
+ *   Enqueueing calls allocate nothing on the device, except neighbor_build
+ *   when a larger cell grid than any before is needed.
+ *
+ * Layouts
+ *   pos, vel:  [P][N][3] float64, bead-major (bead j of the paper is index
+ *              j-1), positions unwrapped (any periodic image).
+ *   F:         [P][N][3] float32, eV/A.
+ *   E:         [P] float64, per-bead total potential energy U(r_j).
+ *   W:         [P][9] float64, per-bead virial W_ab = -sum_i sum_j' r_ij'^a
+ *              (dU_i/dr_ij')^b, row-major (a, b).
+ *   types:     [N] int32, species index 0..n_species-1 (atoms grouped by
+ *              species run fastest).
+ *   box:       host double[9], cell row vectors a, b, c; only orthorhombic
+ *              cells are supported (off-diagonal entries must be zero).
+ */
+#ifndef NEPPIMD_H
+#define NEPPIMD_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nep_model nep_model;
+typedef struct nep_nlist nep_nlist;
+typedef struct nep_ws nep_ws;
+typedef struct pimd_ctx pimd_ctx;
+
+enum nep_status {
+    NEP_OK = 0,
+    NEP_ERR_INVALID_ARG = 1,      /* null pointer, bad size, mismatched handle */
+    NEP_ERR_PARAMS_FILE = 2,      /* model file missing or malformed */
+    NEP_ERR_UNSUPPORTED = 3,      /* model shape, species count, bead count or cell not supported */
+    NEP_ERR_BOX_TOO_SMALL = 4,    /* a box edge is shorter than twice the largest cutoff */
+    NEP_ERR_NEIGHBOR_OVERFLOW = 5,/* reported by nep_nlist_poll when a list exceeded its capacity */
+    NEP_ERR_NONFINITE = 6,        /* reported by nep_poll_flags for NaN/Inf forces */
+    NEP_ERR_HIP = 7,              /* a HIP runtime call failed */
+    NEP_ERR_NOMEM = 8             /* device or host allocation failed */
+};
+
+/* Sticky device flag bits. */
+enum nep_flag_bits {
+    NEP_FLAG_NEIGHBOR_OVERFLOW = 1u,  /* some list held more neighbours than its capacity */
+    NEP_FLAG_NONFINITE = 2u,          /* a force or a position was NaN or Inf */
+    NEP_FLAG_BAD_TYPE = 4u            /* a species index was outside 0..n_species-1 */
+};
+
+/* Thread-local message describing the last error of the calling thread. */
+const char *nep_last_error(void);
+
+/* ------------------------------------------------------------------ */
+/* Model (Sec. II.C)                                                   */
+/* ------------------------------------------------------------------ */
+
+typedef struct nep_hparams {
+    int32_t n_species;      /* 1..4 */
+    int32_t n_max_radial;   /* radial descriptors n = 0..n_max_radial */
+    int32_t n_max_angular;  /* angular descriptors n = 0..n_max_angular */
+    int32_t basis_radial;   /* Chebyshev functions k = 0..basis_radial */
+    int32_t basis_angular;
+    int32_t l_max;          /* angular l = 1..l_max */
+    int32_t four_body;      /* 1: one (2,2,2)-coupled invariant per angular n */
+    int32_t hidden;         /* hidden-layer width */
+    int32_t dim;            /* descriptor length */
+    double rc_radial;       /* A */
+    double rc_angular;      /* A */
+} nep_hparams;
+
+/* Parse the plain-text model file at `path` (host) and upload its weights
+ * to the current device.  The file holds the hyperparameters, the radial
+ * and angular Chebyshev coefficients c[ti][tj][n][k], one scale per
+ * descriptor, per-species network weights W0[H][D], b0[H], w1[H] and the
+ * shared output bias b1.  Supported shapes: l_max = 4, basis sizes 8,
+ * (n_max_radial, n_max_angular, four_body) in {(4,4,0), (4,4,1), (6,4,0),
+ * (8,6,0), (8,8,1)}, rc_angular <= rc_radial.  Errors: NEP_ERR_PARAMS_FILE,
+ * NEP_ERR_UNSUPPORTED, NEP_ERR_HIP, NEP_ERR_NOMEM.  *out is owned by the
+ * caller and released with nep_model_destroy. */
+int32_t nep_load_params(const char *path, nep_model **out);
+
+/* Copy the hyperparameters of a model into *out (host). */
+int32_t nep_model_info(const nep_model *model, nep_hparams *out);
+
+void nep_model_destroy(nep_model *model);
+
+/* ------------------------------------------------------------------ */
+/* Neighbour lists (per bead, minimum image, cell list)                */
+/* ------------------------------------------------------------------ */
+
+/* Create lists for P beads of N atoms.  cap_radial / cap_angular are the
+ * capacities of each per-(atom, neighbour species) block.  The lists live
+ * on the current device.  Errors: NEP_ERR_INVALID_ARG, NEP_ERR_NOMEM. */
+int32_t nep_nlist_create(const nep_model *model, int32_t P, int32_t N, int32_t cap_radial,
+                         int32_t cap_angular, nep_nlist **out);
+void nep_nlist_destroy(nep_nlist *nl);
+
+/* Build, for every bead b and atom i, the set of atoms i' != i with
+ * |mic(r_i' - r_i)|^2 < rc^2, for the radial and the angular cutoff.  The
+ * minimum image of d = r_i' - r_i is d - L rint(d / L) per axis and the test
+ * is (dx*dx + dy*dy) + dz*dz < rc*rc, all in IEEE FP64 without contraction,
+ * so the sets are exactly those of a brute-force search (Sec. II.A: periodic
+ * boundary conditions).  pos [P][N][3] dev, types [N] dev, box host[9].
+ * Errors: NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED (non-orthorhombic box),
+ * NEP_ERR_BOX_TOO_SMALL (an edge < 2 rc_radial), NEP_ERR_HIP, NEP_ERR_NOMEM.
+ * Overflow of a capacity sets NEP_FLAG_NEIGHBOR_OVERFLOW (the list then
+ * holds the first `cap` neighbours of that block). */
+int32_t neighbor_build(const nep_model *model, nep_nlist *nl, const double *pos, const double box[9],
+                       const int32_t *types, int32_t P, int32_t N, hipStream_t stream);
+
+/* Device layout of the lists (pointers stay owned by the handle).
+ *   cnt_*: [P][S][N] int32, number of neighbours of species s of atom i in
+ *          bead b (may exceed the capacity after an overflow);
+ *   idx_*: [P][S][cap][N] int32, slot-major so that consecutive atoms read
+ *          consecutive words; within a block the order is the traversal
+ *          order of the cell list (deterministic), not sorted. */
+typedef struct nep_nlist_layout {
+    int32_t P, N, n_species, cap_radial, cap_angular;
+    const int32_t *cnt_radial;
+    const int32_t *idx_radial;
+    const int32_t *cnt_angular;
+    const int32_t *idx_angular;
+} nep_nlist_layout;
+int32_t nep_nlist_view(const nep_nlist *nl, nep_nlist_layout *out);
+
+typedef struct nep_nlist_status {
+    uint32_t flags;          /* nep_flag_bits seen by neighbor_build */
+    int32_t max_radial;      /* largest per-species-block radial count seen */
+    int32_t max_angular;     /* largest per-species-block angular count seen */
+} nep_nlist_status;
+
+/* Synchronise `stream`, read the sticky status of the lists into *out and,
+ * if clear != 0, reset it.  Returns NEP_ERR_NEIGHBOR_OVERFLOW if the
+ * overflow bit is set (after filling *out). */
+int32_t nep_nlist_poll(nep_nlist *nl, nep_nlist_status *out, int32_t clear, hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Energy, forces, virial                                              */
+/* ------------------------------------------------------------------ */
+
+/* Workspace for P beads of N atoms (descriptor adjoints, partial sums,
+ * flags) on the current device. */
+int32_t nep_ws_create(const nep_model *model, int32_t P, int32_t N, nep_ws **out);
+void nep_ws_destroy(nep_ws *ws);
+
+/* NEP energy, forces and virial of every bead (Sec. II.C site energies,
+ * Sec. II.A bead forces and virial), from lists built by neighbor_build on
+ * the same pos/box/types.
+ *   E      [P]      dev float64  per-bead sum of site energies
+ *   F      [P][N][3] dev float32 forces, F_i = sum_j (dU_i/dr_ij - dU_j/dr_ji)
+ *   W      [P][9]   dev float64  per-bead virial
+ *   E_atom [P][N]   dev float32  site energies U_i, or NULL
+ *   W_atom [P][N][9] dev float32 per-atom virial -1/2 sum_j r_ij (x)
+ *                   (dU_i/dr_ij - dU_j/dr_ji), or NULL
+ * Positions enter as FP64; pair vectors are formed in FP64 and the rest is
+ * FP32 arithmetic with FP64 accumulation of forces, energies and virials.
+ * The summation order is fixed, so repeated calls give identical bits.
+ * Errors: NEP_ERR_INVALID_ARG (sizes differ from the handles'), NEP_ERR_HIP.
+ * Non-finite forces set NEP_FLAG_NONFINITE in the workspace. */
+int32_t nep_compute(const nep_model *model, const nep_nlist *nl, nep_ws *ws, const double *pos,
+                    const double box[9], const int32_t *types, int32_t P, int32_t N, double *E, float *F,
+                    double *W, float *E_atom, float *W_atom, hipStream_t stream);
+
+/* Synchronise `stream`, read the workspace flags into *flags and, if
+ * clear != 0, reset them.  Returns NEP_ERR_NONFINITE if that bit is set. */
+int32_t nep_poll_flags(nep_ws *ws, uint32_t *flags, int32_t clear, hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Ring polymer (Sec. II.A, Eqs. (3)-(12))                             */
+/* ------------------------------------------------------------------ */
+
+enum pimd_mode { PIMD_MODE_PILE = 0, PIMD_MODE_TRPMD = 1, PIMD_MODE_RPMD = 2 };
+enum pimd_stage { PIMD_STAGE_PRE = 0, PIMD_STAGE_POST = 1, PIMD_STAGE_FUSED = 2 };
+
+typedef struct pimd_params {
+    double dt_fs;      /* time step */
+    double T_K;        /* physical temperature; beads run at P T */
+    double tau_T_fs;   /* centroid friction time, gamma_0 = 1/tau (PILE only) */
+    int32_t mode;      /* enum pimd_mode */
+    uint64_t seed;     /* key of the counter-based normal generator */
+} pimd_params;
+
+/* Integrator context for P beads of N atoms: the orthogonal matrix C_jk
+ * (j = 1..P as printed in Sec. II.A; odd P has no (-1)^j row), the
+ * frequencies omega_k = 2 omega_P sin(k pi / P) with omega_P = P kB T / hbar,
+ * the Cayley coefficients and c_1k = exp(-gamma_k dt / 2), c_2k =
+ * sqrt(1 - c_1k^2), gamma_0 = 1/tau, gamma_k = omega_k.  mass [N] dev amu is
+ * copied.  Supported P: 1..64.  Errors: NEP_ERR_INVALID_ARG,
+ * NEP_ERR_UNSUPPORTED, NEP_ERR_HIP, NEP_ERR_NOMEM. */
+int32_t pimd_create(int32_t P, int32_t N, const pimd_params *params, const double *mass, pimd_ctx **out);
+void pimd_destroy(pimd_ctx *ctx);
+
+/* dir = +1: out_k = sum_j C_jk in_j (beads -> normal modes, Eqs. (3)-(4));
+ * dir = -1: out_j = sum_k C_jk in_k (modes -> beads, the transpose map).
+ * in, out [P][N][3] dev float64 (mode index in place of the bead index);
+ * in == out is not allowed. */
+int32_t rp_normal_modes(const pimd_ctx *ctx, int32_t dir, const double *in, double *out, hipStream_t stream);
+
+/* One integrator stage, in place on pos and vel, with forces F at the
+ * current positions:
+ *   PRE   = O, B, A: thermostat (Eqs. (10)-(12)) with noise stage 0 of
+ *           `step`, half kick (Eq. (9)), transform + Cayley + back transform
+ *           (Eqs. (3)-(8)); then the caller evaluates forces;
+ *   POST  = B, O with noise stage 1 of `step`;
+ *   FUSED = POST(step) followed by PRE(step + 1).
+ * Thermostatted modes: all (PILE), k > 0 (TRPMD), none (RPMD).  Normals:
+ * Philox-4x32-10 keyed by the seed with counter (atom, (component P + k)/4,
+ * step mod 2^32, 2 (step >> 32) + stage), uniforms (x + 1) 2^-32 and
+ * Box-Muller pairs.  pos, vel [P][N][3] dev float64; F [P][N][3] dev float32.
+ * Errors: NEP_ERR_INVALID_ARG, NEP_ERR_HIP. */
+int32_t trpmd_step(const pimd_ctx *ctx, double *pos, double *vel, const float *F, int64_t step, int32_t stage,
+                   hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEPPIMD_H */

@@ -184,10 +184,11 @@ def philox4x64(key, ctr):
     return out
 
 
-def normals(seed: int, step: int, stage: int, atom: int, count: int):
-    out = np.zeros(count)
-    lib().or_normals(seed, step, stage, atom, count, _d(out))
-    return out
+def normals(seed: int, step: int, stage: int, atom: int, P: int):
+    """Thermostat normals of one atom: [3, P] (component, mode)."""
+    out = np.zeros(3 * P)
+    lib().or_normals(seed, step, stage, atom, P, _d(out))
+    return out.reshape(3, P)
 
 
 def nm_matrix(P: int) -> np.ndarray:

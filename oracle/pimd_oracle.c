@@ -19,8 +19,9 @@
  *  - The thermostat acts before and after the free-polymer part: one step is
  *    O B A (force) B O, each O with c1 = exp(-gamma_k dt/2).
  *  - Random normals: Philox-4x32-10 (Salmon et al., SC'11) keyed by the seed,
- *    counter (atom, (component*P + k)/4, step low, 2*step high + stage),
- *    uniforms u = (x + 1) 2^-32, Box-Muller pairs (u0,u1), (u2,u3).
+ *    counter (atom, component*ceil(P/4) + k/4, step low, 2*step high + stage);
+ *    normal k&3 of the block; uniforms u = (x + 1) 2^-32, Box-Muller pairs
+ *    (u0,u1) -> normals 0,1 and (u2,u3) -> normals 2,3 (cos first).
  * Units: A, fs, amu, eV, K; velocities in A/fs.
  */
 #include <math.h>
@@ -78,16 +79,19 @@ PHILOX_DEFINE(or_philox4x32, uint32_t, mulhilo32, 0xD2511F53u, 0xCD9E8D57u, 0x9E
 PHILOX_DEFINE(or_philox4x64, uint64_t, mulhilo64, 0xD2E7470EE14C6C93ull, 0xCA5A826395121157ull,
               0x9E3779B97F4A7C15ull, 0xBB67AE8584CAA73Bull)
 
-/* Standard normal number m (= component*P + k) of atom i at (step, stage). */
-static double normal_at(uint64_t seed, int64_t step, int stage, int i, int m)
+/* Standard normal of mode k, Cartesian component a of atom i at (step, stage),
+ * for a ring polymer of P beads. */
+static double normal_at(uint64_t seed, int64_t step, int stage, int i, int a, int k, int P)
 {
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint64_t st = (uint64_t)step;
-    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)(m >> 2), (uint32_t)st,
+    uint32_t nb = (uint32_t)((P + 3) / 4);
+    uint32_t ctr[4] = {(uint32_t)i, (uint32_t)a * nb + (uint32_t)(k >> 2), (uint32_t)st,
                        (uint32_t)((st >> 32) * 2u + (uint32_t)stage)};
     uint32_t x[4];
     or_philox4x32(key, ctr, x);
-    int pair = (m & 3) >> 1;
+    int m = k & 3;
+    int pair = m >> 1;
     double u0 = ((double)x[2 * pair] + 1.0) * (1.0 / 4294967296.0);
     double u1 = ((double)x[2 * pair + 1] + 1.0) * (1.0 / 4294967296.0);
     double rad = sqrt(-2.0 * log(u0));
@@ -95,9 +99,11 @@ static double normal_at(uint64_t seed, int64_t step, int stage, int i, int m)
     return (m & 1) ? rad * sin(ang) : rad * cos(ang);
 }
 
-void or_normals(uint64_t seed, int64_t step, int stage, int i, int count, double *out)
+/* out[a*P + k] = normal of (component a, mode k), a = 0..2, k = 0..P-1. */
+void or_normals(uint64_t seed, int64_t step, int stage, int i, int P, double *out)
 {
-    for (int m = 0; m < count; ++m) out[m] = normal_at(seed, step, stage, i, m);
+    for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < P; ++k) out[a * P + k] = normal_at(seed, step, stage, i, a, k, P);
 }
 
 /* ------------------------------------------------------------------ */
@@ -172,7 +178,7 @@ static void thermo_O(const rp_t *s, double *v, int i, int a, int64_t step, int s
     for (int k = 0; k < P; ++k) {
         int on = (s->mode == OR_PIMD) || (s->mode == OR_TRPMD && k > 0);
         if (!on) continue;
-        double xi = normal_at(s->seed, step, stage, i, a * P + k);
+        double xi = normal_at(s->seed, step, stage, i, a, k, P);
         vt[k] = s->c1[k] * vt[k] + sig * s->c2[k] * xi;
     }
     for (int b = 0; b < P; ++b) {

@@ -1,0 +1,364 @@
+// Host side of libneppimd.so: error state, model file, handle lifetimes.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "internal.hpp"
+
+namespace nep {
+
+static thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+bool box_lengths(const double box[9], double L[3])
+{
+    if (box[1] != 0.0 || box[2] != 0.0 || box[3] != 0.0 || box[5] != 0.0 || box[6] != 0.0 || box[7] != 0.0)
+        return false;
+    L[0] = box[0];
+    L[1] = box[4];
+    L[2] = box[8];
+    return true;
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s)
+{
+    if (n == 0) return;
+    unsigned g = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, s, p, v, n);
+}
+
+void fill_i32(int32_t *p, int32_t v, size_t n, hipStream_t s)
+{
+    fill_u32(reinterpret_cast<uint32_t *>(p), (uint32_t)v, n, s);
+}
+
+// ---------------------------------------------------------------- model ---
+
+static bool read_tokens(const char *path, std::vector<std::string> &tok)
+{
+    std::ifstream f(path);
+    if (!f) return false;
+    std::string line;
+    while (std::getline(f, line)) {
+        size_t p = line.find_first_not_of(" \t\r");
+        if (p == std::string::npos || line[p] == '#') continue;
+        std::istringstream ss(line);
+        std::string w;
+        while (ss >> w) tok.push_back(w);
+    }
+    return true;
+}
+
+struct TokReader {
+    const std::vector<std::string> &t;
+    size_t i = 0;
+    bool ok = true;
+    explicit TokReader(const std::vector<std::string> &tt) : t(tt) {}
+    const std::string *next()
+    {
+        if (i >= t.size()) { ok = false; return nullptr; }
+        return &t[i++];
+    }
+    void expect(const char *w)
+    {
+        const std::string *s = next();
+        if (!s || *s != w) ok = false;
+    }
+    int geti()
+    {
+        const std::string *s = next();
+        if (!s) return 0;
+        char *e = nullptr;
+        long v = strtol(s->c_str(), &e, 10);
+        if (*e) ok = false;
+        return (int)v;
+    }
+    double getd()
+    {
+        const std::string *s = next();
+        if (!s) return 0.0;
+        char *e = nullptr;
+        double v = strtod(s->c_str(), &e);
+        if (*e) ok = false;
+        return v;
+    }
+};
+
+static bool shape_supported(const nep_hparams &h)
+{
+    if (h.l_max != kLmax || h.basis_radial != 8 || h.basis_angular != 8) return false;
+    if (h.n_species < 1 || h.n_species > kMaxSpecies) return false;
+    if (h.hidden < 1 || h.hidden > 512) return false;
+    if (!(h.rc_angular > 0.0) || !(h.rc_radial >= h.rc_angular)) return false;
+    const int ok[][3] = {{4, 4, 0}, {4, 4, 1}, {6, 4, 0}, {8, 6, 0}, {8, 8, 1}};
+    for (auto &s : ok)
+        if (h.n_max_radial == s[0] && h.n_max_angular == s[1] && h.four_body == s[2]) return true;
+    return false;
+}
+
+// Orthonormal real spherical harmonics l = 1..4 as constant x polynomial;
+// these are the constants, in m = -l..l order.
+static void sh_norms(double *c)
+{
+    const double pi = M_PI;
+    double v[kNumSH] = {
+        std::sqrt(3 / (4 * pi)), std::sqrt(3 / (4 * pi)), std::sqrt(3 / (4 * pi)),
+        0.5 * std::sqrt(15 / pi), 0.5 * std::sqrt(15 / pi), 0.25 * std::sqrt(5 / pi), 0.5 * std::sqrt(15 / pi),
+        0.25 * std::sqrt(15 / pi),
+        0.25 * std::sqrt(35 / (2 * pi)), 0.5 * std::sqrt(105 / pi), 0.25 * std::sqrt(21 / (2 * pi)),
+        0.25 * std::sqrt(7 / pi), 0.25 * std::sqrt(21 / (2 * pi)), 0.25 * std::sqrt(105 / pi),
+        0.25 * std::sqrt(35 / (2 * pi)),
+        0.75 * std::sqrt(35 / pi), 0.75 * std::sqrt(35 / (2 * pi)), 0.75 * std::sqrt(5 / pi),
+        0.75 * std::sqrt(5 / (2 * pi)), 3.0 / 16.0 * std::sqrt(1 / pi), 0.75 * std::sqrt(5 / (2 * pi)),
+        0.375 * std::sqrt(5 / pi), 0.75 * std::sqrt(35 / (2 * pi)), 3.0 / 16.0 * std::sqrt(35 / pi)};
+    for (int i = 0; i < kNumSH; ++i) c[i] = v[i];
+}
+
+}  // namespace nep
+
+using namespace nep;
+
+extern "C" const char *nep_last_error(void) { return g_err.c_str(); }
+
+extern "C" int32_t nep_load_params(const char *path, nep_model **out)
+{
+    if (!path || !out) return fail(NEP_ERR_INVALID_ARG, "nep_load_params: null argument");
+    *out = nullptr;
+    std::vector<std::string> tok;
+    if (!read_tokens(path, tok)) return fail(NEP_ERR_PARAMS_FILE, "cannot open model file '%s'", path);
+    TokReader r(tok);
+    nep_hparams h{};
+    r.expect("nep_pimd_model");
+    if (r.geti() != 1) r.ok = false;
+    r.expect("species"); h.n_species = r.geti();
+    r.expect("cutoff"); h.rc_radial = r.getd(); h.rc_angular = r.getd();
+    r.expect("n_max"); h.n_max_radial = r.geti(); h.n_max_angular = r.geti();
+    r.expect("basis"); h.basis_radial = r.geti(); h.basis_angular = r.geti();
+    r.expect("l_max"); h.l_max = r.geti();
+    r.expect("four_body"); h.four_body = r.geti();
+    r.expect("hidden"); h.hidden = r.geti();
+    if (!r.ok) return fail(NEP_ERR_PARAMS_FILE, "malformed header in model file '%s'", path);
+    if (!shape_supported(h))
+        return fail(NEP_ERR_UNSUPPORTED,
+                    "unsupported model shape (species %d, n_max %d/%d, basis %d/%d, l_max %d, four_body %d, "
+                    "hidden %d, rc %g/%g)", h.n_species, h.n_max_radial, h.n_max_angular, h.basis_radial,
+                    h.basis_angular, h.l_max, h.four_body, h.hidden, h.rc_radial, h.rc_angular);
+    const int S = h.n_species, NR1 = h.n_max_radial + 1, NA1 = h.n_max_angular + 1;
+    const int KR1 = h.basis_radial + 1, KA1 = h.basis_angular + 1, H = h.hidden;
+    h.dim = NR1 + h.l_max * NA1 + (h.four_body ? NA1 : 0);
+    const int D = h.dim;
+
+    nep_model *m = new (std::nothrow) nep_model;
+    if (!m) return fail(NEP_ERR_NOMEM, "host allocation failed");
+    m->hp = h;
+    ParamLayout &o = m->off;
+    int p = 0;
+    o.cR = p; p += S * S * NR1 * KR1;
+    o.cA = p; p += S * S * NA1 * KA1;
+    o.qs = p; p += D;
+    o.W0 = p; p += S * H * D;
+    o.b0 = p; p += S * H;
+    o.w1 = p; p += S * H;
+    o.b1 = p; p += 1;
+    o.sh = p; p += kNumSH;
+    o.total = p;
+    m->host.assign(p, 0.0f);
+    auto rd = [&](int off, int n) {
+        for (int i = 0; i < n; ++i) m->host[off + i] = (float)r.getd();
+    };
+    r.expect("c_radial"); rd(o.cR, S * S * NR1 * KR1);
+    r.expect("c_angular"); rd(o.cA, S * S * NA1 * KA1);
+    r.expect("q_scale"); rd(o.qs, D);
+    r.expect("ann");
+    for (int s = 0; s < S; ++s) {
+        rd(o.W0 + s * H * D, H * D);
+        rd(o.b0 + s * H, H);
+        rd(o.w1 + s * H, H);
+    }
+    r.expect("b1"); rd(o.b1, 1);
+    if (!r.ok) {
+        delete m;
+        return fail(NEP_ERR_PARAMS_FILE, "malformed or truncated parameter blocks in '%s'", path);
+    }
+    double shc[kNumSH];
+    sh_norms(shc);
+    for (int i = 0; i < kNumSH; ++i) m->host[o.sh + i] = (float)shc[i];
+
+    hipError_t e = hipGetDevice(&m->device);
+    if (e == hipSuccess) e = hipMalloc(&m->dev, sizeof(float) * (size_t)o.total);
+    if (e == hipSuccess)
+        e = hipMemcpy(m->dev, m->host.data(), sizeof(float) * (size_t)o.total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (m->dev) (void)hipFree(m->dev);
+        delete m;
+        return fail(e == hipErrorOutOfMemory ? NEP_ERR_NOMEM : NEP_ERR_HIP, "model upload failed: %s",
+                    hipGetErrorString(e));
+    }
+    *out = m;
+    return NEP_OK;
+}
+
+extern "C" int32_t nep_model_info(const nep_model *m, nep_hparams *out)
+{
+    if (!m || !out) return fail(NEP_ERR_INVALID_ARG, "nep_model_info: null argument");
+    *out = m->hp;
+    return NEP_OK;
+}
+
+extern "C" void nep_model_destroy(nep_model *m)
+{
+    if (!m) return;
+    if (m->dev) (void)hipFree(m->dev);
+    delete m;
+}
+
+// ----------------------------------------------------------- neighbour ---
+
+template <class T>
+static hipError_t dalloc(T **p, size_t n)
+{
+    return hipMalloc((void **)p, sizeof(T) * (n ? n : 1));
+}
+
+extern "C" int32_t nep_nlist_create(const nep_model *m, int32_t P, int32_t N, int32_t capR, int32_t capA,
+                                    nep_nlist **out)
+{
+    if (!m || !out) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_create: null argument");
+    if (P < 0 || N < 0 || capR < 1 || capA < 1 || capR > 4096 || capA > 4096)
+        return fail(NEP_ERR_INVALID_ARG, "nep_nlist_create: bad sizes P=%d N=%d caps=%d/%d", P, N, capR, capA);
+    *out = nullptr;
+    nep_nlist *nl = new (std::nothrow) nep_nlist;
+    if (!nl) return fail(NEP_ERR_NOMEM, "host allocation failed");
+    nl->P = P; nl->N = N; nl->S = m->hp.n_species; nl->capR = capR; nl->capA = capA;
+    const size_t PSN = (size_t)P * nl->S * N;
+    hipError_t e = hipGetDevice(&nl->device);
+    if (e == hipSuccess) e = dalloc(&nl->cntR, PSN);
+    if (e == hipSuccess) e = dalloc(&nl->cntA, PSN);
+    if (e == hipSuccess) e = dalloc(&nl->idxR, PSN * capR);
+    if (e == hipSuccess) e = dalloc(&nl->idxA, PSN * capA);
+    if (e == hipSuccess) e = dalloc(&nl->cell_atoms, (size_t)P * N);
+    if (e == hipSuccess) e = dalloc(&nl->status, 4);
+    if (e == hipSuccess) e = hipMemset(nl->status, 0, 4 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(nl->cntR, 0, sizeof(int32_t) * (PSN ? PSN : 1));
+    if (e == hipSuccess) e = hipMemset(nl->cntA, 0, sizeof(int32_t) * (PSN ? PSN : 1));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        nep_nlist_destroy(nl);
+        return fail(e == hipErrorOutOfMemory ? NEP_ERR_NOMEM : NEP_ERR_HIP, "nlist allocation failed: %s",
+                    hipGetErrorString(e));
+    }
+    *out = nl;
+    return NEP_OK;
+}
+
+extern "C" void nep_nlist_destroy(nep_nlist *nl)
+{
+    if (!nl) return;
+    for (void *p : {(void *)nl->cntR, (void *)nl->idxR, (void *)nl->cntA, (void *)nl->idxA,
+                    (void *)nl->cell_cnt, (void *)nl->cell_start, (void *)nl->cell_atoms, (void *)nl->status})
+        if (p) (void)hipFree(p);
+    delete nl;
+}
+
+extern "C" int32_t nep_nlist_view(const nep_nlist *nl, nep_nlist_layout *out)
+{
+    if (!nl || !out) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_view: null argument");
+    out->P = nl->P; out->N = nl->N; out->n_species = nl->S;
+    out->cap_radial = nl->capR; out->cap_angular = nl->capA;
+    out->cnt_radial = nl->cntR; out->idx_radial = nl->idxR;
+    out->cnt_angular = nl->cntA; out->idx_angular = nl->idxA;
+    return NEP_OK;
+}
+
+extern "C" int32_t nep_nlist_poll(nep_nlist *nl, nep_nlist_status *out, int32_t clear, hipStream_t s)
+{
+    if (!nl || !out) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_poll: null argument");
+    uint32_t h[4];
+    NEP_HIP(hipStreamSynchronize(s));
+    NEP_HIP(hipMemcpy(h, nl->status, sizeof h, hipMemcpyDeviceToHost));
+    out->flags = h[0];
+    out->max_radial = (int32_t)h[1];
+    out->max_angular = (int32_t)h[2];
+    if (clear) {
+        fill_u32(nl->status, 0u, 4, s);
+        NEP_HIP(hipGetLastError());
+        NEP_HIP(hipStreamSynchronize(s));
+    }
+    if (h[0] & NEP_FLAG_NEIGHBOR_OVERFLOW)
+        return fail(NEP_ERR_NEIGHBOR_OVERFLOW, "neighbour list overflow (largest counts %u/%u, capacities %d/%d)",
+                    h[1], h[2], nl->capR, nl->capA);
+    return NEP_OK;
+}
+
+// ----------------------------------------------------------- workspace ---
+
+extern "C" int32_t nep_ws_create(const nep_model *m, int32_t P, int32_t N, nep_ws **out)
+{
+    if (!m || !out) return fail(NEP_ERR_INVALID_ARG, "nep_ws_create: null argument");
+    if (P < 0 || N < 0) return fail(NEP_ERR_INVALID_ARG, "nep_ws_create: bad sizes P=%d N=%d", P, N);
+    *out = nullptr;
+    nep_ws *w = new (std::nothrow) nep_ws;
+    if (!w) return fail(NEP_ERR_NOMEM, "host allocation failed");
+    w->P = P; w->N = N; w->S = m->hp.n_species;
+    w->NA1 = m->hp.n_max_angular + 1;
+    w->KRP = ((m->hp.basis_radial + 1) + 3) / 4 * 4;
+    w->nblk = div_up(N > 0 ? N : 1, kBlock);
+    const size_t PN = (size_t)P * N;
+    hipError_t e = hipGetDevice(&w->device);
+    if (e == hipSuccess) e = dalloc(&w->B, PN * w->NA1 * kNumSH);
+    if (e == hipSuccess) e = dalloc(&w->arad, PN * w->S * w->KRP);
+    if (e == hipSuccess) e = dalloc(&w->partE, (size_t)P * w->nblk);
+    if (e == hipSuccess) e = dalloc(&w->partW, (size_t)P * w->nblk * 9);
+    if (e == hipSuccess) e = dalloc(&w->flags, 4);
+    if (e == hipSuccess) e = hipMemset(w->flags, 0, 4 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        nep_ws_destroy(w);
+        return fail(e == hipErrorOutOfMemory ? NEP_ERR_NOMEM : NEP_ERR_HIP, "workspace allocation failed: %s",
+                    hipGetErrorString(e));
+    }
+    *out = w;
+    return NEP_OK;
+}
+
+extern "C" void nep_ws_destroy(nep_ws *w)
+{
+    if (!w) return;
+    for (void *p : {(void *)w->B, (void *)w->arad, (void *)w->partE, (void *)w->partW, (void *)w->flags})
+        if (p) (void)hipFree(p);
+    delete w;
+}
+
+extern "C" int32_t nep_poll_flags(nep_ws *w, uint32_t *flags, int32_t clear, hipStream_t s)
+{
+    if (!w || !flags) return fail(NEP_ERR_INVALID_ARG, "nep_poll_flags: null argument");
+    uint32_t h[4];
+    NEP_HIP(hipStreamSynchronize(s));
+    NEP_HIP(hipMemcpy(h, w->flags, sizeof h, hipMemcpyDeviceToHost));
+    *flags = h[0];
+    if (clear) {
+        fill_u32(w->flags, 0u, 4, s);
+        NEP_HIP(hipGetLastError());
+        NEP_HIP(hipStreamSynchronize(s));
+    }
+    if (h[0] & NEP_FLAG_NONFINITE) return fail(NEP_ERR_NONFINITE, "non-finite force or position");
+    return NEP_OK;
+}

@@ -1,0 +1,90 @@
+// Library-internal declarations shared by the HIP translation units of
+// libneppimd.so.  Nothing here is part of the C ABI (see include/neppimd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "neppimd.h"
+
+namespace nep {
+
+constexpr int kMaxSpecies = 4;
+constexpr int kLmax = 4;
+constexpr int kNumSH = 24;          // real spherical harmonics l = 1..4
+constexpr int kMaxBeads = 64;
+
+int fail(int code, const char *fmt, ...);   // records the thread-local message, returns code
+
+#define NEP_HIP(call)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return ::nep::fail(NEP_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));    \
+    } while (0)
+
+// Offsets (in floats) of the packed device parameter block of a model.
+struct ParamLayout {
+    int cR, cA, qs, W0, b0, w1, b1, sh;   // sh: 24 spherical-harmonic normalisations
+    int total;
+};
+
+}  // namespace nep
+
+struct nep_model {
+    nep_hparams hp;
+    nep::ParamLayout off;
+    std::vector<float> host;   // packed parameters (FP32)
+    float *dev = nullptr;      // device copy
+    int device = 0;
+};
+
+struct nep_nlist {
+    int P = 0, N = 0, S = 0, capR = 0, capA = 0;
+    int device = 0;
+    int32_t *cntR = nullptr, *idxR = nullptr, *cntA = nullptr, *idxA = nullptr;
+    // cell list (grown on demand): cell_cnt [P][ncell], cell_start [P][ncell+1], cell_atoms [P][N]
+    int ncell_alloc = 0;
+    int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_atoms = nullptr;
+    uint32_t *status = nullptr;   // [0] flags, [1] max radial, [2] max angular
+};
+
+struct nep_ws {
+    int P = 0, N = 0, S = 0, nblk = 0;
+    int device = 0;
+    int NA1 = 0, KRP = 0;
+    float *B = nullptr;        // [P*N][NA1*24] angular adjoints dU_i/dA_nlm
+    float *arad = nullptr;     // [P*N][S][KRP] radial adjoints sum_n dU_i/dq_n c_nk
+    double *partE = nullptr;   // [P][nblk]
+    double *partW = nullptr;   // [P][nblk][9]
+    uint32_t *flags = nullptr; // [1]
+};
+
+struct pimd_ctx {
+    int P = 0, N = 0;
+    pimd_params prm;
+    int device = 0;
+    double *mass = nullptr;    // [N]
+    double *consts = nullptr;  // C [P][P] then per mode {c1, c2, cq, qv, vq}
+    std::vector<double> hC;    // host copy of C
+};
+
+namespace nep {
+
+// Number of threads per block used by the per-atom kernels.
+constexpr int kBlock = 256;
+
+inline int div_up(int a, int b) { return (a + b - 1) / b; }
+
+// Orthorhombic edge lengths from a row-vector cell; false if not orthorhombic.
+bool box_lengths(const double box[9], double L[3]);
+
+// Zero-fill on a stream by a kernel (capturable into graphs).
+void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
+void fill_i32(int32_t *p, int32_t v, size_t n, hipStream_t s);
+
+}  // namespace nep

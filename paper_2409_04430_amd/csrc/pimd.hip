@@ -1,0 +1,349 @@
+// Ring-polymer integrator on gfx950 (Sec. II.A of arXiv:2409.04430):
+// normal-mode transform (Eqs. (3)-(4), (7)-(8)), Cayley free ring-polymer
+// step (Eqs. (5)-(6)), half kick (Eq. (9)) and the Langevin thermostat on
+// normal-mode momenta (Eqs. (10)-(12)).
+//
+// One lane per (atom, Cartesian component) holds the P normal-mode
+// velocities (and positions) in registers.  Because C is orthogonal, the
+// kicks and the thermostat of a stage are applied in mode space: a stage
+// maps each mode as v~ <- alpha_k v~ + beta_k hk F~ + gamma_k, with
+//   PRE   (O then B):        alpha = c1, beta = 1,          gamma = sig c2 xi0
+//   POST  (B then O):        alpha = c1, beta = c1,         gamma = sig c2 xi1
+//   FUSED (B, O, O, B):      alpha = c1^2, beta = c1^2 + 1, gamma = sig c2 (c1 xi1 + xi0)
+// (c1 = 1, c2 = 0 on modes that are not thermostatted), followed for PRE
+// and FUSED by the Cayley map.  F~ is accumulated straight from the bead
+// forces with the beta-weighted matrix, so only two P-vectors stay live.
+// The bead data move once: read q, v, F and write q, v.
+#include <cmath>
+
+#include "internal.hpp"
+
+namespace nep {
+
+constexpr double kKB = 8.617333262e-5;     // eV/K
+constexpr double kHbar = 0.6582119569;     // eV fs
+// 1 amu A^2/fs^2 in eV
+inline double amu_a2_fs2_ev() { return 1.66053906660e-27 * 1e10 / 1.602176634e-19; }
+
+// Offsets into the per-context constant block.
+struct PimdLayout {
+    int P;
+    int C, CFpost, CFfused, c1, sc2, cq, qv, vq, total;
+    __host__ __device__ explicit PimdLayout(int p) : P(p)
+    {
+        C = 0;
+        CFpost = P * P;
+        CFfused = 2 * P * P;
+        c1 = 3 * P * P;
+        sc2 = c1 + P;
+        cq = sc2 + P;
+        qv = cq + P;
+        vq = qv + P;
+        total = vq + P;
+    }
+};
+
+// ---------------------------------------------------- Philox-4x32-10 ---
+// Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3",
+// SC'11: ten rounds of two 32x32->64 multiplies with Weyl key schedule.
+__device__ __forceinline__ void philox4x32_10(uint32_t k0, uint32_t k1, uint32_t c[4])
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// Four standard normals of block kb of component a of atom i (kept out of
+// line: one copy of the FP64 Box-Muller code serves every block).
+__device__ __noinline__ void normals4(uint64_t seed, uint64_t step, int stage, int i, int a, int nb, int kb,
+                                         double z[4])
+{
+    uint32_t c[4] = {(uint32_t)i, (uint32_t)(a * nb + kb), (uint32_t)step,
+                     (uint32_t)((step >> 32) * 2u + (uint64_t)stage)};
+    philox4x32_10((uint32_t)seed, (uint32_t)(seed >> 32), c);
+    const double s = 1.0 / 4294967296.0;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const double u0 = ((double)c[2 * p] + 1.0) * s;
+        const double u1 = ((double)c[2 * p + 1] + 1.0) * s;
+        const double rad = sqrt(-2.0 * log(u0));
+        double sn, cs;
+        sincos(2.0 * M_PI * u1, &sn, &cs);
+        z[2 * p] = rad * cs;
+        z[2 * p + 1] = rad * sn;
+    }
+}
+
+struct StepArgs {
+    double *pos, *vel;
+    const float *F;
+    const double *mass;
+    int N;
+    double dt, kTP, conv;
+    uint64_t seed;
+    int64_t step;
+    int stage, noise;
+};
+
+template <int P>
+__global__ __launch_bounds__(256) void k_trpmd(StepArgs a, const double *__restrict__ cst)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int M = 3 * a.N;
+    if (e >= M) return;
+    const int i = e / 3, comp = e - 3 * i;
+    const PimdLayout Lo(P);
+    const double m = a.mass[i];
+    const double hk = 0.5 * a.dt / (m * a.conv);
+    const double sig = sqrt(a.kTP / (m * a.conv));
+    const size_t stride = (size_t)M;
+    const bool pre = a.stage != PIMD_STAGE_POST, post = a.stage != PIMD_STAGE_PRE;
+
+    double vt[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) vt[k] = 0.0;
+#pragma unroll 1
+    for (int b = 0; b < P; ++b) {
+        const double v = a.vel[b * stride + e];
+        const double *Cb = cst + Lo.C + b * P;
+#pragma unroll
+        for (int k = 0; k < P; ++k) vt[k] += Cb[k] * v;
+    }
+    // alpha and gamma
+    if (a.noise) {
+        constexpr int NB = (P + 3) / 4;
+        const uint64_t step_pre = (uint64_t)(a.stage == PIMD_STAGE_FUSED ? a.step + 1 : a.step);
+#pragma unroll
+        for (int kb = 0; kb < NB; ++kb) {
+            double z1[4] = {0.0, 0.0, 0.0, 0.0}, z0[4] = {0.0, 0.0, 0.0, 0.0};
+            if (post) normals4(a.seed, (uint64_t)a.step, 1, i, comp, NB, kb, z1);
+            if (pre) normals4(a.seed, step_pre, 0, i, comp, NB, kb, z0);
+#pragma unroll
+            for (int e4 = 0; e4 < 4; ++e4) {
+                const int k = 4 * kb + e4;
+                if (k < P) {
+                    const double c1 = cst[Lo.c1 + k], gs = sig * cst[Lo.sc2 + k];
+                    if (a.stage == PIMD_STAGE_FUSED)
+                        vt[k] = c1 * c1 * vt[k] + gs * (c1 * z1[e4] + z0[e4]);
+                    else
+                        vt[k] = c1 * vt[k] + gs * (post ? z1[e4] : z0[e4]);
+                }
+            }
+        }
+    }
+    // beta-weighted force in mode space
+    const int CF = a.stage == PIMD_STAGE_PRE ? Lo.C : (a.stage == PIMD_STAGE_POST ? Lo.CFpost : Lo.CFfused);
+#pragma unroll 1
+    for (int b = 0; b < P; ++b) {
+        const double f = hk * (double)a.F[b * stride + e];
+        const double *Cb = cst + CF + b * P;
+#pragma unroll
+        for (int k = 0; k < P; ++k) vt[k] += Cb[k] * f;
+    }
+    if (pre) {
+        double qt[P];
+#pragma unroll
+        for (int k = 0; k < P; ++k) qt[k] = 0.0;
+#pragma unroll 1
+        for (int b = 0; b < P; ++b) {
+            const double q = a.pos[b * stride + e];
+            const double *Cb = cst + Lo.C + b * P;
+#pragma unroll
+            for (int k = 0; k < P; ++k) qt[k] += Cb[k] * q;
+        }
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+            const double cq = cst[Lo.cq + k], qv = cst[Lo.qv + k], vq = cst[Lo.vq + k];
+            const double qn = cq * qt[k] + qv * vt[k];
+            const double vn = cq * vt[k] - vq * qt[k];
+            qt[k] = qn;
+            vt[k] = vn;
+        }
+#pragma unroll 1
+        for (int b = 0; b < P; ++b) {
+            const double *Cb = cst + Lo.C + b * P;
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < P; ++k) s += Cb[k] * qt[k];
+            a.pos[b * stride + e] = s;
+        }
+    }
+#pragma unroll 1
+    for (int b = 0; b < P; ++b) {
+        const double *Cb = cst + Lo.C + b * P;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < P; ++k) s += Cb[k] * vt[k];
+        a.vel[b * stride + e] = s;
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k_modes(const double *__restrict__ in, double *__restrict__ out, int M,
+                                               int dir, const double *__restrict__ cst)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= M) return;
+    double x[P];
+#pragma unroll
+    for (int b = 0; b < P; ++b) x[b] = in[(size_t)b * M + e];
+#pragma unroll 1
+    for (int o = 0; o < P; ++o) {
+        double s = 0.0;
+        if (dir > 0) {
+#pragma unroll
+            for (int k = 0; k < P; ++k) s += cst[k * P + o] * x[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < P; ++k) s += cst[o * P + k] * x[k];
+        }
+        out[(size_t)o * M + e] = s;
+    }
+}
+
+template <int P>
+static void launch_step(const StepArgs &a, const double *cst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_trpmd<P>, dim3(div_up(3 * a.N, 256)), dim3(256), 0, s, a, cst);
+}
+
+template <int P>
+static void launch_modes(const double *in, double *out, int M, int dir, const double *cst, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_modes<P>, dim3(div_up(M, 256)), dim3(256), 0, s, in, out, M, dir, cst);
+}
+
+#define NEP_P_CASES(X)                                                                                  \
+    X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16) X(17) X(18)   \
+    X(19) X(20) X(21) X(22) X(23) X(24) X(25) X(26) X(27) X(28) X(29) X(30) X(31) X(32) X(33) X(34)      \
+    X(35) X(36) X(37) X(38) X(39) X(40) X(41) X(42) X(43) X(44) X(45) X(46) X(47) X(48) X(49) X(50)      \
+    X(51) X(52) X(53) X(54) X(55) X(56) X(57) X(58) X(59) X(60) X(61) X(62) X(63) X(64)
+
+}  // namespace nep
+
+using namespace nep;
+
+extern "C" int32_t pimd_create(int32_t P, int32_t N, const pimd_params *prm, const double *mass, pimd_ctx **out)
+{
+    if (!prm || !out) return fail(NEP_ERR_INVALID_ARG, "pimd_create: null argument");
+    *out = nullptr;
+    if (P < 1 || P > kMaxBeads) return fail(NEP_ERR_UNSUPPORTED, "pimd_create: P=%d outside 1..%d", P, kMaxBeads);
+    if (N < 0 || (N > 0 && !mass)) return fail(NEP_ERR_INVALID_ARG, "pimd_create: bad N or mass");
+    if (!(prm->dt_fs > 0.0) || !(prm->T_K >= 0.0) || prm->mode < 0 || prm->mode > 2 ||
+        (prm->mode == PIMD_MODE_PILE && !(prm->tau_T_fs > 0.0)))
+        return fail(NEP_ERR_INVALID_ARG, "pimd_create: bad dt/T/tau/mode");
+    pimd_ctx *c = new (std::nothrow) pimd_ctx;
+    if (!c) return fail(NEP_ERR_NOMEM, "host allocation failed");
+    c->P = P;
+    c->N = N;
+    c->prm = *prm;
+    // host tables
+    PimdLayout Lo(P);
+    std::vector<double> h(Lo.total, 0.0);
+    const double sq = std::sqrt((double)P), sq2 = std::sqrt(2.0 / P);
+    for (int b = 0; b < P; ++b) {
+        const int j = b + 1;
+        for (int k = 0; k < P; ++k) {
+            double v;
+            if (k == 0) v = 1.0 / sq;
+            else if (2 * k == P) v = ((j % 2) ? -1.0 : 1.0) / sq;
+            else if (2 * k < P) v = sq2 * std::cos(2.0 * M_PI * j * k / P);
+            else v = sq2 * std::sin(2.0 * M_PI * j * k / P);
+            h[Lo.C + b * P + k] = v;
+        }
+    }
+    const double wP = P * kKB * prm->T_K / kHbar;
+    for (int k = 0; k < P; ++k) {
+        const double wk = 2.0 * wP * std::sin(k * M_PI / P);
+        const bool th = prm->mode == PIMD_MODE_PILE || (prm->mode == PIMD_MODE_TRPMD && k > 0);
+        const double gamma = (k == 0) ? (prm->mode == PIMD_MODE_PILE ? 1.0 / prm->tau_T_fs : 0.0) : wk;
+        const double c1 = th ? std::exp(-0.5 * prm->dt_fs * gamma) : 1.0;
+        const double c2 = th ? std::sqrt(1.0 - c1 * c1) : 0.0;
+        h[Lo.c1 + k] = c1;
+        h[Lo.sc2 + k] = c2;
+        const double hh = 0.5 * wk * prm->dt_fs, den = 1.0 + hh * hh;
+        h[Lo.cq + k] = (1.0 - hh * hh) / den;
+        h[Lo.qv + k] = prm->dt_fs / den;
+        h[Lo.vq + k] = wk * wk * prm->dt_fs / den;
+        for (int b = 0; b < P; ++b) {
+            h[Lo.CFpost + b * P + k] = h[Lo.C + b * P + k] * c1;
+            h[Lo.CFfused + b * P + k] = h[Lo.C + b * P + k] * (c1 * c1 + 1.0);
+        }
+    }
+    c->hC.assign(h.begin(), h.begin() + P * P);
+    hipError_t e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = hipMalloc(&c->consts, sizeof(double) * Lo.total);
+    if (e == hipSuccess) e = hipMalloc(&c->mass, sizeof(double) * (N > 0 ? N : 1));
+    if (e == hipSuccess) e = hipMemcpy(c->consts, h.data(), sizeof(double) * Lo.total, hipMemcpyHostToDevice);
+    if (e == hipSuccess && N > 0) e = hipMemcpy(c->mass, mass, sizeof(double) * N, hipMemcpyDeviceToDevice);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        pimd_destroy(c);
+        return fail(e == hipErrorOutOfMemory ? NEP_ERR_NOMEM : NEP_ERR_HIP, "pimd_create: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return NEP_OK;
+}
+
+extern "C" void pimd_destroy(pimd_ctx *c)
+{
+    if (!c) return;
+    if (c->consts) (void)hipFree(c->consts);
+    if (c->mass) (void)hipFree(c->mass);
+    delete c;
+}
+
+extern "C" int32_t rp_normal_modes(const pimd_ctx *c, int32_t dir, const double *in, double *out, hipStream_t s)
+{
+    if (!c) return fail(NEP_ERR_INVALID_ARG, "rp_normal_modes: null context");
+    if (dir != 1 && dir != -1) return fail(NEP_ERR_INVALID_ARG, "rp_normal_modes: dir must be +1 or -1");
+    if (c->N == 0) return NEP_OK;
+    if (!in || !out || in == out) return fail(NEP_ERR_INVALID_ARG, "rp_normal_modes: bad arrays");
+    const int M = 3 * c->N;
+    switch (c->P) {
+#define X(p) case p: launch_modes<p>(in, out, M, dir, c->consts, s); break;
+        NEP_P_CASES(X)
+#undef X
+    default: return fail(NEP_ERR_UNSUPPORTED, "rp_normal_modes: P=%d", c->P);
+    }
+    NEP_HIP(hipGetLastError());
+    return NEP_OK;
+}
+
+extern "C" int32_t trpmd_step(const pimd_ctx *c, double *pos, double *vel, const float *F, int64_t step, int32_t stage,
+                              hipStream_t s)
+{
+    if (!c) return fail(NEP_ERR_INVALID_ARG, "trpmd_step: null context");
+    if (stage < PIMD_STAGE_PRE || stage > PIMD_STAGE_FUSED) return fail(NEP_ERR_INVALID_ARG, "trpmd_step: bad stage");
+    if (step < 0) return fail(NEP_ERR_INVALID_ARG, "trpmd_step: negative step");
+    if (c->N == 0) return NEP_OK;
+    if (!pos || !vel || !F) return fail(NEP_ERR_INVALID_ARG, "trpmd_step: null array");
+    StepArgs a;
+    a.pos = pos; a.vel = vel; a.F = F; a.mass = c->mass; a.N = c->N;
+    a.dt = c->prm.dt_fs;
+    a.kTP = c->P * kKB * c->prm.T_K;
+    a.conv = amu_a2_fs2_ev();
+    a.seed = c->prm.seed;
+    a.step = step;
+    a.stage = stage;
+    a.noise = c->prm.mode != PIMD_MODE_RPMD && !(c->prm.mode == PIMD_MODE_TRPMD && c->P == 1);
+    switch (c->P) {
+#define X(p) case p: launch_step<p>(a, c->consts, s); break;
+        NEP_P_CASES(X)
+#undef X
+    default: return fail(NEP_ERR_UNSUPPORTED, "trpmd_step: P=%d", c->P);
+    }
+    NEP_HIP(hipGetLastError());
+    return NEP_OK;
+}

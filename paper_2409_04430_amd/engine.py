@@ -1,0 +1,120 @@
+"""Driver loop of the hot path: neighbour build -> NEP forces -> integrator.
+
+One stream, no per-step host synchronisation: the sticky device flags of
+the neighbour lists and of the force workspace are polled every
+`check_every` steps.  The step is the paper's workflow (Sec. II.A): thermostat,
+half kick, free ring-polymer step, forces, half kick, thermostat; the two
+integrator halves around consecutive force evaluations run as one fused
+launch.
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import numpy as np
+
+from . import inputs as I
+from . import lib
+
+
+def default_capacity(rc: float, density: float, n_species: int, slack: float = 1.6) -> int:
+    """Capacity per species block from the mean density (overflow is detected)."""
+    n = density * 4.0 / 3.0 * math.pi * rc ** 3
+    return int(math.ceil(n * slack)) + 8
+
+
+class NepPimd:
+    """NEP forces for P beads of one periodic system plus the ring-polymer integrator."""
+
+    def __init__(self, model_path: str, system: I.System, *, dt: float, T: float, tau: float = 100.0,
+                 mode: str = "trpmd", seed: int = 0, cap_radial: Optional[int] = None,
+                 cap_angular: Optional[int] = None, check_every: int = 50, want_atom: bool = False):
+        import torch
+        self.torch = torch
+        dev = torch.device("cuda")
+        self.model = lib.Model(model_path)
+        self.P, self.N = system.P, system.N
+        self.box = np.asarray(system.box, np.float64)
+        self.pos = torch.tensor(system.pos, dtype=torch.float64, device=dev)
+        self.vel = torch.tensor(system.vel, dtype=torch.float64, device=dev)
+        self.types = torch.tensor(system.types, dtype=torch.int32, device=dev)
+        self.mass = torch.tensor(system.masses, dtype=torch.float64, device=dev)
+        self.F = torch.zeros((self.P, self.N, 3), dtype=torch.float32, device=dev)
+        self.E = torch.zeros(self.P, dtype=torch.float64, device=dev)
+        self.W = torch.zeros((self.P, 9), dtype=torch.float64, device=dev)
+        self.E_atom = torch.zeros((self.P, self.N), dtype=torch.float32, device=dev) if want_atom else None
+        self.W_atom = torch.zeros((self.P, self.N, 9), dtype=torch.float32, device=dev) if want_atom else None
+        dens = self.N / float(np.prod(self.box))
+        S = self.model.n_species
+        self.cap_radial = cap_radial or default_capacity(self.model.rc_radial, dens, S)
+        self.cap_angular = cap_angular or default_capacity(self.model.rc_angular, dens, S)
+        self.nl = lib.NeighborList(self.model, self.P, self.N, self.cap_radial, self.cap_angular)
+        self.ws = lib.Workspace(self.model, self.P, self.N)
+        self.pimd = lib.Pimd(self.P, self.N, self.mass, dt, T, tau, mode, seed)
+        self.check_every = check_every
+        self.step_no = 0
+        self.started = False
+        self._fit_capacity()
+
+    # ------------------------------------------------------------------
+    def _fit_capacity(self):
+        """Build once, then shrink or grow the capacities to the observed need."""
+        for _ in range(4):
+            self.nl.build(self.pos, self.box, self.types)
+            flags, mr, ma = self.nl.poll(clear=True)
+            if flags & lib.FLAG_BAD_TYPE:
+                raise lib.NepError(1, "species index outside the model's range")
+            need_r = int(math.ceil(mr * 1.25)) + 8
+            need_a = int(math.ceil(ma * 1.25)) + 8
+            if flags & lib.FLAG_NEIGHBOR_OVERFLOW or need_r < self.cap_radial // 2 or need_a < self.cap_angular // 2:
+                self.cap_radial, self.cap_angular = max(need_r, 8), max(need_a, 8)
+                self.nl = lib.NeighborList(self.model, self.P, self.N, self.cap_radial, self.cap_angular)
+                continue
+            return
+        raise lib.NepError(5, "could not size the neighbour lists")
+
+    def forces(self):
+        """Neighbour lists + NEP energy, forces and virial at the current positions."""
+        self.nl.build(self.pos, self.box, self.types)
+        self.ws.compute(self.nl, self.pos, self.box, self.types, self.E, self.F, self.W, self.E_atom, self.W_atom)
+
+    def check(self):
+        """Poll the sticky flags (synchronises); raise on overflow or non-finite values."""
+        flags, mr, ma = self.nl.poll(clear=True)
+        if flags & lib.FLAG_NEIGHBOR_OVERFLOW:
+            raise lib.NepError(5, f"neighbour overflow: need {mr}/{ma}, capacity {self.cap_radial}/{self.cap_angular}")
+        wf = self.ws.poll(clear=True)
+        if (flags | wf) & lib.FLAG_NONFINITE:
+            raise lib.NepError(6, "non-finite force or position")
+        if (flags | wf) & lib.FLAG_BAD_TYPE:
+            raise lib.NepError(1, "species index outside the model's range")
+        return mr, ma
+
+    def start(self):
+        self.forces()
+        self.pimd.step(self.pos, self.vel, self.F, self.step_no, lib.PRE)
+        self.started = True
+
+    def step(self):
+        """One full step: forces at the advanced positions, then POST(n) + PRE(n+1)."""
+        if not self.started:
+            self.start()
+        self.forces()
+        self.pimd.step(self.pos, self.vel, self.F, self.step_no, lib.FUSED)
+        self.step_no += 1
+        if self.check_every and self.step_no % self.check_every == 0:
+            self.check()
+
+    def run(self, n: int):
+        for _ in range(n):
+            self.step()
+
+    def finish(self):
+        """Close the current step (forces + POST), leaving synchronised q and v."""
+        if not self.started:
+            self.start()
+        self.forces()
+        self.pimd.step(self.pos, self.vel, self.F, self.step_no, lib.POST)
+        self.started = False
+        self.step_no += 1

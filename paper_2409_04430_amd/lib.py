@@ -1,0 +1,292 @@
+"""Thin Python binding of libneppimd.so (the HIP C-ABI library).
+
+Argument marshalling only: every step of the hot path runs in the library's
+kernels.  Tensors are torch CUDA (HIP) tensors; work is enqueued on the
+current torch stream.  If the shared library is missing this module raises
+on import: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libneppimd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or python -m paper_2409_04430_amd.build")
+
+_lib = C.CDLL(LIB_PATH)
+
+NEP_OK = 0
+ERRORS = {1: "INVALID_ARG", 2: "PARAMS_FILE", 3: "UNSUPPORTED", 4: "BOX_TOO_SMALL", 5: "NEIGHBOR_OVERFLOW",
+          6: "NONFINITE", 7: "HIP", 8: "NOMEM"}
+FLAG_NEIGHBOR_OVERFLOW, FLAG_NONFINITE, FLAG_BAD_TYPE = 1, 2, 4
+MODE = {"pimd": 0, "pile": 0, "trpmd": 1, "rpmd": 2}
+PRE, POST, FUSED = 0, 1, 2
+
+
+class NepError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class HParams(C.Structure):
+    _fields_ = [("n_species", C.c_int32), ("n_max_radial", C.c_int32), ("n_max_angular", C.c_int32),
+                ("basis_radial", C.c_int32), ("basis_angular", C.c_int32), ("l_max", C.c_int32),
+                ("four_body", C.c_int32), ("hidden", C.c_int32), ("dim", C.c_int32),
+                ("rc_radial", C.c_double), ("rc_angular", C.c_double)]
+
+
+class NlistLayout(C.Structure):
+    _fields_ = [("P", C.c_int32), ("N", C.c_int32), ("n_species", C.c_int32), ("cap_radial", C.c_int32),
+                ("cap_angular", C.c_int32), ("cnt_radial", C.c_void_p), ("idx_radial", C.c_void_p),
+                ("cnt_angular", C.c_void_p), ("idx_angular", C.c_void_p)]
+
+
+class NlistStatus(C.Structure):
+    _fields_ = [("flags", C.c_uint32), ("max_radial", C.c_int32), ("max_angular", C.c_int32)]
+
+
+class PimdParams(C.Structure):
+    _fields_ = [("dt_fs", C.c_double), ("T_K", C.c_double), ("tau_T_fs", C.c_double), ("mode", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+_vp = C.c_void_p
+_i32 = C.c_int32
+_sig = {
+    "nep_last_error": (C.c_char_p, []),
+    "nep_load_params": (_i32, [C.c_char_p, C.POINTER(_vp)]),
+    "nep_model_info": (_i32, [_vp, C.POINTER(HParams)]),
+    "nep_model_destroy": (None, [_vp]),
+    "nep_nlist_create": (_i32, [_vp, _i32, _i32, _i32, _i32, C.POINTER(_vp)]),
+    "nep_nlist_destroy": (None, [_vp]),
+    "neighbor_build": (_i32, [_vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, _vp]),
+    "nep_nlist_view": (_i32, [_vp, C.POINTER(NlistLayout)]),
+    "nep_nlist_poll": (_i32, [_vp, C.POINTER(NlistStatus), _i32, _vp]),
+    "nep_ws_create": (_i32, [_vp, _i32, _i32, C.POINTER(_vp)]),
+    "nep_ws_destroy": (None, [_vp]),
+    "nep_compute": (_i32, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
+                           _vp]),
+    "nep_poll_flags": (_i32, [_vp, C.POINTER(C.c_uint32), _i32, _vp]),
+    "pimd_create": (_i32, [_i32, _i32, C.POINTER(PimdParams), _vp, C.POINTER(_vp)]),
+    "pimd_destroy": (None, [_vp]),
+    "rp_normal_modes": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "trpmd_step": (_i32, [_vp, _vp, _vp, _vp, C.c_int64, _i32, _vp]),
+}
+for _n, (_r, _a) in _sig.items():
+    _f = getattr(_lib, _n)
+    _f.restype = _r
+    _f.argtypes = _a
+
+
+def last_error() -> str:
+    return (_lib.nep_last_error() or b"").decode()
+
+
+def _check(rc: int):
+    if rc != NEP_OK:
+        raise NepError(rc, last_error())
+
+
+def _stream():
+    import torch
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype, shape=None, name="tensor"):
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return _vp(t.data_ptr())
+
+
+def _box9(box) -> C.Array:
+    b = np.asarray(box, np.float64)
+    if b.shape == (3,):
+        b = np.diag(b)
+    b = np.ascontiguousarray(b.reshape(9))
+    return (C.c_double * 9)(*b)
+
+
+# ------------------------------------------------------------------ handles
+
+class Model:
+    """nep_load_params / nep_model_info / nep_model_destroy."""
+
+    def __init__(self, path: str):
+        self._h = _vp()
+        _check(_lib.nep_load_params(path.encode(), C.byref(self._h)))
+        hp = HParams()
+        _check(_lib.nep_model_info(self._h, C.byref(hp)))
+        self.hp = {f: getattr(hp, f) for f, _ in HParams._fields_}
+        self.path = path
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __getattr__(self, k):
+        hp = self.__dict__.get("hp")
+        if hp is not None and k in hp:
+            return hp[k]
+        raise AttributeError(k)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.nep_model_destroy(h)
+            self._h = None
+
+
+class NeighborList:
+    """nep_nlist_create / neighbor_build / nep_nlist_view / nep_nlist_poll."""
+
+    def __init__(self, model: Model, P: int, N: int, cap_radial: int, cap_angular: int):
+        self._h = _vp()
+        _check(_lib.nep_nlist_create(model.handle, P, N, cap_radial, cap_angular, C.byref(self._h)))
+        self.model, self.P, self.N = model, P, N
+        self.cap_radial, self.cap_angular = cap_radial, cap_angular
+
+    def build(self, pos, box, types):
+        _check(_lib.neighbor_build(self.model.handle, self._h, _ptr(pos, _torch().float64, (self.P, self.N, 3), "pos"),
+                                   _box9(box), _ptr(types, _torch().int32, (self.N,), "types"), self.P, self.N,
+                                   _stream()))
+
+    def poll(self, clear: bool = True):
+        """(flags, max_radial, max_angular); synchronises the stream."""
+        st = NlistStatus()
+        rc = _lib.nep_nlist_poll(self._h, C.byref(st), int(clear), _stream())
+        if rc not in (NEP_OK, 5):
+            _check(rc)
+        return st.flags, st.max_radial, st.max_angular
+
+    def view(self):
+        """Raw layout: device pointers of cnt [P,S,N] and idx [P,S,cap,N] (radial, angular)."""
+        lay = NlistLayout()
+        _check(_lib.nep_nlist_view(self._h, C.byref(lay)))
+        return lay
+
+    def to_host(self):
+        """Copy the lists to host numpy arrays (synchronise the stream first)."""
+        _torch().cuda.synchronize()
+        lay = self.view()
+        S = lay.n_species
+        return dict(cnt_radial=device_to_host(lay.cnt_radial, (lay.P, S, lay.N), np.int32),
+                    idx_radial=device_to_host(lay.idx_radial, (lay.P, S, lay.cap_radial, lay.N), np.int32),
+                    cnt_angular=device_to_host(lay.cnt_angular, (lay.P, S, lay.N), np.int32),
+                    idx_angular=device_to_host(lay.idx_angular, (lay.P, S, lay.cap_angular, lay.N), np.int32))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.nep_nlist_destroy(h)
+            self._h = None
+
+
+class Workspace:
+    """nep_ws_create / nep_compute / nep_poll_flags."""
+
+    def __init__(self, model: Model, P: int, N: int):
+        self._h = _vp()
+        _check(_lib.nep_ws_create(model.handle, P, N, C.byref(self._h)))
+        self.model, self.P, self.N = model, P, N
+
+    def compute(self, nl: NeighborList, pos, box, types, E, F, W, E_atom=None, W_atom=None):
+        t = _torch()
+        P, N = self.P, self.N
+        _check(_lib.nep_compute(self.model.handle, nl.handle, self._h, _ptr(pos, t.float64, (P, N, 3), "pos"),
+                                _box9(box), _ptr(types, t.int32, (N,), "types"), P, N,
+                                _ptr(E, t.float64, (P,), "E"), _ptr(F, t.float32, (P, N, 3), "F"),
+                                _ptr(W, t.float64, (P, 9), "W"), _ptr(E_atom, t.float32, (P, N), "E_atom"),
+                                _ptr(W_atom, t.float32, (P, N, 9), "W_atom"), _stream()))
+
+    def poll(self, clear: bool = True) -> int:
+        f = C.c_uint32()
+        rc = _lib.nep_poll_flags(self._h, C.byref(f), int(clear), _stream())
+        if rc not in (NEP_OK, 6):
+            _check(rc)
+        return f.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.nep_ws_destroy(h)
+            self._h = None
+
+
+class Pimd:
+    """pimd_create / rp_normal_modes / trpmd_step."""
+
+    def __init__(self, P: int, N: int, mass, dt: float, T: float, tau: float, mode="trpmd", seed: int = 0):
+        t = _torch()
+        self._h = _vp()
+        prm = PimdParams(float(dt), float(T), float(tau), MODE[mode] if isinstance(mode, str) else int(mode),
+                         int(seed))
+        _check(_lib.pimd_create(P, N, C.byref(prm), _ptr(mass, t.float64, (N,), "mass"), C.byref(self._h)))
+        self.P, self.N = P, N
+
+    def normal_modes(self, x, out, direction: int):
+        t = _torch()
+        _check(_lib.rp_normal_modes(self._h, int(direction), _ptr(x, t.float64, (self.P, self.N, 3), "in"),
+                                    _ptr(out, t.float64, (self.P, self.N, 3), "out"), _stream()))
+
+    def step(self, pos, vel, F, step: int, stage: int):
+        t = _torch()
+        shp = (self.P, self.N, 3)
+        _check(_lib.trpmd_step(self._h, _ptr(pos, t.float64, shp, "pos"), _ptr(vel, t.float64, shp, "vel"),
+                               _ptr(F, t.float32, shp, "F"), int(step), int(stage), _stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.pimd_destroy(h)
+            self._h = None
+
+
+def _torch():
+    import torch
+    return torch
+
+
+_hip = None
+
+
+def device_to_host(ptr, shape, dtype) -> np.ndarray:
+    """Copy a library-owned device array (e.g. from NeighborList.view()) to host."""
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.restype = C.c_int
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    out = np.empty(shape, dtype)
+    if out.nbytes:
+        rc = _hip.hipMemcpy(out.ctypes.data_as(C.c_void_p), C.c_void_p(ptr), C.c_size_t(out.nbytes), 2)
+        if rc != 0:
+            raise NepError(7, f"hipMemcpy failed ({rc})")
+    return out
+
+
+def exported_symbols():
+    return list(_sig)

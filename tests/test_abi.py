@@ -1,0 +1,85 @@
+"""The C-ABI library: it loads, exports every function include/neppimd.h
+declares, and rejects bad model files and sizes on the host.  CPU only (no
+call here reaches the device)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "neppimd.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int32_t|void|const char\s*\*)\s*\*?\s*(\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2409_04430_amd import lib
+    return lib
+
+
+def test_header_declares_expected_entry_points():
+    names = declared_functions()
+    for n in ("nep_load_params", "neighbor_build", "nep_compute", "rp_normal_modes", "trpmd_step"):
+        assert n in names
+
+
+def test_library_exports_every_declared_function(L):
+    so = C.CDLL(L.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(so, n)]
+    assert not missing, missing
+    assert sorted(L.exported_symbols()) == declared_functions()
+
+
+def test_library_links_no_cpu_oracle(L):
+    import subprocess
+    out = subprocess.run(["nm", "-D", L.LIB_PATH], capture_output=True, text=True).stdout
+    assert "or_nep" not in out and "or_trpmd" not in out
+
+
+def test_model_file_errors(L, tmp_path):
+    with pytest.raises(L.NepError) as e:
+        L.Model(str(tmp_path / "missing.nep"))
+    assert e.value.code == 2
+    bad = tmp_path / "bad.nep"
+    bad.write_text("nep_pimd_model 1\nspecies 1\ncutoff 5 4\n")
+    with pytest.raises(L.NepError) as e:
+        L.Model(str(bad))
+    assert e.value.code == 2
+    from paper_2409_04430_amd import inputs as I
+    h = I.NepHyper(1, 5.0, 4.0, 5, 3, 8, 8, 4, False, 10)       # (5,3) is not a built shape
+    m = I.random_model(h, np.random.default_rng(0), 0.06)
+    p = tmp_path / "unsup.nep"
+    I.write_model(str(p), m)
+    with pytest.raises(L.NepError) as e:
+        L.Model(str(p))
+    assert e.value.code == 3
+    # truncated weights
+    good = tmp_path / "good.nep"
+    I.write_model(str(good), I.random_model(I.NepHyper(1, 5.0, 4.0, 4, 4, 8, 8, 4, False, 10),
+                                            np.random.default_rng(0), 0.06))
+    txt = good.read_text().split("\n")
+    trunc = tmp_path / "trunc.nep"
+    trunc.write_text("\n".join(txt[: len(txt) // 2]))
+    with pytest.raises(L.NepError) as e:
+        L.Model(str(trunc))
+    assert e.value.code == 2
+
+
+def test_pimd_rejects_bad_sizes(L):
+    out = C.c_void_p()
+    prm = L.PimdParams(0.5, 300.0, 100.0, 1, 1)
+    assert L._lib.pimd_create(0, 10, C.byref(prm), None, C.byref(out)) == 3
+    assert L._lib.pimd_create(65, 10, C.byref(prm), None, C.byref(out)) == 3
+    assert L._lib.pimd_create(4, 10, C.byref(prm), None, C.byref(out)) == 1     # null mass
+    bad = L.PimdParams(-0.5, 300.0, 100.0, 1, 1)
+    assert L._lib.pimd_create(4, 0, C.byref(bad), None, C.byref(out)) == 1
+    assert "dt" in L.last_error()
+    assert L._lib.trpmd_step(None, None, None, None, 0, 0, None) == 1

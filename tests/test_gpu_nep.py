@@ -1,0 +1,275 @@
+"""GPU parity of the NEP path (neighbour lists, energy, forces, virial)
+against the FP64 oracle, through the C-ABI library.
+
+Bar: neighbour sets bit-exact; per bead |dE|/N <= 1e-6 eV/atom,
+max_i |dF_i| <= 1e-5 max_i |F_i|, max |dW| <= 1e-5 max |W| (FP32 kernels
+against the FP64 oracle)."""
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import write_model
+from paper_2409_04430_amd import configs
+from paper_2409_04430_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+E_TOL = 1e-6      # eV/atom
+F_TOL = 1e-5      # relative to the largest force of the bead
+W_TOL = 1e-5      # relative to the largest virial component of the bead
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as T
+    assert T.cuda.is_available(), "GPU tests need a device"
+    return T
+
+
+@pytest.fixture(scope="module")
+def L(torch):
+    from paper_2409_04430_amd import lib
+    return lib
+
+
+def beads_of(name, P, extra_sigma=0.03, seed=1, box_index=0):
+    w = configs.WORKLOADS[name]
+    s = w.systems(P=P)[box_index]
+    rng = np.random.default_rng(seed)
+    pos = s.pos + rng.normal(0.0, extra_sigma, s.pos.shape)
+    # put some atoms in other periodic images: the path must not care
+    pos[:, ::7, :] += s.box * rng.integers(-2, 3, (1, len(pos[0, ::7]), 3))
+    return pos, s.types, s.box
+
+
+def oracle_caps(orc, pos, box, rc_r, rc_a):
+    mr = max(orc.neighbors(p, box, rc_r, cap=1024)[0].max() for p in pos)
+    ma = max(orc.neighbors(p, box, rc_a, cap=1024)[0].max() for p in pos)
+    return int(mr) + 8, int(ma) + 8
+
+
+def gpu_nep(torch, L, path, pos, types, box, capR, capA, atom=True):
+    P, N = pos.shape[:2]
+    m = L.Model(path)
+    nl = L.NeighborList(m, P, N, capR, capA)
+    ws = L.Workspace(m, P, N)
+    dev = torch.device("cuda")
+    tpos = torch.tensor(pos, dtype=torch.float64, device=dev)
+    ttyp = torch.tensor(types, dtype=torch.int32, device=dev)
+    E = torch.zeros(P, dtype=torch.float64, device=dev)
+    F = torch.zeros((P, N, 3), dtype=torch.float32, device=dev)
+    W = torch.zeros((P, 9), dtype=torch.float64, device=dev)
+    Ea = torch.zeros((P, N), dtype=torch.float32, device=dev) if atom else None
+    Wa = torch.zeros((P, N, 9), dtype=torch.float32, device=dev) if atom else None
+    nl.build(tpos, box, ttyp)
+    ws.compute(nl, tpos, box, ttyp, E, F, W, Ea, Wa)
+    torch.cuda.synchronize()
+    flags, mr, ma = nl.poll()
+    assert flags == 0, (flags, mr, ma)
+    assert ws.poll() == 0
+    out = dict(E=E.cpu().numpy(), F=F.cpu().numpy().astype(np.float64), W=W.cpu().numpy().reshape(P, 3, 3),
+               lists=nl.to_host(), nl=nl, ws=ws, model=m, tensors=(tpos, ttyp, E, F, W, Ea, Wa))
+    if atom:
+        out["U"] = Ea.cpu().numpy()
+        out["Wat"] = Wa.cpu().numpy().reshape(P, N, 3, 3)
+    return out
+
+
+def check_lists(orc, lists, pos, box, rc_r, rc_a, beads=None, atoms=None):
+    P, N = pos.shape[:2]
+    beads = range(P) if beads is None else beads
+    for kind, rc in (("radial", rc_r), ("angular", rc_a)):
+        cnt, idx = lists["cnt_" + kind], lists["idx_" + kind]
+        S, cap = idx.shape[1], idx.shape[2]
+        for b in beads:
+            oc, oi = orc.neighbors(pos[b], box, rc, cap=1024)
+            sel = range(N) if atoms is None else atoms
+            for i in sel:
+                got = np.sort(np.concatenate([idx[b, t, :cnt[b, t, i], i] for t in range(S)]))
+                assert cnt[b, :, i].sum() == oc[i], (kind, b, i)
+                np.testing.assert_array_equal(got, oi[i, :oc[i]], err_msg=f"{kind} bead {b} atom {i}")
+
+
+def check_nep(ref, got, beads, N, atom=True):
+    for k, b in enumerate(beads):
+        dE = abs(got["E"][b] - ref["E"][k]) / N
+        fmax = np.abs(ref["F"][k]).max()
+        dF = np.abs(got["F"][b] - ref["F"][k]).max()
+        wmax = np.abs(ref["W"][k]).max()
+        dW = np.abs(got["W"][b] - ref["W"][k]).max()
+        say(f"  bead {b}: dE/N={dE:.2e} dF/Fmax={dF / fmax:.2e} dW/Wmax={dW / wmax:.2e} (Fmax {fmax:.3g})")
+        assert dE <= E_TOL
+        assert dF <= F_TOL * fmax
+        assert dW <= W_TOL * wmax
+        if atom:
+            # U_i is one FP32 value: the bar is FP32 precision relative to the largest |U_i|
+            assert np.abs(got["U"][b] - ref["U"][k]).max() <= F_TOL * np.abs(ref["U"][k]).max()
+            wa = np.abs(ref["Wat"][k]).max()
+            assert np.abs(got["Wat"][b] - ref["Wat"][k]).max() <= 10 * W_TOL * wa
+
+
+def oracle_beads(orc, path, pos, types, box, beads):
+    M = orc.Model(path)
+    r = M.beads(pos[list(beads)], types, box)
+    return r
+
+
+@pytest.mark.parametrize("name,P", [("fcc108", 4), ("rocksalt4096", 2)])
+def test_nep_parity_workload(torch, L, orc, tmpdir_session, name, P):
+    say(f"[nep parity] {name} P={P}")
+    w = configs.WORKLOADS[name]
+    path = write_model(tmpdir_session, name, w.model())
+    pos, types, box = beads_of(name, P)
+    h = w.hyper
+    capR, capA = oracle_caps(orc, pos, box, h.rc_radial, h.rc_angular)
+    got = gpu_nep(torch, L, path, pos, types, box, capR, capA)
+    check_lists(orc, got["lists"], pos, box, h.rc_radial, h.rc_angular)
+    ref = oracle_beads(orc, path, pos, types, box, range(P))
+    check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"], U=ref["U"], Wat=ref["Wat"]), got, range(P), pos.shape[1])
+
+
+def test_nep_parity_four_body(torch, L, orc, tmpdir_session):
+    say("[nep parity] four-body model on FCC, P=3")
+    h = I.NepHyper(1, 5.0, 4.0, 4, 4, 8, 8, 4, True, 16)
+    m = I.random_model(h, np.random.default_rng(99), 0.06, 30.0)
+    path = write_model(tmpdir_session, "four", m)
+    pos, types, box = beads_of("fcc108", 3, extra_sigma=0.08, seed=4)
+    capR, capA = oracle_caps(orc, pos, box, 5.0, 4.0)
+    got = gpu_nep(torch, L, path, pos, types, box, capR, capA)
+    ref = oracle_beads(orc, path, pos, types, box, range(3))
+    check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"], U=ref["U"], Wat=ref["Wat"]), got, range(3), pos.shape[1])
+
+
+def test_nep_parity_water_boxes(torch, L, orc, tmpdir_session):
+    """Two water boxes: 64 molecules (L = 12.4 A, two cells per edge) and
+    512 molecules; ragged atom counts (192, 1536)."""
+    w = configs.WORKLOADS["water16"]
+    path = write_model(tmpdir_session, "water", w.model())
+    for bi in (0, 7):
+        say(f"[nep parity] water box {bi}")
+        pos, types, box = beads_of("water16", 2, extra_sigma=0.02, seed=bi, box_index=bi)
+        capR, capA = oracle_caps(orc, pos, box, 6.0, 4.0)
+        got = gpu_nep(torch, L, path, pos, types, box, capR, capA)
+        check_lists(orc, got["lists"], pos, box, 6.0, 4.0)
+        ref = oracle_beads(orc, path, pos, types, box, range(2))
+        check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"], U=ref["U"], Wat=ref["Wat"]), got, range(2),
+                  pos.shape[1])
+
+
+def test_nep_parity_porous_one_bead(torch, L, orc, tmpdir_session):
+    say("[nep parity] porous framework, 13824 atoms, four species")
+    w = configs.WORKLOADS["porous13824"]
+    path = write_model(tmpdir_session, "porous", w.model())
+    pos, types, box = beads_of("porous13824", 1, extra_sigma=0.05, seed=3)
+    got = gpu_nep(torch, L, path, pos, types, box, 96, 48)
+    rng = np.random.default_rng(0)
+    check_lists(orc, got["lists"], pos, box, 6.0, 4.0, atoms=rng.choice(pos.shape[1], 500, replace=False))
+    ref = oracle_beads(orc, path, pos, types, box, [0])
+    check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"], U=ref["U"], Wat=ref["Wat"]), got, [0], pos.shape[1])
+
+
+def test_nep_full_size_rocksalt_sampled_beads(torch, L, orc, tmpdir_session):
+    """All 32 beads of 4096 atoms at once (the benchmark launch); the oracle
+    checks beads 0 and 31 completely."""
+    say("[nep parity] rocksalt 4096 x 32 beads, sampled beads")
+    w = configs.WORKLOADS["rocksalt4096"]
+    path = write_model(tmpdir_session, "rs_full", w.model())
+    pos, types, box = beads_of("rocksalt4096", 32, extra_sigma=0.04, seed=11)
+    got = gpu_nep(torch, L, path, pos, types, box, 80, 32, atom=False)
+    check_lists(orc, got["lists"], pos, box, 6.0, 4.0, beads=[0, 31])
+    ref = oracle_beads(orc, path, pos, types, box, [0, 31])
+    check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"]), got, [0, 31], pos.shape[1], atom=False)
+    # the beads the oracle did not check still obey sum F = 0 and a symmetric virial
+    F = got["F"]
+    assert np.abs(F.sum(axis=1)).max() <= 1e-4 * np.abs(F).max() * np.sqrt(pos.shape[1])
+    Wt = got["W"]
+    assert np.abs(Wt - Wt.transpose(0, 2, 1)).max() <= 1e-4 * np.abs(Wt).max()
+
+
+def test_nep_fcc32000_teacher_one_bead(torch, L, orc, tmpdir_session):
+    say("[nep parity] teacher with four-body terms, 32000 atoms")
+    w = configs.WORKLOADS["fcc32000"]
+    path = write_model(tmpdir_session, "teacher", w.model())
+    pos, types, box = beads_of("fcc32000", 1, extra_sigma=0.02, seed=5)
+    got = gpu_nep(torch, L, path, pos, types, box, 96, 72, atom=False)
+    rng = np.random.default_rng(1)
+    check_lists(orc, got["lists"], pos, box, 6.0, 5.0, atoms=rng.choice(pos.shape[1], 300, replace=False))
+    ref = oracle_beads(orc, path, pos, types, box, [0])
+    check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"]), got, [0], pos.shape[1], atom=False)
+
+
+def test_nep_deterministic(torch, L, tmpdir_session):
+    say("[nep] bitwise determinism")
+    w = configs.WORKLOADS["rocksalt4096"]
+    path = write_model(tmpdir_session, "det", w.model())
+    pos, types, box = beads_of("rocksalt4096", 4)
+    a = gpu_nep(torch, L, path, pos, types, box, 80, 32)
+    b = gpu_nep(torch, L, path, pos, types, box, 80, 32)
+    for k in ("E", "F", "W", "U", "Wat"):
+        np.testing.assert_array_equal(a[k], b[k])
+    for k in a["lists"]:
+        np.testing.assert_array_equal(a["lists"][k], b["lists"][k])
+
+
+def test_nep_edge_cases(torch, L, tmpdir_session):
+    say("[nep] edge cases")
+    w = configs.WORKLOADS["fcc108"]
+    path = write_model(tmpdir_session, "edge", w.model())
+    m = L.Model(path)
+    dev = torch.device("cuda")
+    # empty: N = 0 and P = 0
+    for P, N in ((2, 0), (0, 5)):
+        nl = L.NeighborList(m, P, N, 8, 8)
+        ws = L.Workspace(m, P, N)
+        pos = torch.zeros((P, N, 3), dtype=torch.float64, device=dev)
+        typ = torch.zeros(N, dtype=torch.int32, device=dev)
+        E = torch.full((P,), 7.0, dtype=torch.float64, device=dev)
+        W = torch.full((P, 9), 7.0, dtype=torch.float64, device=dev)
+        F = torch.zeros((P, N, 3), dtype=torch.float32, device=dev)
+        nl.build(pos, [20.0, 20.0, 20.0], typ)
+        ws.compute(nl, pos, [20.0, 20.0, 20.0], typ, E, F, W)
+        torch.cuda.synchronize()
+        if P:
+            assert torch.all(E == 0) and torch.all(W == 0)
+    pos, types, box = beads_of("fcc108", 2)
+    tpos = torch.tensor(pos, dtype=torch.float64, device=dev)
+    ttyp = torch.tensor(types, dtype=torch.int32, device=dev)
+    # box shorter than twice the cutoff
+    nl = L.NeighborList(m, 2, 108, 64, 32)
+    with pytest.raises(L.NepError) as e:
+        nl.build(tpos, [9.0, 12.15, 12.15], ttyp)
+    assert e.value.code == 4
+    with pytest.raises(L.NepError) as e:
+        nl.build(tpos, np.array([[12.15, 0.1, 0], [0, 12.15, 0], [0, 0, 12.15]]), ttyp)
+    assert e.value.code == 3
+    # capacity overflow is flagged and the lists stay within bounds
+    small = L.NeighborList(m, 2, 108, 10, 4)
+    small.build(tpos, box, ttyp)
+    flags, mr, ma = small.poll()
+    assert flags & L.FLAG_NEIGHBOR_OVERFLOW and mr > 10 and ma > 4
+    lst = small.to_host()
+    assert lst["idx_radial"].shape[2] == 10
+    # a NaN position is flagged, a bad species index is flagged
+    bad = tpos.clone()
+    bad[1, 5, 0] = float("nan")
+    nl.build(bad, box, ttyp)
+    flags, _, _ = nl.poll()
+    assert flags & L.FLAG_NONFINITE
+    bt = ttyp.clone()
+    bt[3] = 5
+    nl.build(tpos, box, bt)
+    flags, _, _ = nl.poll()
+    assert flags & L.FLAG_BAD_TYPE
+    # mismatched sizes are rejected on the host
+    ws = L.Workspace(m, 2, 108)
+    with pytest.raises(L.NepError) as e:
+        ws.compute(L.NeighborList(m, 2, 100, 8, 8), tpos, box, ttyp, torch.zeros(2, dtype=torch.float64, device=dev),
+                   torch.zeros((2, 108, 3), dtype=torch.float32, device=dev),
+                   torch.zeros((2, 9), dtype=torch.float64, device=dev))
+    assert e.value.code == 1
