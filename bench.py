@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Throughput of the NEP-PIMD hot path on one MI355X.
+
+One step = neighbour lists for all beads + NEP energy, forces and virial for
+all beads + one fused integrator launch (thermostat, kicks, normal-mode
+transform, Cayley step), i.e. every stage of the paper's integration loop
+(Sec. II.A workflow, steps 2a-2e without the optional barostat).
+
+Workload (default): two-species rocksalt binary, 8x8x8 conventional cells =
+4096 atoms, a = 4.2 A, 32 beads at 100 K, TRPMD, dt = 0.5 fs; NEP with
+cutoffs 6/4 A, n_max 6/4, basis 8, l_max 4, 50 hidden units, seeded random
+weights.  Inputs are resident in device memory before the timed region.
+
+Prints one JSON line (metric, value in atom*bead*steps/s, roofline of the
+dominant kernel from live hipEvent timings, oracle CPU baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import tempfile
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "atom·bead·steps/s of NEP-PIMD on 1 MI355X; student vs teacher at force RMSE"
+UNIT = "atom*bead*steps/s"
+
+# Published MI355X peaks.
+PEAK_FP32_VALU_TFLOPS = 157.3      # vector FP32 (packed); 78.6 without packed FP32 instructions
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="rocksalt4096")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-beads", type=int, default=0, help="oracle sample size in beads (0: auto)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (HBM counter calibration)")
+    ap.add_argument("--no-profile", action="store_true", help="do not bracket kernels with timing events")
+    return ap.parse_args()
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2409_04430_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+# ---------------------------------------------------------------------------
+# Algorithmic work of each kernel per (bead, atom).  Counting rule: add, mul
+# = 1 flop, FMA = 2, sqrt / reciprocal / sin / cos / tanh = 1, rounding and
+# conversions 0.  nR, nA: mean radial / angular neighbour counts.
+# ---------------------------------------------------------------------------
+
+def flops_per_atom(hp: dict, nR: float, nA: float) -> dict:
+    S, NR1, NA1 = hp["n_species"], hp["n_max_radial"] + 1, hp["n_max_angular"] + 1
+    KR1, KA1, H, D = hp["basis_radial"] + 1, hp["basis_angular"] + 1, hp["hidden"], hp["dim"]
+    four = hp["four_body"]
+    G = 18                                   # pair vector + minimum image (12) + r (6)
+    Bf = lambda K1: 13 + 6 * (K1 - 2)       # Chebyshev basis x cutoff
+    Bfd = lambda K1: 24 + 18 * (K1 - 2)     # basis and derivative
+    Ysh = 70                                 # 24 real spherical harmonics
+    desc = (nR * (G + Bf(KR1) + KR1) + S * 2 * NR1 * KR1
+            + nA * (G + 4 + Bf(KA1) + Ysh + 2 * NA1 * KA1 + 2 * NA1 * 24)
+            + 2 * NA1 * 24 + (40 * NA1 if four else 0)
+            + H * (4 * D + 7) + 2 * D + 2 * NA1 * 24 + S * 2 * NR1 * KR1)
+    force = (nR * (G + Bfd(KR1) + 2 * KR1 + 1 + 3 + 3 + 27)
+             + nA * (G + 4 + Bfd(KA1) + 4 * 2 * NA1 * KA1 + 8 * NA1 * 24 + Ysh + 48 + 24 + 160 + 5 + 15 + 3 + 27))
+    return {"descriptor": desc, "force": force}
+
+
+def bytes_per_atom(hp: dict, nR: float, nA: float, P: int) -> dict:
+    """Minimum HBM bytes per (bead, atom): every array read or written once."""
+    S, NA1 = hp["n_species"], hp["n_max_angular"] + 1
+    KRP = (hp["basis_radial"] + 1 + 3) // 4 * 4
+    lists = 4 * (nR + nA) + 2 * 4 * S
+    return {
+        "nlist": 24 + 4 + lists,
+        "descriptor": 24 + 4 + lists + 4 * NA1 * 24 + 4 * S * KRP,
+        "force": 24 + 4 + lists + 4 * NA1 * 24 + 4 * S * KRP + 12,
+        "trpmd": 3 * (8 + 8 + 4 + 8 + 8),
+    }
+
+
+def cpu_baseline(w, model_path, system, nb_req: int):
+    """The FP64 oracle (OpenMP over atoms) on a bounded sample of the same step."""
+    import oracle
+    M = oracle.Model(model_path)
+    P, N = system.P, system.N
+    nb = nb_req or 2
+    t0 = time.perf_counter()
+    M.beads(system.pos[:nb], system.types, system.box)
+    t_nep = time.perf_counter() - t0
+    if not nb_req:
+        per = t_nep / nb
+        nb2 = int(max(1, min(P - nb, math.floor(12.0 / max(per, 1e-3)))))
+        t0 = time.perf_counter()
+        M.beads(system.pos[nb:nb + nb2], system.types, system.box)
+        t_nep += time.perf_counter() - t0
+        nb += nb2
+    pos, vel = system.pos.copy(), system.vel.copy()
+    F = np.zeros_like(pos)
+    t0 = time.perf_counter()
+    oracle.trpmd_stage(pos, vel, F, system.masses, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed,
+                       step=1, stage=oracle.FUSED)
+    t_int = time.perf_counter() - t0
+    t_step = t_nep / nb * P + t_int
+    return {"value": N * P / t_step, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"NEP energy/forces/virial (brute-force neighbours) of {nb} of {P} beads x {N} atoms "
+                      f"({t_nep:.1f} s) plus one fused integrator stage over all beads ({t_int:.2f} s); "
+                      f"step time = per-bead NEP time x {P} + integrator time"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a "
+              f"design note, not an implementation", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2409_04430_amd import configs, lib
+    from paper_2409_04430_amd import inputs as I
+    from paper_2409_04430_amd.engine import NepPimd
+
+    w = configs.WORKLOADS[args.workload]
+    systems = w.systems()
+    if len(systems) != 1:
+        raise SystemExit("bench.py times single-system workloads")
+    s = systems[0]
+    tmp = tempfile.mkdtemp(prefix="neppimd_")
+    model_path = os.path.join(tmp, f"{w.name}.nep")
+    I.write_model(model_path, w.model())
+
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    eng = NepPimd(model_path, s, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=0)
+    eng.run(args.warmup)
+    eng.check()
+    lst = eng.nl.to_host()
+    nR = float(lst["cnt_radial"].sum(axis=1).mean())
+    nA = float(lst["cnt_angular"].sum(axis=1).mean())
+    hp = eng.model.hp
+
+    prof = not args.no_profile
+    lib.profile_read(reset=True)
+    if prof:
+        lib.profile_enable(True)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    eng.run(args.steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lib.profile_enable(False)
+    kt = lib.profile_read(reset=True)
+    mr, ma = eng.check()
+    gpu_ms = ev0.elapsed_time(ev1)
+    elapsed = max(gpu_ms / 1e3, 1e-12)
+    value = s.N * s.P * args.steps / elapsed
+
+    flops = flops_per_atom(hp, nR, nA)
+    byts = bytes_per_atom(hp, nR, nA, s.P)
+    units = s.N * s.P
+    kernels = {k: {"avg_us": 1e3 * v[0] / v[1], "launches": v[1]} for k, v in kt.items() if v[1]}
+    roof = None
+    if kernels:
+        dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+        avg_s = kernels[dom]["avg_us"] * 1e-6
+        if dom in flops:
+            ach = flops[dom] * units / avg_s / 1e12
+            roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_VALU_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
+                    "kernel": dom, "avg_us": round(kernels[dom]["avg_us"], 2),
+                    "flop_per_atom_bead": round(flops[dom], 1), "units_per_launch": units}
+        else:
+            ach = byts.get(dom, 0.0) * units / avg_s / 1e9
+            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": dom,
+                    "avg_us": round(kernels[dom]["avg_us"], 2)}
+        tr_path = os.path.join(ROOT, "profiles", "traffic.json")
+        if os.path.exists(tr_path):
+            tr = json.load(open(tr_path))
+            rec = tr.get(args.workload, {}).get(dom)
+            if rec and rec.get("source_hash") == source_hash():
+                roof["traffic"] = rec["bytes_per_launch"]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, model_path, s, args.cpu_beads)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": UNIT,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(gpu_ms / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}_p{s.P}", "atoms": s.N, "beads": s.P, "species": hp["n_species"],
+                   "cutoffs_A": [hp["rc_radial"], hp["rc_angular"]],
+                   "n_max": [hp["n_max_radial"], hp["n_max_angular"]], "l_max": hp["l_max"],
+                   "hidden": hp["hidden"], "mode": w.mode, "dt_fs": w.dt, "T_K": w.T,
+                   "mean_neighbours": [round(nR, 2), round(nA, 2)], "max_block_neighbours": [mr, ma],
+                   "arithmetic": "positions, integrator, force/energy/virial sums FP64; descriptors, network, "
+                                 "pair terms FP32",
+                   "wall_s": round(wall, 4)},
+        "roofline": roof,
+        "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -238,6 +238,26 @@ int32_t rp_normal_modes(const pimd_ctx *ctx, int32_t dir, const double *in, doub
 int32_t trpmd_step(const pimd_ctx *ctx, double *pos, double *vel, const float *F, int64_t step, int32_t stage,
                    hipStream_t stream);
 
+/* ------------------------------------------------------------------ */
+/* Kernel timing                                                       */
+/* ------------------------------------------------------------------ */
+
+/* Turn per-kernel timing on (on != 0) or off for the whole process.  While
+ * on, every kernel the library launches is bracketed by two hipEvents
+ * recorded on the caller's stream; events come from a library-owned pool. */
+int32_t nep_profile_enable(int32_t on);
+
+/* Number of kernel kinds and the name of kind `id` ("descriptor", "force",
+ * "nlist", "trpmd", ...); "" for an unknown id. */
+int32_t nep_profile_num_kernels(void);
+const char *nep_profile_kernel_name(int32_t id);
+
+/* Wait for every recorded launch, then write per-kind totals:
+ * total_ms[nep_profile_num_kernels()] (host) summed event-to-event
+ * durations, launches[...] (host) launch counts.  reset != 0 starts new
+ * totals.  Errors: NEP_ERR_INVALID_ARG, NEP_ERR_HIP. */
+int32_t nep_profile_read(double *total_ms, int64_t *launches, int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,8 +1,10 @@
 // Host side of libneppimd.so: error state, model file, handle lifetimes.
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 
 #include "internal.hpp"
@@ -32,6 +34,56 @@ bool box_lengths(const double box[9], double L[3])
     return true;
 }
 
+// ---------------------------------------------------------- profiling ---
+
+static const char *kKernelNames[K_NUM] = {"fill", "cell_count", "cell_scan", "cell_fill", "cell_sort", "nlist",
+                                          "descriptor", "force", "reduce", "trpmd", "modes"};
+static std::atomic<int> g_prof_on{0};
+static std::mutex g_prof_mu;
+struct ProfRecord {
+    int id;
+    hipEvent_t e0, e1;
+};
+static std::vector<ProfRecord> g_prof_pending;
+static std::vector<hipEvent_t> g_prof_pool;
+
+static hipEvent_t prof_event()
+{
+    // caller holds g_prof_mu
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+ProfScope::ProfScope(int kid, hipStream_t stream) : id(kid), s(stream)
+{
+    if (!g_prof_on.load(std::memory_order_relaxed)) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    e0 = prof_event();
+    if (e0 && hipEventRecord(e0, s) != hipSuccess) {
+        g_prof_pool.push_back(e0);
+        e0 = nullptr;
+    }
+}
+
+ProfScope::~ProfScope()
+{
+    if (!e0) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    hipEvent_t e1 = prof_event();
+    if (e1 && hipEventRecord(e1, s) == hipSuccess) {
+        g_prof_pending.push_back({id, e0, e1});
+    } else {
+        g_prof_pool.push_back(e0);
+        if (e1) g_prof_pool.push_back(e1);
+    }
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t n)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -42,6 +94,7 @@ void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s)
 {
     if (n == 0) return;
     unsigned g = (unsigned)((n + 255) / 256);
+    ProfScope ps(K_FILL, s);
     hipLaunchKernelGGL(k_fill_u32, dim3(g), dim3(256), 0, s, p, v, n);
 }
 
@@ -137,6 +190,46 @@ static void sh_norms(double *c)
 using namespace nep;
 
 extern "C" const char *nep_last_error(void) { return g_err.c_str(); }
+
+extern "C" int32_t nep_profile_enable(int32_t on)
+{
+    g_prof_on.store(on ? 1 : 0);
+    return NEP_OK;
+}
+
+extern "C" int32_t nep_profile_num_kernels(void) { return K_NUM; }
+
+extern "C" const char *nep_profile_kernel_name(int32_t id)
+{
+    return (id >= 0 && id < K_NUM) ? kKernelNames[id] : "";
+}
+
+extern "C" int32_t nep_profile_read(double *total_ms, int64_t *launches, int32_t reset)
+{
+    if (!total_ms || !launches) return fail(NEP_ERR_INVALID_ARG, "nep_profile_read: null argument");
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    static double acc_ms[K_NUM] = {0};
+    static int64_t acc_n[K_NUM] = {0};
+    for (auto &r : g_prof_pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.e1) != hipSuccess || hipEventElapsedTime(&ms, r.e0, r.e1) != hipSuccess)
+            return fail(NEP_ERR_HIP, "nep_profile_read: event query failed");
+        acc_ms[r.id] += ms;
+        acc_n[r.id] += 1;
+        g_prof_pool.push_back(r.e0);
+        g_prof_pool.push_back(r.e1);
+    }
+    g_prof_pending.clear();
+    for (int k = 0; k < K_NUM; ++k) {
+        total_ms[k] = acc_ms[k];
+        launches[k] = acc_n[k];
+        if (reset) {
+            acc_ms[k] = 0.0;
+            acc_n[k] = 0;
+        }
+    }
+    return NEP_OK;
+}
 
 extern "C" int32_t nep_load_params(const char *path, nep_model **out)
 {

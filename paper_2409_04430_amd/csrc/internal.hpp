@@ -83,6 +83,19 @@ inline int div_up(int a, int b) { return (a + b - 1) / b; }
 // Orthorhombic edge lengths from a row-vector cell; false if not orthorhombic.
 bool box_lengths(const double box[9], double L[3]);
 
+// Kernel timing (hipEvents around launches on the caller's stream), off by default.
+enum KernelId {
+    K_FILL = 0, K_CELL_COUNT, K_CELL_SCAN, K_CELL_FILL, K_CELL_SORT, K_NLIST,
+    K_DESCRIPTOR, K_FORCE, K_REDUCE, K_TRPMD, K_MODES, K_NUM
+};
+struct ProfScope {
+    int id;
+    hipStream_t s;
+    hipEvent_t e0 = nullptr;
+    ProfScope(int kid, hipStream_t stream);
+    ~ProfScope();
+};
+
 // Zero-fill on a stream by a kernel (capturable into graphs).
 void fill_u32(uint32_t *p, uint32_t v, size_t n, hipStream_t s);
 void fill_i32(int32_t *p, int32_t v, size_t n, hipStream_t s);

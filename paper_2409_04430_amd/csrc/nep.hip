@@ -571,8 +571,14 @@ template <int NR1, int NA1, bool FOUR>
 static void launch(const NepArgs &a, const float *prm, int P, hipStream_t s)
 {
     const dim3 g(div_up(a.N, kBlock), P);
-    hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR>), g, dim3(kBlock), 0, s, a, prm);
-    hipLaunchKernelGGL((k_force<NR1, NA1, 9, 9, FOUR>), g, dim3(kBlock), 0, s, a, prm);
+    {
+        ProfScope ps_(K_DESCRIPTOR, s);
+        hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR>), g, dim3(kBlock), 0, s, a, prm);
+    }
+    {
+        ProfScope ps_(K_FORCE, s);
+        hipLaunchKernelGGL((k_force<NR1, NA1, 9, 9, FOUR>), g, dim3(kBlock), 0, s, a, prm);
+    }
 }
 
 }  // namespace nep
@@ -623,7 +629,10 @@ extern "C" int32_t nep_compute(const nep_model *m, const nep_nlist *nl, nep_ws *
     case 881: launch<9, 9, true>(a, m->dev, P, s); break;
     default: return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");
     }
-    hipLaunchKernelGGL(k_reduce, dim3(P), dim3(64), 0, s, ws->partE, ws->partW, ws->nblk, E, W);
+    {
+        ProfScope ps_(K_REDUCE, s);
+        hipLaunchKernelGGL(k_reduce, dim3(P), dim3(64), 0, s, ws->partE, ws->partW, ws->nblk, E, W);
+    }
     NEP_HIP(hipGetLastError());
     return NEP_OK;
 }

@@ -271,14 +271,29 @@ extern "C" int32_t neighbor_build(const nep_model *m, nep_nlist *nl, const doubl
     const double rcA2 = m->hp.rc_angular * m->hp.rc_angular;
     fill_i32(nl->cell_cnt, 0, (size_t)P * g.ncell, s);
     const dim3 ga(div_up(N, kBlock), P);
-    hipLaunchKernelGGL(k_cell_count, ga, dim3(kBlock), 0, s, pos, types, N, nl->S, g, nl->cell_cnt, nl->status);
-    hipLaunchKernelGGL(k_cell_scan, dim3(P), dim3(1024), 0, s, nl->cell_cnt, nl->cell_start, g.ncell);
-    hipLaunchKernelGGL(k_cell_fill, ga, dim3(kBlock), 0, s, pos, N, g, nl->cell_cnt, nl->cell_start,
-                       nl->cell_atoms);
-    hipLaunchKernelGGL(k_cell_sort, dim3(div_up(g.ncell, kBlock), P), dim3(kBlock), 0, s, N, g.ncell,
-                       nl->cell_start, nl->cell_atoms);
-    hipLaunchKernelGGL(k_nlist, ga, dim3(kBlock), 0, s, pos, types, N, nl->S, g, nl->cell_start, nl->cell_atoms,
-                       rcR2, rcA2, nl->capR, nl->capA, nl->cntR, nl->idxR, nl->cntA, nl->idxA, nl->status);
+    {
+        ProfScope ps_(K_CELL_COUNT, s);
+        hipLaunchKernelGGL(k_cell_count, ga, dim3(kBlock), 0, s, pos, types, N, nl->S, g, nl->cell_cnt, nl->status);
+    }
+    {
+        ProfScope ps_(K_CELL_SCAN, s);
+        hipLaunchKernelGGL(k_cell_scan, dim3(P), dim3(1024), 0, s, nl->cell_cnt, nl->cell_start, g.ncell);
+    }
+    {
+        ProfScope ps_(K_CELL_FILL, s);
+        hipLaunchKernelGGL(k_cell_fill, ga, dim3(kBlock), 0, s, pos, N, g, nl->cell_cnt, nl->cell_start,
+                           nl->cell_atoms);
+    }
+    {
+        ProfScope ps_(K_CELL_SORT, s);
+        hipLaunchKernelGGL(k_cell_sort, dim3(div_up(g.ncell, kBlock), P), dim3(kBlock), 0, s, N, g.ncell,
+                           nl->cell_start, nl->cell_atoms);
+    }
+    {
+        ProfScope ps_(K_NLIST, s);
+        hipLaunchKernelGGL(k_nlist, ga, dim3(kBlock), 0, s, pos, types, N, nl->S, g, nl->cell_start, nl->cell_atoms,
+                           rcR2, rcA2, nl->capR, nl->capA, nl->cntR, nl->idxR, nl->cntA, nl->idxA, nl->status);
+    }
     NEP_HIP(hipGetLastError());
     return NEP_OK;
 }

@@ -215,13 +215,19 @@ __global__ __launch_bounds__(256) void k_modes(const double *__restrict__ in, do
 template <int P>
 static void launch_step(const StepArgs &a, const double *cst, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_trpmd<P>, dim3(div_up(3 * a.N, 256)), dim3(256), 0, s, a, cst);
+    {
+        ProfScope ps_(K_TRPMD, s);
+        hipLaunchKernelGGL(k_trpmd<P>, dim3(div_up(3 * a.N, 256)), dim3(256), 0, s, a, cst);
+    }
 }
 
 template <int P>
 static void launch_modes(const double *in, double *out, int M, int dir, const double *cst, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_modes<P>, dim3(div_up(M, 256)), dim3(256), 0, s, in, out, M, dir, cst);
+    {
+        ProfScope ps_(K_MODES, s);
+        hipLaunchKernelGGL(k_modes<P>, dim3(div_up(M, 256)), dim3(256), 0, s, in, out, M, dir, cst);
+    }
 }
 
 #define NEP_P_CASES(X)                                                                                  \

@@ -78,6 +78,10 @@ _sig = {
     "pimd_destroy": (None, [_vp]),
     "rp_normal_modes": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "trpmd_step": (_i32, [_vp, _vp, _vp, _vp, C.c_int64, _i32, _vp]),
+    "nep_profile_enable": (_i32, [_i32]),
+    "nep_profile_num_kernels": (_i32, []),
+    "nep_profile_kernel_name": (C.c_char_p, [_i32]),
+    "nep_profile_read": (_i32, [C.POINTER(C.c_double), C.POINTER(C.c_int64), _i32]),
 }
 for _n, (_r, _a) in _sig.items():
     _f = getattr(_lib, _n)
@@ -268,6 +272,19 @@ class Pimd:
 def _torch():
     import torch
     return torch
+
+
+def profile_enable(on: bool = True):
+    _check(_lib.nep_profile_enable(int(on)))
+
+
+def profile_read(reset: bool = True) -> dict:
+    """{kernel name: (total_ms, launches)} of the launches recorded so far."""
+    n = _lib.nep_profile_num_kernels()
+    ms = (C.c_double * n)()
+    cnt = (C.c_int64 * n)()
+    _check(_lib.nep_profile_read(ms, cnt, int(reset)))
+    return {_lib.nep_profile_kernel_name(k).decode(): (ms[k], cnt[k]) for k in range(n)}
 
 
 _hip = None
