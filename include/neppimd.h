@@ -127,7 +127,11 @@ void nep_nlist_destroy(nep_nlist *nl);
  * minimum image of d = r_i' - r_i is d - L rint(d / L) per axis and the test
  * is (dx*dx + dy*dy) + dz*dz < rc*rc, all in IEEE FP64 without contraction,
  * so the sets are exactly those of a brute-force search (Sec. II.A: periodic
- * boundary conditions).  pos [P][N][3] dev, types [N] dev, box host[9].
+ * boundary conditions).  Candidates come from one cell-list search over the
+ * ring-polymer centroids with radius rc + 2 D, D the largest bead-to-centroid
+ * distance measured on the device in the same call; every bead pair closer
+ * than rc has centroids closer than rc + 2 D, so filtering the candidates
+ * bead by bead loses nothing.  pos [P][N][3] dev, types [N] dev, box host[9].
  * Errors: NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED (non-orthorhombic box),
  * NEP_ERR_BOX_TOO_SMALL (an edge < 2 rc_radial), NEP_ERR_HIP, NEP_ERR_NOMEM.
  * Overflow of a capacity sets NEP_FLAG_NEIGHBOR_OVERFLOW (the list then
@@ -151,9 +155,12 @@ typedef struct nep_nlist_layout {
 int32_t nep_nlist_view(const nep_nlist *nl, nep_nlist_layout *out);
 
 typedef struct nep_nlist_status {
-    uint32_t flags;          /* nep_flag_bits seen by neighbor_build */
-    int32_t max_radial;      /* largest per-species-block radial count seen */
-    int32_t max_angular;     /* largest per-species-block angular count seen */
+    uint32_t flags;              /* nep_flag_bits seen by neighbor_build */
+    int32_t max_radial;          /* largest per-species-block radial count seen */
+    int32_t max_angular;         /* largest per-species-block angular count seen */
+    int32_t max_candidates;      /* largest centroid candidate count seen */
+    int32_t capacity_candidates; /* candidate capacity: 2 n_species cap_radial + 32 (at most 8192) */
+    float bead_spread;           /* largest distance of a bead from its centroid in the last build, A */
 } nep_nlist_status;
 
 /* Synchronise `stream`, read the sticky status of the lists into *out and,

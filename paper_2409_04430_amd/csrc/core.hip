@@ -36,8 +36,9 @@ bool box_lengths(const double box[9], double L[3])
 
 // ---------------------------------------------------------- profiling ---
 
-static const char *kKernelNames[K_NUM] = {"fill", "cell_count", "cell_scan", "cell_fill", "cell_sort", "nlist",
-                                          "descriptor", "force", "reduce", "trpmd", "modes"};
+static const char *kKernelNames[K_NUM] = {"fill", "centroid", "grid", "cell_count", "cell_scan", "cell_fill",
+                                          "cell_sort", "candidates", "nlist",
+                                          "descriptor", "force_ang", "force", "reduce", "trpmd", "modes"};
 static std::atomic<int> g_prof_on{0};
 static std::mutex g_prof_mu;
 struct ProfRecord {
@@ -335,21 +336,28 @@ extern "C" int32_t nep_nlist_create(const nep_model *m, int32_t P, int32_t N, in
                                     nep_nlist **out)
 {
     if (!m || !out) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_create: null argument");
-    if (P < 0 || N < 0 || capR < 1 || capA < 1 || capR > 4096 || capA > 4096)
+    if (P < 0 || N < 0 || capR < 1 || capA < 1 || capR > 4096 || capA > 4096 || N > (1 << 29))
         return fail(NEP_ERR_INVALID_ARG, "nep_nlist_create: bad sizes P=%d N=%d caps=%d/%d", P, N, capR, capA);
     *out = nullptr;
     nep_nlist *nl = new (std::nothrow) nep_nlist;
     if (!nl) return fail(NEP_ERR_NOMEM, "host allocation failed");
     nl->P = P; nl->N = N; nl->S = m->hp.n_species; nl->capR = capR; nl->capA = capA;
+    nl->capC = 2 * nl->S * capR + 32;
+    if (nl->capC > 8192) nl->capC = 8192;
     const size_t PSN = (size_t)P * nl->S * N;
     hipError_t e = hipGetDevice(&nl->device);
     if (e == hipSuccess) e = dalloc(&nl->cntR, PSN);
     if (e == hipSuccess) e = dalloc(&nl->cntA, PSN);
     if (e == hipSuccess) e = dalloc(&nl->idxR, PSN * capR);
     if (e == hipSuccess) e = dalloc(&nl->idxA, PSN * capA);
-    if (e == hipSuccess) e = dalloc(&nl->cell_atoms, (size_t)P * N);
-    if (e == hipSuccess) e = dalloc(&nl->status, 4);
-    if (e == hipSuccess) e = hipMemset(nl->status, 0, 4 * sizeof(uint32_t));
+    if (e == hipSuccess) e = dalloc(&nl->cen, (size_t)N * 3);
+    if (e == hipSuccess) e = dalloc(&nl->cand, (size_t)N * nl->capC);
+    if (e == hipSuccess) e = dalloc(&nl->candN, (size_t)N);
+    if (e == hipSuccess) e = dalloc(&nl->cell_atoms, (size_t)N);
+    if (e == hipSuccess) e = dalloc(&nl->grid, 8);
+    if (e == hipSuccess) e = dalloc(&nl->status, 8);
+    if (e == hipSuccess) e = hipMemset(nl->status, 0, 8 * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(nl->grid, 0, 8 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipMemset(nl->cntR, 0, sizeof(int32_t) * (PSN ? PSN : 1));
     if (e == hipSuccess) e = hipMemset(nl->cntA, 0, sizeof(int32_t) * (PSN ? PSN : 1));
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -365,8 +373,9 @@ extern "C" int32_t nep_nlist_create(const nep_model *m, int32_t P, int32_t N, in
 extern "C" void nep_nlist_destroy(nep_nlist *nl)
 {
     if (!nl) return;
-    for (void *p : {(void *)nl->cntR, (void *)nl->idxR, (void *)nl->cntA, (void *)nl->idxA,
-                    (void *)nl->cell_cnt, (void *)nl->cell_start, (void *)nl->cell_atoms, (void *)nl->status})
+    for (void *p : {(void *)nl->cntR, (void *)nl->idxR, (void *)nl->cntA, (void *)nl->idxA, (void *)nl->cen,
+                    (void *)nl->cand, (void *)nl->candN, (void *)nl->cell_cnt, (void *)nl->cell_start,
+                    (void *)nl->cell_atoms, (void *)nl->grid, (void *)nl->status})
         if (p) (void)hipFree(p);
     delete nl;
 }
@@ -384,20 +393,26 @@ extern "C" int32_t nep_nlist_view(const nep_nlist *nl, nep_nlist_layout *out)
 extern "C" int32_t nep_nlist_poll(nep_nlist *nl, nep_nlist_status *out, int32_t clear, hipStream_t s)
 {
     if (!nl || !out) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_poll: null argument");
-    uint32_t h[4];
+    uint32_t h[8];
     NEP_HIP(hipStreamSynchronize(s));
     NEP_HIP(hipMemcpy(h, nl->status, sizeof h, hipMemcpyDeviceToHost));
     out->flags = h[0];
     out->max_radial = (int32_t)h[1];
     out->max_angular = (int32_t)h[2];
+    out->max_candidates = (int32_t)h[3];
+    out->capacity_candidates = nl->capC;
+    float spread;
+    std::memcpy(&spread, &h[4], sizeof spread);
+    out->bead_spread = spread;
     if (clear) {
-        fill_u32(nl->status, 0u, 4, s);
+        fill_u32(nl->status, 0u, 8, s);
         NEP_HIP(hipGetLastError());
         NEP_HIP(hipStreamSynchronize(s));
     }
     if (h[0] & NEP_FLAG_NEIGHBOR_OVERFLOW)
-        return fail(NEP_ERR_NEIGHBOR_OVERFLOW, "neighbour list overflow (largest counts %u/%u, capacities %d/%d)",
-                    h[1], h[2], nl->capR, nl->capA);
+        return fail(NEP_ERR_NEIGHBOR_OVERFLOW,
+                    "neighbour list overflow (largest counts %u/%u/%u, capacities %d/%d/%d)", h[1], h[2], h[3],
+                    nl->capR, nl->capA, nl->capC);
     return NEP_OK;
 }
 
@@ -419,7 +434,8 @@ extern "C" int32_t nep_ws_create(const nep_model *m, int32_t P, int32_t N, nep_w
     if (e == hipSuccess) e = dalloc(&w->B, PN * w->NA1 * kNumSH);
     if (e == hipSuccess) e = dalloc(&w->arad, PN * w->S * w->KRP);
     if (e == hipSuccess) e = dalloc(&w->partE, (size_t)P * w->nblk);
-    if (e == hipSuccess) e = dalloc(&w->partW, (size_t)P * w->nblk * 9);
+    if (e == hipSuccess) e = dalloc(&w->partW, (size_t)2 * P * w->nblk * 9);
+    if (e == hipSuccess) e = dalloc(&w->Fang, PN * 3);
     if (e == hipSuccess) e = dalloc(&w->flags, 4);
     if (e == hipSuccess) e = hipMemset(w->flags, 0, 4 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -435,7 +451,8 @@ extern "C" int32_t nep_ws_create(const nep_model *m, int32_t P, int32_t N, nep_w
 extern "C" void nep_ws_destroy(nep_ws *w)
 {
     if (!w) return;
-    for (void *p : {(void *)w->B, (void *)w->arad, (void *)w->partE, (void *)w->partW, (void *)w->flags})
+    for (void *p : {(void *)w->B, (void *)w->arad, (void *)w->partE, (void *)w->partW, (void *)w->Fang,
+                    (void *)w->flags})
         if (p) (void)hipFree(p);
     delete w;
 }

@@ -47,10 +47,17 @@ struct nep_nlist {
     int P = 0, N = 0, S = 0, capR = 0, capA = 0;
     int device = 0;
     int32_t *cntR = nullptr, *idxR = nullptr, *cntA = nullptr, *idxA = nullptr;
-    // cell list (grown on demand): cell_cnt [P][ncell], cell_start [P][ncell+1], cell_atoms [P][N]
+    // Ring-polymer centroids and the candidate lists they give (shared by all beads).
+    int capC = 0;
+    double *cen = nullptr;        // [N][3]
+    int32_t *cand = nullptr;      // [capC][N], entries (j << 2) | species
+    int32_t *candN = nullptr;     // [N]
+    // Centroid cell list (grown on demand): cell_cnt [ncell], cell_start [ncell+1], cell_atoms [N].
     int ncell_alloc = 0;
     int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_atoms = nullptr;
-    uint32_t *status = nullptr;   // [0] flags, [1] max radial, [2] max angular
+    uint32_t *grid = nullptr;     // device-chosen grid: nc[3], ncell, spread bits, pad, R^2 (double)
+    uint32_t *status = nullptr;   // [0] flags, [1] max radial, [2] max angular, [3] max candidates,
+                                  // [4] largest bead-to-centroid distance (float bits)
 };
 
 struct nep_ws {
@@ -60,7 +67,8 @@ struct nep_ws {
     float *B = nullptr;        // [P*N][NA1*24] angular adjoints dU_i/dA_nlm
     float *arad = nullptr;     // [P*N][S][KRP] radial adjoints sum_n dU_i/dq_n c_nk
     double *partE = nullptr;   // [P][nblk]
-    double *partW = nullptr;   // [P][nblk][9]
+    double *partW = nullptr;   // [2][P][nblk][9] (angular pass, radial pass)
+    float *Fang = nullptr;     // [P*N][3] angular part of the forces
     uint32_t *flags = nullptr; // [1]
 };
 
@@ -80,13 +88,28 @@ constexpr int kBlock = 256;
 
 inline int div_up(int a, int b) { return (a + b - 1) / b; }
 
+// (bead, tile) of this workgroup for a grid (tiles, beads).  Workgroups are
+// handed to the 8 XCDs round-robin in linear order; when the grid size is a
+// multiple of 8 the linear id is permuted so that each XCD receives one
+// contiguous run of (bead, tile) pairs, i.e. works through a few beads at a
+// time and their gathers stay in its own L2.
+__device__ __forceinline__ void bead_tile(int &bead, int &tile)
+{
+    const int nt = gridDim.x;
+    const int total = nt * gridDim.y;
+    int lin = blockIdx.y * nt + blockIdx.x;
+    if ((total & 7) == 0) lin = (lin & 7) * (total >> 3) + (lin >> 3);
+    bead = lin / nt;
+    tile = lin - bead * nt;
+}
+
 // Orthorhombic edge lengths from a row-vector cell; false if not orthorhombic.
 bool box_lengths(const double box[9], double L[3]);
 
 // Kernel timing (hipEvents around launches on the caller's stream), off by default.
 enum KernelId {
-    K_FILL = 0, K_CELL_COUNT, K_CELL_SCAN, K_CELL_FILL, K_CELL_SORT, K_NLIST,
-    K_DESCRIPTOR, K_FORCE, K_REDUCE, K_TRPMD, K_MODES, K_NUM
+    K_FILL = 0, K_CENTROID, K_GRID, K_CELL_COUNT, K_CELL_SCAN, K_CELL_FILL, K_CELL_SORT, K_CANDIDATES, K_NLIST,
+    K_DESCRIPTOR, K_FORCE_ANG, K_FORCE, K_REDUCE, K_TRPMD, K_MODES, K_NUM
 };
 struct ProfScope {
     int id;

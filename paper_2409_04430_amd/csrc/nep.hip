@@ -1,22 +1,24 @@
 // NEP energy, forces and virial on gfx950 (site-energy model of Sec. II.C,
 // bead forces and virial of Sec. II.A of arXiv:2409.04430).
 //
-// Three kernels per call, one lane per (bead, atom):
+// Four kernels per call, one lane per (bead, atom):
 //   k_descriptor  radial sums, angular sums A_nlm = sum_j g_n(r_ij) Y_lm(u_ij)
 //                 over real orthonormal spherical harmonics, q_nl = sum_m A_nlm^2
 //                 (equal to the Legendre double sum by the addition theorem),
 //                 the optional (2,2,2) four-body invariant, the tanh network,
 //                 and the adjoints: B_nlm = dU_i/dA_nlm and the radial
 //                 a_k(t) = sum_n dU_i/dq_n c^{ti t}_nk;
-//   k_force       gather form F_i = sum_j (dU_i/dr_ij - dU_j/dr_ji) using the
-//                 neighbour's adjoints, so no atomics: the angular pair term
-//                 is one contraction with B^i_nlm g^{ij}_n + (-1)^l B^j_nlm g^{ji}_n;
-//                 per-atom virial -1/2 sum_j r_ij (x) (dU_i/dr_ij - dU_j/dr_ji);
+//   k_force_ang   angular pair terms in gather form, one contraction with
+//                 B^i_nlm g^{ij}_n + (-1)^l B^j_nlm g^{ji}_n per neighbour, so
+//                 F_i = sum_j (dU_i/dr_ij - dU_j/dr_ji) needs no atomics;
+//   k_force_rad   radial pair terms (a^i_k(tj) + a^j_k(ti)) f'_k(r) u, added to
+//                 the angular part; per-atom virial -1/2 sum_j r_ij (x) phi_ij;
 //   k_reduce      per-bead energy and virial from per-block partial sums in
 //                 a fixed order (bitwise reproducible).
-// Waves run species-uniform: the lanes of a wave are processed in groups
-// that share the centre species, which makes every model-coefficient address
-// wave-uniform (scalar loads, SGPR operands).
+// The descriptor and angular-force passes run species-uniform groups of
+// lanes, which makes every model-coefficient address wave-uniform (scalar
+// loads, SGPR operands).  Neighbour loops prefetch the next index and
+// position so that gathers overlap arithmetic.
 #include "internal.hpp"
 
 namespace nep {
@@ -28,7 +30,7 @@ struct NepArgs {
     const int32_t *types;
     int N, S, H;
     double L[3], invL[3];
-    float rcR, rcA, rcRinv, rcAinv;
+    float rcRinv, rcAinv;
     float kappa4;
     // lists
     const int32_t *cntR, *idxR, *cntA, *idxA;
@@ -36,8 +38,9 @@ struct NepArgs {
     // workspace
     float *B;
     float *arad;
+    float *Fang;
     int KRP;
-    double *partE, *partW;
+    double *partE, *partWa, *partWr;
     uint32_t *flags;
     // outputs
     float *F;
@@ -48,10 +51,10 @@ struct NepArgs {
 };
 
 // Pair vector r_j - r_i under the minimum image, formed in FP64, returned in FP32.
-__device__ __forceinline__ void pair_vec(const double *__restrict__ pb, double xi, double yi, double zi, int j,
+__device__ __forceinline__ void pair_vec(double xj, double yj, double zj, double xi, double yi, double zi,
                                          const NepArgs &a, float &dx, float &dy, float &dz)
 {
-    double x = pb[3 * j] - xi, y = pb[3 * j + 1] - yi, z = pb[3 * j + 2] - zi;
+    double x = xj - xi, y = yj - yi, z = zj - zi;
     x -= a.L[0] * rint(x * a.invL[0]);
     y -= a.L[1] * rint(y * a.invL[1]);
     z -= a.L[2] * rint(z * a.invL[2]);
@@ -60,12 +63,41 @@ __device__ __forceinline__ void pair_vec(const double *__restrict__ pb, double x
     dz = (float)z;
 }
 
-// f_k(r) = (T_k(x) + 1)/2 f_c(r), x = 2 (r/rc - 1)^2 - 1.
+// sin(pi z) and cos(pi z) for z in [0, 1]: with w = z - 1/2, cos(pi z) =
+// -sin(pi w) and sin(pi z) = cos(pi w), and |pi w| <= pi/2, where the Taylor
+// series through x^13 (sin) and x^14 (cos) is accurate to ~2e-7 in FP32.
+__device__ __forceinline__ void sincospi01(float z, float &s, float &c)
+{
+    const float x = kPi * (z - 0.5f);
+    const float x2 = x * x;
+    float ps = (float)(-1.0 / 6227020800.0);
+    ps = ps * x2 + (float)(1.0 / 39916800.0);
+    ps = ps * x2 + (float)(-1.0 / 362880.0);
+    ps = ps * x2 + (float)(1.0 / 5040.0);
+    ps = ps * x2 + (float)(-1.0 / 120.0);
+    ps = ps * x2 + (float)(1.0 / 6.0);
+    float sw = x - x * x2 * ps;
+    float pc = (float)(-1.0 / 87178291200.0);
+    pc = pc * x2 + (float)(1.0 / 479001600.0);
+    pc = pc * x2 + (float)(-1.0 / 3628800.0);
+    pc = pc * x2 + (float)(1.0 / 40320.0);
+    pc = pc * x2 + (float)(-1.0 / 720.0);
+    pc = pc * x2 + (float)(1.0 / 24.0);
+    pc = pc * x2 + (float)(-1.0 / 2.0);
+    float cw = 1.0f + x2 * pc;
+    c = -sw;
+    s = cw;
+}
+
+// f_k(r) = (T_k(x) + 1)/2 f_c(r), x = 2 (r/rc - 1)^2 - 1, f_c = (1 + cos(pi r/rc))/2.
 template <int K1>
 __device__ __forceinline__ void cheb_f(float r, float rcinv, float *f)
 {
-    const float fc = 0.5f + 0.5f * cosf(kPi * r * rcinv);
-    const float y = r * rcinv - 1.0f;
+    float sn, cs;
+    const float z = r * rcinv;
+    sincospi01(z, sn, cs);
+    const float fc = 0.5f + 0.5f * cs;
+    const float y = z - 1.0f;
     const float x = 2.0f * y * y - 1.0f;
     float t0 = 1.0f, t1 = x;
     f[0] = fc;
@@ -84,10 +116,11 @@ template <int K1>
 __device__ __forceinline__ void cheb_fd(float r, float rcinv, float *f, float *fp)
 {
     float sn, cs;
-    sincosf(kPi * r * rcinv, &sn, &cs);
+    const float z = r * rcinv;
+    sincospi01(z, sn, cs);
     const float fc = 0.5f + 0.5f * cs;
     const float fcp = -0.5f * kPi * rcinv * sn;
-    const float y = r * rcinv - 1.0f;
+    const float y = z - 1.0f;
     const float x = 2.0f * y * y - 1.0f;
     const float dx = 4.0f * y * rcinv;
     float t0 = 1.0f, t1 = x, d0 = 0.0f, d1 = 1.0f;
@@ -218,18 +251,42 @@ __device__ __forceinline__ double block_sum(double v, double *lds)
     return r;
 }
 
+// Four-body helper: M_n = sum_j g_n (u u^T - I/3) rebuilt from the l = 2 sums
+// (slots 3..7 hold m = -2..2): returns mxy, myz, mzz, mxz, d = mxx - myy.
+__device__ __forceinline__ void m_from_l2(const float *A2, const float *shc, float *M)
+{
+    M[0] = A2[0] / shc[3];
+    M[1] = A2[1] / shc[4];
+    M[2] = A2[2] / (3.0f * shc[5]);
+    M[3] = A2[3] / shc[6];
+    M[4] = A2[4] / shc[7];
+}
+
+constexpr int kBatch = 4;   // neighbours whose index and position are loaded together
+
+// Hide a uniform pointer from loop-invariant code motion, so that the model
+// coefficients it addresses are re-read through the scalar cache inside a
+// neighbour loop instead of being hoisted into (scarce) vector registers.
+__device__ __forceinline__ const float *launder(const float *p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
 // ----------------------------------------------------------- pass 1 ---
 
 template <int NR1, int NA1, int KR1, int KA1, bool FOUR>
-__global__ __launch_bounds__(kBlock) void k_descriptor(NepArgs a, const float *__restrict__ prm)
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+void k_descriptor(NepArgs a, const float *__restrict__ prm)
 {
     constexpr int D = Dims<NR1, NA1, FOUR>::D;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
+    int b, tile;
+    bead_tile(b, tile);
+    const int i = tile * blockDim.x + threadIdx.x;
     const int N = a.N, S = a.S;
     const bool valid = i < N;
     const int ii = valid ? i : N - 1;
-    int ti = a.types[ii];
+    const int ti = a.types[ii];
     const bool tok = ti >= 0 && ti < S;
     const double *pb = a.pos + (size_t)b * N * 3;
     const double xi = pb[3 * ii], yi = pb[3 * ii + 1], zi = pb[3 * ii + 2];
@@ -256,15 +313,29 @@ __global__ __launch_bounds__(kBlock) void k_descriptor(NepArgs a, const float *_
             float sk[KR1];
 #pragma unroll
             for (int k = 0; k < KR1; ++k) sk[k] = 0.0f;
-            for (int s = 0; s < cnt; ++s) {
-                const int j = ix[(size_t)s * N];
-                float dx, dy, dz;
-                pair_vec(pb, xi, yi, zi, j, a, dx, dy, dz);
-                const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-                float f[KR1];
-                cheb_f<KR1>(r, a.rcRinv, f);
+            for (int s0 = 0; s0 < cnt; s0 += kBatch) {
+                int jj[kBatch];
 #pragma unroll
-                for (int k = 0; k < KR1; ++k) sk[k] += f[k];
+                for (int u = 0; u < kBatch; ++u) jj[u] = (s0 + u < cnt) ? ix[(size_t)(s0 + u) * N] : i;
+                double px[kBatch], py[kBatch], pz[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    px[u] = pb[3 * jj[u]];
+                    py[u] = pb[3 * jj[u] + 1];
+                    pz[u] = pb[3 * jj[u] + 2];
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    if (s0 + u < cnt) {
+                        float dx, dy, dz;
+                        pair_vec(px[u], py[u], pz[u], xi, yi, zi, a, dx, dy, dz);
+                        const float r = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
+                        float f[KR1];
+                        cheb_f<KR1>(r, a.rcRinv, f);
+#pragma unroll
+                        for (int k = 0; k < KR1; ++k) sk[k] += f[k];
+                    }
+                }
             }
             const float *c = prm + a.oR + (tc * S + t) * NR1 * KR1;
 #pragma unroll
@@ -287,12 +358,21 @@ __global__ __launch_bounds__(kBlock) void k_descriptor(NepArgs a, const float *_
             const int cnt = min(a.cntA[blk * N + i], a.capA);
             const int32_t *ix = a.idxA + blk * a.capA * N + i;
             const float *c = prm + a.oA + (tc * S + t) * NA1 * KA1;
+            int jn = cnt > 0 ? ix[0] : i;
+            double nx = pb[3 * jn], ny = pb[3 * jn + 1], nz = pb[3 * jn + 2];
             for (int s = 0; s < cnt; ++s) {
-                const int j = ix[(size_t)s * N];
+                const double cx = nx, cy = ny, cz = nz;
+                if (s + 1 < cnt) {
+                    jn = ix[(size_t)(s + 1) * N];
+                    nx = pb[3 * jn];
+                    ny = pb[3 * jn + 1];
+                    nz = pb[3 * jn + 2];
+                }
                 float dx, dy, dz;
-                pair_vec(pb, xi, yi, zi, j, a, dx, dy, dz);
-                const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-                const float rinv = 1.0f / r;
+                pair_vec(cx, cy, cz, xi, yi, zi, a, dx, dy, dz);
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float rinv = __builtin_amdgcn_rsqf(r2);
+                const float r = r2 * rinv;
                 float f[KA1];
                 cheb_f<KA1>(r, a.rcAinv, f);
                 float Y[kNumSH];
@@ -317,21 +397,25 @@ __global__ __launch_bounds__(kBlock) void k_descriptor(NepArgs a, const float *_
                     if (sh_l(m) == l) s2 += A[n][m] * A[n][m];
                 q[NR1 + (l - 1) * NA1 + n] = s2;
             }
-        }
-        // four-body: M_n = sum_j g_n (u u^T - I/3) rebuilt from the l = 2 sums
-        float Mc[FOUR ? NA1 : 1][5];   // mxy, myz, mzz, mxz, d = mxx - myy
-        if (FOUR) {
-#pragma unroll
-            for (int n = 0; n < (FOUR ? NA1 : 1); ++n) {
-                const float mxy = A[n][3] / shc[3], myz = A[n][4] / shc[4];
-                const float mzz = A[n][5] / (3.0f * shc[5]), mxz = A[n][6] / shc[6], dd = A[n][7] / shc[7];
+            if (FOUR) {
+                float M[5];
+                m_from_l2(&A[n][3], shc, M);
+                const float mxy = M[0], myz = M[1], mzz = M[2], mxz = M[3], dd = M[4];
                 const float mxx = 0.5f * (dd - mzz), myy = 0.5f * (-dd - mzz);
-                Mc[n][0] = mxy; Mc[n][1] = myz; Mc[n][2] = mzz; Mc[n][3] = mxz; Mc[n][4] = dd;
                 const float tr3 = mxx * mxx * mxx + myy * myy * myy + mzz * mzz * mzz +
                                   3.0f * mxx * (mxy * mxy + mxz * mxz) + 3.0f * myy * (mxy * mxy + myz * myz) +
                                   3.0f * mzz * (mxz * mxz + myz * myz) + 6.0f * mxy * myz * mxz;
                 q[NR1 + kLmax * NA1 + n] = a.kappa4 * tr3;
             }
+        }
+        // park A in this atom's adjoint row (overwritten with B below)
+        float *Bo = a.B + ((size_t)b * N + i) * (NA1 * kNumSH);
+#pragma unroll
+        for (int n = 0; n < NA1; ++n) {
+            float4 *o4 = reinterpret_cast<float4 *>(Bo + n * kNumSH);
+#pragma unroll
+            for (int q4 = 0; q4 < kNumSH / 4; ++q4)
+                o4[q4] = make_float4(A[n][4 * q4], A[n][4 * q4 + 1], A[n][4 * q4 + 2], A[n][4 * q4 + 3]);
         }
 
         // network: U = sum_mu w1 tanh(sum_nu W0 s_nu q_nu - b0) - b1;  G_nu = dU/dq_nu
@@ -360,17 +444,25 @@ __global__ __launch_bounds__(kBlock) void k_descriptor(NepArgs a, const float *_
         for (int v = 0; v < D; ++v) G[v] *= qs[v];
         U = u;
 
-        // adjoints: B_nlm = dU/dA_nlm
-        float *Bo = a.B + ((size_t)b * N + i) * (NA1 * kNumSH);
+        // adjoints: B_nlm = dU/dA_nlm (A read back from the parked row)
 #pragma unroll
         for (int n = 0; n < NA1; ++n) {
+            float An[kNumSH];
+            float4 *o4 = reinterpret_cast<float4 *>(Bo + n * kNumSH);
+#pragma unroll
+            for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
+                const float4 v4 = o4[q4];
+                An[4 * q4] = v4.x; An[4 * q4 + 1] = v4.y; An[4 * q4 + 2] = v4.z; An[4 * q4 + 3] = v4.w;
+            }
             float Bn[kNumSH];
 #pragma unroll
-            for (int m = 0; m < kNumSH; ++m) Bn[m] = 2.0f * G[NR1 + (sh_l(m) - 1) * NA1 + n] * A[n][m];
+            for (int m = 0; m < kNumSH; ++m) Bn[m] = 2.0f * G[NR1 + (sh_l(m) - 1) * NA1 + n] * An[m];
             if (FOUR) {
-                const float mxy = Mc[n][0], myz = Mc[n][1], mzz = Mc[n][2], mxz = Mc[n][3], dd = Mc[n][4];
+                float M[5];
+                m_from_l2(&An[3], shc, M);
+                const float mxy = M[0], myz = M[1], mzz = M[2], mxz = M[3], dd = M[4];
                 const float mxx = 0.5f * (dd - mzz), myy = 0.5f * (-dd - mzz);
-                // M^2 entries
+                // entries of M^2
                 const float sxx = mxx * mxx + mxy * mxy + mxz * mxz;
                 const float syy = mxy * mxy + myy * myy + myz * myz;
                 const float szz = mxz * mxz + myz * myz + mzz * mzz;
@@ -384,7 +476,6 @@ __global__ __launch_bounds__(kBlock) void k_descriptor(NepArgs a, const float *_
                 Bn[6] += g4 * 6.0f * sxz / shc[6];
                 Bn[7] += g4 * 1.5f * (sxx - syy) / shc[7];
             }
-            float4 *o4 = reinterpret_cast<float4 *>(Bo + n * kNumSH);
 #pragma unroll
             for (int q4 = 0; q4 < kNumSH / 4; ++q4)
                 o4[q4] = make_float4(Bn[4 * q4], Bn[4 * q4 + 1], Bn[4 * q4 + 2], Bn[4 * q4 + 3]);
@@ -407,16 +498,23 @@ __global__ __launch_bounds__(kBlock) void k_descriptor(NepArgs a, const float *_
     if (valid && !tok) atomicOr(a.flags, (uint32_t)NEP_FLAG_BAD_TYPE);
     __shared__ double lds[4];
     const double e = block_sum(valid ? (double)U : 0.0, lds);
-    if (threadIdx.x == 0) a.partE[(size_t)b * gridDim.x + blockIdx.x] = e;
+    if (threadIdx.x == 0) a.partE[(size_t)b * gridDim.x + tile] = e;
 }
 
-// ----------------------------------------------------------- pass 2 ---
+// ------------------------------------------------------ pass 2: angular ---
 
-template <int NR1, int NA1, int KR1, int KA1, bool FOUR>
-__global__ __launch_bounds__(kBlock) void k_force(NepArgs a, const float *__restrict__ prm)
+// SYM: one species, so c^{ij} = c^{ji} and the pair term uses
+// B~ = B^i + (-1)^l B^j once.  BREG: the own adjoints stay in registers
+// (small n_max); otherwise they are re-read row by row (L1-resident).
+// Per-atom sums of the 26-odd angular pair terms are kept in FP32; the radial
+// pass adds them to its FP64 sums.
+template <int NA1, int KA1, bool SYM, bool BREG>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+void k_force_ang(NepArgs a, const float *__restrict__ prm)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
+    int b, tile;
+    bead_tile(b, tile);
+    const int i = tile * blockDim.x + threadIdx.x;
     const int N = a.N, S = a.S;
     const bool valid = i < N;
     const int ii = valid ? i : N - 1;
@@ -425,66 +523,86 @@ __global__ __launch_bounds__(kBlock) void k_force(NepArgs a, const float *__rest
     const double *pb = a.pos + (size_t)b * N * 3;
     const double xi = pb[3 * ii], yi = pb[3 * ii + 1], zi = pb[3 * ii + 2];
     const float *shc = prm + a.osh;
-    double Fx = 0.0, Fy = 0.0, Fz = 0.0;
-    double Wv[9];
+    float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f;
+    float Wv[9];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) Wv[e] = 0.0;
+    for (int e = 0; e < 9; ++e) Wv[e] = 0.0f;
 
+    // Control flow stays wave-uniform: lanes outside the current centre
+    // species (or past their neighbour count) compute on a dummy pair and
+    // contribute nothing.
     uint64_t todo = __ballot(valid && tok);
     while (todo) {
         const int lead = __builtin_ctzll(todo);
         const int tc = __builtin_amdgcn_readlane(ti, lead);
         const bool mine = valid && tok && ti == tc;
         todo &= ~__ballot(mine);
-        if (!mine) continue;
 
-        // radial: phi = sum_k (a^i_k(tj) + a^j_k(ti)) f'_k(r) u
-        const float *ai_base = a.arad + ((size_t)b * N + i) * S * a.KRP;
-        for (int t = 0; t < S; ++t) {
-            const size_t blk = ((size_t)b * S + t);
-            const int cnt = min(a.cntR[blk * N + i], a.capR);
-            const int32_t *ix = a.idxR + blk * a.capR * N + i;
-            float ai[KR1];
+        const float4 *bi4 = reinterpret_cast<const float4 *>(a.B + ((size_t)b * N + ii) * (NA1 * kNumSH));
+        float Bi[BREG ? NA1 : 1][kNumSH];
+        if (BREG) {
 #pragma unroll
-            for (int k = 0; k < KR1; ++k) ai[k] = ai_base[t * a.KRP + k];
-            for (int s = 0; s < cnt; ++s) {
-                const int j = ix[(size_t)s * N];
-                float dx, dy, dz;
-                pair_vec(pb, xi, yi, zi, j, a, dx, dy, dz);
-                const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-                float f[KR1], fp[KR1];
-                cheb_fd<KR1>(r, a.rcRinv, f, fp);
-                const float *aj = a.arad + ((size_t)b * N + j) * S * a.KRP + tc * a.KRP;
-                float sc = 0.0f;
+            for (int n = 0; n < (BREG ? NA1 : 1); ++n)
 #pragma unroll
-                for (int k = 0; k < KR1; ++k) sc += (ai[k] + aj[k]) * fp[k];
-                const float w = sc / r;
-                const float px = w * dx, py = w * dy, pz = w * dz;
-                Fx += px; Fy += py; Fz += pz;
-                Wv[0] -= 0.5 * dx * px; Wv[1] -= 0.5 * dx * py; Wv[2] -= 0.5 * dx * pz;
-                Wv[3] -= 0.5 * dy * px; Wv[4] -= 0.5 * dy * py; Wv[5] -= 0.5 * dy * pz;
-                Wv[6] -= 0.5 * dz * px; Wv[7] -= 0.5 * dz * py; Wv[8] -= 0.5 * dz * pz;
-            }
+                for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
+                    const float4 v4 = bi4[n * (kNumSH / 4) + q4];
+                    Bi[n][4 * q4] = v4.x; Bi[n][4 * q4 + 1] = v4.y;
+                    Bi[n][4 * q4 + 2] = v4.z; Bi[n][4 * q4 + 3] = v4.w;
+                }
         }
-
-        // angular
-        const float *Bi = a.B + ((size_t)b * N + i) * (NA1 * kNumSH);
         for (int t = 0; t < S; ++t) {
             const size_t blk = ((size_t)b * S + t);
-            const int cnt = min(a.cntA[blk * N + i], a.capA);
-            const int32_t *ix = a.idxA + blk * a.capA * N + i;
+            const int cnt = mine ? min(a.cntA[blk * N + i], a.capA) : 0;
+            int cmax = cnt;
+            for (int o = 32; o > 0; o >>= 1) cmax = max(cmax, __shfl_xor(cmax, o));
+            cmax = __builtin_amdgcn_readfirstlane(cmax);
+            const int32_t *ix = a.idxA + blk * a.capA * N + ii;
             const float *cij = prm + a.oA + (tc * S + t) * NA1 * KA1;
             const float *cji = prm + a.oA + (t * S + tc) * NA1 * KA1;
-            for (int s = 0; s < cnt; ++s) {
-                const int j = ix[(size_t)s * N];
+            int jn = cnt > 0 ? ix[0] : ii;
+            for (int s = 0; s < cmax; ++s) {
+                const float *cij_l = launder(cij), *cji_l = launder(cji), *shc_l = launder(shc);
+                const bool act = s < cnt;
+                const int j = jn;
+                if (s + 1 < cnt) jn = ix[(size_t)(s + 1) * N];
+                const float4 *bj4 = reinterpret_cast<const float4 *>(a.B + ((size_t)b * N + j) * (NA1 * kNumSH));
                 float dx, dy, dz;
-                pair_vec(pb, xi, yi, zi, j, a, dx, dy, dz);
-                const float r = sqrtf(dx * dx + dy * dy + dz * dz);
-                const float rinv = 1.0f / r;
+                pair_vec(pb[3 * j], pb[3 * j + 1], pb[3 * j + 2], xi, yi, zi, a, dx, dy, dz);
+                if (!act) {
+                    dx = 1.0f;
+                    dy = 0.0f;
+                    dz = 0.0f;
+                }
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float rinv = __builtin_amdgcn_rsqf(r2);
+                const float r = r2 * rinv;
                 const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
-                float f[KA1], fp[KA1];
-                cheb_fd<KA1>(r, a.rcAinv, f, fp);
-                const float *Bj = a.B + ((size_t)b * N + j) * (NA1 * kNumSH);
+                float gij[NA1], gpij[NA1], gji[SYM ? 1 : NA1], gpji[SYM ? 1 : NA1];
+                {
+                    float f[KA1], fp[KA1];
+                    cheb_fd<KA1>(r, a.rcAinv, f, fp);
+#pragma unroll
+                    for (int n = 0; n < NA1; ++n) {
+                        float g0 = 0.0f, g1 = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < KA1; ++k) {
+                            g0 = fmaf(cij_l[n * KA1 + k], f[k], g0);
+                            g1 = fmaf(cij_l[n * KA1 + k], fp[k], g1);
+                        }
+                        gij[n] = g0;
+                        gpij[n] = g1;
+                        if (!SYM) {
+                            float h0 = 0.0f, h1 = 0.0f;
+#pragma unroll
+                            for (int k = 0; k < KA1; ++k) {
+                                h0 = fmaf(cji_l[n * KA1 + k], f[k], h0);
+                                h1 = fmaf(cji_l[n * KA1 + k], fp[k], h1);
+                            }
+                            gji[SYM ? 0 : n] = h0;
+                            gpji[SYM ? 0 : n] = h1;
+                        }
+                    }
+                }
                 float beta[kNumSH], betap[kNumSH];
 #pragma unroll
                 for (int m = 0; m < kNumSH; ++m) {
@@ -493,67 +611,160 @@ __global__ __launch_bounds__(kBlock) void k_force(NepArgs a, const float *__rest
                 }
 #pragma unroll
                 for (int n = 0; n < NA1; ++n) {
-                    float gij = 0.0f, gpij = 0.0f, gji = 0.0f, gpji = 0.0f;
-#pragma unroll
-                    for (int k = 0; k < KA1; ++k) {
-                        gij += cij[n * KA1 + k] * f[k];
-                        gpij += cij[n * KA1 + k] * fp[k];
-                        gji += cji[n * KA1 + k] * f[k];
-                        gpji += cji[n * KA1 + k] * fp[k];
-                    }
-                    const float4 *bi4 = reinterpret_cast<const float4 *>(Bi + n * kNumSH);
-                    const float4 *bj4 = reinterpret_cast<const float4 *>(Bj + n * kNumSH);
 #pragma unroll
                     for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
-                        const float4 x = bi4[q4], y = bj4[q4];
-                        const float bi[4] = {x.x, x.y, x.z, x.w};
-                        const float bj[4] = {y.x, y.y, y.z, y.w};
+                        const float4 y4 = bj4[n * (kNumSH / 4) + q4];
+                        const float bj[4] = {y4.x, y4.y, y4.z, y4.w};
+                        float bx[4];
+                        if (!BREG) {
+                            const float4 x4 = bi4[n * (kNumSH / 4) + q4];
+                            bx[0] = x4.x; bx[1] = x4.y; bx[2] = x4.z; bx[3] = x4.w;
+                        }
 #pragma unroll
                         for (int e = 0; e < 4; ++e) {
                             const int m = 4 * q4 + e;
+                            const float bi = BREG ? Bi[BREG ? n : 0][m] : bx[e];
                             const float sj = (sh_l(m) & 1) ? -bj[e] : bj[e];
-                            beta[m] += bi[e] * gij + sj * gji;
-                            betap[m] += bi[e] * gpij + sj * gpji;
+                            if (SYM) {
+                                const float bt = bi + sj;
+                                beta[m] = fmaf(bt, gij[n], beta[m]);
+                                betap[m] = fmaf(bt, gpij[n], betap[m]);
+                            } else {
+                                beta[m] = fmaf(sj, gji[SYM ? 0 : n], fmaf(bi, gij[n], beta[m]));
+                                betap[m] = fmaf(sj, gpji[SYM ? 0 : n], fmaf(bi, gpij[n], betap[m]));
+                            }
                         }
                     }
+                    // keep the loads of row n + 1 behind this row's arithmetic (register pressure)
+                    __builtin_amdgcn_sched_barrier(0);
                 }
                 float sY, gx, gy, gz;
-                sh_contract(ux, uy, uz, shc, beta, betap, sY, gx, gy, gz);
+                sh_contract(ux, uy, uz, shc_l, beta, betap, sY, gx, gy, gz);
                 const float ug = ux * gx + uy * gy + uz * gz;
-                const float px = sY * ux + (gx - ux * ug) * rinv;
-                const float py = sY * uy + (gy - uy * ug) * rinv;
-                const float pz = sY * uz + (gz - uz * ug) * rinv;
+                const float sel = act ? 1.0f : 0.0f;
+                const float px = sel * (sY * ux + (gx - ux * ug) * rinv);
+                const float py = sel * (sY * uy + (gy - uy * ug) * rinv);
+                const float pz = sel * (sY * uz + (gz - uz * ug) * rinv);
                 Fx += px; Fy += py; Fz += pz;
-                Wv[0] -= 0.5 * dx * px; Wv[1] -= 0.5 * dx * py; Wv[2] -= 0.5 * dx * pz;
-                Wv[3] -= 0.5 * dy * px; Wv[4] -= 0.5 * dy * py; Wv[5] -= 0.5 * dy * pz;
-                Wv[6] -= 0.5 * dz * px; Wv[7] -= 0.5 * dz * py; Wv[8] -= 0.5 * dz * pz;
+                const float hx = -0.5f * dx, hy = -0.5f * dy, hz = -0.5f * dz;
+                Wv[0] = fmaf(hx, px, Wv[0]); Wv[1] = fmaf(hx, py, Wv[1]); Wv[2] = fmaf(hx, pz, Wv[2]);
+                Wv[3] = fmaf(hy, px, Wv[3]); Wv[4] = fmaf(hy, py, Wv[4]); Wv[5] = fmaf(hy, pz, Wv[5]);
+                Wv[6] = fmaf(hz, px, Wv[6]); Wv[7] = fmaf(hz, py, Wv[7]); Wv[8] = fmaf(hz, pz, Wv[8]);
             }
         }
     }
 
     if (valid) {
-        float *Fo = a.F + ((size_t)b * N + i) * 3;
-        Fo[0] = (float)Fx;
-        Fo[1] = (float)Fy;
-        Fo[2] = (float)Fz;
+        float *Fo = a.Fang + ((size_t)b * N + i) * 3;
+        Fo[0] = Fx;
+        Fo[1] = Fy;
+        Fo[2] = Fz;
         if (a.Watom) {
             float *wo = a.Watom + ((size_t)b * N + i) * 9;
 #pragma unroll
-            for (int e = 0; e < 9; ++e) wo[e] = (float)Wv[e];
+            for (int e = 0; e < 9; ++e) wo[e] = Wv[e];
         }
-        if (!(isfinite(Fx) && isfinite(Fy) && isfinite(Fz))) atomicOr(a.flags, (uint32_t)NEP_FLAG_NONFINITE);
+    }
+    __shared__ double lds[4];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+        const double w = block_sum(valid ? (double)Wv[e] : 0.0, lds);
+        if (threadIdx.x == 0) a.partWa[((size_t)b * gridDim.x + tile) * 9 + e] = w;
+    }
+}
+
+// ------------------------------------------------------- pass 2: radial ---
+
+template <int KR1>
+__global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
+{
+    int b, tile;
+    bead_tile(b, tile);
+    const int i = tile * blockDim.x + threadIdx.x;
+    const int N = a.N, S = a.S;
+    const bool valid = i < N;
+    const int ii = valid ? i : N - 1;
+    const int ti = a.types[ii];
+    const bool tok = ti >= 0 && ti < S;
+    const double *pb = a.pos + (size_t)b * N * 3;
+    const double xi = pb[3 * ii], yi = pb[3 * ii + 1], zi = pb[3 * ii + 2];
+    double Fx = 0.0, Fy = 0.0, Fz = 0.0;
+    double Wv[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) Wv[e] = 0.0;
+    if (valid && tok) {
+        const float *ai_base = a.arad + ((size_t)b * N + i) * S * a.KRP;
+        for (int t = 0; t < S; ++t) {
+            const size_t blk = ((size_t)b * S + t);
+            const int cnt = min(a.cntR[blk * N + i], a.capR);
+            const int32_t *ix = a.idxR + blk * a.capR * N + i;
+            float ai[KR1];
+#pragma unroll
+            for (int k = 0; k < KR1; ++k) ai[k] = ai_base[t * a.KRP + k];
+            for (int s0 = 0; s0 < cnt; s0 += kBatch) {
+                int jj[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) jj[u] = (s0 + u < cnt) ? ix[(size_t)(s0 + u) * N] : i;
+                double px[kBatch], py[kBatch], pz[kBatch];
+                float aj[kBatch][KR1];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    px[u] = pb[3 * jj[u]];
+                    py[u] = pb[3 * jj[u] + 1];
+                    pz[u] = pb[3 * jj[u] + 2];
+                    const float *ajp = a.arad + ((size_t)b * N + jj[u]) * S * a.KRP + ti * a.KRP;
+#pragma unroll
+                    for (int k = 0; k < KR1; ++k) aj[u][k] = ajp[k];
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    if (s0 + u < cnt) {
+                        float dx, dy, dz;
+                        pair_vec(px[u], py[u], pz[u], xi, yi, zi, a, dx, dy, dz);
+                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        const float rinv = __builtin_amdgcn_rsqf(r2);
+                        const float r = r2 * rinv;
+                        float f[KR1], fp[KR1];
+                        cheb_fd<KR1>(r, a.rcRinv, f, fp);
+                        float sc = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < KR1; ++k) sc += (ai[k] + aj[u][k]) * fp[k];
+                        const float w = sc * rinv;
+                        const float qx = w * dx, qy = w * dy, qz = w * dz;
+                        Fx += qx; Fy += qy; Fz += qz;
+                        Wv[0] -= 0.5 * dx * qx; Wv[1] -= 0.5 * dx * qy; Wv[2] -= 0.5 * dx * qz;
+                        Wv[3] -= 0.5 * dy * qx; Wv[4] -= 0.5 * dy * qy; Wv[5] -= 0.5 * dy * qz;
+                        Wv[6] -= 0.5 * dz * qx; Wv[7] -= 0.5 * dz * qy; Wv[8] -= 0.5 * dz * qz;
+                    }
+                }
+            }
+        }
+    }
+    if (valid) {
+        const float *fa = a.Fang + ((size_t)b * N + i) * 3;
+        const double gx = Fx + (double)fa[0], gy = Fy + (double)fa[1], gz = Fz + (double)fa[2];
+        float *Fo = a.F + ((size_t)b * N + i) * 3;
+        Fo[0] = (float)gx;
+        Fo[1] = (float)gy;
+        Fo[2] = (float)gz;
+        if (a.Watom) {
+            float *wo = a.Watom + ((size_t)b * N + i) * 9;
+#pragma unroll
+            for (int e = 0; e < 9; ++e) wo[e] = (float)(Wv[e] + (double)wo[e]);
+        }
+        if (!(isfinite(gx) && isfinite(gy) && isfinite(gz))) atomicOr(a.flags, (uint32_t)NEP_FLAG_NONFINITE);
     }
     __shared__ double lds[4];
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
         const double w = block_sum(valid ? Wv[e] : 0.0, lds);
-        if (threadIdx.x == 0) a.partW[((size_t)b * gridDim.x + blockIdx.x) * 9 + e] = w;
+        if (threadIdx.x == 0) a.partWr[((size_t)b * gridDim.x + tile) * 9 + e] = w;
     }
 }
 
 // Per-bead totals from the per-block partial sums, in block order.
-__global__ void k_reduce(const double *__restrict__ partE, const double *__restrict__ partW, int nblk,
-                         double *__restrict__ E, double *__restrict__ W)
+__global__ void k_reduce(const double *__restrict__ partE, const double *__restrict__ partWa,
+                         const double *__restrict__ partWr, int nblk, double *__restrict__ E, double *__restrict__ W)
 {
     const int b = blockIdx.x, t = threadIdx.x;
     if (t == 0) {
@@ -562,13 +773,16 @@ __global__ void k_reduce(const double *__restrict__ partE, const double *__restr
         E[b] = s;
     } else if (t <= 9) {
         double s = 0.0;
-        for (int k = 0; k < nblk; ++k) s += partW[((size_t)b * nblk + k) * 9 + (t - 1)];
+        for (int k = 0; k < nblk; ++k) {
+            const size_t o = ((size_t)b * nblk + k) * 9 + (t - 1);
+            s += partWa[o] + partWr[o];
+        }
         W[(size_t)b * 9 + (t - 1)] = s;
     }
 }
 
 template <int NR1, int NA1, bool FOUR>
-static void launch(const NepArgs &a, const float *prm, int P, hipStream_t s)
+static void launch(const NepArgs &a, const float *prm, int P, bool sym, hipStream_t s)
 {
     const dim3 g(div_up(a.N, kBlock), P);
     {
@@ -576,8 +790,15 @@ static void launch(const NepArgs &a, const float *prm, int P, hipStream_t s)
         hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR>), g, dim3(kBlock), 0, s, a, prm);
     }
     {
+        ProfScope ps_(K_FORCE_ANG, s);
+        if (sym)
+            hipLaunchKernelGGL((k_force_ang<NA1, 9, true, (NA1 <= 5)>), g, dim3(kBlock), 0, s, a, prm);
+        else
+            hipLaunchKernelGGL((k_force_ang<NA1, 9, false, (NA1 <= 5)>), g, dim3(kBlock), 0, s, a, prm);
+    }
+    {
         ProfScope ps_(K_FORCE, s);
-        hipLaunchKernelGGL((k_force<NR1, NA1, 9, 9, FOUR>), g, dim3(kBlock), 0, s, a, prm);
+        hipLaunchKernelGGL((k_force_rad<9>), g, dim3(kBlock), 0, s, a);
     }
 }
 
@@ -610,28 +831,29 @@ extern "C" int32_t nep_compute(const nep_model *m, const nep_nlist *nl, nep_ws *
     }
     const nep_hparams &h = m->hp;
     a.pos = pos; a.types = types; a.N = N; a.S = h.n_species; a.H = h.hidden;
-    a.rcR = (float)h.rc_radial; a.rcA = (float)h.rc_angular;
     a.rcRinv = (float)(1.0 / h.rc_radial); a.rcAinv = (float)(1.0 / h.rc_angular);
     a.kappa4 = (float)(-4.5 * std::sqrt(2.0 / 35.0) * std::pow(5.0 / (4.0 * M_PI), 1.5));
     a.cntR = nl->cntR; a.idxR = nl->idxR; a.cntA = nl->cntA; a.idxA = nl->idxA;
     a.capR = nl->capR; a.capA = nl->capA;
-    a.B = ws->B; a.arad = ws->arad; a.KRP = ws->KRP;
-    a.partE = ws->partE; a.partW = ws->partW; a.flags = ws->flags;
+    a.B = ws->B; a.arad = ws->arad; a.Fang = ws->Fang; a.KRP = ws->KRP;
+    a.partE = ws->partE; a.partWa = ws->partW; a.partWr = ws->partW + (size_t)P * ws->nblk * 9;
+    a.flags = ws->flags;
     a.F = F; a.Eatom = E_atom; a.Watom = W_atom;
     a.oR = m->off.cR; a.oA = m->off.cA; a.oq = m->off.qs; a.oW0 = m->off.W0; a.ob0 = m->off.b0;
     a.ow1 = m->off.w1; a.ob1 = m->off.b1; a.osh = m->off.sh;
+    const bool sym = h.n_species == 1;
     const int key = h.n_max_radial * 100 + h.n_max_angular * 10 + h.four_body;
     switch (key) {
-    case 440: launch<5, 5, false>(a, m->dev, P, s); break;
-    case 441: launch<5, 5, true>(a, m->dev, P, s); break;
-    case 640: launch<7, 5, false>(a, m->dev, P, s); break;
-    case 860: launch<9, 7, false>(a, m->dev, P, s); break;
-    case 881: launch<9, 9, true>(a, m->dev, P, s); break;
+    case 440: launch<5, 5, false>(a, m->dev, P, sym, s); break;
+    case 441: launch<5, 5, true>(a, m->dev, P, sym, s); break;
+    case 640: launch<7, 5, false>(a, m->dev, P, sym, s); break;
+    case 860: launch<9, 7, false>(a, m->dev, P, sym, s); break;
+    case 881: launch<9, 9, true>(a, m->dev, P, sym, s); break;
     default: return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");
     }
     {
         ProfScope ps_(K_REDUCE, s);
-        hipLaunchKernelGGL(k_reduce, dim3(P), dim3(64), 0, s, ws->partE, ws->partW, ws->nblk, E, W);
+        hipLaunchKernelGGL(k_reduce, dim3(P), dim3(64), 0, s, ws->partE, a.partWa, a.partWr, ws->nblk, E, W);
     }
     NEP_HIP(hipGetLastError());
     return NEP_OK;

@@ -60,13 +60,17 @@ class NepPimd:
     # ------------------------------------------------------------------
     def _fit_capacity(self):
         """Build once, then shrink or grow the capacities to the observed need."""
+        S = self.model.n_species
         for _ in range(4):
             self.nl.build(self.pos, self.box, self.types)
-            flags, mr, ma = self.nl.poll(clear=True)
+            st = self.nl.status(clear=True)
+            flags, mr, ma = st["flags"], st["max_radial"], st["max_angular"]
             if flags & lib.FLAG_BAD_TYPE:
                 raise lib.NepError(1, "species index outside the model's range")
             need_r = int(math.ceil(mr * 1.25)) + 8
             need_a = int(math.ceil(ma * 1.25)) + 8
+            # the centroid candidate capacity is 2 S cap_radial + 32
+            need_r = max(need_r, int(math.ceil((1.3 * st["max_candidates"] - 32) / (2 * S))))
             if flags & lib.FLAG_NEIGHBOR_OVERFLOW or need_r < self.cap_radial // 2 or need_a < self.cap_angular // 2:
                 self.cap_radial, self.cap_angular = max(need_r, 8), max(need_a, 8)
                 self.nl = lib.NeighborList(self.model, self.P, self.N, self.cap_radial, self.cap_angular)

@@ -14,7 +14,7 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libneppimd.so")
+LIB_PATH = os.environ.get("NEPPIMD_LIB") or os.path.join(_HERE, "libneppimd.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or python -m paper_2409_04430_amd.build")
@@ -49,7 +49,8 @@ class NlistLayout(C.Structure):
 
 
 class NlistStatus(C.Structure):
-    _fields_ = [("flags", C.c_uint32), ("max_radial", C.c_int32), ("max_angular", C.c_int32)]
+    _fields_ = [("flags", C.c_uint32), ("max_radial", C.c_int32), ("max_angular", C.c_int32),
+                ("max_candidates", C.c_int32), ("capacity_candidates", C.c_int32), ("bead_spread", C.c_float)]
 
 
 class PimdParams(C.Structure):
@@ -170,13 +171,18 @@ class NeighborList:
                                    _box9(box), _ptr(types, _torch().int32, (self.N,), "types"), self.P, self.N,
                                    _stream()))
 
-    def poll(self, clear: bool = True):
-        """(flags, max_radial, max_angular); synchronises the stream."""
+    def status(self, clear: bool = True) -> dict:
+        """Sticky list status (synchronises the stream)."""
         st = NlistStatus()
         rc = _lib.nep_nlist_poll(self._h, C.byref(st), int(clear), _stream())
         if rc not in (NEP_OK, 5):
             _check(rc)
-        return st.flags, st.max_radial, st.max_angular
+        return {f: getattr(st, f) for f, _ in NlistStatus._fields_}
+
+    def poll(self, clear: bool = True):
+        """(flags, max_radial, max_angular); synchronises the stream."""
+        st = self.status(clear)
+        return st["flags"], st["max_radial"], st["max_angular"]
 
     def view(self):
         """Raw layout: device pointers of cnt [P,S,N] and idx [P,S,cap,N] (radial, angular)."""
