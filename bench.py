@@ -68,6 +68,7 @@ def source_hash() -> str:
 # ---------------------------------------------------------------------------
 
 def flops_per_atom(hp: dict, nR: float, nA: float) -> dict:
+    """Algorithmic FP32/FP64 operations per (bead, atom) of each NEP kernel (an FMA counts 2)."""
     S, NR1, NA1 = hp["n_species"], hp["n_max_radial"] + 1, hp["n_max_angular"] + 1
     KR1, KA1, H, D = hp["basis_radial"] + 1, hp["basis_angular"] + 1, hp["hidden"], hp["dim"]
     four = hp["four_body"]
@@ -79,20 +80,26 @@ def flops_per_atom(hp: dict, nR: float, nA: float) -> dict:
             + nA * (G + 4 + Bf(KA1) + Ysh + 2 * NA1 * KA1 + 2 * NA1 * 24)
             + 2 * NA1 * 24 + (40 * NA1 if four else 0)
             + H * (4 * D + 7) + 2 * D + 2 * NA1 * 24 + S * 2 * NR1 * KR1)
-    force = (nR * (G + Bfd(KR1) + 2 * KR1 + 1 + 3 + 3 + 27)
-             + nA * (G + 4 + Bfd(KA1) + 4 * 2 * NA1 * KA1 + 8 * NA1 * 24 + Ysh + 48 + 24 + 160 + 5 + 15 + 3 + 27))
-    return {"descriptor": desc, "force": force}
+    # own angular pair term: basis + derivative, g and g', beta and beta', the
+    # harmonic contraction (values 70, sY 48, weights 24, gradient 160), the
+    # projection (20), the force (3) and the virial (18)
+    force_ang = nA * (G + 4 + Bfd(KA1) + 2 * 2 * NA1 * KA1 + 2 * 2 * NA1 * 24 + Ysh + 48 + 24 + 160 + 20 + 3 + 18)
+    # radial pair term (both site energies) with the FP64 force and virial sums,
+    # then the reverse angular terms
+    force = nR * (G + Bfd(KR1) + 2 * KR1 + 1 + 3 + 3 + 27) + nA * 3
+    return {"descriptor": desc, "force_ang": force_ang, "force": force}
 
 
 def bytes_per_atom(hp: dict, nR: float, nA: float, P: int) -> dict:
     """Minimum HBM bytes per (bead, atom): every array read or written once."""
     S, NA1 = hp["n_species"], hp["n_max_angular"] + 1
     KRP = (hp["basis_radial"] + 1 + 3) // 4 * 4
-    lists = 4 * (nR + nA) + 2 * 4 * S
+    masks = (nR + nA) / 8.0
     return {
-        "nlist": 24 + 4 + lists,
-        "descriptor": 24 + 4 + lists + 4 * NA1 * 24 + 4 * S * KRP,
-        "force": 24 + 4 + lists + 4 * NA1 * 24 + 4 * S * KRP + 12,
+        "nlist": 24 + masks,
+        "descriptor": 24 + 4 + masks + 4 * NA1 * 24 + 4 * S * KRP,
+        "force_ang": 24 + 4 + masks + 4 * NA1 * 24 + 16 * nA + 12,
+        "force": 24 + 4 + masks + 4 * S * KRP + 16 * nA + 12 + 12,
         "trpmd": 3 * (8 + 8 + 4 + 8 + 8),
     }
 
@@ -158,8 +165,8 @@ def main():
     eng.run(args.warmup)
     eng.check()
     lst = eng.nl.to_host()
-    nR = float(lst["cnt_radial"].sum(axis=1).mean())
-    nA = float(lst["cnt_angular"].sum(axis=1).mean())
+    nR = float(lst["cnt_radial"].mean())
+    nA = float(lst["cnt_angular"].mean())
     hp = eng.model.hp
 
     prof = not args.no_profile

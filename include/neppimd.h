@@ -115,11 +115,15 @@ void nep_model_destroy(nep_model *model);
 /* Neighbour lists (per bead, minimum image, cell list)                */
 /* ------------------------------------------------------------------ */
 
-/* Create lists for P beads of N atoms.  cap_radial / cap_angular are the
- * capacities of each per-(atom, neighbour species) block.  The lists live
- * on the current device.  Errors: NEP_ERR_INVALID_ARG, NEP_ERR_NOMEM. */
-int32_t nep_nlist_create(const nep_model *model, int32_t P, int32_t N, int32_t cap_radial,
-                         int32_t cap_angular, nep_nlist **out);
+/* Create neighbour sets for P beads of N atoms on the current device.
+ * cap_candidates bounds the candidate row of one atom (all species, radius
+ * rc_radial + 2 D; see neighbor_build), at most 8192; cap_radial and
+ * cap_angular bound the per-bead neighbour counts of one atom, with
+ * cap_angular <= cap_radial <= cap_candidates.  The handle also holds the
+ * angular pair buffer that nep_compute fills (4 P N cap_candidates floats)
+ * and N <= 2^28.  Errors: NEP_ERR_INVALID_ARG, NEP_ERR_NOMEM. */
+int32_t nep_nlist_create(const nep_model *model, int32_t P, int32_t N, int32_t cap_candidates,
+                         int32_t cap_radial, int32_t cap_angular, nep_nlist **out);
 void nep_nlist_destroy(nep_nlist *nl);
 
 /* Build, for every bead b and atom i, the set of atoms i' != i with
@@ -128,39 +132,56 @@ void nep_nlist_destroy(nep_nlist *nl);
  * is (dx*dx + dy*dy) + dz*dz < rc*rc, all in IEEE FP64 without contraction,
  * so the sets are exactly those of a brute-force search (Sec. II.A: periodic
  * boundary conditions).  Candidates come from one cell-list search over the
- * ring-polymer centroids with radius rc + 2 D, D the largest bead-to-centroid
- * distance measured on the device in the same call; every bead pair closer
- * than rc has centroids closer than rc + 2 D, so filtering the candidates
- * bead by bead loses nothing.  pos [P][N][3] dev, types [N] dev, box host[9].
+ * ring-polymer centroids with radius rc_radial + 2 D (rc_angular <=
+ * rc_radial), D the largest bead-to-centroid distance measured on the
+ * device in the same call; every bead pair closer than rc has centroids
+ * closer than rc + 2 D, so testing the candidates bead by bead loses
+ * nothing.  Positions must keep the P beads of an atom in one periodic image
+ * (unwrapped ring polymers).  pos [P][N][3] dev, types [N] dev, box host[9].
  * Errors: NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED (non-orthorhombic box),
  * NEP_ERR_BOX_TOO_SMALL (an edge < 2 rc_radial), NEP_ERR_HIP, NEP_ERR_NOMEM.
- * Overflow of a capacity sets NEP_FLAG_NEIGHBOR_OVERFLOW (the list then
- * holds the first `cap` neighbours of that block). */
+ * A row or list longer than its capacity sets NEP_FLAG_NEIGHBOR_OVERFLOW
+ * (it is then truncated and the results of nep_compute are not valid). */
 int32_t neighbor_build(const nep_model *model, nep_nlist *nl, const double *pos, const double box[9],
                        const int32_t *types, int32_t P, int32_t N, hipStream_t stream);
 
-/* Device layout of the lists (pointers stay owned by the handle).
- *   cnt_*: [P][S][N] int32, number of neighbours of species s of atom i in
- *          bead b (may exceed the capacity after an overflow);
- *   idx_*: [P][S][cap][N] int32, slot-major so that consecutive atoms read
- *          consecutive words; within a block the order is the traversal
- *          order of the cell list (deterministic), not sorted. */
+/* Device layout of the neighbour sets (pointers stay owned by the handle).
+ * Per atom i, shared by all beads:
+ *   cand [N][cap_candidates] int32: candidates, entry (j << 2) | species(j),
+ *       sorted by (species, j);
+ *   cand_off [N][5] int32: species block starts; entry [n_species] is the
+ *       row length;
+ *   cand_rev [N][cap_candidates] int32: for slot k of atom i holding j, the
+ *       slot of i in j's row (-1 only if j's row overflowed).
+ * Per bead b, slot-major:
+ *   nbr_radial [P][cap_radial][N] int32: the s-th radial neighbour j of i
+ *       in bead b, in row order (species blocks, ascending j);
+ *   end_radial [P][4][N] int32: end of species block t of i's list
+ *       (entry n_species - 1 is the count);
+ *   nbr_angular, end_angular: the same for the angular cutoff;
+ *   slot_angular [P][cap_angular][N] int32: for each angular entry, its
+ *       candidate slot k (low 16 bits) and the reverse slot cand_rev[i][k]
+ *       (high 16 bits, 0xffff if absent).
+ * Entries past a list's count are not written. */
 typedef struct nep_nlist_layout {
-    int32_t P, N, n_species, cap_radial, cap_angular;
-    const int32_t *cnt_radial;
-    const int32_t *idx_radial;
-    const int32_t *cnt_angular;
-    const int32_t *idx_angular;
+    int32_t P, N, n_species, cap_candidates, cap_radial, cap_angular;
+    const int32_t *cand;
+    const int32_t *cand_off;
+    const int32_t *cand_rev;
+    const int32_t *nbr_radial;
+    const int32_t *end_radial;
+    const int32_t *nbr_angular;
+    const int32_t *end_angular;
+    const int32_t *slot_angular;
 } nep_nlist_layout;
 int32_t nep_nlist_view(const nep_nlist *nl, nep_nlist_layout *out);
 
 typedef struct nep_nlist_status {
-    uint32_t flags;              /* nep_flag_bits seen by neighbor_build */
-    int32_t max_radial;          /* largest per-species-block radial count seen */
-    int32_t max_angular;         /* largest per-species-block angular count seen */
-    int32_t max_candidates;      /* largest centroid candidate count seen */
-    int32_t capacity_candidates; /* candidate capacity: 2 n_species cap_radial + 32 (at most 8192) */
-    float bead_spread;           /* largest distance of a bead from its centroid in the last build, A */
+    uint32_t flags;            /* nep_flag_bits seen by neighbor_build */
+    int32_t max_radial;        /* largest radial neighbour count of an atom in a bead */
+    int32_t max_angular;       /* largest angular neighbour count */
+    int32_t max_candidates;    /* longest candidate row */
+    float bead_spread;         /* largest distance of a bead from its centroid, A */
 } nep_nlist_status;
 
 /* Synchronise `stream`, read the sticky status of the lists into *out and,
@@ -178,8 +199,10 @@ int32_t nep_ws_create(const nep_model *model, int32_t P, int32_t N, nep_ws **out
 void nep_ws_destroy(nep_ws *ws);
 
 /* NEP energy, forces and virial of every bead (Sec. II.C site energies,
- * Sec. II.A bead forces and virial), from lists built by neighbor_build on
- * the same pos/box/types.
+ * Sec. II.A bead forces and virial), from neighbour sets built by
+ * neighbor_build on the same pos/box/types.  The angular pair terms
+ * dU_i/dr_ij are stored in the handle's pair buffer and gathered back by
+ * the reverse slots, so no atomics are used.
  *   E      [P]      dev float64  per-bead sum of site energies
  *   F      [P][N][3] dev float32 forces, F_i = sum_j (dU_i/dr_ij - dU_j/dr_ji)
  *   W      [P][9]   dev float64  per-bead virial
@@ -191,7 +214,7 @@ void nep_ws_destroy(nep_ws *ws);
  * The summation order is fixed, so repeated calls give identical bits.
  * Errors: NEP_ERR_INVALID_ARG (sizes differ from the handles'), NEP_ERR_HIP.
  * Non-finite forces set NEP_FLAG_NONFINITE in the workspace. */
-int32_t nep_compute(const nep_model *model, const nep_nlist *nl, nep_ws *ws, const double *pos,
+int32_t nep_compute(const nep_model *model, nep_nlist *nl, nep_ws *ws, const double *pos,
                     const double box[9], const int32_t *types, int32_t P, int32_t N, double *E, float *F,
                     double *W, float *E_atom, float *W_atom, hipStream_t stream);
 

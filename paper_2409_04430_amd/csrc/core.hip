@@ -37,8 +37,8 @@ bool box_lengths(const double box[9], double L[3])
 // ---------------------------------------------------------- profiling ---
 
 static const char *kKernelNames[K_NUM] = {"fill", "centroid", "grid", "cell_count", "cell_scan", "cell_fill",
-                                          "cell_sort", "candidates", "nlist",
-                                          "descriptor", "force_ang", "force", "reduce", "trpmd", "modes"};
+                                          "cell_sort", "candidates", "sort_rows", "reverse", "nlist",
+                                          "pack", "descriptor", "force_ang", "force", "reduce", "trpmd", "modes"};
 static std::atomic<int> g_prof_on{0};
 static std::mutex g_prof_mu;
 struct ProfRecord {
@@ -332,34 +332,42 @@ static hipError_t dalloc(T **p, size_t n)
     return hipMalloc((void **)p, sizeof(T) * (n ? n : 1));
 }
 
-extern "C" int32_t nep_nlist_create(const nep_model *m, int32_t P, int32_t N, int32_t capR, int32_t capA,
-                                    nep_nlist **out)
+extern "C" int32_t nep_nlist_create(const nep_model *m, int32_t P, int32_t N, int32_t capC, int32_t capR,
+                                    int32_t capA, nep_nlist **out)
 {
     if (!m || !out) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_create: null argument");
-    if (P < 0 || N < 0 || capR < 1 || capA < 1 || capR > 4096 || capA > 4096 || N > (1 << 29))
-        return fail(NEP_ERR_INVALID_ARG, "nep_nlist_create: bad sizes P=%d N=%d caps=%d/%d", P, N, capR, capA);
+    if (P < 0 || N < 0 || capC < 1 || capR < 1 || capA < 1 || capC > 8192 || capR > capC || capA > capR ||
+        N > (1 << 28))
+        return fail(NEP_ERR_INVALID_ARG, "nep_nlist_create: bad sizes P=%d N=%d caps=%d/%d/%d", P, N, capC, capR,
+                    capA);
     *out = nullptr;
     nep_nlist *nl = new (std::nothrow) nep_nlist;
     if (!nl) return fail(NEP_ERR_NOMEM, "host allocation failed");
-    nl->P = P; nl->N = N; nl->S = m->hp.n_species; nl->capR = capR; nl->capA = capA;
-    nl->capC = 2 * nl->S * capR + 32;
-    if (nl->capC > 8192) nl->capC = 8192;
-    const size_t PSN = (size_t)P * nl->S * N;
+    nl->P = P; nl->N = N; nl->S = m->hp.n_species;
+    nl->capC = capC; nl->capR = capR; nl->capA = capA;
+    const size_t Nn = (size_t)N, PN = (size_t)P * N;
     hipError_t e = hipGetDevice(&nl->device);
-    if (e == hipSuccess) e = dalloc(&nl->cntR, PSN);
-    if (e == hipSuccess) e = dalloc(&nl->cntA, PSN);
-    if (e == hipSuccess) e = dalloc(&nl->idxR, PSN * capR);
-    if (e == hipSuccess) e = dalloc(&nl->idxA, PSN * capA);
-    if (e == hipSuccess) e = dalloc(&nl->cen, (size_t)N * 3);
-    if (e == hipSuccess) e = dalloc(&nl->cand, (size_t)N * nl->capC);
-    if (e == hipSuccess) e = dalloc(&nl->candN, (size_t)N);
-    if (e == hipSuccess) e = dalloc(&nl->cell_atoms, (size_t)N);
-    if (e == hipSuccess) e = dalloc(&nl->grid, 8);
+    if (e == hipSuccess) e = dalloc(&nl->cen, Nn * 3);
+    if (e == hipSuccess) e = dalloc(&nl->cand, Nn * capC);
+    if (e == hipSuccess) e = dalloc(&nl->rowlen, Nn);
+    if (e == hipSuccess) e = dalloc(&nl->offC, Nn * (kMaxSpecies + 1));
+    if (e == hipSuccess) e = dalloc(&nl->revC, Nn * capC);
+    if (e == hipSuccess) e = dalloc(&nl->listR, PN * capR);
+    if (e == hipSuccess) e = dalloc(&nl->endR, PN * kMaxSpecies);
+    if (e == hipSuccess) e = dalloc(&nl->listA, PN * capA);
+    if (e == hipSuccess) e = dalloc(&nl->endA, PN * kMaxSpecies);
+    if (e == hipSuccess) e = dalloc(&nl->slotA, PN * capA);
+    nl->WC = div_up(capC, 32);
+    if (e == hipSuccess) e = dalloc(&nl->maskA, PN * nl->WC);
+    if (e == hipSuccess) e = dalloc(&nl->pairbuf, 4 * PN * capA);
+    if (e == hipSuccess) e = dalloc(&nl->cell_atoms, Nn);
+    if (e == hipSuccess) e = dalloc(&nl->grid, 16);
     if (e == hipSuccess) e = dalloc(&nl->status, 8);
     if (e == hipSuccess) e = hipMemset(nl->status, 0, 8 * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemset(nl->grid, 0, 8 * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemset(nl->cntR, 0, sizeof(int32_t) * (PSN ? PSN : 1));
-    if (e == hipSuccess) e = hipMemset(nl->cntA, 0, sizeof(int32_t) * (PSN ? PSN : 1));
+    if (e == hipSuccess) e = hipMemset(nl->grid, 0, 16 * sizeof(uint32_t));
+    if (e == hipSuccess && Nn) e = hipMemset(nl->offC, 0, sizeof(int32_t) * Nn * (kMaxSpecies + 1));
+    if (e == hipSuccess && PN) e = hipMemset(nl->endR, 0, sizeof(int32_t) * PN * kMaxSpecies);
+    if (e == hipSuccess && PN) e = hipMemset(nl->endA, 0, sizeof(int32_t) * PN * kMaxSpecies);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         nep_nlist_destroy(nl);
@@ -373,9 +381,10 @@ extern "C" int32_t nep_nlist_create(const nep_model *m, int32_t P, int32_t N, in
 extern "C" void nep_nlist_destroy(nep_nlist *nl)
 {
     if (!nl) return;
-    for (void *p : {(void *)nl->cntR, (void *)nl->idxR, (void *)nl->cntA, (void *)nl->idxA, (void *)nl->cen,
-                    (void *)nl->cand, (void *)nl->candN, (void *)nl->cell_cnt, (void *)nl->cell_start,
-                    (void *)nl->cell_atoms, (void *)nl->grid, (void *)nl->status})
+    for (void *p : {(void *)nl->cen, (void *)nl->cand, (void *)nl->rowlen, (void *)nl->offC, (void *)nl->revC,
+                    (void *)nl->listR, (void *)nl->endR, (void *)nl->listA, (void *)nl->endA, (void *)nl->slotA,
+                    (void *)nl->maskA, (void *)nl->pairbuf, (void *)nl->cell_cnt, (void *)nl->cell_start, (void *)nl->cell_atoms,
+                    (void *)nl->grid, (void *)nl->status})
         if (p) (void)hipFree(p);
     delete nl;
 }
@@ -384,9 +393,10 @@ extern "C" int32_t nep_nlist_view(const nep_nlist *nl, nep_nlist_layout *out)
 {
     if (!nl || !out) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_view: null argument");
     out->P = nl->P; out->N = nl->N; out->n_species = nl->S;
-    out->cap_radial = nl->capR; out->cap_angular = nl->capA;
-    out->cnt_radial = nl->cntR; out->idx_radial = nl->idxR;
-    out->cnt_angular = nl->cntA; out->idx_angular = nl->idxA;
+    out->cap_candidates = nl->capC; out->cap_radial = nl->capR; out->cap_angular = nl->capA;
+    out->cand = nl->cand; out->cand_off = nl->offC; out->cand_rev = nl->revC;
+    out->nbr_radial = nl->listR; out->end_radial = nl->endR;
+    out->nbr_angular = nl->listA; out->end_angular = nl->endA; out->slot_angular = nl->slotA;
     return NEP_OK;
 }
 
@@ -400,7 +410,6 @@ extern "C" int32_t nep_nlist_poll(nep_nlist *nl, nep_nlist_status *out, int32_t 
     out->max_radial = (int32_t)h[1];
     out->max_angular = (int32_t)h[2];
     out->max_candidates = (int32_t)h[3];
-    out->capacity_candidates = nl->capC;
     float spread;
     std::memcpy(&spread, &h[4], sizeof spread);
     out->bead_spread = spread;
@@ -410,9 +419,8 @@ extern "C" int32_t nep_nlist_poll(nep_nlist *nl, nep_nlist_status *out, int32_t 
         NEP_HIP(hipStreamSynchronize(s));
     }
     if (h[0] & NEP_FLAG_NEIGHBOR_OVERFLOW)
-        return fail(NEP_ERR_NEIGHBOR_OVERFLOW,
-                    "neighbour list overflow (largest counts %u/%u/%u, capacities %d/%d/%d)", h[1], h[2], h[3],
-                    nl->capR, nl->capA, nl->capC);
+        return fail(NEP_ERR_NEIGHBOR_OVERFLOW, "list overflow (largest %u candidates, %u radial, %u angular; "
+                    "capacities %d/%d/%d)", h[3], h[1], h[2], nl->capC, nl->capR, nl->capA);
     return NEP_OK;
 }
 
@@ -436,6 +444,7 @@ extern "C" int32_t nep_ws_create(const nep_model *m, int32_t P, int32_t N, nep_w
     if (e == hipSuccess) e = dalloc(&w->partE, (size_t)P * w->nblk);
     if (e == hipSuccess) e = dalloc(&w->partW, (size_t)2 * P * w->nblk * 9);
     if (e == hipSuccess) e = dalloc(&w->Fang, PN * 3);
+    if (e == hipSuccess) e = dalloc(&w->pos4, PN * 4);
     if (e == hipSuccess) e = dalloc(&w->flags, 4);
     if (e == hipSuccess) e = hipMemset(w->flags, 0, 4 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -451,7 +460,7 @@ extern "C" int32_t nep_ws_create(const nep_model *m, int32_t P, int32_t N, nep_w
 extern "C" void nep_ws_destroy(nep_ws *w)
 {
     if (!w) return;
-    for (void *p : {(void *)w->B, (void *)w->arad, (void *)w->partE, (void *)w->partW, (void *)w->Fang,
+    for (void *p : {(void *)w->B, (void *)w->arad, (void *)w->partE, (void *)w->partW, (void *)w->Fang, (void *)w->pos4,
                     (void *)w->flags})
         if (p) (void)hipFree(p);
     delete w;

@@ -44,20 +44,33 @@ struct nep_model {
 };
 
 struct nep_nlist {
-    int P = 0, N = 0, S = 0, capR = 0, capA = 0;
+    int P = 0, N = 0, S = 0;
+    int capC = 0;                 // candidate row capacity per atom
+    int capR = 0, capA = 0;       // per-bead neighbour capacities per atom (radial, angular)
     int device = 0;
-    int32_t *cntR = nullptr, *idxR = nullptr, *cntA = nullptr, *idxA = nullptr;
-    // Ring-polymer centroids and the candidate lists they give (shared by all beads).
-    int capC = 0;
+    // Per call, shared by all beads: ring-polymer centroids and candidate rows.
     double *cen = nullptr;        // [N][3]
-    int32_t *cand = nullptr;      // [capC][N], entries (j << 2) | species
-    int32_t *candN = nullptr;     // [N]
+    int32_t *cand = nullptr;      // [N][capC], entries (j << 2) | species(j), sorted by (species, j)
+    int32_t *rowlen = nullptr;    // [N] candidates found (may exceed capC: overflow)
+    int32_t *offC = nullptr;      // [N][5], species block starts, [S] = row length
+    int32_t *revC = nullptr;      // [N][capC], slot of i in the row of cand[i][k] (-1 if absent)
+    // Per bead: compact lists, slot-major ([bead][slot][atom]).
+    int32_t *listR = nullptr;     // [P][capR][N] neighbour index j
+    int32_t *endR = nullptr;      // [P][4][N] species block ends
+    int32_t *listA = nullptr;     // [P][capA][N]
+    int32_t *endA = nullptr;      // [P][4][N]
+    int32_t *slotA = nullptr;     // [P][capA][N] candidate slot k | reverse slot << 16 (0xffff: none)
+    int WC = 0;                   // words of one candidate-row bitmask: ceil(capC / 32)
+    uint64_t *maskA = nullptr;    // [P][WC][N] angular hits of word w (low 32 bits) | hits before w << 32
+    // Angular pair terms dU_j/dr_ji stored at the receiving atom i's list
+    // position s of j: [P][capA][N] xyz + pad.
+    float *pairbuf = nullptr;
     // Centroid cell list (grown on demand): cell_cnt [ncell], cell_start [ncell+1], cell_atoms [N].
     int ncell_alloc = 0;
     int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_atoms = nullptr;
-    uint32_t *grid = nullptr;     // device-chosen grid: nc[3], ncell, spread bits, pad, R^2 (double)
-    uint32_t *status = nullptr;   // [0] flags, [1] max radial, [2] max angular, [3] max candidates,
-                                  // [4] largest bead-to-centroid distance (float bits)
+    uint32_t *grid = nullptr;     // device-chosen grid record
+    uint32_t *status = nullptr;   // [0] flags, [1] max radial neighbours, [2] max angular neighbours,
+                                  // [3] max candidates, [4] spread (float bits)
 };
 
 struct nep_ws {
@@ -69,6 +82,7 @@ struct nep_ws {
     double *partE = nullptr;   // [P][nblk]
     double *partW = nullptr;   // [2][P][nblk][9] (angular pass, radial pass)
     float *Fang = nullptr;     // [P*N][3] angular part of the forces
+    float *pos4 = nullptr;     // [P*N][4] packed positions: offsets in a fine grid cell + cell index bits
     uint32_t *flags = nullptr; // [1]
 };
 
@@ -108,8 +122,9 @@ bool box_lengths(const double box[9], double L[3]);
 
 // Kernel timing (hipEvents around launches on the caller's stream), off by default.
 enum KernelId {
-    K_FILL = 0, K_CENTROID, K_GRID, K_CELL_COUNT, K_CELL_SCAN, K_CELL_FILL, K_CELL_SORT, K_CANDIDATES, K_NLIST,
-    K_DESCRIPTOR, K_FORCE_ANG, K_FORCE, K_REDUCE, K_TRPMD, K_MODES, K_NUM
+    K_FILL = 0, K_CENTROID, K_GRID, K_CELL_COUNT, K_CELL_SCAN, K_CELL_FILL, K_CELL_SORT, K_CANDIDATES,
+    K_SORT_ROWS, K_REVERSE, K_NLIST,
+    K_PACK, K_DESCRIPTOR, K_FORCE_ANG, K_FORCE, K_REDUCE, K_TRPMD, K_MODES, K_NUM
 };
 struct ProfScope {
     int id;

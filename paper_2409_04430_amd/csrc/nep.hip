@@ -1,24 +1,25 @@
 // NEP energy, forces and virial on gfx950 (site-energy model of Sec. II.C,
 // bead forces and virial of Sec. II.A of arXiv:2409.04430).
 //
-// Four kernels per call, one lane per (bead, atom):
+// Four kernels per call, one lane per (bead, atom), neighbours taken from
+// the per-bead compact lists built over the shared centroid candidate rows:
 //   k_descriptor  radial sums, angular sums A_nlm = sum_j g_n(r_ij) Y_lm(u_ij)
 //                 over real orthonormal spherical harmonics, q_nl = sum_m A_nlm^2
 //                 (equal to the Legendre double sum by the addition theorem),
 //                 the optional (2,2,2) four-body invariant, the tanh network,
 //                 and the adjoints: B_nlm = dU_i/dA_nlm and the radial
 //                 a_k(t) = sum_n dU_i/dq_n c^{ti t}_nk;
-//   k_force_ang   angular pair terms in gather form, one contraction with
-//                 B^i_nlm g^{ij}_n + (-1)^l B^j_nlm g^{ji}_n per neighbour, so
-//                 F_i = sum_j (dU_i/dr_ij - dU_j/dr_ji) needs no atomics;
-//   k_force_rad   radial pair terms (a^i_k(tj) + a^j_k(ti)) f'_k(r) u, added to
-//                 the angular part; per-atom virial -1/2 sum_j r_ij (x) phi_ij;
+//   k_force_ang   angular pair terms d_ij = dU_i/dr_ij from the atom's own
+//                 adjoints, kept per (bead, atom, candidate slot);
+//   k_force_rad   radial pair terms (a^i_k(tj) + a^j_k(ti)) f'_k(r) u, the
+//                 reverse angular terms d_ji gathered through the reverse
+//                 slots, so that F_i = sum_j (dU_i/dr_ij - dU_j/dr_ji) needs no
+//                 atomics; per-atom virial -1/2 sum_j r_ij (x) (d_ij - d_ji);
 //   k_reduce      per-bead energy and virial from per-block partial sums in
 //                 a fixed order (bitwise reproducible).
 // The descriptor and angular-force passes run species-uniform groups of
 // lanes, which makes every model-coefficient address wave-uniform (scalar
-// loads, SGPR operands).  Neighbour loops prefetch the next index and
-// position so that gathers overlap arithmetic.
+// loads, SGPR operands).  Neighbour loops keep several gathers in flight.
 #include "internal.hpp"
 
 namespace nep {
@@ -26,15 +27,18 @@ namespace nep {
 constexpr float kPi = 3.14159265358979f;
 
 struct NepArgs {
-    const double *pos;
+    const float4 *p4;   // packed positions [P][N]: offsets in a fine grid cell, cell index bits in w
     const int32_t *types;
     int N, S, H;
-    double L[3], invL[3];
+    int M[3];            // fine grid cells per axis
+    float h[3];          // fine grid spacing L / M
     float rcRinv, rcAinv;
     float kappa4;
-    // lists
-    const int32_t *cntR, *idxR, *cntA, *idxA;
-    int capR, capA;
+    // per-bead lists, slot-major: list[(b * cap + s) * N + i]
+    const int32_t *listR, *endR, *listA, *endA, *slotA;
+    const uint64_t *maskA;   // [P][WC][N] angular hits per candidate word | hits before the word << 32
+    int capR, capA, capC, WC;
+    float4 *pairbuf;   // [P][capA][N] dU_j/dr_ji at the receiving atom's list position (w unused)
     // workspace
     float *B;
     float *arad;
@@ -50,17 +54,61 @@ struct NepArgs {
     int oR, oA, oq, oW0, ob0, ow1, ob1, osh;
 };
 
-// Pair vector r_j - r_i under the minimum image, formed in FP64, returned in FP32.
-__device__ __forceinline__ void pair_vec(double xj, double yj, double zj, double xi, double yi, double zi,
-                                         const NepArgs &a, float &dx, float &dy, float &dz)
+// Start and end of species block t in the list of (bead b, atom i).
+__device__ __forceinline__ void block_range(const int32_t *end, int b, int t, int N, int i, int &s0, int &s1)
 {
-    double x = xj - xi, y = yj - yi, z = zj - zi;
-    x -= a.L[0] * rint(x * a.invL[0]);
-    y -= a.L[1] * rint(y * a.invL[1]);
-    z -= a.L[2] * rint(z * a.invL[2]);
-    dx = (float)x;
-    dy = (float)y;
-    dz = (float)z;
+    const size_t base = (size_t)b * kMaxSpecies * N + i;
+    s0 = t ? end[base + (size_t)(t - 1) * N] : 0;
+    s1 = end[base + (size_t)t * N];
+}
+
+// Minimum-image difference of two fine-grid cell indices (0 <= c < M).
+__device__ __forceinline__ int wrap_cell(int d, int M)
+{
+    const int hM = M >> 1;
+    return d > hM ? d - M : (d < -hM ? d + M : d);
+}
+
+// Pair vector r_j - r_i from packed positions: the FP32 offsets inside the
+// fine grid cells plus the minimum-image cell difference times the spacing.
+// Exact in the image choice whenever |r_ij| < L/2 - h (every pair inside a
+// cutoff; the host picks h accordingly), and accurate to a few 1e-7 A.
+__device__ __forceinline__ void pair_vec(const float4 &pj, const float4 &pi, const NepArgs &a, float &dx, float &dy,
+                                         float &dz)
+{
+    const int wj = __float_as_int(pj.w), wi = __float_as_int(pi.w);
+    const int cx = wrap_cell((wj & 1023) - (wi & 1023), a.M[0]);
+    const int cy = wrap_cell(((wj >> 10) & 1023) - ((wi >> 10) & 1023), a.M[1]);
+    const int cz = wrap_cell(((wj >> 20) & 1023) - ((wi >> 20) & 1023), a.M[2]);
+    dx = fmaf(a.h[0], (float)cx, pj.x - pi.x);
+    dy = fmaf(a.h[1], (float)cy, pj.y - pi.y);
+    dz = fmaf(a.h[2], (float)cz, pj.z - pi.z);
+}
+
+// Packs the FP64 positions: per axis the fine cell c = floor(x / h) mod M
+// and the offset x - floor(x / h) h in FP32 (unwrapped coordinates allowed).
+__global__ void k_pack(const double *__restrict__ pos, size_t n, double3 Minv, int3 M, double3 h,
+                       float4 *__restrict__ out)
+{
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const double x[3] = {pos[3 * e], pos[3 * e + 1], pos[3 * e + 2]};
+    const double mi[3] = {Minv.x, Minv.y, Minv.z}, hh[3] = {h.x, h.y, h.z};
+    const int mm[3] = {M.x, M.y, M.z};
+    float o[3];
+    int bits = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        double fl = floor(x[d] * mi[d]);
+        if (!isfinite(fl)) fl = 0.0;
+        o[d] = (float)(x[d] - fl * hh[d]);
+        double c = fl - (double)mm[d] * floor(fl / (double)mm[d]);
+        int ci = (int)c;
+        ci = ci < 0 ? 0 : (ci >= mm[d] ? mm[d] - 1 : ci);
+        bits |= ci << (10 * d);
+    }
+    if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) o[0] = __int_as_float(0x7fc00000);
+    out[e] = make_float4(o[0], o[1], o[2], __int_as_float(bits));
 }
 
 // sin(pi z) and cos(pi z) for z in [0, 1]: with w = z - 1/2, cos(pi z) =
@@ -288,8 +336,8 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
     const int ii = valid ? i : N - 1;
     const int ti = a.types[ii];
     const bool tok = ti >= 0 && ti < S;
-    const double *pb = a.pos + (size_t)b * N * 3;
-    const double xi = pb[3 * ii], yi = pb[3 * ii + 1], zi = pb[3 * ii + 2];
+    const float4 *pb = a.p4 + (size_t)b * N;
+    const float4 pi = pb[ii];
     const float *shc = prm + a.osh;
     float U = 0.0f;
 
@@ -306,34 +354,31 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
         for (int v = 0; v < D; ++v) q[v] = 0.0f;
 
         // radial: per neighbour species, sum the basis, then contract with c
+        const int32_t *lR = a.listR + (size_t)b * a.capR * N + i;
+        const int32_t *lA = a.listA + (size_t)b * a.capA * N + i;
         for (int t = 0; t < S; ++t) {
-            const size_t blk = ((size_t)b * S + t);
-            const int cnt = min(a.cntR[blk * N + i], a.capR);
-            const int32_t *ix = a.idxR + blk * a.capR * N + i;
+            int s0, s1;
+            block_range(a.endR, b, t, N, i, s0, s1);
             float sk[KR1];
 #pragma unroll
             for (int k = 0; k < KR1; ++k) sk[k] = 0.0f;
-            for (int s0 = 0; s0 < cnt; s0 += kBatch) {
-                int jj[kBatch];
-#pragma unroll
-                for (int u = 0; u < kBatch; ++u) jj[u] = (s0 + u < cnt) ? ix[(size_t)(s0 + u) * N] : i;
-                double px[kBatch], py[kBatch], pz[kBatch];
+            for (int sb = s0; sb < s1; sb += kBatch) {
+                float4 pj[kBatch];
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
-                    px[u] = pb[3 * jj[u]];
-                    py[u] = pb[3 * jj[u] + 1];
-                    pz[u] = pb[3 * jj[u] + 2];
+                    const int j = (sb + u < s1) ? lR[(size_t)(sb + u) * N] : i;
+                    pj[u] = pb[j];
                 }
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
-                    if (s0 + u < cnt) {
+                    if (sb + u < s1) {
                         float dx, dy, dz;
-                        pair_vec(px[u], py[u], pz[u], xi, yi, zi, a, dx, dy, dz);
+                        pair_vec(pj[u], pi, a, dx, dy, dz);
                         const float r = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
                         float f[KR1];
                         cheb_f<KR1>(r, a.rcRinv, f);
 #pragma unroll
-                        for (int k = 0; k < KR1; ++k) sk[k] += f[k];
+                        for (int q2 = 0; q2 < KR1; ++q2) sk[q2] += f[q2];
                     }
                 }
             }
@@ -342,7 +387,7 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             for (int n = 0; n < NR1; ++n) {
                 float acc = q[n];
 #pragma unroll
-                for (int k = 0; k < KR1; ++k) acc += c[n * KR1 + k] * sk[k];
+                for (int q2 = 0; q2 < KR1; ++q2) acc += c[n * KR1 + q2] * sk[q2];
                 q[n] = acc;
             }
         }
@@ -354,22 +399,15 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
 #pragma unroll
             for (int m = 0; m < kNumSH; ++m) A[n][m] = 0.0f;
         for (int t = 0; t < S; ++t) {
-            const size_t blk = ((size_t)b * S + t);
-            const int cnt = min(a.cntA[blk * N + i], a.capA);
-            const int32_t *ix = a.idxA + blk * a.capA * N + i;
+            int s0, s1;
+            block_range(a.endA, b, t, N, i, s0, s1);
             const float *c = prm + a.oA + (tc * S + t) * NA1 * KA1;
-            int jn = cnt > 0 ? ix[0] : i;
-            double nx = pb[3 * jn], ny = pb[3 * jn + 1], nz = pb[3 * jn + 2];
-            for (int s = 0; s < cnt; ++s) {
-                const double cx = nx, cy = ny, cz = nz;
-                if (s + 1 < cnt) {
-                    jn = ix[(size_t)(s + 1) * N];
-                    nx = pb[3 * jn];
-                    ny = pb[3 * jn + 1];
-                    nz = pb[3 * jn + 2];
-                }
+            float4 pn = pb[s0 < s1 ? lA[(size_t)s0 * N] : i];
+            for (int sn = s0; sn < s1; ++sn) {
+                const float4 pc = pn;
+                if (sn + 1 < s1) pn = pb[lA[(size_t)(sn + 1) * N]];
                 float dx, dy, dz;
-                pair_vec(cx, cy, cz, xi, yi, zi, a, dx, dy, dz);
+                pair_vec(pc, pi, a, dx, dy, dz);
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 const float rinv = __builtin_amdgcn_rsqf(r2);
                 const float r = r2 * rinv;
@@ -381,7 +419,7 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                 for (int n = 0; n < NA1; ++n) {
                     float g = 0.0f;
 #pragma unroll
-                    for (int k = 0; k < KA1; ++k) g += c[n * KA1 + k] * f[k];
+                    for (int q2 = 0; q2 < KA1; ++q2) g += c[n * KA1 + q2] * f[q2];
 #pragma unroll
                     for (int m = 0; m < kNumSH; ++m) A[n][m] += g * Y[m];
                 }
@@ -501,14 +539,19 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
     if (threadIdx.x == 0) a.partE[(size_t)b * gridDim.x + tile] = e;
 }
 
-// ------------------------------------------------------ pass 2: angular ---
+// ------------------------------------------------ pass 2: angular, own ---
 
-// SYM: one species, so c^{ij} = c^{ji} and the pair term uses
-// B~ = B^i + (-1)^l B^j once.  BREG: the own adjoints stay in registers
-// (small n_max); otherwise they are re-read row by row (L1-resident).
-// Per-atom sums of the 26-odd angular pair terms are kept in FP32; the radial
-// pass adds them to its FP64 sums.
-template <int NA1, int KA1, bool SYM, bool BREG>
+// One lane per (bead, atom i): the angular pair terms d_ij = dU_i/dr_ij of
+// the atom's own site energy, contracted with its own adjoints only:
+//   d_ij = sum_n sum_lm B^i_nlm d/dr_ij [ g^{ij}_n(r) Y_lm(u) ],
+// stored at (bead, i, candidate slot of j) for the reverse gather of the
+// radial pass, and summed into the angular force part F_i += d_ij and the
+// virial -r_ij (x) d_ij (the total needs no reverse terms).  BREG keeps B^i
+// in registers (small n_max); otherwise it is re-read from its L1-resident
+// row.  Control flow stays wave-uniform: lanes outside the current centre
+// species, or past their last neighbour, compute on a dummy pair and
+// contribute nothing.
+template <int NA1, int KA1, bool BREG>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void k_force_ang(NepArgs a, const float *__restrict__ prm)
 {
@@ -520,17 +563,18 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
     const int ii = valid ? i : N - 1;
     const int ti = a.types[ii];
     const bool tok = ti >= 0 && ti < S;
-    const double *pb = a.pos + (size_t)b * N * 3;
-    const double xi = pb[3 * ii], yi = pb[3 * ii + 1], zi = pb[3 * ii + 2];
+    const float4 *pb = a.p4 + (size_t)b * N;
+    const float4 pi = pb[ii];
     const float *shc = prm + a.osh;
+    const int32_t *lA = a.listA + (size_t)b * a.capA * N + ii;
+    const int32_t *sA = a.slotA + (size_t)b * a.capA * N + ii;
+    const uint64_t *mkb = a.maskA + (size_t)b * a.WC * N;
+    float4 *pbuf = a.pairbuf + (size_t)b * a.capA * N;
     float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f;
     float Wv[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) Wv[e] = 0.0f;
 
-    // Control flow stays wave-uniform: lanes outside the current centre
-    // species (or past their neighbour count) compute on a dummy pair and
-    // contribute nothing.
     uint64_t todo = __ballot(valid && tok);
     while (todo) {
         const int lead = __builtin_ctzll(todo);
@@ -551,23 +595,32 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
                 }
         }
         for (int t = 0; t < S; ++t) {
-            const size_t blk = ((size_t)b * S + t);
-            const int cnt = mine ? min(a.cntA[blk * N + i], a.capA) : 0;
+            int s0 = 0, s1 = 0;
+            if (mine) block_range(a.endA, b, t, N, ii, s0, s1);
+            const int cnt = s1 - s0;
             int cmax = cnt;
             for (int o = 32; o > 0; o >>= 1) cmax = max(cmax, __shfl_xor(cmax, o));
             cmax = __builtin_amdgcn_readfirstlane(cmax);
-            const int32_t *ix = a.idxA + blk * a.capA * N + ii;
             const float *cij = prm + a.oA + (tc * S + t) * NA1 * KA1;
-            const float *cji = prm + a.oA + (t * S + tc) * NA1 * KA1;
-            int jn = cnt > 0 ? ix[0] : ii;
-            for (int s = 0; s < cmax; ++s) {
-                const float *cij_l = launder(cij), *cji_l = launder(cji), *shc_l = launder(shc);
-                const bool act = s < cnt;
-                const int j = jn;
-                if (s + 1 < cnt) jn = ix[(size_t)(s + 1) * N];
-                const float4 *bj4 = reinterpret_cast<const float4 *>(a.B + ((size_t)b * N + j) * (NA1 * kNumSH));
+            int jn = cnt > 0 ? lA[(size_t)s0 * N] : ii;
+            int rn = cnt > 0 ? (int)((uint32_t)sA[(size_t)s0 * N] >> 16) : 0xffff;
+            for (int sc = 0; sc < cmax; ++sc) {
+                const float *cij_l = launder(cij), *shc_l = launder(shc);
+                const bool act = sc < cnt;
+                const int j = jn, rc = rn;
+                if (sc + 1 < cnt) {
+                    jn = lA[(size_t)(s0 + sc + 1) * N];
+                    rn = (int)((uint32_t)sA[(size_t)(s0 + sc + 1) * N] >> 16);
+                }
+                // list position of i in j's angular list: angular hits of j before its slot rc
+                int dst = -1;
+                if (act && rc != 0xffff) {
+                    const uint64_t m = mkb[(size_t)(rc >> 5) * N + j];
+                    dst = (int)(m >> 32) + __popc((uint32_t)m & ((1u << (rc & 31)) - 1u));
+                    if (dst >= a.capA) dst = -1;
+                }
                 float dx, dy, dz;
-                pair_vec(pb[3 * j], pb[3 * j + 1], pb[3 * j + 2], xi, yi, zi, a, dx, dy, dz);
+                pair_vec(pb[j], pi, a, dx, dy, dz);
                 if (!act) {
                     dx = 1.0f;
                     dy = 0.0f;
@@ -577,7 +630,7 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
                 const float rinv = __builtin_amdgcn_rsqf(r2);
                 const float r = r2 * rinv;
                 const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
-                float gij[NA1], gpij[NA1], gji[SYM ? 1 : NA1], gpji[SYM ? 1 : NA1];
+                float gij[NA1], gpij[NA1];
                 {
                     float f[KA1], fp[KA1];
                     cheb_fd<KA1>(r, a.rcAinv, f, fp);
@@ -585,22 +638,12 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
                     for (int n = 0; n < NA1; ++n) {
                         float g0 = 0.0f, g1 = 0.0f;
 #pragma unroll
-                        for (int k = 0; k < KA1; ++k) {
-                            g0 = fmaf(cij_l[n * KA1 + k], f[k], g0);
-                            g1 = fmaf(cij_l[n * KA1 + k], fp[k], g1);
+                        for (int q2 = 0; q2 < KA1; ++q2) {
+                            g0 = fmaf(cij_l[n * KA1 + q2], f[q2], g0);
+                            g1 = fmaf(cij_l[n * KA1 + q2], fp[q2], g1);
                         }
                         gij[n] = g0;
                         gpij[n] = g1;
-                        if (!SYM) {
-                            float h0 = 0.0f, h1 = 0.0f;
-#pragma unroll
-                            for (int k = 0; k < KA1; ++k) {
-                                h0 = fmaf(cji_l[n * KA1 + k], f[k], h0);
-                                h1 = fmaf(cji_l[n * KA1 + k], fp[k], h1);
-                            }
-                            gji[SYM ? 0 : n] = h0;
-                            gpji[SYM ? 0 : n] = h1;
-                        }
                     }
                 }
                 float beta[kNumSH], betap[kNumSH];
@@ -613,8 +656,6 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
                 for (int n = 0; n < NA1; ++n) {
 #pragma unroll
                     for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
-                        const float4 y4 = bj4[n * (kNumSH / 4) + q4];
-                        const float bj[4] = {y4.x, y4.y, y4.z, y4.w};
                         float bx[4];
                         if (!BREG) {
                             const float4 x4 = bi4[n * (kNumSH / 4) + q4];
@@ -624,32 +665,24 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
                         for (int e = 0; e < 4; ++e) {
                             const int m = 4 * q4 + e;
                             const float bi = BREG ? Bi[BREG ? n : 0][m] : bx[e];
-                            const float sj = (sh_l(m) & 1) ? -bj[e] : bj[e];
-                            if (SYM) {
-                                const float bt = bi + sj;
-                                beta[m] = fmaf(bt, gij[n], beta[m]);
-                                betap[m] = fmaf(bt, gpij[n], betap[m]);
-                            } else {
-                                beta[m] = fmaf(sj, gji[SYM ? 0 : n], fmaf(bi, gij[n], beta[m]));
-                                betap[m] = fmaf(sj, gpji[SYM ? 0 : n], fmaf(bi, gpij[n], betap[m]));
-                            }
+                            beta[m] = fmaf(bi, gij[n], beta[m]);
+                            betap[m] = fmaf(bi, gpij[n], betap[m]);
                         }
                     }
-                    // keep the loads of row n + 1 behind this row's arithmetic (register pressure)
-                    __builtin_amdgcn_sched_barrier(0);
                 }
                 float sY, gx, gy, gz;
                 sh_contract(ux, uy, uz, shc_l, beta, betap, sY, gx, gy, gz);
                 const float ug = ux * gx + uy * gy + uz * gz;
-                const float sel = act ? 1.0f : 0.0f;
-                const float px = sel * (sY * ux + (gx - ux * ug) * rinv);
-                const float py = sel * (sY * uy + (gy - uy * ug) * rinv);
-                const float pz = sel * (sY * uz + (gz - uz * ug) * rinv);
-                Fx += px; Fy += py; Fz += pz;
-                const float hx = -0.5f * dx, hy = -0.5f * dy, hz = -0.5f * dz;
-                Wv[0] = fmaf(hx, px, Wv[0]); Wv[1] = fmaf(hx, py, Wv[1]); Wv[2] = fmaf(hx, pz, Wv[2]);
-                Wv[3] = fmaf(hy, px, Wv[3]); Wv[4] = fmaf(hy, py, Wv[4]); Wv[5] = fmaf(hy, pz, Wv[5]);
-                Wv[6] = fmaf(hz, px, Wv[6]); Wv[7] = fmaf(hz, py, Wv[7]); Wv[8] = fmaf(hz, pz, Wv[8]);
+                const float px = sY * ux + (gx - ux * ug) * rinv;
+                const float py = sY * uy + (gy - uy * ug) * rinv;
+                const float pz = sY * uz + (gz - uz * ug) * rinv;
+                if (act) {
+                    if (dst >= 0) pbuf[(size_t)dst * N + j] = make_float4(px, py, pz, 0.0f);
+                    Fx += px; Fy += py; Fz += pz;
+                    Wv[0] = fmaf(-dx, px, Wv[0]); Wv[1] = fmaf(-dx, py, Wv[1]); Wv[2] = fmaf(-dx, pz, Wv[2]);
+                    Wv[3] = fmaf(-dy, px, Wv[3]); Wv[4] = fmaf(-dy, py, Wv[4]); Wv[5] = fmaf(-dy, pz, Wv[5]);
+                    Wv[6] = fmaf(-dz, px, Wv[6]); Wv[7] = fmaf(-dz, py, Wv[7]); Wv[8] = fmaf(-dz, pz, Wv[8]);
+                }
             }
         }
     }
@@ -660,9 +693,10 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
         Fo[1] = Fy;
         Fo[2] = Fz;
         if (a.Watom) {
+            // own half of the per-atom split; the reverse half is added by the radial pass
             float *wo = a.Watom + ((size_t)b * N + i) * 9;
 #pragma unroll
-            for (int e = 0; e < 9; ++e) wo[e] = Wv[e];
+            for (int e = 0; e < 9; ++e) wo[e] = 0.5f * Wv[e];
         }
     }
     __shared__ double lds[4];
@@ -673,8 +707,13 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
     }
 }
 
-// ------------------------------------------------------- pass 2: radial ---
+// ----------------------------------------- pass 3: radial + combination ---
 
+// One lane per (bead, atom i): radial pair terms (a^i_k(tj) + a^j_k(ti)) f'_k(r) u
+// (both site energies at once, the adjoints a_k are gathered), then the
+// reverse angular terms -dU_j/dr_ji gathered from the pair buffer through the
+// reverse slot of each angular neighbour, then the angular own part of pass 2.
+// Force and per-atom virial sums are kept in FP64.
 template <int KR1>
 __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
 {
@@ -686,41 +725,40 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
     const int ii = valid ? i : N - 1;
     const int ti = a.types[ii];
     const bool tok = ti >= 0 && ti < S;
-    const double *pb = a.pos + (size_t)b * N * 3;
-    const double xi = pb[3 * ii], yi = pb[3 * ii + 1], zi = pb[3 * ii + 2];
+    const float4 *pb = a.p4 + (size_t)b * N;
+    const float4 pi = pb[ii];
     double Fx = 0.0, Fy = 0.0, Fz = 0.0;
     double Wv[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) Wv[e] = 0.0;
+    float Wa[9];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) Wa[e] = 0.0f;
     if (valid && tok) {
         const float *ai_base = a.arad + ((size_t)b * N + i) * S * a.KRP;
+        const int32_t *lR = a.listR + (size_t)b * a.capR * N + i;
         for (int t = 0; t < S; ++t) {
-            const size_t blk = ((size_t)b * S + t);
-            const int cnt = min(a.cntR[blk * N + i], a.capR);
-            const int32_t *ix = a.idxR + blk * a.capR * N + i;
+            int s0, s1;
+            block_range(a.endR, b, t, N, i, s0, s1);
             float ai[KR1];
 #pragma unroll
-            for (int k = 0; k < KR1; ++k) ai[k] = ai_base[t * a.KRP + k];
-            for (int s0 = 0; s0 < cnt; s0 += kBatch) {
-                int jj[kBatch];
-#pragma unroll
-                for (int u = 0; u < kBatch; ++u) jj[u] = (s0 + u < cnt) ? ix[(size_t)(s0 + u) * N] : i;
-                double px[kBatch], py[kBatch], pz[kBatch];
+            for (int q2 = 0; q2 < KR1; ++q2) ai[q2] = ai_base[t * a.KRP + q2];
+            for (int sb = s0; sb < s1; sb += kBatch) {
+                float4 pj[kBatch];
                 float aj[kBatch][KR1];
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
-                    px[u] = pb[3 * jj[u]];
-                    py[u] = pb[3 * jj[u] + 1];
-                    pz[u] = pb[3 * jj[u] + 2];
-                    const float *ajp = a.arad + ((size_t)b * N + jj[u]) * S * a.KRP + ti * a.KRP;
+                    const int j = (sb + u < s1) ? lR[(size_t)(sb + u) * N] : i;
+                    pj[u] = pb[j];
+                    const float *ajp = a.arad + ((size_t)b * N + j) * S * a.KRP + ti * a.KRP;
 #pragma unroll
-                    for (int k = 0; k < KR1; ++k) aj[u][k] = ajp[k];
+                    for (int q2 = 0; q2 < KR1; ++q2) aj[u][q2] = ajp[q2];
                 }
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
-                    if (s0 + u < cnt) {
+                    if (sb + u < s1) {
                         float dx, dy, dz;
-                        pair_vec(px[u], py[u], pz[u], xi, yi, zi, a, dx, dy, dz);
+                        pair_vec(pj[u], pi, a, dx, dy, dz);
                         const float r2 = dx * dx + dy * dy + dz * dz;
                         const float rinv = __builtin_amdgcn_rsqf(r2);
                         const float r = r2 * rinv;
@@ -728,7 +766,7 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
                         cheb_fd<KR1>(r, a.rcRinv, f, fp);
                         float sc = 0.0f;
 #pragma unroll
-                        for (int k = 0; k < KR1; ++k) sc += (ai[k] + aj[u][k]) * fp[k];
+                        for (int q2 = 0; q2 < KR1; ++q2) sc += (ai[q2] + aj[u][q2]) * fp[q2];
                         const float w = sc * rinv;
                         const float qx = w * dx, qy = w * dy, qz = w * dz;
                         Fx += qx; Fy += qy; Fz += qz;
@@ -739,6 +777,40 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
                 }
             }
         }
+
+        // reverse angular terms: F_i -= dU_j/dr_ji for every angular neighbour j,
+        // deposited at this atom's own list positions by the angular pass
+        const int32_t *lA = a.listA + (size_t)b * a.capA * N + i;
+        const float4 *pbuf = a.pairbuf + (size_t)b * a.capA * N + i;
+        const int nA = a.endA[((size_t)b * kMaxSpecies + (S - 1)) * N + i];
+        float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+        for (int sb = 0; sb < nA; sb += kBatch) {
+            float4 d[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u)
+                d[u] = sb + u < nA ? pbuf[(size_t)(sb + u) * N] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                gx -= d[u].x; gy -= d[u].y; gz -= d[u].z;
+            }
+            if (a.Watom) {
+                // reverse half of the per-atom split: +1/2 r_ij (x) dU_j/dr_ji
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    if (sb + u < nA) {
+                        float dx, dy, dz;
+                        pair_vec(pb[lA[(size_t)(sb + u) * N]], pi, a, dx, dy, dz);
+                        const float hx = 0.5f * dx, hy = 0.5f * dy, hz = 0.5f * dz;
+                        Wa[0] = fmaf(hx, d[u].x, Wa[0]); Wa[1] = fmaf(hx, d[u].y, Wa[1]); Wa[2] = fmaf(hx, d[u].z, Wa[2]);
+                        Wa[3] = fmaf(hy, d[u].x, Wa[3]); Wa[4] = fmaf(hy, d[u].y, Wa[4]); Wa[5] = fmaf(hy, d[u].z, Wa[5]);
+                        Wa[6] = fmaf(hz, d[u].x, Wa[6]); Wa[7] = fmaf(hz, d[u].y, Wa[7]); Wa[8] = fmaf(hz, d[u].z, Wa[8]);
+                    }
+                }
+            }
+        }
+        Fx += (double)gx;
+        Fy += (double)gy;
+        Fz += (double)gz;
     }
     if (valid) {
         const float *fa = a.Fang + ((size_t)b * N + i) * 3;
@@ -750,7 +822,7 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
         if (a.Watom) {
             float *wo = a.Watom + ((size_t)b * N + i) * 9;
 #pragma unroll
-            for (int e = 0; e < 9; ++e) wo[e] = (float)(Wv[e] + (double)wo[e]);
+            for (int e = 0; e < 9; ++e) wo[e] = (float)(Wv[e] + (double)Wa[e] + (double)wo[e]);
         }
         if (!(isfinite(gx) && isfinite(gy) && isfinite(gz))) atomicOr(a.flags, (uint32_t)NEP_FLAG_NONFINITE);
     }
@@ -782,7 +854,7 @@ __global__ void k_reduce(const double *__restrict__ partE, const double *__restr
 }
 
 template <int NR1, int NA1, bool FOUR>
-static void launch(const NepArgs &a, const float *prm, int P, bool sym, hipStream_t s)
+static void launch(const NepArgs &a, const float *prm, int P, hipStream_t s)
 {
     const dim3 g(div_up(a.N, kBlock), P);
     {
@@ -791,10 +863,7 @@ static void launch(const NepArgs &a, const float *prm, int P, bool sym, hipStrea
     }
     {
         ProfScope ps_(K_FORCE_ANG, s);
-        if (sym)
-            hipLaunchKernelGGL((k_force_ang<NA1, 9, true, (NA1 <= 5)>), g, dim3(kBlock), 0, s, a, prm);
-        else
-            hipLaunchKernelGGL((k_force_ang<NA1, 9, false, (NA1 <= 5)>), g, dim3(kBlock), 0, s, a, prm);
+        hipLaunchKernelGGL((k_force_ang<NA1, 9, (NA1 <= 5)>), g, dim3(kBlock), 0, s, a, prm);
     }
     {
         ProfScope ps_(K_FORCE, s);
@@ -806,7 +875,7 @@ static void launch(const NepArgs &a, const float *prm, int P, bool sym, hipStrea
 
 using namespace nep;
 
-extern "C" int32_t nep_compute(const nep_model *m, const nep_nlist *nl, nep_ws *ws, const double *pos,
+extern "C" int32_t nep_compute(const nep_model *m, nep_nlist *nl, nep_ws *ws, const double *pos,
                                const double box[9], const int32_t *types, int32_t P, int32_t N, double *E, float *F,
                                double *W, float *E_atom, float *W_atom, hipStream_t s)
 {
@@ -824,31 +893,55 @@ extern "C" int32_t nep_compute(const nep_model *m, const nep_nlist *nl, nep_ws *
     }
     if (!pos || !types || !F) return fail(NEP_ERR_INVALID_ARG, "nep_compute: null array");
     NepArgs a{};
-    if (!box_lengths(box, a.L)) return fail(NEP_ERR_UNSUPPORTED, "nep_compute: only orthorhombic cells");
+    double L[3];
+    if (!box_lengths(box, L)) return fail(NEP_ERR_UNSUPPORTED, "nep_compute: only orthorhombic cells");
+    const double rcmax = std::max(m->hp.rc_radial, m->hp.rc_angular);
+    int3 Mi;
+    double3 Minv, hh;
     for (int d = 0; d < 3; ++d) {
-        if (!(a.L[d] > 0.0)) return fail(NEP_ERR_INVALID_ARG, "nep_compute: bad box edge %g", a.L[d]);
-        a.invL[d] = 1.0 / a.L[d];
+        if (!(L[d] > 0.0) || !std::isfinite(L[d]))
+            return fail(NEP_ERR_INVALID_ARG, "nep_compute: bad box edge %g", L[d]);
+        // fine grid spacing h <= 1 A and h < (L/2 - rc)/2, so that every pair
+        // inside the cutoff gets its minimum image from the cell difference
+        const double room = 0.5 * (0.5 * L[d] - rcmax);
+        const double hmax = std::min(1.0, room);
+        int M = (hmax > L[d] / 1023.0) ? (int)std::ceil(L[d] / hmax) : 1023;
+        M = std::max(1, std::min(M, 1023));
+        a.M[d] = M;
+        a.h[d] = (float)(L[d] / M);
+        (&Mi.x)[d] = M;
+        (&Minv.x)[d] = M / L[d];
+        (&hh.x)[d] = L[d] / M;
     }
     const nep_hparams &h = m->hp;
-    a.pos = pos; a.types = types; a.N = N; a.S = h.n_species; a.H = h.hidden;
+    a.p4 = reinterpret_cast<const float4 *>(ws->pos4); a.types = types; a.N = N; a.S = h.n_species; a.H = h.hidden;
     a.rcRinv = (float)(1.0 / h.rc_radial); a.rcAinv = (float)(1.0 / h.rc_angular);
     a.kappa4 = (float)(-4.5 * std::sqrt(2.0 / 35.0) * std::pow(5.0 / (4.0 * M_PI), 1.5));
-    a.cntR = nl->cntR; a.idxR = nl->idxR; a.cntA = nl->cntA; a.idxA = nl->idxA;
-    a.capR = nl->capR; a.capA = nl->capA;
+    a.listR = nl->listR; a.endR = nl->endR; a.listA = nl->listA; a.endA = nl->endA; a.slotA = nl->slotA;
+    a.maskA = nl->maskA;
+    a.capR = nl->capR; a.capA = nl->capA; a.capC = nl->capC; a.WC = nl->WC;
+    a.pairbuf = reinterpret_cast<float4 *>(nl->pairbuf);
     a.B = ws->B; a.arad = ws->arad; a.Fang = ws->Fang; a.KRP = ws->KRP;
     a.partE = ws->partE; a.partWa = ws->partW; a.partWr = ws->partW + (size_t)P * ws->nblk * 9;
     a.flags = ws->flags;
     a.F = F; a.Eatom = E_atom; a.Watom = W_atom;
     a.oR = m->off.cR; a.oA = m->off.cA; a.oq = m->off.qs; a.oW0 = m->off.W0; a.ob0 = m->off.b0;
     a.ow1 = m->off.w1; a.ob1 = m->off.b1; a.osh = m->off.sh;
-    const bool sym = h.n_species == 1;
     const int key = h.n_max_radial * 100 + h.n_max_angular * 10 + h.four_body;
+    if (key != 440 && key != 441 && key != 640 && key != 860 && key != 881)
+        return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");
+    {
+        ProfScope ps_(K_PACK, s);
+        const size_t n = (size_t)P * N;
+        hipLaunchKernelGGL(k_pack, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pos, n, Minv, Mi,
+                           hh, reinterpret_cast<float4 *>(ws->pos4));
+    }
     switch (key) {
-    case 440: launch<5, 5, false>(a, m->dev, P, sym, s); break;
-    case 441: launch<5, 5, true>(a, m->dev, P, sym, s); break;
-    case 640: launch<7, 5, false>(a, m->dev, P, sym, s); break;
-    case 860: launch<9, 7, false>(a, m->dev, P, sym, s); break;
-    case 881: launch<9, 9, true>(a, m->dev, P, sym, s); break;
+    case 440: launch<5, 5, false>(a, m->dev, P, s); break;
+    case 441: launch<5, 5, true>(a, m->dev, P, s); break;
+    case 640: launch<7, 5, false>(a, m->dev, P, s); break;
+    case 860: launch<9, 7, false>(a, m->dev, P, s); break;
+    case 881: launch<9, 9, true>(a, m->dev, P, s); break;
     default: return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");
     }
     {

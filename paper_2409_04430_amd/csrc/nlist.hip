@@ -1,24 +1,30 @@
-// Per-bead neighbour lists through ring-polymer centroids (orthorhombic box).
+// Per-bead neighbour sets through ring-polymer centroids (orthorhombic box).
 //
 // Pairs are accepted by the literal FP64 minimum-image test
 //   d = r_j - r_i;  d -= L * rint(d / L)  (per axis);  (dx*dx + dy*dy) + dz*dz < rc*rc
 // without contraction, so the sets equal those of a brute-force search over
 // all pairs of a bead.  The division is replaced by a multiply with 1/L
 // whenever that provably gives the same integer (t = d/L farther than 1e-9
-// from a half-integer and |t| < 2^20); otherwise the division runs.
+// from a half-integer and |t| < 2^20); otherwise the division runs.  The
+// test is symmetric in i and j (every step of it is exactly antisymmetric),
+// so j is a neighbour of i exactly when i is one of j.
 //
 // Candidates: the P beads of an atom stay within D of their centroid, so a
 // bead pair closer than rc has centroids closer than rc + 2D.  One cell-list
-// search over the N centroids (instead of P searches over N beads) gives a
-// candidate list shared by every bead; each bead then filters it with the
-// exact test.  D, the cell grid and the search radius are computed on the
-// device in the same call (no host round trip), so the launch sequence can
-// be captured in a graph.
+// search over the N centroids (radius rc_radial + 2D, the larger cutoff)
+// gives each atom one candidate row, sorted by (species, index), and for
+// every candidate the slot at which the atom sits in the candidate's own
+// row.  Each bead then filters the row exactly into compact radial and
+// angular lists (slot-major, so that lanes read them coalesced), with
+// per-species block ends; each angular entry also carries the candidate
+// slot and the reverse slot used to address the angular pair terms.
+// D, the cell grid and the radius are computed on the device in the same
+// call, so the launch sequence needs no host round trip.
 //
-// Kernels per call: centroids and D -> grid -> count atoms per cell ->
-// scan -> scatter -> order each cell (rank sort, deterministic) ->
-// centroid candidates -> per-bead exact filter into species-blocked,
-// slot-major lists.
+// Kernels per call: centroids and D -> grid -> count atoms per cell -> scan
+// -> scatter -> order each cell -> candidate rows (a workgroup per cell,
+// stencil centroids staged in LDS) -> sort rows -> reverse slots ->
+// per-bead exact lists.
 #include "internal.hpp"
 
 namespace nep {
@@ -26,16 +32,16 @@ namespace nep {
 struct HostGrid {
     double L[3], invL[3];
     int nc_cap[3];     // allocation bound: floor(L / rc) per axis, at most 64
-    double rc;         // largest cutoff
+    double rcR, rcA;
 };
 
-// Device grid record (written by k_grid): nc[3], ncell, spread (float bits), pad, R^2 (double).
+// Device grid record (written by k_grid).
 struct DevGrid {
     int nc[3];
     int ncell;
     uint32_t spread_bits;
     uint32_t pad;
-    double R2;
+    double R2;    // candidate radius squared
 };
 
 __device__ __forceinline__ int cell_axis(double x, double L, double invL, int nc)
@@ -116,12 +122,13 @@ __global__ void k_centroid(const double *__restrict__ pos, const int32_t *__rest
     if (f) atomicOr(&status[0], f);
 }
 
-// Grid and search radius from the measured spread.
+// Grid and candidate radii from the measured spread.
 __global__ void k_grid(HostGrid g, uint32_t *__restrict__ grid, uint32_t *__restrict__ status)
 {
     DevGrid *dg = reinterpret_cast<DevGrid *>(grid);
     const float spread = __uint_as_float(dg->spread_bits);
-    const double R = g.rc + 2.0 * (double)spread + 1e-9 * (1.0 + g.rc);
+    const double rc = g.rcR > g.rcA ? g.rcR : g.rcA;
+    const double R = rc + 2.0 * (double)spread + 1e-9 * (1.0 + rc);
     int ncell = 1;
     for (int a = 0; a < 3; ++a) {
         int nc = (int)floor(g.L[a] / (R * (1.0 + 1e-9)));
@@ -225,145 +232,269 @@ __global__ __launch_bounds__(64) void k_cell_rank(const uint32_t *__restrict__ g
     }
 }
 
-// Candidates of atom i: centroids within R of its centroid (conservative
-// test).  One wavefront per atom: the lanes take the members of each stencil
-// cell together and append the accepted ones in order with a ballot and a
-// prefix popcount, so the order is fixed (stencil order, ascending index in
-// a cell).
+// Candidate rows.  One workgroup per cell; the centroids of its stencil
+// cells (3 x 3 x 3, fewer along an axis with fewer than 3 cells) are staged
+// in LDS when they fit, and each wavefront takes one atom of the cell at a
+// time, its lanes testing 64 stencil atoms at once and appending the
+// accepted ones by ballot + prefix popcount (stencil order; sorted later).
+// A stencil too large for LDS is read from global memory instead.
+constexpr int kStage = 2048;
 __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ cen, const int32_t *__restrict__ types,
                                                     int N, int S, HostGrid g, const uint32_t *__restrict__ grid,
                                                     const int32_t *__restrict__ cell_start,
                                                     const int32_t *__restrict__ cell_atoms, int capC,
-                                                    int32_t *__restrict__ cand, int32_t *__restrict__ candN,
+                                                    int32_t *__restrict__ cand, int32_t *__restrict__ rowlen,
                                                     uint32_t *__restrict__ status)
 {
-    const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (i >= N) return;   // whole wavefront
+    __shared__ double sx[kStage], sy[kStage], sz[kStage];
+    __shared__ int32_t sw[kStage];
+    __shared__ int32_t rs[28], rp[28];
+    __shared__ int nrange;
     const DevGrid *dg = reinterpret_cast<const DevGrid *>(grid);
+    const int c = blockIdx.x;
+    if (c >= dg->ncell) return;   // whole workgroup
     const int nc0 = dg->nc[0], nc1 = dg->nc[1], nc2 = dg->nc[2];
     const double R2 = dg->R2;
-    const double ci[3] = {cen[3 * i], cen[3 * i + 1], cen[3 * i + 2]};
-    const int cx = cell_axis(ci[0], g.L[0], g.invL[0], nc0);
-    const int cy = cell_axis(ci[1], g.L[1], g.invL[1], nc1);
-    const int cz = cell_axis(ci[2], g.L[2], g.invL[2], nc2);
-    const int oz_n = nc2 >= 3 ? 3 : nc2, oy_n = nc1 >= 3 ? 3 : nc1, ox_n = nc0 >= 3 ? 3 : nc0;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int n = 0;
-    for (int oz = 0; oz < oz_n; ++oz) {
-        int z = cz + (nc2 >= 3 ? oz - 1 : oz);
-        z = z < 0 ? z + nc2 : (z >= nc2 ? z - nc2 : z);
-        for (int oy = 0; oy < oy_n; ++oy) {
-            int y = cy + (nc1 >= 3 ? oy - 1 : oy);
-            y = y < 0 ? y + nc1 : (y >= nc1 ? y - nc1 : y);
-            for (int ox = 0; ox < ox_n; ++ox) {
-                int x = cx + (nc0 >= 3 ? ox - 1 : ox);
-                x = x < 0 ? x + nc0 : (x >= nc0 ? x - nc0 : x);
-                const int c = (z * nc1 + y) * nc0 + x;
-                const int p0 = cell_start[c], p1 = cell_start[c + 1];
-                for (int base = p0; base < p1; base += 64) {
-                    const int p = base + lane;
-                    bool ok = false;
-                    int w = 0;
-                    if (p < p1) {
-                        const int j = cell_atoms[p];
-                        if (j != i) {
-                            double r2 = 0.0;
-#pragma unroll
-                            for (int a = 0; a < 3; ++a) {
-                                double d = cen[3 * j + a] - ci[a];
-                                d -= g.L[a] * rint(d * g.invL[a]);
-                                r2 += d * d;
-                            }
-                            const int t = types[j];
-                            ok = r2 < R2 && t >= 0 && t < S;
-                            w = (j << 2) | t;
-                        }
-                    }
-                    const uint64_t mball = __ballot(ok);
-                    const int slot = n + __popcll(mball & below);
-                    if (ok && slot < capC) cand[(size_t)slot * N + i] = w;
-                    n += __popcll(mball);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        const int cx = c % nc0, cy = (c / nc0) % nc1, cz = c / (nc0 * nc1);
+        const int oz_n = nc2 >= 3 ? 3 : nc2, oy_n = nc1 >= 3 ? 3 : nc1, ox_n = nc0 >= 3 ? 3 : nc0;
+        int nr = 0, tot = 0;
+        for (int oz = 0; oz < oz_n; ++oz) {
+            int z = nc2 >= 3 ? cz + oz - 1 : oz;
+            z = z < 0 ? z + nc2 : (z >= nc2 ? z - nc2 : z);
+            for (int oy = 0; oy < oy_n; ++oy) {
+                int y = nc1 >= 3 ? cy + oy - 1 : oy;
+                y = y < 0 ? y + nc1 : (y >= nc1 ? y - nc1 : y);
+                for (int ox = 0; ox < ox_n; ++ox) {
+                    int x = nc0 >= 3 ? cx + ox - 1 : ox;
+                    x = x < 0 ? x + nc0 : (x >= nc0 ? x - nc0 : x);
+                    const int cc = (z * nc1 + y) * nc0 + x;
+                    rs[nr] = cell_start[cc];
+                    rp[nr] = tot;
+                    tot += cell_start[cc + 1] - cell_start[cc];
+                    ++nr;
                 }
             }
         }
+        rp[nr] = tot;
+        nrange = nr;
     }
-    if (lane == 0) {
-        candN[i] = n;
-        atomicMax(&status[3], (uint32_t)n);
-        if (n > capC) atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
+    __syncthreads();
+    const int nr = nrange, total = rp[nr];
+    const bool staged = total <= kStage;
+    // flat stencil position q -> index into cell_atoms
+    auto at = [&](int q) {
+        int r = 0;
+        while (r + 1 < nr && rp[r + 1] <= q) ++r;
+        return rs[r] + (q - rp[r]);
+    };
+    if (staged) {
+        for (int q = threadIdx.x; q < total; q += blockDim.x) {
+            const int j = cell_atoms[at(q)];
+            const int tj = types[j];
+            sx[q] = cen[3 * j];
+            sy[q] = cen[3 * j + 1];
+            sz[q] = cen[3 * j + 2];
+            sw[q] = (tj >= 0 && tj < S) ? ((j << 2) | tj) : -1;
+        }
+    }
+    __syncthreads();
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int a0 = cell_start[c], a1 = cell_start[c + 1];
+    for (int a = a0 + wv; a < a1; a += blockDim.x >> 6) {
+        const int i = cell_atoms[a];
+        const double ci[3] = {cen[3 * i], cen[3 * i + 1], cen[3 * i + 2]};
+        int32_t *row = cand + (size_t)i * capC;
+        int cnt = 0;
+        for (int q0 = 0; q0 < total; q0 += 64) {
+            const int q = q0 + lane;
+            bool ok = false;
+            int w = -1;
+            if (q < total) {
+                double p[3];
+                if (staged) {
+                    p[0] = sx[q]; p[1] = sy[q]; p[2] = sz[q];
+                    w = sw[q];
+                } else {
+                    const int j = cell_atoms[at(q)];
+                    const int tj = types[j];
+                    p[0] = cen[3 * j]; p[1] = cen[3 * j + 1]; p[2] = cen[3 * j + 2];
+                    w = (tj >= 0 && tj < S) ? ((j << 2) | tj) : -1;
+                }
+                if (w >= 0 && (w >> 2) != i) {
+                    double r2 = 0.0;
+#pragma unroll
+                    for (int e = 0; e < 3; ++e) {
+                        double d = p[e] - ci[e];
+                        d -= g.L[e] * rint(d * g.invL[e]);
+                        r2 += d * d;
+                    }
+                    ok = r2 < R2;
+                }
+            }
+            const uint64_t m = __ballot(ok);
+            const int pos = cnt + __popcll(m & below);
+            if (ok && pos < capC) row[pos] = w;
+            cnt += __popcll(m);
+        }
+        if (lane == 0) {
+            rowlen[i] = cnt;
+            atomicMax(&status[3], (uint32_t)cnt);
+            if (cnt > capC) atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
+        }
     }
 }
 
-// Per-bead exact filter of the shared candidates.  Candidates are taken in
-// batches so that several index and position loads are in flight at once.
+// Sort each candidate row by (species, index) and record the species block
+// starts.  One wavefront per atom: rank sort (each element's position is the
+// number of smaller keys), in LDS for rows up to kSortLds, otherwise through
+// the atom's reverse-slot row as scratch (it is rewritten afterwards).
+constexpr int kSortLds = 512;
+__global__ __launch_bounds__(256) void k_sort_rows(int N, int S, int capC, int32_t *__restrict__ cand,
+                                                   const int32_t *__restrict__ rowlen, int32_t *__restrict__ off,
+                                                   int32_t *__restrict__ scratch)
+{
+    __shared__ int32_t buf[kBlock / 64][kSortLds];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = blockIdx.x * (kBlock / 64) + wv;
+    if (i >= N) return;   // whole wavefront
+    const int n = min(rowlen[i], capC);
+    int32_t *row = cand + (size_t)i * capC;
+    const bool lds = n <= kSortLds;
+    int32_t *src = lds ? buf[wv] : scratch + (size_t)i * capC;
+    for (int e = lane; e < n; e += 64) src[e] = row[e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // key: species above index; entries are distinct
+    auto key = [](int32_t w) { return ((uint32_t)(w & 3) << 29) | (uint32_t)(w >> 2); };
+    int cntS[kMaxSpecies] = {0, 0, 0, 0};
+    for (int e = lane; e < n; e += 64) {
+        const int32_t w = src[e];
+        const uint32_t kw = key(w);
+        int r = 0;
+        for (int f = 0; f < n; ++f) r += key(src[f]) < kw;
+        row[r] = w;
+#pragma unroll
+        for (int t = 0; t < kMaxSpecies; ++t) cntS[t] += (w & 3) == t;
+    }
+#pragma unroll
+    for (int t = 0; t < kMaxSpecies; ++t)
+        for (int o = 32; o > 0; o >>= 1) cntS[t] += __shfl_xor(cntS[t], o);
+    if (lane == 0) {
+        int run = 0;
+        for (int t = 0; t < S; ++t) {
+            off[(size_t)i * (kMaxSpecies + 1) + t] = run;
+            run += cntS[t];
+        }
+        off[(size_t)i * (kMaxSpecies + 1) + S] = run;
+    }
+}
+
+// Reverse slots: for candidate j of i (slot k), the slot of i in j's row,
+// by binary search in the species block of i (ordered by index); -1 if i
+// is missing (only when j's row overflowed).  One wavefront per atom.
+__global__ __launch_bounds__(256) void k_reverse(int N, int capC, const int32_t *__restrict__ types,
+                                                 const int32_t *__restrict__ cand, const int32_t *__restrict__ off,
+                                                 int32_t *__restrict__ rev)
+{
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (i >= N) return;
+    const int ti = types[i] & 3;
+    const int S1 = kMaxSpecies + 1;
+    int n = 0;
+    for (int t = 0; t < kMaxSpecies; ++t) n = max(n, off[(size_t)i * S1 + t + 1]);
+    n = min(n, capC);
+    for (int k = lane; k < n; k += 64) {
+        const int j = cand[(size_t)i * capC + k] >> 2;
+        const int32_t *rj = cand + (size_t)j * capC;
+        int lo = min(off[(size_t)j * S1 + ti], capC), hi = min(off[(size_t)j * S1 + ti + 1], capC);
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if ((rj[mid] >> 2) < i) lo = mid + 1;
+            else hi = mid;
+        }
+        rev[(size_t)i * capC + k] = (lo < min(off[(size_t)j * S1 + ti + 1], capC) && (rj[lo] >> 2) == i) ? lo : -1;
+    }
+}
+
+// Per-bead exact lists.  One lane per (bead, atom); candidates are taken in
+// batches so that several position loads are in flight at once.
 constexpr int kFilterBatch = 8;
 __global__ __launch_bounds__(256) void k_filter(const double *__restrict__ pos, int N, int S, HostGrid g,
-                                                const int32_t *__restrict__ cand, const int32_t *__restrict__ candN,
-                                                int capC, double rcR2, double rcA2, int capR, int capA,
-                                                int32_t *__restrict__ cntR, int32_t *__restrict__ idxR,
-                                                int32_t *__restrict__ cntA, int32_t *__restrict__ idxA,
-                                                uint32_t *__restrict__ status)
+                                                const int32_t *__restrict__ cand, const int32_t *__restrict__ off,
+                                                const int32_t *__restrict__ rev, int capC, int capR, int capA,
+                                                double rcR2, double rcA2, int32_t *__restrict__ listR,
+                                                int32_t *__restrict__ endR, int32_t *__restrict__ listA,
+                                                int32_t *__restrict__ endA, int32_t *__restrict__ slotA,
+                                                uint64_t *__restrict__ maskA, uint32_t *__restrict__ status)
 {
     int b, tile;
     bead_tile(b, tile);
     const int i = tile * blockDim.x + threadIdx.x;
-    int nR[kMaxSpecies] = {0, 0, 0, 0};
-    int nA[kMaxSpecies] = {0, 0, 0, 0};
+    int sR = 0, sA = 0;
     if (i < N) {
         const double *pb = pos + (size_t)b * N * 3;
         const double ri[3] = {pb[3 * i], pb[3 * i + 1], pb[3 * i + 2]};
-        const int nc = min(candN[i], capC);
-        int32_t *oR = idxR + (size_t)b * S * capR * N + i;
-        int32_t *oA = idxA + (size_t)b * S * capA * N + i;
-        for (int k0 = 0; k0 < nc; k0 += kFilterBatch) {
-            int w[kFilterBatch];
-            double pj[kFilterBatch][3];
+        const int32_t *row = cand + (size_t)i * capC;
+        const int32_t *rrow = rev + (size_t)i * capC;
+        const int32_t *oi = off + (size_t)i * (kMaxSpecies + 1);
+        int32_t *lR = listR + (size_t)b * capR * N + i;
+        int32_t *lA = listA + (size_t)b * capA * N + i;
+        int32_t *sl = slotA + (size_t)b * capA * N + i;
+        uint64_t *mk = maskA + (size_t)b * ((capC + 31) >> 5) * N + i;
+        uint32_t word = 0;   // angular hits of the current 32-slot word
+        int wcur = 0;        // index of that word
+        int before = 0;      // angular hits in the words before it
+        for (int t = 0; t < S; ++t) {
+            const int k0 = min(oi[t], capC), k1 = min(oi[t + 1], capC);
+            for (int kb = k0; kb < k1; kb += kFilterBatch) {
+                int w[kFilterBatch];
+                double pj[kFilterBatch][3];
 #pragma unroll
-            for (int u = 0; u < kFilterBatch; ++u) w[u] = (k0 + u < nc) ? cand[(size_t)(k0 + u) * N + i] : -1;
+                for (int u = 0; u < kFilterBatch; ++u) {
+                    const int k = kb + u;
+                    w[u] = row[k < k1 ? k : k0];
+                    const int j = w[u] >> 2;
+                    pj[u][0] = pb[3 * j];
+                    pj[u][1] = pb[3 * j + 1];
+                    pj[u][2] = pb[3 * j + 2];
+                }
 #pragma unroll
-            for (int u = 0; u < kFilterBatch; ++u) {
-                const int j = w[u] >= 0 ? (w[u] >> 2) : i;
-                pj[u][0] = pb[3 * j];
-                pj[u][1] = pb[3 * j + 1];
-                pj[u][2] = pb[3 * j + 2];
-            }
-#pragma unroll
-            for (int u = 0; u < kFilterBatch; ++u) {
-                if (w[u] < 0) continue;
-                const int j = w[u] >> 2, t = w[u] & 3;
-                const double r2 = mic_r2_exact(ri, pj[u], g);
-                if (r2 < rcR2) {
-                    int kr = 0;
-#pragma unroll
-                    for (int s = 0; s < kMaxSpecies; ++s)
-                        if (s == t) kr = nR[s]++;
-                    if (kr < capR) oR[((size_t)t * capR + kr) * N] = j;
-                    if (r2 < rcA2) {
-                        int ka = 0;
-#pragma unroll
-                        for (int s = 0; s < kMaxSpecies; ++s)
-                            if (s == t) ka = nA[s]++;
-                        if (ka < capA) oA[((size_t)t * capA + ka) * N] = j;
+                for (int u = 0; u < kFilterBatch; ++u) {
+                    const int k = kb + u;
+                    if (k < k1) {
+                        const double r2 = mic_r2_exact(ri, pj[u], g);
+                        while ((k >> 5) > wcur) {   // close the finished words
+                            mk[(size_t)wcur * N] = (uint64_t)word | ((uint64_t)before << 32);
+                            before += __popc(word);
+                            word = 0;
+                            ++wcur;
+                        }
+                        if (r2 < rcR2) {
+                            if (sR < capR) lR[(size_t)sR * N] = w[u] >> 2;
+                            ++sR;
+                            if (r2 < rcA2) {
+                                word |= 1u << (k & 31);
+                                if (sA < capA) {
+                                    lA[(size_t)sA * N] = w[u] >> 2;
+                                    sl[(size_t)sA * N] = k | (int32_t)((uint32_t)(rrow[k] & 0xffff) << 16);
+                                }
+                                ++sA;
+                            }
+                        }
                     }
                 }
             }
+            endR[((size_t)b * kMaxSpecies + t) * N + i] = min(sR, capR);
+            endA[((size_t)b * kMaxSpecies + t) * N + i] = min(sA, capA);
         }
-#pragma unroll
-        for (int s = 0; s < kMaxSpecies; ++s) {
-            if (s < S) {
-                cntR[((size_t)b * S + s) * N + i] = nR[s];
-                cntA[((size_t)b * S + s) * N + i] = nA[s];
-            }
-        }
+        if (min(off[(size_t)i * (kMaxSpecies + 1) + S], capC) > 0)
+            mk[(size_t)wcur * N] = (uint64_t)word | ((uint64_t)before << 32);
     }
-    int mR = 0, mA = 0;
-#pragma unroll
-    for (int s = 0; s < kMaxSpecies; ++s) {
-        mR = max(mR, nR[s]);
-        mA = max(mA, nA[s]);
-    }
-    const int wR = wave_max_i(mR), wA = wave_max_i(mA);
+    const int wR = wave_max_i(sR), wA = wave_max_i(sA);
     if ((threadIdx.x & 63) == 0) {
         if (wR > 0) atomicMax(&status[1], (uint32_t)wR);
         if (wA > 0) atomicMax(&status[2], (uint32_t)wA);
@@ -386,15 +517,17 @@ extern "C" int32_t neighbor_build(const nep_model *m, nep_nlist *nl, const doubl
     if (!pos || !types) return fail(NEP_ERR_INVALID_ARG, "neighbor_build: null array");
     HostGrid g;
     if (!box_lengths(box, g.L)) return fail(NEP_ERR_UNSUPPORTED, "neighbor_build: only orthorhombic cells");
-    g.rc = m->hp.rc_radial > m->hp.rc_angular ? m->hp.rc_radial : m->hp.rc_angular;
+    g.rcR = m->hp.rc_radial;
+    g.rcA = m->hp.rc_angular;
+    const double rc = g.rcR > g.rcA ? g.rcR : g.rcA;
     int ncell_cap = 1;
     for (int a = 0; a < 3; ++a) {
         if (!(g.L[a] > 0.0) || !std::isfinite(g.L[a]))
             return fail(NEP_ERR_INVALID_ARG, "neighbor_build: bad box edge %g", g.L[a]);
-        if (g.L[a] < 2.0 * g.rc)
-            return fail(NEP_ERR_BOX_TOO_SMALL, "box edge %g is shorter than twice the cutoff %g", g.L[a], g.rc);
+        if (g.L[a] < 2.0 * rc)
+            return fail(NEP_ERR_BOX_TOO_SMALL, "box edge %g is shorter than twice the cutoff %g", g.L[a], rc);
         g.invL[a] = 1.0 / g.L[a];
-        int nc = (int)std::floor(g.L[a] / (g.rc * (1.0 + 1e-9)));
+        int nc = (int)std::floor(g.L[a] / (rc * (1.0 + 1e-9)));
         g.nc_cap[a] = nc < 1 ? 1 : (nc > 64 ? 64 : nc);
         ncell_cap *= g.nc_cap[a];
     }
@@ -410,9 +543,10 @@ extern "C" int32_t neighbor_build(const nep_model *m, nep_nlist *nl, const doubl
     }
     const double rcR2 = m->hp.rc_radial * m->hp.rc_radial;
     const double rcA2 = m->hp.rc_angular * m->hp.rc_angular;
-    fill_u32(nl->grid, 0u, 8, s);
+    fill_u32(nl->grid, 0u, 16, s);
     fill_i32(nl->cell_cnt, 0, (size_t)ncell_cap, s);
     const dim3 g1(div_up(N, kBlock));
+    const dim3 gw(div_up(N, kBlock / 64));
     {
         ProfScope ps_(K_CENTROID, s);
         hipLaunchKernelGGL(k_centroid, g1, dim3(kBlock), 0, s, pos, types, P, N, nl->S, nl->cen, nl->grid, nl->status);
@@ -440,15 +574,23 @@ extern "C" int32_t neighbor_build(const nep_model *m, nep_nlist *nl, const doubl
     }
     {
         ProfScope ps_(K_CANDIDATES, s);
-        hipLaunchKernelGGL(k_candidates, dim3(div_up(N, kBlock / 64)), dim3(kBlock), 0, s, nl->cen, types, N, nl->S,
-                           g, nl->grid,
-                           nl->cell_start, nl->cell_atoms, nl->capC, nl->cand, nl->candN, nl->status);
+        hipLaunchKernelGGL(k_candidates, dim3(ncell_cap), dim3(kBlock), 0, s, nl->cen, types, N, nl->S, g, nl->grid,
+                           nl->cell_start, nl->cell_atoms, nl->capC, nl->cand, nl->rowlen, nl->status);
+    }
+    {
+        ProfScope ps_(K_SORT_ROWS, s);
+        hipLaunchKernelGGL(k_sort_rows, gw, dim3(kBlock), 0, s, N, nl->S, nl->capC, nl->cand, nl->rowlen, nl->offC,
+                           nl->revC);
+    }
+    {
+        ProfScope ps_(K_REVERSE, s);
+        hipLaunchKernelGGL(k_reverse, gw, dim3(kBlock), 0, s, N, nl->capC, types, nl->cand, nl->offC, nl->revC);
     }
     {
         ProfScope ps_(K_NLIST, s);
         hipLaunchKernelGGL(k_filter, dim3(div_up(N, kBlock), P), dim3(kBlock), 0, s, pos, N, nl->S, g, nl->cand,
-                           nl->candN, nl->capC, rcR2, rcA2, nl->capR, nl->capA, nl->cntR, nl->idxR, nl->cntA,
-                           nl->idxA, nl->status);
+                           nl->offC, nl->revC, nl->capC, nl->capR, nl->capA, rcR2, rcA2, nl->listR, nl->endR,
+                           nl->listA, nl->endA, nl->slotA, nl->maskA, nl->status);
     }
     NEP_HIP(hipGetLastError());
     return NEP_OK;

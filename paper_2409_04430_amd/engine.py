@@ -19,7 +19,7 @@ from . import lib
 
 
 def default_capacity(rc: float, density: float, n_species: int, slack: float = 1.6) -> int:
-    """Capacity per species block from the mean density (overflow is detected)."""
+    """First guess of a candidate row length from the mean density (refitted after one build)."""
     n = density * 4.0 / 3.0 * math.pi * rc ** 3
     return int(math.ceil(n * slack)) + 8
 
@@ -28,8 +28,8 @@ class NepPimd:
     """NEP forces for P beads of one periodic system plus the ring-polymer integrator."""
 
     def __init__(self, model_path: str, system: I.System, *, dt: float, T: float, tau: float = 100.0,
-                 mode: str = "trpmd", seed: int = 0, cap_radial: Optional[int] = None,
-                 cap_angular: Optional[int] = None, check_every: int = 50, want_atom: bool = False):
+                 mode: str = "trpmd", seed: int = 0, caps: Optional[tuple] = None, check_every: int = 50,
+                 want_atom: bool = False):
         import torch
         self.torch = torch
         dev = torch.device("cuda")
@@ -47,9 +47,10 @@ class NepPimd:
         self.W_atom = torch.zeros((self.P, self.N, 9), dtype=torch.float32, device=dev) if want_atom else None
         dens = self.N / float(np.prod(self.box))
         S = self.model.n_species
-        self.cap_radial = cap_radial or default_capacity(self.model.rc_radial, dens, S)
-        self.cap_angular = cap_angular or default_capacity(self.model.rc_angular, dens, S)
-        self.nl = lib.NeighborList(self.model, self.P, self.N, self.cap_radial, self.cap_angular)
+        rcR, rcA = self.model.rc_radial, self.model.rc_angular
+        self.caps = tuple(caps) if caps else (default_capacity(rcR + 0.5, dens, S), default_capacity(rcR, dens, S),
+                                              default_capacity(rcA, dens, S))
+        self.nl = None
         self.ws = lib.Workspace(self.model, self.P, self.N)
         self.pimd = lib.Pimd(self.P, self.N, self.mass, dt, T, tau, mode, seed)
         self.check_every = check_every
@@ -59,24 +60,9 @@ class NepPimd:
 
     # ------------------------------------------------------------------
     def _fit_capacity(self):
-        """Build once, then shrink or grow the capacities to the observed need."""
-        S = self.model.n_species
-        for _ in range(4):
-            self.nl.build(self.pos, self.box, self.types)
-            st = self.nl.status(clear=True)
-            flags, mr, ma = st["flags"], st["max_radial"], st["max_angular"]
-            if flags & lib.FLAG_BAD_TYPE:
-                raise lib.NepError(1, "species index outside the model's range")
-            need_r = int(math.ceil(mr * 1.25)) + 8
-            need_a = int(math.ceil(ma * 1.25)) + 8
-            # the centroid candidate capacity is 2 S cap_radial + 32
-            need_r = max(need_r, int(math.ceil((1.3 * st["max_candidates"] - 32) / (2 * S))))
-            if flags & lib.FLAG_NEIGHBOR_OVERFLOW or need_r < self.cap_radial // 2 or need_a < self.cap_angular // 2:
-                self.cap_radial, self.cap_angular = max(need_r, 8), max(need_a, 8)
-                self.nl = lib.NeighborList(self.model, self.P, self.N, self.cap_radial, self.cap_angular)
-                continue
-            return
-        raise lib.NepError(5, "could not size the neighbour lists")
+        """Size the candidate rows to the starting configuration (slack for the run)."""
+        self.nl = lib.fitted_neighbor_list(self.model, self.pos, self.box, self.types, *self.caps)
+        self.caps = self.nl.caps
 
     def forces(self):
         """Neighbour lists + NEP energy, forces and virial at the current positions."""
@@ -85,9 +71,10 @@ class NepPimd:
 
     def check(self):
         """Poll the sticky flags (synchronises); raise on overflow or non-finite values."""
-        flags, mr, ma = self.nl.poll(clear=True)
+        st = self.nl.status(clear=True)
+        flags, mr, ma = st["flags"], st["max_radial"], st["max_angular"]
         if flags & lib.FLAG_NEIGHBOR_OVERFLOW:
-            raise lib.NepError(5, f"neighbour overflow: need {mr}/{ma}, capacity {self.cap_radial}/{self.cap_angular}")
+            raise lib.NepError(5, f"list overflow: need {st['max_candidates']}/{mr}/{ma}, capacities {self.caps}")
         wf = self.ws.poll(clear=True)
         if (flags | wf) & lib.FLAG_NONFINITE:
             raise lib.NepError(6, "non-finite force or position")

@@ -43,14 +43,16 @@ class HParams(C.Structure):
 
 
 class NlistLayout(C.Structure):
-    _fields_ = [("P", C.c_int32), ("N", C.c_int32), ("n_species", C.c_int32), ("cap_radial", C.c_int32),
-                ("cap_angular", C.c_int32), ("cnt_radial", C.c_void_p), ("idx_radial", C.c_void_p),
-                ("cnt_angular", C.c_void_p), ("idx_angular", C.c_void_p)]
+    _fields_ = [("P", C.c_int32), ("N", C.c_int32), ("n_species", C.c_int32), ("cap_candidates", C.c_int32),
+                ("cap_radial", C.c_int32), ("cap_angular", C.c_int32), ("cand", C.c_void_p),
+                ("cand_off", C.c_void_p), ("cand_rev", C.c_void_p), ("nbr_radial", C.c_void_p),
+                ("end_radial", C.c_void_p), ("nbr_angular", C.c_void_p), ("end_angular", C.c_void_p),
+                ("slot_angular", C.c_void_p)]
 
 
 class NlistStatus(C.Structure):
     _fields_ = [("flags", C.c_uint32), ("max_radial", C.c_int32), ("max_angular", C.c_int32),
-                ("max_candidates", C.c_int32), ("capacity_candidates", C.c_int32), ("bead_spread", C.c_float)]
+                ("max_candidates", C.c_int32), ("bead_spread", C.c_float)]
 
 
 class PimdParams(C.Structure):
@@ -65,7 +67,7 @@ _sig = {
     "nep_load_params": (_i32, [C.c_char_p, C.POINTER(_vp)]),
     "nep_model_info": (_i32, [_vp, C.POINTER(HParams)]),
     "nep_model_destroy": (None, [_vp]),
-    "nep_nlist_create": (_i32, [_vp, _i32, _i32, _i32, _i32, C.POINTER(_vp)]),
+    "nep_nlist_create": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, C.POINTER(_vp)]),
     "nep_nlist_destroy": (None, [_vp]),
     "neighbor_build": (_i32, [_vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, _vp]),
     "nep_nlist_view": (_i32, [_vp, C.POINTER(NlistLayout)]),
@@ -160,11 +162,12 @@ class Model:
 class NeighborList:
     """nep_nlist_create / neighbor_build / nep_nlist_view / nep_nlist_poll."""
 
-    def __init__(self, model: Model, P: int, N: int, cap_radial: int, cap_angular: int):
+    def __init__(self, model: Model, P: int, N: int, cap_candidates: int, cap_radial: int, cap_angular: int):
         self._h = _vp()
-        _check(_lib.nep_nlist_create(model.handle, P, N, cap_radial, cap_angular, C.byref(self._h)))
+        _check(_lib.nep_nlist_create(model.handle, P, N, cap_candidates, cap_radial, cap_angular,
+                                     C.byref(self._h)))
         self.model, self.P, self.N = model, P, N
-        self.cap_radial, self.cap_angular = cap_radial, cap_angular
+        self.caps = (cap_candidates, cap_radial, cap_angular)
 
     def build(self, pos, box, types):
         _check(_lib.neighbor_build(self.model.handle, self._h, _ptr(pos, _torch().float64, (self.P, self.N, 3), "pos"),
@@ -185,20 +188,38 @@ class NeighborList:
         return st["flags"], st["max_radial"], st["max_angular"]
 
     def view(self):
-        """Raw layout: device pointers of cnt [P,S,N] and idx [P,S,cap,N] (radial, angular)."""
+        """Raw layout: device pointers of the candidate rows and the per-bead lists."""
         lay = NlistLayout()
         _check(_lib.nep_nlist_view(self._h, C.byref(lay)))
         return lay
 
     def to_host(self):
-        """Copy the lists to host numpy arrays (synchronise the stream first)."""
+        """Copy the lists to host numpy arrays (synchronises the device first).
+
+        cand [N, capC] (entries (j << 2) | species), cand_off [N, 5],
+        cand_rev [N, capC]; per kind in (radial, angular): nbr_<kind>
+        [P, cap, N], end_<kind> [P, 4, N], cnt_<kind> [P, N]; slot_angular
+        [P, capA, N].  Entries past a row's or list's count are undefined.
+        """
         _torch().cuda.synchronize()
         lay = self.view()
-        S = lay.n_species
-        return dict(cnt_radial=device_to_host(lay.cnt_radial, (lay.P, S, lay.N), np.int32),
-                    idx_radial=device_to_host(lay.idx_radial, (lay.P, S, lay.cap_radial, lay.N), np.int32),
-                    cnt_angular=device_to_host(lay.cnt_angular, (lay.P, S, lay.N), np.int32),
-                    idx_angular=device_to_host(lay.idx_angular, (lay.P, S, lay.cap_angular, lay.N), np.int32))
+        P, N, C_ = lay.P, lay.N, lay.cap_candidates
+        out = {"n_species": lay.n_species,
+               "cand": device_to_host(lay.cand, (N, C_), np.int32),
+               "cand_off": device_to_host(lay.cand_off, (N, 5), np.int32),
+               "cand_rev": device_to_host(lay.cand_rev, (N, C_), np.int32)}
+        for kind, cap, nbr, end in (("radial", lay.cap_radial, lay.nbr_radial, lay.end_radial),
+                                    ("angular", lay.cap_angular, lay.nbr_angular, lay.end_angular)):
+            out["nbr_" + kind] = device_to_host(nbr, (P, cap, N), np.int32)
+            out["end_" + kind] = device_to_host(end, (P, 4, N), np.int32)
+            out["cnt_" + kind] = out["end_" + kind][:, max(lay.n_species - 1, 0), :].copy()
+        out["slot_angular"] = device_to_host(lay.slot_angular, (P, lay.cap_angular, N), np.int32)
+        return out
+
+    @staticmethod
+    def neighbors(lists, kind: str, b: int, i: int) -> np.ndarray:
+        """Neighbour indices of atom i in bead b, in list order, from to_host() arrays."""
+        return lists["nbr_" + kind][b, :lists["cnt_" + kind][b, i], i]
 
     @property
     def handle(self):
@@ -209,6 +230,32 @@ class NeighborList:
         if h:
             _lib.nep_nlist_destroy(h)
             self._h = None
+
+
+def fitted_neighbor_list(model: "Model", pos, box, types, cap_candidates: int = 96, cap_radial: int = 80,
+                         cap_angular: int = 32, slack: float = 1.25, tries: int = 4) -> NeighborList:
+    """A NeighborList whose capacities fit the given positions.
+
+    Builds once, reads the longest candidate row and lists from the sticky
+    status and re-creates the list with `slack` x those lengths + 8 when it
+    overflowed or is more than twice too large.  Synchronises the stream.
+    """
+    P, N = int(pos.shape[0]), int(pos.shape[1])
+    caps = [int(cap_candidates), int(cap_radial), int(cap_angular)]
+    for _ in range(tries):
+        caps[1] = min(caps[1], caps[0])
+        caps[2] = min(caps[2], caps[1])
+        nl = NeighborList(model, P, N, *caps)
+        nl.build(pos, box, types)
+        st = nl.status(clear=True)
+        if st["flags"] & FLAG_BAD_TYPE:
+            raise NepError(1, "species index outside the model's range")
+        need = [int(np.ceil(v * slack)) + 8 for v in (st["max_candidates"], st["max_radial"], st["max_angular"])]
+        if not (st["flags"] & FLAG_NEIGHBOR_OVERFLOW) and all(2 * n >= c for n, c in zip(need, caps)):
+            return nl
+        caps = [max(n, 8) for n in need]
+        del nl
+    raise NepError(5, "could not size the neighbour lists")
 
 
 class Workspace:

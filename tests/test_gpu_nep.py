@@ -57,11 +57,11 @@ def oracle_caps(orc, pos, box, rc_r, rc_a):
 def gpu_nep(torch, L, path, pos, types, box, capR, capA, atom=True):
     P, N = pos.shape[:2]
     m = L.Model(path)
-    nl = L.NeighborList(m, P, N, capR, capA)
-    ws = L.Workspace(m, P, N)
     dev = torch.device("cuda")
     tpos = torch.tensor(pos, dtype=torch.float64, device=dev)
     ttyp = torch.tensor(types, dtype=torch.int32, device=dev)
+    nl = L.fitted_neighbor_list(m, tpos, box, ttyp, int(capR * 1.3) + 8, capR, capA)
+    ws = L.Workspace(m, P, N)
     E = torch.zeros(P, dtype=torch.float64, device=dev)
     F = torch.zeros((P, N, 3), dtype=torch.float32, device=dev)
     W = torch.zeros((P, 9), dtype=torch.float64, device=dev)
@@ -81,19 +81,49 @@ def gpu_nep(torch, L, path, pos, types, box, capR, capA, atom=True):
     return out
 
 
-def check_lists(orc, lists, pos, box, rc_r, rc_a, beads=None, atoms=None):
+def check_lists(orc, lists, pos, box, rc_r, rc_a, beads=None, atoms=None, types=None):
+    """Per-bead neighbour lists equal the oracle's sets, in (species, index)
+    order; candidate rows and reverse slots are consistent."""
     P, N = pos.shape[:2]
     beads = range(P) if beads is None else beads
+    sel = range(N) if atoms is None else atoms
+    S = lists["n_species"]
+    cand, coff, crev = lists["cand"], lists["cand_off"][:, :S + 1], lists["cand_rev"]
+    for i in sel:
+        n = coff[i, S]
+        row = cand[i, :n]
+        assert coff[i, 0] == 0 and np.all(np.diff(coff[i]) >= 0), i
+        key = (row & 3).astype(np.int64) * (1 << 30) + (row >> 2)
+        assert np.all(np.diff(key) > 0) and not np.any((row >> 2) == i), i
+        blocks = np.searchsorted(coff[i, 1:], np.arange(n), side="right")
+        np.testing.assert_array_equal(row & 3, blocks, err_msg=f"candidate blocks {i}")
+        if types is not None:
+            np.testing.assert_array_equal(row & 3, np.asarray(types)[row >> 2], err_msg=f"species tags {i}")
+        j = row >> 2
+        np.testing.assert_array_equal(cand[j, crev[i, :n]] >> 2, np.full(n, i), err_msg=f"reverse slots {i}")
     for kind, rc in (("radial", rc_r), ("angular", rc_a)):
-        cnt, idx = lists["cnt_" + kind], lists["idx_" + kind]
-        S, cap = idx.shape[1], idx.shape[2]
+        nbr, cnt, end = lists["nbr_" + kind], lists["cnt_" + kind], lists["end_" + kind]
         for b in beads:
             oc, oi = orc.neighbors(pos[b], box, rc, cap=1024)
-            sel = range(N) if atoms is None else atoms
             for i in sel:
-                got = np.sort(np.concatenate([idx[b, t, :cnt[b, t, i], i] for t in range(S)]))
-                assert cnt[b, :, i].sum() == oc[i], (kind, b, i)
-                np.testing.assert_array_equal(got, oi[i, :oc[i]], err_msg=f"{kind} bead {b} atom {i}")
+                got = nbr[b, :cnt[b, i], i]
+                assert cnt[b, i] == oc[i], (kind, b, i)
+                if types is not None:
+                    # species blocks in order, ascending index inside each block
+                    tj = np.asarray(types)[got]
+                    np.testing.assert_array_equal(np.sort(tj, kind="stable"), tj)
+                    for t in range(S):
+                        assert end[b, t, i] == np.count_nonzero(tj <= t), (kind, b, i, t)
+                np.testing.assert_array_equal(np.sort(got), oi[i, :oc[i]], err_msg=f"{kind} bead {b} atom {i}")
+        if kind == "angular":
+            # every angular entry carries its candidate slot and reverse slot
+            sl = lists["slot_angular"]
+            for b in beads:
+                for i in sel:
+                    c = cnt[b, i]
+                    k, r = sl[b, :c, i] & 0xFFFF, (sl[b, :c, i] >> 16) & 0xFFFF
+                    np.testing.assert_array_equal(cand[i, k] >> 2, nbr[b, :c, i])
+                    np.testing.assert_array_equal(r, crev[i, k])
 
 
 def check_nep(ref, got, beads, N, atom=True):
@@ -129,7 +159,7 @@ def test_nep_parity_workload(torch, L, orc, tmpdir_session, name, P):
     h = w.hyper
     capR, capA = oracle_caps(orc, pos, box, h.rc_radial, h.rc_angular)
     got = gpu_nep(torch, L, path, pos, types, box, capR, capA)
-    check_lists(orc, got["lists"], pos, box, h.rc_radial, h.rc_angular)
+    check_lists(orc, got["lists"], pos, box, h.rc_radial, h.rc_angular, types=types)
     ref = oracle_beads(orc, path, pos, types, box, range(P))
     check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"], U=ref["U"], Wat=ref["Wat"]), got, range(P), pos.shape[1])
 
@@ -156,7 +186,7 @@ def test_nep_parity_water_boxes(torch, L, orc, tmpdir_session):
         pos, types, box = beads_of("water16", 2, extra_sigma=0.02, seed=bi, box_index=bi)
         capR, capA = oracle_caps(orc, pos, box, 6.0, 4.0)
         got = gpu_nep(torch, L, path, pos, types, box, capR, capA)
-        check_lists(orc, got["lists"], pos, box, 6.0, 4.0)
+        check_lists(orc, got["lists"], pos, box, 6.0, 4.0, types=types)
         ref = oracle_beads(orc, path, pos, types, box, range(2))
         check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"], U=ref["U"], Wat=ref["Wat"]), got, range(2),
                   pos.shape[1])
@@ -169,7 +199,8 @@ def test_nep_parity_porous_one_bead(torch, L, orc, tmpdir_session):
     pos, types, box = beads_of("porous13824", 1, extra_sigma=0.05, seed=3)
     got = gpu_nep(torch, L, path, pos, types, box, 96, 48)
     rng = np.random.default_rng(0)
-    check_lists(orc, got["lists"], pos, box, 6.0, 4.0, atoms=rng.choice(pos.shape[1], 500, replace=False))
+    check_lists(orc, got["lists"], pos, box, 6.0, 4.0, atoms=rng.choice(pos.shape[1], 500, replace=False),
+                types=types)
     ref = oracle_beads(orc, path, pos, types, box, [0])
     check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"], U=ref["U"], Wat=ref["Wat"]), got, [0], pos.shape[1])
 
@@ -182,7 +213,7 @@ def test_nep_full_size_rocksalt_sampled_beads(torch, L, orc, tmpdir_session):
     path = write_model(tmpdir_session, "rs_full", w.model())
     pos, types, box = beads_of("rocksalt4096", 32, extra_sigma=0.04, seed=11)
     got = gpu_nep(torch, L, path, pos, types, box, 80, 32, atom=False)
-    check_lists(orc, got["lists"], pos, box, 6.0, 4.0, beads=[0, 31])
+    check_lists(orc, got["lists"], pos, box, 6.0, 4.0, beads=[0, 31], types=types)
     ref = oracle_beads(orc, path, pos, types, box, [0, 31])
     check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"]), got, [0, 31], pos.shape[1], atom=False)
     # the beads the oracle did not check still obey sum F = 0 and a symmetric virial
@@ -199,7 +230,8 @@ def test_nep_fcc32000_teacher_one_bead(torch, L, orc, tmpdir_session):
     pos, types, box = beads_of("fcc32000", 1, extra_sigma=0.02, seed=5)
     got = gpu_nep(torch, L, path, pos, types, box, 96, 72, atom=False)
     rng = np.random.default_rng(1)
-    check_lists(orc, got["lists"], pos, box, 6.0, 5.0, atoms=rng.choice(pos.shape[1], 300, replace=False))
+    check_lists(orc, got["lists"], pos, box, 6.0, 5.0, atoms=rng.choice(pos.shape[1], 300, replace=False),
+                types=types)
     ref = oracle_beads(orc, path, pos, types, box, [0])
     check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"]), got, [0], pos.shape[1], atom=False)
 
@@ -213,8 +245,20 @@ def test_nep_deterministic(torch, L, tmpdir_session):
     b = gpu_nep(torch, L, path, pos, types, box, 80, 32)
     for k in ("E", "F", "W", "U", "Wat"):
         np.testing.assert_array_equal(a[k], b[k])
-    for k in a["lists"]:
-        np.testing.assert_array_equal(a["lists"][k], b["lists"][k])
+    la, lb = a["lists"], b["lists"]
+    S = la["n_species"]
+    for k in ("cnt_radial", "cnt_angular", "end_radial", "end_angular", "cand_off"):
+        np.testing.assert_array_equal(la[k][..., :S + 1, :] if k.startswith("end") else la[k],
+                                      lb[k][..., :S + 1, :] if k.startswith("end") else lb[k])
+    n = la["cand_off"][:, S]
+    valid = np.arange(la["cand"].shape[1])[None, :] < n[:, None]
+    for k in ("cand", "cand_rev"):
+        np.testing.assert_array_equal(la[k][valid], lb[k][valid])
+    for kind, keys in (("radial", ("nbr_radial",)), ("angular", ("nbr_angular", "slot_angular"))):
+        cnt = la["cnt_" + kind]
+        valid = np.arange(la["nbr_" + kind].shape[1])[None, :, None] < cnt[:, None, :]
+        for k in keys:
+            np.testing.assert_array_equal(la[k][valid], lb[k][valid])
 
 
 def test_nep_edge_cases(torch, L, tmpdir_session):
@@ -225,7 +269,7 @@ def test_nep_edge_cases(torch, L, tmpdir_session):
     dev = torch.device("cuda")
     # empty: N = 0 and P = 0
     for P, N in ((2, 0), (0, 5)):
-        nl = L.NeighborList(m, P, N, 8, 8)
+        nl = L.NeighborList(m, P, N, 8, 8, 8)
         ws = L.Workspace(m, P, N)
         pos = torch.zeros((P, N, 3), dtype=torch.float64, device=dev)
         typ = torch.zeros(N, dtype=torch.int32, device=dev)
@@ -241,7 +285,7 @@ def test_nep_edge_cases(torch, L, tmpdir_session):
     tpos = torch.tensor(pos, dtype=torch.float64, device=dev)
     ttyp = torch.tensor(types, dtype=torch.int32, device=dev)
     # box shorter than twice the cutoff
-    nl = L.NeighborList(m, 2, 108, 64, 32)
+    nl = L.NeighborList(m, 2, 108, 96, 80, 32)
     with pytest.raises(L.NepError) as e:
         nl.build(tpos, [9.0, 12.15, 12.15], ttyp)
     assert e.value.code == 4
@@ -249,12 +293,19 @@ def test_nep_edge_cases(torch, L, tmpdir_session):
         nl.build(tpos, np.array([[12.15, 0.1, 0], [0, 12.15, 0], [0, 0, 12.15]]), ttyp)
     assert e.value.code == 3
     # capacity overflow is flagged and the lists stay within bounds
-    small = L.NeighborList(m, 2, 108, 10, 4)
-    small.build(tpos, box, ttyp)
-    flags, mr, ma = small.poll()
-    assert flags & L.FLAG_NEIGHBOR_OVERFLOW and mr > 10 and ma > 4
-    lst = small.to_host()
-    assert lst["idx_radial"].shape[2] == 10
+    for caps in ((10, 10, 4), (96, 10, 4), (96, 80, 4)):
+        small = L.NeighborList(m, 2, 108, *caps)
+        small.build(tpos, box, ttyp)
+        st = small.status()
+        need = (st["max_candidates"], st["max_radial"], st["max_angular"])
+        assert st["flags"] & L.FLAG_NEIGHBOR_OVERFLOW and any(n > c for n, c in zip(need, caps)), (caps, need)
+        lst = small.to_host()
+        assert lst["cand"].shape[1] == caps[0] and lst["cnt_radial"].max() <= caps[1]
+        assert lst["cnt_angular"].max() <= caps[2]
+    # capacities out of order are rejected
+    with pytest.raises(L.NepError) as e:
+        L.NeighborList(m, 2, 108, 40, 80, 32)
+    assert e.value.code == 1
     # a NaN position is flagged, a bad species index is flagged
     bad = tpos.clone()
     bad[1, 5, 0] = float("nan")
@@ -269,7 +320,7 @@ def test_nep_edge_cases(torch, L, tmpdir_session):
     # mismatched sizes are rejected on the host
     ws = L.Workspace(m, 2, 108)
     with pytest.raises(L.NepError) as e:
-        ws.compute(L.NeighborList(m, 2, 100, 8, 8), tpos, box, ttyp, torch.zeros(2, dtype=torch.float64, device=dev),
+        ws.compute(L.NeighborList(m, 2, 100, 8, 8, 8), tpos, box, ttyp, torch.zeros(2, dtype=torch.float64, device=dev),
                    torch.zeros((2, 108, 3), dtype=torch.float32, device=dev),
                    torch.zeros((2, 9), dtype=torch.float64, device=dev))
     assert e.value.code == 1
