@@ -145,6 +145,20 @@ void nep_nlist_destroy(nep_nlist *nl);
 int32_t neighbor_build(const nep_model *model, nep_nlist *nl, const double *pos, const double box[9],
                        const int32_t *types, int32_t P, int32_t N, hipStream_t stream);
 
+/* Reuse of the candidate rows (a Verlet skin on the centroid search): with
+ * skin > 0 the rows are built with radius rc_radial + 2 D + skin and kept
+ * while 2 (D - D_build) + 2 max_i |c_i - c_i,build| <= skin, which keeps
+ * them a superset of every bead pair within the cutoffs (triangle
+ * inequality); the decision is taken on the device, without a host round
+ * trip, and the per-bead lists stay exact.  A changed box rebuilds.  The
+ * species of the atoms must not change between calls on one handle unless
+ * nep_nlist_invalidate is called.  skin = 0 (the default) rebuilds on every
+ * call.  Errors: NEP_ERR_INVALID_ARG (skin outside [0, 10] A). */
+int32_t nep_nlist_set_skin(nep_nlist *nl, double skin);
+
+/* Force a candidate-row rebuild on the next neighbor_build. */
+int32_t nep_nlist_invalidate(nep_nlist *nl);
+
 /* Device layout of the neighbour sets (pointers stay owned by the handle).
  * Per atom i, shared by all beads:
  *   cand [N][cap_candidates] int32: candidates, entry (j << 2) | species(j),
@@ -182,6 +196,7 @@ typedef struct nep_nlist_status {
     int32_t max_angular;       /* largest angular neighbour count */
     int32_t max_candidates;    /* longest candidate row */
     float bead_spread;         /* largest distance of a bead from its centroid, A */
+    int32_t rebuilds;          /* candidate-row rebuilds since the last clear */
 } nep_nlist_status;
 
 /* Synchronise `stream`, read the sticky status of the lists into *out and,
@@ -276,6 +291,11 @@ int32_t trpmd_step(const pimd_ctx *ctx, double *pos, double *vel, const float *F
  * on, every kernel the library launches is bracketed by two hipEvents
  * recorded on the caller's stream; events come from a library-owned pool. */
 int32_t nep_profile_enable(int32_t on);
+
+/* Restrict timing to the kernel kind `id` (-1: every kind, the default), so
+ * that a timed region carries two events per launch of one kernel only.
+ * Errors: NEP_ERR_INVALID_ARG for an unknown id. */
+int32_t nep_profile_select(int32_t id);
 
 /* Number of kernel kinds and the name of kind `id` ("descriptor", "force",
  * "nlist", "trpmd", ...); "" for an unknown id. */

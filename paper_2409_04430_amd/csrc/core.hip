@@ -34,12 +34,63 @@ bool box_lengths(const double box[9], double L[3])
     return true;
 }
 
+FineGrid fine_grid(const double L[3], double rc)
+{
+    FineGrid g{};
+    g.exact = 1;
+    for (int d = 0; d < 3; ++d) {
+        const double room = 0.5 * (0.5 * L[d] - rc);
+        const double hmax = std::min(1.0, room);
+        int M = 1023;
+        if (hmax > L[d] / 1023.0) M = (int)std::ceil(L[d] / hmax);
+        else g.exact = 0;
+        M = std::max(1, std::min(M, 1023));
+        g.M[d] = M;
+        g.h[d] = (float)(L[d] / M);
+        g.Minv[d] = M / L[d];
+        g.hd[d] = L[d] / M;
+    }
+    return g;
+}
+
+// Per axis: fine cell c = floor(x / h) mod M and offset x - floor(x / h) h
+// (unwrapped coordinates allowed); non-finite input gives a NaN offset.
+__global__ void k_pack(const double *__restrict__ pos, size_t n, FineGrid g, float4 *__restrict__ out)
+{
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float o[3];
+    int bits = 0;
+    bool fin = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double x = pos[3 * e + d];
+        fin = fin && isfinite(x);
+        double fl = floor(x * g.Minv[d]);
+        if (!isfinite(fl)) fl = 0.0;
+        o[d] = (float)(x - fl * g.hd[d]);
+        int ci = (int)(fl - (double)g.M[d] * floor(fl / (double)g.M[d]));
+        ci = ci < 0 ? 0 : (ci >= g.M[d] ? g.M[d] - 1 : ci);
+        bits |= ci << (10 * d);
+    }
+    if (!fin) o[0] = __int_as_float(0x7fc00000);
+    out[e] = make_float4(o[0], o[1], o[2], __int_as_float(bits));
+}
+
+void pack_positions(const double *pos, size_t n, const FineGrid &g, float4 *out, hipStream_t s)
+{
+    if (n == 0) return;
+    ProfScope ps_(K_PACK, s);
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pos, n, g, out);
+}
+
 // ---------------------------------------------------------- profiling ---
 
-static const char *kKernelNames[K_NUM] = {"fill", "centroid", "grid", "cell_count", "cell_scan", "cell_fill",
+static const char *kKernelNames[K_NUM] = {"fill", "pack", "centroid", "grid", "cell_count", "cell_scan", "cell_fill",
                                           "cell_sort", "candidates", "sort_rows", "reverse", "nlist",
-                                          "pack", "descriptor", "force_ang", "force", "reduce", "trpmd", "modes"};
+                                          "descriptor", "force_ang", "force", "reduce", "trpmd", "modes"};
 static std::atomic<int> g_prof_on{0};
+static std::atomic<int> g_prof_only{-1};   // -1: every kind
 static std::mutex g_prof_mu;
 struct ProfRecord {
     int id;
@@ -64,6 +115,8 @@ static hipEvent_t prof_event()
 ProfScope::ProfScope(int kid, hipStream_t stream) : id(kid), s(stream)
 {
     if (!g_prof_on.load(std::memory_order_relaxed)) return;
+    const int only = g_prof_only.load(std::memory_order_relaxed);
+    if (only >= 0 && only != kid) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
     e0 = prof_event();
     if (e0 && hipEventRecord(e0, s) != hipSuccess) {
@@ -195,6 +248,13 @@ extern "C" const char *nep_last_error(void) { return g_err.c_str(); }
 extern "C" int32_t nep_profile_enable(int32_t on)
 {
     g_prof_on.store(on ? 1 : 0);
+    return NEP_OK;
+}
+
+extern "C" int32_t nep_profile_select(int32_t id)
+{
+    if (id < -1 || id >= K_NUM) return fail(NEP_ERR_INVALID_ARG, "nep_profile_select: unknown kernel kind %d", id);
+    g_prof_only.store(id);
     return NEP_OK;
 }
 
@@ -348,6 +408,7 @@ extern "C" int32_t nep_nlist_create(const nep_model *m, int32_t P, int32_t N, in
     const size_t Nn = (size_t)N, PN = (size_t)P * N;
     hipError_t e = hipGetDevice(&nl->device);
     if (e == hipSuccess) e = dalloc(&nl->cen, Nn * 3);
+    if (e == hipSuccess) e = dalloc(&nl->cen_ref, Nn * 3);
     if (e == hipSuccess) e = dalloc(&nl->cand, Nn * capC);
     if (e == hipSuccess) e = dalloc(&nl->rowlen, Nn);
     if (e == hipSuccess) e = dalloc(&nl->offC, Nn * (kMaxSpecies + 1));
@@ -360,6 +421,7 @@ extern "C" int32_t nep_nlist_create(const nep_model *m, int32_t P, int32_t N, in
     nl->WC = div_up(capC, 32);
     if (e == hipSuccess) e = dalloc(&nl->maskA, PN * nl->WC);
     if (e == hipSuccess) e = dalloc(&nl->pairbuf, 4 * PN * capA);
+    if (e == hipSuccess) e = dalloc(&nl->pos4, 4 * PN);
     if (e == hipSuccess) e = dalloc(&nl->cell_atoms, Nn);
     if (e == hipSuccess) e = dalloc(&nl->grid, 16);
     if (e == hipSuccess) e = dalloc(&nl->status, 8);
@@ -381,9 +443,9 @@ extern "C" int32_t nep_nlist_create(const nep_model *m, int32_t P, int32_t N, in
 extern "C" void nep_nlist_destroy(nep_nlist *nl)
 {
     if (!nl) return;
-    for (void *p : {(void *)nl->cen, (void *)nl->cand, (void *)nl->rowlen, (void *)nl->offC, (void *)nl->revC,
+    for (void *p : {(void *)nl->cen, (void *)nl->cen_ref, (void *)nl->cand, (void *)nl->rowlen, (void *)nl->offC, (void *)nl->revC,
                     (void *)nl->listR, (void *)nl->endR, (void *)nl->listA, (void *)nl->endA, (void *)nl->slotA,
-                    (void *)nl->maskA, (void *)nl->pairbuf, (void *)nl->cell_cnt, (void *)nl->cell_start, (void *)nl->cell_atoms,
+                    (void *)nl->maskA, (void *)nl->pairbuf, (void *)nl->pos4, (void *)nl->cell_cnt, (void *)nl->cell_start, (void *)nl->cell_atoms,
                     (void *)nl->grid, (void *)nl->status})
         if (p) (void)hipFree(p);
     delete nl;
@@ -413,6 +475,7 @@ extern "C" int32_t nep_nlist_poll(nep_nlist *nl, nep_nlist_status *out, int32_t 
     float spread;
     std::memcpy(&spread, &h[4], sizeof spread);
     out->bead_spread = spread;
+    out->rebuilds = (int32_t)h[5];
     if (clear) {
         fill_u32(nl->status, 0u, 8, s);
         NEP_HIP(hipGetLastError());

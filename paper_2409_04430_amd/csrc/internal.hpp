@@ -48,8 +48,13 @@ struct nep_nlist {
     int capC = 0;                 // candidate row capacity per atom
     int capR = 0, capA = 0;       // per-bead neighbour capacities per atom (radial, angular)
     int device = 0;
-    // Per call, shared by all beads: ring-polymer centroids and candidate rows.
-    double *cen = nullptr;        // [N][3]
+    // Candidate rows are reused across calls while the skin covers the motion.
+    double skin = 0.0;            // extra candidate radius, A (0: rebuild every call)
+    int built = 0;                // candidate rows valid for box_built
+    double box_built[3] = {0.0, 0.0, 0.0};
+    // Shared by all beads: ring-polymer centroids and candidate rows.
+    double *cen = nullptr;        // [N][3] centroids of this call
+    double *cen_ref = nullptr;    // [N][3] centroids at the last rebuild
     int32_t *cand = nullptr;      // [N][capC], entries (j << 2) | species(j), sorted by (species, j)
     int32_t *rowlen = nullptr;    // [N] candidates found (may exceed capC: overflow)
     int32_t *offC = nullptr;      // [N][5], species block starts, [S] = row length
@@ -65,12 +70,13 @@ struct nep_nlist {
     // Angular pair terms dU_j/dr_ji stored at the receiving atom i's list
     // position s of j: [P][capA][N] xyz + pad.
     float *pairbuf = nullptr;
+    float *pos4 = nullptr;        // [P][N][4] packed positions of the last build
     // Centroid cell list (grown on demand): cell_cnt [ncell], cell_start [ncell+1], cell_atoms [N].
     int ncell_alloc = 0;
     int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_atoms = nullptr;
     uint32_t *grid = nullptr;     // device-chosen grid record
     uint32_t *status = nullptr;   // [0] flags, [1] max radial neighbours, [2] max angular neighbours,
-                                  // [3] max candidates, [4] spread (float bits)
+                                  // [3] max candidates, [4] spread (float bits), [5] rebuilds
 };
 
 struct nep_ws {
@@ -120,11 +126,44 @@ __device__ __forceinline__ void bead_tile(int &bead, int &tile)
 // Orthorhombic edge lengths from a row-vector cell; false if not orthorhombic.
 bool box_lengths(const double box[9], double L[3]);
 
+// Packed positions: per axis a fine grid of M cells of width h = L / M; a
+// bead position is stored as FP32 offsets inside its cell plus the three
+// cell indices (10 bits each) in the w word.  h <= 1 A and h <= (L/2 - rc)/2,
+// so every pair closer than rc takes its minimum image from the integer cell
+// difference (exact = 1); the pair vector is then accurate to about 1e-6 A.
+struct FineGrid {
+    int M[3];
+    float h[3];
+    double Minv[3], hd[3];
+    int exact;
+};
+FineGrid fine_grid(const double L[3], double rc);
+void pack_positions(const double *pos, size_t n, const FineGrid &g, float4 *out, hipStream_t s);
+
+__device__ __forceinline__ int wrap_cell(int d, int M)
+{
+    const int hM = M >> 1;
+    return d > hM ? d - M : (d < -hM ? d + M : d);
+}
+
+// r_j - r_i from packed positions.
+__device__ __forceinline__ void packed_pair(const float4 &pj, const float4 &pi, const int M[3], const float h[3],
+                                            float &dx, float &dy, float &dz)
+{
+    const int wj = __float_as_int(pj.w), wi = __float_as_int(pi.w);
+    const int cx = wrap_cell((wj & 1023) - (wi & 1023), M[0]);
+    const int cy = wrap_cell(((wj >> 10) & 1023) - ((wi >> 10) & 1023), M[1]);
+    const int cz = wrap_cell(((wj >> 20) & 1023) - ((wi >> 20) & 1023), M[2]);
+    dx = fmaf(h[0], (float)cx, pj.x - pi.x);
+    dy = fmaf(h[1], (float)cy, pj.y - pi.y);
+    dz = fmaf(h[2], (float)cz, pj.z - pi.z);
+}
+
 // Kernel timing (hipEvents around launches on the caller's stream), off by default.
 enum KernelId {
-    K_FILL = 0, K_CENTROID, K_GRID, K_CELL_COUNT, K_CELL_SCAN, K_CELL_FILL, K_CELL_SORT, K_CANDIDATES,
+    K_FILL = 0, K_PACK, K_CENTROID, K_GRID, K_CELL_COUNT, K_CELL_SCAN, K_CELL_FILL, K_CELL_SORT, K_CANDIDATES,
     K_SORT_ROWS, K_REVERSE, K_NLIST,
-    K_PACK, K_DESCRIPTOR, K_FORCE_ANG, K_FORCE, K_REDUCE, K_TRPMD, K_MODES, K_NUM
+    K_DESCRIPTOR, K_FORCE_ANG, K_FORCE, K_REDUCE, K_TRPMD, K_MODES, K_NUM
 };
 struct ProfScope {
     int id;

@@ -62,53 +62,11 @@ __device__ __forceinline__ void block_range(const int32_t *end, int b, int t, in
     s1 = end[base + (size_t)t * N];
 }
 
-// Minimum-image difference of two fine-grid cell indices (0 <= c < M).
-__device__ __forceinline__ int wrap_cell(int d, int M)
-{
-    const int hM = M >> 1;
-    return d > hM ? d - M : (d < -hM ? d + M : d);
-}
-
-// Pair vector r_j - r_i from packed positions: the FP32 offsets inside the
-// fine grid cells plus the minimum-image cell difference times the spacing.
-// Exact in the image choice whenever |r_ij| < L/2 - h (every pair inside a
-// cutoff; the host picks h accordingly), and accurate to a few 1e-7 A.
+// Pair vector r_j - r_i from packed positions (see FineGrid).
 __device__ __forceinline__ void pair_vec(const float4 &pj, const float4 &pi, const NepArgs &a, float &dx, float &dy,
                                          float &dz)
 {
-    const int wj = __float_as_int(pj.w), wi = __float_as_int(pi.w);
-    const int cx = wrap_cell((wj & 1023) - (wi & 1023), a.M[0]);
-    const int cy = wrap_cell(((wj >> 10) & 1023) - ((wi >> 10) & 1023), a.M[1]);
-    const int cz = wrap_cell(((wj >> 20) & 1023) - ((wi >> 20) & 1023), a.M[2]);
-    dx = fmaf(a.h[0], (float)cx, pj.x - pi.x);
-    dy = fmaf(a.h[1], (float)cy, pj.y - pi.y);
-    dz = fmaf(a.h[2], (float)cz, pj.z - pi.z);
-}
-
-// Packs the FP64 positions: per axis the fine cell c = floor(x / h) mod M
-// and the offset x - floor(x / h) h in FP32 (unwrapped coordinates allowed).
-__global__ void k_pack(const double *__restrict__ pos, size_t n, double3 Minv, int3 M, double3 h,
-                       float4 *__restrict__ out)
-{
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    const double x[3] = {pos[3 * e], pos[3 * e + 1], pos[3 * e + 2]};
-    const double mi[3] = {Minv.x, Minv.y, Minv.z}, hh[3] = {h.x, h.y, h.z};
-    const int mm[3] = {M.x, M.y, M.z};
-    float o[3];
-    int bits = 0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        double fl = floor(x[d] * mi[d]);
-        if (!isfinite(fl)) fl = 0.0;
-        o[d] = (float)(x[d] - fl * hh[d]);
-        double c = fl - (double)mm[d] * floor(fl / (double)mm[d]);
-        int ci = (int)c;
-        ci = ci < 0 ? 0 : (ci >= mm[d] ? mm[d] - 1 : ci);
-        bits |= ci << (10 * d);
-    }
-    if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]))) o[0] = __int_as_float(0x7fc00000);
-    out[e] = make_float4(o[0], o[1], o[2], __int_as_float(bits));
+    packed_pair(pj, pi, a.M, a.h, dx, dy, dz);
 }
 
 // sin(pi z) and cos(pi z) for z in [0, 1]: with w = z - 1/2, cos(pi z) =
@@ -895,23 +853,16 @@ extern "C" int32_t nep_compute(const nep_model *m, nep_nlist *nl, nep_ws *ws, co
     NepArgs a{};
     double L[3];
     if (!box_lengths(box, L)) return fail(NEP_ERR_UNSUPPORTED, "nep_compute: only orthorhombic cells");
-    const double rcmax = std::max(m->hp.rc_radial, m->hp.rc_angular);
-    int3 Mi;
-    double3 Minv, hh;
-    for (int d = 0; d < 3; ++d) {
+    for (int d = 0; d < 3; ++d)
         if (!(L[d] > 0.0) || !std::isfinite(L[d]))
             return fail(NEP_ERR_INVALID_ARG, "nep_compute: bad box edge %g", L[d]);
-        // fine grid spacing h <= 1 A and h < (L/2 - rc)/2, so that every pair
-        // inside the cutoff gets its minimum image from the cell difference
-        const double room = 0.5 * (0.5 * L[d] - rcmax);
-        const double hmax = std::min(1.0, room);
-        int M = (hmax > L[d] / 1023.0) ? (int)std::ceil(L[d] / hmax) : 1023;
-        M = std::max(1, std::min(M, 1023));
-        a.M[d] = M;
-        a.h[d] = (float)(L[d] / M);
-        (&Mi.x)[d] = M;
-        (&Minv.x)[d] = M / L[d];
-        (&hh.x)[d] = L[d] / M;
+    const FineGrid fg = fine_grid(L, std::max(m->hp.rc_radial, m->hp.rc_angular));
+    if (!fg.exact)
+        return fail(NEP_ERR_BOX_TOO_SMALL, "nep_compute: box edges %g %g %g leave no margin over twice the cutoff",
+                    L[0], L[1], L[2]);
+    for (int d = 0; d < 3; ++d) {
+        a.M[d] = fg.M[d];
+        a.h[d] = fg.h[d];
     }
     const nep_hparams &h = m->hp;
     a.p4 = reinterpret_cast<const float4 *>(ws->pos4); a.types = types; a.N = N; a.S = h.n_species; a.H = h.hidden;
@@ -930,12 +881,7 @@ extern "C" int32_t nep_compute(const nep_model *m, nep_nlist *nl, nep_ws *ws, co
     const int key = h.n_max_radial * 100 + h.n_max_angular * 10 + h.four_body;
     if (key != 440 && key != 441 && key != 640 && key != 860 && key != 881)
         return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");
-    {
-        ProfScope ps_(K_PACK, s);
-        const size_t n = (size_t)P * N;
-        hipLaunchKernelGGL(k_pack, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pos, n, Minv, Mi,
-                           hh, reinterpret_cast<float4 *>(ws->pos4));
-    }
+    pack_positions(pos, (size_t)P * N, fg, reinterpret_cast<float4 *>(ws->pos4), s);
     switch (key) {
     case 440: launch<5, 5, false>(a, m->dev, P, s); break;
     case 441: launch<5, 5, true>(a, m->dev, P, s); break;

@@ -35,14 +35,20 @@ struct HostGrid {
     double rcR, rcA;
 };
 
-// Device grid record (written by k_grid).
+// Device grid record.  Words 0-3 and 7-9 describe the candidate rows of the
+// last rebuild and persist across calls; 4-5 are per-call maxima; 6 is the
+// rebuild decision of this call.
 struct DevGrid {
     int nc[3];
     int ncell;
-    uint32_t spread_bits;
-    uint32_t pad;
-    double R2;    // candidate radius squared
+    uint32_t spread_bits;   // D of this call (float bits, atomicMax)
+    uint32_t disp_bits;     // largest centroid displacement since the rebuild (float bits)
+    int rebuild;            // 1: rebuild the candidate rows in this call
+    float d_build;          // D at the last rebuild
+    double R2;              // candidate radius squared of the last rebuild
+    uint32_t rows_overflow; // a candidate row of the last rebuild was truncated
 };
+static_assert(sizeof(DevGrid) <= 16 * sizeof(uint32_t), "grid record exceeds its 16-word buffer");
 
 __device__ __forceinline__ int cell_axis(double x, double L, double invL, int nc)
 {
@@ -84,13 +90,15 @@ __device__ __forceinline__ float wave_max_f(float v)
     return v;
 }
 
-// Centroid of each atom's ring polymer and its largest bead distance.
+// Centroid of each atom's ring polymer, its largest bead distance and its
+// displacement from the centroid of the last rebuild (both rounded up).
 __global__ void k_centroid(const double *__restrict__ pos, const int32_t *__restrict__ types, int P, int N, int S,
-                           double *__restrict__ cen, uint32_t *__restrict__ grid, uint32_t *__restrict__ status)
+                           double *__restrict__ cen, const double *__restrict__ cen_ref, uint32_t *__restrict__ grid,
+                           uint32_t *__restrict__ status)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t f = 0;
-    float spread = 0.0f;
+    float spread = 0.0f, disp = 0.0f;
     if (i < N) {
         const size_t st = (size_t)N * 3;
         double c[3] = {0.0, 0.0, 0.0};
@@ -112,23 +120,45 @@ __global__ void k_centroid(const double *__restrict__ pos, const int32_t *__rest
         cen[3 * i + 1] = c[1];
         cen[3 * i + 2] = c[2];
         const bool finite = isfinite(c[0]) && isfinite(c[1]) && isfinite(c[2]) && isfinite(m2);
-        if (!finite) f |= NEP_FLAG_NONFINITE;
-        else spread = (float)sqrt(m2) * 1.000001f + 1e-7f;   // rounded up
+        if (!finite) {
+            f |= NEP_FLAG_NONFINITE;
+        } else {
+            spread = (float)sqrt(m2) * 1.000001f + 1e-7f;   // rounded up
+            const double dx = c[0] - cen_ref[3 * i], dy = c[1] - cen_ref[3 * i + 1], dz = c[2] - cen_ref[3 * i + 2];
+            const double d2 = dx * dx + dy * dy + dz * dz;
+            disp = isfinite(d2) ? (float)sqrt(d2) * 1.000001f + 1e-7f : 3.0e38f;
+        }
         const int t = types[i];
         if (t < 0 || t >= S) f |= NEP_FLAG_BAD_TYPE;
     }
     spread = wave_max_f(spread);
+    disp = wave_max_f(disp);
     if ((threadIdx.x & 63) == 0 && spread > 0.0f) atomicMax(&grid[4], __float_as_uint(spread));
+    if ((threadIdx.x & 63) == 0 && disp > 0.0f) atomicMax(&grid[5], __float_as_uint(disp));
     if (f) atomicOr(&status[0], f);
 }
 
-// Grid and candidate radii from the measured spread.
-__global__ void k_grid(HostGrid g, uint32_t *__restrict__ grid, uint32_t *__restrict__ status)
+// Rebuild decision and, on a rebuild, the grid and candidate radius from the
+// measured spread.  Candidate rows built with radius rc + 2 D0 + skin stay
+// complete while 2 (D - D0) + 2 max|c - c0| <= skin (triangle inequality on
+// the periodic centroid distance); otherwise they are rebuilt.
+__global__ void k_grid(HostGrid g, double skin, int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status)
 {
     DevGrid *dg = reinterpret_cast<DevGrid *>(grid);
     const float spread = __uint_as_float(dg->spread_bits);
+    const float disp = __uint_as_float(dg->disp_bits);
+    const double need = 2.0 * ((double)spread - (double)dg->d_build) + 2.0 * (double)disp;
+    const int rebuild = force || !(need <= skin);
+    dg->rebuild = rebuild;
+    atomicMax(&status[4], dg->spread_bits);
+    if (!rebuild) {
+        // reused rows that were truncated keep the overflow flag raised
+        if (dg->rows_overflow) atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
+        return;
+    }
+    dg->rows_overflow = 0;
     const double rc = g.rcR > g.rcA ? g.rcR : g.rcA;
-    const double R = rc + 2.0 * (double)spread + 1e-9 * (1.0 + rc);
+    const double R = rc + 2.0 * (double)spread + skin + 1e-9 * (1.0 + rc);
     int ncell = 1;
     for (int a = 0; a < 3; ++a) {
         int nc = (int)floor(g.L[a] / (R * (1.0 + 1e-9)));
@@ -138,15 +168,16 @@ __global__ void k_grid(HostGrid g, uint32_t *__restrict__ grid, uint32_t *__rest
     }
     dg->ncell = ncell;
     dg->R2 = R * R;
-    atomicMax(&status[4], dg->spread_bits);
+    dg->d_build = spread;
+    atomicAdd(&status[5], 1u);
 }
 
 __global__ void k_cell_count(const double *__restrict__ cen, int N, HostGrid g, const uint32_t *__restrict__ grid,
                              int32_t *__restrict__ cell_cnt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
     const DevGrid *dg = reinterpret_cast<const DevGrid *>(grid);
+    if (i >= N || !dg->rebuild) return;
     const int cx = cell_axis(cen[3 * i], g.L[0], g.invL[0], dg->nc[0]);
     const int cy = cell_axis(cen[3 * i + 1], g.L[1], g.invL[1], dg->nc[1]);
     const int cz = cell_axis(cen[3 * i + 2], g.L[2], g.invL[2], dg->nc[2]);
@@ -157,6 +188,7 @@ __global__ __launch_bounds__(1024) void k_cell_scan(const uint32_t *__restrict__
                                                     int32_t *__restrict__ st)
 {
     __shared__ int32_t part[1024];
+    if (!reinterpret_cast<const DevGrid *>(grid)->rebuild) return;   // whole workgroup
     const int ncell = reinterpret_cast<const DevGrid *>(grid)->ncell;
     const int t = threadIdx.x;
     const int per = (ncell + 1023) / 1024;
@@ -185,8 +217,8 @@ __global__ void k_cell_fill(const double *__restrict__ cen, int N, HostGrid g, c
                             int32_t *__restrict__ cell_atoms)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
     const DevGrid *dg = reinterpret_cast<const DevGrid *>(grid);
+    if (i >= N || !dg->rebuild) return;
     const int cx = cell_axis(cen[3 * i], g.L[0], g.invL[0], dg->nc[0]);
     const int cy = cell_axis(cen[3 * i + 1], g.L[1], g.invL[1], dg->nc[1]);
     const int cz = cell_axis(cen[3 * i + 2], g.L[2], g.invL[2], dg->nc[2]);
@@ -205,7 +237,8 @@ __global__ __launch_bounds__(64) void k_cell_rank(const uint32_t *__restrict__ g
     __shared__ int32_t v[kRankMax];
     __shared__ int32_t out[kRankMax];
     const int c = blockIdx.x;
-    if (c >= reinterpret_cast<const DevGrid *>(grid)->ncell) return;
+    if (!reinterpret_cast<const DevGrid *>(grid)->rebuild || c >= reinterpret_cast<const DevGrid *>(grid)->ncell)
+        return;
     const int s0 = cell_start[c], n = cell_start[c + 1] - s0;
     int32_t *a = cell_atoms + s0;
     if (n <= kRankMax) {
@@ -240,19 +273,19 @@ __global__ __launch_bounds__(64) void k_cell_rank(const uint32_t *__restrict__ g
 // A stencil too large for LDS is read from global memory instead.
 constexpr int kStage = 2048;
 __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ cen, const int32_t *__restrict__ types,
-                                                    int N, int S, HostGrid g, const uint32_t *__restrict__ grid,
+                                                    int N, int S, HostGrid g, uint32_t *__restrict__ grid,
                                                     const int32_t *__restrict__ cell_start,
                                                     const int32_t *__restrict__ cell_atoms, int capC,
                                                     int32_t *__restrict__ cand, int32_t *__restrict__ rowlen,
-                                                    uint32_t *__restrict__ status)
+                                                    double *__restrict__ cen_ref, uint32_t *__restrict__ status)
 {
     __shared__ double sx[kStage], sy[kStage], sz[kStage];
     __shared__ int32_t sw[kStage];
     __shared__ int32_t rs[28], rp[28];
     __shared__ int nrange;
-    const DevGrid *dg = reinterpret_cast<const DevGrid *>(grid);
+    DevGrid *dg = reinterpret_cast<DevGrid *>(grid);
     const int c = blockIdx.x;
-    if (c >= dg->ncell) return;   // whole workgroup
+    if (!dg->rebuild || c >= dg->ncell) return;   // whole workgroup
     const int nc0 = dg->nc[0], nc1 = dg->nc[1], nc2 = dg->nc[2];
     const double R2 = dg->R2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -340,8 +373,14 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
         }
         if (lane == 0) {
             rowlen[i] = cnt;
+            cen_ref[3 * i] = ci[0];
+            cen_ref[3 * i + 1] = ci[1];
+            cen_ref[3 * i + 2] = ci[2];
             atomicMax(&status[3], (uint32_t)cnt);
-            if (cnt > capC) atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
+            if (cnt > capC) {
+                atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
+                atomicOr(&dg->rows_overflow, 1u);
+            }
         }
     }
 }
@@ -351,10 +390,11 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
 // number of smaller keys), in LDS for rows up to kSortLds, otherwise through
 // the atom's reverse-slot row as scratch (it is rewritten afterwards).
 constexpr int kSortLds = 512;
-__global__ __launch_bounds__(256) void k_sort_rows(int N, int S, int capC, int32_t *__restrict__ cand,
-                                                   const int32_t *__restrict__ rowlen, int32_t *__restrict__ off,
-                                                   int32_t *__restrict__ scratch)
+__global__ __launch_bounds__(256) void k_sort_rows(const uint32_t *__restrict__ grid, int N, int S, int capC,
+                                                   int32_t *__restrict__ cand, const int32_t *__restrict__ rowlen,
+                                                   int32_t *__restrict__ off, int32_t *__restrict__ scratch)
 {
+    if (!reinterpret_cast<const DevGrid *>(grid)->rebuild) return;   // whole workgroup
     __shared__ int32_t buf[kBlock / 64][kSortLds];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = blockIdx.x * (kBlock / 64) + wv;
@@ -395,10 +435,11 @@ __global__ __launch_bounds__(256) void k_sort_rows(int N, int S, int capC, int32
 // Reverse slots: for candidate j of i (slot k), the slot of i in j's row,
 // by binary search in the species block of i (ordered by index); -1 if i
 // is missing (only when j's row overflowed).  One wavefront per atom.
-__global__ __launch_bounds__(256) void k_reverse(int N, int capC, const int32_t *__restrict__ types,
-                                                 const int32_t *__restrict__ cand, const int32_t *__restrict__ off,
-                                                 int32_t *__restrict__ rev)
+__global__ __launch_bounds__(256) void k_reverse(const uint32_t *__restrict__ grid, int N, int capC,
+                                                 const int32_t *__restrict__ types, const int32_t *__restrict__ cand,
+                                                 const int32_t *__restrict__ off, int32_t *__restrict__ rev)
 {
+    if (!reinterpret_cast<const DevGrid *>(grid)->rebuild) return;   // whole workgroup
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (i >= N) return;
@@ -421,9 +462,14 @@ __global__ __launch_bounds__(256) void k_reverse(int N, int capC, const int32_t 
 }
 
 // Per-bead exact lists.  One lane per (bead, atom); candidates are taken in
-// batches so that several position loads are in flight at once.
+// batches so that several position loads are in flight at once.  The test
+// runs first on the packed FP32 positions; only a pair whose FP32 squared
+// distance lies within `margin` of a cutoff squared (far above the packed
+// error bound) is decided by the FP64 test, so every decision equals the
+// FP64 one.
 constexpr int kFilterBatch = 8;
-__global__ __launch_bounds__(256) void k_filter(const double *__restrict__ pos, int N, int S, HostGrid g,
+__global__ __launch_bounds__(256) void k_filter(const double *__restrict__ pos, const float4 *__restrict__ pos4,
+                                                FineGrid fg, float margin, int N, int S, HostGrid g,
                                                 const int32_t *__restrict__ cand, const int32_t *__restrict__ off,
                                                 const int32_t *__restrict__ rev, int capC, int capR, int capA,
                                                 double rcR2, double rcA2, int32_t *__restrict__ listR,
@@ -437,7 +483,9 @@ __global__ __launch_bounds__(256) void k_filter(const double *__restrict__ pos, 
     int sR = 0, sA = 0;
     if (i < N) {
         const double *pb = pos + (size_t)b * N * 3;
-        const double ri[3] = {pb[3 * i], pb[3 * i + 1], pb[3 * i + 2]};
+        const float4 *p4 = pos4 + (size_t)b * N;
+        const float4 pi = p4[i];
+        const float rR2f = (float)rcR2, rA2f = (float)rcA2;
         const int32_t *row = cand + (size_t)i * capC;
         const int32_t *rrow = rev + (size_t)i * capC;
         const int32_t *oi = off + (size_t)i * (kMaxSpecies + 1);
@@ -452,31 +500,39 @@ __global__ __launch_bounds__(256) void k_filter(const double *__restrict__ pos, 
             const int k0 = min(oi[t], capC), k1 = min(oi[t + 1], capC);
             for (int kb = k0; kb < k1; kb += kFilterBatch) {
                 int w[kFilterBatch];
-                double pj[kFilterBatch][3];
+                float4 pj[kFilterBatch];
 #pragma unroll
                 for (int u = 0; u < kFilterBatch; ++u) {
                     const int k = kb + u;
                     w[u] = row[k < k1 ? k : k0];
-                    const int j = w[u] >> 2;
-                    pj[u][0] = pb[3 * j];
-                    pj[u][1] = pb[3 * j + 1];
-                    pj[u][2] = pb[3 * j + 2];
+                    pj[u] = p4[w[u] >> 2];
                 }
 #pragma unroll
                 for (int u = 0; u < kFilterBatch; ++u) {
                     const int k = kb + u;
                     if (k < k1) {
-                        const double r2 = mic_r2_exact(ri, pj[u], g);
+                        float dx, dy, dz;
+                        packed_pair(pj[u], pi, fg.M, fg.h, dx, dy, dz);
+                        const float r2f = dx * dx + dy * dy + dz * dz;
+                        bool inR = r2f < rR2f, inA = r2f < rA2f;
+                        if (fabsf(r2f - rR2f) <= margin || fabsf(r2f - rA2f) <= margin) {
+                            const int j = w[u] >> 2;
+                            const double ri[3] = {pb[3 * i], pb[3 * i + 1], pb[3 * i + 2]};
+                            const double rj[3] = {pb[3 * j], pb[3 * j + 1], pb[3 * j + 2]};
+                            const double r2 = mic_r2_exact(ri, rj, g);
+                            inR = r2 < rcR2;
+                            inA = r2 < rcA2;
+                        }
                         while ((k >> 5) > wcur) {   // close the finished words
                             mk[(size_t)wcur * N] = (uint64_t)word | ((uint64_t)before << 32);
                             before += __popc(word);
                             word = 0;
                             ++wcur;
                         }
-                        if (r2 < rcR2) {
+                        if (inR) {
                             if (sR < capR) lR[(size_t)sR * N] = w[u] >> 2;
                             ++sR;
-                            if (r2 < rcA2) {
+                            if (inA) {
                                 word |= 1u << (k & 31);
                                 if (sA < capA) {
                                     lA[(size_t)sA * N] = w[u] >> 2;
@@ -543,17 +599,29 @@ extern "C" int32_t neighbor_build(const nep_model *m, nep_nlist *nl, const doubl
     }
     const double rcR2 = m->hp.rc_radial * m->hp.rc_radial;
     const double rcA2 = m->hp.rc_angular * m->hp.rc_angular;
-    fill_u32(nl->grid, 0u, 16, s);
+    const FineGrid fg = fine_grid(g.L, rc);
+    if (!fg.exact)
+        return fail(NEP_ERR_BOX_TOO_SMALL, "box edges %g %g %g leave no margin over twice the cutoff %g", g.L[0],
+                    g.L[1], g.L[2], rc);
+    // decision margin for the FP32 prefilter: ~50x the packed error bound
+    const double hmax = std::max(std::max(fg.hd[0], fg.hd[1]), fg.hd[2]);
+    const float margin = (float)(1e-3 * std::max(1.0, hmax * hmax) * std::max(1.0, rc * rc / 36.0));
+    // a changed box invalidates the candidate rows
+    bool force = !nl->built;
+    for (int a = 0; a < 3; ++a) force = force || g.L[a] != nl->box_built[a];
+    fill_u32(nl->grid + 4, 0u, 2, s);
+    pack_positions(pos, (size_t)P * N, fg, reinterpret_cast<float4 *>(nl->pos4), s);
     fill_i32(nl->cell_cnt, 0, (size_t)ncell_cap, s);
     const dim3 g1(div_up(N, kBlock));
     const dim3 gw(div_up(N, kBlock / 64));
     {
         ProfScope ps_(K_CENTROID, s);
-        hipLaunchKernelGGL(k_centroid, g1, dim3(kBlock), 0, s, pos, types, P, N, nl->S, nl->cen, nl->grid, nl->status);
+        hipLaunchKernelGGL(k_centroid, g1, dim3(kBlock), 0, s, pos, types, P, N, nl->S, nl->cen, nl->cen_ref, nl->grid,
+                           nl->status);
     }
     {
         ProfScope ps_(K_GRID, s);
-        hipLaunchKernelGGL(k_grid, dim3(1), dim3(1), 0, s, g, nl->grid, nl->status);
+        hipLaunchKernelGGL(k_grid, dim3(1), dim3(1), 0, s, g, nl->skin, force ? 1 : 0, nl->grid, nl->status);
     }
     {
         ProfScope ps_(K_CELL_COUNT, s);
@@ -575,23 +643,43 @@ extern "C" int32_t neighbor_build(const nep_model *m, nep_nlist *nl, const doubl
     {
         ProfScope ps_(K_CANDIDATES, s);
         hipLaunchKernelGGL(k_candidates, dim3(ncell_cap), dim3(kBlock), 0, s, nl->cen, types, N, nl->S, g, nl->grid,
-                           nl->cell_start, nl->cell_atoms, nl->capC, nl->cand, nl->rowlen, nl->status);
+                           nl->cell_start, nl->cell_atoms, nl->capC, nl->cand, nl->rowlen, nl->cen_ref, nl->status);
     }
     {
         ProfScope ps_(K_SORT_ROWS, s);
-        hipLaunchKernelGGL(k_sort_rows, gw, dim3(kBlock), 0, s, N, nl->S, nl->capC, nl->cand, nl->rowlen, nl->offC,
-                           nl->revC);
+        hipLaunchKernelGGL(k_sort_rows, gw, dim3(kBlock), 0, s, nl->grid, N, nl->S, nl->capC, nl->cand, nl->rowlen,
+                           nl->offC, nl->revC);
     }
     {
         ProfScope ps_(K_REVERSE, s);
-        hipLaunchKernelGGL(k_reverse, gw, dim3(kBlock), 0, s, N, nl->capC, types, nl->cand, nl->offC, nl->revC);
+        hipLaunchKernelGGL(k_reverse, gw, dim3(kBlock), 0, s, nl->grid, N, nl->capC, types, nl->cand, nl->offC,
+                           nl->revC);
     }
     {
         ProfScope ps_(K_NLIST, s);
-        hipLaunchKernelGGL(k_filter, dim3(div_up(N, kBlock), P), dim3(kBlock), 0, s, pos, N, nl->S, g, nl->cand,
+        hipLaunchKernelGGL(k_filter, dim3(div_up(N, kBlock), P), dim3(kBlock), 0, s, pos,
+                           reinterpret_cast<const float4 *>(nl->pos4), fg, margin, N, nl->S, g, nl->cand,
                            nl->offC, nl->revC, nl->capC, nl->capR, nl->capA, rcR2, rcA2, nl->listR, nl->endR,
                            nl->listA, nl->endA, nl->slotA, nl->maskA, nl->status);
     }
     NEP_HIP(hipGetLastError());
+    nl->built = 1;
+    for (int a = 0; a < 3; ++a) nl->box_built[a] = g.L[a];
+    return NEP_OK;
+}
+
+extern "C" int32_t nep_nlist_set_skin(nep_nlist *nl, double skin)
+{
+    if (!nl) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_set_skin: null argument");
+    if (!(skin >= 0.0) || !(skin <= 10.0)) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_set_skin: bad skin %g", skin);
+    nl->skin = skin;
+    nl->built = 0;
+    return NEP_OK;
+}
+
+extern "C" int32_t nep_nlist_invalidate(nep_nlist *nl)
+{
+    if (!nl) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_invalidate: null argument");
+    nl->built = 0;
     return NEP_OK;
 }

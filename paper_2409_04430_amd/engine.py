@@ -29,7 +29,7 @@ class NepPimd:
 
     def __init__(self, model_path: str, system: I.System, *, dt: float, T: float, tau: float = 100.0,
                  mode: str = "trpmd", seed: int = 0, caps: Optional[tuple] = None, check_every: int = 50,
-                 want_atom: bool = False):
+                 want_atom: bool = False, skin: float = 0.5):
         import torch
         self.torch = torch
         dev = torch.device("cuda")
@@ -51,6 +51,7 @@ class NepPimd:
         self.caps = tuple(caps) if caps else (default_capacity(rcR + 0.5, dens, S), default_capacity(rcR, dens, S),
                                               default_capacity(rcA, dens, S))
         self.nl = None
+        self.skin = skin
         self.ws = lib.Workspace(self.model, self.P, self.N)
         self.pimd = lib.Pimd(self.P, self.N, self.mass, dt, T, tau, mode, seed)
         self.check_every = check_every
@@ -61,7 +62,7 @@ class NepPimd:
     # ------------------------------------------------------------------
     def _fit_capacity(self):
         """Size the candidate rows to the starting configuration (slack for the run)."""
-        self.nl = lib.fitted_neighbor_list(self.model, self.pos, self.box, self.types, *self.caps)
+        self.nl = lib.fitted_neighbor_list(self.model, self.pos, self.box, self.types, *self.caps, skin=self.skin)
         self.caps = self.nl.caps
 
     def forces(self):

@@ -52,7 +52,7 @@ class NlistLayout(C.Structure):
 
 class NlistStatus(C.Structure):
     _fields_ = [("flags", C.c_uint32), ("max_radial", C.c_int32), ("max_angular", C.c_int32),
-                ("max_candidates", C.c_int32), ("bead_spread", C.c_float)]
+                ("max_candidates", C.c_int32), ("bead_spread", C.c_float), ("rebuilds", C.c_int32)]
 
 
 class PimdParams(C.Structure):
@@ -81,7 +81,10 @@ _sig = {
     "pimd_destroy": (None, [_vp]),
     "rp_normal_modes": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "trpmd_step": (_i32, [_vp, _vp, _vp, _vp, C.c_int64, _i32, _vp]),
+    "nep_nlist_set_skin": (_i32, [_vp, C.c_double]),
+    "nep_nlist_invalidate": (_i32, [_vp]),
     "nep_profile_enable": (_i32, [_i32]),
+    "nep_profile_select": (_i32, [_i32]),
     "nep_profile_num_kernels": (_i32, []),
     "nep_profile_kernel_name": (C.c_char_p, [_i32]),
     "nep_profile_read": (_i32, [C.POINTER(C.c_double), C.POINTER(C.c_int64), _i32]),
@@ -169,6 +172,13 @@ class NeighborList:
         self.model, self.P, self.N = model, P, N
         self.caps = (cap_candidates, cap_radial, cap_angular)
 
+    def set_skin(self, skin: float):
+        """Reuse candidate rows across builds while the skin covers the motion (0: rebuild every call)."""
+        _check(_lib.nep_nlist_set_skin(self._h, float(skin)))
+
+    def invalidate(self):
+        _check(_lib.nep_nlist_invalidate(self._h))
+
     def build(self, pos, box, types):
         _check(_lib.neighbor_build(self.model.handle, self._h, _ptr(pos, _torch().float64, (self.P, self.N, 3), "pos"),
                                    _box9(box), _ptr(types, _torch().int32, (self.N,), "types"), self.P, self.N,
@@ -233,7 +243,8 @@ class NeighborList:
 
 
 def fitted_neighbor_list(model: "Model", pos, box, types, cap_candidates: int = 96, cap_radial: int = 80,
-                         cap_angular: int = 32, slack: float = 1.25, tries: int = 4) -> NeighborList:
+                         cap_angular: int = 32, slack: float = 1.25, tries: int = 4,
+                         skin: float = 0.0) -> NeighborList:
     """A NeighborList whose capacities fit the given positions.
 
     Builds once, reads the longest candidate row and lists from the sticky
@@ -246,6 +257,7 @@ def fitted_neighbor_list(model: "Model", pos, box, types, cap_candidates: int = 
         caps[1] = min(caps[1], caps[0])
         caps[2] = min(caps[2], caps[1])
         nl = NeighborList(model, P, N, *caps)
+        nl.set_skin(skin)
         nl.build(pos, box, types)
         st = nl.status(clear=True)
         if st["flags"] & FLAG_BAD_TYPE:
@@ -327,7 +339,13 @@ def _torch():
     return torch
 
 
-def profile_enable(on: bool = True):
+def profile_enable(on: bool = True, only: Optional[str] = None):
+    """Per-kernel event timing on/off; `only` restricts it to one kernel kind."""
+    kid = -1
+    if only is not None:
+        names = [_lib.nep_profile_kernel_name(k).decode() for k in range(_lib.nep_profile_num_kernels())]
+        kid = names.index(only)
+    _check(_lib.nep_profile_select(kid))
     _check(_lib.nep_profile_enable(int(on)))
 
 

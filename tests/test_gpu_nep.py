@@ -324,3 +324,44 @@ def test_nep_edge_cases(torch, L, tmpdir_session):
                    torch.zeros((2, 108, 3), dtype=torch.float32, device=dev),
                    torch.zeros((2, 9), dtype=torch.float64, device=dev))
     assert e.value.code == 1
+
+
+def test_skin_reuse_matches_fresh_lists(torch, L, tmpdir_session):
+    """Candidate rows reused under a skin give the same per-bead lists and
+    bitwise the same forces as rows rebuilt at every call; with a small skin
+    the run goes through both reuse and rebuild calls."""
+    say("[nep] candidate reuse under a skin")
+    from paper_2409_04430_amd.engine import NepPimd
+    w = configs.WORKLOADS["rocksalt4096"]
+    path = write_model(tmpdir_session, "skin", w.model())
+    s = w.systems(P=4)[0]
+    eng = NepPimd(path, s, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=0, skin=0.02)
+    eng.nl.status(clear=True)
+    dev = torch.device("cuda")
+    P, N = s.P, s.N
+    for _ in range(4):
+        eng.run(10)
+        eng.nl.build(eng.pos, eng.box, eng.types)   # lists at the current positions (reuse or rebuild)
+        la = eng.nl.to_host()
+        ref = L.NeighborList(eng.model, P, N, *eng.caps)
+        ref.build(eng.pos, eng.box, eng.types)
+        assert ref.status()["flags"] == 0
+        lb = ref.to_host()
+        S = la["n_species"]
+        for kind in ("radial", "angular"):
+            np.testing.assert_array_equal(la["cnt_" + kind], lb["cnt_" + kind])
+            np.testing.assert_array_equal(la["end_" + kind][:, :S], lb["end_" + kind][:, :S])
+            valid = np.arange(la["nbr_" + kind].shape[1])[None, :, None] < la["cnt_" + kind][:, None, :]
+            np.testing.assert_array_equal(la["nbr_" + kind][valid], lb["nbr_" + kind][valid])
+        # forces from the reused rows equal those from fresh rows, bitwise
+        F1 = torch.zeros((P, N, 3), dtype=torch.float32, device=dev)
+        F2 = torch.zeros_like(F1)
+        E = torch.zeros(P, dtype=torch.float64, device=dev)
+        W = torch.zeros((P, 9), dtype=torch.float64, device=dev)
+        eng.ws.compute(eng.nl, eng.pos, eng.box, eng.types, E, F1, W)
+        eng.ws.compute(ref, eng.pos, eng.box, eng.types, E, F2, W)
+        torch.cuda.synchronize()
+        assert torch.equal(F1, F2)
+    st = eng.nl.status(clear=True)
+    say(f"  rebuilds in 40 steps: {st['rebuilds']}")
+    assert st["flags"] == 0 and 1 <= st["rebuilds"] < 40
