@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--workload", default="rocksalt4096")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-beads", type=int, default=0, help="oracle sample size in beads (0: auto)")
+    ap.add_argument("--graph", action="store_true",
+                    help="time replays of the captured step graph instead of eager launches")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--no-profile", action="store_true", help="do not bracket kernels with timing events")
@@ -182,11 +184,30 @@ def main():
         kernels = {k: {"avg_us": 1e3 * v[0] / v[1], "launches": v[1]} for k, v in kt.items() if v[1]}
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"]) if kernels else None
 
-    # timed region: K whole steps; only the dominant kernel carries events
+    # eager pass: the dominant kernel bracketed by events on its launch stream
+    eager_steps = max(10, min(50, args.steps))
     if dom:
         lib.profile_read(reset=True)
         lib.profile_enable(True, only=dom)
     stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    eng.run(eager_steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    lib.profile_enable(False)
+    lib.profile_enable(False, only=None)
+    eager_ms = e0.elapsed_time(e1) / eager_steps
+    dom_avg_us = None
+    if dom:
+        v = lib.profile_read(reset=True)[dom]
+        dom_avg_us = 1e3 * v[0] / v[1] if v[1] else None
+
+    # timed region: K whole steps (eager launches, or graph replays with --graph)
+    if args.graph:
+        eng.capture()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -196,12 +217,6 @@ def main():
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    lib.profile_enable(False)
-    lib.profile_enable(False, only=None)
-    dom_avg_us = None
-    if dom:
-        v = lib.profile_read(reset=True)[dom]
-        dom_avg_us = 1e3 * v[0] / v[1] if v[1] else None
     mr, ma = eng.check()
     gpu_ms = ev0.elapsed_time(ev1)
     elapsed = max(gpu_ms / 1e3, 1e-12)
@@ -255,7 +270,8 @@ def main():
                    "mean_neighbours": [round(nR, 2), round(nA, 2)], "max_block_neighbours": [mr, ma],
                    "arithmetic": "positions, integrator, force/energy/virial sums FP64; descriptors, network, "
                                  "pair terms FP32",
-                   "wall_s": round(wall, 4)},
+                   "wall_s": round(wall, 4), "launch": "hipGraph replay" if args.graph else "eager",
+                   "eager_ms_per_step": round(eager_ms, 4)},
         "roofline": roof,
         "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
         "cpu_baseline": cpu,

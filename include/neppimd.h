@@ -283,6 +283,13 @@ int32_t rp_normal_modes(const pimd_ctx *ctx, int32_t dir, const double *in, doub
 int32_t trpmd_step(const pimd_ctx *ctx, double *pos, double *vel, const float *F, int64_t step, int32_t stage,
                    hipStream_t stream);
 
+/* trpmd_step with the step number read from device memory (*step, int64)
+ * at launch time; after a POST or FUSED stage the counter is advanced by one
+ * on the stream.  For graph capture: a captured step replays with fresh
+ * noise.  Errors as trpmd_step, and NEP_ERR_INVALID_ARG for a null counter. */
+int32_t trpmd_step_dev(const pimd_ctx *ctx, double *pos, double *vel, const float *F, int64_t *step,
+                       int32_t stage, hipStream_t stream);
+
 /* ------------------------------------------------------------------ */
 /* Kernel timing                                                       */
 /* ------------------------------------------------------------------ */

@@ -97,7 +97,7 @@ struct pimd_ctx {
     pimd_params prm;
     int device = 0;
     double *mass = nullptr;    // [N]
-    double *consts = nullptr;  // C [P][P] then per mode {c1, c2, cq, qv, vq}
+    double *consts = nullptr;  // C [P][P] then per mode c1, c2, cq, qv, vq
     std::vector<double> hC;    // host copy of C
 };
 

@@ -3,17 +3,16 @@
 // step (Eqs. (5)-(6)), half kick (Eq. (9)) and the Langevin thermostat on
 // normal-mode momenta (Eqs. (10)-(12)).
 //
-// One lane per (atom, Cartesian component) holds the P normal-mode
-// velocities (and positions) in registers.  Because C is orthogonal, the
+// P lanes per (atom, Cartesian component), one per normal mode, with the
+// element's bead and mode vectors staged in LDS.  Because C is orthogonal, the
 // kicks and the thermostat of a stage are applied in mode space: a stage
 // maps each mode as v~ <- alpha_k v~ + beta_k hk F~ + gamma_k, with
 //   PRE   (O then B):        alpha = c1, beta = 1,          gamma = sig c2 xi0
 //   POST  (B then O):        alpha = c1, beta = c1,         gamma = sig c2 xi1
 //   FUSED (B, O, O, B):      alpha = c1^2, beta = c1^2 + 1, gamma = sig c2 (c1 xi1 + xi0)
 // (c1 = 1, c2 = 0 on modes that are not thermostatted), followed for PRE
-// and FUSED by the Cayley map.  F~ is accumulated straight from the bead
-// forces with the beta-weighted matrix, so only two P-vectors stay live.
-// The bead data move once: read q, v, F and write q, v.
+// and FUSED by the Cayley map.  The bead data move once: read q, v, F and
+// write q, v.
 #include <cmath>
 
 #include "internal.hpp"
@@ -28,13 +27,11 @@ inline double amu_a2_fs2_ev() { return 1.66053906660e-27 * 1e10 / 1.602176634e-1
 // Offsets into the per-context constant block.
 struct PimdLayout {
     int P;
-    int C, CFpost, CFfused, c1, sc2, cq, qv, vq, total;
+    int C, c1, sc2, cq, qv, vq, total;
     __host__ __device__ explicit PimdLayout(int p) : P(p)
     {
         C = 0;
-        CFpost = P * P;
-        CFfused = 2 * P * P;
-        c1 = 3 * P * P;
+        c1 = P * P;
         sc2 = c1 + P;
         cq = sc2 + P;
         qv = cq + P;
@@ -89,105 +86,127 @@ struct StepArgs {
     double *pos, *vel;
     const float *F;
     const double *mass;
-    int N;
+    int N, P;
     double dt, kTP, conv;
     uint64_t seed;
     int64_t step;
+    const int64_t *step_dev;   // if set, the step number is read from device memory
     int stage, noise;
 };
 
-template <int P>
-__global__ __launch_bounds__(256) void k_trpmd(StepArgs a, const double *__restrict__ cst)
+// One workgroup holds floor(256 / P) (atom, component) elements; lane
+// (element, k) works on normal mode k of its element (and bead k for the
+// back transform), so every P x P transform becomes P-long dot products
+// spread over P lanes.  Bead data, mode data and C are staged in LDS; global
+// loads and stores run over consecutive elements of one bead.
+constexpr int kStepBlock = 256;
+__global__ __launch_bounds__(kStepBlock) void k_trpmd(StepArgs a, const double *__restrict__ cst)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    const int M = 3 * a.N;
-    if (e >= M) return;
-    const int i = e / 3, comp = e - 3 * i;
+    extern __shared__ double sh[];
+    const int P = a.P;
+    const int EPB = kStepBlock / P;
     const PimdLayout Lo(P);
-    const double m = a.mass[i];
-    const double hk = 0.5 * a.dt / (m * a.conv);
-    const double sig = sqrt(a.kTP / (m * a.conv));
-    const size_t stride = (size_t)M;
+    double *Cs = sh;                 // [P][P]: C[b][k]
+    double *vb = Cs + P * P;         // [EPB][P]
+    double *qb = vb + EPB * P;
+    double *fb = qb + EPB * P;
+    const int M = 3 * a.N;
+    const int e0 = blockIdx.x * EPB;
+    const int t = threadIdx.x;
     const bool pre = a.stage != PIMD_STAGE_POST, post = a.stage != PIMD_STAGE_PRE;
+    const int64_t step = a.step_dev ? *a.step_dev : a.step;
 
-    double vt[P];
-#pragma unroll
-    for (int k = 0; k < P; ++k) vt[k] = 0.0;
-#pragma unroll 1
-    for (int b = 0; b < P; ++b) {
-        const double v = a.vel[b * stride + e];
-        const double *Cb = cst + Lo.C + b * P;
-#pragma unroll
-        for (int k = 0; k < P; ++k) vt[k] += Cb[k] * v;
+    for (int x = t; x < P * P; x += blockDim.x) Cs[x] = cst[Lo.C + x];
+    for (int x = t; x < EPB * P; x += blockDim.x) {
+        const int b = x / EPB, el = x - b * EPB, e = e0 + el;
+        double v = 0.0, q = 0.0, f = 0.0;
+        if (e < M) {
+            v = a.vel[(size_t)b * M + e];
+            f = (double)a.F[(size_t)b * M + e];
+            if (pre) q = a.pos[(size_t)b * M + e];
+        }
+        vb[el * P + b] = v;
+        qb[el * P + b] = q;
+        fb[el * P + b] = f;
     }
-    // alpha and gamma
-    if (a.noise) {
-        constexpr int NB = (P + 3) / 4;
-        const uint64_t step_pre = (uint64_t)(a.stage == PIMD_STAGE_FUSED ? a.step + 1 : a.step);
-#pragma unroll
-        for (int kb = 0; kb < NB; ++kb) {
-            double z1[4] = {0.0, 0.0, 0.0, 0.0}, z0[4] = {0.0, 0.0, 0.0, 0.0};
-            if (post) normals4(a.seed, (uint64_t)a.step, 1, i, comp, NB, kb, z1);
-            if (pre) normals4(a.seed, step_pre, 0, i, comp, NB, kb, z0);
-#pragma unroll
-            for (int e4 = 0; e4 < 4; ++e4) {
-                const int k = 4 * kb + e4;
-                if (k < P) {
-                    const double c1 = cst[Lo.c1 + k], gs = sig * cst[Lo.sc2 + k];
-                    if (a.stage == PIMD_STAGE_FUSED)
-                        vt[k] = c1 * c1 * vt[k] + gs * (c1 * z1[e4] + z0[e4]);
-                    else
-                        vt[k] = c1 * vt[k] + gs * (post ? z1[e4] : z0[e4]);
-                }
+    __syncthreads();
+
+    const int el = t / P, k = t - el * P;
+    const bool act = el < EPB && e0 + el < M;
+    double qn = 0.0, vn = 0.0;
+    if (act) {
+        const int e = e0 + el;
+        const int i = e / 3, comp = e - 3 * i;
+        const double m = a.mass[i];
+        const double hk = 0.5 * a.dt / (m * a.conv);
+        const double sig = sqrt(a.kTP / (m * a.conv));
+        double vt = 0.0, ft = 0.0, qt = 0.0;
+        for (int b = 0; b < P; ++b) {
+            const double c = Cs[b * P + k];
+            vt += c * vb[el * P + b];
+            ft += c * fb[el * P + b];
+            if (pre) qt += c * qb[el * P + b];
+        }
+        const double c1 = cst[Lo.c1 + k];
+        double alpha = c1, beta = 1.0, gamma = 0.0;
+        if (a.stage == PIMD_STAGE_POST) beta = c1;
+        if (a.stage == PIMD_STAGE_FUSED) {
+            alpha = c1 * c1;
+            beta = c1 * c1 + 1.0;
+        }
+        if (a.noise) {
+            const int NB = (P + 3) / 4, kb = k >> 2, e4 = k & 3;
+            const double gs = sig * cst[Lo.sc2 + k];
+            double z[4];
+            if (a.stage == PIMD_STAGE_FUSED) {
+                normals4(a.seed, (uint64_t)step, 1, i, comp, NB, kb, z);
+                const double z1 = z[e4];
+                normals4(a.seed, (uint64_t)(step + 1), 0, i, comp, NB, kb, z);
+                gamma = gs * (c1 * z1 + z[e4]);
+            } else {
+                normals4(a.seed, (uint64_t)step, post ? 1 : 0, i, comp, NB, kb, z);
+                gamma = gs * z[e4];
             }
         }
-    }
-    // beta-weighted force in mode space
-    const int CF = a.stage == PIMD_STAGE_PRE ? Lo.C : (a.stage == PIMD_STAGE_POST ? Lo.CFpost : Lo.CFfused);
-#pragma unroll 1
-    for (int b = 0; b < P; ++b) {
-        const double f = hk * (double)a.F[b * stride + e];
-        const double *Cb = cst + CF + b * P;
-#pragma unroll
-        for (int k = 0; k < P; ++k) vt[k] += Cb[k] * f;
-    }
-    if (pre) {
-        double qt[P];
-#pragma unroll
-        for (int k = 0; k < P; ++k) qt[k] = 0.0;
-#pragma unroll 1
-        for (int b = 0; b < P; ++b) {
-            const double q = a.pos[b * stride + e];
-            const double *Cb = cst + Lo.C + b * P;
-#pragma unroll
-            for (int k = 0; k < P; ++k) qt[k] += Cb[k] * q;
-        }
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
+        vt = alpha * vt + gamma + beta * (hk * ft);
+        if (pre) {
             const double cq = cst[Lo.cq + k], qv = cst[Lo.qv + k], vq = cst[Lo.vq + k];
-            const double qn = cq * qt[k] + qv * vt[k];
-            const double vn = cq * vt[k] - vq * qt[k];
-            qt[k] = qn;
-            vt[k] = vn;
-        }
-#pragma unroll 1
-        for (int b = 0; b < P; ++b) {
-            const double *Cb = cst + Lo.C + b * P;
-            double s = 0.0;
-#pragma unroll
-            for (int k = 0; k < P; ++k) s += Cb[k] * qt[k];
-            a.pos[b * stride + e] = s;
+            qn = cq * qt + qv * vt;
+            vn = cq * vt - vq * qt;
+        } else {
+            vn = vt;
         }
     }
-#pragma unroll 1
-    for (int b = 0; b < P; ++b) {
-        const double *Cb = cst + Lo.C + b * P;
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < P; ++k) s += Cb[k] * vt[k];
-        a.vel[b * stride + e] = s;
+    __syncthreads();
+    if (act) {
+        vb[el * P + k] = vn;
+        qb[el * P + k] = qn;
+    }
+    __syncthreads();
+    double sv = 0.0, sq = 0.0;
+    if (act) {   // back transform: lane (element, bead k)
+        for (int kk = 0; kk < P; ++kk) {
+            const double c = Cs[k * P + kk];
+            sv += c * vb[el * P + kk];
+            if (pre) sq += c * qb[el * P + kk];
+        }
+    }
+    __syncthreads();
+    if (act) {
+        vb[el * P + k] = sv;
+        qb[el * P + k] = sq;
+    }
+    __syncthreads();
+    for (int x = t; x < EPB * P; x += blockDim.x) {
+        const int b = x / EPB, elx = x - b * EPB, e = e0 + elx;
+        if (e < M) {
+            a.vel[(size_t)b * M + e] = vb[elx * P + b];
+            if (pre) a.pos[(size_t)b * M + e] = qb[elx * P + b];
+        }
     }
 }
+
+__global__ void k_step_advance(int64_t *step) { *step += 1; }
 
 template <int P>
 __global__ __launch_bounds__(256) void k_modes(const double *__restrict__ in, double *__restrict__ out, int M,
@@ -212,12 +231,13 @@ __global__ __launch_bounds__(256) void k_modes(const double *__restrict__ in, do
     }
 }
 
-template <int P>
 static void launch_step(const StepArgs &a, const double *cst, hipStream_t s)
 {
+    const int EPB = kStepBlock / a.P;
+    const size_t lds = sizeof(double) * ((size_t)a.P * a.P + 3 * (size_t)EPB * a.P);
     {
         ProfScope ps_(K_TRPMD, s);
-        hipLaunchKernelGGL(k_trpmd<P>, dim3(div_up(3 * a.N, 256)), dim3(256), 0, s, a, cst);
+        hipLaunchKernelGGL(k_trpmd, dim3(div_up(3 * a.N, EPB)), dim3(kStepBlock), lds, s, a, cst);
     }
 }
 
@@ -282,10 +302,6 @@ extern "C" int32_t pimd_create(int32_t P, int32_t N, const pimd_params *prm, con
         h[Lo.cq + k] = (1.0 - hh * hh) / den;
         h[Lo.qv + k] = prm->dt_fs / den;
         h[Lo.vq + k] = wk * wk * prm->dt_fs / den;
-        for (int b = 0; b < P; ++b) {
-            h[Lo.CFpost + b * P + k] = h[Lo.C + b * P + k] * c1;
-            h[Lo.CFfused + b * P + k] = h[Lo.C + b * P + k] * (c1 * c1 + 1.0);
-        }
     }
     c->hC.assign(h.begin(), h.begin() + P * P);
     hipError_t e = hipGetDevice(&c->device);
@@ -327,8 +343,8 @@ extern "C" int32_t rp_normal_modes(const pimd_ctx *c, int32_t dir, const double 
     return NEP_OK;
 }
 
-extern "C" int32_t trpmd_step(const pimd_ctx *c, double *pos, double *vel, const float *F, int64_t step, int32_t stage,
-                              hipStream_t s)
+static int32_t step_common(const pimd_ctx *c, double *pos, double *vel, const float *F, int64_t step,
+                           int64_t *step_dev, int32_t stage, hipStream_t s)
 {
     if (!c) return fail(NEP_ERR_INVALID_ARG, "trpmd_step: null context");
     if (stage < PIMD_STAGE_PRE || stage > PIMD_STAGE_FUSED) return fail(NEP_ERR_INVALID_ARG, "trpmd_step: bad stage");
@@ -336,20 +352,31 @@ extern "C" int32_t trpmd_step(const pimd_ctx *c, double *pos, double *vel, const
     if (c->N == 0) return NEP_OK;
     if (!pos || !vel || !F) return fail(NEP_ERR_INVALID_ARG, "trpmd_step: null array");
     StepArgs a;
-    a.pos = pos; a.vel = vel; a.F = F; a.mass = c->mass; a.N = c->N;
+    a.pos = pos; a.vel = vel; a.F = F; a.mass = c->mass; a.N = c->N; a.P = c->P;
     a.dt = c->prm.dt_fs;
     a.kTP = c->P * kKB * c->prm.T_K;
     a.conv = amu_a2_fs2_ev();
     a.seed = c->prm.seed;
     a.step = step;
+    a.step_dev = step_dev;
     a.stage = stage;
     a.noise = c->prm.mode != PIMD_MODE_RPMD && !(c->prm.mode == PIMD_MODE_TRPMD && c->P == 1);
-    switch (c->P) {
-#define X(p) case p: launch_step<p>(a, c->consts, s); break;
-        NEP_P_CASES(X)
-#undef X
-    default: return fail(NEP_ERR_UNSUPPORTED, "trpmd_step: P=%d", c->P);
-    }
+    if (c->P < 1 || c->P > kMaxBeads) return fail(NEP_ERR_UNSUPPORTED, "trpmd_step: P=%d", c->P);
+    launch_step(a, c->consts, s);
+    if (step_dev && stage != PIMD_STAGE_PRE) hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(1), 0, s, step_dev);
     NEP_HIP(hipGetLastError());
     return NEP_OK;
+}
+
+extern "C" int32_t trpmd_step(const pimd_ctx *c, double *pos, double *vel, const float *F, int64_t step, int32_t stage,
+                              hipStream_t s)
+{
+    return step_common(c, pos, vel, F, step, nullptr, stage, s);
+}
+
+extern "C" int32_t trpmd_step_dev(const pimd_ctx *c, double *pos, double *vel, const float *F, int64_t *step,
+                                  int32_t stage, hipStream_t s)
+{
+    if (!step) return fail(NEP_ERR_INVALID_ARG, "trpmd_step_dev: null step counter");
+    return step_common(c, pos, vel, F, 0, step, stage, s);
 }

@@ -57,6 +57,8 @@ class NepPimd:
         self.check_every = check_every
         self.step_no = 0
         self.started = False
+        self.graph = None
+        self.step_dev = None
         self._fit_capacity()
 
     # ------------------------------------------------------------------
@@ -90,10 +92,13 @@ class NepPimd:
 
     def step(self):
         """One full step: forces at the advanced positions, then POST(n) + PRE(n+1)."""
-        if not self.started:
-            self.start()
-        self.forces()
-        self.pimd.step(self.pos, self.vel, self.F, self.step_no, lib.FUSED)
+        if self.graph is not None:
+            self.graph.replay()
+        else:
+            if not self.started:
+                self.start()
+            self.forces()
+            self.pimd.step(self.pos, self.vel, self.F, self.step_no, lib.FUSED)
         self.step_no += 1
         if self.check_every and self.step_no % self.check_every == 0:
             self.check()
@@ -102,8 +107,35 @@ class NepPimd:
         for _ in range(n):
             self.step()
 
+    def capture(self):
+        """Capture one full step (lists, forces, fused integrator stage) as a HIP graph.
+
+        The step number then lives in a device counter advanced by the graph
+        itself, so every replay draws fresh noise.  The box and the species
+        must stay fixed while the graph is in use; `release()` returns to
+        eager launches."""
+        t = self.torch
+        if not self.started:
+            self.start()
+        # one eager step first so that every lazy allocation has happened
+        self.step()
+        self.step_dev = t.tensor([self.step_no], dtype=t.int64, device=self.pos.device)
+        t.cuda.synchronize()
+        g = t.cuda.CUDAGraph()
+        with t.cuda.graph(g):
+            self.nl.build(self.pos, self.box, self.types)
+            self.ws.compute(self.nl, self.pos, self.box, self.types, self.E, self.F, self.W, self.E_atom, self.W_atom)
+            self.pimd.step_dev(self.pos, self.vel, self.F, self.step_dev, lib.FUSED)
+        t.cuda.synchronize()
+        # capture does not execute: the counter and the state are unchanged
+        self.graph = g
+
+    def release(self):
+        self.graph = None
+
     def finish(self):
         """Close the current step (forces + POST), leaving synchronised q and v."""
+        self.graph = None
         if not self.started:
             self.start()
         self.forces()

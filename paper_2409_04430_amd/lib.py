@@ -81,6 +81,7 @@ _sig = {
     "pimd_destroy": (None, [_vp]),
     "rp_normal_modes": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "trpmd_step": (_i32, [_vp, _vp, _vp, _vp, C.c_int64, _i32, _vp]),
+    "trpmd_step_dev": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "nep_nlist_set_skin": (_i32, [_vp, C.c_double]),
     "nep_nlist_invalidate": (_i32, [_vp]),
     "nep_profile_enable": (_i32, [_i32]),
@@ -326,6 +327,14 @@ class Pimd:
         shp = (self.P, self.N, 3)
         _check(_lib.trpmd_step(self._h, _ptr(pos, t.float64, shp, "pos"), _ptr(vel, t.float64, shp, "vel"),
                                _ptr(F, t.float32, shp, "F"), int(step), int(stage), _stream()))
+
+    def step_dev(self, pos, vel, F, step, stage: int):
+        """trpmd_step with the step number in a device int64 tensor (advanced after POST/FUSED)."""
+        t = _torch()
+        shp = (self.P, self.N, 3)
+        _check(_lib.trpmd_step_dev(self._h, _ptr(pos, t.float64, shp, "pos"), _ptr(vel, t.float64, shp, "vel"),
+                                   _ptr(F, t.float32, shp, "F"), _ptr(step, t.int64, (1,), "step"), int(stage),
+                                   _stream()))
 
     def __del__(self):
         h = getattr(self, "_h", None)
