@@ -166,7 +166,7 @@ def main():
     eng = NepPimd(model_path, s, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=0)
     eng.run(args.warmup)
     eng.check()
-    lst = eng.nl.to_host()
+    lst = eng.nl.to_host(eng.pos, eng.box, eng.caps[0], eng.caps[1])
     nR = float(lst["cnt_radial"].mean())
     nA = float(lst["cnt_angular"].mean())
     hp = eng.model.hp

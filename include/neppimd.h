@@ -115,86 +115,114 @@ void nep_model_destroy(nep_model *model);
 /* Neighbour lists (per bead, minimum image, cell list)                */
 /* ------------------------------------------------------------------ */
 
-/* Create neighbour sets for P beads of N atoms on the current device.
- * cap_candidates bounds the candidate row of one atom (all species, radius
- * rc_radial + 2 D; see neighbor_build), at most 8192; cap_radial and
- * cap_angular bound the per-bead neighbour counts of one atom, with
- * cap_angular <= cap_radial <= cap_candidates.  The handle also holds the
- * angular pair buffer that nep_compute fills (4 P N cap_candidates floats)
- * and N <= 2^28.  Errors: NEP_ERR_INVALID_ARG, NEP_ERR_NOMEM. */
-int32_t nep_nlist_create(const nep_model *model, int32_t P, int32_t N, int32_t cap_candidates,
-                         int32_t cap_radial, int32_t cap_angular, nep_nlist **out);
+/* Create neighbour sets for P <= 64 beads of N <= 2^28 atoms on the
+ * current device.  cap_radial and cap_angular bound the candidate rows of
+ * one atom (all species, radius rc + 2 D + skin; see neighbor_build), at
+ * most 8192 each.  The handle also holds the angular pair buffer that
+ * nep_compute fills (4 N cap_angular P floats).
+ * Errors: NEP_ERR_INVALID_ARG, NEP_ERR_NOMEM. */
+int32_t nep_nlist_create(const nep_model *model, int32_t P, int32_t N, int32_t cap_radial, int32_t cap_angular,
+                         nep_nlist **out);
 void nep_nlist_destroy(nep_nlist *nl);
 
-/* Build, for every bead b and atom i, the set of atoms i' != i with
- * |mic(r_i' - r_i)|^2 < rc^2, for the radial and the angular cutoff.  The
- * minimum image of d = r_i' - r_i is d - L rint(d / L) per axis and the test
- * is (dx*dx + dy*dy) + dz*dz < rc*rc, all in IEEE FP64 without contraction,
- * so the sets are exactly those of a brute-force search (Sec. II.A: periodic
- * boundary conditions).  Candidates come from one cell-list search over the
- * ring-polymer centroids with radius rc_radial + 2 D (rc_angular <=
- * rc_radial), D the largest bead-to-centroid distance measured on the
- * device in the same call; every bead pair closer than rc has centroids
- * closer than rc + 2 D, so testing the candidates bead by bead loses
- * nothing.  Positions must keep the P beads of an atom in one periodic image
- * (unwrapped ring polymers).  pos [P][N][3] dev, types [N] dev, box host[9].
- * Errors: NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED (non-orthorhombic box),
- * NEP_ERR_BOX_TOO_SMALL (an edge < 2 rc_radial), NEP_ERR_HIP, NEP_ERR_NOMEM.
- * A row or list longer than its capacity sets NEP_FLAG_NEIGHBOR_OVERFLOW
- * (it is then truncated and the results of nep_compute are not valid). */
+/* Batches of independent periodic systems (uneven sizes) share one handle:
+ * atoms [offsets[s], offsets[s+1]) form system s (offsets host [nsys+1],
+ * starting at 0, non-decreasing, nsys <= 4096), all with the same P beads
+ * and model.  Arrays are concatenated along the atom axis; boxes are host
+ * [nsys][9].  Every kernel of a call covers all systems at once: the
+ * neighbour kernels look up each atom's system, and the force kernels take
+ * tiles (an atom range of one system) so that per-system sums need no
+ * atomics.  The single-system calls are the case nsys = 1.  A box change
+ * re-uploads the geometry with a synchronous copy (not capturable).
+ * Errors as the single-system calls. */
+int32_t nep_nlist_create_batched(const nep_model *model, int32_t P, int32_t nsys, const int32_t *offsets,
+                                 int32_t cap_radial, int32_t cap_angular, nep_nlist **out);
+int32_t neighbor_build_batched(const nep_model *model, nep_nlist *nl, const double *pos, const double *boxes,
+                               const int32_t *types, int32_t P, int32_t N, hipStream_t stream);
+
+/* Neighbour sets for every bead b and atom i: the atoms i' != i with
+ * |mic(r_i' - r_i)|^2 < rc^2, for the radial and the angular cutoff (Sec.
+ * II.A: periodic boundary conditions).  The minimum image of d = r_i' - r_i
+ * is d - L rint(d / L) per axis and the test is (dx*dx + dy*dy) + dz*dz <
+ * rc*rc in IEEE FP64 without contraction, so the sets are exactly those of
+ * a brute-force search; the force path takes the same decision on packed
+ * FP32 pair vectors and falls back to the FP64 test near the cutoff.
+ * This call builds what the sets are drawn from: per atom, candidate rows
+ * shared by all beads from one cell-list search over the ring-polymer
+ * centroids (radius rc + 2 D [+ skin], D the largest bead-to-centroid
+ * distance measured on the device in the same call; every bead pair closer
+ * than rc has centroids closer than rc + 2 D), sorted by (species, index),
+ * and per call the "union" lists: the candidates inside the cutoff for at
+ * least one bead.  Positions must keep the P beads of an atom in one
+ * periodic image (unwrapped ring polymers).  pos [P][N][3] dev, types [N]
+ * dev, box host[9].  Errors: NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED
+ * (non-orthorhombic box), NEP_ERR_BOX_TOO_SMALL (an edge < 2 rc_radial, or
+ * too close to it for the packed positions: L/2 - rc must exceed 2 L/1023),
+ * NEP_ERR_HIP, NEP_ERR_NOMEM.  A candidate row longer than its capacity
+ * sets NEP_FLAG_NEIGHBOR_OVERFLOW (the row is then truncated and the
+ * results of nep_compute are not valid). */
 int32_t neighbor_build(const nep_model *model, nep_nlist *nl, const double *pos, const double box[9],
                        const int32_t *types, int32_t P, int32_t N, hipStream_t stream);
 
 /* Reuse of the candidate rows (a Verlet skin on the centroid search): with
- * skin > 0 the rows are built with radius rc_radial + 2 D + skin and kept
- * while 2 (D - D_build) + 2 max_i |c_i - c_i,build| <= skin, which keeps
- * them a superset of every bead pair within the cutoffs (triangle
- * inequality); the decision is taken on the device, without a host round
- * trip, and the per-bead lists stay exact.  A changed box rebuilds.  The
- * species of the atoms must not change between calls on one handle unless
- * nep_nlist_invalidate is called.  skin = 0 (the default) rebuilds on every
- * call.  Errors: NEP_ERR_INVALID_ARG (skin outside [0, 10] A). */
+ * skin > 0 the rows are built with radius rc + 2 D + skin and kept while
+ * 2 (D - D_build) + 2 max_i |c_i - c_i,build| <= skin, which keeps them a
+ * superset of every bead pair within the cutoffs (triangle inequality); the
+ * decision is taken on the device, without a host round trip.  A changed
+ * box rebuilds.  The species of the atoms must not change between calls on
+ * one handle unless nep_nlist_invalidate is called.  skin = 0 (the default)
+ * rebuilds on every call.  Errors: NEP_ERR_INVALID_ARG (skin outside
+ * [0, 10] A). */
 int32_t nep_nlist_set_skin(nep_nlist *nl, double skin);
 
 /* Force a candidate-row rebuild on the next neighbor_build. */
 int32_t nep_nlist_invalidate(nep_nlist *nl);
 
-/* Device layout of the neighbour sets (pointers stay owned by the handle).
- * Per atom i, shared by all beads:
- *   cand [N][cap_candidates] int32: candidates, entry (j << 2) | species(j),
- *       sorted by (species, j);
- *   cand_off [N][5] int32: species block starts; entry [n_species] is the
- *       row length;
- *   cand_rev [N][cap_candidates] int32: for slot k of atom i holding j, the
- *       slot of i in j's row (-1 only if j's row overflowed).
- * Per bead b, slot-major:
- *   nbr_radial [P][cap_radial][N] int32: the s-th radial neighbour j of i
- *       in bead b, in row order (species blocks, ascending j);
- *   end_radial [P][4][N] int32: end of species block t of i's list
- *       (entry n_species - 1 is the count);
- *   nbr_angular, end_angular: the same for the angular cutoff;
- *   slot_angular [P][cap_angular][N] int32: for each angular entry, its
- *       candidate slot k (low 16 bits) and the reverse slot cand_rev[i][k]
- *       (high 16 bits, 0xffff if absent).
- * Entries past a list's count are not written. */
+/* Device layout (pointers stay owned by the handle), per atom i:
+ *   cand_radial [N][cap_radial] int32: candidates, entry (j << 2) |
+ *       species(j), sorted by (species, j);
+ *   cand_radial_off [N][5] int32: species block starts, [n_species] = length;
+ *   cand_angular, cand_angular_off: the same for the angular radius;
+ *   cand_angular_rev [N][cap_angular] int32: for slot k of atom i holding
+ *       j, the slot of i in j's angular row (-1 only if j's row overflowed);
+ *   union_radial [N][cap_radial] int32: the candidates j (row order) that
+ *       are inside rc_radial for at least one bead of the last build;
+ *   union_radial_end [N][4] int32: end of species block t in that list;
+ *   union_angular, union_angular_end: the same for the angular cutoff,
+ *       holding slots k of the angular row instead of atom indices.
+ * Entries past a row's length are not written. */
 typedef struct nep_nlist_layout {
-    int32_t P, N, n_species, cap_candidates, cap_radial, cap_angular;
-    const int32_t *cand;
-    const int32_t *cand_off;
-    const int32_t *cand_rev;
-    const int32_t *nbr_radial;
-    const int32_t *end_radial;
-    const int32_t *nbr_angular;
-    const int32_t *end_angular;
-    const int32_t *slot_angular;
+    int32_t P, N, n_species, cap_radial, cap_angular;
+    const int32_t *cand_radial;
+    const int32_t *cand_radial_off;
+    const int32_t *cand_angular;
+    const int32_t *cand_angular_off;
+    const int32_t *cand_angular_rev;
+    const int32_t *union_radial;
+    const int32_t *union_radial_end;
+    const int32_t *union_angular;
+    const int32_t *union_angular_end;
 } nep_nlist_layout;
 int32_t nep_nlist_view(const nep_nlist *nl, nep_nlist_layout *out);
 
+/* Write the per-bead neighbour lists of the positions of the last
+ * neighbor_build (for tests and analysis; the force path does not need
+ * them; boxes host [nsys][9] as given to that build): for bead b and atom
+ * i the neighbours in (species, index) order at
+ * nbr_radial[b][s][i] (s < min(count, cap_radial)) and their count at
+ * cnt_radial[b][i] (the full count, which may exceed cap_radial); the same
+ * for the angular cutoff.  pos [P][N][3] dev must be the positions of that
+ * build.  All outputs dev int32.  Errors: NEP_ERR_INVALID_ARG. */
+int32_t nep_nlist_materialize(const nep_model *model, const nep_nlist *nl, const double *pos, const double *boxes,
+                              int32_t P, int32_t N, int32_t cap_radial, int32_t cap_angular, int32_t *nbr_radial,
+                              int32_t *cnt_radial, int32_t *nbr_angular, int32_t *cnt_angular, hipStream_t stream);
+
 typedef struct nep_nlist_status {
     uint32_t flags;            /* nep_flag_bits seen by neighbor_build */
-    int32_t max_radial;        /* largest radial neighbour count of an atom in a bead */
-    int32_t max_angular;       /* largest angular neighbour count */
-    int32_t max_candidates;    /* longest candidate row */
+    int32_t max_union_radial;  /* longest radial union list of an atom */
+    int32_t max_union_angular; /* longest angular union list */
+    int32_t max_cand_radial;   /* longest radial candidate row (rebuild calls) */
+    int32_t max_cand_angular;  /* longest angular candidate row (rebuild calls) */
     float bead_spread;         /* largest distance of a bead from its centroid, A */
     int32_t rebuilds;          /* candidate-row rebuilds since the last clear */
 } nep_nlist_status;
@@ -211,6 +239,9 @@ int32_t nep_nlist_poll(nep_nlist *nl, nep_nlist_status *out, int32_t clear, hipS
 /* Workspace for P beads of N atoms (descriptor adjoints, partial sums,
  * flags) on the current device. */
 int32_t nep_ws_create(const nep_model *model, int32_t P, int32_t N, nep_ws **out);
+/* Workspace for a batch (see nep_nlist_create_batched); the partition must
+ * equal the list's. */
+int32_t nep_ws_create_batched(const nep_model *model, int32_t P, int32_t nsys, const int32_t *offsets, nep_ws **out);
 void nep_ws_destroy(nep_ws *ws);
 
 /* NEP energy, forces and virial of every bead (Sec. II.C site energies,
@@ -232,6 +263,28 @@ void nep_ws_destroy(nep_ws *ws);
 int32_t nep_compute(const nep_model *model, nep_nlist *nl, nep_ws *ws, const double *pos,
                     const double box[9], const int32_t *types, int32_t P, int32_t N, double *E, float *F,
                     double *W, float *E_atom, float *W_atom, hipStream_t stream);
+
+/* nep_compute over a batch: boxes host [nsys][9], E [nsys][P] and W
+ * [nsys][P][9] per system and bead, the other arrays concatenated along
+ * the atom axis. */
+int32_t nep_compute_batched(const nep_model *model, nep_nlist *nl, nep_ws *ws, const double *pos,
+                            const double *boxes, const int32_t *types, int32_t P, int32_t N, double *E, float *F,
+                            double *W, float *E_atom, float *W_atom, hipStream_t stream);
+
+/* Tile shape of the force kernels: 1, 2 or 4 wavefronts per workgroup, each
+ * wavefront holding 64 / G atoms with their G >= P beads (default 4).  The
+ * tile table is re-uploaded synchronously.  Errors: NEP_ERR_INVALID_ARG. */
+int32_t nep_ws_set_tile(nep_ws *ws, int32_t waves_per_group);
+int32_t nep_ws_get_tile(const nep_ws *ws, int32_t *waves_per_group);
+
+/* Autotuner: times nep_compute_batched (one warm-up plus `reps` calls, HIP
+ * events on `stream`) for every tile shape, keeps the fastest in the
+ * workspace and reports it in *best (host), with the mean times in ms_out[3]
+ * (host, for 1, 2 and 4 wavefronts; may be NULL).  E, F, W are overwritten.
+ * Synchronises the stream.  Errors as nep_compute_batched. */
+int32_t nep_autotune(const nep_model *model, nep_nlist *nl, nep_ws *ws, const double *pos, const double *boxes,
+                     const int32_t *types, int32_t P, int32_t N, double *E, float *F, double *W, int32_t reps,
+                     float *ms_out, int32_t *best, hipStream_t stream);
 
 /* Synchronise `stream`, read the workspace flags into *flags and, if
  * clear != 0, reset them.  Returns NEP_ERR_NONFINITE if that bit is set. */
@@ -289,6 +342,55 @@ int32_t trpmd_step(const pimd_ctx *ctx, double *pos, double *vel, const float *F
  * noise.  Errors as trpmd_step, and NEP_ERR_INVALID_ARG for a null counter. */
 int32_t trpmd_step_dev(const pimd_ctx *ctx, double *pos, double *vel, const float *F, int64_t *step,
                        int32_t stage, hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Training (gradient of an energy / force / virial loss, Adam)        */
+/* ------------------------------------------------------------------ */
+
+/* Offsets (in floats) of the parameter blocks inside a model's device
+ * parameter array: c_radial [S][S][n_R+1][9], c_angular [S][S][n_A+1][9],
+ * q_scale [D], W0 [S][H][D], b0 [S][H], w1 [S][H], b1 [1], then the 24
+ * spherical-harmonic constants (not parameters). */
+typedef struct nep_param_offsets {
+    int32_t c_radial, c_angular, q_scale, W0, b0, w1, b1, sh;
+} nep_param_offsets;
+
+/* Device parameter array of a model (owned by the model; the NEP kernels
+ * read it, so writing it changes the model), its length and block offsets.
+ * Errors: NEP_ERR_INVALID_ARG. */
+int32_t nep_model_params(nep_model *model, float **params, int32_t *count, nep_param_offsets *offsets);
+
+typedef struct nep_train_ws nep_train_ws;
+
+/* Training workspace for P configurations of N atoms (the beads of a
+ * neighbour handle of one system).  Models with the four-body term are not
+ * trainable (NEP_ERR_UNSUPPORTED).  Errors: NEP_ERR_INVALID_ARG,
+ * NEP_ERR_UNSUPPORTED, NEP_ERR_NOMEM. */
+int32_t nep_train_ws_create(const nep_model *model, int32_t P, int32_t N, nep_train_ws **out);
+void nep_train_ws_destroy(nep_train_ws *tw);
+
+/* Loss and parameter gradient for the P configurations pos [P][N][3] (the
+ * lists nl must have been built at pos) with references E_ref [P] (eV),
+ * F_ref [P][N][3] (eV/A), W_ref [P][9] (eV), all device:
+ *   L = sum_b lE (dE_b/N)^2 + lF sum_i |dF_bi|^2 / (3N) + lW sum_ab (dW_b,ab/N)^2
+ * with lambda = {lE, lF, lW} (host).  grad [count] (device, the model's
+ * parameter layout) is accumulated: += dL/dtheta for W0, b0, w1, b1 and
+ * c_radial (other entries untouched); loss [4] (device) is accumulated:
+ * total, energy, force and virial parts.  The force and virial parts enter
+ * as mixed derivatives through a forward-mode pass of the descriptor along
+ * the residual field.  Errors as nep_compute. */
+int32_t nep_param_grad(const nep_model *model, nep_nlist *nl, nep_ws *ws, nep_train_ws *tw, const double *pos,
+                       const double box[9], const int32_t *types, int32_t P, int32_t N, const double *E_ref,
+                       const float *F_ref, const double *W_ref, const double lambda[3], float *grad, double *loss,
+                       hipStream_t stream);
+
+/* One Adam step (Kingma and Ba, with bias correction) on the model's
+ * parameters: theta -= lr mhat / (sqrt(vhat) + eps), for the parameter
+ * groups in mask (1: network W0, b0, w1, b1; 2: c_radial; 3: both).  m1, m2
+ * [count] device moment arrays (zero before step 1), step >= 1.  Errors:
+ * NEP_ERR_INVALID_ARG. */
+int32_t nep_adam_step(nep_model *model, nep_train_ws *tw, const float *grad, float *m1, float *m2, int64_t step,
+                      float lr, float beta1, float beta2, float eps, int32_t mask, hipStream_t stream);
 
 /* ------------------------------------------------------------------ */
 /* Kernel timing                                                       */

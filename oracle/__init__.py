@@ -230,3 +230,19 @@ def trpmd_stage(pos, vel, F, mass, *, dt, T, tau, mode, seed, step, stage):
                               _d(pos), _d(vel), _d(F), int(step), int(stage))
     if rc:
         raise ValueError("oracle: bad trpmd_stage arguments")
+
+
+def train_loss(out: dict, ref: dict, lambdas, N: int):
+    """Training loss of a set of configurations (a bead batch), in FP64:
+
+        L = sum_b lE (dE_b/N)^2 + lF sum_i |dF_bi|^2 / (3N) + lW sum_ab (dW_b,ab/N)^2
+
+    out / ref: dicts with E [P], F [P,N,3], W [P,3,3] (the model's and the
+    reference values).  Returns (L, [L_E, L_F, L_W])."""
+    lE, lF, lW = (float(x) for x in lambdas)
+    dE = np.asarray(out["E"], np.float64) - np.asarray(ref["E"], np.float64)
+    dF = np.asarray(out["F"], np.float64) - np.asarray(ref["F"], np.float64)
+    dW = np.asarray(out["W"], np.float64).reshape(-1, 9) - np.asarray(ref["W"], np.float64).reshape(-1, 9)
+    parts = [lE * float(np.sum((dE / N) ** 2)), lF * float(np.sum(dF ** 2)) / (3.0 * N),
+             lW * float(np.sum((dW / N) ** 2))]
+    return sum(parts), parts

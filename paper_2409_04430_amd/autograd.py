@@ -44,8 +44,8 @@ class NepCalculator:
         dens = self.N / float(np.prod(self.box))
         rc = self.model.rc_radial
         n = dens * 4.0 / 3.0 * np.pi
-        caps = (int(n * (rc + 0.5) ** 3 * 1.6) + 8, int(n * rc ** 3 * 1.6) + 8,
-                int(n * self.model.rc_angular ** 3 * 1.6) + 8)
+        caps = (int(n * (rc + 0.5 + self.skin) ** 3 * 1.6) + 8,
+                int(n * (self.model.rc_angular + 0.5 + self.skin) ** 3 * 1.6) + 8)
         self.nl = lib.fitted_neighbor_list(self.model, p, self.box, self.types, *caps, skin=self.skin)
 
     def evaluate(self, pos, want_virial: bool = False):

@@ -54,11 +54,16 @@ FineGrid fine_grid(const double L[3], double rc)
 }
 
 // Per axis: fine cell c = floor(x / h) mod M and offset x - floor(x / h) h
-// (unwrapped coordinates allowed); non-finite input gives a NaN offset.
-__global__ void k_pack(const double *__restrict__ pos, size_t n, FineGrid g, float4 *__restrict__ out)
+// (unwrapped coordinates allowed) on the fine grid of the atom's system;
+// non-finite input gives a NaN offset.  Reads pos [P][N][3], writes out
+// [N][P] (bead-minor).
+__global__ void k_pack(const double *__restrict__ pos, int P, int N, const int32_t *__restrict__ atom_sys,
+                       const SysGeom *__restrict__ geom, float4 *__restrict__ out)
 {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
+    if (e >= (size_t)P * N) return;
+    const int b = (int)(e / (size_t)N), i = (int)(e - (size_t)b * N);
+    const SysGeom &g = geom[atom_sys[i]];
     float o[3];
     int bits = 0;
     bool fin = true;
@@ -74,21 +79,24 @@ __global__ void k_pack(const double *__restrict__ pos, size_t n, FineGrid g, flo
         bits |= ci << (10 * d);
     }
     if (!fin) o[0] = __int_as_float(0x7fc00000);
-    out[e] = make_float4(o[0], o[1], o[2], __int_as_float(bits));
+    out[(size_t)i * P + b] = make_float4(o[0], o[1], o[2], __int_as_float(bits));
 }
 
-void pack_positions(const double *pos, size_t n, const FineGrid &g, float4 *out, hipStream_t s)
+void pack_positions(const double *pos, int P, int N, const int32_t *atom_sys, const SysGeom *geom, float4 *out,
+                    hipStream_t s)
 {
+    const size_t n = (size_t)P * N;
     if (n == 0) return;
     ProfScope ps_(K_PACK, s);
-    hipLaunchKernelGGL(k_pack, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pos, n, g, out);
+    hipLaunchKernelGGL(k_pack, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pos, P, N, atom_sys,
+                       geom, out);
 }
 
 // ---------------------------------------------------------- profiling ---
 
 static const char *kKernelNames[K_NUM] = {"fill", "pack", "centroid", "grid", "cell_count", "cell_scan", "cell_fill",
                                           "cell_sort", "candidates", "sort_rows", "reverse", "nlist",
-                                          "descriptor", "force_ang", "force", "reduce", "trpmd", "modes"};
+                                          "materialize", "descriptor", "force_ang", "force", "reduce", "trpmd", "modes"};
 static std::atomic<int> g_prof_on{0};
 static std::atomic<int> g_prof_only{-1};   // -1: every kind
 static std::mutex g_prof_mu;
@@ -392,44 +400,68 @@ static hipError_t dalloc(T **p, size_t n)
     return hipMalloc((void **)p, sizeof(T) * (n ? n : 1));
 }
 
-extern "C" int32_t nep_nlist_create(const nep_model *m, int32_t P, int32_t N, int32_t capC, int32_t capR,
-                                    int32_t capA, nep_nlist **out)
+// Validates a batch partition: offsets [nsys+1], non-decreasing from 0.
+static int32_t check_offsets(int32_t nsys, const int32_t *off, const char *who)
+{
+    if (nsys < 1 || nsys > 4096 || !off) return fail(NEP_ERR_INVALID_ARG, "%s: bad system count %d", who, nsys);
+    if (off[0] != 0) return fail(NEP_ERR_INVALID_ARG, "%s: offsets must start at 0", who);
+    for (int s = 0; s < nsys; ++s)
+        if (off[s + 1] < off[s]) return fail(NEP_ERR_INVALID_ARG, "%s: offsets must not decrease", who);
+    if (off[nsys] > (1 << 28)) return fail(NEP_ERR_INVALID_ARG, "%s: too many atoms", who);
+    return NEP_OK;
+}
+
+extern "C" int32_t nep_nlist_create_batched(const nep_model *m, int32_t P, int32_t nsys, const int32_t *off,
+                                            int32_t capR, int32_t capA, nep_nlist **out)
 {
     if (!m || !out) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_create: null argument");
-    if (P < 0 || N < 0 || capC < 1 || capR < 1 || capA < 1 || capC > 8192 || capR > capC || capA > capR ||
-        N > (1 << 28))
-        return fail(NEP_ERR_INVALID_ARG, "nep_nlist_create: bad sizes P=%d N=%d caps=%d/%d/%d", P, N, capC, capR,
-                    capA);
+    const int32_t rc0 = check_offsets(nsys, off, "nep_nlist_create");
+    if (rc0 != NEP_OK) return rc0;
+    const int32_t N = off[nsys];
+    if (P < 0 || P > kMaxBeads || capR < 1 || capA < 1 || capR > 8192 || capA > 8192)
+        return fail(NEP_ERR_INVALID_ARG, "nep_nlist_create: bad sizes P=%d N=%d caps=%d/%d", P, N, capR, capA);
     *out = nullptr;
     nep_nlist *nl = new (std::nothrow) nep_nlist;
     if (!nl) return fail(NEP_ERR_NOMEM, "host allocation failed");
     nl->P = P; nl->N = N; nl->S = m->hp.n_species;
-    nl->capC = capC; nl->capR = capR; nl->capA = capA;
+    nl->capR = capR; nl->capA = capA;
+    nl->nsys = nsys;
+    nl->off.assign(off, off + nsys + 1);
+    nl->boxL.assign(3 * (size_t)nsys, 0.0);
+    std::vector<int32_t> asys((size_t)N);
+    for (int s = 0; s < nsys; ++s)
+        for (int i = off[s]; i < off[s + 1]; ++i) asys[i] = s;
     const size_t Nn = (size_t)N, PN = (size_t)P * N;
     hipError_t e = hipGetDevice(&nl->device);
+    if (e == hipSuccess) e = dalloc(&nl->geom, (size_t)nsys);
+    if (e == hipSuccess) e = dalloc(&nl->atom_sys, Nn);
+    if (e == hipSuccess && Nn) e = hipMemcpy(nl->atom_sys, asys.data(), sizeof(int32_t) * Nn, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = dalloc(&nl->cen, Nn * 3);
     if (e == hipSuccess) e = dalloc(&nl->cen_ref, Nn * 3);
-    if (e == hipSuccess) e = dalloc(&nl->cand, Nn * capC);
-    if (e == hipSuccess) e = dalloc(&nl->rowlen, Nn);
-    if (e == hipSuccess) e = dalloc(&nl->offC, Nn * (kMaxSpecies + 1));
-    if (e == hipSuccess) e = dalloc(&nl->revC, Nn * capC);
-    if (e == hipSuccess) e = dalloc(&nl->listR, PN * capR);
-    if (e == hipSuccess) e = dalloc(&nl->endR, PN * kMaxSpecies);
-    if (e == hipSuccess) e = dalloc(&nl->listA, PN * capA);
-    if (e == hipSuccess) e = dalloc(&nl->endA, PN * kMaxSpecies);
-    if (e == hipSuccess) e = dalloc(&nl->slotA, PN * capA);
-    nl->WC = div_up(capC, 32);
-    if (e == hipSuccess) e = dalloc(&nl->maskA, PN * nl->WC);
+    if (e == hipSuccess) e = dalloc(&nl->candR, Nn * capR);
+    if (e == hipSuccess) e = dalloc(&nl->lenR, Nn);
+    if (e == hipSuccess) e = dalloc(&nl->offR, Nn * (kMaxSpecies + 1));
+    if (e == hipSuccess) e = dalloc(&nl->candA, Nn * capA);
+    if (e == hipSuccess) e = dalloc(&nl->lenA, Nn);
+    if (e == hipSuccess) e = dalloc(&nl->offA, Nn * (kMaxSpecies + 1));
+    if (e == hipSuccess) e = dalloc(&nl->revA, Nn * capA);
+    if (e == hipSuccess) e = dalloc(&nl->uniR, Nn * capR);
+    if (e == hipSuccess) e = dalloc(&nl->umR, Nn * capR);
+    if (e == hipSuccess) e = dalloc(&nl->umA, Nn * capA);
+    if (e == hipSuccess) e = dalloc(&nl->uendR, Nn * kMaxSpecies);
+    if (e == hipSuccess) e = dalloc(&nl->uniA, Nn * capA);
+    if (e == hipSuccess) e = dalloc(&nl->uendA, Nn * kMaxSpecies);
     if (e == hipSuccess) e = dalloc(&nl->pairbuf, 4 * PN * capA);
     if (e == hipSuccess) e = dalloc(&nl->pos4, 4 * PN);
     if (e == hipSuccess) e = dalloc(&nl->cell_atoms, Nn);
-    if (e == hipSuccess) e = dalloc(&nl->grid, 16);
+    if (e == hipSuccess) e = dalloc(&nl->grid, 16 + 4 * (size_t)nsys);
     if (e == hipSuccess) e = dalloc(&nl->status, 8);
     if (e == hipSuccess) e = hipMemset(nl->status, 0, 8 * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemset(nl->grid, 0, 16 * sizeof(uint32_t));
-    if (e == hipSuccess && Nn) e = hipMemset(nl->offC, 0, sizeof(int32_t) * Nn * (kMaxSpecies + 1));
-    if (e == hipSuccess && PN) e = hipMemset(nl->endR, 0, sizeof(int32_t) * PN * kMaxSpecies);
-    if (e == hipSuccess && PN) e = hipMemset(nl->endA, 0, sizeof(int32_t) * PN * kMaxSpecies);
+    if (e == hipSuccess) e = hipMemset(nl->grid, 0, (16 + 4 * (size_t)nsys) * sizeof(uint32_t));
+    if (e == hipSuccess && Nn) e = hipMemset(nl->offR, 0, sizeof(int32_t) * Nn * (kMaxSpecies + 1));
+    if (e == hipSuccess && Nn) e = hipMemset(nl->offA, 0, sizeof(int32_t) * Nn * (kMaxSpecies + 1));
+    if (e == hipSuccess && Nn) e = hipMemset(nl->uendR, 0, sizeof(int32_t) * Nn * kMaxSpecies);
+    if (e == hipSuccess && Nn) e = hipMemset(nl->uendA, 0, sizeof(int32_t) * Nn * kMaxSpecies);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         nep_nlist_destroy(nl);
@@ -440,13 +472,22 @@ extern "C" int32_t nep_nlist_create(const nep_model *m, int32_t P, int32_t N, in
     return NEP_OK;
 }
 
+extern "C" int32_t nep_nlist_create(const nep_model *m, int32_t P, int32_t N, int32_t capR, int32_t capA,
+                                    nep_nlist **out)
+{
+    if (N < 0) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_create: bad sizes P=%d N=%d", P, N);
+    const int32_t off[2] = {0, N};
+    return nep_nlist_create_batched(m, P, 1, off, capR, capA, out);
+}
+
 extern "C" void nep_nlist_destroy(nep_nlist *nl)
 {
     if (!nl) return;
-    for (void *p : {(void *)nl->cen, (void *)nl->cen_ref, (void *)nl->cand, (void *)nl->rowlen, (void *)nl->offC, (void *)nl->revC,
-                    (void *)nl->listR, (void *)nl->endR, (void *)nl->listA, (void *)nl->endA, (void *)nl->slotA,
-                    (void *)nl->maskA, (void *)nl->pairbuf, (void *)nl->pos4, (void *)nl->cell_cnt, (void *)nl->cell_start, (void *)nl->cell_atoms,
-                    (void *)nl->grid, (void *)nl->status})
+    for (void *p : {(void *)nl->geom, (void *)nl->atom_sys, (void *)nl->cell_sys, (void *)nl->cen, (void *)nl->cen_ref, (void *)nl->candR, (void *)nl->lenR, (void *)nl->offR,
+                    (void *)nl->candA, (void *)nl->lenA, (void *)nl->offA, (void *)nl->revA, (void *)nl->uniR,
+                    (void *)nl->umR, (void *)nl->umA, (void *)nl->uendR, (void *)nl->uniA, (void *)nl->uendA, (void *)nl->pairbuf, (void *)nl->pos4,
+                    (void *)nl->cell_cnt, (void *)nl->cell_start, (void *)nl->cell_atoms, (void *)nl->grid,
+                    (void *)nl->status})
         if (p) (void)hipFree(p);
     delete nl;
 }
@@ -455,10 +496,11 @@ extern "C" int32_t nep_nlist_view(const nep_nlist *nl, nep_nlist_layout *out)
 {
     if (!nl || !out) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_view: null argument");
     out->P = nl->P; out->N = nl->N; out->n_species = nl->S;
-    out->cap_candidates = nl->capC; out->cap_radial = nl->capR; out->cap_angular = nl->capA;
-    out->cand = nl->cand; out->cand_off = nl->offC; out->cand_rev = nl->revC;
-    out->nbr_radial = nl->listR; out->end_radial = nl->endR;
-    out->nbr_angular = nl->listA; out->end_angular = nl->endA; out->slot_angular = nl->slotA;
+    out->cap_radial = nl->capR; out->cap_angular = nl->capA;
+    out->cand_radial = nl->candR; out->cand_radial_off = nl->offR;
+    out->cand_angular = nl->candA; out->cand_angular_off = nl->offA; out->cand_angular_rev = nl->revA;
+    out->union_radial = nl->uniR; out->union_radial_end = nl->uendR;
+    out->union_angular = nl->uniA; out->union_angular_end = nl->uendA;
     return NEP_OK;
 }
 
@@ -469,9 +511,10 @@ extern "C" int32_t nep_nlist_poll(nep_nlist *nl, nep_nlist_status *out, int32_t 
     NEP_HIP(hipStreamSynchronize(s));
     NEP_HIP(hipMemcpy(h, nl->status, sizeof h, hipMemcpyDeviceToHost));
     out->flags = h[0];
-    out->max_radial = (int32_t)h[1];
-    out->max_angular = (int32_t)h[2];
-    out->max_candidates = (int32_t)h[3];
+    out->max_union_radial = (int32_t)h[1];
+    out->max_union_angular = (int32_t)h[2];
+    out->max_cand_radial = (int32_t)h[3];
+    out->max_cand_angular = (int32_t)h[6];
     float spread;
     std::memcpy(&spread, &h[4], sizeof spread);
     out->bead_spread = spread;
@@ -482,30 +525,87 @@ extern "C" int32_t nep_nlist_poll(nep_nlist *nl, nep_nlist_status *out, int32_t 
         NEP_HIP(hipStreamSynchronize(s));
     }
     if (h[0] & NEP_FLAG_NEIGHBOR_OVERFLOW)
-        return fail(NEP_ERR_NEIGHBOR_OVERFLOW, "list overflow (largest %u candidates, %u radial, %u angular; "
-                    "capacities %d/%d/%d)", h[3], h[1], h[2], nl->capC, nl->capR, nl->capA);
+        return fail(NEP_ERR_NEIGHBOR_OVERFLOW, "candidate overflow (longest rows %u/%u, capacities %d/%d)", h[3],
+                    h[6], nl->capR, nl->capA);
     return NEP_OK;
 }
 
 // ----------------------------------------------------------- workspace ---
 
-extern "C" int32_t nep_ws_create(const nep_model *m, int32_t P, int32_t N, nep_ws **out)
+// Tile table for `wpb` wavefronts per workgroup: each tile is up to
+// wpb * 64 / G atoms of one system (G lanes per atom).  Synchronous upload.
+static int32_t set_tiles(nep_ws *w, int wpb)
+{
+    const int apb = wpb * (64 >> lanes_log2(w->P > 0 ? w->P : 1));
+    std::vector<int32_t> t0, t1, ts, st(w->nsys + 1, 0);
+    for (int s = 0; s < w->nsys; ++s) {
+        st[s] = (int32_t)t0.size();
+        for (int a = w->off[s]; a < w->off[s + 1]; a += apb) {
+            t0.push_back(a);
+            t1.push_back(std::min(a + apb, w->off[s + 1]));
+            ts.push_back(s);
+        }
+    }
+    st[w->nsys] = (int32_t)t0.size();
+    if ((int)t0.size() > std::max(w->nblk_cap, 1)) return fail(NEP_ERR_INVALID_ARG, "tile table overflow");
+    NEP_HIP(hipDeviceSynchronize());
+    if (!t0.empty()) {
+        NEP_HIP(hipMemcpy(w->tile_atom0, t0.data(), sizeof(int32_t) * t0.size(), hipMemcpyHostToDevice));
+        NEP_HIP(hipMemcpy(w->tile_atom1, t1.data(), sizeof(int32_t) * t1.size(), hipMemcpyHostToDevice));
+        NEP_HIP(hipMemcpy(w->tile_sys, ts.data(), sizeof(int32_t) * ts.size(), hipMemcpyHostToDevice));
+    }
+    NEP_HIP(hipMemcpy(w->sys_tile0, st.data(), sizeof(int32_t) * st.size(), hipMemcpyHostToDevice));
+    w->nblk = (int)t0.size();
+    w->wpb = wpb;
+    return NEP_OK;
+}
+
+extern "C" int32_t nep_ws_set_tile(nep_ws *w, int32_t waves_per_group)
+{
+    if (!w) return fail(NEP_ERR_INVALID_ARG, "nep_ws_set_tile: null argument");
+    if (waves_per_group != 1 && waves_per_group != 2 && waves_per_group != 4)
+        return fail(NEP_ERR_INVALID_ARG, "nep_ws_set_tile: waves per workgroup must be 1, 2 or 4");
+    return set_tiles(w, waves_per_group);
+}
+
+extern "C" int32_t nep_ws_get_tile(const nep_ws *w, int32_t *waves_per_group)
+{
+    if (!w || !waves_per_group) return fail(NEP_ERR_INVALID_ARG, "nep_ws_get_tile: null argument");
+    *waves_per_group = w->wpb;
+    return NEP_OK;
+}
+
+extern "C" int32_t nep_ws_create_batched(const nep_model *m, int32_t P, int32_t nsys, const int32_t *off,
+                                         nep_ws **out)
 {
     if (!m || !out) return fail(NEP_ERR_INVALID_ARG, "nep_ws_create: null argument");
-    if (P < 0 || N < 0) return fail(NEP_ERR_INVALID_ARG, "nep_ws_create: bad sizes P=%d N=%d", P, N);
+    const int32_t rc0 = check_offsets(nsys, off, "nep_ws_create");
+    if (rc0 != NEP_OK) return rc0;
+    const int32_t N = off[nsys];
+    if (P < 0 || P > kMaxBeads) return fail(NEP_ERR_INVALID_ARG, "nep_ws_create: bad sizes P=%d N=%d", P, N);
     *out = nullptr;
     nep_ws *w = new (std::nothrow) nep_ws;
     if (!w) return fail(NEP_ERR_NOMEM, "host allocation failed");
     w->P = P; w->N = N; w->S = m->hp.n_species;
     w->NA1 = m->hp.n_max_angular + 1;
-    w->KRP = ((m->hp.basis_radial + 1) + 3) / 4 * 4;
-    w->nblk = div_up(N > 0 ? N : 1, kBlock);
+    w->nsys = nsys;
+    w->off.assign(off, off + nsys + 1);
+    const int apw = 64 >> lanes_log2(P > 0 ? P : 1);
+    int cap = 0;
+    for (int s = 0; s < nsys; ++s) cap += div_up(off[s + 1] - off[s], apw);
+    w->nblk_cap = cap;
+    const size_t nb = (size_t)std::max(cap, 1);
     const size_t PN = (size_t)P * N;
     hipError_t e = hipGetDevice(&w->device);
+    if (e == hipSuccess) e = dalloc(&w->tile_atom0, nb);
+    if (e == hipSuccess) e = dalloc(&w->tile_atom1, nb);
+    if (e == hipSuccess) e = dalloc(&w->tile_sys, nb);
+    if (e == hipSuccess) e = dalloc(&w->sys_tile0, (size_t)nsys + 1);
+    if (e == hipSuccess && set_tiles(w, 4) != NEP_OK) e = hipErrorUnknown;
     if (e == hipSuccess) e = dalloc(&w->B, PN * w->NA1 * kNumSH);
-    if (e == hipSuccess) e = dalloc(&w->arad, PN * w->S * w->KRP);
-    if (e == hipSuccess) e = dalloc(&w->partE, (size_t)P * w->nblk);
-    if (e == hipSuccess) e = dalloc(&w->partW, (size_t)2 * P * w->nblk * 9);
+    if (e == hipSuccess) e = dalloc(&w->arad, PN * w->S * 9);
+    if (e == hipSuccess) e = dalloc(&w->partE, (size_t)std::max(P, 1) * nb);
+    if (e == hipSuccess) e = dalloc(&w->partW, (size_t)2 * std::max(P, 1) * nb * 9);
     if (e == hipSuccess) e = dalloc(&w->Fang, PN * 3);
     if (e == hipSuccess) e = dalloc(&w->pos4, PN * 4);
     if (e == hipSuccess) e = dalloc(&w->flags, 4);
@@ -520,11 +620,19 @@ extern "C" int32_t nep_ws_create(const nep_model *m, int32_t P, int32_t N, nep_w
     return NEP_OK;
 }
 
+extern "C" int32_t nep_ws_create(const nep_model *m, int32_t P, int32_t N, nep_ws **out)
+{
+    if (N < 0) return fail(NEP_ERR_INVALID_ARG, "nep_ws_create: bad sizes P=%d N=%d", P, N);
+    const int32_t off[2] = {0, N};
+    return nep_ws_create_batched(m, P, 1, off, out);
+}
+
 extern "C" void nep_ws_destroy(nep_ws *w)
 {
     if (!w) return;
     for (void *p : {(void *)w->B, (void *)w->arad, (void *)w->partE, (void *)w->partW, (void *)w->Fang, (void *)w->pos4,
-                    (void *)w->flags})
+                    (void *)w->flags, (void *)w->tile_atom0, (void *)w->tile_atom1, (void *)w->tile_sys,
+                    (void *)w->sys_tile0})
         if (p) (void)hipFree(p);
     delete w;
 }

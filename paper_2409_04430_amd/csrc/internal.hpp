@@ -43,11 +43,30 @@ struct nep_model {
     int device = 0;
 };
 
+namespace nep {
+// Geometry of one system of a batch (device copy in the list handle).
+struct SysGeom {
+    double L[3], invL[3];     // orthorhombic box edges
+    double hd[3], Minv[3];    // fine grid spacing and M / L (packing)
+    float h[3];               // fine grid spacing (FP32, pair vectors)
+    int M[3];                 // fine grid cells per axis
+    int nc_cap[3];            // cell-list allocation bound per axis
+    int cell_base;            // first global cell of the system
+    int atom0, atom1;         // atom range [atom0, atom1)
+};
+}  // namespace nep
+
 struct nep_nlist {
     int P = 0, N = 0, S = 0;
-    int capC = 0;                 // candidate row capacity per atom
-    int capR = 0, capA = 0;       // per-bead neighbour capacities per atom (radial, angular)
+    int capR = 0, capA = 0;       // candidate row capacities per atom (radial, angular radius)
     int device = 0;
+    // Batch of independent systems: atoms [off[s], off[s+1]) form system s.
+    int nsys = 1;
+    std::vector<int> off;         // host [nsys+1]
+    std::vector<double> boxL;     // host [nsys][3] edges of the last build (0: none yet)
+    nep::SysGeom *geom = nullptr; // [nsys]
+    int32_t *atom_sys = nullptr;  // [N]
+    int32_t *cell_sys = nullptr;  // [ncell_alloc]
     // Candidate rows are reused across calls while the skin covers the motion.
     double skin = 0.0;            // extra candidate radius, A (0: rebuild every call)
     int built = 0;                // candidate rows valid for box_built
@@ -55,40 +74,51 @@ struct nep_nlist {
     // Shared by all beads: ring-polymer centroids and candidate rows.
     double *cen = nullptr;        // [N][3] centroids of this call
     double *cen_ref = nullptr;    // [N][3] centroids at the last rebuild
-    int32_t *cand = nullptr;      // [N][capC], entries (j << 2) | species(j), sorted by (species, j)
-    int32_t *rowlen = nullptr;    // [N] candidates found (may exceed capC: overflow)
-    int32_t *offC = nullptr;      // [N][5], species block starts, [S] = row length
-    int32_t *revC = nullptr;      // [N][capC], slot of i in the row of cand[i][k] (-1 if absent)
-    // Per bead: compact lists, slot-major ([bead][slot][atom]).
-    int32_t *listR = nullptr;     // [P][capR][N] neighbour index j
-    int32_t *endR = nullptr;      // [P][4][N] species block ends
-    int32_t *listA = nullptr;     // [P][capA][N]
-    int32_t *endA = nullptr;      // [P][4][N]
-    int32_t *slotA = nullptr;     // [P][capA][N] candidate slot k | reverse slot << 16 (0xffff: none)
-    int WC = 0;                   // words of one candidate-row bitmask: ceil(capC / 32)
-    uint64_t *maskA = nullptr;    // [P][WC][N] angular hits of word w (low 32 bits) | hits before w << 32
-    // Angular pair terms dU_j/dr_ji stored at the receiving atom i's list
-    // position s of j: [P][capA][N] xyz + pad.
+    int32_t *candR = nullptr;     // [N][capR] entries (j << 2) | species(j), sorted by (species, j)
+    int32_t *lenR = nullptr;      // [N] candidates found (may exceed capR: overflow)
+    int32_t *offR = nullptr;      // [N][5] species block starts, [S] = row length
+    int32_t *candA = nullptr;     // [N][capA] the same for the angular radius
+    int32_t *lenA = nullptr;      // [N]
+    int32_t *offA = nullptr;      // [N][5]
+    int32_t *revA = nullptr;      // [N][capA] slot of i in the angular row of candA[i][k] (-1 if absent)
+    // Per call: slots of the candidates inside the cutoff for at least one
+    // bead (row order), with per-species block ends.
+    int32_t *uniR = nullptr;      // [N][capR] atom indices j
+    uint64_t *umR = nullptr;      // [N][capR] bit b: inside the radial cutoff in bead b
+    int32_t *uendR = nullptr;     // [N][4]
+    int32_t *uniA = nullptr;      // [N][capA] angular slots k
+    uint64_t *umA = nullptr;      // [N][capA] bit b: inside the angular cutoff in bead b
+    int32_t *uendA = nullptr;     // [N][4]
+    // Angular pair terms dU_j/dr_ji at the receiving atom i's angular slot of j: [N][capA][P] xyz + pad.
     float *pairbuf = nullptr;
-    float *pos4 = nullptr;        // [P][N][4] packed positions of the last build
+    float *pos4 = nullptr;        // [N][P][4] packed positions of the last build (bead-minor)
     // Centroid cell list (grown on demand): cell_cnt [ncell], cell_start [ncell+1], cell_atoms [N].
-    int ncell_alloc = 0;
+    int ncell_alloc = 0, ncell_total = 0;
     int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_atoms = nullptr;
-    uint32_t *grid = nullptr;     // device-chosen grid record
-    uint32_t *status = nullptr;   // [0] flags, [1] max radial neighbours, [2] max angular neighbours,
-                                  // [3] max candidates, [4] spread (float bits), [5] rebuilds
+    uint32_t *grid = nullptr;     // device-chosen grid record: 16 global words + 4 per system
+    uint32_t *status = nullptr;   // [0] flags, [1] max radial union, [2] max angular union,
+                                  // [3] max radial candidates, [4] spread (float bits), [5] rebuilds,
+                                  // [6] max angular candidates
 };
 
 struct nep_ws {
     int P = 0, N = 0, S = 0, nblk = 0;
     int device = 0;
-    int NA1 = 0, KRP = 0;
-    float *B = nullptr;        // [P*N][NA1*24] angular adjoints dU_i/dA_nlm
-    float *arad = nullptr;     // [P*N][S][KRP] radial adjoints sum_n dU_i/dq_n c_nk
-    double *partE = nullptr;   // [P][nblk]
-    double *partW = nullptr;   // [2][P][nblk][9] (angular pass, radial pass)
-    float *Fang = nullptr;     // [P*N][3] angular part of the forces
-    float *pos4 = nullptr;     // [P*N][4] packed positions: offsets in a fine grid cell + cell index bits
+    int NA1 = 0;
+    int nsys = 1;
+    std::vector<int> off;      // host [nsys+1]
+    // Tiles: each workgroup of the NEP kernels takes up to 4 * 64 / G atoms
+    // (all their beads) of one system.
+    int wpb = 4;                    // wavefronts per workgroup (tile shape), set by nep_ws_set_tile / nep_autotune
+    int nblk_cap = 0;               // tile capacity (the count for one wavefront per workgroup)
+    int32_t *tile_atom0 = nullptr, *tile_atom1 = nullptr, *tile_sys = nullptr;   // [nblk_cap]
+    int32_t *sys_tile0 = nullptr;   // [nsys + 1]
+    float *B = nullptr;        // [N][P][NA1*24] angular adjoints dU_i/dA_nlm
+    float *arad = nullptr;     // [N][S][9][P] radial adjoints sum_n dU_i/dq_n c_nk
+    double *partE = nullptr;   // [nblk_cap][P]
+    double *partW = nullptr;   // [2][nblk_cap][P][9] (angular pass, radial pass)
+    float *Fang = nullptr;     // [N][P][3] angular part of the forces
+    float *pos4 = nullptr;     // [N][P][4] packed positions (bead-minor)
     uint32_t *flags = nullptr; // [1]
 };
 
@@ -138,7 +168,10 @@ struct FineGrid {
     int exact;
 };
 FineGrid fine_grid(const double L[3], double rc);
-void pack_positions(const double *pos, size_t n, const FineGrid &g, float4 *out, hipStream_t s);
+// Packs pos [P][N][3] into out [N][P] (bead-minor), each atom on the fine
+// grid of its system.
+void pack_positions(const double *pos, int P, int N, const int32_t *atom_sys, const SysGeom *geom, float4 *out,
+                    hipStream_t s);
 
 __device__ __forceinline__ int wrap_cell(int d, int M)
 {
@@ -159,10 +192,70 @@ __device__ __forceinline__ void packed_pair(const float4 &pj, const float4 &pi, 
     dz = fmaf(h[2], (float)cz, pj.z - pi.z);
 }
 
+// Exact FP64 minimum-image squared distance, the literal expression
+//   d = r_j - r_i;  d -= L rint(d / L);  (dx*dx + dy*dy) + dz*dz
+// without contraction.  The division is replaced by a multiply with 1/L
+// whenever that provably gives the same integer (d/L farther than 1e-9 from
+// a half-integer and |d/L| < 2^20).  Every step is exactly antisymmetric in
+// i and j, so the test is symmetric.
+__device__ __forceinline__ double mic_r2_exact(const double *ri, const double *rj, const double L[3],
+                                               const double invL[3])
+{
+#pragma clang fp contract(off)
+    double e2[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double d = rj[a] - ri[a];
+        const double t = d * invL[a];
+        double k = rint(t);
+        const double off = t - k;
+        if (!(fabs(off) < 0.499999999) || !(fabs(t) < 1048576.0)) k = rint(d / L[a]);
+        const double sft = L[a] * k;
+        const double e = d - sft;
+        e2[a] = e * e;
+    }
+    return (e2[0] + e2[1]) + e2[2];
+}
+
+// Cutoff decision for a pair of one bead.  It is taken on the packed FP32
+// squared distance when that lies farther than `margin` from rc^2 (far above
+// the packed error bound, so the answer equals the FP64 one) and by the FP64
+// test otherwise.  pos points to the bead's [N][3] FP64 positions.
+struct CutTest {
+    float rc2f, margin;
+    double rc2;
+};
+struct BoxD {
+    double L[3], invL[3];
+};
+__device__ __forceinline__ bool pair_within(float r2f, const CutTest &c, const double *__restrict__ pos, int i, int j,
+                                            const BoxD &box)
+{
+    if (fabsf(r2f - c.rc2f) > c.margin) return r2f < c.rc2f;
+    const double ri[3] = {pos[3 * (size_t)i], pos[3 * (size_t)i + 1], pos[3 * (size_t)i + 2]};
+    const double rj[3] = {pos[3 * (size_t)j], pos[3 * (size_t)j + 1], pos[3 * (size_t)j + 2]};
+    return mic_r2_exact(ri, rj, box.L, box.invL) < c.rc2;
+}
+
+// Lanes per atom: the beads of one atom occupy G = 2^lg consecutive lanes of
+// a wavefront (G >= P, lanes with bead >= P idle), 64 / G atoms per wave.
+inline int lanes_log2(int P)
+{
+    int lg = 0;
+    while ((1 << lg) < P) ++lg;
+    return lg;
+}
+
+// Checks the boxes [nsys][9] of a batch against the model's cutoffs and
+// refreshes the per-system geometry of the list handle (synchronous upload
+// when a box changed).  margin: decision margin of the FP32 pre-test, about
+// 30x the packed error bound.
+int32_t update_geometry(const nep_model *m, nep_nlist *nl, const double *boxes, bool &changed, float &margin);
+
 // Kernel timing (hipEvents around launches on the caller's stream), off by default.
 enum KernelId {
     K_FILL = 0, K_PACK, K_CENTROID, K_GRID, K_CELL_COUNT, K_CELL_SCAN, K_CELL_FILL, K_CELL_SORT, K_CANDIDATES,
-    K_SORT_ROWS, K_REVERSE, K_NLIST,
+    K_SORT_ROWS, K_REVERSE, K_NLIST, K_MATERIALIZE,
     K_DESCRIPTOR, K_FORCE_ANG, K_FORCE, K_REDUCE, K_TRPMD, K_MODES, K_NUM
 };
 struct ProfScope {

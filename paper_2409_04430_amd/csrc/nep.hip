@@ -21,263 +21,9 @@
 // lanes, which makes every model-coefficient address wave-uniform (scalar
 // loads, SGPR operands).  Neighbour loops keep several gathers in flight.
 #include "internal.hpp"
+#include "nep_kernels.hpp"
 
 namespace nep {
-
-constexpr float kPi = 3.14159265358979f;
-
-struct NepArgs {
-    const float4 *p4;   // packed positions [P][N]: offsets in a fine grid cell, cell index bits in w
-    const int32_t *types;
-    int N, S, H;
-    int M[3];            // fine grid cells per axis
-    float h[3];          // fine grid spacing L / M
-    float rcRinv, rcAinv;
-    float kappa4;
-    // per-bead lists, slot-major: list[(b * cap + s) * N + i]
-    const int32_t *listR, *endR, *listA, *endA, *slotA;
-    const uint64_t *maskA;   // [P][WC][N] angular hits per candidate word | hits before the word << 32
-    int capR, capA, capC, WC;
-    float4 *pairbuf;   // [P][capA][N] dU_j/dr_ji at the receiving atom's list position (w unused)
-    // workspace
-    float *B;
-    float *arad;
-    float *Fang;
-    int KRP;
-    double *partE, *partWa, *partWr;
-    uint32_t *flags;
-    // outputs
-    float *F;
-    float *Eatom;
-    float *Watom;
-    // parameter offsets
-    int oR, oA, oq, oW0, ob0, ow1, ob1, osh;
-};
-
-// Start and end of species block t in the list of (bead b, atom i).
-__device__ __forceinline__ void block_range(const int32_t *end, int b, int t, int N, int i, int &s0, int &s1)
-{
-    const size_t base = (size_t)b * kMaxSpecies * N + i;
-    s0 = t ? end[base + (size_t)(t - 1) * N] : 0;
-    s1 = end[base + (size_t)t * N];
-}
-
-// Pair vector r_j - r_i from packed positions (see FineGrid).
-__device__ __forceinline__ void pair_vec(const float4 &pj, const float4 &pi, const NepArgs &a, float &dx, float &dy,
-                                         float &dz)
-{
-    packed_pair(pj, pi, a.M, a.h, dx, dy, dz);
-}
-
-// sin(pi z) and cos(pi z) for z in [0, 1]: with w = z - 1/2, cos(pi z) =
-// -sin(pi w) and sin(pi z) = cos(pi w), and |pi w| <= pi/2, where the Taylor
-// series through x^13 (sin) and x^14 (cos) is accurate to ~2e-7 in FP32.
-__device__ __forceinline__ void sincospi01(float z, float &s, float &c)
-{
-    const float x = kPi * (z - 0.5f);
-    const float x2 = x * x;
-    float ps = (float)(-1.0 / 6227020800.0);
-    ps = ps * x2 + (float)(1.0 / 39916800.0);
-    ps = ps * x2 + (float)(-1.0 / 362880.0);
-    ps = ps * x2 + (float)(1.0 / 5040.0);
-    ps = ps * x2 + (float)(-1.0 / 120.0);
-    ps = ps * x2 + (float)(1.0 / 6.0);
-    float sw = x - x * x2 * ps;
-    float pc = (float)(-1.0 / 87178291200.0);
-    pc = pc * x2 + (float)(1.0 / 479001600.0);
-    pc = pc * x2 + (float)(-1.0 / 3628800.0);
-    pc = pc * x2 + (float)(1.0 / 40320.0);
-    pc = pc * x2 + (float)(-1.0 / 720.0);
-    pc = pc * x2 + (float)(1.0 / 24.0);
-    pc = pc * x2 + (float)(-1.0 / 2.0);
-    float cw = 1.0f + x2 * pc;
-    c = -sw;
-    s = cw;
-}
-
-// f_k(r) = (T_k(x) + 1)/2 f_c(r), x = 2 (r/rc - 1)^2 - 1, f_c = (1 + cos(pi r/rc))/2.
-template <int K1>
-__device__ __forceinline__ void cheb_f(float r, float rcinv, float *f)
-{
-    float sn, cs;
-    const float z = r * rcinv;
-    sincospi01(z, sn, cs);
-    const float fc = 0.5f + 0.5f * cs;
-    const float y = z - 1.0f;
-    const float x = 2.0f * y * y - 1.0f;
-    float t0 = 1.0f, t1 = x;
-    f[0] = fc;
-    if (K1 > 1) f[1] = 0.5f * (x + 1.0f) * fc;
-#pragma unroll
-    for (int k = 2; k < K1; ++k) {
-        const float t2 = 2.0f * x * t1 - t0;
-        f[k] = 0.5f * (t2 + 1.0f) * fc;
-        t0 = t1;
-        t1 = t2;
-    }
-}
-
-// f_k and df_k/dr.
-template <int K1>
-__device__ __forceinline__ void cheb_fd(float r, float rcinv, float *f, float *fp)
-{
-    float sn, cs;
-    const float z = r * rcinv;
-    sincospi01(z, sn, cs);
-    const float fc = 0.5f + 0.5f * cs;
-    const float fcp = -0.5f * kPi * rcinv * sn;
-    const float y = z - 1.0f;
-    const float x = 2.0f * y * y - 1.0f;
-    const float dx = 4.0f * y * rcinv;
-    float t0 = 1.0f, t1 = x, d0 = 0.0f, d1 = 1.0f;
-    f[0] = fc;
-    fp[0] = fcp;
-    if (K1 > 1) {
-        f[1] = 0.5f * (x + 1.0f) * fc;
-        fp[1] = 0.5f * dx * fc + 0.5f * (x + 1.0f) * fcp;
-    }
-#pragma unroll
-    for (int k = 2; k < K1; ++k) {
-        const float t2 = 2.0f * x * t1 - t0;
-        const float d2 = 2.0f * t1 + 2.0f * x * d1 - d0;
-        f[k] = 0.5f * (t2 + 1.0f) * fc;
-        fp[k] = 0.5f * d2 * dx * fc + 0.5f * (t2 + 1.0f) * fcp;
-        t0 = t1; t1 = t2;
-        d0 = d1; d1 = d2;
-    }
-}
-
-// Real spherical harmonics l = 1..4 (m = -l..l) at unit vector (x, y, z);
-// c holds the normalisations.
-__device__ __forceinline__ void sh_eval(float x, float y, float z, const float *__restrict__ c, float *Y)
-{
-    const float x2 = x * x, y2 = y * y, z2 = z * z;
-    Y[0] = c[0] * y;
-    Y[1] = c[1] * z;
-    Y[2] = c[2] * x;
-    Y[3] = c[3] * x * y;
-    Y[4] = c[4] * y * z;
-    Y[5] = c[5] * (3.0f * z2 - 1.0f);
-    Y[6] = c[6] * x * z;
-    Y[7] = c[7] * (x2 - y2);
-    Y[8] = c[8] * y * (3.0f * x2 - y2);
-    Y[9] = c[9] * x * y * z;
-    Y[10] = c[10] * y * (5.0f * z2 - 1.0f);
-    Y[11] = c[11] * z * (5.0f * z2 - 3.0f);
-    Y[12] = c[12] * x * (5.0f * z2 - 1.0f);
-    Y[13] = c[13] * z * (x2 - y2);
-    Y[14] = c[14] * x * (x2 - 3.0f * y2);
-    Y[15] = c[15] * x * y * (x2 - y2);
-    Y[16] = c[16] * y * z * (3.0f * x2 - y2);
-    Y[17] = c[17] * x * y * (7.0f * z2 - 1.0f);
-    Y[18] = c[18] * y * z * (7.0f * z2 - 3.0f);
-    Y[19] = c[19] * (35.0f * z2 * z2 - 30.0f * z2 + 3.0f);
-    Y[20] = c[20] * x * z * (7.0f * z2 - 3.0f);
-    Y[21] = c[21] * (x2 - y2) * (7.0f * z2 - 1.0f);
-    Y[22] = c[22] * x * z * (x2 - 3.0f * y2);
-    Y[23] = c[23] * (x2 * (x2 - 3.0f * y2) - y2 * (3.0f * x2 - y2));
-}
-
-// sY = sum_m bp_m Y_m(u);  g = sum_m b_m grad p_m(u), where Y_m = c_m p_m and
-// the polynomial p_m is differentiated as a function on R^3 (the tangential
-// projection is applied by the caller).
-__device__ __forceinline__ void sh_contract(float x, float y, float z, const float *__restrict__ c, const float *b,
-                                            const float *bp, float &sY, float &gx, float &gy, float &gz)
-{
-    float Y[kNumSH];
-    sh_eval(x, y, z, c, Y);
-    float s = 0.0f;
-#pragma unroll
-    for (int m = 0; m < kNumSH; ++m) s += bp[m] * Y[m];
-    sY = s;
-    float w[kNumSH];
-#pragma unroll
-    for (int m = 0; m < kNumSH; ++m) w[m] = b[m] * c[m];
-    const float x2 = x * x, y2 = y * y, z2 = z * z;
-    const float xy = x * y, yz = y * z, xz = x * z;
-    float X = 0.0f, Yv = 0.0f, Z = 0.0f;
-    // l = 1
-    Yv += w[0];
-    Z += w[1];
-    X += w[2];
-    // l = 2
-    X += w[3] * y;  Yv += w[3] * x;
-    Yv += w[4] * z; Z += w[4] * y;
-    Z += w[5] * 6.0f * z;
-    X += w[6] * z;  Z += w[6] * x;
-    X += w[7] * 2.0f * x; Yv -= w[7] * 2.0f * y;
-    // l = 3
-    X += w[8] * 6.0f * xy;  Yv += w[8] * 3.0f * (x2 - y2);
-    X += w[9] * yz; Yv += w[9] * xz; Z += w[9] * xy;
-    Yv += w[10] * (5.0f * z2 - 1.0f); Z += w[10] * 10.0f * yz;
-    Z += w[11] * (15.0f * z2 - 3.0f);
-    X += w[12] * (5.0f * z2 - 1.0f); Z += w[12] * 10.0f * xz;
-    X += w[13] * 2.0f * xz; Yv -= w[13] * 2.0f * yz; Z += w[13] * (x2 - y2);
-    X += w[14] * 3.0f * (x2 - y2); Yv -= w[14] * 6.0f * xy;
-    // l = 4
-    X += w[15] * (3.0f * x2 * y - y2 * y); Yv += w[15] * (x2 * x - 3.0f * x * y2);
-    X += w[16] * 6.0f * xy * z; Yv += w[16] * 3.0f * z * (x2 - y2); Z += w[16] * (3.0f * x2 * y - y2 * y);
-    X += w[17] * y * (7.0f * z2 - 1.0f); Yv += w[17] * x * (7.0f * z2 - 1.0f); Z += w[17] * 14.0f * xy * z;
-    Yv += w[18] * z * (7.0f * z2 - 3.0f); Z += w[18] * y * (21.0f * z2 - 3.0f);
-    Z += w[19] * z * (140.0f * z2 - 60.0f);
-    X += w[20] * z * (7.0f * z2 - 3.0f); Z += w[20] * x * (21.0f * z2 - 3.0f);
-    X += w[21] * 2.0f * x * (7.0f * z2 - 1.0f); Yv -= w[21] * 2.0f * y * (7.0f * z2 - 1.0f);
-    Z += w[21] * 14.0f * z * (x2 - y2);
-    X += w[22] * 3.0f * z * (x2 - y2); Yv -= w[22] * 6.0f * xy * z; Z += w[22] * x * (x2 - 3.0f * y2);
-    X += w[23] * (4.0f * x2 * x - 12.0f * x * y2); Yv += w[23] * (4.0f * y2 * y - 12.0f * x2 * y);
-    gx = X;
-    gy = Yv;
-    gz = Z;
-}
-
-// l of spherical-harmonic slot m (0..23).
-__host__ __device__ constexpr int sh_l(int m) { return m < 3 ? 1 : (m < 8 ? 2 : (m < 15 ? 3 : 4)); }
-
-template <int NR1, int NA1, bool FOUR>
-struct Dims {
-    static constexpr int D = NR1 + kLmax * NA1 + (FOUR ? NA1 : 0);
-};
-
-__device__ __forceinline__ double wave_sum(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-// Block-wide sum (256 threads = 4 waves) in a fixed order; result valid in thread 0.
-__device__ __forceinline__ double block_sum(double v, double *lds)
-{
-    v = wave_sum(v);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) lds[w] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0) r = (lds[0] + lds[1]) + (lds[2] + lds[3]);
-    __syncthreads();
-    return r;
-}
-
-// Four-body helper: M_n = sum_j g_n (u u^T - I/3) rebuilt from the l = 2 sums
-// (slots 3..7 hold m = -2..2): returns mxy, myz, mzz, mxz, d = mxx - myy.
-__device__ __forceinline__ void m_from_l2(const float *A2, const float *shc, float *M)
-{
-    M[0] = A2[0] / shc[3];
-    M[1] = A2[1] / shc[4];
-    M[2] = A2[2] / (3.0f * shc[5]);
-    M[3] = A2[3] / shc[6];
-    M[4] = A2[4] / shc[7];
-}
-
-constexpr int kBatch = 4;   // neighbours whose index and position are loaded together
-
-// Hide a uniform pointer from loop-invariant code motion, so that the model
-// coefficients it addresses are re-read through the scalar cache inside a
-// neighbour loop instead of being hoisted into (scarce) vector registers.
-__device__ __forceinline__ const float *launder(const float *p)
-{
-    asm volatile("" : "+s"(p));
-    return p;
-}
 
 // ----------------------------------------------------------- pass 1 ---
 
@@ -286,16 +32,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void k_descriptor(NepArgs a, const float *__restrict__ prm)
 {
     constexpr int D = Dims<NR1, NA1, FOUR>::D;
-    int b, tile;
-    bead_tile(b, tile);
-    const int i = tile * blockDim.x + threadIdx.x;
-    const int N = a.N, S = a.S;
-    const bool valid = i < N;
-    const int ii = valid ? i : N - 1;
-    const int ti = a.types[ii];
+    const LaneMap lm = lane_map(a);
+    const int i = lm.i, b = lm.b, P = a.P, S = a.S;
+    const bool valid = lm.valid;
+    const int ti = a.types[i];
     const bool tok = ti >= 0 && ti < S;
-    const float4 *pb = a.p4 + (size_t)b * N;
-    const float4 pi = pb[ii];
+    const float4 *p4 = a.p4;
+    const float4 pi = p4[(size_t)i * P + b];
     const float *shc = prm + a.osh;
     float U = 0.0f;
 
@@ -312,31 +55,38 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
         for (int v = 0; v < D; ++v) q[v] = 0.0f;
 
         // radial: per neighbour species, sum the basis, then contract with c
-        const int32_t *lR = a.listR + (size_t)b * a.capR * N + i;
-        const int32_t *lA = a.listA + (size_t)b * a.capA * N + i;
+        const int32_t *uR = a.uniR + (size_t)i * a.capR;
+        const uint64_t *mR = a.umR + (size_t)i * a.capR;
         for (int t = 0; t < S; ++t) {
             int s0, s1;
-            block_range(a.endR, b, t, N, i, s0, s1);
+            block_range(a.uendR, i, t, s0, s1);
             float sk[KR1];
 #pragma unroll
             for (int k = 0; k < KR1; ++k) sk[k] = 0.0f;
             for (int sb = s0; sb < s1; sb += kBatch) {
+                int jj[kBatch];
+                bool in[kBatch];
                 float4 pj[kBatch];
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
-                    const int j = (sb + u < s1) ? lR[(size_t)(sb + u) * N] : i;
-                    pj[u] = pb[j];
+                    const bool ok = sb + u < s1;
+                    jj[u] = ok ? uR[sb + u] : i;
+                    in[u] = ok && ((mR[ok ? sb + u : 0] >> b) & 1u);
+                    pj[u] = p4[(size_t)jj[u] * P + b];
                 }
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
-                    if (sb + u < s1) {
+                    if (in[u]) {
                         float dx, dy, dz;
-                        pair_vec(pj[u], pi, a, dx, dy, dz);
-                        const float r = __builtin_amdgcn_sqrtf(dx * dx + dy * dy + dz * dz);
-                        float f[KR1];
-                        cheb_f<KR1>(r, a.rcRinv, f);
+                        pair_vec(pj[u], pi, lm, dx, dy, dz);
+                        const float r2 = dx * dx + dy * dy + dz * dz;
+                        {
+                            const float r = __builtin_amdgcn_sqrtf(r2);
+                            float f[KR1];
+                            cheb_f<KR1>(r, a.rcRinv, f);
 #pragma unroll
-                        for (int q2 = 0; q2 < KR1; ++q2) sk[q2] += f[q2];
+                            for (int q2 = 0; q2 < KR1; ++q2) sk[q2] += f[q2];
+                        }
                     }
                 }
             }
@@ -356,16 +106,27 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
         for (int n = 0; n < NA1; ++n)
 #pragma unroll
             for (int m = 0; m < kNumSH; ++m) A[n][m] = 0.0f;
+        const int32_t *uA = a.uniA + (size_t)i * a.capA;
+        const uint64_t *mA = a.umA + (size_t)i * a.capA;
+        const int32_t *rowA = a.candA + (size_t)i * a.capA;
         for (int t = 0; t < S; ++t) {
             int s0, s1;
-            block_range(a.endA, b, t, N, i, s0, s1);
+            block_range(a.uendA, i, t, s0, s1);
             const float *c = prm + a.oA + (tc * S + t) * NA1 * KA1;
-            float4 pn = pb[s0 < s1 ? lA[(size_t)s0 * N] : i];
+            int jn = s0 < s1 ? (rowA[uA[s0]] >> 2) : i;
+            bool inn = s0 < s1 && ((mA[s0 < s1 ? s0 : 0] >> b) & 1u);
+            float4 pn = p4[(size_t)jn * P + b];
             for (int sn = s0; sn < s1; ++sn) {
                 const float4 pc = pn;
-                if (sn + 1 < s1) pn = pb[lA[(size_t)(sn + 1) * N]];
+                const bool inc = inn;
+                if (sn + 1 < s1) {
+                    jn = rowA[uA[sn + 1]] >> 2;
+                    inn = (mA[sn + 1] >> b) & 1u;
+                    pn = p4[(size_t)jn * P + b];
+                }
+                if (!inc) continue;
                 float dx, dy, dz;
-                pair_vec(pc, pi, a, dx, dy, dz);
+                pair_vec(pc, pi, lm, dx, dy, dz);
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 const float rinv = __builtin_amdgcn_rsqf(r2);
                 const float r = r2 * rinv;
@@ -405,7 +166,7 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             }
         }
         // park A in this atom's adjoint row (overwritten with B below)
-        float *Bo = a.B + ((size_t)b * N + i) * (NA1 * kNumSH);
+        float *Bo = a.B + ((size_t)i * P + b) * (NA1 * kNumSH);
 #pragma unroll
         for (int n = 0; n < NA1; ++n) {
             float4 *o4 = reinterpret_cast<float4 *>(Bo + n * kNumSH);
@@ -476,8 +237,8 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             for (int q4 = 0; q4 < kNumSH / 4; ++q4)
                 o4[q4] = make_float4(Bn[4 * q4], Bn[4 * q4 + 1], Bn[4 * q4 + 2], Bn[4 * q4 + 3]);
         }
-        // radial adjoints a_k(t) = sum_n G_n c^{tc t}_nk
-        float *ao = a.arad + ((size_t)b * N + i) * S * a.KRP;
+        // radial adjoints a_k(t) = sum_n G_n c^{tc t}_nk, bead-minor
+        float *ao = a.arad + (size_t)i * S * KR1 * P + b;
         for (int t = 0; t < S; ++t) {
             const float *c = prm + a.oR + (tc * S + t) * NR1 * KR1;
 #pragma unroll
@@ -485,49 +246,47 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                 float acc = 0.0f;
 #pragma unroll
                 for (int n = 0; n < NR1; ++n) acc += G[n] * c[n * KR1 + k];
-                ao[t * a.KRP + k] = acc;
+                ao[(size_t)(t * KR1 + k) * P] = acc;
             }
         }
     }
 
-    if (valid && a.Eatom) a.Eatom[(size_t)b * N + i] = U;
+    if (valid && a.Eatom) a.Eatom[(size_t)b * a.N + i] = U;
     if (valid && !tok) atomicOr(a.flags, (uint32_t)NEP_FLAG_BAD_TYPE);
-    __shared__ double lds[4];
-    const double e = block_sum(valid ? (double)U : 0.0, lds);
-    if (threadIdx.x == 0) a.partE[(size_t)b * gridDim.x + tile] = e;
+    __shared__ double lds[kBlock];
+    bead_block_sum(valid ? (double)U : 0.0, lds, P, a.lg, a.partE + (size_t)blockIdx.x * P, 1);
 }
 
 // ------------------------------------------------ pass 2: angular, own ---
 
-// One lane per (bead, atom i): the angular pair terms d_ij = dU_i/dr_ij of
+// One lane per (atom i, bead): the angular pair terms d_ij = dU_i/dr_ij of
 // the atom's own site energy, contracted with its own adjoints only:
 //   d_ij = sum_n sum_lm B^i_nlm d/dr_ij [ g^{ij}_n(r) Y_lm(u) ],
-// stored at (bead, i, candidate slot of j) for the reverse gather of the
-// radial pass, and summed into the angular force part F_i += d_ij and the
-// virial -r_ij (x) d_ij (the total needs no reverse terms).  BREG keeps B^i
-// in registers (small n_max); otherwise it is re-read from its L1-resident
-// row.  Control flow stays wave-uniform: lanes outside the current centre
-// species, or past their last neighbour, compute on a dummy pair and
-// contribute nothing.
+// deposited where the partner j reads it back (its angular slot of i, same
+// bead), and summed into the angular force part F_i += d_ij and the virial
+// -r_ij (x) d_ij (the total needs no reverse terms).  BREG keeps B^i in
+// registers (small n_max); otherwise it is re-read from its L1-resident row.
+// Control flow stays wave-uniform: lanes outside the current centre species,
+// past their atom's last candidate or outside the cutoff compute on a dummy
+// pair and contribute nothing; a candidate outside for every lane is
+// skipped.
 template <int NA1, int KA1, bool BREG>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void k_force_ang(NepArgs a, const float *__restrict__ prm)
 {
-    int b, tile;
-    bead_tile(b, tile);
-    const int i = tile * blockDim.x + threadIdx.x;
-    const int N = a.N, S = a.S;
-    const bool valid = i < N;
-    const int ii = valid ? i : N - 1;
-    const int ti = a.types[ii];
+    const LaneMap lm = lane_map(a);
+    const int i = lm.i, b = lm.b, P = a.P, S = a.S;
+    const bool valid = lm.valid;
+    const int ii = i;
+    const int ti = a.types[i];
     const bool tok = ti >= 0 && ti < S;
-    const float4 *pb = a.p4 + (size_t)b * N;
-    const float4 pi = pb[ii];
+    const float4 *p4 = a.p4;
+    const float4 pi = p4[(size_t)i * P + b];
     const float *shc = prm + a.osh;
-    const int32_t *lA = a.listA + (size_t)b * a.capA * N + ii;
-    const int32_t *sA = a.slotA + (size_t)b * a.capA * N + ii;
-    const uint64_t *mkb = a.maskA + (size_t)b * a.WC * N;
-    float4 *pbuf = a.pairbuf + (size_t)b * a.capA * N;
+    const int32_t *uA = a.uniA + (size_t)i * a.capA;
+    const uint64_t *mA = a.umA + (size_t)i * a.capA;
+    const int32_t *rowA = a.candA + (size_t)i * a.capA;
+    const int32_t *rvA = a.revA + (size_t)i * a.capA;
     float Fx = 0.0f, Fy = 0.0f, Fz = 0.0f;
     float Wv[9];
 #pragma unroll
@@ -540,7 +299,7 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
         const bool mine = valid && tok && ti == tc;
         todo &= ~__ballot(mine);
 
-        const float4 *bi4 = reinterpret_cast<const float4 *>(a.B + ((size_t)b * N + ii) * (NA1 * kNumSH));
+        const float4 *bi4 = reinterpret_cast<const float4 *>(a.B + ((size_t)i * P + b) * (NA1 * kNumSH));
         float Bi[BREG ? NA1 : 1][kNumSH];
         if (BREG) {
 #pragma unroll
@@ -554,31 +313,29 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
         }
         for (int t = 0; t < S; ++t) {
             int s0 = 0, s1 = 0;
-            if (mine) block_range(a.endA, b, t, N, ii, s0, s1);
+            if (mine) block_range(a.uendA, i, t, s0, s1);
             const int cnt = s1 - s0;
             int cmax = cnt;
             for (int o = 32; o > 0; o >>= 1) cmax = max(cmax, __shfl_xor(cmax, o));
             cmax = __builtin_amdgcn_readfirstlane(cmax);
             const float *cij = prm + a.oA + (tc * S + t) * NA1 * KA1;
-            int jn = cnt > 0 ? lA[(size_t)s0 * N] : ii;
-            int rn = cnt > 0 ? (int)((uint32_t)sA[(size_t)s0 * N] >> 16) : 0xffff;
+            int kn = cnt > 0 ? uA[s0] : 0;
+            int jn = cnt > 0 ? (rowA[kn] >> 2) : i;
+            bool inn = cnt > 0 && ((mA[cnt > 0 ? s0 : 0] >> b) & 1u);
             for (int sc = 0; sc < cmax; ++sc) {
                 const float *cij_l = launder(cij), *shc_l = launder(shc);
-                const bool act = sc < cnt;
-                const int j = jn, rc = rn;
+                const int j = jn, kc = kn;
+                const bool act = inn;
+                const float4 pj = p4[(size_t)j * P + b];
+                inn = false;
                 if (sc + 1 < cnt) {
-                    jn = lA[(size_t)(s0 + sc + 1) * N];
-                    rn = (int)((uint32_t)sA[(size_t)(s0 + sc + 1) * N] >> 16);
+                    kn = uA[s0 + sc + 1];
+                    inn = (mA[s0 + sc + 1] >> b) & 1u;
+                    jn = rowA[kn] >> 2;
                 }
-                // list position of i in j's angular list: angular hits of j before its slot rc
-                int dst = -1;
-                if (act && rc != 0xffff) {
-                    const uint64_t m = mkb[(size_t)(rc >> 5) * N + j];
-                    dst = (int)(m >> 32) + __popc((uint32_t)m & ((1u << (rc & 31)) - 1u));
-                    if (dst >= a.capA) dst = -1;
-                }
+                if (__ballot(act) == 0) continue;
                 float dx, dy, dz;
-                pair_vec(pb[j], pi, a, dx, dy, dz);
+                pair_vec(pj, pi, lm, dx, dy, dz);
                 if (!act) {
                     dx = 1.0f;
                     dy = 0.0f;
@@ -604,38 +361,39 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
                         gpij[n] = g1;
                     }
                 }
-                float beta[kNumSH], betap[kNumSH];
+                float sY, gx, gy, gz;
+                if constexpr (BREG) {
+                    adjoint_contract<NA1>(ux, uy, uz, shc_l, Bi, gij, gpij, sY, gx, gy, gz);
+                } else {
+                    float beta[kNumSH], betap[kNumSH];
 #pragma unroll
-                for (int m = 0; m < kNumSH; ++m) {
-                    beta[m] = 0.0f;
-                    betap[m] = 0.0f;
-                }
+                    for (int m = 0; m < kNumSH; ++m) {
+                        beta[m] = 0.0f;
+                        betap[m] = 0.0f;
+                    }
 #pragma unroll
-                for (int n = 0; n < NA1; ++n) {
+                    for (int n = 0; n < NA1; ++n) {
 #pragma unroll
-                    for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
-                        float bx[4];
-                        if (!BREG) {
+                        for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
                             const float4 x4 = bi4[n * (kNumSH / 4) + q4];
-                            bx[0] = x4.x; bx[1] = x4.y; bx[2] = x4.z; bx[3] = x4.w;
-                        }
+                            const float bx[4] = {x4.x, x4.y, x4.z, x4.w};
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            const int m = 4 * q4 + e;
-                            const float bi = BREG ? Bi[BREG ? n : 0][m] : bx[e];
-                            beta[m] = fmaf(bi, gij[n], beta[m]);
-                            betap[m] = fmaf(bi, gpij[n], betap[m]);
+                            for (int e = 0; e < 4; ++e) {
+                                const int m = 4 * q4 + e;
+                                beta[m] = fmaf(bx[e], gij[n], beta[m]);
+                                betap[m] = fmaf(bx[e], gpij[n], betap[m]);
+                            }
                         }
                     }
+                    sh_contract(ux, uy, uz, shc_l, beta, betap, sY, gx, gy, gz);
                 }
-                float sY, gx, gy, gz;
-                sh_contract(ux, uy, uz, shc_l, beta, betap, sY, gx, gy, gz);
                 const float ug = ux * gx + uy * gy + uz * gz;
                 const float px = sY * ux + (gx - ux * ug) * rinv;
                 const float py = sY * uy + (gy - uy * ug) * rinv;
                 const float pz = sY * uz + (gz - uz * ug) * rinv;
                 if (act) {
-                    if (dst >= 0) pbuf[(size_t)dst * N + j] = make_float4(px, py, pz, 0.0f);
+                    const int rk = rvA[kc];
+                    if (rk >= 0) a.pairbuf[((size_t)j * a.capA + rk) * P + b] = make_float4(px, py, pz, 0.0f);
                     Fx += px; Fy += py; Fz += pz;
                     Wv[0] = fmaf(-dx, px, Wv[0]); Wv[1] = fmaf(-dx, py, Wv[1]); Wv[2] = fmaf(-dx, pz, Wv[2]);
                     Wv[3] = fmaf(-dy, px, Wv[3]); Wv[4] = fmaf(-dy, py, Wv[4]); Wv[5] = fmaf(-dy, pz, Wv[5]);
@@ -646,45 +404,39 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
     }
 
     if (valid) {
-        float *Fo = a.Fang + ((size_t)b * N + i) * 3;
+        float *Fo = a.Fang + ((size_t)i * P + b) * 3;
         Fo[0] = Fx;
         Fo[1] = Fy;
         Fo[2] = Fz;
         if (a.Watom) {
             // own half of the per-atom split; the reverse half is added by the radial pass
-            float *wo = a.Watom + ((size_t)b * N + i) * 9;
+            float *wo = a.Watom + ((size_t)b * a.N + i) * 9;
 #pragma unroll
             for (int e = 0; e < 9; ++e) wo[e] = 0.5f * Wv[e];
         }
     }
-    __shared__ double lds[4];
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        const double w = block_sum(valid ? (double)Wv[e] : 0.0, lds);
-        if (threadIdx.x == 0) a.partWa[((size_t)b * gridDim.x + tile) * 9 + e] = w;
-    }
+    __shared__ double lds[kBlock];
+    for (int e = 0; e < 9; ++e)
+        bead_block_sum(valid ? (double)Wv[e] : 0.0, lds, P, a.lg, a.partWa + (size_t)blockIdx.x * P * 9 + e, 9);
 }
 
 // ----------------------------------------- pass 3: radial + combination ---
 
-// One lane per (bead, atom i): radial pair terms (a^i_k(tj) + a^j_k(ti)) f'_k(r) u
-// (both site energies at once, the adjoints a_k are gathered), then the
-// reverse angular terms -dU_j/dr_ji gathered from the pair buffer through the
-// reverse slot of each angular neighbour, then the angular own part of pass 2.
-// Force and per-atom virial sums are kept in FP64.
+// One lane per (atom i, bead): radial pair terms (a^i_k(tj) + a^j_k(ti))
+// f'_k(r) u (both site energies at once, the partner's adjoints gathered
+// bead-minor), then the reverse angular terms -dU_j/dr_ji that the angular
+// pass deposited at this atom's slots, then the angular own part.  Force and
+// per-atom virial sums are kept in FP64.
 template <int KR1>
 __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
 {
-    int b, tile;
-    bead_tile(b, tile);
-    const int i = tile * blockDim.x + threadIdx.x;
-    const int N = a.N, S = a.S;
-    const bool valid = i < N;
-    const int ii = valid ? i : N - 1;
-    const int ti = a.types[ii];
+    const LaneMap lm = lane_map(a);
+    const int i = lm.i, b = lm.b, P = a.P, S = a.S;
+    const bool valid = lm.valid;
+    const int ti = a.types[i];
     const bool tok = ti >= 0 && ti < S;
-    const float4 *pb = a.p4 + (size_t)b * N;
-    const float4 pi = pb[ii];
+    const float4 *p4 = a.p4;
+    const float4 pi = p4[(size_t)i * P + b];
     double Fx = 0.0, Fy = 0.0, Fz = 0.0;
     double Wv[9];
 #pragma unroll
@@ -693,30 +445,35 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
 #pragma unroll
     for (int e = 0; e < 9; ++e) Wa[e] = 0.0f;
     if (valid && tok) {
-        const float *ai_base = a.arad + ((size_t)b * N + i) * S * a.KRP;
-        const int32_t *lR = a.listR + (size_t)b * a.capR * N + i;
+        const float *ai_base = a.arad + (size_t)i * S * KR1 * P + b;
+        const int32_t *uR = a.uniR + (size_t)i * a.capR;
+        const uint64_t *mR = a.umR + (size_t)i * a.capR;
         for (int t = 0; t < S; ++t) {
             int s0, s1;
-            block_range(a.endR, b, t, N, i, s0, s1);
+            block_range(a.uendR, i, t, s0, s1);
             float ai[KR1];
 #pragma unroll
-            for (int q2 = 0; q2 < KR1; ++q2) ai[q2] = ai_base[t * a.KRP + q2];
+            for (int q2 = 0; q2 < KR1; ++q2) ai[q2] = ai_base[(size_t)(t * KR1 + q2) * P];
             for (int sb = s0; sb < s1; sb += kBatch) {
+                int jj[kBatch];
+                bool in[kBatch];
                 float4 pj[kBatch];
                 float aj[kBatch][KR1];
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
-                    const int j = (sb + u < s1) ? lR[(size_t)(sb + u) * N] : i;
-                    pj[u] = pb[j];
-                    const float *ajp = a.arad + ((size_t)b * N + j) * S * a.KRP + ti * a.KRP;
+                    const bool ok = sb + u < s1;
+                    jj[u] = ok ? uR[sb + u] : i;
+                    in[u] = ok && ((mR[ok ? sb + u : 0] >> b) & 1u);
+                    pj[u] = p4[(size_t)jj[u] * P + b];
+                    const float *ajp = a.arad + ((size_t)jj[u] * S + ti) * KR1 * P + b;
 #pragma unroll
-                    for (int q2 = 0; q2 < KR1; ++q2) aj[u][q2] = ajp[q2];
+                    for (int q2 = 0; q2 < KR1; ++q2) aj[u][q2] = ajp[(size_t)q2 * P];
                 }
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
-                    if (sb + u < s1) {
+                    if (in[u]) {
                         float dx, dy, dz;
-                        pair_vec(pj[u], pi, a, dx, dy, dz);
+                        pair_vec(pj[u], pi, lm, dx, dy, dz);
                         const float r2 = dx * dx + dy * dy + dz * dz;
                         const float rinv = __builtin_amdgcn_rsqf(r2);
                         const float r = r2 * rinv;
@@ -736,33 +493,40 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
             }
         }
 
-        // reverse angular terms: F_i -= dU_j/dr_ji for every angular neighbour j,
-        // deposited at this atom's own list positions by the angular pass
-        const int32_t *lA = a.listA + (size_t)b * a.capA * N + i;
-        const float4 *pbuf = a.pairbuf + (size_t)b * a.capA * N + i;
-        const int nA = a.endA[((size_t)b * kMaxSpecies + (S - 1)) * N + i];
+        // reverse angular terms: F_i -= dU_j/dr_ji for every angular neighbour j
+        const int32_t *uA = a.uniA + (size_t)i * a.capA;
+        const uint64_t *mA = a.umA + (size_t)i * a.capA;
+        const int32_t *rowA = a.candA + (size_t)i * a.capA;
+        const float4 *pbuf = a.pairbuf + (size_t)i * a.capA * P + b;
+        const int nA = a.uendA[(size_t)i * kMaxSpecies + S - 1];
         float gx = 0.0f, gy = 0.0f, gz = 0.0f;
         for (int sb = 0; sb < nA; sb += kBatch) {
+            int kk[kBatch];
+            bool in[kBatch];
             float4 d[kBatch];
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u)
-                d[u] = sb + u < nA ? pbuf[(size_t)(sb + u) * N] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            for (int u = 0; u < kBatch; ++u) {
+                const bool ok = sb + u < nA;
+                kk[u] = ok ? uA[sb + u] : 0;
+                in[u] = ok && ((mA[ok ? sb + u : 0] >> b) & 1u);
+                d[u] = in[u] ? pbuf[(size_t)kk[u] * P] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
                 gx -= d[u].x; gy -= d[u].y; gz -= d[u].z;
             }
             if (a.Watom) {
-                // reverse half of the per-atom split: +1/2 r_ij (x) dU_j/dr_ji
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
-                    if (sb + u < nA) {
-                        float dx, dy, dz;
-                        pair_vec(pb[lA[(size_t)(sb + u) * N]], pi, a, dx, dy, dz);
-                        const float hx = 0.5f * dx, hy = 0.5f * dy, hz = 0.5f * dz;
-                        Wa[0] = fmaf(hx, d[u].x, Wa[0]); Wa[1] = fmaf(hx, d[u].y, Wa[1]); Wa[2] = fmaf(hx, d[u].z, Wa[2]);
-                        Wa[3] = fmaf(hy, d[u].x, Wa[3]); Wa[4] = fmaf(hy, d[u].y, Wa[4]); Wa[5] = fmaf(hy, d[u].z, Wa[5]);
-                        Wa[6] = fmaf(hz, d[u].x, Wa[6]); Wa[7] = fmaf(hz, d[u].y, Wa[7]); Wa[8] = fmaf(hz, d[u].z, Wa[8]);
-                    }
+                    if (!in[u]) continue;
+                    float dx, dy, dz;
+                    pair_vec(p4[(size_t)(rowA[kk[u]] >> 2) * P + b], pi, lm, dx, dy, dz);
+                    const float4 dd = d[u];
+                    // reverse half of the per-atom split: +1/2 r_ij (x) dU_j/dr_ji
+                    const float hx = 0.5f * dx, hy = 0.5f * dy, hz = 0.5f * dz;
+                    Wa[0] = fmaf(hx, dd.x, Wa[0]); Wa[1] = fmaf(hx, dd.y, Wa[1]); Wa[2] = fmaf(hx, dd.z, Wa[2]);
+                    Wa[3] = fmaf(hy, dd.x, Wa[3]); Wa[4] = fmaf(hy, dd.y, Wa[4]); Wa[5] = fmaf(hy, dd.z, Wa[5]);
+                    Wa[6] = fmaf(hz, dd.x, Wa[6]); Wa[7] = fmaf(hz, dd.y, Wa[7]); Wa[8] = fmaf(hz, dd.z, Wa[8]);
                 }
             }
         }
@@ -771,61 +535,62 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
         Fz += (double)gz;
     }
     if (valid) {
-        const float *fa = a.Fang + ((size_t)b * N + i) * 3;
+        const float *fa = a.Fang + ((size_t)i * P + b) * 3;
         const double gx = Fx + (double)fa[0], gy = Fy + (double)fa[1], gz = Fz + (double)fa[2];
-        float *Fo = a.F + ((size_t)b * N + i) * 3;
+        float *Fo = a.F + ((size_t)b * a.N + i) * 3;
         Fo[0] = (float)gx;
         Fo[1] = (float)gy;
         Fo[2] = (float)gz;
         if (a.Watom) {
-            float *wo = a.Watom + ((size_t)b * N + i) * 9;
+            float *wo = a.Watom + ((size_t)b * a.N + i) * 9;
 #pragma unroll
             for (int e = 0; e < 9; ++e) wo[e] = (float)(Wv[e] + (double)Wa[e] + (double)wo[e]);
         }
         if (!(isfinite(gx) && isfinite(gy) && isfinite(gz))) atomicOr(a.flags, (uint32_t)NEP_FLAG_NONFINITE);
     }
-    __shared__ double lds[4];
-#pragma unroll
-    for (int e = 0; e < 9; ++e) {
-        const double w = block_sum(valid ? Wv[e] : 0.0, lds);
-        if (threadIdx.x == 0) a.partWr[((size_t)b * gridDim.x + tile) * 9 + e] = w;
-    }
+    __shared__ double lds[kBlock];
+    for (int e = 0; e < 9; ++e)
+        bead_block_sum(valid ? Wv[e] : 0.0, lds, P, a.lg, a.partWr + (size_t)blockIdx.x * P * 9 + e, 9);
 }
 
-// Per-bead totals from the per-block partial sums, in block order.
+// Per-(system, bead) totals from the per-workgroup partial sums of the
+// system's tiles, in tile order.
 __global__ void k_reduce(const double *__restrict__ partE, const double *__restrict__ partWa,
-                         const double *__restrict__ partWr, int nblk, double *__restrict__ E, double *__restrict__ W)
+                         const double *__restrict__ partWr, const int32_t *__restrict__ sys_tile0, int P,
+                         double *__restrict__ E, double *__restrict__ W)
 {
-    const int b = blockIdx.x, t = threadIdx.x;
+    const int sb = blockIdx.x, sy = sb / P, b = sb - sy * P, t = threadIdx.x;
+    const int k0 = sys_tile0[sy], k1 = sys_tile0[sy + 1];
     if (t == 0) {
         double s = 0.0;
-        for (int k = 0; k < nblk; ++k) s += partE[(size_t)b * nblk + k];
-        E[b] = s;
+        for (int k = k0; k < k1; ++k) s += partE[(size_t)k * P + b];
+        E[sb] = s;
     } else if (t <= 9) {
         double s = 0.0;
-        for (int k = 0; k < nblk; ++k) {
-            const size_t o = ((size_t)b * nblk + k) * 9 + (t - 1);
+        for (int k = k0; k < k1; ++k) {
+            const size_t o = ((size_t)k * P + b) * 9 + (t - 1);
             s += partWa[o] + partWr[o];
         }
-        W[(size_t)b * 9 + (t - 1)] = s;
+        W[(size_t)sb * 9 + (t - 1)] = s;
     }
 }
 
 template <int NR1, int NA1, bool FOUR>
-static void launch(const NepArgs &a, const float *prm, int P, hipStream_t s)
+static void launch(const NepArgs &a, const float *prm, int nblk, int wpb, hipStream_t s)
 {
-    const dim3 g(div_up(a.N, kBlock), P);
+    const dim3 g(nblk);
+    const dim3 blk(64 * wpb);
     {
         ProfScope ps_(K_DESCRIPTOR, s);
-        hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR>), g, dim3(kBlock), 0, s, a, prm);
+        hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR>), g, blk, 0, s, a, prm);
     }
     {
         ProfScope ps_(K_FORCE_ANG, s);
-        hipLaunchKernelGGL((k_force_ang<NA1, 9, (NA1 <= 5)>), g, dim3(kBlock), 0, s, a, prm);
+        hipLaunchKernelGGL((k_force_ang<NA1, 9, (NA1 <= 5)>), g, blk, 0, s, a, prm);
     }
     {
         ProfScope ps_(K_FORCE, s);
-        hipLaunchKernelGGL((k_force_rad<9>), g, dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((k_force_rad<9>), g, blk, 0, s, a);
     }
 }
 
@@ -833,46 +598,43 @@ static void launch(const NepArgs &a, const float *prm, int P, hipStream_t s)
 
 using namespace nep;
 
-extern "C" int32_t nep_compute(const nep_model *m, nep_nlist *nl, nep_ws *ws, const double *pos,
-                               const double box[9], const int32_t *types, int32_t P, int32_t N, double *E, float *F,
-                               double *W, float *E_atom, float *W_atom, hipStream_t s)
+extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws *ws, const double *pos,
+                                       const double *boxes, const int32_t *types, int32_t P, int32_t N, double *E,
+                                       float *F, double *W, float *E_atom, float *W_atom, hipStream_t s)
 {
-    if (!m || !nl || !ws || !box) return fail(NEP_ERR_INVALID_ARG, "nep_compute: null argument");
+    if (!m || !nl || !ws || !boxes) return fail(NEP_ERR_INVALID_ARG, "nep_compute: null argument");
     if (nl->P != P || nl->N != N || ws->P != P || ws->N != N || nl->S != m->hp.n_species || ws->S != m->hp.n_species ||
-        ws->NA1 != m->hp.n_max_angular + 1)
+        ws->NA1 != m->hp.n_max_angular + 1 || nl->off != ws->off)
         return fail(NEP_ERR_INVALID_ARG, "nep_compute: P=%d N=%d do not match the list/workspace handles", P, N);
     if (P == 0) return NEP_OK;
     if (!E || !W) return fail(NEP_ERR_INVALID_ARG, "nep_compute: null E or W");
+    const int nsys = nl->nsys;
     if (N == 0) {
-        fill_u32(reinterpret_cast<uint32_t *>(E), 0u, (size_t)P * 2, s);
-        fill_u32(reinterpret_cast<uint32_t *>(W), 0u, (size_t)P * 18, s);
+        fill_u32(reinterpret_cast<uint32_t *>(E), 0u, (size_t)nsys * P * 2, s);
+        fill_u32(reinterpret_cast<uint32_t *>(W), 0u, (size_t)nsys * P * 18, s);
         NEP_HIP(hipGetLastError());
         return NEP_OK;
     }
     if (!pos || !types || !F) return fail(NEP_ERR_INVALID_ARG, "nep_compute: null array");
-    NepArgs a{};
-    double L[3];
-    if (!box_lengths(box, L)) return fail(NEP_ERR_UNSUPPORTED, "nep_compute: only orthorhombic cells");
-    for (int d = 0; d < 3; ++d)
-        if (!(L[d] > 0.0) || !std::isfinite(L[d]))
-            return fail(NEP_ERR_INVALID_ARG, "nep_compute: bad box edge %g", L[d]);
-    const FineGrid fg = fine_grid(L, std::max(m->hp.rc_radial, m->hp.rc_angular));
-    if (!fg.exact)
-        return fail(NEP_ERR_BOX_TOO_SMALL, "nep_compute: box edges %g %g %g leave no margin over twice the cutoff",
-                    L[0], L[1], L[2]);
-    for (int d = 0; d < 3; ++d) {
-        a.M[d] = fg.M[d];
-        a.h[d] = fg.h[d];
+    if (!nl->built) return fail(NEP_ERR_INVALID_ARG, "nep_compute: the neighbour lists were never built");
+    for (int sy = 0; sy < nsys; ++sy) {
+        double L[3];
+        if (!box_lengths(boxes + 9 * sy, L)) return fail(NEP_ERR_UNSUPPORTED, "nep_compute: only orthorhombic cells");
+        if (L[0] != nl->boxL[3 * sy] || L[1] != nl->boxL[3 * sy + 1] || L[2] != nl->boxL[3 * sy + 2])
+            return fail(NEP_ERR_INVALID_ARG, "nep_compute: box of system %d differs from the last neighbor_build", sy);
     }
     const nep_hparams &h = m->hp;
-    a.p4 = reinterpret_cast<const float4 *>(ws->pos4); a.types = types; a.N = N; a.S = h.n_species; a.H = h.hidden;
+    NepArgs a{};
+    a.p4 = reinterpret_cast<const float4 *>(ws->pos4); a.pos = pos; a.types = types; a.N = N; a.S = h.n_species;
+    a.H = h.hidden; a.P = P; a.lg = lanes_log2(P);
+    a.geom = nl->geom; a.tile_atom0 = ws->tile_atom0; a.tile_atom1 = ws->tile_atom1; a.tile_sys = ws->tile_sys;
     a.rcRinv = (float)(1.0 / h.rc_radial); a.rcAinv = (float)(1.0 / h.rc_angular);
     a.kappa4 = (float)(-4.5 * std::sqrt(2.0 / 35.0) * std::pow(5.0 / (4.0 * M_PI), 1.5));
-    a.listR = nl->listR; a.endR = nl->endR; a.listA = nl->listA; a.endA = nl->endA; a.slotA = nl->slotA;
-    a.maskA = nl->maskA;
-    a.capR = nl->capR; a.capA = nl->capA; a.capC = nl->capC; a.WC = nl->WC;
+    a.candA = nl->candA; a.revA = nl->revA; a.uniR = nl->uniR; a.uendR = nl->uendR; a.uniA = nl->uniA;
+    a.umR = nl->umR; a.umA = nl->umA;
+    a.uendA = nl->uendA; a.capR = nl->capR; a.capA = nl->capA;
     a.pairbuf = reinterpret_cast<float4 *>(nl->pairbuf);
-    a.B = ws->B; a.arad = ws->arad; a.Fang = ws->Fang; a.KRP = ws->KRP;
+    a.B = ws->B; a.arad = ws->arad; a.Fang = ws->Fang;
     a.partE = ws->partE; a.partWa = ws->partW; a.partWr = ws->partW + (size_t)P * ws->nblk * 9;
     a.flags = ws->flags;
     a.F = F; a.Eatom = E_atom; a.Watom = W_atom;
@@ -881,19 +643,70 @@ extern "C" int32_t nep_compute(const nep_model *m, nep_nlist *nl, nep_ws *ws, co
     const int key = h.n_max_radial * 100 + h.n_max_angular * 10 + h.four_body;
     if (key != 440 && key != 441 && key != 640 && key != 860 && key != 881)
         return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");
-    pack_positions(pos, (size_t)P * N, fg, reinterpret_cast<float4 *>(ws->pos4), s);
+    pack_positions(pos, P, N, nl->atom_sys, nl->geom, reinterpret_cast<float4 *>(ws->pos4), s);
     switch (key) {
-    case 440: launch<5, 5, false>(a, m->dev, P, s); break;
-    case 441: launch<5, 5, true>(a, m->dev, P, s); break;
-    case 640: launch<7, 5, false>(a, m->dev, P, s); break;
-    case 860: launch<9, 7, false>(a, m->dev, P, s); break;
-    case 881: launch<9, 9, true>(a, m->dev, P, s); break;
+    case 440: launch<5, 5, false>(a, m->dev, ws->nblk, ws->wpb, s); break;
+    case 441: launch<5, 5, true>(a, m->dev, ws->nblk, ws->wpb, s); break;
+    case 640: launch<7, 5, false>(a, m->dev, ws->nblk, ws->wpb, s); break;
+    case 860: launch<9, 7, false>(a, m->dev, ws->nblk, ws->wpb, s); break;
+    case 881: launch<9, 9, true>(a, m->dev, ws->nblk, ws->wpb, s); break;
     default: return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");
     }
     {
         ProfScope ps_(K_REDUCE, s);
-        hipLaunchKernelGGL(k_reduce, dim3(P), dim3(64), 0, s, ws->partE, a.partWa, a.partWr, ws->nblk, E, W);
+        hipLaunchKernelGGL(k_reduce, dim3(nsys * P), dim3(64), 0, s, ws->partE, a.partWa, a.partWr, ws->sys_tile0, P,
+                           E, W);
     }
     NEP_HIP(hipGetLastError());
     return NEP_OK;
+}
+
+extern "C" int32_t nep_compute(const nep_model *m, nep_nlist *nl, nep_ws *ws, const double *pos,
+                               const double box[9], const int32_t *types, int32_t P, int32_t N, double *E, float *F,
+                               double *W, float *E_atom, float *W_atom, hipStream_t s)
+{
+    if (nl && nl->nsys != 1) return fail(NEP_ERR_INVALID_ARG, "nep_compute: the list holds a batch of systems");
+    return nep_compute_batched(m, nl, ws, pos, box, types, P, N, E, F, W, E_atom, W_atom, s);
+}
+
+extern "C" int32_t nep_autotune(const nep_model *m, nep_nlist *nl, nep_ws *ws, const double *pos, const double *boxes,
+                                const int32_t *types, int32_t P, int32_t N, double *E, float *F, double *W,
+                                int32_t reps, float *ms_out, int32_t *best_out, hipStream_t s)
+{
+    if (!m || !nl || !ws) return fail(NEP_ERR_INVALID_ARG, "nep_autotune: null argument");
+    if (reps < 1 || reps > 100) return fail(NEP_ERR_INVALID_ARG, "nep_autotune: reps must be in 1..100");
+    const int choices[3] = {1, 2, 4};
+    float best_ms = 0.0f;
+    int best = 4;
+    hipEvent_t e0, e1;
+    NEP_HIP(hipEventCreate(&e0));
+    NEP_HIP(hipEventCreate(&e1));
+    int32_t rc = NEP_OK;
+    for (int c = 0; c < 3 && rc == NEP_OK; ++c) {
+        rc = nep_ws_set_tile(ws, choices[c]);
+        if (rc != NEP_OK) break;
+        rc = nep_compute_batched(m, nl, ws, pos, boxes, types, P, N, E, F, W, nullptr, nullptr, s);   // warm-up
+        if (rc != NEP_OK) break;
+        if (hipEventRecord(e0, s) != hipSuccess) rc = fail(NEP_ERR_HIP, "nep_autotune: event record failed");
+        for (int r = 0; r < reps && rc == NEP_OK; ++r)
+            rc = nep_compute_batched(m, nl, ws, pos, boxes, types, P, N, E, F, W, nullptr, nullptr, s);
+        if (rc != NEP_OK) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = fail(NEP_ERR_HIP, "nep_autotune: event timing failed");
+            break;
+        }
+        ms /= (float)reps;
+        if (ms_out) ms_out[c] = ms;
+        if (c == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = choices[c];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != NEP_OK) return rc;
+    if (best_out) *best_out = best;
+    return nep_ws_set_tile(ws, best);
 }

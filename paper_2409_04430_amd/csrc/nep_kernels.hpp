@@ -1,0 +1,112 @@
+// Arguments, lane mapping and reductions shared by the NEP force kernels
+// and the training kernels: one workgroup per tile (an atom range of one
+// system), the P beads of an atom in adjacent lanes.
+#pragma once
+
+#include "internal.hpp"
+#include "nep_math.hpp"
+
+namespace nep {
+
+struct NepArgs {
+    const float4 *p4;    // [N][P] packed positions (bead-minor)
+    const double *pos;   // [P][N][3] FP64 positions (exact test near the cutoff)
+    const int32_t *types;
+    int N, S, H, P, lg;  // lg: log2 of the lanes per atom
+    const SysGeom *geom; // per system: fine grid of the packed positions
+    const int32_t *tile_atom0, *tile_atom1, *tile_sys;   // per workgroup: atom range and system
+    float rcRinv, rcAinv;
+    float kappa4;
+    // candidate rows and union lists of the neighbour handle
+    const int32_t *candA, *revA, *uniR, *uendR, *uniA, *uendA;
+    const uint64_t *umR, *umA;   // bead masks of the union entries
+    int capR, capA;
+    float4 *pairbuf;     // [N][capA][P] dU_j/dr_ji at the receiving atom's angular slot of j
+    // workspace
+    float *B;            // [N][P][NA1*24]
+    float *arad;         // [N][S][9][P]
+    float *Fang;         // [N][P][3]
+    double *partE, *partWa, *partWr;   // [blocks][P], [blocks][P][9]
+    uint32_t *flags;
+    // outputs
+    float *F;
+    float *Eatom;
+    float *Watom;
+    // parameter offsets
+    int oR, oA, oq, oW0, ob0, ow1, ob1, osh;
+};
+
+// Lane -> (atom, bead): the beads of one atom occupy 2^lg adjacent lanes;
+// a workgroup takes one tile (an atom range of one system).  M and h are
+// the fine grid of the tile's system (wave-uniform).
+struct LaneMap {
+    int i, b;        // atom and bead (clamped into range for idle lanes)
+    bool valid;      // a real (atom, bead)
+    int M[3];
+    float h[3];
+};
+__device__ __forceinline__ LaneMap lane_map(const NepArgs &a)
+{
+    const int lane = threadIdx.x & 63;
+    const int a0 = a.tile_atom0[blockIdx.x], a1 = a.tile_atom1[blockIdx.x];
+    const int ia = a0 + (threadIdx.x >> 6) * (64 >> a.lg) + (lane >> a.lg);
+    const int b = lane & ((1 << a.lg) - 1);
+    LaneMap m;
+    m.valid = ia < a1 && b < a.P;
+    m.i = ia < a1 ? ia : a1 - 1;
+    m.b = b < a.P ? b : a.P - 1;
+    const SysGeom &g = a.geom[a.tile_sys[blockIdx.x]];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        m.M[d] = g.M[d];
+        m.h[d] = g.h[d];
+    }
+    return m;
+}
+
+// Start and end of species block t in a union list.
+__device__ __forceinline__ void block_range(const int32_t *uend, int i, int t, int &s0, int &s1)
+{
+    s0 = t ? uend[(size_t)i * kMaxSpecies + t - 1] : 0;
+    s1 = uend[(size_t)i * kMaxSpecies + t];
+}
+
+// Pair vector r_j - r_i from packed positions (see FineGrid).
+__device__ __forceinline__ void pair_vec(const float4 &pj, const float4 &pi, const LaneMap &lm, float &dx, float &dy,
+                                         float &dz)
+{
+    packed_pair(pj, pi, lm.M, lm.h, dx, dy, dz);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Per-bead sums over the atoms of a block in a fixed order: thread b < P
+// adds the values of the lanes of bead b and writes out[b * stride].
+__device__ __forceinline__ void bead_block_sum(double v, double *lds, int P, int lg, double *out, int stride)
+{
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    if ((int)threadIdx.x < P) {
+        double s = 0.0;
+        for (int x = threadIdx.x; x < (int)blockDim.x; x += 1 << lg) s += lds[x];
+        out[(size_t)threadIdx.x * stride] = s;
+    }
+    __syncthreads();
+}
+
+constexpr int kBatch = 4;   // neighbours whose index and position are loaded together
+
+// Hide a uniform pointer from loop-invariant code motion, so that the model
+// coefficients it addresses are re-read through the scalar cache inside a
+// neighbour loop instead of being hoisted into (scarce) vector registers.
+__device__ __forceinline__ const float *launder(const float *p)
+{
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+}  // namespace nep

@@ -11,44 +11,53 @@
 //
 // Candidates: the P beads of an atom stay within D of their centroid, so a
 // bead pair closer than rc has centroids closer than rc + 2D.  One cell-list
-// search over the N centroids (radius rc_radial + 2D, the larger cutoff)
-// gives each atom one candidate row, sorted by (species, index), and for
-// every candidate the slot at which the atom sits in the candidate's own
-// row.  Each bead then filters the row exactly into compact radial and
-// angular lists (slot-major, so that lanes read them coalesced), with
-// per-species block ends; each angular entry also carries the candidate
-// slot and the reverse slot used to address the angular pair terms.
-// D, the cell grid and the radius are computed on the device in the same
+// search over the N centroids gives each atom two candidate rows (radius
+// rc_radial + 2D and rc_angular + 2D, plus the skin when rows are reused),
+// sorted by (species, index), and for the angular row the slot at which the
+// atom sits in each candidate's own row.  Every call then keeps, per atom,
+// the slots whose candidate is inside the cutoff for at least one bead (the
+// union lists the force kernels walk, one atom's beads in adjacent lanes).
+// D, the cell grid and the radii are computed on the device in the same
 // call, so the launch sequence needs no host round trip.
 //
-// Kernels per call: centroids and D -> grid -> count atoms per cell -> scan
-// -> scatter -> order each cell -> candidate rows (a workgroup per cell,
-// stencil centroids staged in LDS) -> sort rows -> reverse slots ->
-// per-bead exact lists.
+// Kernels per call: pack positions -> centroids, D and drift -> rebuild
+// decision and grid; on a rebuild: count atoms per cell -> scan -> scatter
+// -> order each cell -> candidate rows (a workgroup per cell, stencil
+// centroids staged in LDS) -> sort rows -> reverse slots; always: union
+// lists.
 #include "internal.hpp"
 
 namespace nep {
 
-struct HostGrid {
-    double L[3], invL[3];
-    int nc_cap[3];     // allocation bound: floor(L / rc) per axis, at most 64
-    double rcR, rcA;
-};
-
-// Device grid record.  Words 0-3 and 7-9 describe the candidate rows of the
-// last rebuild and persist across calls; 4-5 are per-call maxima; 6 is the
-// rebuild decision of this call.
-struct DevGrid {
-    int nc[3];
-    int ncell;
+// Device grid record: 16 global words, then 4 words per system.
+// Global words 2-3 and 5-11 describe the candidate rows of the last rebuild
+// and persist across calls; 0-1 are per-call maxima; 4 is the rebuild
+// decision of this call.
+struct DevGlobal {
     uint32_t spread_bits;   // D of this call (float bits, atomicMax)
     uint32_t disp_bits;     // largest centroid displacement since the rebuild (float bits)
-    int rebuild;            // 1: rebuild the candidate rows in this call
     float d_build;          // D at the last rebuild
-    double R2;              // candidate radius squared of the last rebuild
     uint32_t rows_overflow; // a candidate row of the last rebuild was truncated
+    int rebuild;            // 1: rebuild the candidate rows in this call
+    int pad;
+    double R2;              // radial candidate radius squared of the last rebuild
+    double RA2;             // angular candidate radius squared
 };
-static_assert(sizeof(DevGrid) <= 16 * sizeof(uint32_t), "grid record exceeds its 16-word buffer");
+static_assert(sizeof(DevGlobal) <= 16 * sizeof(uint32_t), "grid record exceeds its 16 global words");
+struct DevSys {
+    int nc[3];              // cells per axis of this system (last rebuild)
+    int ncell;
+};
+__device__ __forceinline__ DevGlobal *dev_global(uint32_t *grid) { return reinterpret_cast<DevGlobal *>(grid); }
+__device__ __forceinline__ const DevGlobal *dev_global(const uint32_t *grid)
+{
+    return reinterpret_cast<const DevGlobal *>(grid);
+}
+__device__ __forceinline__ DevSys *dev_sys(uint32_t *grid, int s) { return reinterpret_cast<DevSys *>(grid + 16) + s; }
+__device__ __forceinline__ const DevSys *dev_sys(const uint32_t *grid, int s)
+{
+    return reinterpret_cast<const DevSys *>(grid + 16) + s;
+}
 
 __device__ __forceinline__ int cell_axis(double x, double L, double invL, int nc)
 {
@@ -57,25 +66,6 @@ __device__ __forceinline__ int cell_axis(double x, double L, double invL, int nc
     if (!(s >= 0.0) || !(s < 1.0)) s = 0.0;   // NaN / Inf, or s rounded up to 1
     int c = (int)(s * nc);
     return c >= nc ? nc - 1 : c;
-}
-
-// Exact minimum-image squared distance (see the file comment).
-__device__ __forceinline__ double mic_r2_exact(const double *ri, const double *rj, const HostGrid &g)
-{
-#pragma clang fp contract(off)
-    double e2[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const double d = rj[a] - ri[a];
-        const double t = d * g.invL[a];
-        double k = rint(t);
-        const double off = t - k;
-        if (!(fabs(off) < 0.499999999) || !(fabs(t) < 1048576.0)) k = rint(d / g.L[a]);
-        const double sft = g.L[a] * k;
-        const double e = d - sft;
-        e2[a] = e * e;
-    }
-    return (e2[0] + e2[1]) + e2[2];
 }
 
 __device__ __forceinline__ int wave_max_i(int v)
@@ -133,8 +123,8 @@ __global__ void k_centroid(const double *__restrict__ pos, const int32_t *__rest
     }
     spread = wave_max_f(spread);
     disp = wave_max_f(disp);
-    if ((threadIdx.x & 63) == 0 && spread > 0.0f) atomicMax(&grid[4], __float_as_uint(spread));
-    if ((threadIdx.x & 63) == 0 && disp > 0.0f) atomicMax(&grid[5], __float_as_uint(disp));
+    if ((threadIdx.x & 63) == 0 && spread > 0.0f) atomicMax(&grid[0], __float_as_uint(spread));
+    if ((threadIdx.x & 63) == 0 && disp > 0.0f) atomicMax(&grid[1], __float_as_uint(disp));
     if (f) atomicOr(&status[0], f);
 }
 
@@ -142,13 +132,33 @@ __global__ void k_centroid(const double *__restrict__ pos, const int32_t *__rest
 // measured spread.  Candidate rows built with radius rc + 2 D0 + skin stay
 // complete while 2 (D - D0) + 2 max|c - c0| <= skin (triangle inequality on
 // the periodic centroid distance); otherwise they are rebuilt.
-__global__ void k_grid(HostGrid g, double skin, int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status)
+__global__ __launch_bounds__(64) void k_grid(const SysGeom *__restrict__ geom, int nsys, double rcR, double rcA,
+                                             double skin, int force, uint32_t *__restrict__ grid,
+                                             uint32_t *__restrict__ status)
 {
-    DevGrid *dg = reinterpret_cast<DevGrid *>(grid);
+    DevGlobal *dg = dev_global(grid);
     const float spread = __uint_as_float(dg->spread_bits);
     const float disp = __uint_as_float(dg->disp_bits);
     const double need = 2.0 * ((double)spread - (double)dg->d_build) + 2.0 * (double)disp;
     const int rebuild = force || !(need <= skin);
+    const double rc = rcR > rcA ? rcR : rcA;
+    const double R = rc + 2.0 * (double)spread + skin + 1e-9 * (1.0 + rc);
+    const double RA = rcA + 2.0 * (double)spread + skin + 1e-9 * (1.0 + rcA);
+    if (rebuild) {
+        for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
+            int ncell = 1;
+            DevSys *ds = dev_sys(grid, s);
+            for (int a = 0; a < 3; ++a) {
+                int nc = (int)floor(geom[s].L[a] / (R * (1.0 + 1e-9)));
+                nc = nc < 1 ? 1 : (nc > geom[s].nc_cap[a] ? geom[s].nc_cap[a] : nc);
+                ds->nc[a] = nc;
+                ncell *= nc;
+            }
+            ds->ncell = ncell;
+        }
+    }
+    __syncthreads();   // every thread has read the record of the last rebuild
+    if (threadIdx.x != 0) return;
     dg->rebuild = rebuild;
     atomicMax(&status[4], dg->spread_bits);
     if (!rebuild) {
@@ -157,39 +167,36 @@ __global__ void k_grid(HostGrid g, double skin, int force, uint32_t *__restrict_
         return;
     }
     dg->rows_overflow = 0;
-    const double rc = g.rcR > g.rcA ? g.rcR : g.rcA;
-    const double R = rc + 2.0 * (double)spread + skin + 1e-9 * (1.0 + rc);
-    int ncell = 1;
-    for (int a = 0; a < 3; ++a) {
-        int nc = (int)floor(g.L[a] / (R * (1.0 + 1e-9)));
-        nc = nc < 1 ? 1 : (nc > g.nc_cap[a] ? g.nc_cap[a] : nc);
-        dg->nc[a] = nc;
-        ncell *= nc;
-    }
-    dg->ncell = ncell;
     dg->R2 = R * R;
+    dg->RA2 = RA * RA;
     dg->d_build = spread;
     atomicAdd(&status[5], 1u);
 }
 
-__global__ void k_cell_count(const double *__restrict__ cen, int N, HostGrid g, const uint32_t *__restrict__ grid,
+// Global cell of atom i's centroid (system s).
+__device__ __forceinline__ int atom_cell(const double *__restrict__ cen, int i, const SysGeom &g, const DevSys &ds)
+{
+    const int cx = cell_axis(cen[3 * i], g.L[0], g.invL[0], ds.nc[0]);
+    const int cy = cell_axis(cen[3 * i + 1], g.L[1], g.invL[1], ds.nc[1]);
+    const int cz = cell_axis(cen[3 * i + 2], g.L[2], g.invL[2], ds.nc[2]);
+    return g.cell_base + (cz * ds.nc[1] + cy) * ds.nc[0] + cx;
+}
+
+__global__ void k_cell_count(const double *__restrict__ cen, int N, const int32_t *__restrict__ atom_sys,
+                             const SysGeom *__restrict__ geom, const uint32_t *__restrict__ grid,
                              int32_t *__restrict__ cell_cnt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const DevGrid *dg = reinterpret_cast<const DevGrid *>(grid);
-    if (i >= N || !dg->rebuild) return;
-    const int cx = cell_axis(cen[3 * i], g.L[0], g.invL[0], dg->nc[0]);
-    const int cy = cell_axis(cen[3 * i + 1], g.L[1], g.invL[1], dg->nc[1]);
-    const int cz = cell_axis(cen[3 * i + 2], g.L[2], g.invL[2], dg->nc[2]);
-    atomicAdd(&cell_cnt[(cz * dg->nc[1] + cy) * dg->nc[0] + cx], 1);
+    if (i >= N || !dev_global(grid)->rebuild) return;
+    const int s = atom_sys[i];
+    atomicAdd(&cell_cnt[atom_cell(cen, i, geom[s], *dev_sys(grid, s))], 1);
 }
 
-__global__ __launch_bounds__(1024) void k_cell_scan(const uint32_t *__restrict__ grid, int32_t *__restrict__ cnt,
-                                                    int32_t *__restrict__ st)
+__global__ __launch_bounds__(1024) void k_cell_scan(const uint32_t *__restrict__ grid, int ncell,
+                                                    int32_t *__restrict__ cnt, int32_t *__restrict__ st)
 {
     __shared__ int32_t part[1024];
-    if (!reinterpret_cast<const DevGrid *>(grid)->rebuild) return;   // whole workgroup
-    const int ncell = reinterpret_cast<const DevGrid *>(grid)->ncell;
+    if (!dev_global(grid)->rebuild) return;   // whole workgroup
     const int t = threadIdx.x;
     const int per = (ncell + 1023) / 1024;
     const int c0 = min(t * per, ncell), c1 = min(c0 + per, ncell);
@@ -212,17 +219,15 @@ __global__ __launch_bounds__(1024) void k_cell_scan(const uint32_t *__restrict__
     if (t == 1023) st[ncell] = part[1023];
 }
 
-__global__ void k_cell_fill(const double *__restrict__ cen, int N, HostGrid g, const uint32_t *__restrict__ grid,
+__global__ void k_cell_fill(const double *__restrict__ cen, int N, const int32_t *__restrict__ atom_sys,
+                            const SysGeom *__restrict__ geom, const uint32_t *__restrict__ grid,
                             int32_t *__restrict__ cell_cnt, const int32_t *__restrict__ cell_start,
                             int32_t *__restrict__ cell_atoms)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const DevGrid *dg = reinterpret_cast<const DevGrid *>(grid);
-    if (i >= N || !dg->rebuild) return;
-    const int cx = cell_axis(cen[3 * i], g.L[0], g.invL[0], dg->nc[0]);
-    const int cy = cell_axis(cen[3 * i + 1], g.L[1], g.invL[1], dg->nc[1]);
-    const int cz = cell_axis(cen[3 * i + 2], g.L[2], g.invL[2], dg->nc[2]);
-    const int c = (cz * dg->nc[1] + cy) * dg->nc[0] + cx;
+    if (i >= N || !dev_global(grid)->rebuild) return;
+    const int s = atom_sys[i];
+    const int c = atom_cell(cen, i, geom[s], *dev_sys(grid, s));
     const int slot = atomicAdd(&cell_cnt[c], 1);
     cell_atoms[cell_start[c] + slot] = i;
 }
@@ -237,8 +242,7 @@ __global__ __launch_bounds__(64) void k_cell_rank(const uint32_t *__restrict__ g
     __shared__ int32_t v[kRankMax];
     __shared__ int32_t out[kRankMax];
     const int c = blockIdx.x;
-    if (!reinterpret_cast<const DevGrid *>(grid)->rebuild || c >= reinterpret_cast<const DevGrid *>(grid)->ncell)
-        return;
+    if (!dev_global(grid)->rebuild) return;   // whole workgroup; unused cells are empty
     const int s0 = cell_start[c], n = cell_start[c + 1] - s0;
     int32_t *a = cell_atoms + s0;
     if (n <= kRankMax) {
@@ -273,21 +277,26 @@ __global__ __launch_bounds__(64) void k_cell_rank(const uint32_t *__restrict__ g
 // A stencil too large for LDS is read from global memory instead.
 constexpr int kStage = 2048;
 __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ cen, const int32_t *__restrict__ types,
-                                                    int N, int S, HostGrid g, uint32_t *__restrict__ grid,
+                                                    int N, int S, const SysGeom *__restrict__ geom,
+                                                    const int32_t *__restrict__ cell_sys, uint32_t *__restrict__ grid,
                                                     const int32_t *__restrict__ cell_start,
-                                                    const int32_t *__restrict__ cell_atoms, int capC,
-                                                    int32_t *__restrict__ cand, int32_t *__restrict__ rowlen,
+                                                    const int32_t *__restrict__ cell_atoms, int capR, int capA,
+                                                    int32_t *__restrict__ candR, int32_t *__restrict__ lenR,
+                                                    int32_t *__restrict__ candA, int32_t *__restrict__ lenA,
                                                     double *__restrict__ cen_ref, uint32_t *__restrict__ status)
 {
     __shared__ double sx[kStage], sy[kStage], sz[kStage];
     __shared__ int32_t sw[kStage];
     __shared__ int32_t rs[28], rp[28];
     __shared__ int nrange;
-    DevGrid *dg = reinterpret_cast<DevGrid *>(grid);
-    const int c = blockIdx.x;
-    if (!dg->rebuild || c >= dg->ncell) return;   // whole workgroup
-    const int nc0 = dg->nc[0], nc1 = dg->nc[1], nc2 = dg->nc[2];
-    const double R2 = dg->R2;
+    DevGlobal *dg = dev_global(grid);
+    const int sy_ = cell_sys[blockIdx.x];
+    const SysGeom &g = geom[sy_];
+    const DevSys ds = *dev_sys(grid, sy_);
+    const int c = blockIdx.x - g.cell_base;   // cell within its system
+    if (!dg->rebuild || c >= ds.ncell) return;   // whole workgroup
+    const int nc0 = ds.nc[0], nc1 = ds.nc[1], nc2 = ds.nc[2];
+    const double R2 = dg->R2, RA2 = dg->RA2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     if (threadIdx.x == 0) {
         const int cx = c % nc0, cy = (c / nc0) % nc1, cz = c / (nc0 * nc1);
@@ -302,7 +311,7 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
                 for (int ox = 0; ox < ox_n; ++ox) {
                     int x = nc0 >= 3 ? cx + ox - 1 : ox;
                     x = x < 0 ? x + nc0 : (x >= nc0 ? x - nc0 : x);
-                    const int cc = (z * nc1 + y) * nc0 + x;
+                    const int cc = g.cell_base + (z * nc1 + y) * nc0 + x;
                     rs[nr] = cell_start[cc];
                     rp[nr] = tot;
                     tot += cell_start[cc + 1] - cell_start[cc];
@@ -334,15 +343,16 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
     }
     __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int a0 = cell_start[c], a1 = cell_start[c + 1];
+    const int a0 = cell_start[blockIdx.x], a1 = cell_start[blockIdx.x + 1];
     for (int a = a0 + wv; a < a1; a += blockDim.x >> 6) {
         const int i = cell_atoms[a];
         const double ci[3] = {cen[3 * i], cen[3 * i + 1], cen[3 * i + 2]};
-        int32_t *row = cand + (size_t)i * capC;
-        int cnt = 0;
+        int32_t *rowR = candR + (size_t)i * capR;
+        int32_t *rowA = candA + (size_t)i * capA;
+        int cR = 0, cA = 0;
         for (int q0 = 0; q0 < total; q0 += 64) {
             const int q = q0 + lane;
-            bool ok = false;
+            bool okR = false, okA = false;
             int w = -1;
             if (q < total) {
                 double p[3];
@@ -363,21 +373,26 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
                         d -= g.L[e] * rint(d * g.invL[e]);
                         r2 += d * d;
                     }
-                    ok = r2 < R2;
+                    okR = r2 < R2;
+                    okA = r2 < RA2;
                 }
             }
-            const uint64_t m = __ballot(ok);
-            const int pos = cnt + __popcll(m & below);
-            if (ok && pos < capC) row[pos] = w;
-            cnt += __popcll(m);
+            const uint64_t mR = __ballot(okR), mA = __ballot(okA);
+            const int pR = cR + __popcll(mR & below), pA = cA + __popcll(mA & below);
+            if (okR && pR < capR) rowR[pR] = w;
+            if (okA && pA < capA) rowA[pA] = w;
+            cR += __popcll(mR);
+            cA += __popcll(mA);
         }
         if (lane == 0) {
-            rowlen[i] = cnt;
+            lenR[i] = cR;
+            lenA[i] = cA;
             cen_ref[3 * i] = ci[0];
             cen_ref[3 * i + 1] = ci[1];
             cen_ref[3 * i + 2] = ci[2];
-            atomicMax(&status[3], (uint32_t)cnt);
-            if (cnt > capC) {
+            atomicMax(&status[3], (uint32_t)cR);
+            atomicMax(&status[6], (uint32_t)cA);
+            if (cR > capR || cA > capA) {
                 atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
                 atomicOr(&dg->rows_overflow, 1u);
             }
@@ -394,7 +409,7 @@ __global__ __launch_bounds__(256) void k_sort_rows(const uint32_t *__restrict__ 
                                                    int32_t *__restrict__ cand, const int32_t *__restrict__ rowlen,
                                                    int32_t *__restrict__ off, int32_t *__restrict__ scratch)
 {
-    if (!reinterpret_cast<const DevGrid *>(grid)->rebuild) return;   // whole workgroup
+    if (!dev_global(grid)->rebuild) return;   // whole workgroup
     __shared__ int32_t buf[kBlock / 64][kSortLds];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = blockIdx.x * (kBlock / 64) + wv;
@@ -439,7 +454,7 @@ __global__ __launch_bounds__(256) void k_reverse(const uint32_t *__restrict__ gr
                                                  const int32_t *__restrict__ types, const int32_t *__restrict__ cand,
                                                  const int32_t *__restrict__ off, int32_t *__restrict__ rev)
 {
-    if (!reinterpret_cast<const DevGrid *>(grid)->rebuild) return;   // whole workgroup
+    if (!dev_global(grid)->rebuild) return;   // whole workgroup
     const int lane = threadIdx.x & 63;
     const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     if (i >= N) return;
@@ -461,159 +476,211 @@ __global__ __launch_bounds__(256) void k_reverse(const uint32_t *__restrict__ gr
     }
 }
 
-// Per-bead exact lists.  One lane per (bead, atom); candidates are taken in
-// batches so that several position loads are in flight at once.  The test
-// runs first on the packed FP32 positions; only a pair whose FP32 squared
-// distance lies within `margin` of a cutoff squared (far above the packed
-// error bound) is decided by the FP64 test, so every decision equals the
-// FP64 one.
-constexpr int kFilterBatch = 8;
-__global__ __launch_bounds__(256) void k_filter(const double *__restrict__ pos, const float4 *__restrict__ pos4,
-                                                FineGrid fg, float margin, int N, int S, HostGrid g,
-                                                const int32_t *__restrict__ cand, const int32_t *__restrict__ off,
-                                                const int32_t *__restrict__ rev, int capC, int capR, int capA,
-                                                double rcR2, double rcA2, int32_t *__restrict__ listR,
-                                                int32_t *__restrict__ endR, int32_t *__restrict__ listA,
-                                                int32_t *__restrict__ endA, int32_t *__restrict__ slotA,
-                                                uint64_t *__restrict__ maskA, uint32_t *__restrict__ status)
+// Union lists.  The beads of an atom sit in G = 2^lg adjacent lanes; each
+// lane group walks its atom's candidate rows and keeps a candidate when the
+// pair is inside the cutoff for at least one bead (ballot over the group):
+// the radial list stores the atom index j, the angular list the slot k, and
+// both the bead mask of the exact decision, so that the force kernels take
+// it from there.
+__global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, const float4 *__restrict__ pos4, int P,
+                                               int N, int S, int lg, const int32_t *__restrict__ atom_sys,
+                                               const SysGeom *__restrict__ geom, CutTest cR, CutTest cA,
+                                               const int32_t *__restrict__ candR, const int32_t *__restrict__ offR,
+                                               const int32_t *__restrict__ candA, const int32_t *__restrict__ offA,
+                                               int capR, int capA, int32_t *__restrict__ uniR,
+                                               uint64_t *__restrict__ umR, int32_t *__restrict__ uendR,
+                                               int32_t *__restrict__ uniA, uint64_t *__restrict__ umA,
+                                               int32_t *__restrict__ uendA, uint32_t *__restrict__ status)
 {
-    int b, tile;
-    bead_tile(b, tile);
-    const int i = tile * blockDim.x + threadIdx.x;
-    int sR = 0, sA = 0;
-    if (i < N) {
-        const double *pb = pos + (size_t)b * N * 3;
-        const float4 *p4 = pos4 + (size_t)b * N;
-        const float4 pi = p4[i];
-        const float rR2f = (float)rcR2, rA2f = (float)rcA2;
-        const int32_t *row = cand + (size_t)i * capC;
-        const int32_t *rrow = rev + (size_t)i * capC;
-        const int32_t *oi = off + (size_t)i * (kMaxSpecies + 1);
-        int32_t *lR = listR + (size_t)b * capR * N + i;
-        int32_t *lA = listA + (size_t)b * capA * N + i;
-        int32_t *sl = slotA + (size_t)b * capA * N + i;
-        uint64_t *mk = maskA + (size_t)b * ((capC + 31) >> 5) * N + i;
-        uint32_t word = 0;   // angular hits of the current 32-slot word
-        int wcur = 0;        // index of that word
-        int before = 0;      // angular hits in the words before it
+    const int lane = threadIdx.x & 63, G = 1 << lg;
+    const int ia = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 >> lg) + (lane >> lg);
+    const int b = lane & (G - 1);
+    const bool atom_ok = ia < N, bead_ok = b < P;
+    const int i = atom_ok ? ia : N - 1;
+    const int bb = bead_ok ? b : P - 1;
+    const float4 pi = pos4[(size_t)i * P + bb];
+    const double *pb = pos + (size_t)bb * N * 3;
+    const SysGeom &g = geom[atom_sys[i]];
+    const BoxD box{{g.L[0], g.L[1], g.L[2]}, {g.invL[0], g.invL[1], g.invL[2]}};
+    const int base = lane & ~(G - 1);
+    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << base);
+    int most[2] = {0, 0};
+#pragma unroll
+    for (int kind = 0; kind < 2; ++kind) {
+        const int cap = kind ? capA : capR;
+        const int32_t *row = (kind ? candA : candR) + (size_t)i * cap;
+        const int32_t *o = (kind ? offA : offR) + (size_t)i * (kMaxSpecies + 1);
+        int32_t *uni = (kind ? uniA : uniR) + (size_t)i * cap;
+        uint64_t *um = (kind ? umA : umR) + (size_t)i * cap;
+        int32_t *uend = (kind ? uendA : uendR) + (size_t)i * kMaxSpecies;
+        const CutTest c = kind ? cA : cR;
+        int cnt = 0;
         for (int t = 0; t < S; ++t) {
-            const int k0 = min(oi[t], capC), k1 = min(oi[t + 1], capC);
-            for (int kb = k0; kb < k1; kb += kFilterBatch) {
-                int w[kFilterBatch];
-                float4 pj[kFilterBatch];
-#pragma unroll
-                for (int u = 0; u < kFilterBatch; ++u) {
-                    const int k = kb + u;
-                    w[u] = row[k < k1 ? k : k0];
-                    pj[u] = p4[w[u] >> 2];
-                }
-#pragma unroll
-                for (int u = 0; u < kFilterBatch; ++u) {
-                    const int k = kb + u;
-                    if (k < k1) {
-                        float dx, dy, dz;
-                        packed_pair(pj[u], pi, fg.M, fg.h, dx, dy, dz);
-                        const float r2f = dx * dx + dy * dy + dz * dz;
-                        bool inR = r2f < rR2f, inA = r2f < rA2f;
-                        if (fabsf(r2f - rR2f) <= margin || fabsf(r2f - rA2f) <= margin) {
-                            const int j = w[u] >> 2;
-                            const double ri[3] = {pb[3 * i], pb[3 * i + 1], pb[3 * i + 2]};
-                            const double rj[3] = {pb[3 * j], pb[3 * j + 1], pb[3 * j + 2]};
-                            const double r2 = mic_r2_exact(ri, rj, g);
-                            inR = r2 < rcR2;
-                            inA = r2 < rcA2;
-                        }
-                        while ((k >> 5) > wcur) {   // close the finished words
-                            mk[(size_t)wcur * N] = (uint64_t)word | ((uint64_t)before << 32);
-                            before += __popc(word);
-                            word = 0;
-                            ++wcur;
-                        }
-                        if (inR) {
-                            if (sR < capR) lR[(size_t)sR * N] = w[u] >> 2;
-                            ++sR;
-                            if (inA) {
-                                word |= 1u << (k & 31);
-                                if (sA < capA) {
-                                    lA[(size_t)sA * N] = w[u] >> 2;
-                                    sl[(size_t)sA * N] = k | (int32_t)((uint32_t)(rrow[k] & 0xffff) << 16);
-                                }
-                                ++sA;
-                            }
-                        }
+            const int k0 = min(o[t], cap), k1 = min(o[t + 1], cap);
+            for (int k = k0; k < k1; ++k) {
+                const int j = row[k] >> 2;
+                const float4 pj = pos4[(size_t)j * P + bb];
+                float dx, dy, dz;
+                packed_pair(pj, pi, g.M, g.h, dx, dy, dz);
+                const float r2f = dx * dx + dy * dy + dz * dz;
+                const bool in = atom_ok && bead_ok && pair_within(r2f, c, pb, i, j, box);
+                const uint64_t m = __ballot(in) & gmask;
+                if (m) {
+                    // radial lists keep the atom index, angular ones the candidate slot;
+                    // bit b of the mask: inside in bead b
+                    if (b == 0 && atom_ok) {
+                        uni[cnt] = kind ? k : j;
+                        um[cnt] = m >> base;
                     }
+                    ++cnt;
                 }
             }
-            endR[((size_t)b * kMaxSpecies + t) * N + i] = min(sR, capR);
-            endA[((size_t)b * kMaxSpecies + t) * N + i] = min(sA, capA);
+            if (b == 0 && atom_ok) uend[t] = cnt;
         }
-        if (min(off[(size_t)i * (kMaxSpecies + 1) + S], capC) > 0)
-            mk[(size_t)wcur * N] = (uint64_t)word | ((uint64_t)before << 32);
+        most[kind] = atom_ok ? cnt : 0;
     }
-    const int wR = wave_max_i(sR), wA = wave_max_i(sA);
-    if ((threadIdx.x & 63) == 0) {
+    const int wR = wave_max_i(most[0]), wA = wave_max_i(most[1]);
+    if (lane == 0) {
         if (wR > 0) atomicMax(&status[1], (uint32_t)wR);
         if (wA > 0) atomicMax(&status[2], (uint32_t)wA);
-        if (wR > capR || wA > capA) atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
     }
+}
+
+// Per-bead lists written out for tests and analysis: one lane per (bead,
+// atom), the same decision as the force path over the candidate rows.
+__global__ __launch_bounds__(256) void k_materialize(const double *__restrict__ pos, const float4 *__restrict__ pos4,
+                                                     int P, int N, int S, const int32_t *__restrict__ atom_sys,
+                                                     const SysGeom *__restrict__ geom, CutTest cR,
+                                                     CutTest cA, const int32_t *__restrict__ candR,
+                                                     const int32_t *__restrict__ offR,
+                                                     const int32_t *__restrict__ candA,
+                                                     const int32_t *__restrict__ offA, int capR, int capA,
+                                                     int outR, int outA, int32_t *__restrict__ nbrR,
+                                                     int32_t *__restrict__ cntR, int32_t *__restrict__ nbrA,
+                                                     int32_t *__restrict__ cntA)
+{
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (size_t)P * N) return;
+    const int b = (int)(e / (size_t)N), i = (int)(e - (size_t)b * N);
+    const float4 pi = pos4[(size_t)i * P + b];
+    const double *pb = pos + (size_t)b * N * 3;
+    const SysGeom &g = geom[atom_sys[i]];
+    const BoxD box{{g.L[0], g.L[1], g.L[2]}, {g.invL[0], g.invL[1], g.invL[2]}};
+    for (int kind = 0; kind < 2; ++kind) {
+        const int cap = kind ? capA : capR, out = kind ? outA : outR;
+        const int32_t *row = (kind ? candA : candR) + (size_t)i * cap;
+        const int n = min((kind ? offA : offR)[(size_t)i * (kMaxSpecies + 1) + S], cap);
+        int32_t *nb = (kind ? nbrA : nbrR) + (size_t)b * out * N + i;
+        const CutTest c = kind ? cA : cR;
+        int cnt = 0;
+        for (int k = 0; k < n; ++k) {
+            const int j = row[k] >> 2;
+            float dx, dy, dz;
+            packed_pair(pos4[(size_t)j * P + b], pi, g.M, g.h, dx, dy, dz);
+            if (pair_within(dx * dx + dy * dy + dz * dz, c, pb, i, j, box)) {
+                if (cnt < out) nb[(size_t)cnt * N] = j;
+                ++cnt;
+            }
+        }
+        (kind ? cntA : cntR)[(size_t)b * N + i] = cnt;
+    }
+}
+
+// Checks the boxes of a batch and refreshes the per-system geometry (fine
+// grids, cell bounds, cell ranges).  The device copy is rewritten, with a
+// synchronous copy, only when a box changed; `changed` reports that.
+int32_t update_geometry(const nep_model *m, nep_nlist *nl, const double *boxes, bool &changed, float &margin)
+{
+    const double rc = std::max(m->hp.rc_radial, m->hp.rc_angular);
+    std::vector<SysGeom> G(nl->nsys);
+    int cell_total = 0;
+    double hmax = 0.0;
+    changed = false;
+    for (int s = 0; s < nl->nsys; ++s) {
+        SysGeom &g = G[s];
+        double L[3];
+        if (!box_lengths(boxes + 9 * s, L)) return fail(NEP_ERR_UNSUPPORTED, "system %d: only orthorhombic cells", s);
+        for (int a = 0; a < 3; ++a) {
+            if (!(L[a] > 0.0) || !std::isfinite(L[a]))
+                return fail(NEP_ERR_INVALID_ARG, "system %d: bad box edge %g", s, L[a]);
+            if (L[a] < 2.0 * rc)
+                return fail(NEP_ERR_BOX_TOO_SMALL, "system %d: box edge %g is shorter than twice the cutoff %g", s,
+                            L[a], rc);
+        }
+        const FineGrid fg = fine_grid(L, rc);
+        if (!fg.exact)
+            return fail(NEP_ERR_BOX_TOO_SMALL, "system %d: box edges %g %g %g leave no margin over twice the cutoff",
+                        s, L[0], L[1], L[2]);
+        int ncap = 1;
+        for (int a = 0; a < 3; ++a) {
+            g.L[a] = L[a];
+            g.invL[a] = 1.0 / L[a];
+            g.hd[a] = fg.hd[a];
+            g.Minv[a] = fg.Minv[a];
+            g.h[a] = fg.h[a];
+            g.M[a] = fg.M[a];
+            const int nc = (int)std::floor(L[a] / (rc * (1.0 + 1e-9)));
+            g.nc_cap[a] = nc < 1 ? 1 : (nc > 64 ? 64 : nc);
+            ncap *= g.nc_cap[a];
+            hmax = std::max(hmax, fg.hd[a]);
+            if (nl->boxL[3 * s + a] != L[a]) changed = true;
+        }
+        g.cell_base = cell_total;
+        cell_total += ncap;
+        g.atom0 = nl->off[s];
+        g.atom1 = nl->off[s + 1];
+    }
+    margin = (float)(1e-3 * std::max(1.0, hmax * hmax) * std::max(1.0, rc * rc / 36.0));
+    if (!changed) return NEP_OK;
+    if (cell_total > nl->ncell_alloc) {
+        for (int32_t **p : {&nl->cell_cnt, &nl->cell_start, &nl->cell_sys}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+        nl->ncell_alloc = 0;
+        NEP_HIP(hipMalloc(&nl->cell_cnt, sizeof(int32_t) * (size_t)cell_total));
+        NEP_HIP(hipMalloc(&nl->cell_start, sizeof(int32_t) * (size_t)(cell_total + 1)));
+        NEP_HIP(hipMalloc(&nl->cell_sys, sizeof(int32_t) * (size_t)cell_total));
+        nl->ncell_alloc = cell_total;
+    }
+    std::vector<int32_t> cs(cell_total);
+    for (int s = 0; s < nl->nsys; ++s) {
+        const int n = G[s].nc_cap[0] * G[s].nc_cap[1] * G[s].nc_cap[2];
+        for (int c = 0; c < n; ++c) cs[G[s].cell_base + c] = s;
+    }
+    NEP_HIP(hipDeviceSynchronize());
+    NEP_HIP(hipMemcpy(nl->cell_sys, cs.data(), sizeof(int32_t) * cs.size(), hipMemcpyHostToDevice));
+    NEP_HIP(hipMemcpy(nl->geom, G.data(), sizeof(SysGeom) * G.size(), hipMemcpyHostToDevice));
+    nl->ncell_total = cell_total;
+    for (int s = 0; s < nl->nsys; ++s)
+        for (int a = 0; a < 3; ++a) nl->boxL[3 * s + a] = G[s].L[a];
+    return NEP_OK;
 }
 
 }  // namespace nep
 
 using namespace nep;
 
-extern "C" int32_t neighbor_build(const nep_model *m, nep_nlist *nl, const double *pos, const double box[9],
-                                  const int32_t *types, int32_t P, int32_t N, hipStream_t s)
+extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, const double *pos, const double *boxes,
+                                          const int32_t *types, int32_t P, int32_t N, hipStream_t s)
 {
-    if (!m || !nl || !box) return fail(NEP_ERR_INVALID_ARG, "neighbor_build: null argument");
+    if (!m || !nl || !boxes) return fail(NEP_ERR_INVALID_ARG, "neighbor_build: null argument");
     if (P != nl->P || N != nl->N || nl->S != m->hp.n_species)
         return fail(NEP_ERR_INVALID_ARG, "neighbor_build: P=%d N=%d do not match the list (P=%d N=%d)", P, N,
                     nl->P, nl->N);
     if (P == 0 || N == 0) return NEP_OK;
     if (!pos || !types) return fail(NEP_ERR_INVALID_ARG, "neighbor_build: null array");
-    HostGrid g;
-    if (!box_lengths(box, g.L)) return fail(NEP_ERR_UNSUPPORTED, "neighbor_build: only orthorhombic cells");
-    g.rcR = m->hp.rc_radial;
-    g.rcA = m->hp.rc_angular;
-    const double rc = g.rcR > g.rcA ? g.rcR : g.rcA;
-    int ncell_cap = 1;
-    for (int a = 0; a < 3; ++a) {
-        if (!(g.L[a] > 0.0) || !std::isfinite(g.L[a]))
-            return fail(NEP_ERR_INVALID_ARG, "neighbor_build: bad box edge %g", g.L[a]);
-        if (g.L[a] < 2.0 * rc)
-            return fail(NEP_ERR_BOX_TOO_SMALL, "box edge %g is shorter than twice the cutoff %g", g.L[a], rc);
-        g.invL[a] = 1.0 / g.L[a];
-        int nc = (int)std::floor(g.L[a] / (rc * (1.0 + 1e-9)));
-        g.nc_cap[a] = nc < 1 ? 1 : (nc > 64 ? 64 : nc);
-        ncell_cap *= g.nc_cap[a];
-    }
-    if (ncell_cap > nl->ncell_alloc) {
-        if (nl->cell_cnt) (void)hipFree(nl->cell_cnt);
-        if (nl->cell_start) (void)hipFree(nl->cell_start);
-        nl->cell_cnt = nullptr;
-        nl->cell_start = nullptr;
-        nl->ncell_alloc = 0;
-        NEP_HIP(hipMalloc(&nl->cell_cnt, sizeof(int32_t) * (size_t)ncell_cap));
-        NEP_HIP(hipMalloc(&nl->cell_start, sizeof(int32_t) * (size_t)(ncell_cap + 1)));
-        nl->ncell_alloc = ncell_cap;
-    }
-    const double rcR2 = m->hp.rc_radial * m->hp.rc_radial;
-    const double rcA2 = m->hp.rc_angular * m->hp.rc_angular;
-    const FineGrid fg = fine_grid(g.L, rc);
-    if (!fg.exact)
-        return fail(NEP_ERR_BOX_TOO_SMALL, "box edges %g %g %g leave no margin over twice the cutoff %g", g.L[0],
-                    g.L[1], g.L[2], rc);
-    // decision margin for the FP32 prefilter: ~50x the packed error bound
-    const double hmax = std::max(std::max(fg.hd[0], fg.hd[1]), fg.hd[2]);
-    const float margin = (float)(1e-3 * std::max(1.0, hmax * hmax) * std::max(1.0, rc * rc / 36.0));
-    // a changed box invalidates the candidate rows
-    bool force = !nl->built;
-    for (int a = 0; a < 3; ++a) force = force || g.L[a] != nl->box_built[a];
-    fill_u32(nl->grid + 4, 0u, 2, s);
-    pack_positions(pos, (size_t)P * N, fg, reinterpret_cast<float4 *>(nl->pos4), s);
-    fill_i32(nl->cell_cnt, 0, (size_t)ncell_cap, s);
+    bool changed = false;
+    float margin = 0.0f;
+    const int32_t rc_ = update_geometry(m, nl, boxes, changed, margin);
+    if (rc_ != NEP_OK) return rc_;
+    const bool force = !nl->built || changed;
+    fill_u32(nl->grid, 0u, 2, s);
+    pack_positions(pos, P, N, nl->atom_sys, nl->geom, reinterpret_cast<float4 *>(nl->pos4), s);
+    fill_i32(nl->cell_cnt, 0, (size_t)nl->ncell_total, s);
     const dim3 g1(div_up(N, kBlock));
     const dim3 gw(div_up(N, kBlock / 64));
+    const dim3 gc(nl->ncell_total);
     {
         ProfScope ps_(K_CENTROID, s);
         hipLaunchKernelGGL(k_centroid, g1, dim3(kBlock), 0, s, pos, types, P, N, nl->S, nl->cen, nl->cen_ref, nl->grid,
@@ -621,50 +688,104 @@ extern "C" int32_t neighbor_build(const nep_model *m, nep_nlist *nl, const doubl
     }
     {
         ProfScope ps_(K_GRID, s);
-        hipLaunchKernelGGL(k_grid, dim3(1), dim3(1), 0, s, g, nl->skin, force ? 1 : 0, nl->grid, nl->status);
+        hipLaunchKernelGGL(k_grid, dim3(1), dim3(64), 0, s, nl->geom, nl->nsys, m->hp.rc_radial, m->hp.rc_angular,
+                           nl->skin, force ? 1 : 0, nl->grid, nl->status);
     }
     {
         ProfScope ps_(K_CELL_COUNT, s);
-        hipLaunchKernelGGL(k_cell_count, g1, dim3(kBlock), 0, s, nl->cen, N, g, nl->grid, nl->cell_cnt);
+        hipLaunchKernelGGL(k_cell_count, g1, dim3(kBlock), 0, s, nl->cen, N, nl->atom_sys, nl->geom, nl->grid,
+                           nl->cell_cnt);
     }
     {
         ProfScope ps_(K_CELL_SCAN, s);
-        hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, nl->grid, nl->cell_cnt, nl->cell_start);
+        hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, nl->grid, nl->ncell_total, nl->cell_cnt,
+                           nl->cell_start);
     }
     {
         ProfScope ps_(K_CELL_FILL, s);
-        hipLaunchKernelGGL(k_cell_fill, g1, dim3(kBlock), 0, s, nl->cen, N, g, nl->grid, nl->cell_cnt,
-                           nl->cell_start, nl->cell_atoms);
+        hipLaunchKernelGGL(k_cell_fill, g1, dim3(kBlock), 0, s, nl->cen, N, nl->atom_sys, nl->geom, nl->grid,
+                           nl->cell_cnt, nl->cell_start, nl->cell_atoms);
     }
     {
         ProfScope ps_(K_CELL_SORT, s);
-        hipLaunchKernelGGL(k_cell_rank, dim3(ncell_cap), dim3(64), 0, s, nl->grid, nl->cell_start, nl->cell_atoms);
+        hipLaunchKernelGGL(k_cell_rank, gc, dim3(64), 0, s, nl->grid, nl->cell_start, nl->cell_atoms);
     }
     {
         ProfScope ps_(K_CANDIDATES, s);
-        hipLaunchKernelGGL(k_candidates, dim3(ncell_cap), dim3(kBlock), 0, s, nl->cen, types, N, nl->S, g, nl->grid,
-                           nl->cell_start, nl->cell_atoms, nl->capC, nl->cand, nl->rowlen, nl->cen_ref, nl->status);
+        hipLaunchKernelGGL(k_candidates, gc, dim3(kBlock), 0, s, nl->cen, types, N, nl->S, nl->geom, nl->cell_sys,
+                           nl->grid, nl->cell_start, nl->cell_atoms, nl->capR, nl->capA, nl->candR, nl->lenR,
+                           nl->candA, nl->lenA, nl->cen_ref, nl->status);
     }
     {
+        // the union-list and reverse-slot arrays serve as sort scratch before they are filled
         ProfScope ps_(K_SORT_ROWS, s);
-        hipLaunchKernelGGL(k_sort_rows, gw, dim3(kBlock), 0, s, nl->grid, N, nl->S, nl->capC, nl->cand, nl->rowlen,
-                           nl->offC, nl->revC);
+        hipLaunchKernelGGL(k_sort_rows, gw, dim3(kBlock), 0, s, nl->grid, N, nl->S, nl->capR, nl->candR, nl->lenR,
+                           nl->offR, nl->uniR);
+        hipLaunchKernelGGL(k_sort_rows, gw, dim3(kBlock), 0, s, nl->grid, N, nl->S, nl->capA, nl->candA, nl->lenA,
+                           nl->offA, nl->revA);
     }
     {
         ProfScope ps_(K_REVERSE, s);
-        hipLaunchKernelGGL(k_reverse, gw, dim3(kBlock), 0, s, nl->grid, N, nl->capC, types, nl->cand, nl->offC,
-                           nl->revC);
+        hipLaunchKernelGGL(k_reverse, gw, dim3(kBlock), 0, s, nl->grid, N, nl->capA, types, nl->candA, nl->offA,
+                           nl->revA);
     }
     {
         ProfScope ps_(K_NLIST, s);
-        hipLaunchKernelGGL(k_filter, dim3(div_up(N, kBlock), P), dim3(kBlock), 0, s, pos,
-                           reinterpret_cast<const float4 *>(nl->pos4), fg, margin, N, nl->S, g, nl->cand,
-                           nl->offC, nl->revC, nl->capC, nl->capR, nl->capA, rcR2, rcA2, nl->listR, nl->endR,
-                           nl->listA, nl->endA, nl->slotA, nl->maskA, nl->status);
+        const int lg = lanes_log2(P);
+        const int apw = 64 >> lg;
+        const double rR2 = m->hp.rc_radial * m->hp.rc_radial, rA2 = m->hp.rc_angular * m->hp.rc_angular;
+        const CutTest cR{(float)rR2, margin, rR2};
+        const CutTest cA{(float)rA2, margin, rA2};
+        hipLaunchKernelGGL(k_union, dim3(div_up(N, 4 * apw)), dim3(kBlock), 0, s, pos,
+                           reinterpret_cast<const float4 *>(nl->pos4), P, N, nl->S, lg, nl->atom_sys, nl->geom, cR,
+                           cA, nl->candR, nl->offR, nl->candA, nl->offA, nl->capR, nl->capA, nl->uniR, nl->umR,
+                           nl->uendR, nl->uniA, nl->umA, nl->uendA, nl->status);
     }
     NEP_HIP(hipGetLastError());
     nl->built = 1;
-    for (int a = 0; a < 3; ++a) nl->box_built[a] = g.L[a];
+    return NEP_OK;
+}
+
+extern "C" int32_t neighbor_build(const nep_model *m, nep_nlist *nl, const double *pos, const double box[9],
+                                  const int32_t *types, int32_t P, int32_t N, hipStream_t s)
+{
+    if (nl && nl->nsys != 1) return fail(NEP_ERR_INVALID_ARG, "neighbor_build: the list holds a batch of systems");
+    return neighbor_build_batched(m, nl, pos, box, types, P, N, s);
+}
+
+extern "C" int32_t nep_nlist_materialize(const nep_model *m, const nep_nlist *nl, const double *pos,
+                                         const double *boxes, int32_t P, int32_t N, int32_t outR, int32_t outA,
+                                         int32_t *nbrR, int32_t *cntR, int32_t *nbrA, int32_t *cntA, hipStream_t s)
+{
+    if (!m || !nl || !boxes) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_materialize: null argument");
+    if (P != nl->P || N != nl->N || outR < 1 || outA < 1)
+        return fail(NEP_ERR_INVALID_ARG, "nep_nlist_materialize: bad sizes");
+    if (P == 0 || N == 0) return NEP_OK;
+    if (!pos || !nbrR || !cntR || !nbrA || !cntA) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_materialize: null array");
+    if (!nl->built) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_materialize: no neighbor_build yet");
+    for (int sy = 0; sy < nl->nsys; ++sy) {
+        double L[3];
+        if (!box_lengths(boxes + 9 * sy, L) || L[0] != nl->boxL[3 * sy] || L[1] != nl->boxL[3 * sy + 1] ||
+            L[2] != nl->boxL[3 * sy + 2])
+            return fail(NEP_ERR_INVALID_ARG, "nep_nlist_materialize: box of system %d differs from the last build", sy);
+    }
+    const double rc = std::max(m->hp.rc_radial, m->hp.rc_angular);
+    double hmax = 0.0;
+    for (int sy = 0; sy < nl->nsys; ++sy)
+        for (int a = 0; a < 3; ++a) hmax = std::max(hmax, fine_grid(&nl->boxL[3 * sy], rc).hd[a]);
+    const float margin = (float)(1e-3 * std::max(1.0, hmax * hmax) * std::max(1.0, rc * rc / 36.0));
+    const double rR2 = m->hp.rc_radial * m->hp.rc_radial, rA2 = m->hp.rc_angular * m->hp.rc_angular;
+    const CutTest cR{(float)rR2, margin, rR2};
+    const CutTest cA{(float)rA2, margin, rA2};
+    const size_t n = (size_t)P * N;
+    {
+        ProfScope ps_(K_MATERIALIZE, s);
+        hipLaunchKernelGGL(k_materialize, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pos,
+                           reinterpret_cast<const float4 *>(nl->pos4), P, N, nl->S, nl->atom_sys, nl->geom, cR, cA,
+                           nl->candR, nl->offR, nl->candA, nl->offA, nl->capR, nl->capA, outR, outA, nbrR, cntR, nbrA,
+                           cntA);
+    }
+    NEP_HIP(hipGetLastError());
     return NEP_OK;
 }
 

@@ -25,34 +25,54 @@ def default_capacity(rc: float, density: float, n_species: int, slack: float = 1
 
 
 class NepPimd:
-    """NEP forces for P beads of one periodic system plus the ring-polymer integrator."""
+    """NEP forces for P beads of one periodic system, or of a batch of
+    independent systems of uneven size, plus the ring-polymer integrator.
 
-    def __init__(self, model_path: str, system: I.System, *, dt: float, T: float, tau: float = 100.0,
+    With a list of systems the atoms are concatenated along the atom axis,
+    every kernel of a step covers all systems at once, and E / W gain a
+    leading system axis ([nsys, P], [nsys, P, 9])."""
+
+    def __init__(self, model_path: str, system, *, dt: float, T: float, tau: float = 100.0,
                  mode: str = "trpmd", seed: int = 0, caps: Optional[tuple] = None, check_every: int = 50,
-                 want_atom: bool = False, skin: float = 0.5):
+                 want_atom: bool = False, skin: float = 0.5, autotune: bool = False):
         import torch
         self.torch = torch
         dev = torch.device("cuda")
         self.model = lib.Model(model_path)
-        self.P, self.N = system.P, system.N
-        self.box = np.asarray(system.box, np.float64)
-        self.pos = torch.tensor(system.pos, dtype=torch.float64, device=dev)
-        self.vel = torch.tensor(system.vel, dtype=torch.float64, device=dev)
-        self.types = torch.tensor(system.types, dtype=torch.int32, device=dev)
-        self.mass = torch.tensor(system.masses, dtype=torch.float64, device=dev)
+        systems = list(system) if isinstance(system, (list, tuple)) else [system]
+        self.batched = isinstance(system, (list, tuple))
+        self.P = systems[0].P
+        if any(s.P != self.P for s in systems):
+            raise ValueError("all systems of a batch need the same number of beads")
+        sizes = [s.N for s in systems]
+        self.offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+        self.N = int(self.offsets[-1])
+        self.nsys = len(systems)
+        self.box = np.stack([np.asarray(s.box, np.float64) for s in systems]) if self.batched \
+            else np.asarray(systems[0].box, np.float64)
+        cat = lambda f, ax: np.concatenate([f(s) for s in systems], axis=ax)
+        self.pos = torch.tensor(cat(lambda s: s.pos, 1), dtype=torch.float64, device=dev)
+        self.vel = torch.tensor(cat(lambda s: s.vel, 1), dtype=torch.float64, device=dev)
+        self.types = torch.tensor(cat(lambda s: s.types, 0), dtype=torch.int32, device=dev)
+        self.mass = torch.tensor(cat(lambda s: s.masses, 0), dtype=torch.float64, device=dev)
         self.F = torch.zeros((self.P, self.N, 3), dtype=torch.float32, device=dev)
-        self.E = torch.zeros(self.P, dtype=torch.float64, device=dev)
-        self.W = torch.zeros((self.P, 9), dtype=torch.float64, device=dev)
+        eshape = (self.nsys, self.P) if self.batched else (self.P,)
+        self.E = torch.zeros(eshape, dtype=torch.float64, device=dev)
+        self.W = torch.zeros(eshape + (9,), dtype=torch.float64, device=dev)
         self.E_atom = torch.zeros((self.P, self.N), dtype=torch.float32, device=dev) if want_atom else None
         self.W_atom = torch.zeros((self.P, self.N, 9), dtype=torch.float32, device=dev) if want_atom else None
-        dens = self.N / float(np.prod(self.box))
+        vol = sum(float(np.prod(np.asarray(s.box, np.float64).reshape(-1)[[0, 4, 8]] if np.asarray(s.box).size == 9
+                                 else np.asarray(s.box, np.float64))) for s in systems)
+        dens = self.N / vol
+        self.density = dens
         S = self.model.n_species
         rcR, rcA = self.model.rc_radial, self.model.rc_angular
-        self.caps = tuple(caps) if caps else (default_capacity(rcR + 0.5, dens, S), default_capacity(rcR, dens, S),
-                                              default_capacity(rcA, dens, S))
+        self.caps = tuple(caps) if caps else (default_capacity(rcR + 0.5 + skin, dens, S),
+                                              default_capacity(rcA + 0.5 + skin, dens, S))
         self.nl = None
         self.skin = skin
-        self.ws = lib.Workspace(self.model, self.P, self.N)
+        offs = self.offsets if self.batched else None
+        self.ws = lib.Workspace(self.model, self.P, self.N, offsets=offs)
         self.pimd = lib.Pimd(self.P, self.N, self.mass, dt, T, tau, mode, seed)
         self.check_every = check_every
         self.step_no = 0
@@ -60,12 +80,25 @@ class NepPimd:
         self.graph = None
         self.step_dev = None
         self._fit_capacity()
+        self.tile = None
+        if autotune:
+            self.tile = self.ws.autotune(self.nl, self.pos, self.box, self.types, self.E, self.F, self.W)
 
     # ------------------------------------------------------------------
     def _fit_capacity(self):
-        """Size the candidate rows to the starting configuration (slack for the run)."""
-        self.nl = lib.fitted_neighbor_list(self.model, self.pos, self.box, self.types, *self.caps, skin=self.skin)
-        self.caps = self.nl.caps
+        """Size the candidate rows to the starting configuration, with room for
+        the ring polymers to spread: the rows are at least as long as a uniform
+        system of the same density needs for radius rc + skin + 1 A."""
+        self.nl = lib.fitted_neighbor_list(self.model, self.pos, self.box, self.types, *self.caps, skin=self.skin,
+                                           offsets=self.offsets if self.batched else None)
+        floor = (default_capacity(self.model.rc_radial + self.skin + 1.0, self.density, 1, slack=1.3),
+                 default_capacity(self.model.rc_angular + self.skin + 1.0, self.density, 1, slack=1.3))
+        caps = tuple(max(a, b) for a, b in zip(self.nl.caps, floor))
+        if caps != tuple(self.nl.caps):
+            self.nl = lib.NeighborList(self.model, self.P, self.N, *caps,
+                                       offsets=self.offsets if self.batched else None)
+            self.nl.set_skin(self.skin)
+        self.caps = caps
 
     def forces(self):
         """Neighbour lists + NEP energy, forces and virial at the current positions."""
@@ -75,9 +108,10 @@ class NepPimd:
     def check(self):
         """Poll the sticky flags (synchronises); raise on overflow or non-finite values."""
         st = self.nl.status(clear=True)
-        flags, mr, ma = st["flags"], st["max_radial"], st["max_angular"]
+        flags, mr, ma = st["flags"], st["max_union_radial"], st["max_union_angular"]
         if flags & lib.FLAG_NEIGHBOR_OVERFLOW:
-            raise lib.NepError(5, f"list overflow: need {st['max_candidates']}/{mr}/{ma}, capacities {self.caps}")
+            raise lib.NepError(5, f"candidate overflow: rows {st['max_cand_radial']}/{st['max_cand_angular']}, "
+                                  f"capacities {self.caps}")
         wf = self.ws.poll(clear=True)
         if (flags | wf) & lib.FLAG_NONFINITE:
             raise lib.NepError(6, "non-finite force or position")

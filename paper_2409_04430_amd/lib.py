@@ -43,16 +43,21 @@ class HParams(C.Structure):
 
 
 class NlistLayout(C.Structure):
-    _fields_ = [("P", C.c_int32), ("N", C.c_int32), ("n_species", C.c_int32), ("cap_candidates", C.c_int32),
-                ("cap_radial", C.c_int32), ("cap_angular", C.c_int32), ("cand", C.c_void_p),
-                ("cand_off", C.c_void_p), ("cand_rev", C.c_void_p), ("nbr_radial", C.c_void_p),
-                ("end_radial", C.c_void_p), ("nbr_angular", C.c_void_p), ("end_angular", C.c_void_p),
-                ("slot_angular", C.c_void_p)]
+    _fields_ = [("P", C.c_int32), ("N", C.c_int32), ("n_species", C.c_int32), ("cap_radial", C.c_int32),
+                ("cap_angular", C.c_int32), ("cand_radial", C.c_void_p), ("cand_radial_off", C.c_void_p),
+                ("cand_angular", C.c_void_p), ("cand_angular_off", C.c_void_p), ("cand_angular_rev", C.c_void_p),
+                ("union_radial", C.c_void_p), ("union_radial_end", C.c_void_p), ("union_angular", C.c_void_p),
+                ("union_angular_end", C.c_void_p)]
 
 
 class NlistStatus(C.Structure):
-    _fields_ = [("flags", C.c_uint32), ("max_radial", C.c_int32), ("max_angular", C.c_int32),
-                ("max_candidates", C.c_int32), ("bead_spread", C.c_float), ("rebuilds", C.c_int32)]
+    _fields_ = [("flags", C.c_uint32), ("max_union_radial", C.c_int32), ("max_union_angular", C.c_int32),
+                ("max_cand_radial", C.c_int32), ("max_cand_angular", C.c_int32), ("bead_spread", C.c_float),
+                ("rebuilds", C.c_int32)]
+
+
+class ParamOffsets(C.Structure):
+    _fields_ = [(k, C.c_int32) for k in ("c_radial", "c_angular", "q_scale", "W0", "b0", "w1", "b1", "sh")]
 
 
 class PimdParams(C.Structure):
@@ -67,7 +72,14 @@ _sig = {
     "nep_load_params": (_i32, [C.c_char_p, C.POINTER(_vp)]),
     "nep_model_info": (_i32, [_vp, C.POINTER(HParams)]),
     "nep_model_destroy": (None, [_vp]),
-    "nep_nlist_create": (_i32, [_vp, _i32, _i32, _i32, _i32, _i32, C.POINTER(_vp)]),
+    "nep_nlist_create": (_i32, [_vp, _i32, _i32, _i32, _i32, C.POINTER(_vp)]),
+    "nep_nlist_create_batched": (_i32, [_vp, _i32, _i32, C.POINTER(C.c_int32), _i32, _i32, C.POINTER(_vp)]),
+    "neighbor_build_batched": (_i32, [_vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, _vp]),
+    "nep_ws_create_batched": (_i32, [_vp, _i32, _i32, C.POINTER(C.c_int32), C.POINTER(_vp)]),
+    "nep_compute_batched": (_i32, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, _vp, _vp, _vp, _vp,
+                                   _vp, _vp]),
+    "nep_nlist_materialize": (_i32, [_vp, _vp, _vp, C.POINTER(C.c_double), _i32, _i32, _i32, _i32, _vp, _vp, _vp,
+                                     _vp, _vp]),
     "nep_nlist_destroy": (None, [_vp]),
     "neighbor_build": (_i32, [_vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, _vp]),
     "nep_nlist_view": (_i32, [_vp, C.POINTER(NlistLayout)]),
@@ -84,6 +96,17 @@ _sig = {
     "trpmd_step_dev": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "nep_nlist_set_skin": (_i32, [_vp, C.c_double]),
     "nep_nlist_invalidate": (_i32, [_vp]),
+    "nep_ws_set_tile": (_i32, [_vp, _i32]),
+    "nep_ws_get_tile": (_i32, [_vp, C.POINTER(C.c_int32)]),
+    "nep_autotune": (_i32, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, _vp, _vp, _vp, _i32,
+                            C.POINTER(C.c_float), C.POINTER(C.c_int32), _vp]),
+    "nep_model_params": (_i32, [_vp, C.POINTER(_vp), C.POINTER(C.c_int32), C.POINTER(ParamOffsets)]),
+    "nep_train_ws_create": (_i32, [_vp, _i32, _i32, C.POINTER(_vp)]),
+    "nep_train_ws_destroy": (None, [_vp]),
+    "nep_param_grad": (_i32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, _vp, _vp, _vp,
+                              C.POINTER(C.c_double), _vp, _vp, _vp]),
+    "nep_adam_step": (_i32, [_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, _i32,
+                             _vp]),
     "nep_profile_enable": (_i32, [_i32]),
     "nep_profile_select": (_i32, [_i32]),
     "nep_profile_num_kernels": (_i32, []),
@@ -125,6 +148,19 @@ def _ptr(t, dtype, shape=None, name="tensor"):
     return _vp(t.data_ptr())
 
 
+def _boxes(box, nsys: int) -> C.Array:
+    """[nsys][9] row-vector cells as a C array (orthorhombic edges [3] accepted)."""
+    b = np.asarray(box, np.float64)
+    if nsys == 1 and b.shape in ((3,), (3, 3), (9,)):
+        return _box9(b)
+    b = b.reshape(nsys, -1)
+    if b.shape[1] == 3:
+        b = np.stack([np.diag(r).reshape(9) for r in b])
+    if b.shape != (nsys, 9):
+        raise ValueError(f"boxes must have shape [{nsys}, 3] or [{nsys}, 3, 3]")
+    return (C.c_double * (9 * nsys))(*b.reshape(-1).tolist())
+
+
 def _box9(box) -> C.Array:
     b = np.asarray(box, np.float64)
     if b.shape == (3,):
@@ -156,6 +192,31 @@ class Model:
             return hp[k]
         raise AttributeError(k)
 
+    def params(self):
+        """(device pointer, count, offsets) of the model's FP32 parameter array."""
+        ptr = _vp()
+        cnt = C.c_int32()
+        off = ParamOffsets()
+        _check(_lib.nep_model_params(self._h, C.byref(ptr), C.byref(cnt), C.byref(off)))
+        return ptr.value, cnt.value, {k: getattr(off, k) for k, _ in ParamOffsets._fields_}
+
+    def to_dict(self) -> dict:
+        """The current (possibly trained) parameters as a model dict for inputs.write_model."""
+        from . import inputs as I
+        _torch().cuda.synchronize()
+        ptr, cnt, off = self.params()
+        v = device_to_host(ptr, (cnt,), np.float32).astype(np.float64)
+        hp = self.hp
+        S, NR1, NA1, H, D = hp["n_species"], hp["n_max_radial"] + 1, hp["n_max_angular"] + 1, hp["hidden"], hp["dim"]
+        KR1, KA1 = hp["basis_radial"] + 1, hp["basis_angular"] + 1
+        hyper = I.NepHyper(S, hp["rc_radial"], hp["rc_angular"], hp["n_max_radial"], hp["n_max_angular"],
+                           hp["basis_radial"], hp["basis_angular"], hp["l_max"], bool(hp["four_body"]), H)
+        blk = lambda k, n, shp: v[off[k]:off[k] + n].reshape(shp)
+        return dict(hyper=hyper, c_radial=blk("c_radial", S * S * NR1 * KR1, (S, S, NR1, KR1)),
+                    c_angular=blk("c_angular", S * S * NA1 * KA1, (S, S, NA1, KA1)), q_scale=blk("q_scale", D, (D,)),
+                    W0=blk("W0", S * H * D, (S, H, D)), b0=blk("b0", S * H, (S, H)), w1=blk("w1", S * H, (S, H)),
+                    b1=float(v[off["b1"]]))
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
@@ -166,12 +227,23 @@ class Model:
 class NeighborList:
     """nep_nlist_create / neighbor_build / nep_nlist_view / nep_nlist_poll."""
 
-    def __init__(self, model: Model, P: int, N: int, cap_candidates: int, cap_radial: int, cap_angular: int):
+    def __init__(self, model: Model, P: int, N: int, cap_radial: int, cap_angular: int, offsets=None):
         self._h = _vp()
-        _check(_lib.nep_nlist_create(model.handle, P, N, cap_candidates, cap_radial, cap_angular,
-                                     C.byref(self._h)))
+        self.offsets = None if offsets is None else np.asarray(offsets, np.int32)
+        if self.offsets is None:
+            _check(_lib.nep_nlist_create(model.handle, P, N, cap_radial, cap_angular, C.byref(self._h)))
+        else:
+            if int(self.offsets[-1]) != N:
+                raise ValueError("offsets[-1] must equal N")
+            o = (C.c_int32 * len(self.offsets))(*self.offsets.tolist())
+            _check(_lib.nep_nlist_create_batched(model.handle, P, len(self.offsets) - 1, o, cap_radial, cap_angular,
+                                                 C.byref(self._h)))
         self.model, self.P, self.N = model, P, N
-        self.caps = (cap_candidates, cap_radial, cap_angular)
+        self.caps = (cap_radial, cap_angular)
+
+    @property
+    def nsys(self) -> int:
+        return 1 if self.offsets is None else len(self.offsets) - 1
 
     def set_skin(self, skin: float):
         """Reuse candidate rows across builds while the skin covers the motion (0: rebuild every call)."""
@@ -181,9 +253,11 @@ class NeighborList:
         _check(_lib.nep_nlist_invalidate(self._h))
 
     def build(self, pos, box, types):
-        _check(_lib.neighbor_build(self.model.handle, self._h, _ptr(pos, _torch().float64, (self.P, self.N, 3), "pos"),
-                                   _box9(box), _ptr(types, _torch().int32, (self.N,), "types"), self.P, self.N,
-                                   _stream()))
+        """box: [3] / [3,3] for one system, [nsys, 3] / [nsys, 3, 3] for a batch."""
+        _check(_lib.neighbor_build_batched(self.model.handle, self._h,
+                                           _ptr(pos, _torch().float64, (self.P, self.N, 3), "pos"),
+                                           _boxes(box, self.nsys), _ptr(types, _torch().int32, (self.N,), "types"),
+                                           self.P, self.N, _stream()))
 
     def status(self, clear: bool = True) -> dict:
         """Sticky list status (synchronises the stream)."""
@@ -194,43 +268,59 @@ class NeighborList:
         return {f: getattr(st, f) for f, _ in NlistStatus._fields_}
 
     def poll(self, clear: bool = True):
-        """(flags, max_radial, max_angular); synchronises the stream."""
+        """(flags, longest radial union list, longest angular union list); synchronises the stream."""
         st = self.status(clear)
-        return st["flags"], st["max_radial"], st["max_angular"]
+        return st["flags"], st["max_union_radial"], st["max_union_angular"]
 
     def view(self):
-        """Raw layout: device pointers of the candidate rows and the per-bead lists."""
+        """Raw layout: device pointers of the candidate rows and union lists."""
         lay = NlistLayout()
         _check(_lib.nep_nlist_view(self._h, C.byref(lay)))
         return lay
 
-    def to_host(self):
-        """Copy the lists to host numpy arrays (synchronises the device first).
+    def materialize(self, pos, box, cap_radial: int, cap_angular: int):
+        """Per-bead lists of the positions of the last build (device tensors):
+        nbr_radial [P, cap_radial, N], cnt_radial [P, N], and the angular pair."""
+        t = _torch()
+        P, N = self.P, self.N
+        dev = t.device("cuda")
+        nR = t.empty((P, cap_radial, N), dtype=t.int32, device=dev)
+        cR = t.empty((P, N), dtype=t.int32, device=dev)
+        nA = t.empty((P, cap_angular, N), dtype=t.int32, device=dev)
+        cA = t.empty((P, N), dtype=t.int32, device=dev)
+        _check(_lib.nep_nlist_materialize(self.model.handle, self._h, _ptr(pos, t.float64, (P, N, 3), "pos"),
+                                          _boxes(box, self.nsys), P, N, cap_radial, cap_angular,
+                                          _ptr(nR, t.int32, None, "nR"),
+                                          _ptr(cR, t.int32, None, "cR"), _ptr(nA, t.int32, None, "nA"),
+                                          _ptr(cA, t.int32, None, "cA"), _stream()))
+        return nR, cR, nA, cA
 
-        cand [N, capC] (entries (j << 2) | species), cand_off [N, 5],
-        cand_rev [N, capC]; per kind in (radial, angular): nbr_<kind>
-        [P, cap, N], end_<kind> [P, 4, N], cnt_<kind> [P, N]; slot_angular
-        [P, capA, N].  Entries past a row's or list's count are undefined.
-        """
+    def to_host(self, pos=None, box=None, cap_radial: int = 0, cap_angular: int = 0):
+        """Copy the candidate rows and union lists to host numpy arrays; with
+        pos/box also the per-bead lists (nbr_<kind> [P, cap, N], cnt_<kind> [P, N]).
+        Entries past a row's or list's count are undefined."""
         _torch().cuda.synchronize()
         lay = self.view()
-        P, N, C_ = lay.P, lay.N, lay.cap_candidates
-        out = {"n_species": lay.n_species,
-               "cand": device_to_host(lay.cand, (N, C_), np.int32),
-               "cand_off": device_to_host(lay.cand_off, (N, 5), np.int32),
-               "cand_rev": device_to_host(lay.cand_rev, (N, C_), np.int32)}
-        for kind, cap, nbr, end in (("radial", lay.cap_radial, lay.nbr_radial, lay.end_radial),
-                                    ("angular", lay.cap_angular, lay.nbr_angular, lay.end_angular)):
-            out["nbr_" + kind] = device_to_host(nbr, (P, cap, N), np.int32)
-            out["end_" + kind] = device_to_host(end, (P, 4, N), np.int32)
-            out["cnt_" + kind] = out["end_" + kind][:, max(lay.n_species - 1, 0), :].copy()
-        out["slot_angular"] = device_to_host(lay.slot_angular, (P, lay.cap_angular, N), np.int32)
+        N = lay.N
+        out = {"n_species": lay.n_species}
+        for kind, cap, cand, off, uni, uend in (
+                ("radial", lay.cap_radial, lay.cand_radial, lay.cand_radial_off, lay.union_radial,
+                 lay.union_radial_end),
+                ("angular", lay.cap_angular, lay.cand_angular, lay.cand_angular_off, lay.union_angular,
+                 lay.union_angular_end)):
+            out["cand_" + kind] = device_to_host(cand, (N, cap), np.int32)
+            out["cand_off_" + kind] = device_to_host(off, (N, 5), np.int32)
+            out["union_" + kind] = device_to_host(uni, (N, cap), np.int32)
+            out["union_end_" + kind] = device_to_host(uend, (N, 4), np.int32)
+        out["cand_rev_angular"] = device_to_host(lay.cand_angular_rev, (N, lay.cap_angular), np.int32)
+        if pos is not None:
+            cr = cap_radial or lay.cap_radial
+            ca = cap_angular or lay.cap_angular
+            nR, cR, nA, cA = self.materialize(pos, box, cr, ca)
+            _torch().cuda.synchronize()
+            out.update(nbr_radial=nR.cpu().numpy(), cnt_radial=cR.cpu().numpy(), nbr_angular=nA.cpu().numpy(),
+                       cnt_angular=cA.cpu().numpy())
         return out
-
-    @staticmethod
-    def neighbors(lists, kind: str, b: int, i: int) -> np.ndarray:
-        """Neighbour indices of atom i in bead b, in list order, from to_host() arrays."""
-        return lists["nbr_" + kind][b, :lists["cnt_" + kind][b, i], i]
 
     @property
     def handle(self):
@@ -243,27 +333,24 @@ class NeighborList:
             self._h = None
 
 
-def fitted_neighbor_list(model: "Model", pos, box, types, cap_candidates: int = 96, cap_radial: int = 80,
-                         cap_angular: int = 32, slack: float = 1.25, tries: int = 4,
-                         skin: float = 0.0) -> NeighborList:
-    """A NeighborList whose capacities fit the given positions.
+def fitted_neighbor_list(model: "Model", pos, box, types, cap_radial: int = 96, cap_angular: int = 48,
+                         slack: float = 1.25, tries: int = 4, skin: float = 0.0, offsets=None) -> NeighborList:
+    """A NeighborList whose candidate capacities fit the given positions.
 
-    Builds once, reads the longest candidate row and lists from the sticky
-    status and re-creates the list with `slack` x those lengths + 8 when it
-    overflowed or is more than twice too large.  Synchronises the stream.
+    Builds once, reads the longest candidate rows from the sticky status and
+    re-creates the list with `slack` x those lengths + 8 when it overflowed or
+    is more than twice too large.  Synchronises the stream.
     """
     P, N = int(pos.shape[0]), int(pos.shape[1])
-    caps = [int(cap_candidates), int(cap_radial), int(cap_angular)]
+    caps = [int(cap_radial), int(cap_angular)]
     for _ in range(tries):
-        caps[1] = min(caps[1], caps[0])
-        caps[2] = min(caps[2], caps[1])
-        nl = NeighborList(model, P, N, *caps)
+        nl = NeighborList(model, P, N, *caps, offsets=offsets)
         nl.set_skin(skin)
         nl.build(pos, box, types)
         st = nl.status(clear=True)
         if st["flags"] & FLAG_BAD_TYPE:
             raise NepError(1, "species index outside the model's range")
-        need = [int(np.ceil(v * slack)) + 8 for v in (st["max_candidates"], st["max_radial"], st["max_angular"])]
+        need = [int(np.ceil(v * slack)) + 8 for v in (st["max_cand_radial"], st["max_cand_angular"])]
         if not (st["flags"] & FLAG_NEIGHBOR_OVERFLOW) and all(2 * n >= c for n, c in zip(need, caps)):
             return nl
         caps = [max(n, 8) for n in need]
@@ -274,19 +361,51 @@ def fitted_neighbor_list(model: "Model", pos, box, types, cap_candidates: int = 
 class Workspace:
     """nep_ws_create / nep_compute / nep_poll_flags."""
 
-    def __init__(self, model: Model, P: int, N: int):
+    def __init__(self, model: Model, P: int, N: int, offsets=None):
         self._h = _vp()
-        _check(_lib.nep_ws_create(model.handle, P, N, C.byref(self._h)))
+        self.offsets = None if offsets is None else np.asarray(offsets, np.int32)
+        if self.offsets is None:
+            _check(_lib.nep_ws_create(model.handle, P, N, C.byref(self._h)))
+        else:
+            o = (C.c_int32 * len(self.offsets))(*self.offsets.tolist())
+            _check(_lib.nep_ws_create_batched(model.handle, P, len(self.offsets) - 1, o, C.byref(self._h)))
         self.model, self.P, self.N = model, P, N
 
+    @property
+    def nsys(self) -> int:
+        return 1 if self.offsets is None else len(self.offsets) - 1
+
     def compute(self, nl: NeighborList, pos, box, types, E, F, W, E_atom=None, W_atom=None):
+        """E [P] and W [P, 9] for one system; E [nsys, P] and W [nsys, P, 9] for a batch."""
         t = _torch()
-        P, N = self.P, self.N
-        _check(_lib.nep_compute(self.model.handle, nl.handle, self._h, _ptr(pos, t.float64, (P, N, 3), "pos"),
-                                _box9(box), _ptr(types, t.int32, (N,), "types"), P, N,
-                                _ptr(E, t.float64, (P,), "E"), _ptr(F, t.float32, (P, N, 3), "F"),
-                                _ptr(W, t.float64, (P, 9), "W"), _ptr(E_atom, t.float32, (P, N), "E_atom"),
-                                _ptr(W_atom, t.float32, (P, N, 9), "W_atom"), _stream()))
+        P, N, S = self.P, self.N, self.nsys
+        es, ws = ((P,), (P, 9)) if self.offsets is None else ((S, P), (S, P, 9))
+        _check(_lib.nep_compute_batched(self.model.handle, nl.handle, self._h, _ptr(pos, t.float64, (P, N, 3), "pos"),
+                                        _boxes(box, S), _ptr(types, t.int32, (N,), "types"), P, N,
+                                        _ptr(E, t.float64, es, "E"), _ptr(F, t.float32, (P, N, 3), "F"),
+                                        _ptr(W, t.float64, ws, "W"), _ptr(E_atom, t.float32, (P, N), "E_atom"),
+                                        _ptr(W_atom, t.float32, (P, N, 9), "W_atom"), _stream()))
+
+    def set_tile(self, waves_per_group: int):
+        _check(_lib.nep_ws_set_tile(self._h, int(waves_per_group)))
+
+    def get_tile(self) -> int:
+        v = C.c_int32()
+        _check(_lib.nep_ws_get_tile(self._h, C.byref(v)))
+        return v.value
+
+    def autotune(self, nl: NeighborList, pos, box, types, E, F, W, reps: int = 3):
+        """Time every tile shape, keep the fastest; returns (waves per group, {shape: ms})."""
+        t = _torch()
+        P, N, S = self.P, self.N, self.nsys
+        es, ws = ((P,), (P, 9)) if self.offsets is None else ((S, P), (S, P, 9))
+        ms = (C.c_float * 3)()
+        best = C.c_int32()
+        _check(_lib.nep_autotune(self.model.handle, nl.handle, self._h, _ptr(pos, t.float64, (P, N, 3), "pos"),
+                                 _boxes(box, S), _ptr(types, t.int32, (N,), "types"), P, N,
+                                 _ptr(E, t.float64, es, "E"), _ptr(F, t.float32, (P, N, 3), "F"),
+                                 _ptr(W, t.float64, ws, "W"), int(reps), ms, C.byref(best), _stream()))
+        return best.value, {1: ms[0], 2: ms[1], 4: ms[2]}
 
     def poll(self, clear: bool = True) -> int:
         f = C.c_uint32()
@@ -340,6 +459,56 @@ class Pimd:
         h = getattr(self, "_h", None)
         if h:
             _lib.pimd_destroy(h)
+            self._h = None
+
+
+class Trainer:
+    """nep_train_ws_create / nep_param_grad / nep_adam_step on one model.
+
+    Holds the gradient, the Adam moments and the loss accumulator as device
+    tensors in the model's parameter layout."""
+
+    NETWORK, RADIAL = 1, 2
+
+    def __init__(self, model: Model, P: int, N: int):
+        t = _torch()
+        self.model, self.P, self.N = model, P, N
+        self._h = _vp()
+        _check(_lib.nep_train_ws_create(model.handle, P, N, C.byref(self._h)))
+        _, cnt, self.offsets = model.params()
+        dev = t.device("cuda")
+        self.grad = t.zeros(cnt, dtype=t.float32, device=dev)
+        self.m1 = t.zeros(cnt, dtype=t.float32, device=dev)
+        self.m2 = t.zeros(cnt, dtype=t.float32, device=dev)
+        self.loss = t.zeros(4, dtype=t.float64, device=dev)
+        self.step_no = 0
+
+    def zero(self):
+        self.grad.zero_()
+        self.loss.zero_()
+
+    def accumulate(self, nl: NeighborList, ws: "Workspace", pos, box, types, E_ref, F_ref, W_ref, lambdas):
+        """grad += dL/dtheta and loss += (L, L_E, L_F, L_W) for the P configurations pos."""
+        t = _torch()
+        P, N = self.P, self.N
+        lam = (C.c_double * 3)(*[float(x) for x in lambdas])
+        _check(_lib.nep_param_grad(self.model.handle, nl.handle, ws.handle, self._h,
+                                   _ptr(pos, t.float64, (P, N, 3), "pos"), _box9(box),
+                                   _ptr(types, t.int32, (N,), "types"), P, N,
+                                   _ptr(E_ref, t.float64, (P,), "E_ref"), _ptr(F_ref, t.float32, (P, N, 3), "F_ref"),
+                                   _ptr(W_ref, t.float64, (P, 9), "W_ref"), lam, _ptr(self.grad, t.float32),
+                                   _ptr(self.loss, t.float64), _stream()))
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, mask: int = 3):
+        self.step_no += 1
+        _check(_lib.nep_adam_step(self.model.handle, self._h, _ptr(self.grad, _torch().float32),
+                                  _ptr(self.m1, _torch().float32), _ptr(self.m2, _torch().float32), self.step_no,
+                                  float(lr), float(beta1), float(beta2), float(eps), int(mask), _stream()))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.nep_train_ws_destroy(h)
             self._h = None
 
 

@@ -60,7 +60,7 @@ def gpu_nep(torch, L, path, pos, types, box, capR, capA, atom=True):
     dev = torch.device("cuda")
     tpos = torch.tensor(pos, dtype=torch.float64, device=dev)
     ttyp = torch.tensor(types, dtype=torch.int32, device=dev)
-    nl = L.fitted_neighbor_list(m, tpos, box, ttyp, int(capR * 1.3) + 8, capR, capA)
+    nl = L.fitted_neighbor_list(m, tpos, box, ttyp, int(capR * 1.5) + 8, int(capA * 1.5) + 8)
     ws = L.Workspace(m, P, N)
     E = torch.zeros(P, dtype=torch.float64, device=dev)
     F = torch.zeros((P, N, 3), dtype=torch.float32, device=dev)
@@ -74,7 +74,7 @@ def gpu_nep(torch, L, path, pos, types, box, capR, capA, atom=True):
     assert flags == 0, (flags, mr, ma)
     assert ws.poll() == 0
     out = dict(E=E.cpu().numpy(), F=F.cpu().numpy().astype(np.float64), W=W.cpu().numpy().reshape(P, 3, 3),
-               lists=nl.to_host(), nl=nl, ws=ws, model=m, tensors=(tpos, ttyp, E, F, W, Ea, Wa))
+               lists=nl.to_host(tpos, box, *nl.caps), nl=nl, ws=ws, model=m, tensors=(tpos, ttyp, E, F, W, Ea, Wa))
     if atom:
         out["U"] = Ea.cpu().numpy()
         out["Wat"] = Wa.cpu().numpy().reshape(P, N, 3, 3)
@@ -83,47 +83,47 @@ def gpu_nep(torch, L, path, pos, types, box, capR, capA, atom=True):
 
 def check_lists(orc, lists, pos, box, rc_r, rc_a, beads=None, atoms=None, types=None):
     """Per-bead neighbour lists equal the oracle's sets, in (species, index)
-    order; candidate rows and reverse slots are consistent."""
+    order; candidate rows, reverse slots and union lists are consistent."""
     P, N = pos.shape[:2]
+    all_beads = beads is None
     beads = range(P) if beads is None else beads
     sel = range(N) if atoms is None else atoms
     S = lists["n_species"]
-    cand, coff, crev = lists["cand"], lists["cand_off"][:, :S + 1], lists["cand_rev"]
-    for i in sel:
-        n = coff[i, S]
-        row = cand[i, :n]
-        assert coff[i, 0] == 0 and np.all(np.diff(coff[i]) >= 0), i
-        key = (row & 3).astype(np.int64) * (1 << 30) + (row >> 2)
-        assert np.all(np.diff(key) > 0) and not np.any((row >> 2) == i), i
-        blocks = np.searchsorted(coff[i, 1:], np.arange(n), side="right")
-        np.testing.assert_array_equal(row & 3, blocks, err_msg=f"candidate blocks {i}")
-        if types is not None:
-            np.testing.assert_array_equal(row & 3, np.asarray(types)[row >> 2], err_msg=f"species tags {i}")
-        j = row >> 2
-        np.testing.assert_array_equal(cand[j, crev[i, :n]] >> 2, np.full(n, i), err_msg=f"reverse slots {i}")
     for kind, rc in (("radial", rc_r), ("angular", rc_a)):
-        nbr, cnt, end = lists["nbr_" + kind], lists["cnt_" + kind], lists["end_" + kind]
+        cand, coff = lists["cand_" + kind], lists["cand_off_" + kind][:, :S + 1]
+        for i in sel:
+            n = coff[i, S]
+            row = cand[i, :n]
+            assert coff[i, 0] == 0 and np.all(np.diff(coff[i]) >= 0), (kind, i)
+            key = (row & 3).astype(np.int64) * (1 << 30) + (row >> 2)
+            assert np.all(np.diff(key) > 0) and not np.any((row >> 2) == i), (kind, i)
+            blocks = np.searchsorted(coff[i, 1:], np.arange(n), side="right")
+            np.testing.assert_array_equal(row & 3, blocks, err_msg=f"{kind} candidate blocks {i}")
+            if types is not None:
+                np.testing.assert_array_equal(row & 3, np.asarray(types)[row >> 2], err_msg=f"{kind} tags {i}")
+            if kind == "angular":
+                rev = lists["cand_rev_angular"]
+                np.testing.assert_array_equal(cand[row >> 2, rev[i, :n]] >> 2, np.full(n, i),
+                                              err_msg=f"reverse slots {i}")
+        nbr, cnt = lists["nbr_" + kind], lists["cnt_" + kind]
+        sets = {}
         for b in beads:
             oc, oi = orc.neighbors(pos[b], box, rc, cap=1024)
             for i in sel:
                 got = nbr[b, :cnt[b, i], i]
                 assert cnt[b, i] == oc[i], (kind, b, i)
                 if types is not None:
-                    # species blocks in order, ascending index inside each block
                     tj = np.asarray(types)[got]
-                    np.testing.assert_array_equal(np.sort(tj, kind="stable"), tj)
-                    for t in range(S):
-                        assert end[b, t, i] == np.count_nonzero(tj <= t), (kind, b, i, t)
+                    assert np.all(np.diff(tj) >= 0), (kind, b, i)
                 np.testing.assert_array_equal(np.sort(got), oi[i, :oc[i]], err_msg=f"{kind} bead {b} atom {i}")
-        if kind == "angular":
-            # every angular entry carries its candidate slot and reverse slot
-            sl = lists["slot_angular"]
-            for b in beads:
-                for i in sel:
-                    c = cnt[b, i]
-                    k, r = sl[b, :c, i] & 0xFFFF, (sl[b, :c, i] >> 16) & 0xFFFF
-                    np.testing.assert_array_equal(cand[i, k] >> 2, nbr[b, :c, i])
-                    np.testing.assert_array_equal(r, crev[i, k])
+                sets.setdefault(i, set()).update(got.tolist())
+        if all_beads:
+            # union lists: every candidate inside for at least one bead, in row order
+            uni, uend = lists["union_" + kind], lists["union_end_" + kind]
+            for i in sel:
+                m = uend[i, S - 1]
+                j = uni[i, :m] if kind == "radial" else cand[i, uni[i, :m]] >> 2
+                assert set(j.tolist()) == sets[i] and len(j) == len(sets[i]), (kind, i)
 
 
 def check_nep(ref, got, beads, N, atom=True):
@@ -247,18 +247,19 @@ def test_nep_deterministic(torch, L, tmpdir_session):
         np.testing.assert_array_equal(a[k], b[k])
     la, lb = a["lists"], b["lists"]
     S = la["n_species"]
-    for k in ("cnt_radial", "cnt_angular", "end_radial", "end_angular", "cand_off"):
-        np.testing.assert_array_equal(la[k][..., :S + 1, :] if k.startswith("end") else la[k],
-                                      lb[k][..., :S + 1, :] if k.startswith("end") else lb[k])
-    n = la["cand_off"][:, S]
-    valid = np.arange(la["cand"].shape[1])[None, :] < n[:, None]
-    for k in ("cand", "cand_rev"):
-        np.testing.assert_array_equal(la[k][valid], lb[k][valid])
-    for kind, keys in (("radial", ("nbr_radial",)), ("angular", ("nbr_angular", "slot_angular"))):
+    for kind in ("radial", "angular"):
+        np.testing.assert_array_equal(la["cnt_" + kind], lb["cnt_" + kind])
+        np.testing.assert_array_equal(la["cand_off_" + kind], lb["cand_off_" + kind])
+        np.testing.assert_array_equal(la["union_end_" + kind][:, :S], lb["union_end_" + kind][:, :S])
+        n = la["cand_off_" + kind][:, S]
+        valid = np.arange(la["cand_" + kind].shape[1])[None, :] < n[:, None]
+        np.testing.assert_array_equal(la["cand_" + kind][valid], lb["cand_" + kind][valid])
+        m = la["union_end_" + kind][:, S - 1]
+        valid = np.arange(la["union_" + kind].shape[1])[None, :] < m[:, None]
+        np.testing.assert_array_equal(la["union_" + kind][valid], lb["union_" + kind][valid])
         cnt = la["cnt_" + kind]
         valid = np.arange(la["nbr_" + kind].shape[1])[None, :, None] < cnt[:, None, :]
-        for k in keys:
-            np.testing.assert_array_equal(la[k][valid], lb[k][valid])
+        np.testing.assert_array_equal(la["nbr_" + kind][valid], lb["nbr_" + kind][valid])
 
 
 def test_nep_edge_cases(torch, L, tmpdir_session):
@@ -269,7 +270,7 @@ def test_nep_edge_cases(torch, L, tmpdir_session):
     dev = torch.device("cuda")
     # empty: N = 0 and P = 0
     for P, N in ((2, 0), (0, 5)):
-        nl = L.NeighborList(m, P, N, 8, 8, 8)
+        nl = L.NeighborList(m, P, N, 8, 8)
         ws = L.Workspace(m, P, N)
         pos = torch.zeros((P, N, 3), dtype=torch.float64, device=dev)
         typ = torch.zeros(N, dtype=torch.int32, device=dev)
@@ -285,7 +286,7 @@ def test_nep_edge_cases(torch, L, tmpdir_session):
     tpos = torch.tensor(pos, dtype=torch.float64, device=dev)
     ttyp = torch.tensor(types, dtype=torch.int32, device=dev)
     # box shorter than twice the cutoff
-    nl = L.NeighborList(m, 2, 108, 96, 80, 32)
+    nl = L.NeighborList(m, 2, 108, 96, 48)
     with pytest.raises(L.NepError) as e:
         nl.build(tpos, [9.0, 12.15, 12.15], ttyp)
     assert e.value.code == 4
@@ -293,18 +294,24 @@ def test_nep_edge_cases(torch, L, tmpdir_session):
         nl.build(tpos, np.array([[12.15, 0.1, 0], [0, 12.15, 0], [0, 0, 12.15]]), ttyp)
     assert e.value.code == 3
     # capacity overflow is flagged and the lists stay within bounds
-    for caps in ((10, 10, 4), (96, 10, 4), (96, 80, 4)):
+    for caps in ((10, 4), (96, 4), (10, 48)):
         small = L.NeighborList(m, 2, 108, *caps)
         small.build(tpos, box, ttyp)
         st = small.status()
-        need = (st["max_candidates"], st["max_radial"], st["max_angular"])
+        need = (st["max_cand_radial"], st["max_cand_angular"])
         assert st["flags"] & L.FLAG_NEIGHBOR_OVERFLOW and any(n > c for n, c in zip(need, caps)), (caps, need)
         lst = small.to_host()
-        assert lst["cand"].shape[1] == caps[0] and lst["cnt_radial"].max() <= caps[1]
-        assert lst["cnt_angular"].max() <= caps[2]
-    # capacities out of order are rejected
+        assert lst["cand_radial"].shape[1] == caps[0] and lst["cand_angular"].shape[1] == caps[1]
+        assert lst["union_end_radial"][:, 0].max() <= caps[0] and lst["union_end_angular"][:, 0].max() <= caps[1]
+        # the overflow stays flagged while truncated rows are reused under a skin
+        small.set_skin(0.5)
+        small.build(tpos, box, ttyp)
+        small.status(clear=True)
+        small.build(tpos, box, ttyp)
+        assert small.status()["flags"] & L.FLAG_NEIGHBOR_OVERFLOW
+    # bad capacities are rejected
     with pytest.raises(L.NepError) as e:
-        L.NeighborList(m, 2, 108, 40, 80, 32)
+        L.NeighborList(m, 2, 108, 0, 32)
     assert e.value.code == 1
     # a NaN position is flagged, a bad species index is flagged
     bad = tpos.clone()
@@ -320,7 +327,7 @@ def test_nep_edge_cases(torch, L, tmpdir_session):
     # mismatched sizes are rejected on the host
     ws = L.Workspace(m, 2, 108)
     with pytest.raises(L.NepError) as e:
-        ws.compute(L.NeighborList(m, 2, 100, 8, 8, 8), tpos, box, ttyp, torch.zeros(2, dtype=torch.float64, device=dev),
+        ws.compute(L.NeighborList(m, 2, 100, 8, 8), tpos, box, ttyp, torch.zeros(2, dtype=torch.float64, device=dev),
                    torch.zeros((2, 108, 3), dtype=torch.float32, device=dev),
                    torch.zeros((2, 9), dtype=torch.float64, device=dev))
     assert e.value.code == 1
@@ -342,15 +349,13 @@ def test_skin_reuse_matches_fresh_lists(torch, L, tmpdir_session):
     for _ in range(4):
         eng.run(10)
         eng.nl.build(eng.pos, eng.box, eng.types)   # lists at the current positions (reuse or rebuild)
-        la = eng.nl.to_host()
+        la = eng.nl.to_host(eng.pos, eng.box, 160, 64)
         ref = L.NeighborList(eng.model, P, N, *eng.caps)
         ref.build(eng.pos, eng.box, eng.types)
         assert ref.status()["flags"] == 0
-        lb = ref.to_host()
-        S = la["n_species"]
+        lb = ref.to_host(eng.pos, eng.box, 160, 64)
         for kind in ("radial", "angular"):
             np.testing.assert_array_equal(la["cnt_" + kind], lb["cnt_" + kind])
-            np.testing.assert_array_equal(la["end_" + kind][:, :S], lb["end_" + kind][:, :S])
             valid = np.arange(la["nbr_" + kind].shape[1])[None, :, None] < la["cnt_" + kind][:, None, :]
             np.testing.assert_array_equal(la["nbr_" + kind][valid], lb["nbr_" + kind][valid])
         # forces from the reused rows equal those from fresh rows, bitwise

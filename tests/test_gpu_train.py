@@ -1,0 +1,141 @@
+"""Training kernels: the GPU gradient of the energy / force / virial loss
+against central finite differences of the FP64 oracle loss, and Adam
+lowering the loss.
+
+The student is a small NEP (n_max 4/4, 12 hidden units) on the 108-atom FCC
+crystal; the references come from a different random NEP evaluated by the
+oracle, so every residual is non-zero."""
+import copy
+import sys
+
+import numpy as np
+import pytest
+
+from conftest import write_model
+from paper_2409_04430_amd import configs
+from paper_2409_04430_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+LAM = (1.0, 1.0, 0.5)
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def L(torch):
+    from paper_2409_04430_amd import lib
+    return lib
+
+
+def setup(orc, tmpdir):
+    w = configs.WORKLOADS["fcc108"]
+    h = I.NepHyper(1, 5.0, 4.0, 4, 4, 8, 8, 4, False, 12)
+    student = I.random_model(h, np.random.default_rng(5), 0.06, 10.0)
+    teacher = I.random_model(h, np.random.default_rng(6), 0.06, 10.0)
+    s = w.systems(P=2)[0]
+    pos = s.pos + np.random.default_rng(1).normal(0.0, 0.05, s.pos.shape)
+    tp = write_model(tmpdir, "train_teacher", teacher)
+    r = orc.Model(tp).beads(pos, s.types, s.box)
+    ref = dict(E=r["E"], F=r["F"], W=r["W"])
+    return student, ref, pos, s.types, s.box
+
+
+def oracle_loss(orc, tmpdir, model, ref, pos, types, box):
+    path = write_model(tmpdir, "train_fd", model)
+    r = orc.Model(path).beads(pos, types, box)
+    return orc.train_loss(dict(E=r["E"], F=r["F"], W=r["W"]), ref, LAM, pos.shape[1])[0]
+
+
+def gpu_grad(torch, L, path, ref, pos, types, box):
+    m = L.Model(path)
+    P, N = pos.shape[:2]
+    dev = torch.device("cuda")
+    tpos = torch.tensor(pos, dtype=torch.float64, device=dev)
+    ttyp = torch.tensor(types, dtype=torch.int32, device=dev)
+    nl = L.fitted_neighbor_list(m, tpos, box, ttyp, 96, 48)
+    ws = L.Workspace(m, P, N)
+    tr = L.Trainer(m, P, N)
+    refs = (torch.tensor(ref["E"], dtype=torch.float64, device=dev),
+            torch.tensor(ref["F"], dtype=torch.float32, device=dev),
+            torch.tensor(ref["W"].reshape(P, 9), dtype=torch.float64, device=dev))
+    return m, nl, ws, tr, tpos, ttyp, refs
+
+
+def test_gradient_matches_oracle_fd(torch, L, orc, tmpdir_session):
+    student, ref, pos, types, box = setup(orc, tmpdir_session)
+    path = write_model(tmpdir_session, "train_student", student)
+    m, nl, ws, tr, tpos, ttyp, refs = gpu_grad(torch, L, path, ref, pos, types, box)
+    nl.build(tpos, box, ttyp)
+    tr.zero()
+    tr.accumulate(nl, ws, tpos, box, ttyp, *refs, LAM)
+    torch.cuda.synchronize()
+    g = tr.grad.cpu().numpy().astype(np.float64)
+    loss = tr.loss.cpu().numpy()
+    L0 = oracle_loss(orc, tmpdir_session, student, ref, pos, types, box)
+    say(f"[train] loss GPU {loss[0]:.6e} oracle {L0:.6e}")
+    assert abs(loss[0] - L0) <= 1e-4 * L0
+    off = tr.offsets
+    hp = student["hyper"]
+    H, D, NR1, KR1 = hp.hidden, hp.dim, hp.n_max_radial + 1, hp.basis_radial + 1
+    rng = np.random.default_rng(0)
+    picks = [("W0", (0, int(rng.integers(H)), int(rng.integers(D)))) for _ in range(6)]
+    picks += [("b0", (0, int(rng.integers(H)))) for _ in range(3)]
+    picks += [("w1", (0, int(rng.integers(H)))) for _ in range(3)]
+    picks += [("b1", None)]
+    picks += [("c_radial", (0, 0, int(rng.integers(NR1)), int(rng.integers(KR1)))) for _ in range(5)]
+    flat = {"W0": lambda ix: off["W0"] + ix[1] * D + ix[2], "b0": lambda ix: off["b0"] + ix[1],
+            "w1": lambda ix: off["w1"] + ix[1], "b1": lambda ix: off["b1"],
+            "c_radial": lambda ix: off["c_radial"] + ix[2] * KR1 + ix[3]}
+    h = 1e-4
+    fds, gs = [], []
+    for name, ix in picks:
+        vals = []
+        for sgn in (1, -1):
+            mm = copy.deepcopy(student)
+            if name == "b1":
+                mm["b1"] = student["b1"] + sgn * h
+            else:
+                arr = np.array(student[name], dtype=np.float64)
+                arr[ix] += sgn * h
+                mm[name] = arr
+            vals.append(oracle_loss(orc, tmpdir_session, mm, ref, pos, types, box))
+        fds.append((vals[0] - vals[1]) / (2 * h))
+        gs.append(g[flat[name](ix)])
+    fds, gs = np.array(fds), np.array(gs)
+    scale = np.abs(fds).max()
+    for (name, ix), a, b in zip(picks, gs, fds):
+        say(f"  d/d{name}{ix}: GPU {a:+.6e}  FD {b:+.6e}")
+    assert np.all(np.abs(gs - fds) <= 2e-3 * scale + 1e-7)
+
+
+def test_adam_lowers_loss(torch, L, orc, tmpdir_session):
+    student, ref, pos, types, box = setup(orc, tmpdir_session)
+    path = write_model(tmpdir_session, "train_student2", student)
+    m, nl, ws, tr, tpos, ttyp, refs = gpu_grad(torch, L, path, ref, pos, types, box)
+    nl.build(tpos, box, ttyp)
+    losses = []
+    for it in range(40):
+        tr.zero()
+        tr.accumulate(nl, ws, tpos, box, ttyp, *refs, LAM)
+        losses.append(float(tr.loss[0].item()))
+        tr.adam(2e-3, mask=L.Trainer.NETWORK | L.Trainer.RADIAL)
+    say(f"[train] Adam: loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    assert losses[-1] < 0.5 * losses[0]
+    # the trained parameters, written back as a model file, reproduce the GPU loss in the oracle
+    trained = m.to_dict()
+    L1 = oracle_loss(orc, tmpdir_session, trained, ref, pos, types, box)
+    tr.zero()
+    tr.accumulate(nl, ws, tpos, box, ttyp, *refs, LAM)
+    assert abs(float(tr.loss[0].item()) - L1) <= 1e-3 * L1
