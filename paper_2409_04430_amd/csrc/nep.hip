@@ -554,25 +554,36 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
 }
 
 // Per-(system, bead) totals from the per-workgroup partial sums of the
-// system's tiles, in tile order.
-__global__ void k_reduce(const double *__restrict__ partE, const double *__restrict__ partWa,
-                         const double *__restrict__ partWr, const int32_t *__restrict__ sys_tile0, int P,
-                         double *__restrict__ E, double *__restrict__ W)
+// system's tiles.  One workgroup per (system, bead): thread t adds tiles
+// t, t + 256, ... in order, then a fixed-shape tree over the threads, so the
+// result is bitwise reproducible.  Component 0 is E, 1..9 the virial.
+__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partE, const double *__restrict__ partWa,
+                                                const double *__restrict__ partWr, const int32_t *__restrict__ sys_tile0,
+                                                int P, double *__restrict__ E, double *__restrict__ W)
 {
+    __shared__ double red[10][256];
     const int sb = blockIdx.x, sy = sb / P, b = sb - sy * P, t = threadIdx.x;
     const int k0 = sys_tile0[sy], k1 = sys_tile0[sy + 1];
-    if (t == 0) {
-        double s = 0.0;
-        for (int k = k0; k < k1; ++k) s += partE[(size_t)k * P + b];
-        E[sb] = s;
-    } else if (t <= 9) {
-        double s = 0.0;
-        for (int k = k0; k < k1; ++k) {
-            const size_t o = ((size_t)k * P + b) * 9 + (t - 1);
-            s += partWa[o] + partWr[o];
-        }
-        W[(size_t)sb * 9 + (t - 1)] = s;
+    double acc[10];
+#pragma unroll
+    for (int c = 0; c < 10; ++c) acc[c] = 0.0;
+    for (int k = k0 + t; k < k1; k += blockDim.x) {
+        acc[0] += partE[(size_t)k * P + b];
+        const size_t o = ((size_t)k * P + b) * 9;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) acc[c + 1] += partWa[o + c] + partWr[o + c];
     }
+#pragma unroll
+    for (int c = 0; c < 10; ++c) red[c][t] = acc[c];
+    __syncthreads();
+    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int c = 0; c < 10; ++c) red[c][t] += red[c][t + w];
+        __syncthreads();
+    }
+    if (t == 0) E[sb] = red[0][0];
+    if (t >= 1 && t <= 9) W[(size_t)sb * 9 + (t - 1)] = red[t][0];
 }
 
 template <int NR1, int NA1, bool FOUR>
@@ -654,8 +665,8 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
     }
     {
         ProfScope ps_(K_REDUCE, s);
-        hipLaunchKernelGGL(k_reduce, dim3(nsys * P), dim3(64), 0, s, ws->partE, a.partWa, a.partWr, ws->sys_tile0, P,
-                           E, W);
+        hipLaunchKernelGGL(k_reduce, dim3(nsys * P), dim3(256), 0, s, ws->partE, a.partWa, a.partWr, ws->sys_tile0,
+                           P, E, W);
     }
     NEP_HIP(hipGetLastError());
     return NEP_OK;

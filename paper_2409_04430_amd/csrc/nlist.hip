@@ -476,12 +476,13 @@ __global__ __launch_bounds__(256) void k_reverse(const uint32_t *__restrict__ gr
     }
 }
 
-// Union lists.  The beads of an atom sit in G = 2^lg adjacent lanes; each
-// lane group walks its atom's candidate rows and keeps a candidate when the
-// pair is inside the cutoff for at least one bead (ballot over the group):
-// the radial list stores the atom index j, the angular list the slot k, and
-// both the bead mask of the exact decision, so that the force kernels take
-// it from there.
+// Union lists.  One wavefront per atom; its lanes hold 64 / G candidates
+// x G beads (G = 2^lg >= P), so a chunk of candidates is tested for every
+// bead at once.  A candidate is kept when the pair is inside the cutoff for
+// at least one bead (ballot over its lane group): the radial list stores the
+// atom index j, the angular list the slot k, and both the bead mask of the
+// exact decision, so that the force kernels take it from there.  Chunks are
+// appended in candidate order.
 __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, const float4 *__restrict__ pos4, int P,
                                                int N, int S, int lg, const int32_t *__restrict__ atom_sys,
                                                const SysGeom *__restrict__ geom, CutTest cR, CutTest cA,
@@ -492,18 +493,17 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
                                                int32_t *__restrict__ uniA, uint64_t *__restrict__ umA,
                                                int32_t *__restrict__ uendA, uint32_t *__restrict__ status)
 {
-    const int lane = threadIdx.x & 63, G = 1 << lg;
-    const int ia = ((blockIdx.x * blockDim.x + threadIdx.x) >> 6) * (64 >> lg) + (lane >> lg);
-    const int b = lane & (G - 1);
-    const bool atom_ok = ia < N, bead_ok = b < P;
-    const int i = atom_ok ? ia : N - 1;
+    const int lane = threadIdx.x & 63, G = 1 << lg, CPW = 64 >> lg;
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (i >= N) return;   // whole wavefront
+    const int cg = lane >> lg, b = lane & (G - 1);
+    const bool bead_ok = b < P;
     const int bb = bead_ok ? b : P - 1;
     const float4 pi = pos4[(size_t)i * P + bb];
     const double *pb = pos + (size_t)bb * N * 3;
     const SysGeom &g = geom[atom_sys[i]];
     const BoxD box{{g.L[0], g.L[1], g.L[2]}, {g.invL[0], g.invL[1], g.invL[2]}};
-    const int base = lane & ~(G - 1);
-    const uint64_t gmask = (G == 64) ? ~0ull : (((1ull << G) - 1ull) << base);
+    const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
     int most[2] = {0, 0};
 #pragma unroll
     for (int kind = 0; kind < 2; ++kind) {
@@ -514,35 +514,37 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
         uint64_t *um = (kind ? umA : umR) + (size_t)i * cap;
         int32_t *uend = (kind ? uendA : uendR) + (size_t)i * kMaxSpecies;
         const CutTest c = kind ? cA : cR;
-        int cnt = 0;
+        int cnt = 0;   // wave-uniform
         for (int t = 0; t < S; ++t) {
             const int k0 = min(o[t], cap), k1 = min(o[t + 1], cap);
-            for (int k = k0; k < k1; ++k) {
-                const int j = row[k] >> 2;
-                const float4 pj = pos4[(size_t)j * P + bb];
+            for (int kc = k0; kc < k1; kc += CPW) {
+                const int k = kc + cg;
+                const bool kin = k < k1;
+                const int j = row[kin ? k : k0] >> 2;
                 float dx, dy, dz;
-                packed_pair(pj, pi, g.M, g.h, dx, dy, dz);
+                packed_pair(pos4[(size_t)j * P + bb], pi, g.M, g.h, dx, dy, dz);
                 const float r2f = dx * dx + dy * dy + dz * dz;
-                const bool in = atom_ok && bead_ok && pair_within(r2f, c, pb, i, j, box);
-                const uint64_t m = __ballot(in) & gmask;
-                if (m) {
-                    // radial lists keep the atom index, angular ones the candidate slot;
-                    // bit b of the mask: inside in bead b
-                    if (b == 0 && atom_ok) {
-                        uni[cnt] = kind ? k : j;
-                        um[cnt] = m >> base;
+                const bool in = kin && bead_ok && pair_within(r2f, c, pb, i, j, box);
+                const uint64_t m = __ballot(in);
+                for (int q = 0; q < CPW && kc + q < k1; ++q) {
+                    const uint64_t gm = (m >> (q * G)) & gmask;
+                    if (gm) {
+                        // radial lists keep the atom index, angular ones the candidate slot
+                        if (lane == q * G) {
+                            uni[cnt] = kind ? k : j;
+                            um[cnt] = gm;
+                        }
+                        ++cnt;
                     }
-                    ++cnt;
                 }
             }
-            if (b == 0 && atom_ok) uend[t] = cnt;
+            if (lane == 0) uend[t] = cnt;
         }
-        most[kind] = atom_ok ? cnt : 0;
+        most[kind] = cnt;
     }
-    const int wR = wave_max_i(most[0]), wA = wave_max_i(most[1]);
     if (lane == 0) {
-        if (wR > 0) atomicMax(&status[1], (uint32_t)wR);
-        if (wA > 0) atomicMax(&status[2], (uint32_t)wA);
+        if (most[0] > 0) atomicMax(&status[1], (uint32_t)most[0]);
+        if (most[1] > 0) atomicMax(&status[2], (uint32_t)most[1]);
     }
 }
 
@@ -732,11 +734,10 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
     {
         ProfScope ps_(K_NLIST, s);
         const int lg = lanes_log2(P);
-        const int apw = 64 >> lg;
         const double rR2 = m->hp.rc_radial * m->hp.rc_radial, rA2 = m->hp.rc_angular * m->hp.rc_angular;
         const CutTest cR{(float)rR2, margin, rR2};
         const CutTest cA{(float)rA2, margin, rA2};
-        hipLaunchKernelGGL(k_union, dim3(div_up(N, 4 * apw)), dim3(kBlock), 0, s, pos,
+        hipLaunchKernelGGL(k_union, dim3(div_up(N, kBlock / 64)), dim3(kBlock), 0, s, pos,
                            reinterpret_cast<const float4 *>(nl->pos4), P, N, nl->S, lg, nl->atom_sys, nl->geom, cR,
                            cA, nl->candR, nl->offR, nl->candA, nl->offA, nl->capR, nl->capA, nl->uniR, nl->umR,
                            nl->uendR, nl->uniA, nl->umA, nl->uendA, nl->status);

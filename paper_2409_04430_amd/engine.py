@@ -98,6 +98,7 @@ class NepPimd:
             self.nl = lib.NeighborList(self.model, self.P, self.N, *caps,
                                        offsets=self.offsets if self.batched else None)
             self.nl.set_skin(self.skin)
+            self.nl.build(self.pos, self.box, self.types)
         self.caps = caps
 
     def forces(self):
