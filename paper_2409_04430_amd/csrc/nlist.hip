@@ -476,7 +476,8 @@ __global__ __launch_bounds__(256) void k_reverse(const uint32_t *__restrict__ gr
     }
 }
 
-// Union lists.  One wavefront per atom; its lanes hold 64 / G candidates
+// Union lists.  One wavefront per atom and list (grid.y picks the radial or
+// angular list); its lanes hold 64 / G candidates
 // x G beads (G = 2^lg >= P), so a chunk of candidates is tested for every
 // bead at once.  A candidate is kept when the pair is inside the cutoff for
 // at least one bead (ballot over its lane group): the radial list stores the
@@ -495,7 +496,8 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
 {
     const int lane = threadIdx.x & 63, G = 1 << lg, CPW = 64 >> lg;
     const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (i >= N) return;   // whole wavefront
+    const int kind = blockIdx.y;   // 0: radial list, 1: angular list
+    if (i >= N) return;            // whole wavefront
     const int cg = lane >> lg, b = lane & (G - 1);
     const bool bead_ok = b < P;
     const int bb = bead_ok ? b : P - 1;
@@ -504,9 +506,7 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
     const SysGeom &g = geom[atom_sys[i]];
     const BoxD box{{g.L[0], g.L[1], g.L[2]}, {g.invL[0], g.invL[1], g.invL[2]}};
     const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
-    int most[2] = {0, 0};
-#pragma unroll
-    for (int kind = 0; kind < 2; ++kind) {
+    {
         const int cap = kind ? capA : capR;
         const int32_t *row = (kind ? candA : candR) + (size_t)i * cap;
         const int32_t *o = (kind ? offA : offR) + (size_t)i * (kMaxSpecies + 1);
@@ -540,11 +540,7 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
             }
             if (lane == 0) uend[t] = cnt;
         }
-        most[kind] = cnt;
-    }
-    if (lane == 0) {
-        if (most[0] > 0) atomicMax(&status[1], (uint32_t)most[0]);
-        if (most[1] > 0) atomicMax(&status[2], (uint32_t)most[1]);
+        if (lane == 0 && cnt > 0) atomicMax(&status[1 + kind], (uint32_t)cnt);
     }
 }
 
@@ -737,7 +733,7 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
         const double rR2 = m->hp.rc_radial * m->hp.rc_radial, rA2 = m->hp.rc_angular * m->hp.rc_angular;
         const CutTest cR{(float)rR2, margin, rR2};
         const CutTest cA{(float)rA2, margin, rA2};
-        hipLaunchKernelGGL(k_union, dim3(div_up(N, kBlock / 64)), dim3(kBlock), 0, s, pos,
+        hipLaunchKernelGGL(k_union, dim3(div_up(N, kBlock / 64), 2), dim3(kBlock), 0, s, pos,
                            reinterpret_cast<const float4 *>(nl->pos4), P, N, nl->S, lg, nl->atom_sys, nl->geom, cR,
                            cA, nl->candR, nl->offR, nl->candA, nl->offA, nl->capR, nl->capA, nl->uniR, nl->umR,
                            nl->uendR, nl->uniA, nl->umA, nl->uendA, nl->status);
