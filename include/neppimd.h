@@ -111,6 +111,25 @@ int32_t nep_model_info(const nep_model *model, nep_hparams *out);
 
 void nep_model_destroy(nep_model *model);
 
+/* Arithmetic of the per-atom network (Sec. II.C) in nep_compute. */
+enum nep_mlp_mode {
+    NEP_MLP_FP32 = 0,       /* FP32 vector arithmetic (default) */
+    NEP_MLP_BF16_MFMA = 1   /* BF16 weights on the matrix cores, FP32 accumulate */
+};
+
+/* Select the network arithmetic used by nep_compute.  NEP_MLP_BF16_MFMA
+ * evaluates the hidden layer and its adjoint as [64 x D] x [D x H] and
+ * [64 x H] x [H x D] matrix-core products per wavefront of (atom, bead)
+ * rows: W0 is rounded to the nearest BF16 value (ties to even) from the
+ * model's FP32 weights, activations enter exactly (each as a sum of three
+ * BF16 terms), products accumulate in FP32.  It needs D <= 32 and H <= 32
+ * (NEP_ERR_UNSUPPORTED otherwise).  The BF16 copy is taken now, on
+ * `stream`, from the current device weights: call again after the weights
+ * change (nep_adam_step).  Not for concurrent use with nep_compute on
+ * another stream.  Errors: NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED,
+ * NEP_ERR_HIP. */
+int32_t nep_model_set_mlp(nep_model *model, int32_t mode, hipStream_t stream);
+
 /* ------------------------------------------------------------------ */
 /* Neighbour lists (per bead, minimum image, cell list)                */
 /* ------------------------------------------------------------------ */

@@ -67,6 +67,10 @@ def lib():
         L.or_trpmd_stage.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                      C.c_uint64, dp, dp, dp, dp, C.c_int64, C.c_int]
         L.or_cayley_coeffs.argtypes = [C.c_int, C.c_double, C.c_double, dp]
+        L.or_bf16_round.argtypes = [C.c_double]
+        L.or_bf16_round.restype = C.c_double
+        L.or_bf16_round_array.argtypes = [dp, dp, C.c_int]
+        L.or_model_round_w0_bf16.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -108,6 +112,11 @@ class Model:
          self.l_max, self.four_body, self.hidden, self.dim) = [int(x) for x in dims]
         self.rc_radial, self.rc_angular = float(rcs[0]), float(rcs[1])
 
+    def round_w0_bf16(self):
+        """Replace W0 by its BF16 values (the network of the matrix-core path); returns self."""
+        lib().or_model_round_w0_bf16(self._h)
+        return self
+
     def __del__(self):
         if getattr(self, "_h", None) and lib is not None:
             try:
@@ -145,6 +154,14 @@ class Model:
         if rc:
             raise RuntimeError(f"oracle: neighbour capacity {cap} too small")
         return dict(E=E, F=F, W=W.reshape(P, 3, 3), U=U, Wat=Wat.reshape(P, N, 3, 3))
+
+
+def bf16_round(x):
+    """Nearest BF16 value of the nearest FP32 value of each element (ties to even), as float64."""
+    x = _f64(x)
+    y = np.empty_like(x)
+    lib().or_bf16_round_array(_d(x), _d(y), x.size)
+    return y
 
 
 def neighbors(pos, box, rc: float, cap: int = 512):

@@ -148,6 +148,37 @@ void or_model_dims(const or_model *m, int *dims, double *rc)
 }
 
 /* ------------------------------------------------------------------ */
+/* BF16 weights                                                        */
+/* ------------------------------------------------------------------ */
+
+/* The BF16 number nearest to the FP32 number nearest to x (BF16: 8
+ * significant bits and the FP32 exponent range; ties to the even
+ * significand).  From the definition: with f = m 2^e, 1/2 <= |m| < 1, the
+ * BF16 numbers of that binade are k 2^(e-8), 128 <= k <= 256. */
+double or_bf16_round(double x)
+{
+    const float f = (float)x;
+    if (f == 0.0f || !isfinite(f)) return (double)f;
+    int e;
+    const double m = frexp((double)f, &e);
+    const double k = nearbyint(ldexp(m, 8));   /* default rounding: to nearest, ties to even */
+    return ldexp(k, e - 8);
+}
+
+void or_bf16_round_array(const double *x, double *y, int n)
+{
+    for (int i = 0; i < n; ++i) y[i] = or_bf16_round(x[i]);
+}
+
+/* Replace the first-layer weights W0 of every species by their BF16 values
+ * (the network of the matrix-core inference path). */
+void or_model_round_w0_bf16(or_model *m)
+{
+    const size_t n = (size_t)m->S * m->H * m->D;
+    for (size_t i = 0; i < n; ++i) m->W0[i] = or_bf16_round(m->W0[i]);
+}
+
+/* ------------------------------------------------------------------ */
 /* geometry                                                            */
 /* ------------------------------------------------------------------ */
 

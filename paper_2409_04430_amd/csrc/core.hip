@@ -389,7 +389,47 @@ extern "C" void nep_model_destroy(nep_model *m)
 {
     if (!m) return;
     if (m->dev) (void)hipFree(m->dev);
+    if (m->w0b) (void)hipFree(m->w0b);
     delete m;
+}
+
+// BF16 copies of the first-layer weights for the matrix-core network: each
+// FP32 weight rounded to the nearest BF16 value (ties to even mantissa),
+// zero-padded to 32 x 32 per species, once as [mu][v] (operand of the
+// forward product) and once as [v][mu] (operand of the adjoint product).
+__global__ void k_w0_bf16(const float *__restrict__ W0, int S, int H, int D, uint16_t *__restrict__ out)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= S * 1024) return;
+    const int s = t >> 10, mu = (t >> 5) & 31, v = t & 31;
+    uint16_t r = 0;
+    if (mu < H && v < D) {
+        const uint32_t u = __float_as_uint(W0[(size_t)s * H * D + mu * D + v]);
+        r = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    }
+    out[(size_t)s * 2048 + mu * 32 + v] = r;
+    out[(size_t)s * 2048 + 1024 + v * 32 + mu] = r;
+}
+
+extern "C" int32_t nep_model_set_mlp(nep_model *m, int32_t mode, hipStream_t s)
+{
+    if (!m) return fail(NEP_ERR_INVALID_ARG, "nep_model_set_mlp: null model");
+    if (mode == NEP_MLP_FP32) {
+        m->mlp = mode;
+        return NEP_OK;
+    }
+    if (mode != NEP_MLP_BF16_MFMA) return fail(NEP_ERR_INVALID_ARG, "nep_model_set_mlp: unknown mode %d", mode);
+    const nep_hparams &h = m->hp;
+    if (h.dim > 32 || h.hidden > 32)
+        return fail(NEP_ERR_UNSUPPORTED, "nep_model_set_mlp: the matrix-core network needs D <= 32 and H <= 32 "
+                                         "(model has D = %d, H = %d)", h.dim, h.hidden);
+    if (!m->w0b) NEP_HIP(hipMalloc(&m->w0b, sizeof(uint16_t) * 2048 * (size_t)h.n_species));
+    const int n = h.n_species * 1024;
+    hipLaunchKernelGGL(k_w0_bf16, dim3((n + 255) / 256), dim3(256), 0, s, m->dev + m->off.W0, h.n_species, h.hidden,
+                       h.dim, m->w0b);
+    NEP_HIP(hipGetLastError());
+    m->mlp = mode;
+    return NEP_OK;
 }
 
 // ----------------------------------------------------------- neighbour ---

@@ -41,6 +41,8 @@ struct nep_model {
     std::vector<float> host;   // packed parameters (FP32)
     float *dev = nullptr;      // device copy
     int device = 0;
+    int mlp = 0;               // NEP_MLP_FP32 or NEP_MLP_BF16_MFMA
+    uint16_t *w0b = nullptr;   // BF16 W0 per species: [S][2][32][32], layouts [mu][v] and [v][mu]
 };
 
 namespace nep {

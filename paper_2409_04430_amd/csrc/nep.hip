@@ -25,12 +25,145 @@
 
 namespace nep {
 
+// ------------------------------------------ matrix-core network ---
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kMfLd = 36;                       // LDS row stride (floats) of the staged tiles
+constexpr int kMfWave = 2 * 64 * kMfLd;         // floats of LDS per wavefront
+
+// Orders this wavefront's LDS writes before its later LDS reads (LDS
+// operations of one wavefront complete in issue order).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Eight FP32 values as three BF16 vectors whose sum is exact: truncation
+// keeps the top 8 significant bits, the remainder's top 8 bits follow, and
+// the last remainder has at most 8 significant bits left.
+__device__ __forceinline__ void split3(const float4 x0, const float4 x1, bf16x8 &hi, bf16x8 &mid, bf16x8 &lo)
+{
+    const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const uint32_t u0 = __float_as_uint(x[e]) & 0xffff0000u;
+        const float r1 = x[e] - __uint_as_float(u0);
+        const uint32_t u1 = __float_as_uint(r1) & 0xffff0000u;
+        const float r2 = r1 - __uint_as_float(u1);
+        hi[e] = __builtin_bit_cast(__bf16, (uint16_t)(u0 >> 16));
+        mid[e] = __builtin_bit_cast(__bf16, (uint16_t)(u1 >> 16));
+        lo[e] = __builtin_bit_cast(__bf16, (uint16_t)(__float_as_uint(r2) >> 16));
+    }
+}
+
+__device__ __forceinline__ f32x4 mfma3(const bf16x8 &hi, const bf16x8 &mid, const bf16x8 &lo, const bf16x8 &w, f32x4 c)
+{
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, w, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mid, w, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, w, c, 0, 0, 0);
+    return c;
+}
+
+// The network of the wavefront's 64 (atom, bead) rows on the matrix cores
+// (16 x 16 x 32 BF16 tiles, FP32 accumulate):
+//   Z = Qh W0^T,  h = tanh(Z - b0),  U = h w1 - b1,  G = (w1 (1 - h^2)) W0,
+// with Qh the scaled descriptors of each lane's own row (zero rows for lanes
+// outside the current species) and W0 the BF16 copy [S][2][32][32].  Tile
+// layout: operand element (row r, k) in lane r + 16 (k / 8), slot k % 8;
+// result (row r, col c) in lane c + 16 (r / 4), slot r % 4.  X and Y are
+// this wavefront's two 64 x kMfLd LDS tiles.  Returns U of the lane's row,
+// G (without the descriptor scale) in G[0..D).
+template <int D>
+__device__ float mlp_mfma(const float (&qh)[D], bool mine, const uint16_t *__restrict__ w0b, const float *b0,
+                          const float *w1, float b1, int H, float *X, float *Y, float (&G)[D])
+{
+    const int l = threadIdx.x & 63, lr = l & 15, lk = (l >> 4) * 8;
+#pragma unroll
+    for (int v4 = 0; v4 < 8; ++v4) {
+        float4 w;
+        w.x = (mine && 4 * v4 + 0 < D) ? qh[(4 * v4 + 0) < D ? 4 * v4 + 0 : 0] : 0.0f;
+        w.y = (mine && 4 * v4 + 1 < D) ? qh[(4 * v4 + 1) < D ? 4 * v4 + 1 : 0] : 0.0f;
+        w.z = (mine && 4 * v4 + 2 < D) ? qh[(4 * v4 + 2) < D ? 4 * v4 + 2 : 0] : 0.0f;
+        w.w = (mine && 4 * v4 + 3 < D) ? qh[(4 * v4 + 3) < D ? 4 * v4 + 3 : 0] : 0.0f;
+        *reinterpret_cast<float4 *>(X + l * kMfLd + 4 * v4) = w;
+    }
+    wave_lds_sync();
+    // weight operands: forward B(k = v, col = mu) = W0[mu][v]; adjoint B(k = mu, col = v) = W0[mu][v]
+    bf16x8 wf[2], wt[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        wf[c] = *reinterpret_cast<const bf16x8 *>(w0b + (16 * c + lr) * 32 + lk);
+        wt[c] = *reinterpret_cast<const bf16x8 *>(w0b + 1024 + (16 * c + lr) * 32 + lk);
+    }
+    float b0c[2], w1c[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int mu = 16 * c + lr;
+        b0c[c] = mu < H ? b0[mu] : 0.0f;
+        w1c[c] = mu < H ? w1[mu] : 0.0f;
+    }
+    // forward, one 16-row tile at a time; the hidden-layer adjoint goes to Y
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+        const float *xr = X + (16 * rt + lr) * kMfLd + lk;
+        bf16x8 ah, am, al;
+        split3(*reinterpret_cast<const float4 *>(xr), *reinterpret_cast<const float4 *>(xr + 4), ah, am, al);
+        float us[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+            z = mfma3(ah, am, al, wf[c], z);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float hh = tanhf(z[e] - b0c[c]);
+                us[e] += w1c[c] * hh;
+                Y[(16 * rt + 4 * (l >> 4) + e) * kMfLd + 16 * c + lr] = w1c[c] * (1.0f - hh * hh);
+            }
+        }
+        // row sums over the 16 lanes that share the rows
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) us[e] += __shfl_xor(us[e], o, 64);
+        }
+        if (lr == 0) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) X[(16 * rt + 4 * (l >> 4) + e) * kMfLd + 32] = us[e];
+        }
+    }
+    wave_lds_sync();
+    // adjoint: G = Y W0, written over the descriptor columns of X
+#pragma unroll
+    for (int rt = 0; rt < 4; ++rt) {
+        const float *yr = Y + (16 * rt + lr) * kMfLd + lk;
+        bf16x8 ah, am, al;
+        split3(*reinterpret_cast<const float4 *>(yr), *reinterpret_cast<const float4 *>(yr + 4), ah, am, al);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            f32x4 g = {0.0f, 0.0f, 0.0f, 0.0f};
+            g = mfma3(ah, am, al, wt[c], g);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) X[(16 * rt + 4 * (l >> 4) + e) * kMfLd + 16 * c + lr] = g[e];
+        }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int v = 0; v < D; ++v) G[v] = X[l * kMfLd + v];
+    const float u = X[l * kMfLd + 32] - b1;
+    wave_lds_sync();   // X and Y are rewritten by the next species of this wavefront
+    return u;
+}
+
 // ----------------------------------------------------------- pass 1 ---
 
-template <int NR1, int NA1, int KR1, int KA1, bool FOUR>
+template <int NR1, int NA1, int KR1, int KA1, bool FOUR, bool MF>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void k_descriptor(NepArgs a, const float *__restrict__ prm)
 {
+    extern __shared__ float mf_lds[];   // MF: two 64 x kMfLd tiles per wavefront
     constexpr int D = Dims<NR1, NA1, FOUR>::D;
     const LaneMap lm = lane_map(a);
     const int i = lm.i, b = lm.b, P = a.P, S = a.S;
@@ -48,11 +181,15 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
         const int tc = __builtin_amdgcn_readlane(ti, lead);
         const bool mine = valid && tok && ti == tc;
         todo &= ~__ballot(mine);
-        if (!mine) continue;
+        if constexpr (!MF) {
+            if (!mine) continue;
+        }
 
         float q[D];
 #pragma unroll
         for (int v = 0; v < D; ++v) q[v] = 0.0f;
+        float *Bo = a.B + ((size_t)i * P + b) * (NA1 * kNumSH);
+        if (MF ? mine : true) {
 
         // radial: per neighbour species, sum the basis, then contract with c
         const int32_t *uR = a.uniR + (size_t)i * a.capR;
@@ -166,7 +303,6 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             }
         }
         // park A in this atom's adjoint row (overwritten with B below)
-        float *Bo = a.B + ((size_t)i * P + b) * (NA1 * kNumSH);
 #pragma unroll
         for (int n = 0; n < NA1; ++n) {
             float4 *o4 = reinterpret_cast<float4 *>(Bo + n * kNumSH);
@@ -174,6 +310,7 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             for (int q4 = 0; q4 < kNumSH / 4; ++q4)
                 o4[q4] = make_float4(A[n][4 * q4], A[n][4 * q4 + 1], A[n][4 * q4 + 2], A[n][4 * q4 + 3]);
         }
+        }   // descriptors of the lanes of species tc
 
         // network: U = sum_mu w1 tanh(sum_nu W0 s_nu q_nu - b0) - b1;  G_nu = dU/dq_nu
         const float *qs = prm + a.oq;
@@ -183,23 +320,31 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             qh[v] = qs[v] * q[v];
             G[v] = 0.0f;
         }
-        const float *W0 = prm + a.oW0 + tc * a.H * D;
         const float *b0 = prm + a.ob0 + tc * a.H;
         const float *w1 = prm + a.ow1 + tc * a.H;
-        float u = -prm[a.ob1];
-        for (int mu = 0; mu < a.H; ++mu) {
-            float z = -b0[mu];
+        if constexpr (MF) {
+            float *X = mf_lds + (threadIdx.x >> 6) * kMfWave;
+            const float u = mlp_mfma<D>(qh, mine, a.w0b + (size_t)tc * 2048, b0, w1, prm[a.ob1], a.H, X,
+                                        X + 64 * kMfLd, G);
+            if (mine) U = u;
+        } else {
+            const float *W0 = prm + a.oW0 + tc * a.H * D;
+            float u = -prm[a.ob1];
+            for (int mu = 0; mu < a.H; ++mu) {
+                float z = -b0[mu];
 #pragma unroll
-            for (int v = 0; v < D; ++v) z += W0[mu * D + v] * qh[v];
-            const float h = tanhf(z);
-            u += w1[mu] * h;
-            const float gz = w1[mu] * (1.0f - h * h);
+                for (int v = 0; v < D; ++v) z += W0[mu * D + v] * qh[v];
+                const float h = tanhf(z);
+                u += w1[mu] * h;
+                const float gz = w1[mu] * (1.0f - h * h);
 #pragma unroll
-            for (int v = 0; v < D; ++v) G[v] += gz * W0[mu * D + v];
+                for (int v = 0; v < D; ++v) G[v] += gz * W0[mu * D + v];
+            }
+            U = u;
         }
 #pragma unroll
         for (int v = 0; v < D; ++v) G[v] *= qs[v];
-        U = u;
+        if (MF ? !mine : false) continue;
 
         // adjoints: B_nlm = dU/dA_nlm (A read back from the parked row)
 #pragma unroll
@@ -586,14 +731,15 @@ __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partE
     if (t >= 1 && t <= 9) W[(size_t)sb * 9 + (t - 1)] = red[t][0];
 }
 
-template <int NR1, int NA1, bool FOUR>
+template <int NR1, int NA1, bool FOUR, bool MF = false>
 static void launch(const NepArgs &a, const float *prm, int nblk, int wpb, hipStream_t s)
 {
     const dim3 g(nblk);
     const dim3 blk(64 * wpb);
     {
         ProfScope ps_(K_DESCRIPTOR, s);
-        hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR>), g, blk, 0, s, a, prm);
+        const size_t lds = MF ? sizeof(float) * kMfWave * wpb : 0;
+        hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, MF>), g, blk, lds, s, a, prm);
     }
     {
         ProfScope ps_(K_FORCE_ANG, s);
@@ -651,14 +797,25 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
     a.F = F; a.Eatom = E_atom; a.Watom = W_atom;
     a.oR = m->off.cR; a.oA = m->off.cA; a.oq = m->off.qs; a.oW0 = m->off.W0; a.ob0 = m->off.b0;
     a.ow1 = m->off.w1; a.ob1 = m->off.b1; a.osh = m->off.sh;
+    a.w0b = m->w0b;
+    const bool mf = m->mlp == NEP_MLP_BF16_MFMA;
     const int key = h.n_max_radial * 100 + h.n_max_angular * 10 + h.four_body;
     if (key != 440 && key != 441 && key != 640 && key != 860 && key != 881)
         return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");
     pack_positions(pos, P, N, nl->atom_sys, nl->geom, reinterpret_cast<float4 *>(ws->pos4), s);
     switch (key) {
-    case 440: launch<5, 5, false>(a, m->dev, ws->nblk, ws->wpb, s); break;
-    case 441: launch<5, 5, true>(a, m->dev, ws->nblk, ws->wpb, s); break;
-    case 640: launch<7, 5, false>(a, m->dev, ws->nblk, ws->wpb, s); break;
+    case 440:
+        if (mf) launch<5, 5, false, true>(a, m->dev, ws->nblk, ws->wpb, s);
+        else launch<5, 5, false>(a, m->dev, ws->nblk, ws->wpb, s);
+        break;
+    case 441:
+        if (mf) launch<5, 5, true, true>(a, m->dev, ws->nblk, ws->wpb, s);
+        else launch<5, 5, true>(a, m->dev, ws->nblk, ws->wpb, s);
+        break;
+    case 640:
+        if (mf) launch<7, 5, false, true>(a, m->dev, ws->nblk, ws->wpb, s);
+        else launch<7, 5, false>(a, m->dev, ws->nblk, ws->wpb, s);
+        break;
     case 860: launch<9, 7, false>(a, m->dev, ws->nblk, ws->wpb, s); break;
     case 881: launch<9, 9, true>(a, m->dev, ws->nblk, ws->wpb, s); break;
     default: return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");

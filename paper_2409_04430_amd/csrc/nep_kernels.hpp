@@ -34,6 +34,7 @@ struct NepArgs {
     float *Watom;
     // parameter offsets
     int oR, oA, oq, oW0, ob0, ow1, ob1, osh;
+    const uint16_t *w0b; // BF16 first-layer weights of the matrix-core network ([S][2][32][32])
 };
 
 // Lane -> (atom, bead): the beads of one atom occupy 2^lg adjacent lanes;

@@ -72,6 +72,7 @@ _sig = {
     "nep_load_params": (_i32, [C.c_char_p, C.POINTER(_vp)]),
     "nep_model_info": (_i32, [_vp, C.POINTER(HParams)]),
     "nep_model_destroy": (None, [_vp]),
+    "nep_model_set_mlp": (_i32, [_vp, _i32, _vp]),
     "nep_nlist_create": (_i32, [_vp, _i32, _i32, _i32, _i32, C.POINTER(_vp)]),
     "nep_nlist_create_batched": (_i32, [_vp, _i32, _i32, C.POINTER(C.c_int32), _i32, _i32, C.POINTER(_vp)]),
     "neighbor_build_batched": (_i32, [_vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, _vp]),
@@ -171,6 +172,9 @@ def _box9(box) -> C.Array:
 
 # ------------------------------------------------------------------ handles
 
+MLP_FP32, MLP_BF16_MFMA = 0, 1
+
+
 class Model:
     """nep_load_params / nep_model_info / nep_model_destroy."""
 
@@ -181,6 +185,7 @@ class Model:
         _check(_lib.nep_model_info(self._h, C.byref(hp)))
         self.hp = {f: getattr(hp, f) for f, _ in HParams._fields_}
         self.path = path
+        self.mlp = MLP_FP32
 
     @property
     def handle(self):
@@ -191,6 +196,11 @@ class Model:
         if hp is not None and k in hp:
             return hp[k]
         raise AttributeError(k)
+
+    def set_mlp(self, mode: int):
+        """nep_model_set_mlp on the current stream: MLP_FP32 or MLP_BF16_MFMA (re-call after the weights change)."""
+        _check(_lib.nep_model_set_mlp(self._h, int(mode), _stream()))
+        self.mlp = int(mode)
 
     def params(self):
         """(device pointer, count, offsets) of the model's FP32 parameter array."""
