@@ -393,11 +393,13 @@ void nep_train_ws_destroy(nep_train_ws *tw);
  * F_ref [P][N][3] (eV/A), W_ref [P][9] (eV), all device:
  *   L = sum_b lE (dE_b/N)^2 + lF sum_i |dF_bi|^2 / (3N) + lW sum_ab (dW_b,ab/N)^2
  * with lambda = {lE, lF, lW} (host).  grad [count] (device, the model's
- * parameter layout) is accumulated: += dL/dtheta for W0, b0, w1, b1 and
- * c_radial (other entries untouched); loss [4] (device) is accumulated:
- * total, energy, force and virial parts.  The force and virial parts enter
- * as mixed derivatives through a forward-mode pass of the descriptor along
- * the residual field.  Errors as nep_compute. */
+ * parameter layout) is accumulated: += dL/dtheta for W0, b0, w1, b1,
+ * c_radial and c_angular (other entries untouched); loss [4] (device) is
+ * accumulated: total, energy, force and virial parts.  The force and virial
+ * parts enter as mixed derivatives through a forward-mode pass of the
+ * descriptor along the residual field.  The model must use the FP32 network
+ * (NEP_ERR_INVALID_ARG after nep_model_set_mlp(NEP_MLP_BF16_MFMA)).  Errors
+ * as nep_compute. */
 int32_t nep_param_grad(const nep_model *model, nep_nlist *nl, nep_ws *ws, nep_train_ws *tw, const double *pos,
                        const double box[9], const int32_t *types, int32_t P, int32_t N, const double *E_ref,
                        const float *F_ref, const double *W_ref, const double lambda[3], float *grad, double *loss,
@@ -405,11 +407,19 @@ int32_t nep_param_grad(const nep_model *model, nep_nlist *nl, nep_ws *ws, nep_tr
 
 /* One Adam step (Kingma and Ba, with bias correction) on the model's
  * parameters: theta -= lr mhat / (sqrt(vhat) + eps), for the parameter
- * groups in mask (1: network W0, b0, w1, b1; 2: c_radial; 3: both).  m1, m2
+ * groups in mask (bits: 1 network W0, b0, w1, b1; 2 c_radial; 4 c_angular).  m1, m2
  * [count] device moment arrays (zero before step 1), step >= 1.  Errors:
  * NEP_ERR_INVALID_ARG. */
 int32_t nep_adam_step(nep_model *model, nep_train_ws *tw, const float *grad, float *m1, float *m2, int64_t step,
                       float lr, float beta1, float beta2, float eps, int32_t mask, hipStream_t stream);
+
+/* Force error of a model against another (the judge of a learned
+ * student against its teacher): work[0] = sqrt(sum_e (Fa[e] - Fb[e])^2 / n)
+ * over the n = 3 P N components of two force arrays Fa, Fb (device FP32,
+ * same layout), in eV/A.  work (device, caller-owned, 1025 doubles) also
+ * holds the partial sums; the sum order is fixed, so the result is bitwise
+ * reproducible.  n = 0 gives 0.  Errors: NEP_ERR_INVALID_ARG. */
+int32_t nep_force_rmse(const float *Fa, const float *Fb, int64_t n, double *work, hipStream_t stream);
 
 /* ------------------------------------------------------------------ */
 /* Kernel timing                                                       */

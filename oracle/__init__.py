@@ -156,6 +156,12 @@ class Model:
         return dict(E=E, F=F, W=W.reshape(P, 3, 3), U=U, Wat=Wat.reshape(P, N, 3, 3))
 
 
+def force_rmse(Fa, Fb) -> float:
+    """Root-mean-square difference over every force component, in FP64."""
+    d = _f64(Fa).ravel() - _f64(Fb).ravel()
+    return float(np.sqrt(np.mean(d * d))) if d.size else 0.0
+
+
 def bf16_round(x):
     """Nearest BF16 value of the nearest FP32 value of each element (ties to even), as float64."""
     x = _f64(x)

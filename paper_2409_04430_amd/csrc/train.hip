@@ -1,6 +1,7 @@
 // Training of a NEP model on GPU: gradient of an energy / force / virial
 // loss with respect to the network parameters (W0, b0, w1, b1) and the radial
-// descriptor coefficients c^R, and an Adam update (Kingma and Ba, ICLR 2015).
+// and angular descriptor coefficients c^R, c^A, and an Adam update (Kingma
+// and Ba, ICLR 2015).
 // The NEP site-energy model is that of Sec. II.C of arXiv:2409.04430; the
 // paper fits its models by SNES, this library by gradients.
 //
@@ -27,16 +28,17 @@ struct TrainArgs {
     const float *eE;    // [P] 2 lE/N^2 (E - E_ref)
     float *rows;        // [N*P][RW] factor rows, row i * P + b
     int RW;
+    float *xb;          // [N*P][2][NA1][24] scratch: X and B of the angular-coefficient pass
 };
 
 // Row layout (floats): type | u[H] | v[H] | gw1[H] | sq[D] | sqd[D] | gR[NR1] | GR[NR1] | sk[S][KR1] |
-// skd[S][KR1] | eE.
+// skd[S][KR1] | eE | gA[S][NA1][KA1].
 struct RowLayout {
-    int u, v, gw1, sq, sqd, gR, GR, sk, skd, eE, RW;
-    __host__ __device__ RowLayout(int H, int D, int NR1, int S, int KR1)
+    int u, v, gw1, sq, sqd, gR, GR, sk, skd, eE, gA, RW;
+    __host__ __device__ RowLayout(int H, int D, int NR1, int S, int KR1, int NA1, int KA1)
     {
         u = 1; v = u + H; gw1 = v + H; sq = gw1 + H; sqd = sq + D; gR = sqd + D; GR = gR + NR1; sk = GR + NR1;
-        skd = sk + S * KR1; eE = skd + S * KR1; RW = eE + 1;
+        skd = sk + S * KR1; eE = skd + S * KR1; gA = eE + 1; RW = gA + S * NA1 * KA1;
     }
 };
 
@@ -82,6 +84,14 @@ __global__ void k_residual(const float *__restrict__ F, const float *__restrict_
 
 // Descriptor, its derivative along the pair field d, and the network with
 // its forward derivative; writes the factor row of (atom, bead).
+//
+// Angular coefficients: with T_klm = sum_j f_k(r_ij) Y_lm(u_ij) (per
+// neighbour species), A_nlm = sum_k c_nk T_klm and q_nl = sum_m A_nlm^2, the
+// row's share of dL/dc_nk is sum_lm [X_nlm T_klm + B_nlm Tdot_klm] with
+// B = 2 G_nl A_nlm (the energy adjoint), X = eE B + Bdot and Bdot = 2 (Gdot_nl
+// A_nlm + G_nl Adot_nlm).  B and X are parked in the row's scratch, then a
+// second pass over the angular neighbours (one n at a time) accumulates
+// f_k (X.Y + B.Ydot) + fdot_k (u.d) (B.Y) into the row.
 template <int NR1, int NA1, int KR1, int KA1>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void k_train_jvp(NepArgs a, TrainArgs ta, const float *__restrict__ prm)
@@ -99,8 +109,9 @@ void k_train_jvp(NepArgs a, TrainArgs ta, const float *__restrict__ prm)
 #pragma unroll
     for (int e = 0; e < 9; ++e) cw[e] = ta.cW[9 * b + e];
     const float *shc = prm + a.osh;
-    const RowLayout R(H, D, NR1, S, KR1);
+    const RowLayout R(H, D, NR1, S, KR1, NA1, KA1);
     float *row = ta.rows + ((size_t)i * P + b) * ta.RW;
+    float *xb = ta.xb + ((size_t)i * P + b) * (2 * NA1 * kNumSH);
 
     uint64_t todo = __ballot(valid && tok);
     while (todo) {
@@ -237,6 +248,14 @@ void k_train_jvp(NepArgs a, TrainArgs ta, const float *__restrict__ prm)
                 q[NR1 + (l - 1) * NA1 + n] = s2;
                 qd[NR1 + (l - 1) * NA1 + n] = s2d;
             }
+        // park A and Adot (replaced by X and B once the network adjoints are known)
+#pragma unroll
+        for (int n = 0; n < NA1; ++n)
+#pragma unroll
+            for (int m = 0; m < kNumSH; ++m) {
+                xb[n * kNumSH + m] = A[n][m];
+                xb[(NA1 + n) * kNumSH + m] = Ad[n][m];
+            }
 
         // network and its forward derivative
         const float *qs = prm + a.oq;
@@ -291,6 +310,65 @@ void k_train_jvp(NepArgs a, TrainArgs ta, const float *__restrict__ prm)
             }
         row[R.eE] = eEb;
         row[0] = __int_as_float(tc);
+
+        // angular coefficients: park X and B, then one neighbour pass per n
+#pragma unroll
+        for (int n = 0; n < NA1; ++n)
+#pragma unroll
+            for (int m = 0; m < kNumSH; ++m) {
+                const int vv = NR1 + (sh_l(m) - 1) * NA1 + n;
+                const float g = qs[vv] * G[vv], gd = qs[vv] * Gd[vv];
+                const float An = xb[n * kNumSH + m], Adn = xb[(NA1 + n) * kNumSH + m];
+                const float Bv = 2.0f * g * An;
+                xb[n * kNumSH + m] = eEb * Bv + 2.0f * (gd * An + g * Adn);
+                xb[(NA1 + n) * kNumSH + m] = Bv;
+            }
+        for (int t = 0; t < S; ++t) {
+            int s0, s1;
+            block_range(a.uendA, i, t, s0, s1);
+            for (int n = 0; n < NA1; ++n) {
+                float Xn[kNumSH], Bn[kNumSH];
+#pragma unroll
+                for (int m = 0; m < kNumSH; ++m) {
+                    Xn[m] = xb[n * kNumSH + m];
+                    Bn[m] = xb[(NA1 + n) * kNumSH + m];
+                }
+                float acc[KA1];
+#pragma unroll
+                for (int k = 0; k < KA1; ++k) acc[k] = 0.0f;
+                for (int s = s0; s < s1; ++s) {
+                    if (!((mA[s] >> b) & 1u)) continue;
+                    const int j = rowA[uA[s]] >> 2;
+                    float dx, dy, dz;
+                    pair_vec(p4[(size_t)j * P + b], pi, lm, dx, dy, dz);
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const float rinv = __builtin_amdgcn_rsqf(r2);
+                    const float r = r2 * rinv;
+                    const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+                    float ex, ey, ez;
+                    field(ta.dF[(size_t)j * P + b], dx, dy, dz, ex, ey, ez);
+                    const float rdot = ux * ex + uy * ey + uz * ez;
+                    const float vx = (ex - ux * rdot) * rinv, vy = (ey - uy * rdot) * rinv,
+                                vz = (ez - uz * rdot) * rinv;
+                    float f[KA1], fp[KA1];
+                    cheb_fd<KA1>(r, a.rcAinv, f, fp);
+                    float Y[kNumSH], Dm[kNumSH];
+                    sh_eval(ux, uy, uz, shc, Y);
+                    sh_dir(ux, uy, uz, vx, vy, vz, shc, Dm);
+                    float al = 0.0f, be = 0.0f;
+#pragma unroll
+                    for (int m = 0; m < kNumSH; ++m) {
+                        al = fmaf(Xn[m], Y[m], fmaf(Bn[m], Dm[m], al));
+                        be = fmaf(Bn[m], Y[m], be);
+                    }
+                    be *= rdot;
+#pragma unroll
+                    for (int k = 0; k < KA1; ++k) acc[k] = fmaf(al, f[k], fmaf(be, fp[k], acc[k]));
+                }
+#pragma unroll
+                for (int k = 0; k < KA1; ++k) row[R.gA + (t * NA1 + n) * KA1 + k] = acc[k];
+            }
+        }
     }
 }
 
@@ -301,12 +379,12 @@ void k_train_jvp(NepArgs a, TrainArgs ta, const float *__restrict__ prm)
 // and the last output of the call is b1 -= sum eE.
 constexpr int kRowChunk = 16;
 __global__ __launch_bounds__(256) void k_grad_partial(const float *__restrict__ rows, size_t nrow, int RW, int S,
-                                                      int H, int D, int NR1, int KR1, int rows_per_block,
-                                                      float *__restrict__ part)
+                                                      int H, int D, int NR1, int KR1, int NA1, int KA1,
+                                                      int rows_per_block, float *__restrict__ part)
 {
     extern __shared__ float sh[];   // [kRowChunk][RW]
-    const RowLayout R(H, D, NR1, S, KR1);
-    const int per = H * D + 2 * H + S * NR1 * KR1;
+    const RowLayout R(H, D, NR1, S, KR1, NA1, KA1);
+    const int per = H * D + 2 * H + S * NR1 * KR1 + S * NA1 * KA1;
     const int nout = S * per + 1;
     const size_t r0 = (size_t)blockIdx.x * rows_per_block;
     const size_t r1 = r0 + rows_per_block < nrow ? r0 + rows_per_block : nrow;
@@ -325,11 +403,13 @@ __global__ __launch_bounds__(256) void k_grad_partial(const float *__restrict__ 
                 kind = 1; i1 = q - H * D;
             } else if (q < H * D + 2 * H) {
                 kind = 2; i1 = q - H * D - H;
-            } else {
+            } else if (q < H * D + 2 * H + S * NR1 * KR1) {
                 const int c = q - H * D - 2 * H;   // [t][n][k]
                 kind = 3; t = c / (NR1 * KR1);
                 const int nk = c - t * NR1 * KR1;
                 i1 = nk / KR1; i2 = nk - i1 * KR1;
+            } else {
+                kind = 5; i1 = q - H * D - 2 * H - S * NR1 * KR1;   // [t][n][k] of the angular coefficients
             }
         }
         float acc = 0.0f;
@@ -347,6 +427,7 @@ __global__ __launch_bounds__(256) void k_grad_partial(const float *__restrict__ 
                     if (kind == 0) acc = fmaf(rw[R.u + i1], rw[R.sqd + i2], fmaf(rw[R.v + i1], rw[R.sq + i2], acc));
                     else if (kind == 1) acc -= rw[R.v + i1];
                     else if (kind == 2) acc += rw[R.gw1 + i1];
+                    else if (kind == 5) acc += rw[R.gA + i1];
                     else acc = fmaf(rw[R.gR + i1], rw[R.sk + t * KR1 + i2], fmaf(rw[R.GR + i1], rw[R.skd + t * KR1 + i2], acc));
                 }
             }
@@ -357,9 +438,9 @@ __global__ __launch_bounds__(256) void k_grad_partial(const float *__restrict__ 
 
 // Sums the partials in block order and scatters them to the parameter layout.
 __global__ void k_grad_final(const float *__restrict__ part, int nblk, int S, int H, int D, int NR1, int KR1,
-                             ParamLayout off, float *__restrict__ grad)
+                             int NA1, int KA1, ParamLayout off, float *__restrict__ grad)
 {
-    const int per = H * D + 2 * H + S * NR1 * KR1;
+    const int per = H * D + 2 * H + S * NR1 * KR1 + S * NA1 * KA1;
     const int nout = S * per + 1;
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= nout) return;
@@ -373,7 +454,8 @@ __global__ void k_grad_final(const float *__restrict__ part, int nblk, int S, in
         if (q < H * D) idx = off.W0 + sp * H * D + q;
         else if (q < H * D + H) idx = off.b0 + sp * H + (q - H * D);
         else if (q < H * D + 2 * H) idx = off.w1 + sp * H + (q - H * D - H);
-        else idx = off.cR + sp * S * NR1 * KR1 + (q - H * D - 2 * H);
+        else if (q < H * D + 2 * H + S * NR1 * KR1) idx = off.cR + sp * S * NR1 * KR1 + (q - H * D - 2 * H);
+        else idx = off.cA + sp * S * NA1 * KA1 + (q - H * D - 2 * H - S * NR1 * KR1);
     }
     grad[idx] += (float)s;
 }
@@ -410,6 +492,7 @@ struct nep_train_ws {
     float4 *dF = nullptr;                // [N][P]
     float *cW = nullptr, *eE = nullptr;  // [P][9], [P]
     float *rows = nullptr;               // [N*P][RW]
+    float *xb = nullptr;                 // [N*P][2][NA1][24]
     float *part = nullptr;               // [nblk][nout]
     int RW = 0, nout = 0, nblk = 0, rows_per_block = 0;
     int32_t *trainable = nullptr;        // [params] 0/1
@@ -426,8 +509,9 @@ extern "C" int32_t nep_train_ws_create(const nep_model *m, int32_t P, int32_t N,
     if (key != 440 && key != 640 && key != 860)
         return fail(NEP_ERR_UNSUPPORTED, "nep_train_ws_create: unsupported model shape");
     const int S = h.n_species, H = h.hidden, D = h.dim, NR1 = h.n_max_radial + 1, KR1 = h.basis_radial + 1;
-    const RowLayout R(H, D, NR1, S, KR1);
-    const int nout = S * (H * D + 2 * H + S * NR1 * KR1) + 1;
+    const int NA1 = h.n_max_angular + 1, KA1 = h.basis_angular + 1;
+    const RowLayout R(H, D, NR1, S, KR1, NA1, KA1);
+    const int nout = S * (H * D + 2 * H + S * NR1 * KR1 + S * NA1 * KA1) + 1;
     if ((nout + 255) / 256 > 64) return fail(NEP_ERR_UNSUPPORTED, "nep_train_ws_create: model too large to train");
     *out = nullptr;
     nep_train_ws *w = new (std::nothrow) nep_train_ws;
@@ -447,6 +531,7 @@ extern "C" int32_t nep_train_ws_create(const nep_model *m, int32_t P, int32_t N,
     al((void **)&w->cW, sizeof(float) * 9 * P);
     al((void **)&w->eE, sizeof(float) * P);
     al((void **)&w->rows, sizeof(float) * PN * R.RW);
+    al((void **)&w->xb, sizeof(float) * PN * 2 * NA1 * kNumSH);
     al((void **)&w->part, sizeof(float) * (size_t)w->nblk * nout);
     al((void **)&w->trainable, sizeof(int32_t) * m->off.total);
     if (e != hipSuccess) {
@@ -462,7 +547,7 @@ extern "C" void nep_train_ws_destroy(nep_train_ws *w)
 {
     if (!w) return;
     for (void *p : {(void *)w->E, (void *)w->W, (void *)w->F, (void *)w->dF, (void *)w->cW, (void *)w->eE,
-                    (void *)w->rows, (void *)w->part, (void *)w->trainable})
+                    (void *)w->rows, (void *)w->xb, (void *)w->part, (void *)w->trainable})
         if (p) (void)hipFree(p);
     delete w;
 }
@@ -476,6 +561,8 @@ extern "C" int32_t nep_param_grad(const nep_model *m, nep_nlist *nl, nep_ws *ws,
         return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: null argument");
     if (tw->P != P || tw->N != N || nl->nsys != 1)
         return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: sizes do not match the training workspace");
+    if (m->mlp != NEP_MLP_FP32)
+        return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: training needs the FP32 network (nep_model_set_mlp)");
     int32_t rc = nep_compute(m, nl, ws, pos, box, types, P, N, tw->E, tw->F, tw->W, nullptr, nullptr, s);
     if (rc != NEP_OK) return rc;
     const size_t PN = (size_t)P * N;
@@ -491,7 +578,7 @@ extern "C" int32_t nep_param_grad(const nep_model *m, nep_nlist *nl, nep_ws *ws,
     a.umR = nl->umR; a.umA = nl->umA; a.uendA = nl->uendA; a.capR = nl->capR; a.capA = nl->capA;
     a.oR = m->off.cR; a.oA = m->off.cA; a.oq = m->off.qs; a.oW0 = m->off.W0; a.ob0 = m->off.b0;
     a.ow1 = m->off.w1; a.ob1 = m->off.b1; a.osh = m->off.sh;
-    TrainArgs t{tw->dF, tw->cW, tw->eE, tw->rows, tw->RW};
+    TrainArgs t{tw->dF, tw->cW, tw->eE, tw->rows, tw->RW, tw->xb};
     // rows of idle lanes stay unused: mark every row unused first
     fill_u32(reinterpret_cast<uint32_t *>(tw->rows), 0xffffffffu, PN * tw->RW, s);
     const int key = h.n_max_radial * 100 + h.n_max_angular * 10;
@@ -502,10 +589,11 @@ extern "C" int32_t nep_param_grad(const nep_model *m, nep_nlist *nl, nep_ws *ws,
     default: return fail(NEP_ERR_UNSUPPORTED, "nep_param_grad: unsupported model shape");
     }
     const int S = h.n_species, H = h.hidden, D = h.dim, NR1 = h.n_max_radial + 1, KR1 = h.basis_radial + 1;
+    const int NA1 = h.n_max_angular + 1, KA1 = h.basis_angular + 1;
     hipLaunchKernelGGL(k_grad_partial, dim3(tw->nblk), dim3(256), sizeof(float) * kRowChunk * tw->RW, s, tw->rows,
-                       PN, tw->RW, S, H, D, NR1, KR1, tw->rows_per_block, tw->part);
+                       PN, tw->RW, S, H, D, NR1, KR1, NA1, KA1, tw->rows_per_block, tw->part);
     hipLaunchKernelGGL(k_grad_final, dim3((tw->nout + 255) / 256), dim3(256), 0, s, tw->part, tw->nblk, S, H, D, NR1,
-                       KR1, m->off, grad);
+                       KR1, NA1, KA1, m->off, grad);
     NEP_HIP(hipGetLastError());
     return NEP_OK;
 }
@@ -528,7 +616,7 @@ extern "C" int32_t nep_adam_step(nep_model *m, nep_train_ws *tw, const float *gr
 {
     if (!m || !tw || !grad || !m1 || !m2) return fail(NEP_ERR_INVALID_ARG, "nep_adam_step: null argument");
     if (step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
-        !(eps > 0.0f) || mask < 1 || mask > 3)
+        !(eps > 0.0f) || mask < 1 || mask > 7)
         return fail(NEP_ERR_INVALID_ARG, "nep_adam_step: bad hyperparameters");
     const int n = m->off.total;
     if (tw->ntrain_mask != mask) {
@@ -540,6 +628,10 @@ extern "C" int32_t nep_adam_step(nep_model *m, nep_train_ws *tw, const float *gr
             const int nR = h.n_species * h.n_species * (h.n_max_radial + 1) * (h.basis_radial + 1);
             for (int k = m->off.cR; k < m->off.cR + nR; ++k) tr[k] = 1;
         }
+        if (mask & 4) {
+            const int nA = h.n_species * h.n_species * (h.n_max_angular + 1) * (h.basis_angular + 1);
+            for (int k = m->off.cA; k < m->off.cA + nA; ++k) tr[k] = 1;
+        }
         NEP_HIP(hipStreamSynchronize(s));
         NEP_HIP(hipMemcpy(tw->trainable, tr.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
         tw->ntrain_mask = mask;
@@ -547,6 +639,59 @@ extern "C" int32_t nep_adam_step(nep_model *m, nep_train_ws *tw, const float *gr
     const double c1 = 1.0 - std::pow((double)beta1, (double)step), c2 = 1.0 - std::pow((double)beta2, (double)step);
     hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, s, m->dev, grad, m1, m2, n, tw->trainable, lr,
                        beta1, beta2, eps, (float)c1, (float)c2);
+    NEP_HIP(hipGetLastError());
+    return NEP_OK;
+}
+
+// ------------------------------------------------------- force judge ---
+
+// Root-mean-square difference of two force arrays over every component,
+// sqrt(sum (Fa - Fb)^2 / n): fixed-grid partial sums in FP64, then one
+// block adds the partials in a fixed order (bitwise reproducible).
+constexpr int kRmseBlocks = 1024;
+
+__global__ __launch_bounds__(256) void k_rmse_partial(const float *__restrict__ Fa, const float *__restrict__ Fb,
+                                                      int64_t n, double *__restrict__ part)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const double d = (double)Fa[e] - (double)Fb[e];
+        acc += d * d;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_rmse_final(const double *__restrict__ part, int nblk, int64_t n,
+                                                    double *__restrict__ out)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += blockDim.x) acc += part[k];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = n > 0 ? sqrt(red[0] / (double)n) : 0.0;
+}
+
+extern "C" int32_t nep_force_rmse(const float *Fa, const float *Fb, int64_t n, double *work, hipStream_t s)
+{
+    if (!work) return fail(NEP_ERR_INVALID_ARG, "nep_force_rmse: null work array");
+    if (n < 0) return fail(NEP_ERR_INVALID_ARG, "nep_force_rmse: negative length");
+    if (n > 0 && (!Fa || !Fb)) return fail(NEP_ERR_INVALID_ARG, "nep_force_rmse: null force array");
+    const int nblk = (int)std::min<int64_t>(kRmseBlocks, std::max<int64_t>(1, (n + 255) / 256));
+    if (n > 0)
+        hipLaunchKernelGGL(k_rmse_partial, dim3(nblk), dim3(256), 0, s, Fa, Fb, n, work + 1);
+    hipLaunchKernelGGL(k_rmse_final, dim3(1), dim3(256), 0, s, work + 1, n > 0 ? nblk : 0, n, work);
     NEP_HIP(hipGetLastError());
     return NEP_OK;
 }

@@ -73,6 +73,7 @@ _sig = {
     "nep_model_info": (_i32, [_vp, C.POINTER(HParams)]),
     "nep_model_destroy": (None, [_vp]),
     "nep_model_set_mlp": (_i32, [_vp, _i32, _vp]),
+    "nep_force_rmse": (_i32, [_vp, _vp, C.c_int64, _vp, _vp]),
     "nep_nlist_create": (_i32, [_vp, _i32, _i32, _i32, _i32, C.POINTER(_vp)]),
     "nep_nlist_create_batched": (_i32, [_vp, _i32, _i32, C.POINTER(C.c_int32), _i32, _i32, C.POINTER(_vp)]),
     "neighbor_build_batched": (_i32, [_vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, _vp]),
@@ -229,7 +230,7 @@ class Model:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.nep_model_destroy(h)
             self._h = None
 
@@ -338,7 +339,7 @@ class NeighborList:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.nep_nlist_destroy(h)
             self._h = None
 
@@ -430,7 +431,7 @@ class Workspace:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.nep_ws_destroy(h)
             self._h = None
 
@@ -467,7 +468,7 @@ class Pimd:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.pimd_destroy(h)
             self._h = None
 
@@ -478,7 +479,8 @@ class Trainer:
     Holds the gradient, the Adam moments and the loss accumulator as device
     tensors in the model's parameter layout."""
 
-    NETWORK, RADIAL = 1, 2
+    NETWORK, RADIAL, ANGULAR = 1, 2, 4
+    ALL = 7
 
     def __init__(self, model: Model, P: int, N: int):
         t = _torch()
@@ -509,7 +511,7 @@ class Trainer:
                                    _ptr(W_ref, t.float64, (P, 9), "W_ref"), lam, _ptr(self.grad, t.float32),
                                    _ptr(self.loss, t.float64), _stream()))
 
-    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, mask: int = 3):
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, mask: int = 7):
         self.step_no += 1
         _check(_lib.nep_adam_step(self.model.handle, self._h, _ptr(self.grad, _torch().float32),
                                   _ptr(self.m1, _torch().float32), _ptr(self.m2, _torch().float32), self.step_no,
@@ -517,9 +519,22 @@ class Trainer:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and _lib is not None:
             _lib.nep_train_ws_destroy(h)
             self._h = None
+
+
+def force_rmse(Fa, Fb, work=None):
+    """nep_force_rmse on the current stream: device FP64 scalar tensor (a view of work[0])."""
+    t = _torch()
+    if Fa.shape != Fb.shape:
+        raise ValueError(f"force arrays differ in shape: {tuple(Fa.shape)} vs {tuple(Fb.shape)}")
+    if work is None:
+        work = t.empty(1025, dtype=t.float64, device=Fa.device)
+    n = Fa.numel()
+    _check(_lib.nep_force_rmse(_ptr(Fa, t.float32), _ptr(Fb, t.float32), n, _ptr(work, t.float64, (1025,), "work"),
+                               _stream()))
+    return work[0]
 
 
 def _torch():

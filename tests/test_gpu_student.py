@@ -133,3 +133,101 @@ def test_mfma_rejects_wide_models(torch, L, tmpdir_session):
     with pytest.raises(L.NepError):
         m.set_mlp(7)
     m.set_mlp(L.MLP_FP32)
+
+
+# ------------------------------------------------------------ judge ---
+
+def test_force_rmse_kernel(torch, L, orc):
+    """The judge's reduction against the oracle's plain FP64 mean, several lengths; reproducible."""
+    rng = np.random.default_rng(3)
+    for n in (0, 1, 5, 1000, 3 * 32 * 4096 + 7):
+        a = rng.normal(0.0, 1.0, n).astype(np.float32)
+        b = (a + rng.normal(0.0, 0.01, n)).astype(np.float32)
+        ta, tb = torch.tensor(a, device="cuda"), torch.tensor(b, device="cuda")
+        r1 = float(L.force_rmse(ta, tb))
+        r2 = float(L.force_rmse(ta, tb))
+        ref = orc.force_rmse(a, b)
+        say(f"  [rmse] n={n}: GPU {r1:.15e} oracle {ref:.15e}")
+        assert r1 == r2
+        assert abs(r1 - ref) <= 1e-12 * ref if n else r1 == 0.0
+
+
+# ------------------------------------------------- learned student ---
+
+def test_student_training_judge_and_gain(torch, L, tmpdir_session):
+    """Teacher PIMD labels -> trained student -> judged student PIMD.
+
+    The trained student must cut the force error of the untrained one by at
+    least 4x, run the PIMD loop on its own forces while the teacher's judge
+    accepts them, hand over to the teacher at the first judgement when the
+    threshold is below its error (then the run continues on the teacher's
+    forces, bitwise), and be faster per step than the teacher."""
+    import time
+    from paper_2409_04430_amd.engine import NepPimd
+    from paper_2409_04430_amd.student import StudentPimd, StudentTrainer, teacher_snapshots
+    w = configs.WORKLOADS["fcc32000"]
+    tpath = write_model(tmpdir_session, "gain_teacher", w.model())
+    spath = write_model(tmpdir_session, "gain_student", w.model(student=True))
+    P = 8
+
+    def make_system(T, ncell=4):
+        p0, t, b = I.fcc(ncell, 4.05)
+        return I.make_system(p0, t, b, w.species_masses, P, T, 0.05, np.random.default_rng(int(T) + ncell))
+
+    store = teacher_snapshots(tpath, make_system, [300.0, 500.0, 700.0], steps=60, every=4, warmup=20, dt=w.dt)
+    say(f"[student] {len(store)} snapshots x {P} beads x {store.N} atoms from teacher PIMD")
+    s0 = make_system(300.0)
+    tr = StudentTrainer(spath, store, s0.types, s0.box, holdout=0.2)
+    r0 = tr.rmse()
+    tr.fit(120, lr0=1e-2, lr1=3e-4, every=40, verbose=True)
+    r1 = tr.rmse()
+    say(f"[student] validation force RMSE: untrained {1e3 * r0:.1f} -> trained {1e3 * r1:.1f} meV/A")
+    assert r1 < 0.25 * r0
+    trained = str(tmpdir_session / "gain_student_trained.nep")
+    tr.save(trained)
+
+    # judged run that keeps the student
+    sysT = make_system(500.0)
+    thr = max(3.0 * r1, 0.020)
+    st = StudentPimd(tpath, trained, sysT, dt=w.dt, T=500.0, mode="trpmd", seed=3, judge_every=50, threshold=thr)
+    st.run(101)
+    st.check()
+    say(f"[student] judge history (step, RMSE eV/A): {st.history}, threshold {thr:.4f}")
+    assert st.on_student and [h[0] for h in st.history] == [0, 50, 100]
+    assert all(h[1] <= thr for h in st.history)
+    assert torch.isfinite(st.eng.pos).all()
+
+    # judged run that falls back at once
+    fb = StudentPimd(tpath, trained, sysT, dt=w.dt, T=500.0, mode="trpmd", seed=3, judge_every=50,
+                     threshold=1e-9)
+    fb.run(60)
+    fb.check()
+    assert not fb.on_student and fb.fallback_step == 0 and len(fb.history) == 1
+    e = fb.eng
+    fb.forces()
+    Et = torch.zeros_like(e.E)
+    Ft = torch.zeros_like(e.F)
+    Wt = torch.zeros_like(e.W)
+    fb.tws.compute(e.nl, e.pos, e.box, e.types, Et, Ft, Wt)
+    torch.cuda.synchronize()
+    assert torch.equal(e.F, Ft) and torch.equal(e.E, Et)
+
+    # throughput: student (judged every 50 steps) against the teacher, 2048 atoms x 32 beads
+    big = configs.WORKLOADS["fcc32000"]
+    p0, t, b = I.fcc(8, 4.05)
+    sysB = I.make_system(p0, t, b, big.species_masses, 32, 500.0, 0.05, np.random.default_rng(9))
+
+    def ms_per_step(obj, n=20):
+        obj.run(3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        obj.run(n)
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / n
+
+    teacher = NepPimd(tpath, sysB, dt=w.dt, T=500.0, mode="trpmd", seed=4, check_every=0)
+    student = StudentPimd(tpath, trained, sysB, dt=w.dt, T=500.0, mode="trpmd", seed=4, judge_every=50,
+                          threshold=1.0)
+    mt, ms = ms_per_step(teacher), ms_per_step(student)
+    say(f"[student] 2048 atoms x 32 beads: teacher {mt:.3f} ms/step, student {ms:.3f} ms/step, gain {mt / ms:.2f}x")
+    assert ms < mt / 1.5

@@ -1,6 +1,6 @@
 """Training kernels: the GPU gradient of the energy / force / virial loss
-against central finite differences of the FP64 oracle loss, and Adam
-lowering the loss.
+(network weights, radial and angular coefficients) against central finite
+differences of the FP64 oracle loss, and Adam lowering the loss.
 
 The student is a small NEP (n_max 4/4, 12 hidden units) on the 108-atom FCC
 crystal; the references come from a different random NEP evaluated by the
@@ -39,17 +39,21 @@ def L(torch):
     return lib
 
 
-def setup(orc, tmpdir):
-    w = configs.WORKLOADS["fcc108"]
-    h = I.NepHyper(1, 5.0, 4.0, 4, 4, 8, 8, 4, False, 12)
+def setup(orc, tmpdir, nspec=1):
+    h = I.NepHyper(nspec, 5.0, 4.0, 4, 4, 8, 8, 4, False, 12)
     student = I.random_model(h, np.random.default_rng(5), 0.06, 10.0)
     teacher = I.random_model(h, np.random.default_rng(6), 0.06, 10.0)
-    s = w.systems(P=2)[0]
-    pos = s.pos + np.random.default_rng(1).normal(0.0, 0.05, s.pos.shape)
-    tp = write_model(tmpdir, "train_teacher", teacher)
-    r = orc.Model(tp).beads(pos, s.types, s.box)
+    if nspec == 1:
+        s = configs.WORKLOADS["fcc108"].systems(P=2)[0]
+        pos, types, box = s.pos, s.types, s.box
+    else:
+        p0, types, box = I.rocksalt(3, 4.2)       # 216 atoms, L = 12.6 A
+        pos = I.replicate_beads(p0, 2)
+    pos = pos + np.random.default_rng(1).normal(0.0, 0.05, pos.shape)
+    tp = write_model(tmpdir, f"train_teacher{nspec}", teacher)
+    r = orc.Model(tp).beads(pos, types, box)
     ref = dict(E=r["E"], F=r["F"], W=r["W"])
-    return student, ref, pos, s.types, s.box
+    return student, ref, pos, np.asarray(types), np.asarray(box, np.float64)
 
 
 def oracle_loss(orc, tmpdir, model, ref, pos, types, box):
@@ -73,9 +77,10 @@ def gpu_grad(torch, L, path, ref, pos, types, box):
     return m, nl, ws, tr, tpos, ttyp, refs
 
 
-def test_gradient_matches_oracle_fd(torch, L, orc, tmpdir_session):
-    student, ref, pos, types, box = setup(orc, tmpdir_session)
-    path = write_model(tmpdir_session, "train_student", student)
+@pytest.mark.parametrize("nspec", [1, 2])
+def test_gradient_matches_oracle_fd(torch, L, orc, tmpdir_session, nspec):
+    student, ref, pos, types, box = setup(orc, tmpdir_session, nspec)
+    path = write_model(tmpdir_session, f"train_student{nspec}", student)
     m, nl, ws, tr, tpos, ttyp, refs = gpu_grad(torch, L, path, ref, pos, types, box)
     nl.build(tpos, box, ttyp)
     tr.zero()
@@ -89,15 +94,21 @@ def test_gradient_matches_oracle_fd(torch, L, orc, tmpdir_session):
     off = tr.offsets
     hp = student["hyper"]
     H, D, NR1, KR1 = hp.hidden, hp.dim, hp.n_max_radial + 1, hp.basis_radial + 1
+    NA1, KA1 = hp.n_max_angular + 1, hp.basis_angular + 1
+    S = nspec
     rng = np.random.default_rng(0)
-    picks = [("W0", (0, int(rng.integers(H)), int(rng.integers(D)))) for _ in range(6)]
-    picks += [("b0", (0, int(rng.integers(H)))) for _ in range(3)]
-    picks += [("w1", (0, int(rng.integers(H)))) for _ in range(3)]
+    sp = lambda: int(rng.integers(S))
+    picks = [("W0", (sp(), int(rng.integers(H)), int(rng.integers(D)))) for _ in range(6)]
+    picks += [("b0", (sp(), int(rng.integers(H)))) for _ in range(3)]
+    picks += [("w1", (sp(), int(rng.integers(H)))) for _ in range(3)]
     picks += [("b1", None)]
-    picks += [("c_radial", (0, 0, int(rng.integers(NR1)), int(rng.integers(KR1)))) for _ in range(5)]
-    flat = {"W0": lambda ix: off["W0"] + ix[1] * D + ix[2], "b0": lambda ix: off["b0"] + ix[1],
-            "w1": lambda ix: off["w1"] + ix[1], "b1": lambda ix: off["b1"],
-            "c_radial": lambda ix: off["c_radial"] + ix[2] * KR1 + ix[3]}
+    picks += [("c_radial", (sp(), sp(), int(rng.integers(NR1)), int(rng.integers(KR1)))) for _ in range(5)]
+    picks += [("c_angular", (sp(), sp(), int(rng.integers(NA1)), int(rng.integers(KA1)))) for _ in range(6)]
+    flat = {"W0": lambda ix: off["W0"] + (ix[0] * H + ix[1]) * D + ix[2],
+            "b0": lambda ix: off["b0"] + ix[0] * H + ix[1],
+            "w1": lambda ix: off["w1"] + ix[0] * H + ix[1], "b1": lambda ix: off["b1"],
+            "c_radial": lambda ix: off["c_radial"] + ((ix[0] * S + ix[1]) * NR1 + ix[2]) * KR1 + ix[3],
+            "c_angular": lambda ix: off["c_angular"] + ((ix[0] * S + ix[1]) * NA1 + ix[2]) * KA1 + ix[3]}
     h = 1e-4
     fds, gs = [], []
     for name, ix in picks:
@@ -130,7 +141,7 @@ def test_adam_lowers_loss(torch, L, orc, tmpdir_session):
         tr.zero()
         tr.accumulate(nl, ws, tpos, box, ttyp, *refs, LAM)
         losses.append(float(tr.loss[0].item()))
-        tr.adam(2e-3, mask=L.Trainer.NETWORK | L.Trainer.RADIAL)
+        tr.adam(2e-3, mask=L.Trainer.ALL)
     say(f"[train] Adam: loss {losses[0]:.4e} -> {losses[-1]:.4e}")
     assert losses[-1] < 0.5 * losses[0]
     # the trained parameters, written back as a model file, reproduce the GPU loss in the oracle
