@@ -51,6 +51,11 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--no-profile", action="store_true", help="do not bracket kernels with timing events")
+    ap.add_argument("--no-student", action="store_true", help="skip the learned-student leg")
+    ap.add_argument("--student-only", action="store_true",
+                    help="run only the learned-student leg (prints its JSON object)")
+    ap.add_argument("--student-epochs", type=int, default=200)
+    ap.add_argument("--student-steps", type=int, default=100, help="timed steps of the student and teacher runs")
     return ap.parse_args()
 
 
@@ -92,13 +97,16 @@ def flops_per_atom(hp: dict, nR: float, nA: float) -> dict:
     return {"descriptor": desc, "force_ang": force_ang, "force": force}
 
 
-def bytes_per_atom(hp: dict, nR: float, nA: float, P: int) -> dict:
-    """Minimum HBM bytes per (bead, atom): every array read or written once."""
+def bytes_per_atom(hp: dict, nR: float, nA: float, P: int, cR: float = 0.0, cA: float = 0.0) -> dict:
+    """Minimum HBM bytes per (bead, atom): every array read or written once.
+
+    cR, cA: mean candidate-row lengths (radial, angular) of an atom."""
     S, NA1 = hp["n_species"], hp["n_max_angular"] + 1
     KRP = (hp["basis_radial"] + 1 + 3) // 4 * 4
     masks = (nR + nA) / 8.0
     return {
-        "nlist": 24 + masks,
+        # packed position, the atom's candidate rows, its union entries (index + bead mask)
+        "nlist": 16 + 4 * (cR + cA) / P + 12 * (nR + nA) / P,
         "descriptor": 24 + 4 + masks + 4 * NA1 * 24 + 4 * S * KRP,
         "force_ang": 24 + 4 + masks + 4 * NA1 * 24 + 16 * nA + 12,
         "force": 24 + 4 + masks + 4 * S * KRP + 16 * nA + 12 + 12,
@@ -135,6 +143,86 @@ def cpu_baseline(w, model_path, system, nb_req: int):
                       f"step time = per-bead NEP time x {P} + integrator time"}
 
 
+def student_leg(args, torch, lib, configs, I):
+    """Learned student against its teacher on the 32,000-atom FCC crystal x 32 beads.
+
+    Teacher labels come from teacher NEP-PIMD of a 4x4x4-cell crystal
+    (256 atoms x 32 beads) at 300, 500 and 700 K; the student is trained on
+    them on the device, then both models drive NEP-PIMD of the large crystal
+    at 500 K; the student run is judged by the teacher every 50 steps
+    (fallback above 20 meV/A), and its timed steps include the judgements."""
+    from paper_2409_04430_amd.engine import NepPimd
+    from paper_2409_04430_amd.student import StudentPimd, StudentTrainer, teacher_snapshots
+    w = configs.WORKLOADS["fcc32000"]
+    tmp = tempfile.mkdtemp(prefix="neppimd_student_")
+    tpath, spath = os.path.join(tmp, "teacher.nep"), os.path.join(tmp, "student.nep")
+    I.write_model(tpath, w.model())
+    I.write_model(spath, w.model(student=True))
+    P = 32
+
+    def small(T):
+        p0, t, b = I.fcc(4, 4.05)
+        return I.make_system(p0, t, b, w.species_masses, P, T, 0.05, np.random.default_rng(int(T)))
+
+    t0 = time.perf_counter()
+    store = teacher_snapshots(tpath, small, [300.0, 500.0, 700.0], steps=120, every=6, warmup=30, dt=w.dt)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    s0 = small(300.0)
+    tr = StudentTrainer(spath, store, s0.types, s0.box, lambdas=(0.1, 1.0, 0.0), holdout=0.15)
+    t0 = time.perf_counter()
+    tr.fit(args.student_epochs, lr0=1e-2, lr1=3e-4, every=max(1, args.student_epochs))
+    t_train = time.perf_counter() - t0
+    val = tr.log[-1].val_rmse_F
+    trained = os.path.join(tmp, "student_trained.nep")
+    tr.save(trained)
+
+    big = w.systems(P=P)[0]
+    T = 500.0
+    n = args.student_steps
+
+    def timed(obj, steps):
+        stream = torch.cuda.current_stream()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        obj.run(steps)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    teacher = NepPimd(tpath, big, dt=w.dt, T=T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=0)
+    teacher.run(5)
+    ms_t = timed(teacher, max(10, n // 2))
+    teacher.check()
+    del teacher
+    student = StudentPimd(tpath, trained, big, dt=w.dt, T=T, tau=w.tau_T, mode=w.mode, seed=w.seed,
+                          judge_every=50, threshold=0.020)
+    student.run(10)
+    ms_s = timed(student, n)
+    student.check()
+    units = big.N * P
+    return {
+        "workload": f"fcc32000_p{P}", "atoms": big.N, "beads": P, "T_K": T, "mode": w.mode, "dt_fs": w.dt,
+        "teacher": {"value": round(units / (ms_t * 1e-3), 1), "ms_per_step": round(ms_t, 4),
+                    "model": "n_max 8/8, l_max 4 + four-body, 100 hidden, FP32 network"},
+        "student": {"value": round(units / (ms_s * 1e-3), 1), "ms_per_step": round(ms_s, 4),
+                    "model": "n_max 4/4, l_max 4, 30 hidden, BF16 MFMA network",
+                    "judge_every": 50, "threshold_meV_A": 20.0,
+                    "judged_rmse_meV_A": [round(1e3 * r, 3) for _, r in student.history],
+                    "fallback_step": student.fallback_step},
+        "gain": round(ms_t / ms_s, 3),
+        "training": {"bead_snapshots": store.bead_snapshots(), "atoms": store.N, "temperatures_K": [300, 500, 700],
+                     "epochs": len(tr.log) and tr.log[-1].epoch, "seconds": round(t_train, 2),
+                     "teacher_data_seconds": round(t_data, 2), "val_rmse_meV_A": round(1e3 * val, 3),
+                     "trained": "W0, b0, w1, b1, c_radial, c_angular (Adam)"},
+    }
+
+
+def hp_S(eng) -> int:
+    return int(eng.model.hp["n_species"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -146,6 +234,10 @@ def main():
     from paper_2409_04430_amd import inputs as I
     from paper_2409_04430_amd.engine import NepPimd
 
+    if args.student_only:
+        print(json.dumps({"metric": METRIC, "student_vs_teacher": student_leg(args, torch, lib, configs, I)}),
+              flush=True)
+        return
     w = configs.WORKLOADS[args.workload]
     systems = w.systems()
     if len(systems) != 1:
@@ -169,6 +261,8 @@ def main():
     lst = eng.nl.to_host(eng.pos, eng.box, eng.caps[0], eng.caps[1])
     nR = float(lst["cnt_radial"].mean())
     nA = float(lst["cnt_angular"].mean())
+    cR = float(lst["cand_off_radial"][:, hp_S(eng)].mean())
+    cA = float(lst["cand_off_angular"][:, hp_S(eng)].mean())
     hp = eng.model.hp
 
     # per-kernel breakdown: a short pass with every library kernel bracketed
@@ -223,7 +317,7 @@ def main():
     value = s.N * s.P * args.steps / elapsed
 
     flops = flops_per_atom(hp, nR, nA)
-    byts = bytes_per_atom(hp, nR, nA, s.P)
+    byts = bytes_per_atom(hp, nR, nA, s.P, cR, cA)
     units = s.N * s.P
     roof = None
     if dom and dom_avg_us:
@@ -249,6 +343,10 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, model_path, s, args.cpu_beads)
+    stu = None
+    if not args.no_student:
+        del eng
+        stu = student_leg(args, torch, lib, configs, I)
 
     out = {
         "metric": METRIC,
@@ -275,6 +373,7 @@ def main():
         "roofline": roof,
         "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
         "cpu_baseline": cpu,
+        "student_vs_teacher": stu,
     }
     print(json.dumps(out), flush=True)
 
