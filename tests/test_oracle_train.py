@@ -63,3 +63,44 @@ def test_b1_gradient_closed_form(orc, tmpdir_session):
     fd = (vals[0] - vals[1]) / (2 * h)
     closed = -2.0 * lam[0] * np.sum(out["E"] - ref["E"]) / N
     assert abs(fd - closed) <= 1e-7 * max(1.0, abs(closed))
+
+
+def test_w1_gradient_energy_part_closed_form(orc, tmpdir_session):
+    """With only the energy term, dL/dw1_mu = 2 lE / N^2 sum_b dE_b sum_i h_mu(i, b), where
+    h = tanh(W0 (s q) - b0) comes from the oracle's descriptors: FD of the loss must agree."""
+    _, student, teacher, pos, types, box = _setup(tmpdir_session)
+    N = pos.shape[1]
+    lam = (1.0, 0.0, 0.0)
+    ref = _eval(orc, tmpdir_session, "tl_t4", teacher, pos, types, box)
+    out = _eval(orc, tmpdir_session, "tl_s4", student, pos, types, box)
+    path = write_model(tmpdir_session, "tl_s4q", student)
+    M = orc.Model(path)
+    W0, b0, qs = student["W0"][0], student["b0"][0], student["q_scale"]
+    hsum = np.zeros(W0.shape[0])
+    dE = out["E"] - ref["E"]
+    for b in range(pos.shape[0]):
+        q = M.config(pos[b], types, box, want_q=True)["q"]
+        h = np.tanh((q * qs) @ W0.T - b0)           # [N, H]
+        hsum += dE[b] * h.sum(axis=0)
+    closed = 2.0 * lam[0] * hsum / N ** 2
+    hstep = 1e-5
+    for mu in (0, 5, 11):
+        vals = []
+        for sgn in (1, -1):
+            m = copy.deepcopy(student)
+            m["w1"] = np.array(student["w1"], dtype=np.float64)
+            m["w1"][0, mu] += sgn * hstep
+            vals.append(orc.train_loss(_eval(orc, tmpdir_session, "tl_w1", m, pos, types, box), ref, lam, N)[0])
+        fd = (vals[0] - vals[1]) / (2 * hstep)
+        assert abs(fd - closed[mu]) <= 1e-6 * max(1e-3, abs(closed[mu])), (mu, fd, closed[mu])
+
+
+def test_force_rmse_closed_forms(orc):
+    """Judge metric: a constant offset d on every component gives d; one differing component of n gives |d|/sqrt(n)."""
+    rng = np.random.default_rng(2)
+    F = rng.normal(0.0, 1.0, (4, 50, 3))
+    assert np.isclose(orc.force_rmse(F + 0.25, F), 0.25, rtol=1e-14)
+    G = F.copy()
+    G[2, 7, 1] += 3.0
+    assert np.isclose(orc.force_rmse(F, G), 3.0 / np.sqrt(F.size), rtol=1e-14)
+    assert orc.force_rmse(np.zeros(0), np.zeros(0)) == 0.0
