@@ -75,6 +75,7 @@ struct nep_nlist {
     double box_built[3] = {0.0, 0.0, 0.0};
     // Shared by all beads: ring-polymer centroids and candidate rows.
     double *cen = nullptr;        // [N][3] centroids of this call
+    float *spr = nullptr;         // [N] largest bead distance from the centroid (rounded up) of this call
     double *cen_ref = nullptr;    // [N][3] centroids at the last rebuild
     int32_t *candR = nullptr;     // [N][capR] entries (j << 2) | species(j), sorted by (species, j)
     int32_t *lenR = nullptr;      // [N] candidates found (may exceed capR: overflow)

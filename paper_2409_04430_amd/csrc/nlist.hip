@@ -80,11 +80,21 @@ __device__ __forceinline__ float wave_max_f(float v)
     return v;
 }
 
+// Sticky maximum of a status word: thousands of wavefronts updating one
+// address serialise in the L2, so the atomic is issued only when v exceeds
+// the stored value.  The words only grow between the host's clears, and a
+// kernel never sees a value older than the last clear, so a stale read can
+// only cost an extra atomic, never lose a maximum.
+__device__ __forceinline__ void raise_max(uint32_t *word, uint32_t v)
+{
+    if (v > __atomic_load_n(word, __ATOMIC_RELAXED)) atomicMax(word, v);
+}
+
 // Centroid of each atom's ring polymer, its largest bead distance and its
 // displacement from the centroid of the last rebuild (both rounded up).
 __global__ void k_centroid(const double *__restrict__ pos, const int32_t *__restrict__ types, int P, int N, int S,
-                           double *__restrict__ cen, const double *__restrict__ cen_ref, uint32_t *__restrict__ grid,
-                           uint32_t *__restrict__ status)
+                           double *__restrict__ cen, float *__restrict__ spr, const double *__restrict__ cen_ref,
+                           uint32_t *__restrict__ grid, uint32_t *__restrict__ status)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t f = 0;
@@ -110,6 +120,7 @@ __global__ void k_centroid(const double *__restrict__ pos, const int32_t *__rest
         cen[3 * i + 1] = c[1];
         cen[3 * i + 2] = c[2];
         const bool finite = isfinite(c[0]) && isfinite(c[1]) && isfinite(c[2]) && isfinite(m2);
+        spr[i] = finite ? (float)sqrt(m2) * 1.000001f + 1e-7f : 3.0e38f;
         if (!finite) {
             f |= NEP_FLAG_NONFINITE;
         } else {
@@ -121,10 +132,24 @@ __global__ void k_centroid(const double *__restrict__ pos, const int32_t *__rest
         const int t = types[i];
         if (t < 0 || t >= S) f |= NEP_FLAG_BAD_TYPE;
     }
+    // one atomic per workgroup and word (same-address atomics serialise)
+    __shared__ float red[2][kBlock / 64];
     spread = wave_max_f(spread);
     disp = wave_max_f(disp);
-    if ((threadIdx.x & 63) == 0 && spread > 0.0f) atomicMax(&grid[0], __float_as_uint(spread));
-    if ((threadIdx.x & 63) == 0 && disp > 0.0f) atomicMax(&grid[1], __float_as_uint(disp));
+    const int wv = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][wv] = spread;
+        red[1][wv] = disp;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+            spread = fmaxf(spread, red[0][w]);
+            disp = fmaxf(disp, red[1][w]);
+        }
+        if (spread > 0.0f) atomicMax(&grid[0], __float_as_uint(spread));
+        if (disp > 0.0f) atomicMax(&grid[1], __float_as_uint(disp));
+    }
     if (f) atomicOr(&status[0], f);
 }
 
@@ -390,8 +415,8 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
             cen_ref[3 * i] = ci[0];
             cen_ref[3 * i + 1] = ci[1];
             cen_ref[3 * i + 2] = ci[2];
-            atomicMax(&status[3], (uint32_t)cR);
-            atomicMax(&status[6], (uint32_t)cA);
+            raise_max(&status[3], (uint32_t)cR);
+            raise_max(&status[6], (uint32_t)cA);
             if (cR > capR || cA > capA) {
                 atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
                 atomicOr(&dg->rows_overflow, 1u);
@@ -477,14 +502,24 @@ __global__ __launch_bounds__(256) void k_reverse(const uint32_t *__restrict__ gr
 }
 
 // Union lists.  One wavefront per atom and list (grid.y picks the radial or
-// angular list); its lanes hold 64 / G candidates
-// x G beads (G = 2^lg >= P), so a chunk of candidates is tested for every
-// bead at once.  A candidate is kept when the pair is inside the cutoff for
-// at least one bead (ballot over its lane group): the radial list stores the
-// atom index j, the angular list the slot k, and both the bead mask of the
-// exact decision, so that the force kernels take it from there.  Chunks are
-// appended in candidate order.
-__global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, const float4 *__restrict__ pos4, int P,
+// angular list).  A candidate is kept when the pair is inside the cutoff for
+// at least one bead; the radial list stores the atom index j, the angular
+// list the candidate slot k, both with the bead mask of the exact per-bead
+// decisions, in candidate order.
+//
+// Each batch of 64 candidates (one per lane) is first classified from the
+// centroids: with d the minimum-image centroid distance and s = s_i + s_j
+// the two atoms' largest bead distances from their centroids, every bead
+// pair lies within [d - s, d + s] (the minimum image is the shortest image),
+// so d + s < rc - eps keeps all beads and d - s > rc + eps none.  Only the
+// remaining shell candidates are tested bead by bead (the exact test of the
+// per-bead lists), their G lanes per candidate holding the beads; each mask
+// is written back to its candidate's lane, and the kept candidates are
+// appended with one ballot-ranked store per lane.
+constexpr double kShellEps = 1e-3;   // A; far above the rounding of d and s
+
+__global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, const float4 *__restrict__ pos4,
+                                               const double *__restrict__ cen, const float *__restrict__ spr, int P,
                                                int N, int S, int lg, const int32_t *__restrict__ atom_sys,
                                                const SysGeom *__restrict__ geom, CutTest cR, CutTest cA,
                                                const int32_t *__restrict__ candR, const int32_t *__restrict__ offR,
@@ -506,42 +541,75 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
     const SysGeom &g = geom[atom_sys[i]];
     const BoxD box{{g.L[0], g.L[1], g.L[2]}, {g.invL[0], g.invL[1], g.invL[2]}};
     const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
-    {
-        const int cap = kind ? capA : capR;
-        const int32_t *row = (kind ? candA : candR) + (size_t)i * cap;
-        const int32_t *o = (kind ? offA : offR) + (size_t)i * (kMaxSpecies + 1);
-        int32_t *uni = (kind ? uniA : uniR) + (size_t)i * cap;
-        uint64_t *um = (kind ? umA : umR) + (size_t)i * cap;
-        int32_t *uend = (kind ? uendA : uendR) + (size_t)i * kMaxSpecies;
-        const CutTest c = kind ? cA : cR;
-        int cnt = 0;   // wave-uniform
-        for (int t = 0; t < S; ++t) {
-            const int k0 = min(o[t], cap), k1 = min(o[t + 1], cap);
-            for (int kc = k0; kc < k1; kc += CPW) {
-                const int k = kc + cg;
-                const bool kin = k < k1;
-                const int j = row[kin ? k : k0] >> 2;
-                float dx, dy, dz;
-                packed_pair(pos4[(size_t)j * P + bb], pi, g.M, g.h, dx, dy, dz);
-                const float r2f = dx * dx + dy * dy + dz * dz;
-                const bool in = kin && bead_ok && pair_within(r2f, c, pb, i, j, box);
+    const uint64_t full = (P == 64) ? ~0ull : ((1ull << P) - 1ull);
+    const double ci0 = cen[3 * (size_t)i], ci1 = cen[3 * (size_t)i + 1], ci2 = cen[3 * (size_t)i + 2];
+    const double si = (double)spr[i];
+
+    const int cap = kind ? capA : capR;
+    const int32_t *row = (kind ? candA : candR) + (size_t)i * cap;
+    const int32_t *o = (kind ? offA : offR) + (size_t)i * (kMaxSpecies + 1);
+    int32_t *uni = (kind ? uniA : uniR) + (size_t)i * cap;
+    uint64_t *um = (kind ? umA : umR) + (size_t)i * cap;
+    int32_t *uend = (kind ? uendA : uendR) + (size_t)i * kMaxSpecies;
+    const CutTest c = kind ? cA : cR;
+    const double rc = sqrt(c.rc2);
+    int cnt = 0;   // wave-uniform
+    for (int t = 0; t < S; ++t) {
+        const int k0 = min(o[t], cap), k1 = min(o[t + 1], cap);
+        for (int kb = k0; kb < k1; kb += 64) {
+            const int k = kb + lane;
+            const bool kin = k < k1;
+            const int j = kin ? row[k] >> 2 : i;
+            double dx = cen[3 * (size_t)j] - ci0, dy = cen[3 * (size_t)j + 1] - ci1, dz = cen[3 * (size_t)j + 2] - ci2;
+            dx -= box.L[0] * rint(dx * box.invL[0]);
+            dy -= box.L[1] * rint(dy * box.invL[1]);
+            dz -= box.L[2] * rint(dz * box.invL[2]);
+            const double d = sqrt(dx * dx + dy * dy + dz * dz);
+            const double sp = si + (double)spr[j];
+            const bool all_in = kin && d + sp < rc - kShellEps;
+            const bool shell = kin && !all_in && !(d - sp > rc + kShellEps);
+            int mlo = 0, mhi = 0;
+            uint64_t rem = __ballot(shell);
+            while (rem) {
+                // the next CPW shell candidates, one per group of G lanes
+                uint64_t take = rem;
+                int my = 0, nq = 0;
+                for (int q = 0; q < CPW && rem; ++q) {
+                    const int sq = __builtin_ctzll(rem);
+                    rem &= rem - 1;
+                    if (q == cg) my = sq;
+                    nq = q + 1;
+                }
+                const int jq = __shfl(j, my, 64);
+                float ex, ey, ez;
+                packed_pair(pos4[(size_t)jq * P + bb], pi, g.M, g.h, ex, ey, ez);
+                const float r2f = ex * ex + ey * ey + ez * ez;
+                const bool in = cg < nq && bead_ok && pair_within(r2f, c, pb, i, jq, box);
                 const uint64_t m = __ballot(in);
-                for (int q = 0; q < CPW && kc + q < k1; ++q) {
+                for (int q = 0; q < nq; ++q) {
+                    const int sq = __builtin_ctzll(take);
+                    take &= take - 1;
                     const uint64_t gm = (m >> (q * G)) & gmask;
-                    if (gm) {
-                        // radial lists keep the atom index, angular ones the candidate slot
-                        if (lane == q * G) {
-                            uni[cnt] = kind ? k : j;
-                            um[cnt] = gm;
-                        }
-                        ++cnt;
+                    if (lane == sq) {
+                        mlo = (int)(uint32_t)gm;
+                        mhi = (int)(uint32_t)(gm >> 32);
                     }
                 }
             }
-            if (lane == 0) uend[t] = cnt;
+            const uint64_t mask = all_in ? full : (shell ? (((uint64_t)(uint32_t)mhi << 32) | (uint32_t)mlo) : 0ull);
+            const bool keep = mask != 0ull;
+            const uint64_t bal = __ballot(keep);
+            const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0));
+            if (keep) {
+                // radial lists keep the atom index, angular ones the candidate slot
+                uni[cnt + rank] = kind ? k : j;
+                um[cnt + rank] = mask;
+            }
+            cnt += __popcll(bal);
         }
-        if (lane == 0 && cnt > 0) atomicMax(&status[1 + kind], (uint32_t)cnt);
+        if (lane == 0) uend[t] = cnt;
     }
+    if (lane == 0) raise_max(&status[1 + kind], (uint32_t)cnt);
 }
 
 // Per-bead lists written out for tests and analysis: one lane per (bead,
@@ -681,8 +749,8 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
     const dim3 gc(nl->ncell_total);
     {
         ProfScope ps_(K_CENTROID, s);
-        hipLaunchKernelGGL(k_centroid, g1, dim3(kBlock), 0, s, pos, types, P, N, nl->S, nl->cen, nl->cen_ref, nl->grid,
-                           nl->status);
+        hipLaunchKernelGGL(k_centroid, g1, dim3(kBlock), 0, s, pos, types, P, N, nl->S, nl->cen, nl->spr, nl->cen_ref,
+                           nl->grid, nl->status);
     }
     {
         ProfScope ps_(K_GRID, s);
@@ -734,7 +802,7 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
         const CutTest cR{(float)rR2, margin, rR2};
         const CutTest cA{(float)rA2, margin, rA2};
         hipLaunchKernelGGL(k_union, dim3(div_up(N, kBlock / 64), 2), dim3(kBlock), 0, s, pos,
-                           reinterpret_cast<const float4 *>(nl->pos4), P, N, nl->S, lg, nl->atom_sys, nl->geom, cR,
+                           reinterpret_cast<const float4 *>(nl->pos4), nl->cen, nl->spr, P, N, nl->S, lg, nl->atom_sys, nl->geom, cR,
                            cA, nl->candR, nl->offR, nl->candA, nl->offA, nl->capR, nl->capA, nl->uniR, nl->umR,
                            nl->uendR, nl->uniA, nl->umA, nl->uendA, nl->status);
     }

@@ -60,10 +60,17 @@ __global__ void k_residual(const float *__restrict__ F, const float *__restrict_
         const double cf = -2.0 * lF / (3.0 * N);
         dF[(size_t)i * P + b] = make_float4((float)(cf * dx), (float)(cf * dy), (float)(cf * dz), 0.0f);
     }
+    // one pair of atomics per workgroup (same-address atomics serialise)
+    __shared__ double red[4];
     for (int o = 32; o > 0; o >>= 1) lf += __shfl_xor(lf, o);
-    if ((threadIdx.x & 63) == 0 && lf != 0.0) {
-        atomicAdd(&loss[2], lf);
-        atomicAdd(&loss[0], lf);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lf;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) lf += red[w];
+        if (lf != 0.0) {
+            atomicAdd(&loss[2], lf);
+            atomicAdd(&loss[0], lf);
+        }
     }
     if (blockIdx.x == 0 && (int)threadIdx.x < P) {
         const int b = threadIdx.x;
@@ -518,7 +525,8 @@ extern "C" int32_t nep_train_ws_create(const nep_model *m, int32_t P, int32_t N,
     if (!w) return fail(NEP_ERR_NOMEM, "host allocation failed");
     w->P = P; w->N = N; w->RW = R.RW; w->nout = nout;
     const size_t PN = (size_t)P * N;
-    w->rows_per_block = 512;
+    // enough workgroups to fill the chip for a single snapshot, at most 512 rows each
+    w->rows_per_block = (int)std::min<size_t>(512, std::max<size_t>(kRowChunk, (PN + 1023) / 1024));
     w->nblk = (int)((PN + w->rows_per_block - 1) / w->rows_per_block);
     hipError_t e = hipSuccess;
     auto al = [&](void **p, size_t bytes) {
