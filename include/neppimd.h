@@ -265,7 +265,9 @@ void nep_ws_destroy(nep_ws *ws);
 
 /* NEP energy, forces and virial of every bead (Sec. II.C site energies,
  * Sec. II.A bead forces and virial), from neighbour sets built by
- * neighbor_build on the same pos/box/types.  The angular pair terms
+ * neighbor_build on the same pos/box/types; the positions that call packed
+ * are reused, so pos must not change between the two calls.  The angular
+ * pair terms
  * dU_i/dr_ij are stored in the handle's pair buffer and gathered back by
  * the reverse slots, so no atomics are used.
  *   E      [P]      dev float64  per-bead sum of site energies
@@ -274,8 +276,10 @@ void nep_ws_destroy(nep_ws *ws);
  *   E_atom [P][N]   dev float32  site energies U_i, or NULL
  *   W_atom [P][N][9] dev float32 per-atom virial -1/2 sum_j r_ij (x)
  *                   (dU_i/dr_ij - dU_j/dr_ji), or NULL
- * Positions enter as FP64; pair vectors are formed in FP64 and the rest is
- * FP32 arithmetic with FP64 accumulation of forces, energies and virials.
+ * Positions enter as FP64 and are packed per bead as fine-grid cell
+ * indices plus FP32 offsets, from which pair vectors are formed (error
+ * about 1e-6 A); the rest is FP32 arithmetic with FP64 accumulation of
+ * forces, energies and virials.
  * The summation order is fixed, so repeated calls give identical bits.
  * Errors: NEP_ERR_INVALID_ARG (sizes differ from the handles'), NEP_ERR_HIP.
  * Non-finite forces set NEP_FLAG_NONFINITE in the workspace. */

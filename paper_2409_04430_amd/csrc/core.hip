@@ -648,7 +648,6 @@ extern "C" int32_t nep_ws_create_batched(const nep_model *m, int32_t P, int32_t 
     if (e == hipSuccess) e = dalloc(&w->partE, (size_t)std::max(P, 1) * nb);
     if (e == hipSuccess) e = dalloc(&w->partW, (size_t)2 * std::max(P, 1) * nb * 9);
     if (e == hipSuccess) e = dalloc(&w->Fang, PN * 3);
-    if (e == hipSuccess) e = dalloc(&w->pos4, PN * 4);
     if (e == hipSuccess) e = dalloc(&w->flags, 4);
     if (e == hipSuccess) e = hipMemset(w->flags, 0, 4 * sizeof(uint32_t));
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -671,7 +670,7 @@ extern "C" int32_t nep_ws_create(const nep_model *m, int32_t P, int32_t N, nep_w
 extern "C" void nep_ws_destroy(nep_ws *w)
 {
     if (!w) return;
-    for (void *p : {(void *)w->B, (void *)w->arad, (void *)w->partE, (void *)w->partW, (void *)w->Fang, (void *)w->pos4,
+    for (void *p : {(void *)w->B, (void *)w->arad, (void *)w->partE, (void *)w->partW, (void *)w->Fang,
                     (void *)w->flags, (void *)w->tile_atom0, (void *)w->tile_atom1, (void *)w->tile_sys,
                     (void *)w->sys_tile0})
         if (p) (void)hipFree(p);

@@ -121,7 +121,6 @@ struct nep_ws {
     double *partE = nullptr;   // [nblk_cap][P]
     double *partW = nullptr;   // [2][nblk_cap][P][9] (angular pass, radial pass)
     float *Fang = nullptr;     // [N][P][3] angular part of the forces
-    float *pos4 = nullptr;     // [N][P][4] packed positions (bead-minor)
     uint32_t *flags = nullptr; // [1]
 };
 

@@ -782,7 +782,8 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
     }
     const nep_hparams &h = m->hp;
     NepArgs a{};
-    a.p4 = reinterpret_cast<const float4 *>(ws->pos4); a.pos = pos; a.types = types; a.N = N; a.S = h.n_species;
+    // packed positions of the last neighbor_build (the same positions, see the header)
+    a.p4 = reinterpret_cast<const float4 *>(nl->pos4); a.pos = pos; a.types = types; a.N = N; a.S = h.n_species;
     a.H = h.hidden; a.P = P; a.lg = lanes_log2(P);
     a.geom = nl->geom; a.tile_atom0 = ws->tile_atom0; a.tile_atom1 = ws->tile_atom1; a.tile_sys = ws->tile_sys;
     a.rcRinv = (float)(1.0 / h.rc_radial); a.rcAinv = (float)(1.0 / h.rc_angular);
@@ -802,7 +803,6 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
     const int key = h.n_max_radial * 100 + h.n_max_angular * 10 + h.four_body;
     if (key != 440 && key != 441 && key != 640 && key != 860 && key != 881)
         return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");
-    pack_positions(pos, P, N, nl->atom_sys, nl->geom, reinterpret_cast<float4 *>(ws->pos4), s);
     switch (key) {
     case 440:
         if (mf) launch<5, 5, false, true>(a, m->dev, ws->nblk, ws->wpb, s);

@@ -39,7 +39,7 @@ struct DevGlobal {
     float d_build;          // D at the last rebuild
     uint32_t rows_overflow; // a candidate row of the last rebuild was truncated
     int rebuild;            // 1: rebuild the candidate rows in this call
-    int pad;
+    uint32_t ticket;        // workgroups of k_centroid finished in this call (reset by the last)
     double R2;              // radial candidate radius squared of the last rebuild
     double RA2;             // angular candidate radius squared
 };
@@ -92,9 +92,15 @@ __device__ __forceinline__ void raise_max(uint32_t *word, uint32_t v)
 
 // Centroid of each atom's ring polymer, its largest bead distance and its
 // displacement from the centroid of the last rebuild (both rounded up).
-__global__ void k_centroid(const double *__restrict__ pos, const int32_t *__restrict__ types, int P, int N, int S,
-                           double *__restrict__ cen, float *__restrict__ spr, const double *__restrict__ cen_ref,
-                           uint32_t *__restrict__ grid, uint32_t *__restrict__ status)
+__device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double rcR, double rcA, double skin,
+                              int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status);
+
+__global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ pos, const int32_t *__restrict__ types,
+                                                     int P, int N, int S, double *__restrict__ cen,
+                                                     float *__restrict__ spr, const double *__restrict__ cen_ref,
+                                                     const SysGeom *__restrict__ geom, int nsys, double rcR,
+                                                     double rcA, double skin, int force, uint32_t *__restrict__ grid,
+                                                     uint32_t *__restrict__ status)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t f = 0;
@@ -151,19 +157,31 @@ __global__ void k_centroid(const double *__restrict__ pos, const int32_t *__rest
         if (disp > 0.0f) atomicMax(&grid[1], __float_as_uint(disp));
     }
     if (f) atomicOr(&status[0], f);
+
+    // the last workgroup to finish takes the rebuild decision (no waiting:
+    // every other workgroup has already retired its maxima when it counts)
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&dev_global(grid)->ticket, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;   // whole workgroup
+    __threadfence();
+    grid_decision(geom, nsys, rcR, rcA, skin, force, grid, status);
+    if (threadIdx.x == 0) dev_global(grid)->ticket = 0u;
 }
 
 // Rebuild decision and, on a rebuild, the grid and candidate radius from the
 // measured spread.  Candidate rows built with radius rc + 2 D0 + skin stay
 // complete while 2 (D - D0) + 2 max|c - c0| <= skin (triangle inequality on
 // the periodic centroid distance); otherwise they are rebuilt.
-__global__ __launch_bounds__(64) void k_grid(const SysGeom *__restrict__ geom, int nsys, double rcR, double rcA,
-                                             double skin, int force, uint32_t *__restrict__ grid,
-                                             uint32_t *__restrict__ status)
+// Run by the last workgroup of k_centroid, after every workgroup's maxima.
+__device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double rcR, double rcA, double skin,
+                              int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status)
 {
     DevGlobal *dg = dev_global(grid);
-    const float spread = __uint_as_float(dg->spread_bits);
-    const float disp = __uint_as_float(dg->disp_bits);
+    const float spread = __uint_as_float(__atomic_load_n(&dg->spread_bits, __ATOMIC_RELAXED));
+    const float disp = __uint_as_float(__atomic_load_n(&dg->disp_bits, __ATOMIC_RELAXED));
     const double need = 2.0 * ((double)spread - (double)dg->d_build) + 2.0 * (double)disp;
     const int rebuild = force || !(need <= skin);
     const double rc = rcR > rcA ? rcR : rcA;
@@ -185,7 +203,10 @@ __global__ __launch_bounds__(64) void k_grid(const SysGeom *__restrict__ geom, i
     __syncthreads();   // every thread has read the record of the last rebuild
     if (threadIdx.x != 0) return;
     dg->rebuild = rebuild;
-    atomicMax(&status[4], dg->spread_bits);
+    atomicMax(&status[4], __float_as_uint(spread));
+    // the next call's maxima start from zero
+    dg->spread_bits = 0u;
+    dg->disp_bits = 0u;
     if (!rebuild) {
         // reused rows that were truncated keep the overflow flag raised
         if (dg->rows_overflow) atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
@@ -262,7 +283,7 @@ __global__ void k_cell_fill(const double *__restrict__ cen, int N, const int32_t
 constexpr int kRankMax = 1024;
 __global__ __launch_bounds__(64) void k_cell_rank(const uint32_t *__restrict__ grid,
                                                   const int32_t *__restrict__ cell_start,
-                                                  int32_t *__restrict__ cell_atoms)
+                                                  int32_t *__restrict__ cell_atoms, int32_t *__restrict__ cell_cnt)
 {
     __shared__ int32_t v[kRankMax];
     __shared__ int32_t out[kRankMax];
@@ -292,6 +313,7 @@ __global__ __launch_bounds__(64) void k_cell_rank(const uint32_t *__restrict__ g
             a[q + 1] = x;
         }
     }
+    if (threadIdx.x == 0) cell_cnt[c] = 0;   // the counts start from zero at the next rebuild
 }
 
 // Candidate rows.  One workgroup per cell; the centroids of its stencil
@@ -430,11 +452,22 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
 // number of smaller keys), in LDS for rows up to kSortLds, otherwise through
 // the atom's reverse-slot row as scratch (it is rewritten afterwards).
 constexpr int kSortLds = 512;
-__global__ __launch_bounds__(256) void k_sort_rows(const uint32_t *__restrict__ grid, int N, int S, int capC,
-                                                   int32_t *__restrict__ cand, const int32_t *__restrict__ rowlen,
-                                                   int32_t *__restrict__ off, int32_t *__restrict__ scratch)
+struct SortRows {
+    int capC;
+    int32_t *cand;
+    const int32_t *rowlen;
+    int32_t *off, *scratch;
+};
+__global__ __launch_bounds__(256) void k_sort_rows(const uint32_t *__restrict__ grid, int N, int S, SortRows r0,
+                                                   SortRows r1)
 {
     if (!dev_global(grid)->rebuild) return;   // whole workgroup
+    const SortRows &r = blockIdx.y ? r1 : r0;   // radial or angular rows
+    const int capC = r.capC;
+    int32_t *__restrict__ cand = r.cand;
+    const int32_t *__restrict__ rowlen = r.rowlen;
+    int32_t *__restrict__ off = r.off;
+    int32_t *__restrict__ scratch = r.scratch;
     __shared__ int32_t buf[kBlock / 64][kSortLds];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int i = blockIdx.x * (kBlock / 64) + wv;
@@ -705,6 +738,7 @@ int32_t update_geometry(const nep_model *m, nep_nlist *nl, const double *boxes, 
         }
         nl->ncell_alloc = 0;
         NEP_HIP(hipMalloc(&nl->cell_cnt, sizeof(int32_t) * (size_t)cell_total));
+        NEP_HIP(hipMemset(nl->cell_cnt, 0, sizeof(int32_t) * (size_t)cell_total));   // kept zero between rebuilds
         NEP_HIP(hipMalloc(&nl->cell_start, sizeof(int32_t) * (size_t)(cell_total + 1)));
         NEP_HIP(hipMalloc(&nl->cell_sys, sizeof(int32_t) * (size_t)cell_total));
         nl->ncell_alloc = cell_total;
@@ -741,21 +775,15 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
     const int32_t rc_ = update_geometry(m, nl, boxes, changed, margin);
     if (rc_ != NEP_OK) return rc_;
     const bool force = !nl->built || changed;
-    fill_u32(nl->grid, 0u, 2, s);
     pack_positions(pos, P, N, nl->atom_sys, nl->geom, reinterpret_cast<float4 *>(nl->pos4), s);
-    fill_i32(nl->cell_cnt, 0, (size_t)nl->ncell_total, s);
     const dim3 g1(div_up(N, kBlock));
     const dim3 gw(div_up(N, kBlock / 64));
     const dim3 gc(nl->ncell_total);
     {
         ProfScope ps_(K_CENTROID, s);
         hipLaunchKernelGGL(k_centroid, g1, dim3(kBlock), 0, s, pos, types, P, N, nl->S, nl->cen, nl->spr, nl->cen_ref,
-                           nl->grid, nl->status);
-    }
-    {
-        ProfScope ps_(K_GRID, s);
-        hipLaunchKernelGGL(k_grid, dim3(1), dim3(64), 0, s, nl->geom, nl->nsys, m->hp.rc_radial, m->hp.rc_angular,
-                           nl->skin, force ? 1 : 0, nl->grid, nl->status);
+                           nl->geom, nl->nsys, m->hp.rc_radial, m->hp.rc_angular, nl->skin, force ? 1 : 0, nl->grid,
+                           nl->status);
     }
     {
         ProfScope ps_(K_CELL_COUNT, s);
@@ -774,7 +802,7 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
     }
     {
         ProfScope ps_(K_CELL_SORT, s);
-        hipLaunchKernelGGL(k_cell_rank, gc, dim3(64), 0, s, nl->grid, nl->cell_start, nl->cell_atoms);
+        hipLaunchKernelGGL(k_cell_rank, gc, dim3(64), 0, s, nl->grid, nl->cell_start, nl->cell_atoms, nl->cell_cnt);
     }
     {
         ProfScope ps_(K_CANDIDATES, s);
@@ -785,10 +813,9 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
     {
         // the union-list and reverse-slot arrays serve as sort scratch before they are filled
         ProfScope ps_(K_SORT_ROWS, s);
-        hipLaunchKernelGGL(k_sort_rows, gw, dim3(kBlock), 0, s, nl->grid, N, nl->S, nl->capR, nl->candR, nl->lenR,
-                           nl->offR, nl->uniR);
-        hipLaunchKernelGGL(k_sort_rows, gw, dim3(kBlock), 0, s, nl->grid, N, nl->S, nl->capA, nl->candA, nl->lenA,
-                           nl->offA, nl->revA);
+        const SortRows rr{nl->capR, nl->candR, nl->lenR, nl->offR, nl->uniR};
+        const SortRows ra{nl->capA, nl->candA, nl->lenA, nl->offA, nl->revA};
+        hipLaunchKernelGGL(k_sort_rows, dim3(gw.x, 2), dim3(kBlock), 0, s, nl->grid, N, nl->S, rr, ra);
     }
     {
         ProfScope ps_(K_REVERSE, s);

@@ -578,7 +578,7 @@ extern "C" int32_t nep_param_grad(const nep_model *m, nep_nlist *nl, nep_ws *ws,
                        tw->W, W_ref, P, N, lambda[0], lambda[1], lambda[2], tw->dF, tw->cW, tw->eE, loss);
     const nep_hparams &h = m->hp;
     NepArgs a{};
-    a.p4 = reinterpret_cast<const float4 *>(ws->pos4); a.pos = pos; a.types = types; a.N = N; a.S = h.n_species;
+    a.p4 = reinterpret_cast<const float4 *>(nl->pos4); a.pos = pos; a.types = types; a.N = N; a.S = h.n_species;
     a.H = h.hidden; a.P = P; a.lg = lanes_log2(P);
     a.geom = nl->geom; a.tile_atom0 = ws->tile_atom0; a.tile_atom1 = ws->tile_atom1; a.tile_sys = ws->tile_sys;
     a.rcRinv = (float)(1.0 / h.rc_radial); a.rcAinv = (float)(1.0 / h.rc_angular);
