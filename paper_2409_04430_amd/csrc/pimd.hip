@@ -61,25 +61,24 @@ __device__ __forceinline__ void philox4x32_10(uint32_t k0, uint32_t k1, uint32_t
     }
 }
 
-// Four standard normals of block kb of component a of atom i (kept out of
-// line: one copy of the FP64 Box-Muller code serves every block).
-__device__ __noinline__ void normals4(uint64_t seed, uint64_t step, int stage, int i, int a, int nb, int kb,
-                                         double z[4])
+// Standard normal e4 (0..3) of block kb of component a of atom i: the
+// block's Philox output gives two Box-Muller pairs (uniforms (x + 1) 2^-32),
+// normals 0, 1 from the first pair (cosine, sine) and 2, 3 from the second.
+// Each lane evaluates only its own pair (kept out of line: one copy of the
+// FP64 Box-Muller code).
+__device__ __noinline__ double normal1(uint64_t seed, uint64_t step, int stage, int i, int a, int nb, int kb, int e4)
 {
     uint32_t c[4] = {(uint32_t)i, (uint32_t)(a * nb + kb), (uint32_t)step,
                      (uint32_t)((step >> 32) * 2u + (uint64_t)stage)};
     philox4x32_10((uint32_t)seed, (uint32_t)(seed >> 32), c);
     const double s = 1.0 / 4294967296.0;
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-        const double u0 = ((double)c[2 * p] + 1.0) * s;
-        const double u1 = ((double)c[2 * p + 1] + 1.0) * s;
-        const double rad = sqrt(-2.0 * log(u0));
-        double sn, cs;
-        sincos(2.0 * M_PI * u1, &sn, &cs);
-        z[2 * p] = rad * cs;
-        z[2 * p + 1] = rad * sn;
-    }
+    const bool second = e4 >= 2;
+    const double u0 = ((double)(second ? c[2] : c[0]) + 1.0) * s;
+    const double u1 = ((double)(second ? c[3] : c[1]) + 1.0) * s;
+    const double rad = sqrt(-2.0 * log(u0));
+    double sn, cs;
+    sincos(2.0 * M_PI * u1, &sn, &cs);
+    return rad * ((e4 & 1) ? sn : cs);
 }
 
 struct StepArgs {
@@ -94,12 +93,12 @@ struct StepArgs {
     int stage, noise;
 };
 
-// One workgroup holds floor(256 / P) (atom, component) elements; lane
+// One workgroup holds floor(512 / P) (atom, component) elements; lane
 // (element, k) works on normal mode k of its element (and bead k for the
 // back transform), so every P x P transform becomes P-long dot products
 // spread over P lanes.  Bead data, mode data and C are staged in LDS; global
 // loads and stores run over consecutive elements of one bead.
-constexpr int kStepBlock = 256;
+constexpr int kStepBlock = 512;
 __global__ __launch_bounds__(kStepBlock) void k_trpmd(StepArgs a, const double *__restrict__ cst)
 {
     extern __shared__ double sh[];
@@ -157,15 +156,12 @@ __global__ __launch_bounds__(kStepBlock) void k_trpmd(StepArgs a, const double *
         if (a.noise) {
             const int NB = (P + 3) / 4, kb = k >> 2, e4 = k & 3;
             const double gs = sig * cst[Lo.sc2 + k];
-            double z[4];
             if (a.stage == PIMD_STAGE_FUSED) {
-                normals4(a.seed, (uint64_t)step, 1, i, comp, NB, kb, z);
-                const double z1 = z[e4];
-                normals4(a.seed, (uint64_t)(step + 1), 0, i, comp, NB, kb, z);
-                gamma = gs * (c1 * z1 + z[e4]);
+                const double z1 = normal1(a.seed, (uint64_t)step, 1, i, comp, NB, kb, e4);
+                const double z0 = normal1(a.seed, (uint64_t)(step + 1), 0, i, comp, NB, kb, e4);
+                gamma = gs * (c1 * z1 + z0);
             } else {
-                normals4(a.seed, (uint64_t)step, post ? 1 : 0, i, comp, NB, kb, z);
-                gamma = gs * z[e4];
+                gamma = gs * normal1(a.seed, (uint64_t)step, post ? 1 : 0, i, comp, NB, kb, e4);
             }
         }
         vt = alpha * vt + gamma + beta * (hk * ft);
