@@ -181,17 +181,26 @@ __device__ __forceinline__ int wrap_cell(int d, int M)
     return d > hM ? d - M : (d < -hM ? d + M : d);
 }
 
+// Minimum-image cell difference d - M rint(d / M) in FP32 (d, M small
+// integers, so exact).  It equals wrap_cell except, for even M, at
+// |d| = M / 2, where either image lies farther than L/2 - h > rc.
+__device__ __forceinline__ float wrap_cell_f(int d, float Mf, float Minv)
+{
+    const float f = (float)d;
+    return fmaf(-Mf, rintf(f * Minv), f);
+}
+
 // r_j - r_i from packed positions.
 __device__ __forceinline__ void packed_pair(const float4 &pj, const float4 &pi, const int M[3], const float h[3],
                                             float &dx, float &dy, float &dz)
 {
     const int wj = __float_as_int(pj.w), wi = __float_as_int(pi.w);
-    const int cx = wrap_cell((wj & 1023) - (wi & 1023), M[0]);
-    const int cy = wrap_cell(((wj >> 10) & 1023) - ((wi >> 10) & 1023), M[1]);
-    const int cz = wrap_cell(((wj >> 20) & 1023) - ((wi >> 20) & 1023), M[2]);
-    dx = fmaf(h[0], (float)cx, pj.x - pi.x);
-    dy = fmaf(h[1], (float)cy, pj.y - pi.y);
-    dz = fmaf(h[2], (float)cz, pj.z - pi.z);
+    const float cx = wrap_cell_f((wj & 1023) - (wi & 1023), (float)M[0], 1.0f / (float)M[0]);
+    const float cy = wrap_cell_f(((wj >> 10) & 1023) - ((wi >> 10) & 1023), (float)M[1], 1.0f / (float)M[1]);
+    const float cz = wrap_cell_f(((wj >> 20) & 1023) - ((wi >> 20) & 1023), (float)M[2], 1.0f / (float)M[2]);
+    dx = fmaf(h[0], cx, pj.x - pi.x);
+    dy = fmaf(h[1], cy, pj.y - pi.y);
+    dz = fmaf(h[2], cz, pj.z - pi.z);
 }
 
 // Exact FP64 minimum-image squared distance, the literal expression

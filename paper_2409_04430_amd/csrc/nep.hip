@@ -218,15 +218,20 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                         pair_vec(pj[u], pi, lm, dx, dy, dz);
                         const float r2 = dx * dx + dy * dy + dz * dz;
                         {
+                            // sk[0] collects f_c, sk[k > 0] collects f_c T_k
                             const float r = __builtin_amdgcn_sqrtf(r2);
-                            float f[KR1];
-                            cheb_f<KR1>(r, a.rcRinv, f);
+                            float fc, T[KR1];
+                            cheb_t<KR1>(r, a.rcRinv, fc, T);
+                            sk[0] += fc;
 #pragma unroll
-                            for (int q2 = 0; q2 < KR1; ++q2) sk[q2] += f[q2];
+                            for (int q2 = 1; q2 < KR1; ++q2) sk[q2] = fmaf(fc, T[q2], sk[q2]);
                         }
                     }
                 }
             }
+            // sum_j f_k = (sum f_c T_k + sum f_c) / 2 for k > 0, sum f_c for k = 0
+#pragma unroll
+            for (int q2 = 1; q2 < KR1; ++q2) sk[q2] = 0.5f * (sk[q2] + sk[0]);
             const float *c = prm + a.oR + (tc * S + t) * NR1 * KR1;
 #pragma unroll
             for (int n = 0; n < NR1; ++n) {
@@ -250,6 +255,15 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             int s0, s1;
             block_range(a.uendA, i, t, s0, s1);
             const float *c = prm + a.oA + (tc * S + t) * NA1 * KA1;
+            // g_n = f_c / 2 (cs_n + sum_{k>0} c_nk T_k), cs_n = c_n0 + sum_k c_nk
+            float cs[NA1];
+#pragma unroll
+            for (int n = 0; n < NA1; ++n) {
+                float acc = c[n * KA1];
+#pragma unroll
+                for (int q2 = 0; q2 < KA1; ++q2) acc += c[n * KA1 + q2];
+                cs[n] = acc;
+            }
             int jn = s0 < s1 ? (rowA[uA[s0]] >> 2) : i;
             bool inn = s0 < s1 && ((mA[s0 < s1 ? s0 : 0] >> b) & 1u);
             float4 pn = p4[(size_t)jn * P + b];
@@ -267,15 +281,17 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 const float rinv = __builtin_amdgcn_rsqf(r2);
                 const float r = r2 * rinv;
-                float f[KA1];
-                cheb_f<KA1>(r, a.rcAinv, f);
+                float fc, T[KA1];
+                cheb_t<KA1>(r, a.rcAinv, fc, T);
+                const float hf = 0.5f * fc;
                 float Y[kNumSH];
                 sh_eval(dx * rinv, dy * rinv, dz * rinv, shc, Y);
 #pragma unroll
                 for (int n = 0; n < NA1; ++n) {
-                    float g = 0.0f;
+                    float g = cs[n];
 #pragma unroll
-                    for (int q2 = 0; q2 < KA1; ++q2) g += c[n * KA1 + q2] * f[q2];
+                    for (int q2 = 1; q2 < KA1; ++q2) g = fmaf(c[n * KA1 + q2], T[q2], g);
+                    g *= hf;
 #pragma unroll
                     for (int m = 0; m < kNumSH; ++m) A[n][m] += g * Y[m];
                 }
@@ -492,18 +508,21 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
                 const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
                 float gij[NA1], gpij[NA1];
                 {
-                    float f[KA1], fp[KA1];
-                    cheb_fd<KA1>(r, a.rcAinv, f, fp);
+                    // g = f_c Pn / 2, g' = (dx/dr f_c Qn + f_c' Pn) / 2 with
+                    // Pn = sum_k c_nk (T_k + 1), Qn = sum_k c_nk T_k'
+                    float fc, fcp, dxdr, T[KA1], Tp[KA1];
+                    cheb_td<KA1>(r, a.rcAinv, fc, fcp, dxdr, T, Tp);
+                    const float hf = 0.5f * fc, hfp = 0.5f * fcp, hd = hf * dxdr;
 #pragma unroll
                     for (int n = 0; n < NA1; ++n) {
-                        float g0 = 0.0f, g1 = 0.0f;
+                        float pn = 2.0f * cij_l[n * KA1], qn = 0.0f;
 #pragma unroll
-                        for (int q2 = 0; q2 < KA1; ++q2) {
-                            g0 = fmaf(cij_l[n * KA1 + q2], f[q2], g0);
-                            g1 = fmaf(cij_l[n * KA1 + q2], fp[q2], g1);
+                        for (int q2 = 1; q2 < KA1; ++q2) {
+                            pn = fmaf(cij_l[n * KA1 + q2], T[q2] + 1.0f, pn);
+                            qn = fmaf(cij_l[n * KA1 + q2], Tp[q2], qn);
                         }
-                        gij[n] = g0;
-                        gpij[n] = g1;
+                        gij[n] = hf * pn;
+                        gpij[n] = fmaf(hd, qn, hfp * pn);
                     }
                 }
                 float sY, gx, gy, gz;
@@ -622,11 +641,17 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
                         const float r2 = dx * dx + dy * dy + dz * dz;
                         const float rinv = __builtin_amdgcn_rsqf(r2);
                         const float r = r2 * rinv;
-                        float f[KR1], fp[KR1];
-                        cheb_fd<KR1>(r, a.rcRinv, f, fp);
-                        float sc = 0.0f;
+                        // sum_k A_k f_k' = (dx/dr f_c sum A_k T_k' + f_c' sum A_k (T_k + 1)) / 2
+                        float fc, fcp, dxdr, T[KR1], Tp[KR1];
+                        cheb_td<KR1>(r, a.rcRinv, fc, fcp, dxdr, T, Tp);
+                        float s1 = 2.0f * (ai[0] + aj[u][0]), s2 = 0.0f;
 #pragma unroll
-                        for (int q2 = 0; q2 < KR1; ++q2) sc += (ai[q2] + aj[u][q2]) * fp[q2];
+                        for (int q2 = 1; q2 < KR1; ++q2) {
+                            const float A = ai[q2] + aj[u][q2];
+                            s1 = fmaf(A, T[q2] + 1.0f, s1);
+                            s2 = fmaf(A, Tp[q2], s2);
+                        }
+                        const float sc = 0.5f * fmaf(dxdr * fc, s2, fcp * s1);
                         const float w = sc * rinv;
                         const float qx = w * dx, qy = w * dy, qz = w * dz;
                         Fx += qx; Fy += qy; Fz += qz;

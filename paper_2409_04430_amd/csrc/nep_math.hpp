@@ -58,6 +58,52 @@ __device__ __forceinline__ void cheb_f(float r, float rcinv, float *f)
     }
 }
 
+// The cutoff function and the Chebyshev polynomials alone:
+// f_c(r) and T_k(x), x = 2 (r/rc - 1)^2 - 1, so that f_k = (T_k + 1)/2 f_c.
+// Sums of f_k then follow from sums of f_c T_k and of f_c.
+template <int K1>
+__device__ __forceinline__ void cheb_t(float r, float rcinv, float &fc, float *T)
+{
+    float sn, cs;
+    const float z = r * rcinv;
+    sincospi01(z, sn, cs);
+    fc = 0.5f + 0.5f * cs;
+    const float y = z - 1.0f;
+    const float x = 2.0f * y * y - 1.0f;
+    const float x2 = x + x;
+    T[0] = 1.0f;
+    if (K1 > 1) T[1] = x;
+#pragma unroll
+    for (int k = 2; k < K1; ++k) T[k] = fmaf(x2, T[k - 1], -T[k - 2]);
+}
+
+// f_c, df_c/dr, dx/dr, T_k(x) and T_k'(x) (T_{k+1}' = 2 T_k + 2x T_k' - T_{k-1}'),
+// so that df_k/dr = (T_k' dx/dr f_c + (T_k + 1) df_c/dr) / 2.
+template <int K1>
+__device__ __forceinline__ void cheb_td(float r, float rcinv, float &fc, float &fcp, float &dxdr, float *T, float *Tp)
+{
+    float sn, cs;
+    const float z = r * rcinv;
+    sincospi01(z, sn, cs);
+    fc = 0.5f + 0.5f * cs;
+    fcp = -0.5f * kPi * rcinv * sn;
+    const float y = z - 1.0f;
+    const float x = 2.0f * y * y - 1.0f;
+    dxdr = 4.0f * y * rcinv;
+    const float x2 = x + x;
+    T[0] = 1.0f;
+    Tp[0] = 0.0f;
+    if (K1 > 1) {
+        T[1] = x;
+        Tp[1] = 1.0f;
+    }
+#pragma unroll
+    for (int k = 2; k < K1; ++k) {
+        T[k] = fmaf(x2, T[k - 1], -T[k - 2]);
+        Tp[k] = fmaf(x2, Tp[k - 1], fmaf(2.0f, T[k - 1], -Tp[k - 2]));
+    }
+}
+
 // f_k and df_k/dr.
 template <int K1>
 __device__ __forceinline__ void cheb_fd(float r, float rcinv, float *f, float *fp)
