@@ -157,13 +157,24 @@ __device__ float mlp_mfma(const float (&qh)[D], bool mine, const uint16_t *__res
     return u;
 }
 
+// Network arithmetic of k_descriptor: FP32 vector units with the weights
+// read from global memory or staged in LDS, or BF16 matrix cores (student
+// weights).  (FP32 operands on the matrix cores measured slower than the
+// LDS-staged vector form: two wavefronts per SIMD cannot hide the chains of
+// dependent 16 x 16 x 4 FP32 tiles.)
+constexpr int kNetGlobal = 0, kNetLds = 1, kNetBf16 = 2;
+
 // ----------------------------------------------------------- pass 1 ---
 
-template <int NR1, int NA1, int KR1, int KA1, bool FOUR, bool MF>
+template <int NR1, int NA1, int KR1, int KA1, bool FOUR, int NET>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void k_descriptor(NepArgs a, const float *__restrict__ prm)
 {
-    extern __shared__ float mf_lds[];   // MF: two 64 x kMfLd tiles per wavefront
+    constexpr bool MF = NET == kNetBf16;   // whole-wavefront network
+    constexpr bool NL = NET == kNetLds;
+    // dynamic LDS: BF16, two 64 x kMfLd tiles per wavefront; LDS weights,
+    // W0 [S][H][DP] (rows padded to DP = 4 ceil(D / 4)), b0 [S][H], w1 [S][H]
+    extern __shared__ float dyn[];
     constexpr int D = Dims<NR1, NA1, FOUR>::D;
     const LaneMap lm = lane_map(a);
     const int i = lm.i, b = lm.b, P = a.P, S = a.S;
@@ -174,6 +185,20 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
     const float4 pi = p4[(size_t)i * P + b];
     const float *shc = prm + a.osh;
     float U = 0.0f;
+
+    constexpr int DP = (D + 3) & ~3;
+    if constexpr (NL) {
+        const int nw = S * a.H * DP, nb = S * a.H;
+        for (int x = threadIdx.x; x < nw; x += blockDim.x) {
+            const int row = x / DP, v = x - row * DP;
+            dyn[x] = v < D ? prm[a.oW0 + row * D + v] : 0.0f;
+        }
+        for (int x = threadIdx.x; x < nb; x += blockDim.x) {
+            dyn[nw + x] = prm[a.ob0 + x];
+            dyn[nw + nb + x] = prm[a.ow1 + x];
+        }
+        __syncthreads();
+    }
 
     uint64_t todo = __ballot(valid && tok);
     while (todo) {
@@ -336,15 +361,41 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             qh[v] = qs[v] * q[v];
             G[v] = 0.0f;
         }
-        const float *b0 = prm + a.ob0 + tc * a.H;
-        const float *w1 = prm + a.ow1 + tc * a.H;
-        if constexpr (MF) {
-            float *X = mf_lds + (threadIdx.x >> 6) * kMfWave;
+        if constexpr (NET == kNetBf16) {
+            const float *b0 = prm + a.ob0 + tc * a.H;
+            const float *w1 = prm + a.ow1 + tc * a.H;
+            float *X = dyn + (threadIdx.x >> 6) * kMfWave;
             const float u = mlp_mfma<D>(qh, mine, a.w0b + (size_t)tc * 2048, b0, w1, prm[a.ob1], a.H, X,
                                         X + 64 * kMfLd, G);
             if (mine) U = u;
+        } else if constexpr (NL) {
+            const int nw = S * a.H * DP, nb = S * a.H;
+            const float *W0 = dyn + tc * a.H * DP;
+            const float *b0 = dyn + nw + tc * a.H;
+            const float *w1 = dyn + nw + nb + tc * a.H;
+            float u = -prm[a.ob1];
+            for (int mu = 0; mu < a.H; ++mu) {
+                const float4 *w4 = reinterpret_cast<const float4 *>(W0 + mu * DP);
+                float wr[DP];
+#pragma unroll
+                for (int v4 = 0; v4 < DP / 4; ++v4) {
+                    const float4 t4 = w4[v4];
+                    wr[4 * v4] = t4.x; wr[4 * v4 + 1] = t4.y; wr[4 * v4 + 2] = t4.z; wr[4 * v4 + 3] = t4.w;
+                }
+                float z = -b0[mu];
+#pragma unroll
+                for (int v = 0; v < D; ++v) z += wr[v] * qh[v];
+                const float h = tanhf(z);
+                u += w1[mu] * h;
+                const float gz = w1[mu] * (1.0f - h * h);
+#pragma unroll
+                for (int v = 0; v < D; ++v) G[v] += gz * wr[v];
+            }
+            U = u;
         } else {
             const float *W0 = prm + a.oW0 + tc * a.H * D;
+            const float *b0 = prm + a.ob0 + tc * a.H;
+            const float *w1 = prm + a.ow1 + tc * a.H;
             float u = -prm[a.ob1];
             for (int mu = 0; mu < a.H; ++mu) {
                 float z = -b0[mu];
@@ -756,6 +807,8 @@ __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partE
     if (t >= 1 && t <= 9) W[(size_t)sb * 9 + (t - 1)] = red[t][0];
 }
 
+constexpr size_t kNetLdsMax = 60 * 1024;   // bytes of LDS for the staged network weights
+
 template <int NR1, int NA1, bool FOUR, bool MF = false>
 static void launch(const NepArgs &a, const float *prm, int nblk, int wpb, hipStream_t s)
 {
@@ -763,8 +816,15 @@ static void launch(const NepArgs &a, const float *prm, int nblk, int wpb, hipStr
     const dim3 blk(64 * wpb);
     {
         ProfScope ps_(K_DESCRIPTOR, s);
-        const size_t lds = MF ? sizeof(float) * kMfWave * wpb : 0;
-        hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, MF>), g, blk, lds, s, a, prm);
+        constexpr int D = Dims<NR1, NA1, FOUR>::D, DP = (D + 3) & ~3;
+        const size_t net = sizeof(float) * (size_t)a.S * a.H * (DP + 2);
+        if constexpr (MF)   // BF16 weights of the student
+            hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetBf16>), g, blk,
+                               sizeof(float) * kMfWave * wpb, s, a, prm);
+        else if (net <= kNetLdsMax)   // network weights staged in LDS
+            hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetLds>), g, blk, net, s, a, prm);
+        else
+            hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetGlobal>), g, blk, 0, s, a, prm);
     }
     {
         ProfScope ps_(K_FORCE_ANG, s);
