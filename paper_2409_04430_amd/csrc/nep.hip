@@ -214,6 +214,10 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
 #pragma unroll
         for (int v = 0; v < D; ++v) q[v] = 0.0f;
         float *Bo = a.B + ((size_t)i * P + b) * (NA1 * kNumSH);
+        // A stays in registers through the network for small angular sets;
+        // otherwise it is parked in the atom's adjoint row and read back
+        constexpr bool PARK = MF || NA1 > 5;
+        float Ar[PARK ? 1 : NA1][kNumSH];
         if (MF ? mine : true) {
 
         // radial: per neighbour species, sum the basis, then contract with c
@@ -343,13 +347,20 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                 q[NR1 + kLmax * NA1 + n] = a.kappa4 * tr3;
             }
         }
-        // park A in this atom's adjoint row (overwritten with B below)
+        if constexpr (PARK) {
+            // park A in this atom's adjoint row (overwritten with B below)
 #pragma unroll
-        for (int n = 0; n < NA1; ++n) {
-            float4 *o4 = reinterpret_cast<float4 *>(Bo + n * kNumSH);
+            for (int n = 0; n < NA1; ++n) {
+                float4 *o4 = reinterpret_cast<float4 *>(Bo + n * kNumSH);
 #pragma unroll
-            for (int q4 = 0; q4 < kNumSH / 4; ++q4)
-                o4[q4] = make_float4(A[n][4 * q4], A[n][4 * q4 + 1], A[n][4 * q4 + 2], A[n][4 * q4 + 3]);
+                for (int q4 = 0; q4 < kNumSH / 4; ++q4)
+                    o4[q4] = make_float4(A[n][4 * q4], A[n][4 * q4 + 1], A[n][4 * q4 + 2], A[n][4 * q4 + 3]);
+            }
+        } else {
+#pragma unroll
+            for (int n = 0; n < (PARK ? 1 : NA1); ++n)
+#pragma unroll
+                for (int m = 0; m < kNumSH; ++m) Ar[n][m] = A[n][m];
         }
         }   // descriptors of the lanes of species tc
 
@@ -413,15 +424,20 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
         for (int v = 0; v < D; ++v) G[v] *= qs[v];
         if (MF ? !mine : false) continue;
 
-        // adjoints: B_nlm = dU/dA_nlm (A read back from the parked row)
+        // adjoints: B_nlm = dU/dA_nlm
 #pragma unroll
         for (int n = 0; n < NA1; ++n) {
             float An[kNumSH];
             float4 *o4 = reinterpret_cast<float4 *>(Bo + n * kNumSH);
+            if constexpr (PARK) {
 #pragma unroll
-            for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
-                const float4 v4 = o4[q4];
-                An[4 * q4] = v4.x; An[4 * q4 + 1] = v4.y; An[4 * q4 + 2] = v4.z; An[4 * q4 + 3] = v4.w;
+                for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
+                    const float4 v4 = o4[q4];
+                    An[4 * q4] = v4.x; An[4 * q4 + 1] = v4.y; An[4 * q4 + 2] = v4.z; An[4 * q4 + 3] = v4.w;
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < kNumSH; ++m) An[m] = Ar[PARK ? 0 : n][m];
             }
             float Bn[kNumSH];
 #pragma unroll
