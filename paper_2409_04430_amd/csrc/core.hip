@@ -644,7 +644,7 @@ extern "C" int32_t nep_ws_create_batched(const nep_model *m, int32_t P, int32_t 
     if (e == hipSuccess) e = dalloc(&w->sys_tile0, (size_t)nsys + 1);
     if (e == hipSuccess && set_tiles(w, 4) != NEP_OK) e = hipErrorUnknown;
     if (e == hipSuccess) e = dalloc(&w->B, PN * w->NA1 * kNumSH);
-    if (e == hipSuccess) e = dalloc(&w->arad, PN * w->S * 9);
+    if (e == hipSuccess) e = dalloc(&w->arad, PN * w->S * 12);
     if (e == hipSuccess) e = dalloc(&w->partE, (size_t)std::max(P, 1) * nb);
     if (e == hipSuccess) e = dalloc(&w->partW, (size_t)2 * std::max(P, 1) * nb * 9);
     if (e == hipSuccess) e = dalloc(&w->Fang, PN * 3);

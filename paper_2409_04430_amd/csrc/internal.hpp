@@ -117,7 +117,7 @@ struct nep_ws {
     int32_t *tile_atom0 = nullptr, *tile_atom1 = nullptr, *tile_sys = nullptr;   // [nblk_cap]
     int32_t *sys_tile0 = nullptr;   // [nsys + 1]
     float *B = nullptr;        // [N][P][NA1*24] angular adjoints dU_i/dA_nlm
-    float *arad = nullptr;     // [N][S][9][P] radial adjoints sum_n dU_i/dq_n c_nk
+    float *arad = nullptr;     // [N][S][P][12] radial adjoints sum_n dU_i/dq_n c_nk (9 used)
     double *partE = nullptr;   // [nblk_cap][P]
     double *partW = nullptr;   // [2][nblk_cap][P][9] (angular pass, radial pass)
     float *Fang = nullptr;     // [N][P][3] angular part of the forces

@@ -465,17 +465,23 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             for (int q4 = 0; q4 < kNumSH / 4; ++q4)
                 o4[q4] = make_float4(Bn[4 * q4], Bn[4 * q4 + 1], Bn[4 * q4 + 2], Bn[4 * q4 + 3]);
         }
-        // radial adjoints a_k(t) = sum_n G_n c^{tc t}_nk, bead-minor
-        float *ao = a.arad + (size_t)i * S * KR1 * P + b;
+        // radial adjoints a_k(t) = sum_n G_n c^{tc t}_nk, [atom][species][bead][12]
+        static_assert(KR1 <= kRadPad, "radial basis exceeds the padded adjoint row");
         for (int t = 0; t < S; ++t) {
             const float *c = prm + a.oR + (tc * S + t) * NR1 * KR1;
+            float acc[kRadPad];
 #pragma unroll
-            for (int k = 0; k < KR1; ++k) {
-                float acc = 0.0f;
+            for (int k = 0; k < kRadPad; ++k) {
+                acc[k] = 0.0f;
+                if (k < KR1) {
 #pragma unroll
-                for (int n = 0; n < NR1; ++n) acc += G[n] * c[n * KR1 + k];
-                ao[(size_t)(t * KR1 + k) * P] = acc;
+                    for (int n = 0; n < NR1; ++n) acc[k] += G[n] * c[n * KR1 + k];
+                }
             }
+            float4 *ao = reinterpret_cast<float4 *>(a.arad + (((size_t)i * S + t) * P + b) * kRadPad);
+#pragma unroll
+            for (int q4 = 0; q4 < kRadPad / 4; ++q4)
+                ao[q4] = make_float4(acc[4 * q4], acc[4 * q4 + 1], acc[4 * q4 + 2], acc[4 * q4 + 3]);
         }
     }
 
@@ -669,22 +675,31 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
     const float4 *p4 = a.p4;
     const float4 pi = p4[(size_t)i * P + b];
     double Fx = 0.0, Fy = 0.0, Fz = 0.0;
-    double Wv[9];
+    float Wf[9];   // radial pair virial of this (atom, bead), FP32 (a sum of like-signed terms)
 #pragma unroll
-    for (int e = 0; e < 9; ++e) Wv[e] = 0.0;
+    for (int e = 0; e < 9; ++e) Wf[e] = 0.0f;
     float Wa[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) Wa[e] = 0.0f;
     if (valid && tok) {
-        const float *ai_base = a.arad + (size_t)i * S * KR1 * P + b;
+        auto load_a = [&](int atom, int sp, float *out) {
+            const float4 *p = reinterpret_cast<const float4 *>(a.arad + (((size_t)atom * S + sp) * P + b) * kRadPad);
+#pragma unroll
+            for (int q4 = 0; q4 < kRadPad / 4; ++q4) {
+                const float4 v = p[q4];
+                if (4 * q4 < KR1) out[4 * q4] = v.x;
+                if (4 * q4 + 1 < KR1) out[4 * q4 + 1] = v.y;
+                if (4 * q4 + 2 < KR1) out[4 * q4 + 2] = v.z;
+                if (4 * q4 + 3 < KR1) out[4 * q4 + 3] = v.w;
+            }
+        };
         const int32_t *uR = a.uniR + (size_t)i * a.capR;
         const uint64_t *mR = a.umR + (size_t)i * a.capR;
         for (int t = 0; t < S; ++t) {
             int s0, s1;
             block_range(a.uendR, i, t, s0, s1);
             float ai[KR1];
-#pragma unroll
-            for (int q2 = 0; q2 < KR1; ++q2) ai[q2] = ai_base[(size_t)(t * KR1 + q2) * P];
+            load_a(i, t, ai);
             for (int sb = s0; sb < s1; sb += kBatch) {
                 int jj[kBatch];
                 bool in[kBatch];
@@ -696,9 +711,7 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
                     jj[u] = ok ? uR[sb + u] : i;
                     in[u] = ok && ((mR[ok ? sb + u : 0] >> b) & 1u);
                     pj[u] = p4[(size_t)jj[u] * P + b];
-                    const float *ajp = a.arad + ((size_t)jj[u] * S + ti) * KR1 * P + b;
-#pragma unroll
-                    for (int q2 = 0; q2 < KR1; ++q2) aj[u][q2] = ajp[(size_t)q2 * P];
+                    load_a(jj[u], ti, aj[u]);
                 }
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
@@ -722,9 +735,10 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
                         const float w = sc * rinv;
                         const float qx = w * dx, qy = w * dy, qz = w * dz;
                         Fx += qx; Fy += qy; Fz += qz;
-                        Wv[0] -= 0.5 * dx * qx; Wv[1] -= 0.5 * dx * qy; Wv[2] -= 0.5 * dx * qz;
-                        Wv[3] -= 0.5 * dy * qx; Wv[4] -= 0.5 * dy * qy; Wv[5] -= 0.5 * dy * qz;
-                        Wv[6] -= 0.5 * dz * qx; Wv[7] -= 0.5 * dz * qy; Wv[8] -= 0.5 * dz * qz;
+                        const float hx = -0.5f * dx, hy = -0.5f * dy, hz = -0.5f * dz;
+                        Wf[0] = fmaf(hx, qx, Wf[0]); Wf[1] = fmaf(hx, qy, Wf[1]); Wf[2] = fmaf(hx, qz, Wf[2]);
+                        Wf[3] = fmaf(hy, qx, Wf[3]); Wf[4] = fmaf(hy, qy, Wf[4]); Wf[5] = fmaf(hy, qz, Wf[5]);
+                        Wf[6] = fmaf(hz, qx, Wf[6]); Wf[7] = fmaf(hz, qy, Wf[7]); Wf[8] = fmaf(hz, qz, Wf[8]);
                     }
                 }
             }
@@ -781,13 +795,13 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
         if (a.Watom) {
             float *wo = a.Watom + ((size_t)b * a.N + i) * 9;
 #pragma unroll
-            for (int e = 0; e < 9; ++e) wo[e] = (float)(Wv[e] + (double)Wa[e] + (double)wo[e]);
+            for (int e = 0; e < 9; ++e) wo[e] = (float)((double)Wf[e] + (double)Wa[e] + (double)wo[e]);
         }
         if (!(isfinite(gx) && isfinite(gy) && isfinite(gz))) atomicOr(a.flags, (uint32_t)NEP_FLAG_NONFINITE);
     }
     __shared__ double lds[kBlock];
     for (int e = 0; e < 9; ++e)
-        bead_block_sum(valid ? Wv[e] : 0.0, lds, P, a.lg, a.partWr + (size_t)blockIdx.x * P * 9 + e, 9);
+        bead_block_sum(valid ? (double)Wf[e] : 0.0, lds, P, a.lg, a.partWr + (size_t)blockIdx.x * P * 9 + e, 9);
 }
 
 // Per-(system, bead) totals from the per-workgroup partial sums of the

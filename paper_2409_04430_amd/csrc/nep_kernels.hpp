@@ -8,6 +8,8 @@
 
 namespace nep {
 
+constexpr int kRadPad = 12;   // padded length of a radial adjoint row (float4 access)
+
 struct NepArgs {
     const float4 *p4;    // [N][P] packed positions (bead-minor)
     const double *pos;   // [P][N][3] FP64 positions (exact test near the cutoff)
@@ -24,7 +26,7 @@ struct NepArgs {
     float4 *pairbuf;     // [N][capA][P] dU_j/dr_ji at the receiving atom's angular slot of j
     // workspace
     float *B;            // [N][P][NA1*24]
-    float *arad;         // [N][S][9][P]
+    float *arad;         // [N][S][P][kRadPad] radial adjoints, 9 used
     float *Fang;         // [N][P][3]
     double *partE, *partWa, *partWr;   // [blocks][P], [blocks][P][9]
     uint32_t *flags;
