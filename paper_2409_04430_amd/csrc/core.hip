@@ -63,23 +63,7 @@ __global__ void k_pack(const double *__restrict__ pos, int P, int N, const int32
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (size_t)P * N) return;
     const int b = (int)(e / (size_t)N), i = (int)(e - (size_t)b * N);
-    const SysGeom &g = geom[atom_sys[i]];
-    float o[3];
-    int bits = 0;
-    bool fin = true;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const double x = pos[3 * e + d];
-        fin = fin && isfinite(x);
-        double fl = floor(x * g.Minv[d]);
-        if (!isfinite(fl)) fl = 0.0;
-        o[d] = (float)(x - fl * g.hd[d]);
-        int ci = (int)(fl - (double)g.M[d] * floor(fl / (double)g.M[d]));
-        ci = ci < 0 ? 0 : (ci >= g.M[d] ? g.M[d] - 1 : ci);
-        bits |= ci << (10 * d);
-    }
-    if (!fin) o[0] = __int_as_float(0x7fc00000);
-    out[(size_t)i * P + b] = make_float4(o[0], o[1], o[2], __int_as_float(bits));
+    out[(size_t)i * P + b] = pack_one(pos + 3 * e, geom[atom_sys[i]]);
 }
 
 void pack_positions(const double *pos, int P, int N, const int32_t *atom_sys, const SysGeom *geom, float4 *out,

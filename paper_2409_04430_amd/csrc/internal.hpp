@@ -170,10 +170,35 @@ struct FineGrid {
     int exact;
 };
 FineGrid fine_grid(const double L[3], double rc);
+
 // Packs pos [P][N][3] into out [N][P] (bead-minor), each atom on the fine
 // grid of its system.
 void pack_positions(const double *pos, int P, int N, const int32_t *atom_sys, const SysGeom *geom, float4 *out,
                     hipStream_t s);
+
+// One packed position: per axis the fine cell c = floor(x / h) mod M
+// (10 bits per axis in w; unwrapped coordinates allowed) and the FP32
+// offset x - floor(x / h) h inside it; a non-finite coordinate gives a NaN
+// offset.
+__device__ __forceinline__ float4 pack_one(const double *x3, const SysGeom &g)
+{
+    float o[3];
+    int bits = 0;
+    bool fin = true;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double x = x3[d];
+        fin = fin && isfinite(x);
+        double fl = floor(x * g.Minv[d]);
+        if (!isfinite(fl)) fl = 0.0;
+        o[d] = (float)(x - fl * g.hd[d]);
+        int ci = (int)(fl - (double)g.M[d] * floor(fl / (double)g.M[d]));
+        ci = ci < 0 ? 0 : (ci >= g.M[d] ? g.M[d] - 1 : ci);
+        bits |= ci << (10 * d);
+    }
+    if (!fin) o[0] = __int_as_float(0x7fc00000);
+    return make_float4(o[0], o[1], o[2], __int_as_float(bits));
+}
 
 __device__ __forceinline__ int wrap_cell(int d, int M)
 {

@@ -228,30 +228,20 @@ __device__ __forceinline__ int atom_cell(const double *__restrict__ cen, int i, 
     return g.cell_base + (cz * ds.nc[1] + cy) * ds.nc[0] + cx;
 }
 
-__global__ void k_cell_count(const double *__restrict__ cen, int N, const int32_t *__restrict__ atom_sys,
-                             const SysGeom *__restrict__ geom, const uint32_t *__restrict__ grid,
-                             int32_t *__restrict__ cell_cnt)
+// Cell populations, then (last workgroup) their exclusive prefix sums, the
+// counts reset for use as fill counters.
+__device__ void cell_scan_block(int ncell, int32_t *__restrict__ cnt, int32_t *__restrict__ st)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N || !dev_global(grid)->rebuild) return;
-    const int s = atom_sys[i];
-    atomicAdd(&cell_cnt[atom_cell(cen, i, geom[s], *dev_sys(grid, s))], 1);
-}
-
-__global__ __launch_bounds__(1024) void k_cell_scan(const uint32_t *__restrict__ grid, int ncell,
-                                                    int32_t *__restrict__ cnt, int32_t *__restrict__ st)
-{
-    __shared__ int32_t part[1024];
-    if (!dev_global(grid)->rebuild) return;   // whole workgroup
-    const int t = threadIdx.x;
-    const int per = (ncell + 1023) / 1024;
+    __shared__ int32_t part[kBlock];
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int per = (ncell + nt - 1) / nt;
     const int c0 = min(t * per, ncell), c1 = min(c0 + per, ncell);
     int s = 0;
-    for (int c = c0; c < c1; ++c) s += cnt[c];
+    for (int c = c0; c < c1; ++c) s += __atomic_load_n(&cnt[c], __ATOMIC_RELAXED);
     part[t] = s;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        int v = (t >= off) ? part[t - off] : 0;
+    for (int off = 1; off < nt; off <<= 1) {
+        const int v = (t >= off) ? part[t - off] : 0;
         __syncthreads();
         part[t] += v;
         __syncthreads();
@@ -259,10 +249,34 @@ __global__ __launch_bounds__(1024) void k_cell_scan(const uint32_t *__restrict__
     int run = part[t] - s;
     for (int c = c0; c < c1; ++c) {
         st[c] = run;
-        run += cnt[c];
+        run += __atomic_load_n(&cnt[c], __ATOMIC_RELAXED);
         cnt[c] = 0;   // reused as fill counter
     }
-    if (t == 1023) st[ncell] = part[1023];
+    if (t == nt - 1) st[ncell] = part[nt - 1];
+}
+
+__global__ __launch_bounds__(kBlock) void k_cell_count(const double *__restrict__ cen, int N,
+                                                       const int32_t *__restrict__ atom_sys,
+                                                       const SysGeom *__restrict__ geom, uint32_t *__restrict__ grid,
+                                                       int ncell, int32_t *__restrict__ cell_cnt,
+                                                       int32_t *__restrict__ cell_start)
+{
+    if (!dev_global(grid)->rebuild) return;   // whole grid
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) {
+        const int s = atom_sys[i];
+        atomicAdd(&cell_cnt[atom_cell(cen, i, geom[s], *dev_sys(grid, s))], 1);
+    }
+    // the last workgroup to finish scans the counts
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) last = atomicAdd(&dev_global(grid)->ticket, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;   // whole workgroup
+    __threadfence();
+    cell_scan_block(ncell, cell_cnt, cell_start);
+    if (threadIdx.x == 0) dev_global(grid)->ticket = 0u;
 }
 
 __global__ void k_cell_fill(const double *__restrict__ cen, int N, const int32_t *__restrict__ atom_sys,
@@ -278,43 +292,6 @@ __global__ void k_cell_fill(const double *__restrict__ cen, int N, const int32_t
     cell_atoms[cell_start[c] + slot] = i;
 }
 
-// Ascending order inside each cell by rank sort: lane e places element e at
-// the number of smaller elements (entries are distinct atom indices).
-constexpr int kRankMax = 1024;
-__global__ __launch_bounds__(64) void k_cell_rank(const uint32_t *__restrict__ grid,
-                                                  const int32_t *__restrict__ cell_start,
-                                                  int32_t *__restrict__ cell_atoms, int32_t *__restrict__ cell_cnt)
-{
-    __shared__ int32_t v[kRankMax];
-    __shared__ int32_t out[kRankMax];
-    const int c = blockIdx.x;
-    if (!dev_global(grid)->rebuild) return;   // whole workgroup; unused cells are empty
-    const int s0 = cell_start[c], n = cell_start[c + 1] - s0;
-    int32_t *a = cell_atoms + s0;
-    if (n <= kRankMax) {
-        for (int e = threadIdx.x; e < n; e += 64) v[e] = a[e];
-        __syncthreads();
-        for (int e = threadIdx.x; e < n; e += 64) {
-            const int x = v[e];
-            int r = 0;
-            for (int k = 0; k < n; ++k) r += v[k] < x;
-            out[r] = x;
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < n; e += 64) a[e] = out[e];
-    } else if (threadIdx.x == 0) {   // very crowded cell: serial insertion
-        for (int p = 1; p < n; ++p) {
-            const int x = a[p];
-            int q = p - 1;
-            while (q >= 0 && a[q] > x) {
-                a[q + 1] = a[q];
-                --q;
-            }
-            a[q + 1] = x;
-        }
-    }
-    if (threadIdx.x == 0) cell_cnt[c] = 0;   // the counts start from zero at the next rebuild
-}
 
 // Candidate rows.  One workgroup per cell; the centroids of its stencil
 // cells (3 x 3 x 3, fewer along an axis with fewer than 3 cells) are staged
@@ -327,7 +304,8 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
                                                     int N, int S, const SysGeom *__restrict__ geom,
                                                     const int32_t *__restrict__ cell_sys, uint32_t *__restrict__ grid,
                                                     const int32_t *__restrict__ cell_start,
-                                                    const int32_t *__restrict__ cell_atoms, int capR, int capA,
+                                                    const int32_t *__restrict__ cell_atoms,
+                                                    int32_t *__restrict__ cell_cnt, int capR, int capA,
                                                     int32_t *__restrict__ candR, int32_t *__restrict__ lenR,
                                                     int32_t *__restrict__ candA, int32_t *__restrict__ lenA,
                                                     double *__restrict__ cen_ref, uint32_t *__restrict__ status)
@@ -342,6 +320,7 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
     const DevSys ds = *dev_sys(grid, sy_);
     const int c = blockIdx.x - g.cell_base;   // cell within its system
     if (!dg->rebuild || c >= ds.ncell) return;   // whole workgroup
+    if (threadIdx.x == 0) cell_cnt[blockIdx.x] = 0;   // counts start from zero at the next rebuild
     const int nc0 = ds.nc[0], nc1 = ds.nc[1], nc2 = ds.nc[2];
     const double R2 = dg->R2, RA2 = dg->RA2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -788,12 +767,7 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
     {
         ProfScope ps_(K_CELL_COUNT, s);
         hipLaunchKernelGGL(k_cell_count, g1, dim3(kBlock), 0, s, nl->cen, N, nl->atom_sys, nl->geom, nl->grid,
-                           nl->cell_cnt);
-    }
-    {
-        ProfScope ps_(K_CELL_SCAN, s);
-        hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, nl->grid, nl->ncell_total, nl->cell_cnt,
-                           nl->cell_start);
+                           nl->ncell_total, nl->cell_cnt, nl->cell_start);
     }
     {
         ProfScope ps_(K_CELL_FILL, s);
@@ -801,13 +775,10 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
                            nl->cell_cnt, nl->cell_start, nl->cell_atoms);
     }
     {
-        ProfScope ps_(K_CELL_SORT, s);
-        hipLaunchKernelGGL(k_cell_rank, gc, dim3(64), 0, s, nl->grid, nl->cell_start, nl->cell_atoms, nl->cell_cnt);
-    }
-    {
         ProfScope ps_(K_CANDIDATES, s);
         hipLaunchKernelGGL(k_candidates, gc, dim3(kBlock), 0, s, nl->cen, types, N, nl->S, nl->geom, nl->cell_sys,
-                           nl->grid, nl->cell_start, nl->cell_atoms, nl->capR, nl->capA, nl->candR, nl->lenR,
+                           nl->grid, nl->cell_start, nl->cell_atoms, nl->cell_cnt, nl->capR, nl->capA, nl->candR,
+                           nl->lenR,
                            nl->candA, nl->lenA, nl->cen_ref, nl->status);
     }
     {
