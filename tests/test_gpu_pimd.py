@@ -57,7 +57,7 @@ def test_normal_modes_parity(torch, L, orc, P):
 
 
 @pytest.mark.parametrize("mode", ["pimd", "trpmd", "rpmd"])
-@pytest.mark.parametrize("P", [1, 4, 5, 32])
+@pytest.mark.parametrize("P", [1, 4, 5, 16, 32, 48, 64])   # 16..64: matrix-core transforms, ragged last tile
 def test_trpmd_step_parity(torch, L, orc, mode, P):
     say(f"[trpmd_step] mode={mode} P={P}")
     N = 50
