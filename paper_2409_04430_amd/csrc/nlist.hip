@@ -484,34 +484,6 @@ __global__ __launch_bounds__(256) void k_sort_rows(const uint32_t *__restrict__ 
     }
 }
 
-// Reverse slots: for candidate j of i (slot k), the slot of i in j's row,
-// by binary search in the species block of i (ordered by index); -1 if i
-// is missing (only when j's row overflowed).  One wavefront per atom.
-__global__ __launch_bounds__(256) void k_reverse(const uint32_t *__restrict__ grid, int N, int capC,
-                                                 const int32_t *__restrict__ types, const int32_t *__restrict__ cand,
-                                                 const int32_t *__restrict__ off, int32_t *__restrict__ rev)
-{
-    if (!dev_global(grid)->rebuild) return;   // whole workgroup
-    const int lane = threadIdx.x & 63;
-    const int i = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (i >= N) return;
-    const int ti = types[i] & 3;
-    const int S1 = kMaxSpecies + 1;
-    int n = 0;
-    for (int t = 0; t < kMaxSpecies; ++t) n = max(n, off[(size_t)i * S1 + t + 1]);
-    n = min(n, capC);
-    for (int k = lane; k < n; k += 64) {
-        const int j = cand[(size_t)i * capC + k] >> 2;
-        const int32_t *rj = cand + (size_t)j * capC;
-        int lo = min(off[(size_t)j * S1 + ti], capC), hi = min(off[(size_t)j * S1 + ti + 1], capC);
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if ((rj[mid] >> 2) < i) lo = mid + 1;
-            else hi = mid;
-        }
-        rev[(size_t)i * capC + k] = (lo < min(off[(size_t)j * S1 + ti + 1], capC) && (rj[lo] >> 2) == i) ? lo : -1;
-    }
-}
 
 // Union lists.  One wavefront per atom and list (grid.y picks the radial or
 // angular list).  A candidate is kept when the pair is inside the cutoff for
@@ -539,12 +511,35 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
                                                int capR, int capA, int32_t *__restrict__ uniR,
                                                uint64_t *__restrict__ umR, int32_t *__restrict__ uendR,
                                                int32_t *__restrict__ uniA, uint64_t *__restrict__ umA,
-                                               int32_t *__restrict__ uendA, uint32_t *__restrict__ status)
+                                               int32_t *__restrict__ uendA, uint32_t *__restrict__ status,
+                                               const uint32_t *__restrict__ grid, const int32_t *__restrict__ types,
+                                               int32_t *__restrict__ revA)
 {
     const int lane = threadIdx.x & 63, G = 1 << lg, CPW = 64 >> lg;
     const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int kind = blockIdx.y;   // 0: radial list, 1: angular list
     if (i >= N) return;            // whole wavefront
+    if (kind == 1 && dev_global(grid)->rebuild) {
+        // rows rebuilt in this call: reverse slot of every angular candidate, i.e.
+        // for candidate j of i (slot k) the slot of i in j's row, by binary search
+        // in the species block of i (ordered by index); -1 if i is missing (only
+        // when j's row overflowed)
+        const int ti = types[i] & 3;
+        const int S1 = kMaxSpecies + 1;
+        const int n = min(offA[(size_t)i * S1 + S], capA);
+        for (int k = lane; k < n; k += 64) {
+            const int j = candA[(size_t)i * capA + k] >> 2;
+            const int32_t *rj = candA + (size_t)j * capA;
+            const int hi0 = min(offA[(size_t)j * S1 + ti + 1], capA);
+            int lo = min(offA[(size_t)j * S1 + ti], capA), hi = hi0;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((rj[mid] >> 2) < i) lo = mid + 1;
+                else hi = mid;
+            }
+            revA[(size_t)i * capA + k] = (lo < hi0 && (rj[lo] >> 2) == i) ? lo : -1;
+        }
+    }
     const int cg = lane >> lg, b = lane & (G - 1);
     const bool bead_ok = b < P;
     const int bb = bead_ok ? b : P - 1;
@@ -789,11 +784,6 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
         hipLaunchKernelGGL(k_sort_rows, dim3(gw.x, 2), dim3(kBlock), 0, s, nl->grid, N, nl->S, rr, ra);
     }
     {
-        ProfScope ps_(K_REVERSE, s);
-        hipLaunchKernelGGL(k_reverse, gw, dim3(kBlock), 0, s, nl->grid, N, nl->capA, types, nl->candA, nl->offA,
-                           nl->revA);
-    }
-    {
         ProfScope ps_(K_NLIST, s);
         const int lg = lanes_log2(P);
         const double rR2 = m->hp.rc_radial * m->hp.rc_radial, rA2 = m->hp.rc_angular * m->hp.rc_angular;
@@ -802,7 +792,7 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
         hipLaunchKernelGGL(k_union, dim3(div_up(N, kBlock / 64), 2), dim3(kBlock), 0, s, pos,
                            reinterpret_cast<const float4 *>(nl->pos4), nl->cen, nl->spr, P, N, nl->S, lg, nl->atom_sys, nl->geom, cR,
                            cA, nl->candR, nl->offR, nl->candA, nl->offA, nl->capR, nl->capA, nl->uniR, nl->umR,
-                           nl->uendR, nl->uniA, nl->umA, nl->uendA, nl->status);
+                           nl->uendR, nl->uniA, nl->umA, nl->uendA, nl->status, nl->grid, types, nl->revA);
     }
     NEP_HIP(hipGetLastError());
     nl->built = 1;
