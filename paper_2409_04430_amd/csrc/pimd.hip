@@ -205,41 +205,36 @@ __global__ __launch_bounds__(kStepBlock) void k_trpmd(StepArgs a, const double *
 // The same stage with the mode transforms on the matrix cores, for P a
 // multiple of 16: both transforms are products with the P x P matrix C over
 // a block of elements, (C^T X) and (C X~), done as 16 x 16 x 4 FP64 tiles.
-// One wavefront takes 16 elements: the bead values come straight from the
-// bead-major arrays as B fragments (16 consecutive elements of one bead per
-// lane group), the per-mode update runs on the result tiles (lane j + 16 g
-// holds modes g, g + 4, g + 8, g + 12 of a 16-mode tile for element j), and
-// the new mode vectors pass through LDS to become the B fragments of the
-// back transform.  FP64 fragment layout: A(i, k) in lane i + 16 k, B(k, j)
+// One wavefront takes 16 elements and one 16-mode tile: the bead values
+// come straight from the bead-major arrays as B fragments (16 consecutive
+// elements of one bead per lane group), the per-mode update runs on the
+// result tile (lane j + 16 g holds modes g, g + 4, g + 8, g + 12 of the tile
+// for element j), the new mode vectors of all mode tiles meet in LDS, and
+// each wavefront back-transforms one 16-bead tile.  FP64 fragment layout: A(i, k) in lane i + 16 k, B(k, j)
 // in lane j + 16 k, result (i, j) in lane j + 16 (i % 4), slot i / 4.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-template <int P> constexpr int step_mf_waves() { return P <= 32 ? 4 : 2; }   // wavefronts per workgroup
+// Workgroup: ET element tiles x MT mode tiles, one wavefront each (4 or 3).
+template <int P> constexpr int step_mf_et() { return P == 48 ? 1 : 64 / P; }
 
 template <int P>
-__global__ __launch_bounds__(64 * step_mf_waves<P>()) void k_trpmd_mf(StepArgs a, const double *__restrict__ cst)
+__global__ __launch_bounds__(64 * 4) void k_trpmd_mf(StepArgs a, const double *__restrict__ cst)
 {
     static_assert(P % 16 == 0 && P <= 64, "matrix-core stage needs P = 16, 32, 48 or 64");
-    constexpr int MT = P / 16, KS = P / 4, W = step_mf_waves<P>();
-    __shared__ double xt[W][2][P][16];   // new mode vectors v~, q~ per wavefront
+    constexpr int MT = P / 16, KS = P / 4, ET = step_mf_et<P>();
+    __shared__ double xt[ET][2][P][16];   // new mode vectors v~, q~ of each element tile
     const PimdLayout Lo(P);
     const int M = 3 * a.N;
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lg = l >> 4;
-    const int e0 = (blockIdx.x * W + wv) * 16;
-    if (e0 >= M) return;   // whole wavefront (no workgroup barrier below)
+    const int et = wv / MT, mt = wv - et * MT;   // this wavefront's element tile and 16-mode (16-bead) tile
+    const int e0 = (blockIdx.x * ET + et) * 16;
     const int e = e0 + lr;
     const bool ok = e < M;
     const bool pre = a.stage != PIMD_STAGE_POST, post = a.stage != PIMD_STAGE_PRE;
     const int64_t step = a.step_dev ? *a.step_dev : a.step;
     const double *C = cst + Lo.C;   // C[b * P + k]
 
-    // forward: v~ = C^T v, f~ = C^T F, q~ = C^T q, one 16 x 16 tile per mode block
-    f64x4 vt[MT], ft[MT], qt[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-        vt[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
-        ft[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
-        qt[mt] = f64x4{0.0, 0.0, 0.0, 0.0};
-    }
+    // forward, modes 16 mt .. 16 mt + 15: v~ = C^T v, f~ = C^T F, q~ = C^T q
+    f64x4 vt = {0.0, 0.0, 0.0, 0.0}, ft = {0.0, 0.0, 0.0, 0.0}, qt = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const int b = 4 * ks + lg;
@@ -247,13 +242,10 @@ __global__ __launch_bounds__(64 * step_mf_waves<P>()) void k_trpmd_mf(StepArgs a
         const double xv = ok ? a.vel[at] : 0.0;
         const double xf = ok ? (double)a.F[at] : 0.0;
         const double xq = (ok && pre) ? a.pos[at] : 0.0;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const double cA = C[(size_t)b * P + 16 * mt + lr];   // C^T(mode 16 mt + lr, bead b)
-            vt[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(cA, xv, vt[mt], 0, 0, 0);
-            ft[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(cA, xf, ft[mt], 0, 0, 0);
-            if (pre) qt[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(cA, xq, qt[mt], 0, 0, 0);
-        }
+        const double cA = C[(size_t)b * P + 16 * mt + lr];   // C^T(mode 16 mt + lr, bead b)
+        vt = __builtin_amdgcn_mfma_f64_16x16x4f64(cA, xv, vt, 0, 0, 0);
+        ft = __builtin_amdgcn_mfma_f64_16x16x4f64(cA, xf, ft, 0, 0, 0);
+        if (pre) qt = __builtin_amdgcn_mfma_f64_16x16x4f64(cA, xq, qt, 0, 0, 0);
     }
 
     // per (mode, element): thermostat, kicks and the Cayley map
@@ -263,70 +255,54 @@ __global__ __launch_bounds__(64 * step_mf_waves<P>()) void k_trpmd_mf(StepArgs a
     const double sig = sqrt(a.kTP / (m * a.conv));
     const int NB = (P + 3) / 4;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) {
-            const int k = 16 * mt + lg + 4 * s4;
-            const double c1 = cst[Lo.c1 + k];
-            double alpha = c1, beta = 1.0, gamma = 0.0;
-            if (a.stage == PIMD_STAGE_POST) beta = c1;
-            if (a.stage == PIMD_STAGE_FUSED) {
-                alpha = c1 * c1;
-                beta = c1 * c1 + 1.0;
-            }
-            if (a.noise && ok) {
-                const int kb = k >> 2, e4 = k & 3;
-                const double gs = sig * cst[Lo.sc2 + k];
-                if (a.stage == PIMD_STAGE_FUSED) {
-                    const double z1 = normal1(a.seed, (uint64_t)step, 1, i, comp, NB, kb, e4);
-                    const double z0 = normal1(a.seed, (uint64_t)(step + 1), 0, i, comp, NB, kb, e4);
-                    gamma = gs * (c1 * z1 + z0);
-                } else {
-                    gamma = gs * normal1(a.seed, (uint64_t)step, post ? 1 : 0, i, comp, NB, kb, e4);
-                }
-            }
-            const double v1 = alpha * vt[mt][s4] + gamma + beta * (hk * ft[mt][s4]);
-            double vn = v1, qn = 0.0;
-            if (pre) {
-                const double cq = cst[Lo.cq + k], qv = cst[Lo.qv + k], vq = cst[Lo.vq + k];
-                qn = cq * qt[mt][s4] + qv * v1;
-                vn = cq * v1 - vq * qt[mt][s4];
-            }
-            xt[wv][0][k][lr] = vn;
-            xt[wv][1][k][lr] = qn;
+    for (int s4 = 0; s4 < 4; ++s4) {
+        const int k = 16 * mt + lg + 4 * s4;
+        const double c1 = cst[Lo.c1 + k];
+        double alpha = c1, beta = 1.0, gamma = 0.0;
+        if (a.stage == PIMD_STAGE_POST) beta = c1;
+        if (a.stage == PIMD_STAGE_FUSED) {
+            alpha = c1 * c1;
+            beta = c1 * c1 + 1.0;
         }
+        if (a.noise && ok) {
+            const int kb = k >> 2, e4 = k & 3;
+            const double gs = sig * cst[Lo.sc2 + k];
+            if (a.stage == PIMD_STAGE_FUSED) {
+                const double z1 = normal1(a.seed, (uint64_t)step, 1, i, comp, NB, kb, e4);
+                const double z0 = normal1(a.seed, (uint64_t)(step + 1), 0, i, comp, NB, kb, e4);
+                gamma = gs * (c1 * z1 + z0);
+            } else {
+                gamma = gs * normal1(a.seed, (uint64_t)step, post ? 1 : 0, i, comp, NB, kb, e4);
+            }
+        }
+        const double v1 = alpha * vt[s4] + gamma + beta * (hk * ft[s4]);
+        double vn = v1, qn = 0.0;
+        if (pre) {
+            const double cq = cst[Lo.cq + k], qv = cst[Lo.qv + k], vq = cst[Lo.vq + k];
+            qn = cq * qt[s4] + qv * v1;
+            vn = cq * v1 - vq * qt[s4];
+        }
+        xt[et][0][k][lr] = vn;
+        xt[et][1][k][lr] = qn;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __syncthreads();   // every mode tile of the element tile is in LDS
 
-    // back transform: v = C v~, q = C q~
-    f64x4 vb[MT], qb[MT];
-#pragma unroll
-    for (int bt = 0; bt < MT; ++bt) {
-        vb[bt] = f64x4{0.0, 0.0, 0.0, 0.0};
-        qb[bt] = f64x4{0.0, 0.0, 0.0, 0.0};
-    }
+    // back transform, beads 16 mt .. 16 mt + 15: v = C v~, q = C q~
+    f64x4 vb = {0.0, 0.0, 0.0, 0.0}, qb = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const int k = 4 * ks + lg;
-        const double yv = xt[wv][0][k][lr], yq = xt[wv][1][k][lr];
-#pragma unroll
-        for (int bt = 0; bt < MT; ++bt) {
-            const double cA = C[(size_t)(16 * bt + lr) * P + k];   // C(bead 16 bt + lr, mode k)
-            vb[bt] = __builtin_amdgcn_mfma_f64_16x16x4f64(cA, yv, vb[bt], 0, 0, 0);
-            if (pre) qb[bt] = __builtin_amdgcn_mfma_f64_16x16x4f64(cA, yq, qb[bt], 0, 0, 0);
-        }
+        const double cA = C[(size_t)(16 * mt + lr) * P + k];   // C(bead 16 mt + lr, mode k)
+        vb = __builtin_amdgcn_mfma_f64_16x16x4f64(cA, xt[et][0][k][lr], vb, 0, 0, 0);
+        if (pre) qb = __builtin_amdgcn_mfma_f64_16x16x4f64(cA, xt[et][1][k][lr], qb, 0, 0, 0);
     }
     if (ok) {
 #pragma unroll
-        for (int bt = 0; bt < MT; ++bt)
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {
-                const size_t at = (size_t)(16 * bt + lg + 4 * s4) * M + e;
-                a.vel[at] = vb[bt][s4];
-                if (pre) a.pos[at] = qb[bt][s4];
-            }
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const size_t at = (size_t)(16 * mt + lg + 4 * s4) * M + e;
+            a.vel[at] = vb[s4];
+            if (pre) a.pos[at] = qb[s4];
+        }
     }
 }
 
@@ -360,8 +336,8 @@ static void launch_step(const StepArgs &a, const double *cst, hipStream_t s)
     ProfScope ps_(K_TRPMD, s);
 #define NEP_STEP_MF(PP)                                                                                     \
     case PP:                                                                                                \
-        hipLaunchKernelGGL(k_trpmd_mf<PP>, dim3(div_up(3 * a.N, 16 * step_mf_waves<PP>())),                 \
-                           dim3(64 * step_mf_waves<PP>()), 0, s, a, cst);                                   \
+        hipLaunchKernelGGL(k_trpmd_mf<PP>, dim3(div_up(3 * a.N, 16 * step_mf_et<PP>())),                    \
+                           dim3(64 * step_mf_et<PP>() * (PP / 16)), 0, s, a, cst);                          \
         return;
     switch (a.P) {   // matrix-core transforms where P is a multiple of 16
         NEP_STEP_MF(16) NEP_STEP_MF(32) NEP_STEP_MF(48) NEP_STEP_MF(64)
