@@ -71,6 +71,11 @@ def lib():
         L.or_bf16_round.restype = C.c_double
         L.or_bf16_round_array.argtypes = [dp, dp, C.c_int]
         L.or_model_round_w0_bf16.argtypes = [vp]
+        L.or_observables.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp, dp, C.c_double, dp]
+        L.or_observables.restype = None
+        L.or_berendsen.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_int,
+                                   dp]
+        L.or_berendsen.restype = None
         _lib = L
     return _lib
 
@@ -253,6 +258,39 @@ def trpmd_stage(pos, vel, F, mass, *, dt, T, tau, mode, seed, step, stage):
                               _d(pos), _d(vel), _d(F), int(step), int(stage))
     if rc:
         raise ValueError("oracle: bad trpmd_stage arguments")
+
+
+OBS_EPOT, OBS_K, OBS_W, OBS_PTENS, OBS_P = 0, 1, 2, 11, 20
+OBS_COUNT = 21
+
+
+def observables(pos, F, W_bead, E_bead, box, T: float) -> dict:
+    """Centroid-virial observables of one ring-polymer configuration (Sec. II.A).
+
+    pos [P,N,3] (A), F [P,N,3] (eV/A), W_bead [P,9] and E_bead [P] (eV), box
+    edge lengths [3] (A), T (K).  Returns the raw 21-vector and its parts:
+    Epot (eV), K (eV), W [3,3] (eV), Ptens [3,3] (GPa), p (GPa)."""
+    pos = _f64(pos); F = _f64(F); Wb = _f64(W_bead).reshape(-1, 9); Eb = _f64(E_bead).reshape(-1)
+    P, N = pos.shape[:2]
+    L = _f64(np.asarray(box, np.float64).reshape(-1)[[0, 4, 8]] if np.asarray(box).size == 9 else box)
+    out = np.zeros(OBS_COUNT)
+    lib().or_observables(P, N, _d(pos), _d(F), _d(Wb), _d(Eb), _d(L), float(T), _d(out))
+    return {"raw": out, "Epot": out[OBS_EPOT], "K": out[OBS_K], "W": out[OBS_W:OBS_W + 9].reshape(3, 3),
+            "Ptens": out[OBS_PTENS:OBS_PTENS + 9].reshape(3, 3), "p": out[OBS_P]}
+
+
+def berendsen(pos, box, ptens, p0, *, beta: float, tau_p: float, dt: float, aniso: bool):
+    """Berendsen-like pressure control (Sec. II.D): scales pos [P,N,3] in place; returns (new edges [3], mu [3])."""
+    assert pos.dtype == np.float64 and pos.flags.c_contiguous
+    P, N = pos.shape[:2]
+    L = _f64(np.array(np.asarray(box, np.float64).reshape(-1)[[0, 4, 8]] if np.asarray(box).size == 9 else box,
+                      np.float64))
+    pt = _f64(np.asarray(ptens, np.float64).reshape(9))
+    p0 = _f64(np.broadcast_to(np.asarray(p0, np.float64), (3,)).copy())
+    mu = np.zeros(3)
+    lib().or_berendsen(P, N, _d(pos), _d(L), _d(pt), _d(p0), float(beta), float(tau_p), float(dt), int(aniso),
+                       _d(mu))
+    return L, mu
 
 
 def train_loss(out: dict, ref: dict, lambdas, N: int):

@@ -285,3 +285,88 @@ void or_cayley_coeffs(int P, double T, double dt, double *out)
     }
     free(w);
 }
+
+/* ------------------------------------------------------------------ */
+/* Observables of the ring polymer (Sec. II.A: kinetic energy by the    */
+/* centroid virial estimator, the virial tensor and the pressure        */
+/* tensor) and the Berendsen-like pressure control of the workflow      */
+/* (Sec. II.D).                                                          */
+/*                                                                      */
+/* Readings:                                                            */
+/*  - The centroid of atom i follows the periodic boundaries: each bead  */
+/*    is first brought to the image nearest bead 1 of the same atom,     */
+/*    r~_j = r_1 + mic(r_j - r_1), and r_c = (1/P) sum_j r~_j; bead       */
+/*    displacements from it are r~_j - r_c.  For unwrapped ring polymers  */
+/*    (all beads of an atom in one image) this is the plain mean.        */
+/*  - T in K and N kB T is the physical temperature's term; the pressure */
+/*    tensor is (N kB T 1 + W) / V with W the centroid virial tensor      */
+/*    (outer product with the displacement first, the force second) plus */
+/*    the bead average of the potential's virial.                        */
+/*  - Pressure control: mu_a = 1 - beta dt / (3 tau_p) (p0_a - p_a), with */
+/*    p_a = P_aa (anisotropic) or tr(P) / 3 for every axis (isotropic);   */
+/*    every bead coordinate and box edge is multiplied by mu_a.  Pressure */
+/*    in GPa, beta (compressibility) in 1/GPa, dt and tau_p in fs.        */
+/* ------------------------------------------------------------------ */
+
+/* 1 eV / A^3 in GPa */
+static double ev_a3_gpa(void) { return 1.602176634e-19 / 1e-30 / 1e9; }
+
+static double mic1(double d, double L) { return d - L * nearbyint(d / L); }
+
+/* out[0]  potential energy, mean of E_bead over the beads (eV)
+ * out[1]  kinetic energy K = 3/2 N kB T - 1/2 sum_i (1/P) sum_j dr_j . F_j (eV)
+ * out[2..10]  W_ab = -sum_i (1/P) sum_j dr_j,a F_j,b + (1/P) sum_j W_bead[j][ab] (eV)
+ * out[11..19] pressure tensor (N kB T delta_ab + W_ab) / V (GPa)
+ * out[20] scalar pressure tr / 3 (GPa)
+ * pos [P][N][3], F [P][N][3] (eV/A), W_bead [P][9], E_bead [P], L[3] (A). */
+void or_observables(int P, int N, const double *pos, const double *F, const double *W_bead, const double *E_bead,
+                    const double *L, double T, double *out)
+{
+    double Wcv[9] = {0};
+    for (int i = 0; i < N; ++i) {
+        double rc[3] = {0, 0, 0};
+        for (int j = 0; j < P; ++j)
+            for (int a = 0; a < 3; ++a) {
+                const double r1 = pos[(size_t)i * 3 + a];
+                rc[a] += r1 + mic1(pos[((size_t)j * N + i) * 3 + a] - r1, L[a]);
+            }
+        for (int a = 0; a < 3; ++a) rc[a] /= P;
+        for (int j = 0; j < P; ++j) {
+            double dr[3];
+            for (int a = 0; a < 3; ++a) {
+                const double r1 = pos[(size_t)i * 3 + a];
+                dr[a] = r1 + mic1(pos[((size_t)j * N + i) * 3 + a] - r1, L[a]) - rc[a];
+            }
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) Wcv[a * 3 + b] += dr[a] * F[((size_t)j * N + i) * 3 + b];
+        }
+    }
+    double Wpot[9] = {0}, Epot = 0.0;
+    for (int j = 0; j < P; ++j) {
+        Epot += E_bead[j];
+        for (int e = 0; e < 9; ++e) Wpot[e] += W_bead[j * 9 + e];
+    }
+    const double NkT = N * OR_KB * T, V = L[0] * L[1] * L[2];
+    out[0] = Epot / P;
+    out[1] = 1.5 * NkT - 0.5 * (Wcv[0] + Wcv[4] + Wcv[8]) / P;
+    for (int e = 0; e < 9; ++e) {
+        out[2 + e] = -Wcv[e] / P + Wpot[e] / P;
+        out[11 + e] = ((e % 4 == 0 ? NkT : 0.0) + out[2 + e]) / V * ev_a3_gpa();
+    }
+    out[20] = (out[11] + out[15] + out[19]) / 3.0;
+}
+
+/* Berendsen-like scaling: mu[3] from the pressure tensor ptens[9] (GPa), then
+ * pos [P][N][3] and L[3] scaled in place. */
+void or_berendsen(int P, int N, double *pos, double *L, const double *ptens, const double *p0, double beta,
+                  double tau_p, double dt, int aniso, double *mu)
+{
+    const double p_iso = (ptens[0] + ptens[4] + ptens[8]) / 3.0;
+    for (int a = 0; a < 3; ++a) {
+        const double p = aniso ? ptens[a * 4] : p_iso;
+        mu[a] = 1.0 - beta * dt / (3.0 * tau_p) * (p0[a] - p);
+    }
+    for (size_t e = 0; e < (size_t)P * N; ++e)
+        for (int a = 0; a < 3; ++a) pos[e * 3 + a] *= mu[a];
+    for (int a = 0; a < 3; ++a) L[a] *= mu[a];
+}
