@@ -52,6 +52,8 @@ def parse():
                     help="run one plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--no-profile", action="store_true", help="do not bracket kernels with timing events")
     ap.add_argument("--no-student", action="store_true", help="skip the learned-student leg")
+    ap.add_argument("--no-npt", action="store_true", help="skip the barostat (NPT) leg")
+    ap.add_argument("--npt-steps", type=int, default=50, help="timed steps of the NPT leg")
     ap.add_argument("--student-only", action="store_true",
                     help="run only the learned-student leg (prints its JSON object)")
     ap.add_argument("--student-epochs", type=int, default=200)
@@ -141,6 +143,61 @@ def cpu_baseline(w, model_path, system, nb_req: int):
             "sample": f"NEP energy/forces/virial (brute-force neighbours) of {nb} of {P} beads x {N} atoms "
                       f"({t_nep:.1f} s) plus one fused integrator stage over all beads ({t_int:.2f} s); "
                       f"step time = per-bead NEP time x {P} + integrator time"}
+
+
+def npt_leg(args, torch, lib, w, model_path, s, NepPimd, nvt_ms: float):
+    """The same workload with the ring-polymer observables and the isotropic
+    Berendsen-like barostat after every step (Sec. II.A, II.D): step time, and
+    the observables and cell-scaling kernels against the HBM roofline."""
+    baro = dict(p0=0.0, beta=1.0 / 50.0, tau_p=500.0, anisotropic=False)
+    eng = NepPimd(model_path, s, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=0,
+                  obs_every=1, barostat=baro)
+    eng.run(5)
+    eng.check()
+    kernels = {}
+    if not args.no_profile:
+        lib.profile_read(reset=True)
+        lib.profile_enable(True)
+        eng.run(10)
+        torch.cuda.synchronize()
+        lib.profile_enable(False)
+        kt = lib.profile_read(reset=True)
+        kernels = {k: 1e3 * v[0] / v[1] for k, v in kt.items() if v[1]}
+    eng.obs_log.clear()
+    eng.nl.status(clear=True)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    box0 = np.asarray(eng.box, np.float64).copy()
+    e0.record(stream)
+    eng.run(args.npt_steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    eng.check()
+    ms = e0.elapsed_time(e1) / args.npt_steps
+    _, hist = eng.observables_history()
+    units = s.N * s.P
+    out = {"ms_per_step": round(ms, 4), "steps": args.npt_steps, "vs_nvt_step": round(ms / nvt_ms, 3),
+           "barostat": baro, "note": "one host read of the 3 scaling factors per step (the neighbour build needs "
+                                     "the new cell); candidate rows are reused across cell changes while the "
+                                     "box-scaled skin test holds",
+           "rebuilds": int(eng.nl.status(clear=True)["rebuilds"]),
+           "pressure_GPa_first_last": [round(float(hist[0][lib.OBS_PSCALAR]), 4),
+                                       round(float(hist[-1][lib.OBS_PSCALAR]), 4)],
+           "box_A_start_end": [round(float(box0.reshape(-1)[0]), 6),
+                               round(float(np.asarray(eng.box).reshape(-1)[0]), 6)],
+           "kernels_us": {k: round(v, 2) for k, v in kernels.items()}}
+    # HBM roofline: observables read pos (24 B) and F (12 B) per (atom, bead);
+    # the scaling reads and writes pos (48 B)
+    for name, per in (("observables", 36.0), ("barostat", 48.0)):
+        if name in kernels:
+            gbs = per * units / (kernels[name] * 1e-6) / 1e9
+            out[name + "_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,
+                                       "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
+                                       "bytes_per_launch": int(per * units), "avg_us": round(kernels[name], 2)}
+    del eng
+    return out
 
 
 def student_leg(args, torch, lib, configs, I):
@@ -343,6 +400,9 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, model_path, s, args.cpu_beads)
+    npt = None
+    if not args.no_npt:
+        npt = npt_leg(args, torch, lib, w, model_path, s, NepPimd, gpu_ms / args.steps)
     stu = None
     if not args.no_student:
         del eng
@@ -373,6 +433,7 @@ def main():
         "roofline": roof,
         "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
         "cpu_baseline": cpu,
+        "npt": npt,
         "student_vs_teacher": stu,
     }
     print(json.dumps(out), flush=True)

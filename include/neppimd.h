@@ -185,11 +185,15 @@ int32_t neighbor_build(const nep_model *model, nep_nlist *nl, const double *pos,
 
 /* Reuse of the candidate rows (a Verlet skin on the centroid search): with
  * skin > 0 the rows are built with radius rc + 2 D + skin and kept while
- * 2 (D - D_build) + 2 max_i |c_i - c_i,build| <= skin, which keeps them a
- * superset of every bead pair within the cutoffs (triangle inequality); the
- * decision is taken on the device, without a host round trip.  A changed
- * box rebuilds.  The species of the atoms must not change between calls on
- * one handle unless nep_nlist_invalidate is called.  skin = 0 (the default)
+ * (rc + 2 D + 2 max_i |c_i - lambda c_i,build|) / lambda_min - rc - 2 D_build
+ * <= skin for both cutoffs, lambda = L / L_build per axis of the box (so
+ * 2 (D - D_build) + 2 max_i |c_i - c_i,build| <= skin for an unchanged box),
+ * which keeps them a superset of every bead pair within the cutoffs
+ * (triangle inequality, any periodic image); the decision is taken on the
+ * device, without a host round trip.  A box scaled by a barostat therefore
+ * keeps the rows until the skin is used up.  The species of the atoms must
+ * not change between calls on one handle unless nep_nlist_invalidate is
+ * called.  skin = 0 (the default)
  * rebuilds on every call.  Errors: NEP_ERR_INVALID_ARG (skin outside
  * [0, 10] A). */
 int32_t nep_nlist_set_skin(nep_nlist *nl, double skin);
@@ -365,6 +369,58 @@ int32_t trpmd_step(const pimd_ctx *ctx, double *pos, double *vel, const float *F
  * noise.  Errors as trpmd_step, and NEP_ERR_INVALID_ARG for a null counter. */
 int32_t trpmd_step_dev(const pimd_ctx *ctx, double *pos, double *vel, const float *F, int64_t *step,
                        int32_t stage, hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* Observables and pressure control (Sec. II.A, Sec. II.D)             */
+/* ------------------------------------------------------------------ */
+
+/* Entries of the observables vector written by pimd_observables. */
+enum pimd_obs_index {
+    PIMD_OBS_EPOT = 0,      /* potential energy: mean of the per-bead energies (eV) */
+    PIMD_OBS_KINETIC = 1,   /* centroid virial kinetic energy (eV) */
+    PIMD_OBS_VIRIAL = 2,    /* virial tensor W [3][3], row = displacement axis (eV) */
+    PIMD_OBS_PRESSURE = 11, /* pressure tensor [3][3] (GPa) */
+    PIMD_OBS_PSCALAR = 20,  /* trace of the pressure tensor / 3 (GPa) */
+    PIMD_OBS_COUNT = 21
+};
+
+/* Ring-polymer observables of one system (Sec. II.A): with the centroid
+ * r_c of each atom and the bead displacements dr_j = r_j - r_c, taken through
+ * the periodic boundaries (each bead at its image nearest the atom's first
+ * bead),
+ *   K = 3/2 N kB T - 1/2 sum_i (1/P) sum_j dr_j . F_j,
+ *   W = -sum_i (1/P) sum_j dr_j (x) F_j + (1/P) sum_j W_bead[j],
+ *   pressure tensor = (N kB T 1 + W) / V,
+ * T the context's physical temperature.  pos, F [P][N][3] dev (float64,
+ * float32), W_bead [P][9] and E_bead [P] dev float64 (the per-bead virial
+ * and energy of nep_compute), box host [9] (orthorhombic), out
+ * [PIMD_OBS_COUNT] dev float64, written on the stream (pos and F may be
+ * null when N = 0).  The partial sums
+ * live in the context: calls on one context must not overlap.  The sum
+ * order is fixed, so results are bitwise reproducible.  Errors:
+ * NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED (non-orthorhombic cell),
+ * NEP_ERR_HIP. */
+int32_t pimd_observables(const pimd_ctx *ctx, const double *pos, const float *F, const double *W_bead,
+                         const double *E_bead, const double box[9], double *out, hipStream_t stream);
+
+typedef struct pimd_barostat {
+    double p0_GPa[3];       /* target pressure per axis (isotropic: all three equal) */
+    double beta_per_GPa;    /* compressibility, >= 0 */
+    double tau_p_fs;        /* coupling time, > 0 */
+    int32_t anisotropic;    /* 0: couple tr(P)/3 on every axis; 1: each axis to its own P_aa */
+} pimd_barostat;
+
+/* Berendsen-like pressure control of the workflow (Sec. II.D), applied after
+ * the closing half of a step: per axis mu_a = 1 - beta dt / (3 tau_p) (p0_a -
+ * p_a), with p_a = P_aa (anisotropic) or tr(P)/3 (isotropic) read from obs
+ * (the vector of pimd_observables, dev), dt the context's time step; every
+ * bead coordinate pos[j][i][a] (dev, in place) is multiplied by mu_a and the
+ * factors are written to mu [3] (dev).  The caller scales its cell edges by
+ * the same factors before the next neighbour build (a changed box rebuilds
+ * the candidate rows).  Errors: NEP_ERR_INVALID_ARG (null argument, beta < 0,
+ * tau_p <= 0, non-finite target), NEP_ERR_HIP. */
+int32_t pimd_berendsen(const pimd_ctx *ctx, double *pos, const double *obs, const pimd_barostat *params,
+                       double *mu, hipStream_t stream);
 
 /* ------------------------------------------------------------------ */
 /* Training (gradient of an energy / force / virial loss, Adam)        */

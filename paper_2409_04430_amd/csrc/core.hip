@@ -80,7 +80,8 @@ void pack_positions(const double *pos, int P, int N, const int32_t *atom_sys, co
 
 static const char *kKernelNames[K_NUM] = {"fill", "pack", "centroid", "grid", "cell_count", "cell_scan", "cell_fill",
                                           "cell_sort", "candidates", "sort_rows", "reverse", "nlist",
-                                          "materialize", "descriptor", "force_ang", "force", "reduce", "trpmd", "modes"};
+                                          "materialize", "descriptor", "force_ang", "force", "reduce", "trpmd", "modes",
+                                          "observables", "barostat"};
 static std::atomic<int> g_prof_on{0};
 static std::atomic<int> g_prof_only{-1};   // -1: every kind
 static std::mutex g_prof_mu;
@@ -479,10 +480,10 @@ extern "C" int32_t nep_nlist_create_batched(const nep_model *m, int32_t P, int32
     if (e == hipSuccess) e = dalloc(&nl->pairbuf, 4 * PN * capA);
     if (e == hipSuccess) e = dalloc(&nl->pos4, 4 * PN);
     if (e == hipSuccess) e = dalloc(&nl->cell_atoms, Nn);
-    if (e == hipSuccess) e = dalloc(&nl->grid, 16 + 4 * (size_t)nsys);
+    if (e == hipSuccess) e = dalloc(&nl->grid, 16 + kDevSysWords * (size_t)nsys);
     if (e == hipSuccess) e = dalloc(&nl->status, 8);
     if (e == hipSuccess) e = hipMemset(nl->status, 0, 8 * sizeof(uint32_t));
-    if (e == hipSuccess) e = hipMemset(nl->grid, 0, (16 + 4 * (size_t)nsys) * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMemset(nl->grid, 0, (16 + kDevSysWords * (size_t)nsys) * sizeof(uint32_t));
     if (e == hipSuccess && Nn) e = hipMemset(nl->offR, 0, sizeof(int32_t) * Nn * (kMaxSpecies + 1));
     if (e == hipSuccess && Nn) e = hipMemset(nl->offA, 0, sizeof(int32_t) * Nn * (kMaxSpecies + 1));
     if (e == hipSuccess && Nn) e = hipMemset(nl->uendR, 0, sizeof(int32_t) * Nn * kMaxSpecies);

@@ -17,6 +17,8 @@ constexpr int kMaxSpecies = 4;
 constexpr int kLmax = 4;
 constexpr int kNumSH = 24;          // real spherical harmonics l = 1..4
 constexpr int kMaxBeads = 64;
+// 32-bit words per system in the neighbour list's device grid record (after 16 global words)
+constexpr int kDevSysWords = 10;
 
 int fail(int code, const char *fmt, ...);   // records the thread-local message, returns code
 
@@ -131,6 +133,8 @@ struct pimd_ctx {
     double *mass = nullptr;    // [N]
     double *consts = nullptr;  // C [P][P] then per mode c1, c2, cq, qv, vq
     std::vector<double> hC;    // host copy of C
+    double *obs_part = nullptr;  // [obs_blocks][9] partial sums of the observables
+    int obs_blocks = 0;
 };
 
 namespace nep {
@@ -292,7 +296,7 @@ int32_t update_geometry(const nep_model *m, nep_nlist *nl, const double *boxes, 
 enum KernelId {
     K_FILL = 0, K_PACK, K_CENTROID, K_GRID, K_CELL_COUNT, K_CELL_SCAN, K_CELL_FILL, K_CELL_SORT, K_CANDIDATES,
     K_SORT_ROWS, K_REVERSE, K_NLIST, K_MATERIALIZE,
-    K_DESCRIPTOR, K_FORCE_ANG, K_FORCE, K_REDUCE, K_TRPMD, K_MODES, K_NUM
+    K_DESCRIPTOR, K_FORCE_ANG, K_FORCE, K_REDUCE, K_TRPMD, K_MODES, K_OBS, K_BARO, K_NUM
 };
 struct ProfScope {
     int id;

@@ -47,7 +47,9 @@ static_assert(sizeof(DevGlobal) <= 16 * sizeof(uint32_t), "grid record exceeds i
 struct DevSys {
     int nc[3];              // cells per axis of this system (last rebuild)
     int ncell;
+    double Lb[3];           // box edges at the last rebuild
 };
+static_assert(sizeof(DevSys) == kDevSysWords * sizeof(uint32_t), "per-system grid record size");
 __device__ __forceinline__ DevGlobal *dev_global(uint32_t *grid) { return reinterpret_cast<DevGlobal *>(grid); }
 __device__ __forceinline__ const DevGlobal *dev_global(const uint32_t *grid)
 {
@@ -96,6 +98,7 @@ __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double
                               int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status);
 
 __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ pos, const int32_t *__restrict__ types,
+                                                     const int32_t *__restrict__ atom_sys,
                                                      int P, int N, int S, double *__restrict__ cen,
                                                      float *__restrict__ spr, const double *__restrict__ cen_ref,
                                                      const SysGeom *__restrict__ geom, int nsys, double rcR,
@@ -131,7 +134,15 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
             f |= NEP_FLAG_NONFINITE;
         } else {
             spread = (float)sqrt(m2) * 1.000001f + 1e-7f;   // rounded up
-            const double dx = c[0] - cen_ref[3 * i], dy = c[1] - cen_ref[3 * i + 1], dz = c[2] - cen_ref[3 * i + 2];
+            // displacement from the build centroid carried along with the box:
+            // c - lambda c_build, lambda = L / L_build per axis (1 for an unchanged box)
+            const int sy = atom_sys[i];
+            const DevSys *ds = dev_sys(grid, sy);
+            double lam[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) lam[a] = ds->Lb[a] > 0.0 ? geom[sy].L[a] / ds->Lb[a] : 1.0;
+            const double dx = c[0] - lam[0] * cen_ref[3 * i], dy = c[1] - lam[1] * cen_ref[3 * i + 1],
+                         dz = c[2] - lam[2] * cen_ref[3 * i + 2];
             const double d2 = dx * dx + dy * dy + dz * dz;
             disp = isfinite(d2) ? (float)sqrt(d2) * 1.000001f + 1e-7f : 3.0e38f;
         }
@@ -172,18 +183,32 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
 }
 
 // Rebuild decision and, on a rebuild, the grid and candidate radius from the
-// measured spread.  Candidate rows built with radius rc + 2 D0 + skin stay
-// complete while 2 (D - D0) + 2 max|c - c0| <= skin (triangle inequality on
-// the periodic centroid distance); otherwise they are rebuilt.
-// Run by the last workgroup of k_centroid, after every workgroup's maxima.
+// measured spread.  Rows built with radius rc + 2 D0 + skin on edges L0 hold
+// every j whose periodic centroid distance was below that radius.  With the
+// box now L = lambda L0 (per axis) and e = c_j - c_i + n L a minimum-image
+// centroid vector, e0 = c0_j - c0_i + n L0 satisfies
+//   lambda (x) e0 = e - (dc_j - dc_i),  dc = c - lambda (x) c0,
+// so |e0| <= (|e| + 2 max|dc|) / lambda_min, whatever the image n.  Every
+// bead pair inside the cutoff has |e| < rc + 2 D, so the rows stay complete
+// while (rc + 2 D + 2 max|dc|) / lambda_min - rc - 2 D0 <= skin for both
+// cutoffs (for an unchanged box: 2 (D - D0) + 2 max|dc| <= skin); otherwise
+// they are rebuilt.  Run by the last workgroup of k_centroid, after every
+// workgroup's maxima.
 __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double rcR, double rcA, double skin,
                               int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status)
 {
     DevGlobal *dg = dev_global(grid);
     const float spread = __uint_as_float(__atomic_load_n(&dg->spread_bits, __ATOMIC_RELAXED));
     const float disp = __uint_as_float(__atomic_load_n(&dg->disp_bits, __ATOMIC_RELAXED));
-    const double need = 2.0 * ((double)spread - (double)dg->d_build) + 2.0 * (double)disp;
-    const int rebuild = force || !(need <= skin);
+    double lam_min = 1.0;
+    for (int s = 0; s < nsys; ++s) {
+        const DevSys *ds = dev_sys(grid, s);
+        for (int a = 0; a < 3; ++a)
+            if (ds->Lb[a] > 0.0) lam_min = fmin(lam_min, geom[s].L[a] / ds->Lb[a]);
+    }
+    const double reach = 2.0 * (double)spread + 2.0 * (double)disp, d0 = 2.0 * (double)dg->d_build;
+    const double needR = (rcR + reach) / lam_min - rcR - d0, needA = (rcA + reach) / lam_min - rcA - d0;
+    const int rebuild = force || !(needR <= skin && needA <= skin);
     const double rc = rcR > rcA ? rcR : rcA;
     const double R = rc + 2.0 * (double)spread + skin + 1e-9 * (1.0 + rc);
     const double RA = rcA + 2.0 * (double)spread + skin + 1e-9 * (1.0 + rcA);
@@ -195,6 +220,7 @@ __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double
                 int nc = (int)floor(geom[s].L[a] / (R * (1.0 + 1e-9)));
                 nc = nc < 1 ? 1 : (nc > geom[s].nc_cap[a] ? geom[s].nc_cap[a] : nc);
                 ds->nc[a] = nc;
+                ds->Lb[a] = geom[s].L[a];
                 ncell *= nc;
             }
             ds->ncell = ncell;
@@ -748,14 +774,15 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
     float margin = 0.0f;
     const int32_t rc_ = update_geometry(m, nl, boxes, changed, margin);
     if (rc_ != NEP_OK) return rc_;
-    const bool force = !nl->built || changed;
+    const bool force = !nl->built;   // a changed box is covered by the device-side skin test
     pack_positions(pos, P, N, nl->atom_sys, nl->geom, reinterpret_cast<float4 *>(nl->pos4), s);
     const dim3 g1(div_up(N, kBlock));
     const dim3 gw(div_up(N, kBlock / 64));
     const dim3 gc(nl->ncell_total);
     {
         ProfScope ps_(K_CENTROID, s);
-        hipLaunchKernelGGL(k_centroid, g1, dim3(kBlock), 0, s, pos, types, P, N, nl->S, nl->cen, nl->spr, nl->cen_ref,
+        hipLaunchKernelGGL(k_centroid, g1, dim3(kBlock), 0, s, pos, types, nl->atom_sys, P, N, nl->S, nl->cen, nl->spr,
+                           nl->cen_ref,
                            nl->geom, nl->nsys, m->hp.rc_radial, m->hp.rc_angular, nl->skin, force ? 1 : 0, nl->grid,
                            nl->status);
     }

@@ -23,6 +23,8 @@ constexpr double kKB = 8.617333262e-5;     // eV/K
 constexpr double kHbar = 0.6582119569;     // eV fs
 // 1 amu A^2/fs^2 in eV
 inline double amu_a2_fs2_ev() { return 1.66053906660e-27 * 1e10 / 1.602176634e-19; }
+// 1 eV/A^3 in GPa
+inline double ev_a3_gpa() { return 1.602176634e-19 / 1e-30 / 1e9; }
 
 // Offsets into the per-context constant block.
 struct PimdLayout {
@@ -308,6 +310,129 @@ __global__ __launch_bounds__(64 * 4) void k_trpmd_mf(StepArgs a, const double *_
 
 __global__ void k_step_advance(int64_t *step) { *step += 1; }
 
+// ------------------------------------------------------- observables ---
+//
+// Centroid virial estimator of the kinetic energy, the virial tensor and the
+// pressure tensor (Sec. II.A).  One lane per (atom, bead), the P beads of an
+// atom in G = 2^ceil(log2 P) adjacent lanes.  A bead's displacement from the
+// centroid is taken through the periodic boundaries: each bead is brought to
+// the image nearest the atom's first bead, r~_j = r_1 + mic(r_j - r_1), and
+// dr_j = r~_j - mean_k r~_k.  Each workgroup reduces its lanes' dr (x) F to
+// nine FP64 partial sums in a fixed order; one workgroup then reduces the
+// partials in a fixed order and forms the outputs (bitwise reproducible).
+
+constexpr int kObsBlock = 256;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+__global__ __launch_bounds__(kObsBlock) void k_obs_partial(const double *__restrict__ pos, const float *__restrict__ F,
+                                                           int N, int P, int lg, double Lx, double Ly, double Lz,
+                                                           double *__restrict__ part)
+{
+    const int G = 1 << lg;
+    const int t = blockIdx.x * kObsBlock + threadIdx.x;
+    const int i = t >> lg, b = t & (G - 1);
+    const bool valid = i < N && b < P;
+    const double L[3] = {Lx, Ly, Lz};
+    double rel[3] = {0.0, 0.0, 0.0}, f[3] = {0.0, 0.0, 0.0};
+    if (valid) {
+        const double *r = pos + ((size_t)b * N + i) * 3;
+        const double *r1 = pos + (size_t)i * 3;
+        const float *fb = F + ((size_t)b * N + i) * 3;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double d = r[a] - r1[a];
+            rel[a] = d - L[a] * rint(d / L[a]);
+            f[a] = (double)fb[a];
+        }
+    }
+    // mean over the atom's beads (lanes b >= P hold zeros)
+    double dr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double sa = rel[a];
+        for (int o = 1; o < G; o <<= 1) sa += __shfl_xor(sa, o);
+        dr[a] = valid ? rel[a] - sa / P : 0.0;
+    }
+    __shared__ double red[kObsBlock / 64][9];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double v = wave_sum(dr[a] * f[c]);
+            if (lane == 0) red[w][a * 3 + c] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x < 9) {
+        double acc = 0.0;
+        for (int k = 0; k < kObsBlock / 64; ++k) acc += red[k][threadIdx.x];
+        part[(size_t)blockIdx.x * 9 + threadIdx.x] = acc;
+    }
+}
+
+struct ObsFinal {
+    const double *part, *Wb, *Eb;
+    int nblk, P, N;
+    double NkT, inv_vol_gpa;   // N kB T (eV); 1 / V in GPa per eV
+    double *out;
+};
+
+__global__ __launch_bounds__(kObsBlock) void k_obs_final(ObsFinal a)
+{
+    __shared__ double red[kObsBlock];
+    __shared__ double wcv[9];
+    for (int e = 0; e < 9; ++e) {
+        double acc = 0.0;
+        for (int k = threadIdx.x; k < a.nblk; k += kObsBlock) acc += a.part[(size_t)k * 9 + e];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int h = kObsBlock / 2; h > 0; h >>= 1) {
+            if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) wcv[e] = red[0];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double Ep = 0.0, Wp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int j = 0; j < a.P; ++j) {
+            Ep += a.Eb[j];
+            for (int e = 0; e < 9; ++e) Wp[e] += a.Wb[j * 9 + e];
+        }
+        a.out[PIMD_OBS_EPOT] = Ep / a.P;
+        a.out[PIMD_OBS_KINETIC] = 1.5 * a.NkT - 0.5 * (wcv[0] + wcv[4] + wcv[8]) / a.P;
+        for (int e = 0; e < 9; ++e) {
+            const double W = (Wp[e] - wcv[e]) / a.P;
+            a.out[PIMD_OBS_VIRIAL + e] = W;
+            a.out[PIMD_OBS_PRESSURE + e] = ((e % 4 == 0 ? a.NkT : 0.0) + W) * a.inv_vol_gpa;
+        }
+        a.out[PIMD_OBS_PSCALAR] =
+            (a.out[PIMD_OBS_PRESSURE] + a.out[PIMD_OBS_PRESSURE + 4] + a.out[PIMD_OBS_PRESSURE + 8]) / 3.0;
+    }
+}
+
+// Berendsen-like pressure control (Sec. II.D): per axis
+// mu_a = 1 - c (p0_a - p_a), c = beta dt / (3 tau_p), p_a the diagonal
+// pressure (anisotropic) or tr(P) / 3 (isotropic); every bead coordinate is
+// multiplied by mu of its axis.  The factors are also written to mu[3].
+__global__ __launch_bounds__(256) void k_berendsen(double *__restrict__ pos, int64_t M, const double *__restrict__ obs,
+                                                   double p0x, double p0y, double p0z, double c, int aniso,
+                                                   double *__restrict__ mu_out)
+{
+    const double *pt = obs + PIMD_OBS_PRESSURE;
+    const double piso = (pt[0] + pt[4] + pt[8]) / 3.0;
+    const double mu[3] = {1.0 - c * (p0x - (aniso ? pt[0] : piso)), 1.0 - c * (p0y - (aniso ? pt[4] : piso)),
+                          1.0 - c * (p0z - (aniso ? pt[8] : piso))};
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < M) pos[e] *= mu[e % 3];
+    if (e < 3) mu_out[e] = mu[e];
+}
+
 template <int P>
 __global__ __launch_bounds__(256) void k_modes(const double *__restrict__ in, double *__restrict__ out, int M,
                                                int dir, const double *__restrict__ cst)
@@ -415,6 +540,12 @@ extern "C" int32_t pimd_create(int32_t P, int32_t N, const pimd_params *prm, con
     hipError_t e = hipGetDevice(&c->device);
     if (e == hipSuccess) e = hipMalloc(&c->consts, sizeof(double) * Lo.total);
     if (e == hipSuccess) e = hipMalloc(&c->mass, sizeof(double) * (N > 0 ? N : 1));
+    {
+        int G = 1;
+        while (G < P) G <<= 1;
+        c->obs_blocks = (int)(((int64_t)N * G + kObsBlock - 1) / kObsBlock);
+        if (e == hipSuccess) e = hipMalloc(&c->obs_part, sizeof(double) * 9 * (c->obs_blocks > 0 ? c->obs_blocks : 1));
+    }
     if (e == hipSuccess) e = hipMemcpy(c->consts, h.data(), sizeof(double) * Lo.total, hipMemcpyHostToDevice);
     if (e == hipSuccess && N > 0) e = hipMemcpy(c->mass, mass, sizeof(double) * N, hipMemcpyDeviceToDevice);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -431,6 +562,7 @@ extern "C" void pimd_destroy(pimd_ctx *c)
     if (!c) return;
     if (c->consts) (void)hipFree(c->consts);
     if (c->mass) (void)hipFree(c->mass);
+    if (c->obs_part) (void)hipFree(c->obs_part);
     delete c;
 }
 
@@ -487,4 +619,54 @@ extern "C" int32_t trpmd_step_dev(const pimd_ctx *c, double *pos, double *vel, c
 {
     if (!step) return fail(NEP_ERR_INVALID_ARG, "trpmd_step_dev: null step counter");
     return step_common(c, pos, vel, F, 0, step, stage, s);
+}
+
+extern "C" int32_t pimd_observables(const pimd_ctx *c, const double *pos, const float *F, const double *W_bead,
+                                    const double *E_bead, const double box[9], double *out, hipStream_t s)
+{
+    if (!c || !box) return fail(NEP_ERR_INVALID_ARG, "pimd_observables: null argument");
+    if ((c->N > 0 && (!pos || !F)) || !W_bead || !E_bead || !out)
+        return fail(NEP_ERR_INVALID_ARG, "pimd_observables: null array");
+    double L[3];
+    if (!box_lengths(box, L)) return fail(NEP_ERR_UNSUPPORTED, "pimd_observables: only orthorhombic cells");
+    if (!(L[0] > 0.0 && L[1] > 0.0 && L[2] > 0.0)) return fail(NEP_ERR_INVALID_ARG, "pimd_observables: bad box");
+    int lg = 0;
+    while ((1 << lg) < c->P) ++lg;
+    const int nblk = c->obs_blocks;
+    ProfScope ps_(K_OBS, s);
+    if (nblk > 0)
+        hipLaunchKernelGGL(k_obs_partial, dim3(nblk), dim3(kObsBlock), 0, s, pos, F, c->N, c->P, lg, L[0], L[1], L[2],
+                           c->obs_part);
+    ObsFinal a;
+    a.part = c->obs_part;
+    a.Wb = W_bead;
+    a.Eb = E_bead;
+    a.nblk = nblk;
+    a.P = c->P;
+    a.N = c->N;
+    a.NkT = c->N * kKB * c->prm.T_K;
+    a.inv_vol_gpa = ev_a3_gpa() / (L[0] * L[1] * L[2]);
+    a.out = out;
+    hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(kObsBlock), 0, s, a);
+    NEP_HIP(hipGetLastError());
+    return NEP_OK;
+}
+
+extern "C" int32_t pimd_berendsen(const pimd_ctx *c, double *pos, const double *obs, const pimd_barostat *prm,
+                                  double *mu, hipStream_t s)
+{
+    if (!c || !prm) return fail(NEP_ERR_INVALID_ARG, "pimd_berendsen: null argument");
+    if (!obs || !mu || (c->N > 0 && !pos)) return fail(NEP_ERR_INVALID_ARG, "pimd_berendsen: null array");
+    if (!(prm->beta_per_GPa >= 0.0) || !(prm->tau_p_fs > 0.0) || !std::isfinite(prm->p0_GPa[0]) ||
+        !std::isfinite(prm->p0_GPa[1]) || !std::isfinite(prm->p0_GPa[2]) || !std::isfinite(prm->beta_per_GPa) ||
+        !std::isfinite(prm->tau_p_fs))
+        return fail(NEP_ERR_INVALID_ARG, "pimd_berendsen: bad target pressure, compressibility or tau_p");
+    const double cc = prm->beta_per_GPa * c->prm.dt_fs / (3.0 * prm->tau_p_fs);
+    const int64_t M = (int64_t)3 * c->P * c->N;
+    const int64_t nblk = M > 3 ? (M + 255) / 256 : 1;
+    ProfScope ps_(K_BARO, s);
+    hipLaunchKernelGGL(k_berendsen, dim3((unsigned)nblk), dim3(256), 0, s, pos, M, obs, prm->p0_GPa[0],
+                       prm->p0_GPa[1], prm->p0_GPa[2], cc, prm->anisotropic ? 1 : 0, mu);
+    NEP_HIP(hipGetLastError());
+    return NEP_OK;
 }

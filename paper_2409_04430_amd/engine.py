@@ -5,7 +5,10 @@ the neighbour lists and of the force workspace are polled every
 `check_every` steps.  The step is the paper's workflow (Sec. II.A): thermostat,
 half kick, free ring-polymer step, forces, half kick, thermostat; the two
 integrator halves around consecutive force evaluations run as one fused
-launch.
+launch.  Optional: the ring-polymer observables (centroid virial kinetic
+energy, virial and pressure tensors) recorded on the device after the
+closing half of every k-th step, and a Berendsen-like barostat after the
+closing half of every step (Sec. II.D); both split the fused launch.
 """
 from __future__ import annotations
 
@@ -34,7 +37,8 @@ class NepPimd:
 
     def __init__(self, model_path: str, system, *, dt: float, T: float, tau: float = 100.0,
                  mode: str = "trpmd", seed: int = 0, caps: Optional[tuple] = None, check_every: int = 50,
-                 want_atom: bool = False, skin: float = 0.5, autotune: bool = False):
+                 want_atom: bool = False, skin: float = 0.5, autotune: bool = False, obs_every: int = 0,
+                 barostat: Optional[dict] = None):
         import torch
         self.torch = torch
         dev = torch.device("cuda")
@@ -79,6 +83,13 @@ class NepPimd:
         self.started = False
         self.graph = None
         self.step_dev = None
+        self.obs_every = int(obs_every)
+        self.baro = dict(barostat) if barostat else None
+        self.obs_log = []
+        if (self.obs_every or self.baro) and self.batched:
+            raise ValueError("observables and the barostat need a single system")
+        self.obs = torch.zeros(lib.OBS_COUNT, dtype=torch.float64, device=dev)
+        self.mu = torch.ones(3, dtype=torch.float64, device=dev)
         self._fit_capacity()
         self.tile = None
         if autotune:
@@ -125,6 +136,24 @@ class NepPimd:
         self.pimd.step(self.pos, self.vel, self.F, self.step_no, lib.PRE)
         self.started = True
 
+    def _after_post(self, n: int):
+        """Observables and pressure control between the closing half of step n and the next step."""
+        rec = self.obs_every and (n + 1) % self.obs_every == 0
+        if not (rec or self.baro):
+            return
+        self.pimd.observables(self.pos, self.F, self.W, self.E, self.box, self.obs)
+        if rec:
+            self.obs_log.append((n, self.obs.clone()))
+        if self.baro:
+            b = self.baro
+            self.pimd.berendsen(self.pos, self.obs, self.mu, p0=b["p0"], beta=b["beta"], tau_p=b["tau_p"],
+                                anisotropic=b.get("anisotropic", False))
+            mu = self.mu.cpu().numpy()     # the next neighbour build needs the new cell
+            if not (np.all(np.isfinite(mu)) and np.all(mu > 0.0)):
+                raise lib.NepError(6, f"barostat scaling factors {mu}")
+            box = np.asarray(self.box, np.float64)
+            self.box = box * mu if box.shape == (3,) else (box.reshape(3, 3) * mu[:, None]).reshape(box.shape)
+
     def step(self):
         """One full step: forces at the advanced positions, then POST(n) + PRE(n+1)."""
         if self.graph is not None:
@@ -133,7 +162,13 @@ class NepPimd:
             if not self.started:
                 self.start()
             self.forces()
-            self.pimd.step(self.pos, self.vel, self.F, self.step_no, lib.FUSED)
+            n = self.step_no
+            if self.obs_every or self.baro:
+                self.pimd.step(self.pos, self.vel, self.F, n, lib.POST)
+                self._after_post(n)
+                self.pimd.step(self.pos, self.vel, self.F, n + 1, lib.PRE)
+            else:
+                self.pimd.step(self.pos, self.vel, self.F, n, lib.FUSED)
         self.step_no += 1
         if self.check_every and self.step_no % self.check_every == 0:
             self.check()
@@ -150,6 +185,8 @@ class NepPimd:
         must stay fixed while the graph is in use; `release()` returns to
         eager launches."""
         t = self.torch
+        if self.obs_every or self.baro:
+            raise ValueError("capture: observables and the barostat run eagerly")
         if not self.started:
             self.start()
         # one eager step first so that every lazy allocation has happened
@@ -175,5 +212,13 @@ class NepPimd:
             self.start()
         self.forces()
         self.pimd.step(self.pos, self.vel, self.F, self.step_no, lib.POST)
+        self._after_post(self.step_no)
         self.started = False
         self.step_no += 1
+
+    def observables_history(self):
+        """Recorded observables (synchronises): steps [n] and the vectors [n, OBS_COUNT]."""
+        if not self.obs_log:
+            return np.zeros(0, np.int64), np.zeros((0, lib.OBS_COUNT))
+        steps = np.array([n for n, _ in self.obs_log], np.int64)
+        return steps, self.torch.stack([o for _, o in self.obs_log]).cpu().numpy()

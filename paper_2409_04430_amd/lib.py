@@ -65,6 +65,14 @@ class PimdParams(C.Structure):
                 ("seed", C.c_uint64)]
 
 
+class PimdBarostat(C.Structure):
+    _fields_ = [("p0_GPa", C.c_double * 3), ("beta_per_GPa", C.c_double), ("tau_p_fs", C.c_double),
+                ("anisotropic", C.c_int32)]
+
+
+# entries of the observables vector (pimd_observables)
+OBS_EPOT, OBS_KINETIC, OBS_VIRIAL, OBS_PRESSURE, OBS_PSCALAR, OBS_COUNT = 0, 1, 2, 11, 20, 21
+
 _vp = C.c_void_p
 _i32 = C.c_int32
 _sig = {
@@ -96,6 +104,8 @@ _sig = {
     "rp_normal_modes": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "trpmd_step": (_i32, [_vp, _vp, _vp, _vp, C.c_int64, _i32, _vp]),
     "trpmd_step_dev": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "pimd_observables": (_i32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp, _vp]),
+    "pimd_berendsen": (_i32, [_vp, _vp, _vp, C.POINTER(PimdBarostat), _vp, _vp]),
     "nep_nlist_set_skin": (_i32, [_vp, C.c_double]),
     "nep_nlist_invalidate": (_i32, [_vp]),
     "nep_ws_set_tile": (_i32, [_vp, _i32]),
@@ -465,6 +475,23 @@ class Pimd:
         _check(_lib.trpmd_step_dev(self._h, _ptr(pos, t.float64, shp, "pos"), _ptr(vel, t.float64, shp, "vel"),
                                    _ptr(F, t.float32, shp, "F"), _ptr(step, t.int64, (1,), "step"), int(stage),
                                    _stream()))
+
+    def observables(self, pos, F, W, E, box, out):
+        """pimd_observables: out [OBS_COUNT] float64 device tensor, written on the stream."""
+        t = _torch()
+        shp = (self.P, self.N, 3)
+        _check(_lib.pimd_observables(self._h, _ptr(pos, t.float64, shp, "pos"), _ptr(F, t.float32, shp, "F"),
+                                     _ptr(W, t.float64, (self.P, 9), "W"), _ptr(E, t.float64, (self.P,), "E"),
+                                     _box9(box), _ptr(out, t.float64, (OBS_COUNT,), "out"), _stream()))
+
+    def berendsen(self, pos, obs, mu, *, p0, beta: float, tau_p: float, anisotropic: bool = False):
+        """pimd_berendsen: scales pos in place and writes the factors to mu [3] (device)."""
+        t = _torch()
+        p = np.broadcast_to(np.asarray(p0, np.float64), (3,))
+        prm = PimdBarostat((C.c_double * 3)(*p.tolist()), float(beta), float(tau_p), int(bool(anisotropic)))
+        _check(_lib.pimd_berendsen(self._h, _ptr(pos, t.float64, (self.P, self.N, 3), "pos"),
+                                   _ptr(obs, t.float64, (OBS_COUNT,), "obs"), C.byref(prm),
+                                   _ptr(mu, t.float64, (3,), "mu"), _stream()))
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -370,3 +370,49 @@ def test_skin_reuse_matches_fresh_lists(torch, L, tmpdir_session):
     st = eng.nl.status(clear=True)
     say(f"  rebuilds in 40 steps: {st['rebuilds']}")
     assert st["flags"] == 0 and 1 <= st["rebuilds"] < 40
+
+
+def test_skin_reuse_under_box_scaling(torch, L, orc, tmpdir_session):
+    """While the barostat scales the cell after every step, reused candidate
+    rows (skin test carried along with the box) give the oracle's per-bead
+    lists, and the same lists and bitwise the same forces as fresh rows."""
+    say("[nep] candidate reuse while the barostat scales the box")
+    from paper_2409_04430_amd.engine import NepPimd
+    w = configs.WORKLOADS["rocksalt4096"]
+    path = write_model(tmpdir_session, "skin_npt", w.model())
+    s = w.systems(P=4)[0]
+    baro = dict(p0=-10.0, beta=0.02, tau_p=600.0)
+    eng = NepPimd(path, s, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=0, skin=0.3,
+                  barostat=baro)
+    eng.nl.status(clear=True)
+    dev = torch.device("cuda")
+    P, N = s.P, s.N
+    box0 = np.asarray(eng.box, np.float64).copy()
+    rng = np.random.default_rng(12)
+    for r in range(3):
+        eng.run(10)
+        eng.nl.build(eng.pos, eng.box, eng.types)
+        la = eng.nl.to_host(eng.pos, eng.box, 160, 64)
+        ref = L.NeighborList(eng.model, P, N, *eng.caps)
+        ref.build(eng.pos, eng.box, eng.types)
+        assert ref.status()["flags"] == 0
+        lb = ref.to_host(eng.pos, eng.box, 160, 64)
+        for kind in ("radial", "angular"):
+            np.testing.assert_array_equal(la["cnt_" + kind], lb["cnt_" + kind])
+            valid = np.arange(la["nbr_" + kind].shape[1])[None, :, None] < la["cnt_" + kind][:, None, :]
+            np.testing.assert_array_equal(la["nbr_" + kind][valid], lb["nbr_" + kind][valid])
+        check_lists(orc, la, eng.pos.cpu().numpy(), np.asarray(eng.box, np.float64), eng.model.rc_radial,
+                    eng.model.rc_angular, beads=[r], atoms=rng.choice(N, 300, replace=False), types=s.types)
+        F1 = torch.zeros((P, N, 3), dtype=torch.float32, device=dev)
+        F2 = torch.zeros_like(F1)
+        E = torch.zeros(P, dtype=torch.float64, device=dev)
+        W = torch.zeros((P, 9), dtype=torch.float64, device=dev)
+        eng.ws.compute(eng.nl, eng.pos, eng.box, eng.types, E, F1, W)
+        eng.ws.compute(ref, eng.pos, eng.box, eng.types, E, F2, W)
+        torch.cuda.synchronize()
+        assert torch.equal(F1, F2)
+    st = eng.nl.status(clear=True)
+    rel = np.abs(np.asarray(eng.box) / box0 - 1.0).max()
+    say(f"  box moved by {rel:.2e} relative; rebuilds in 30 steps: {st['rebuilds']}")
+    assert rel > 1e-3
+    assert st["flags"] == 0 and st["rebuilds"] < 15
