@@ -71,6 +71,11 @@ def lib():
         L.or_bf16_round.restype = C.c_double
         L.or_bf16_round_array.argtypes = [dp, dp, C.c_int]
         L.or_model_round_w0_bf16.argtypes = [vp]
+        L.or_rdf_counts.argtypes = [C.c_int, C.c_int, dp, ip, C.c_int, dp, C.c_double, C.c_int,
+                                    C.POINTER(C.c_uint64)]
+        L.or_rdf_counts.restype = None
+        L.or_centroid.argtypes = [C.c_int, C.c_int, dp, dp]
+        L.or_centroid.restype = None
         L.or_observables.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp, dp, C.c_double, dp]
         L.or_observables.restype = None
         L.or_berendsen.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_int,
@@ -187,6 +192,44 @@ def neighbors(pos, box, rc: float, cap: int = 512):
     if mx > cap:
         raise RuntimeError(f"oracle: neighbour capacity {cap} < {mx}")
     return cnt, idx
+
+
+def rdf_counts(pos, types, box, rmax: float, nbins: int, n_species: int) -> np.ndarray:
+    """Pair histogram [S, S, nbins] (uint64) of the beads of pos [P, N, 3]: ordered pairs
+    of one bead, bin floor(r nbins / rmax), summed over beads."""
+    pos = _f64(pos)
+    P, N = pos.shape[:2]
+    t = _i32(types)
+    L = _f64(np.asarray(box, np.float64).reshape(-1)[[0, 4, 8]] if np.asarray(box).size == 9 else box)
+    out = np.zeros((n_species, n_species, nbins), np.uint64)
+    lib().or_rdf_counts(P, N, _d(pos), _i(t), int(n_species), _d(L), float(rmax), int(nbins),
+                        out.ctypes.data_as(C.POINTER(C.c_uint64)))
+    return out
+
+
+def rdf_normalise(counts, n_per_species, volume: float, rmax: float, frames: int = 1, P: int = 1):
+    """g_ab(r) from a pair histogram: counts / (frames P N_a rho_b shell volume), with
+    rho_b = (N_b - [a == b]) / V.  Returns (bin centres [nbins], g [S, S, nbins])."""
+    counts = np.asarray(counts, np.float64)
+    S, _, nb = counts.shape
+    edges = np.arange(nb + 1) * (rmax / nb)
+    shell = 4.0 / 3.0 * np.pi * (edges[1:] ** 3 - edges[:-1] ** 3)
+    g = np.zeros_like(counts)
+    for a in range(S):
+        for b in range(S):
+            rho = (n_per_species[b] - (1 if a == b else 0)) / volume
+            den = frames * P * n_per_species[a] * rho * shell
+            g[a, b] = counts[a, b] / den if n_per_species[a] and rho > 0 else 0.0
+    return 0.5 * (edges[1:] + edges[:-1]), g
+
+
+def centroid(x) -> np.ndarray:
+    """Bead mean of x [P, N, 3] (beads summed in order, then divided by P)."""
+    x = _f64(x)
+    P, N = x.shape[:2]
+    out = np.zeros((N, 3))
+    lib().or_centroid(P, N, _d(x), _d(out))
+    return out
 
 
 # --------------------------------------------------------- ring polymer ---

@@ -519,3 +519,41 @@ int or_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------ */
+/* Partial radial distribution functions (the paper's water analysis,  */
+/* Sec. III): pair histogram per species pair over every bead.         */
+/*                                                                      */
+/* counts[(a*S + b)*nbins + k] += number of ordered pairs (i of species a, */
+/* j != i of species b) in one bead with k = floor(r * nbins / rmax) <     */
+/* nbins, r = sqrt(|mic(r_j - r_i)|^2) in FP64 (minimum image as in mic()).*/
+/* Pairs of one bead only (the same imaginary-time slice); all P beads    */
+/* are summed.  pos [P][N][3], types [N] in 0..S-1, L[3].                 */
+/* ------------------------------------------------------------------ */
+void or_rdf_counts(int P, int N, const double *pos, const int *types, int S, const double *L, double rmax,
+                   int nbins, uint64_t *counts)
+{
+    const double inv = nbins / rmax;
+    for (int b = 0; b < P; ++b) {
+        const double *x = pos + (size_t)b * N * 3;
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j) {
+                if (j == i) continue;
+                double d[3], r2;
+                mic(x + 3 * i, x + 3 * j, L, d, &r2);
+                const double t = sqrt(r2) * inv;
+                if (t < nbins) counts[((size_t)types[i] * S + types[j]) * nbins + (int)t] += 1;
+            }
+    }
+}
+
+/* Centroid of a bead array: out[i][a] = (sum_j x[j][i][a]) / P, beads summed
+ * in order j = 0..P-1 (plain mean: unwrapped ring polymers). */
+void or_centroid(int P, int N, const double *x, double *out)
+{
+    for (size_t e = 0; e < (size_t)N * 3; ++e) {
+        double s = 0.0;
+        for (int j = 0; j < P; ++j) s += x[(size_t)j * N * 3 + e];
+        out[e] = s / P;
+    }
+}
