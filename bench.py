@@ -146,12 +146,14 @@ def cpu_baseline(w, model_path, system, nb_req: int):
 
 
 def npt_leg(args, torch, lib, w, model_path, s, NepPimd, nvt_ms: float):
-    """The same workload with the ring-polymer observables and the isotropic
-    Berendsen-like barostat after every step (Sec. II.A, II.D): step time, and
-    the observables and cell-scaling kernels against the HBM roofline."""
+    """The same workload with the ring-polymer observables, the partial RDF
+    histogram and the isotropic Berendsen-like barostat after every step
+    (Sec. II.A, II.D, Sec. III): step time, and those kernels against the HBM
+    roofline."""
     baro = dict(p0=0.0, beta=1.0 / 50.0, tau_p=500.0, anisotropic=False)
+    rmax = 0.9999 * w.hyper.rc_radial
     eng = NepPimd(model_path, s, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=0,
-                  obs_every=1, barostat=baro)
+                  obs_every=1, barostat=baro, rdf=dict(rmax=rmax, nbins=300, every=1))
     eng.run(5)
     eng.check()
     kernels = {}
@@ -189,8 +191,13 @@ def npt_leg(args, torch, lib, w, model_path, s, NepPimd, nvt_ms: float):
                                round(float(np.asarray(eng.box).reshape(-1)[0]), 6)],
            "kernels_us": {k: round(v, 2) for k, v in kernels.items()}}
     # HBM roofline: observables read pos (24 B) and F (12 B) per (atom, bead);
-    # the scaling reads and writes pos (48 B)
-    for name, per in (("observables", 36.0), ("barostat", 48.0)):
+    # the scaling reads and writes pos (48 B); the histogram reads the atom's
+    # position and its radial union list (index + bead mask, shared by the
+    # beads) once, the neighbours' positions from cache
+    lst = eng.nl.to_host()
+    nuni = float(lst["union_end_radial"][:, eng.model.n_species - 1].mean())
+    out["rdf"] = {"rmax": round(rmax, 6), "nbins": 300, "mean_union_radial": round(nuni, 2)}
+    for name, per in (("observables", 36.0), ("barostat", 48.0), ("rdf", 24.0 + 12.0 * nuni / s.P)):
         if name in kernels:
             gbs = per * units / (kernels[name] * 1e-6) / 1e9
             out[name + "_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS,

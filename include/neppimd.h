@@ -422,6 +422,33 @@ typedef struct pimd_barostat {
 int32_t pimd_berendsen(const pimd_ctx *ctx, double *pos, const double *obs, const pimd_barostat *params,
                        double *mu, hipStream_t stream);
 
+/* Bead mean of a ring-polymer array (positions of unwrapped ring polymers,
+ * or velocities, e.g. for velocity dumps of the centroid dynamics):
+ * out[i][a] = (sum_j x[j][i][a]) / P, beads summed in order.  x [P][N][3]
+ * dev float64, out [N][3] dev float64, out != x.  Errors:
+ * NEP_ERR_INVALID_ARG, NEP_ERR_HIP. */
+int32_t pimd_centroid(const pimd_ctx *ctx, const double *x, double *out, hipStream_t stream);
+
+/* Pair-distance histogram per species pair (the partial radial distribution
+ * functions of the water analysis, Sec. III), read off the radial union lists
+ * of the last neighbor_build on these positions: for every bead b and
+ * ordered pair (i, j != i) of that bead with r = |mic(r_j - r_i)| (FP64,
+ * per axis x - L rint(x / L), no contraction) and k = floor(r nbins / rmax)
+ * < nbins, hist[(type_i S + type_j) nbins + k] += 1.  hist [S][S][nbins] dev
+ * uint64 is accumulated, not cleared (so frames add up).  rmax must lie in
+ * (0, rc_radial (1 - 1e-9)] so that every counted pair is on the lists;
+ * S^2 nbins <= 16384.  One system per list.  g_ab(r) follows as
+ * hist / (frames P N_a rho_b shell volume), rho_b = (N_b - [a == b]) / V.
+ * Lists that overflowed (NEP_FLAG_NEIGHBOR_OVERFLOW) give incomplete counts.
+ * The first call on a list allocates a bead-minor copy of the positions
+ * (24 P N bytes) kept by the list.
+ * Errors: NEP_ERR_INVALID_ARG (sizes, rmax, nbins, box differing from the
+ * last build, lists not built), NEP_ERR_UNSUPPORTED (batched list,
+ * non-orthorhombic cell), NEP_ERR_HIP. */
+int32_t nep_rdf_accumulate(const nep_model *model, nep_nlist *nl, const double *pos, const double box[9],
+                           const int32_t *types, int32_t P, int32_t N, double rmax, int32_t nbins, uint64_t *hist,
+                           hipStream_t stream);
+
 /* ------------------------------------------------------------------ */
 /* Training (gradient of an energy / force / virial loss, Adam)        */
 /* ------------------------------------------------------------------ */

@@ -22,8 +22,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libneppimd.so")
 ARCH = os.environ.get("NEPPIMD_ARCH", "gfx950")
 
-SOURCES = ["core.hip", "nlist.hip", "nep.hip", "pimd.hip", "train.hip"]
-EXTRA = {"nlist.hip": ["-ffp-contract=off"]}
+SOURCES = ["core.hip", "nlist.hip", "nep.hip", "pimd.hip", "train.hip", "observe.hip"]
+EXTRA = {"nlist.hip": ["-ffp-contract=off"], "observe.hip": ["-ffp-contract=off"]}
 
 
 def hipcc() -> str:

@@ -81,7 +81,7 @@ void pack_positions(const double *pos, int P, int N, const int32_t *atom_sys, co
 static const char *kKernelNames[K_NUM] = {"fill", "pack", "centroid", "grid", "cell_count", "cell_scan", "cell_fill",
                                           "cell_sort", "candidates", "sort_rows", "reverse", "nlist",
                                           "materialize", "descriptor", "force_ang", "force", "reduce", "trpmd", "modes",
-                                          "observables", "barostat"};
+                                          "observables", "barostat", "rdf"};
 static std::atomic<int> g_prof_on{0};
 static std::atomic<int> g_prof_only{-1};   // -1: every kind
 static std::mutex g_prof_mu;
@@ -511,7 +511,7 @@ extern "C" void nep_nlist_destroy(nep_nlist *nl)
     if (!nl) return;
     for (void *p : {(void *)nl->geom, (void *)nl->atom_sys, (void *)nl->cell_sys, (void *)nl->cen, (void *)nl->spr, (void *)nl->cen_ref, (void *)nl->candR, (void *)nl->lenR, (void *)nl->offR,
                     (void *)nl->candA, (void *)nl->lenA, (void *)nl->offA, (void *)nl->revA, (void *)nl->uniR,
-                    (void *)nl->umR, (void *)nl->umA, (void *)nl->uendR, (void *)nl->uniA, (void *)nl->uendA, (void *)nl->pairbuf, (void *)nl->pos4,
+                    (void *)nl->umR, (void *)nl->umA, (void *)nl->uendR, (void *)nl->uniA, (void *)nl->uendA, (void *)nl->pairbuf, (void *)nl->pos4, (void *)nl->posT,
                     (void *)nl->cell_cnt, (void *)nl->cell_start, (void *)nl->cell_atoms, (void *)nl->grid,
                     (void *)nl->status})
         if (p) (void)hipFree(p);

@@ -97,10 +97,11 @@ struct nep_nlist {
     // Angular pair terms dU_j/dr_ji at the receiving atom i's angular slot of j: [N][capA][P] xyz + pad.
     float *pairbuf = nullptr;
     float *pos4 = nullptr;        // [N][P][4] packed positions of the last build (bead-minor)
+    double *posT = nullptr;       // [N][P][3] bead-minor FP64 positions (pair histograms; allocated on first use)
     // Centroid cell list (grown on demand): cell_cnt [ncell], cell_start [ncell+1], cell_atoms [N].
     int ncell_alloc = 0, ncell_total = 0;
     int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_atoms = nullptr;
-    uint32_t *grid = nullptr;     // device-chosen grid record: 16 global words + 4 per system
+    uint32_t *grid = nullptr;     // device-chosen grid record: 16 global words + kDevSysWords per system
     uint32_t *status = nullptr;   // [0] flags, [1] max radial union, [2] max angular union,
                                   // [3] max radial candidates, [4] spread (float bits), [5] rebuilds,
                                   // [6] max angular candidates
@@ -296,7 +297,7 @@ int32_t update_geometry(const nep_model *m, nep_nlist *nl, const double *boxes, 
 enum KernelId {
     K_FILL = 0, K_PACK, K_CENTROID, K_GRID, K_CELL_COUNT, K_CELL_SCAN, K_CELL_FILL, K_CELL_SORT, K_CANDIDATES,
     K_SORT_ROWS, K_REVERSE, K_NLIST, K_MATERIALIZE,
-    K_DESCRIPTOR, K_FORCE_ANG, K_FORCE, K_REDUCE, K_TRPMD, K_MODES, K_OBS, K_BARO, K_NUM
+    K_DESCRIPTOR, K_FORCE_ANG, K_FORCE, K_REDUCE, K_TRPMD, K_MODES, K_OBS, K_BARO, K_RDF, K_NUM
 };
 struct ProfScope {
     int id;

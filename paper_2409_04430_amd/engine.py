@@ -7,8 +7,11 @@ half kick, free ring-polymer step, forces, half kick, thermostat; the two
 integrator halves around consecutive force evaluations run as one fused
 launch.  Optional: the ring-polymer observables (centroid virial kinetic
 energy, virial and pressure tensors) recorded on the device after the
-closing half of every k-th step, and a Berendsen-like barostat after the
-closing half of every step (Sec. II.D); both split the fused launch.
+closing half of every k-th step, a Berendsen-like barostat after the
+closing half of every step (Sec. II.D), and centroid velocities dumped
+every k-th step (these split the fused launch); partial radial
+distribution functions accumulated on the device from the neighbour lists
+of every k-th force call.
 """
 from __future__ import annotations
 
@@ -27,6 +30,22 @@ def default_capacity(rc: float, density: float, n_species: int, slack: float = 1
     return int(math.ceil(n * slack)) + 8
 
 
+def rdf_normalise(counts, n_per_species, volume: float, rmax: float, frames: int, P: int):
+    """g_ab(r_k) = counts_ab[k] / (frames P N_a rho_b V_k), rho_b = (N_b - [a == b]) / V,
+    V_k the volume of shell k of width rmax / nbins; bins of an absent species are 0."""
+    c = np.asarray(counts, np.float64)
+    S, nb = c.shape[0], c.shape[2]
+    edges = np.linspace(0.0, rmax, nb + 1)
+    shell = (4.0 * np.pi / 3.0) * np.diff(edges ** 3)
+    g = np.zeros_like(c)
+    for a in range(S):
+        for b in range(S):
+            pairs = n_per_species[a] * (n_per_species[b] - (a == b))
+            if pairs > 0 and frames > 0:
+                g[a, b] = c[a, b] * volume / (frames * P * pairs * shell)
+    return 0.5 * (edges[1:] + edges[:-1]), g
+
+
 class NepPimd:
     """NEP forces for P beads of one periodic system, or of a batch of
     independent systems of uneven size, plus the ring-polymer integrator.
@@ -38,7 +57,7 @@ class NepPimd:
     def __init__(self, model_path: str, system, *, dt: float, T: float, tau: float = 100.0,
                  mode: str = "trpmd", seed: int = 0, caps: Optional[tuple] = None, check_every: int = 50,
                  want_atom: bool = False, skin: float = 0.5, autotune: bool = False, obs_every: int = 0,
-                 barostat: Optional[dict] = None):
+                 barostat: Optional[dict] = None, rdf: Optional[dict] = None, dump_every: int = 0):
         import torch
         self.torch = torch
         dev = torch.device("cuda")
@@ -90,6 +109,19 @@ class NepPimd:
             raise ValueError("observables and the barostat need a single system")
         self.obs = torch.zeros(lib.OBS_COUNT, dtype=torch.float64, device=dev)
         self.mu = torch.ones(3, dtype=torch.float64, device=dev)
+        # partial RDFs: rdf = dict(rmax=A, nbins=n, every=k)
+        self.rdf_cfg = dict(rdf) if rdf else None
+        self.rdf_frames = 0
+        self.rdf_hist = None
+        if self.rdf_cfg:
+            if self.batched:
+                raise ValueError("the radial distribution functions need a single system")
+            S_ = self.model.n_species
+            self.rdf_hist = torch.zeros((S_, S_, int(self.rdf_cfg["nbins"])), dtype=torch.int64, device=dev)
+        self.dump_every = int(dump_every)
+        self.dump_log = []
+        if self.dump_every and self.batched:
+            raise ValueError("velocity dumps need a single system")
         self._fit_capacity()
         self.tile = None
         if autotune:
@@ -136,8 +168,22 @@ class NepPimd:
         self.pimd.step(self.pos, self.vel, self.F, self.step_no, lib.PRE)
         self.started = True
 
+    def _split(self) -> bool:
+        return bool(self.obs_every or self.baro or self.dump_every)
+
+    def _after_forces(self, n: int):
+        """Partial RDF counts from the lists of step n's force call."""
+        c = self.rdf_cfg
+        if c and (n + 1) % int(c.get("every", 1)) == 0:
+            self.nl.rdf_accumulate(self.pos, self.box, self.types, self.rdf_hist, c["rmax"])
+            self.rdf_frames += 1
+
     def _after_post(self, n: int):
-        """Observables and pressure control between the closing half of step n and the next step."""
+        """Observables, velocity dump and pressure control between the closing half of step n and the next step."""
+        if self.dump_every and (n + 1) % self.dump_every == 0:
+            out = self.torch.empty((self.N, 3), dtype=self.torch.float64, device=self.pos.device)
+            self.pimd.centroid(self.vel, out)
+            self.dump_log.append((n, out))
         rec = self.obs_every and (n + 1) % self.obs_every == 0
         if not (rec or self.baro):
             return
@@ -163,7 +209,8 @@ class NepPimd:
                 self.start()
             self.forces()
             n = self.step_no
-            if self.obs_every or self.baro:
+            self._after_forces(n)
+            if self._split():
                 self.pimd.step(self.pos, self.vel, self.F, n, lib.POST)
                 self._after_post(n)
                 self.pimd.step(self.pos, self.vel, self.F, n + 1, lib.PRE)
@@ -185,8 +232,8 @@ class NepPimd:
         must stay fixed while the graph is in use; `release()` returns to
         eager launches."""
         t = self.torch
-        if self.obs_every or self.baro:
-            raise ValueError("capture: observables and the barostat run eagerly")
+        if self._split() or self.rdf_cfg:
+            raise ValueError("capture: observables, dumps, RDFs and the barostat run eagerly")
         if not self.started:
             self.start()
         # one eager step first so that every lazy allocation has happened
@@ -211,10 +258,33 @@ class NepPimd:
         if not self.started:
             self.start()
         self.forces()
+        self._after_forces(self.step_no)
         self.pimd.step(self.pos, self.vel, self.F, self.step_no, lib.POST)
         self._after_post(self.step_no)
         self.started = False
         self.step_no += 1
+
+    def rdf(self):
+        """Partial radial distribution functions from the accumulated counts
+        (synchronises): bin centres [nbins] and g [S, S, nbins], normalised by
+        frames x P x N_a x (N_b - [a == b]) / V x shell volume, V the current
+        cell volume.  Also returns the raw counts."""
+        if not self.rdf_cfg:
+            raise ValueError("the engine was created without rdf=")
+        counts = self.rdf_hist.cpu().numpy().astype(np.uint64)
+        types = self.types.cpu().numpy()
+        n_sp = [int((types == a).sum()) for a in range(self.model.n_species)]
+        box = np.asarray(self.box, np.float64).reshape(-1)
+        vol = float(np.prod(box[[0, 4, 8]] if box.size == 9 else box))
+        r, g = rdf_normalise(counts, n_sp, vol, float(self.rdf_cfg["rmax"]), self.rdf_frames, self.P)
+        return r, g, counts
+
+    def centroid_velocities(self):
+        """Dumped centroid velocities (synchronises): steps [n] and [n, N, 3] (A/fs)."""
+        if not self.dump_log:
+            return np.zeros(0, np.int64), np.zeros((0, self.N, 3))
+        steps = np.array([n for n, _ in self.dump_log], np.int64)
+        return steps, self.torch.stack([v for _, v in self.dump_log]).cpu().numpy()
 
     def observables_history(self):
         """Recorded observables (synchronises): steps [n] and the vectors [n, OBS_COUNT]."""

@@ -106,6 +106,9 @@ _sig = {
     "trpmd_step_dev": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "pimd_observables": (_i32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp, _vp]),
     "pimd_berendsen": (_i32, [_vp, _vp, _vp, C.POINTER(PimdBarostat), _vp, _vp]),
+    "pimd_centroid": (_i32, [_vp, _vp, _vp, _vp]),
+    "nep_rdf_accumulate": (_i32, [_vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, C.c_double, _i32, _vp,
+                                  _vp]),
     "nep_nlist_set_skin": (_i32, [_vp, C.c_double]),
     "nep_nlist_invalidate": (_i32, [_vp]),
     "nep_ws_set_tile": (_i32, [_vp, _i32]),
@@ -279,6 +282,18 @@ class NeighborList:
                                            _ptr(pos, _torch().float64, (self.P, self.N, 3), "pos"),
                                            _boxes(box, self.nsys), _ptr(types, _torch().int32, (self.N,), "types"),
                                            self.P, self.N, _stream()))
+
+    def rdf_accumulate(self, pos, box, types, hist, rmax: float):
+        """nep_rdf_accumulate: add this configuration's same-bead pair distances to
+        hist [S, S, nbins] (int64 device tensor holding uint64 counts)."""
+        t = _torch()
+        S = self.model.n_species
+        if hist.dim() != 3 or hist.shape[0] != S or hist.shape[1] != S:
+            raise ValueError(f"hist must have shape [{S}, {S}, nbins]")
+        _check(_lib.nep_rdf_accumulate(self.model.handle, self._h, _ptr(pos, t.float64, (self.P, self.N, 3), "pos"),
+                                       _box9(box), _ptr(types, t.int32, (self.N,), "types"), self.P, self.N,
+                                       float(rmax), int(hist.shape[2]), _ptr(hist, t.int64, None, "hist"),
+                                       _stream()))
 
     def status(self, clear: bool = True) -> dict:
         """Sticky list status (synchronises the stream)."""
@@ -492,6 +507,12 @@ class Pimd:
         _check(_lib.pimd_berendsen(self._h, _ptr(pos, t.float64, (self.P, self.N, 3), "pos"),
                                    _ptr(obs, t.float64, (OBS_COUNT,), "obs"), C.byref(prm),
                                    _ptr(mu, t.float64, (3,), "mu"), _stream()))
+
+    def centroid(self, x, out):
+        """pimd_centroid: bead mean of x [P, N, 3] into out [N, 3] (float64, device)."""
+        t = _torch()
+        _check(_lib.pimd_centroid(self._h, _ptr(x, t.float64, (self.P, self.N, 3), "x"),
+                                  _ptr(out, t.float64, (self.N, 3), "out"), _stream()))
 
     def __del__(self):
         h = getattr(self, "_h", None)
