@@ -76,6 +76,8 @@ def lib():
         L.or_rdf_counts.restype = None
         L.or_centroid.argtypes = [C.c_int, C.c_int, dp, dp]
         L.or_centroid.restype = None
+        L.or_cell_volume.argtypes = [dp]
+        L.or_cell_volume.restype = C.c_double
         L.or_observables.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp, dp, C.c_double, dp]
         L.or_observables.restype = None
         L.or_berendsen.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_int,
@@ -95,6 +97,14 @@ def _i(a):
 
 def _f64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _cell9(box) -> np.ndarray:
+    """Cell edge vectors as the rows of a row-major [9] array; [3] means an orthorhombic cell."""
+    b = np.asarray(box, np.float64)
+    if b.shape == (3,):
+        b = np.diag(b)
+    return np.ascontiguousarray(b.reshape(9), dtype=np.float64)
 
 
 def _i32(a):
@@ -139,7 +149,7 @@ class Model:
         """Energy, forces, virial of one configuration pos [N,3].
 
         Returns dict(E, F [N,3], W [3,3], U [N], Wat [N,3,3], q [N,D]?)."""
-        pos = _f64(pos); types = _i32(types); box = _f64(box)
+        pos = _f64(pos); types = _i32(types); box = _cell9(box)
         N = len(pos)
         E = np.zeros(1); F = np.zeros((N, 3)); W = np.zeros(9)
         U = np.zeros(N); Wat = np.zeros((N, 9))
@@ -155,7 +165,7 @@ class Model:
 
     def beads(self, pos, types, box, cap: int = 512):
         """All beads: pos [P,N,3] -> E [P], F [P,N,3], W [P,3,3], U [P,N]."""
-        pos = _f64(pos); types = _i32(types); box = _f64(box)
+        pos = _f64(pos); types = _i32(types); box = _cell9(box)
         P, N = pos.shape[:2]
         E = np.zeros(P); F = np.zeros((P, N, 3)); W = np.zeros((P, 9)); U = np.zeros((P, N))
         Wat = np.zeros((P, N, 9))
@@ -184,7 +194,7 @@ def neighbors(pos, box, rc: float, cap: int = 512):
     """Brute-force minimum-image neighbour lists of one configuration.
 
     Returns (cnt [N], idx [N,cap] with ascending indices, -1 padded)."""
-    pos = _f64(pos); box = _f64(box)
+    pos = _f64(pos); box = _cell9(box)
     N = len(pos)
     cnt = np.zeros(N, np.int32)
     idx = np.full((N, cap), -1, np.int32)
@@ -200,7 +210,7 @@ def rdf_counts(pos, types, box, rmax: float, nbins: int, n_species: int) -> np.n
     pos = _f64(pos)
     P, N = pos.shape[:2]
     t = _i32(types)
-    L = _f64(np.asarray(box, np.float64).reshape(-1)[[0, 4, 8]] if np.asarray(box).size == 9 else box)
+    L = _cell9(box)
     out = np.zeros((n_species, n_species, nbins), np.uint64)
     lib().or_rdf_counts(P, N, _d(pos), _i(t), int(n_species), _d(L), float(rmax), int(nbins),
                         out.ctypes.data_as(C.POINTER(C.c_uint64)))
@@ -315,7 +325,7 @@ def observables(pos, F, W_bead, E_bead, box, T: float) -> dict:
     Epot (eV), K (eV), W [3,3] (eV), Ptens [3,3] (GPa), p (GPa)."""
     pos = _f64(pos); F = _f64(F); Wb = _f64(W_bead).reshape(-1, 9); Eb = _f64(E_bead).reshape(-1)
     P, N = pos.shape[:2]
-    L = _f64(np.asarray(box, np.float64).reshape(-1)[[0, 4, 8]] if np.asarray(box).size == 9 else box)
+    L = _cell9(box)
     out = np.zeros(OBS_COUNT)
     lib().or_observables(P, N, _d(pos), _d(F), _d(Wb), _d(Eb), _d(L), float(T), _d(out))
     return {"raw": out, "Epot": out[OBS_EPOT], "K": out[OBS_K], "W": out[OBS_W:OBS_W + 9].reshape(3, 3),
@@ -323,17 +333,22 @@ def observables(pos, F, W_bead, E_bead, box, T: float) -> dict:
 
 
 def berendsen(pos, box, ptens, p0, *, beta: float, tau_p: float, dt: float, aniso: bool):
-    """Berendsen-like pressure control (Sec. II.D): scales pos [P,N,3] in place; returns (new edges [3], mu [3])."""
+    """Berendsen-like pressure control (Sec. II.D): scales pos [P,N,3] in place; returns (new cell in the
+    shape of box: edge lengths [3] or edge vectors [3,3], mu [3])."""
     assert pos.dtype == np.float64 and pos.flags.c_contiguous
     P, N = pos.shape[:2]
-    L = _f64(np.array(np.asarray(box, np.float64).reshape(-1)[[0, 4, 8]] if np.asarray(box).size == 9 else box,
-                      np.float64))
+    shape3 = np.asarray(box).shape == (3,)
+    L = _cell9(box).copy()
     pt = _f64(np.asarray(ptens, np.float64).reshape(9))
     p0 = _f64(np.broadcast_to(np.asarray(p0, np.float64), (3,)).copy())
     mu = np.zeros(3)
     lib().or_berendsen(P, N, _d(pos), _d(L), _d(pt), _d(p0), float(beta), float(tau_p), float(dt), int(aniso),
                        _d(mu))
-    return L, mu
+    return (L[[0, 4, 8]].copy() if shape3 else L.reshape(3, 3)), mu
+
+
+def cell_volume(box) -> float:
+    return float(lib().or_cell_volume(_d(_cell9(box))))
 
 
 def train_loss(out: dict, ref: dict, lambdas, N: int):

@@ -182,19 +182,71 @@ void or_model_round_w0_bf16(or_model *m)
 /* geometry                                                            */
 /* ------------------------------------------------------------------ */
 
-/* Minimum-image difference d = r_j - r_i and its squared length. */
-static void mic(const double *ri, const double *rj, const double *L, double *d, double *r2)
+/* Periodic cells are given by their three edge vectors as the rows of
+ * box[9] (row-major H: r = s H with fractional coordinates s).  A cell is
+ * orthorhombic when every off-diagonal entry is zero. */
+static int cell_is_orthorhombic(const double *box)
 {
-    for (int a = 0; a < 3; ++a) {
-        double x = rj[a] - ri[a];
-        double k = rint(x / L[a]);
-        double s = L[a] * k;
-        d[a] = x - s;
+    return box[1] == 0.0 && box[2] == 0.0 && box[3] == 0.0 && box[5] == 0.0 && box[6] == 0.0 && box[7] == 0.0;
+}
+
+/* G = H^-1 from the cofactors: row vectors map to fractional coordinates
+ * as s = x G. */
+static void cell_inverse(const double *H, double *G)
+{
+    const double c00 = H[4] * H[8] - H[5] * H[7], c01 = H[5] * H[6] - H[3] * H[8], c02 = H[3] * H[7] - H[4] * H[6];
+    const double det = H[0] * c00 + H[1] * c01 + H[2] * c02;
+    G[0] = c00 / det;
+    G[3] = c01 / det;
+    G[6] = c02 / det;
+    G[1] = (H[2] * H[7] - H[1] * H[8]) / det;
+    G[4] = (H[0] * H[8] - H[2] * H[6]) / det;
+    G[7] = (H[1] * H[6] - H[0] * H[7]) / det;
+    G[2] = (H[1] * H[5] - H[2] * H[4]) / det;
+    G[5] = (H[2] * H[3] - H[0] * H[5]) / det;
+    G[8] = (H[0] * H[4] - H[1] * H[3]) / det;
+}
+
+/* Minimum-image difference d = r_j - r_i and its squared length.
+ * Orthorhombic cells: per axis x - L rint(x / L).  Other cells: the
+ * fractional difference s = x G is reduced by rint per axis and mapped back,
+ * d = (s - rint(s)) H; this is the nearest image whenever it is shorter than
+ * half the smallest distance between opposite faces of the cell. */
+static void mic(const double *ri, const double *rj, const double *box, double *d, double *r2)
+{
+    if (cell_is_orthorhombic(box)) {
+        for (int a = 0; a < 3; ++a) {
+            double x = rj[a] - ri[a];
+            double L = box[4 * a];
+            double k = rint(x / L);
+            double s = L * k;
+            d[a] = x - s;
+        }
+    } else {
+        double G[9], x[3], f[3];
+        cell_inverse(box, G);
+        for (int a = 0; a < 3; ++a) x[a] = rj[a] - ri[a];
+        for (int c = 0; c < 3; ++c) {
+            double s = (x[0] * G[c] + x[1] * G[3 + c]) + x[2] * G[6 + c];
+            f[c] = s - rint(s);
+        }
+        for (int a = 0; a < 3; ++a) d[a] = (f[0] * box[a] + f[1] * box[3 + a]) + f[2] * box[6 + a];
     }
     double xx = d[0] * d[0];
     double yy = d[1] * d[1];
     double zz = d[2] * d[2];
     *r2 = (xx + yy) + zz;
+}
+
+/* mic() for the other oracle source. */
+void or_mic(const double *ri, const double *rj, const double *box, double *d, double *r2) { mic(ri, rj, box, d, r2); }
+
+/* Volume of the cell (the determinant of H). */
+double or_cell_volume(const double *box)
+{
+    const double c00 = box[4] * box[8] - box[5] * box[7], c01 = box[5] * box[6] - box[3] * box[8],
+                 c02 = box[3] * box[7] - box[4] * box[6];
+    return box[0] * c00 + box[1] * c01 + box[2] * c02;
 }
 
 /* Brute-force neighbour list of one configuration: every j != i with
@@ -438,7 +490,7 @@ static void atom_eval(const or_model *m, int i, const double *pos, const int *ty
 /* ------------------------------------------------------------------ */
 
 /* NEP energy, forces and virial of one configuration (one bead).
- * pos [N,3]; box [3] orthorhombic lengths.  Outputs: E (total), F [N,3],
+ * pos [N,3]; box [9] cell edge vectors as rows.  Outputs: E (total), F [N,3],
  * W [9] (row-major W_ab), optional U [N], Wat [N,9], q [N,D].
  * cap: neighbour-list capacity per atom.  Returns 0, or 3 if cap is too
  * small (the call is then incomplete). */
@@ -528,9 +580,9 @@ int or_num_threads(void)
 /* j != i of species b) in one bead with k = floor(r * nbins / rmax) <     */
 /* nbins, r = sqrt(|mic(r_j - r_i)|^2) in FP64 (minimum image as in mic()).*/
 /* Pairs of one bead only (the same imaginary-time slice); all P beads    */
-/* are summed.  pos [P][N][3], types [N] in 0..S-1, L[3].                 */
+/* are summed.  pos [P][N][3], types [N] in 0..S-1, box [9] (rows: edges). */
 /* ------------------------------------------------------------------ */
-void or_rdf_counts(int P, int N, const double *pos, const int *types, int S, const double *L, double rmax,
+void or_rdf_counts(int P, int N, const double *pos, const int *types, int S, const double *box, double rmax,
                    int nbins, uint64_t *counts)
 {
     const double inv = nbins / rmax;
@@ -540,7 +592,7 @@ void or_rdf_counts(int P, int N, const double *pos, const int *types, int S, con
             for (int j = 0; j < N; ++j) {
                 if (j == i) continue;
                 double d[3], r2;
-                mic(x + 3 * i, x + 3 * j, L, d, &r2);
+                mic(x + 3 * i, x + 3 * j, box, d, &r2);
                 const double t = sqrt(r2) * inv;
                 if (t < nbins) counts[((size_t)types[i] * S + types[j]) * nbins + (int)t] += 1;
             }

@@ -311,32 +311,34 @@ void or_cayley_coeffs(int P, double T, double dt, double *out)
 /* 1 eV / A^3 in GPa */
 static double ev_a3_gpa(void) { return 1.602176634e-19 / 1e-30 / 1e9; }
 
-static double mic1(double d, double L) { return d - L * nearbyint(d / L); }
+/* minimum image and cell volume of the NEP oracle (box [9]: edge vectors as rows) */
+void or_mic(const double *ri, const double *rj, const double *box, double *d, double *r2);
+double or_cell_volume(const double *box);
 
 /* out[0]  potential energy, mean of E_bead over the beads (eV)
  * out[1]  kinetic energy K = 3/2 N kB T - 1/2 sum_i (1/P) sum_j dr_j . F_j (eV)
  * out[2..10]  W_ab = -sum_i (1/P) sum_j dr_j,a F_j,b + (1/P) sum_j W_bead[j][ab] (eV)
  * out[11..19] pressure tensor (N kB T delta_ab + W_ab) / V (GPa)
  * out[20] scalar pressure tr / 3 (GPa)
- * pos [P][N][3], F [P][N][3] (eV/A), W_bead [P][9], E_bead [P], L[3] (A). */
+ * pos [P][N][3], F [P][N][3] (eV/A), W_bead [P][9], E_bead [P], box [9] (A,
+ * edge vectors as rows; V its determinant). */
 void or_observables(int P, int N, const double *pos, const double *F, const double *W_bead, const double *E_bead,
-                    const double *L, double T, double *out)
+                    const double *box, double T, double *out)
 {
     double Wcv[9] = {0};
     for (int i = 0; i < N; ++i) {
+        const double *r1 = pos + (size_t)i * 3;
         double rc[3] = {0, 0, 0};
-        for (int j = 0; j < P; ++j)
-            for (int a = 0; a < 3; ++a) {
-                const double r1 = pos[(size_t)i * 3 + a];
-                rc[a] += r1 + mic1(pos[((size_t)j * N + i) * 3 + a] - r1, L[a]);
-            }
+        for (int j = 0; j < P; ++j) {
+            double d[3], r2;
+            or_mic(r1, pos + ((size_t)j * N + i) * 3, box, d, &r2);
+            for (int a = 0; a < 3; ++a) rc[a] += r1[a] + d[a];
+        }
         for (int a = 0; a < 3; ++a) rc[a] /= P;
         for (int j = 0; j < P; ++j) {
-            double dr[3];
-            for (int a = 0; a < 3; ++a) {
-                const double r1 = pos[(size_t)i * 3 + a];
-                dr[a] = r1 + mic1(pos[((size_t)j * N + i) * 3 + a] - r1, L[a]) - rc[a];
-            }
+            double d[3], r2, dr[3];
+            or_mic(r1, pos + ((size_t)j * N + i) * 3, box, d, &r2);
+            for (int a = 0; a < 3; ++a) dr[a] = r1[a] + d[a] - rc[a];
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b) Wcv[a * 3 + b] += dr[a] * F[((size_t)j * N + i) * 3 + b];
         }
@@ -346,7 +348,7 @@ void or_observables(int P, int N, const double *pos, const double *F, const doub
         Epot += E_bead[j];
         for (int e = 0; e < 9; ++e) Wpot[e] += W_bead[j * 9 + e];
     }
-    const double NkT = N * OR_KB * T, V = L[0] * L[1] * L[2];
+    const double NkT = N * OR_KB * T, V = or_cell_volume(box);
     out[0] = Epot / P;
     out[1] = 1.5 * NkT - 0.5 * (Wcv[0] + Wcv[4] + Wcv[8]) / P;
     for (int e = 0; e < 9; ++e) {
@@ -357,8 +359,9 @@ void or_observables(int P, int N, const double *pos, const double *F, const doub
 }
 
 /* Berendsen-like scaling: mu[3] from the pressure tensor ptens[9] (GPa), then
- * pos [P][N][3] and L[3] scaled in place. */
-void or_berendsen(int P, int N, double *pos, double *L, const double *ptens, const double *p0, double beta,
+ * every Cartesian coordinate a of pos [P][N][3] and of the cell's edge
+ * vectors box [9] (rows) multiplied by mu[a], in place. */
+void or_berendsen(int P, int N, double *pos, double *box, const double *ptens, const double *p0, double beta,
                   double tau_p, double dt, int aniso, double *mu)
 {
     const double p_iso = (ptens[0] + ptens[4] + ptens[8]) / 3.0;
@@ -368,5 +371,6 @@ void or_berendsen(int P, int N, double *pos, double *L, const double *ptens, con
     }
     for (size_t e = 0; e < (size_t)P * N; ++e)
         for (int a = 0; a < 3; ++a) pos[e * 3 + a] *= mu[a];
-    for (int a = 0; a < 3; ++a) L[a] *= mu[a];
+    for (int r = 0; r < 3; ++r)
+        for (int a = 0; a < 3; ++a) box[3 * r + a] *= mu[a];
 }
