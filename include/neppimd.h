@@ -37,8 +37,13 @@
  *              (dU_i/dr_ij')^b, row-major (a, b).
  *   types:     [N] int32, species index 0..n_species-1 (atoms grouped by
  *              species run fastest).
- *   box:       host double[9], cell row vectors a, b, c; only orthorhombic
- *              cells are supported (off-diagonal entries must be zero).
+ *   box:       host double[9], the cell's edge vectors a, b, c as rows (a
+ *              point is r = s H with fractional s); right-handed (det > 0).
+ *              Orthorhombic cells (zero off-diagonal entries) take per-axis
+ *              minimum images; general (triclinic) cells reduce the
+ *              fractional difference s = d H^-1 by rint per axis and map it
+ *              back, which is the nearest image for every pair closer than
+ *              half the smallest distance between opposite faces.
  */
 #ifndef NEPPIMD_H
 #define NEPPIMD_H
@@ -152,7 +157,8 @@ void nep_nlist_destroy(nep_nlist *nl);
  * neighbour kernels look up each atom's system, and the force kernels take
  * tiles (an atom range of one system) so that per-system sums need no
  * atomics.  The single-system calls are the case nsys = 1.  A box change
- * re-uploads the geometry with a synchronous copy (not capturable).
+ * re-uploads the geometry with a synchronous copy (not capturable); a
+ * changed general (triclinic) cell also rebuilds the candidate rows.
  * Errors as the single-system calls. */
 int32_t nep_nlist_create_batched(const nep_model *model, int32_t P, int32_t nsys, const int32_t *offsets,
                                  int32_t cap_radial, int32_t cap_angular, nep_nlist **out);
@@ -162,9 +168,11 @@ int32_t neighbor_build_batched(const nep_model *model, nep_nlist *nl, const doub
 /* Neighbour sets for every bead b and atom i: the atoms i' != i with
  * |mic(r_i' - r_i)|^2 < rc^2, for the radial and the angular cutoff (Sec.
  * II.A: periodic boundary conditions).  The minimum image of d = r_i' - r_i
- * is d - L rint(d / L) per axis and the test is (dx*dx + dy*dy) + dz*dz <
- * rc*rc in IEEE FP64 without contraction, so the sets are exactly those of
- * a brute-force search; the force path takes the same decision on packed
+ * is d - L rint(d / L) per axis (orthorhombic cells) or (f - rint(f)) H with
+ * f_c = (d_x G_xc + d_y G_yc) + d_z G_zc, G = H^-1, H the cell's edge vectors
+ * as rows (general cells), and the test is (dx*dx + dy*dy) + dz*dz < rc*rc
+ * in IEEE FP64 without contraction, so the sets are exactly those of a
+ * brute-force search; the force path takes the same decision on packed
  * FP32 pair vectors and falls back to the FP64 test near the cutoff.
  * This call builds what the sets are drawn from: per atom, candidate rows
  * shared by all beads from one cell-list search over the ring-polymer
@@ -174,9 +182,10 @@ int32_t neighbor_build_batched(const nep_model *model, nep_nlist *nl, const doub
  * and per call the "union" lists: the candidates inside the cutoff for at
  * least one bead.  Positions must keep the P beads of an atom in one
  * periodic image (unwrapped ring polymers).  pos [P][N][3] dev, types [N]
- * dev, box host[9].  Errors: NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED
- * (non-orthorhombic box), NEP_ERR_BOX_TOO_SMALL (an edge < 2 rc_radial, or
- * too close to it for the packed positions: L/2 - rc must exceed 2 L/1023),
+ * dev, box host[9].  Errors: NEP_ERR_INVALID_ARG (also a singular,
+ * left-handed or non-finite cell), NEP_ERR_BOX_TOO_SMALL (two opposite faces
+ * closer than 2 rc, rc the larger cutoff, or too close to it for the packed
+ * positions: w/2 - rc must exceed 2 w/1023, w the face distance),
  * NEP_ERR_HIP, NEP_ERR_NOMEM.  A candidate row longer than its capacity
  * sets NEP_FLAG_NEIGHBOR_OVERFLOW (the row is then truncated and the
  * results of nep_compute are not valid). */
@@ -393,12 +402,12 @@ enum pimd_obs_index {
  *   pressure tensor = (N kB T 1 + W) / V,
  * T the context's physical temperature.  pos, F [P][N][3] dev (float64,
  * float32), W_bead [P][9] and E_bead [P] dev float64 (the per-bead virial
- * and energy of nep_compute), box host [9] (orthorhombic), out
+ * and energy of nep_compute), box host [9] (V its determinant), out
  * [PIMD_OBS_COUNT] dev float64, written on the stream (pos and F may be
  * null when N = 0).  The partial sums
  * live in the context: calls on one context must not overlap.  The sum
  * order is fixed, so results are bitwise reproducible.  Errors:
- * NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED (non-orthorhombic cell),
+ * NEP_ERR_INVALID_ARG (also a singular or left-handed cell),
  * NEP_ERR_HIP. */
 int32_t pimd_observables(const pimd_ctx *ctx, const double *pos, const float *F, const double *W_bead,
                          const double *E_bead, const double box[9], double *out, hipStream_t stream);
@@ -433,7 +442,7 @@ int32_t pimd_centroid(const pimd_ctx *ctx, const double *x, double *out, hipStre
  * functions of the water analysis, Sec. III), read off the radial union lists
  * of the last neighbor_build on these positions: for every bead b and
  * ordered pair (i, j != i) of that bead with r = |mic(r_j - r_i)| (FP64,
- * per axis x - L rint(x / L), no contraction) and k = floor(r nbins / rmax)
+ * the minimum image of the list test, no contraction) and k = floor(r nbins / rmax)
  * < nbins, hist[(type_i S + type_j) nbins + k] += 1.  hist [S][S][nbins] dev
  * uint64 is accumulated, not cleared (so frames add up).  rmax must lie in
  * (0, rc_radial (1 - 1e-9)] so that every counted pair is on the lists;
@@ -443,8 +452,8 @@ int32_t pimd_centroid(const pimd_ctx *ctx, const double *x, double *out, hipStre
  * The first call on a list allocates a bead-minor copy of the positions
  * (24 P N bytes) kept by the list.
  * Errors: NEP_ERR_INVALID_ARG (sizes, rmax, nbins, box differing from the
- * last build, lists not built), NEP_ERR_UNSUPPORTED (batched list,
- * non-orthorhombic cell), NEP_ERR_HIP. */
+ * last build, lists not built), NEP_ERR_UNSUPPORTED (batched list),
+ * NEP_ERR_HIP. */
 int32_t nep_rdf_accumulate(const nep_model *model, nep_nlist *nl, const double *pos, const double box[9],
                            const int32_t *types, int32_t P, int32_t N, double rmax, int32_t nbins, uint64_t *hist,
                            hipStream_t stream);

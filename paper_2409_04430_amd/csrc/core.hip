@@ -34,6 +34,65 @@ bool box_lengths(const double box[9], double L[3])
     return true;
 }
 
+bool cell_info(const double box[9], CellInfo &c)
+{
+#pragma clang fp contract(off)
+    for (int k = 0; k < 9; ++k) {
+        if (!std::isfinite(box[k])) return false;
+        c.H[k] = box[k];
+    }
+    const double *H = c.H;
+    c.tri = !(H[1] == 0.0 && H[2] == 0.0 && H[3] == 0.0 && H[5] == 0.0 && H[6] == 0.0 && H[7] == 0.0);
+    // inverse from the cofactors (s = r G for row vectors)
+    const double c00 = H[4] * H[8] - H[5] * H[7], c01 = H[5] * H[6] - H[3] * H[8], c02 = H[3] * H[7] - H[4] * H[6];
+    const double det = H[0] * c00 + H[1] * c01 + H[2] * c02;
+    if (!(det > 0.0) || !std::isfinite(det)) return false;
+    c.vol = det;
+    double *G = c.G;
+    G[0] = c00 / det;
+    G[3] = c01 / det;
+    G[6] = c02 / det;
+    G[1] = (H[2] * H[7] - H[1] * H[8]) / det;
+    G[4] = (H[0] * H[8] - H[2] * H[6]) / det;
+    G[7] = (H[1] * H[6] - H[0] * H[7]) / det;
+    G[2] = (H[1] * H[5] - H[2] * H[4]) / det;
+    G[5] = (H[2] * H[3] - H[0] * H[5]) / det;
+    G[8] = (H[0] * H[4] - H[1] * H[3]) / det;
+    for (int d = 0; d < 3; ++d) {
+        const double *u = H + 3 * ((d + 1) % 3), *v = H + 3 * ((d + 2) % 3);
+        const double cx = u[1] * v[2] - u[2] * v[1], cy = u[2] * v[0] - u[0] * v[2], cz = u[0] * v[1] - u[1] * v[0];
+        c.w[d] = det / std::sqrt(cx * cx + cy * cy + cz * cz);
+        c.len[d] = std::sqrt(H[3 * d] * H[3 * d] + H[3 * d + 1] * H[3 * d + 1] + H[3 * d + 2] * H[3 * d + 2]);
+    }
+    return true;
+}
+
+FineGrid fine_grid_cell(const CellInfo &c, double rc)
+{
+    if (!c.tri) {
+        const double L[3] = {c.H[0], c.H[4], c.H[8]};
+        return fine_grid(L, rc);
+    }
+    FineGrid g{};
+    g.exact = 1;
+    for (int d = 0; d < 3; ++d) {
+        const double room = 0.5 * (0.5 * c.w[d] - rc);
+        int M = 1023;
+        if (room > 0.0) {
+            const double need = std::ceil(std::max(c.w[d] / room, c.len[d] / 1.0));
+            if (need <= 1023.0) M = std::max(1, (int)need);
+            else g.exact = 0;
+        } else {
+            g.exact = 0;
+        }
+        g.M[d] = M;
+        g.hd[d] = c.len[d] / M;
+        g.h[d] = (float)g.hd[d];
+        g.Minv[d] = M / c.len[d];
+    }
+    return g;
+}
+
 FineGrid fine_grid(const double L[3], double rc)
 {
     FineGrid g{};
@@ -452,7 +511,7 @@ extern "C" int32_t nep_nlist_create_batched(const nep_model *m, int32_t P, int32
     nl->capR = capR; nl->capA = capA;
     nl->nsys = nsys;
     nl->off.assign(off, off + nsys + 1);
-    nl->boxL.assign(3 * (size_t)nsys, 0.0);
+    nl->boxL.assign(9 * (size_t)nsys, 0.0);
     std::vector<int32_t> asys((size_t)N);
     for (int s = 0; s < nsys; ++s)
         for (int i = off[s]; i < off[s + 1]; ++i) asys[i] = s;

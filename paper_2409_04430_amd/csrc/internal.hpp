@@ -50,14 +50,29 @@ struct nep_model {
 namespace nep {
 // Geometry of one system of a batch (device copy in the list handle).
 struct SysGeom {
-    double L[3], invL[3];     // orthorhombic box edges
-    double hd[3], Minv[3];    // fine grid spacing and M / L (packing)
-    float h[3];               // fine grid spacing (FP32, pair vectors)
-    int M[3];                 // fine grid cells per axis
+    double L[3], invL[3];     // orthorhombic box edges (triclinic: the diagonal of H, unused)
+    double hd[3], Minv[3];    // fine grid spacing and M / L (packing, orthorhombic)
+    float h[3];               // fine grid spacing (FP32, pair vectors, orthorhombic)
+    int M[3];                 // fine grid cells per axis (along the cell's edge vectors)
     int nc_cap[3];            // cell-list allocation bound per axis
     int cell_base;            // first global cell of the system
     int atom0, atom1;         // atom range [atom0, atom1)
+    int tri;                  // 1: general (triclinic) cell, fractional-coordinate geometry
+    double H[9], G[9];        // edge vectors as rows (r = s H) and G = H^-1 (s = r G)
+    double w[3];              // distance between opposite faces, per axis
+    double GM[9];             // G with column d scaled by M[d] (fine-grid coordinates)
+    double hvd[9];            // fine-grid step vectors H_d / M_d (rows, FP64, packing)
+    float hv[9];              // the same in FP32 (pair vectors)
 };
+
+// Geometry of one periodic cell given by its edge vectors as rows of box[9]:
+// inverse, face distances, volume, whether it is orthorhombic.  False for a
+// singular, left-handed or non-finite cell.
+struct CellInfo {
+    double H[9], G[9], w[3], len[3], vol;
+    int tri;
+};
+bool cell_info(const double box[9], CellInfo &c);
 }  // namespace nep
 
 struct nep_nlist {
@@ -67,7 +82,8 @@ struct nep_nlist {
     // Batch of independent systems: atoms [off[s], off[s+1]) form system s.
     int nsys = 1;
     std::vector<int> off;         // host [nsys+1]
-    std::vector<double> boxL;     // host [nsys][3] edges of the last build (0: none yet)
+    std::vector<double> boxL;     // host [nsys][9] cells of the last build (0: none yet)
+    float margin = 0.0f;          // FP32 pre-test margin of the last build's geometry
     nep::SysGeom *geom = nullptr; // [nsys]
     int32_t *atom_sys = nullptr;  // [N]
     int32_t *cell_sys = nullptr;  // [ncell_alloc]
@@ -175,6 +191,10 @@ struct FineGrid {
     int exact;
 };
 FineGrid fine_grid(const double L[3], double rc);
+// The same for a general cell: M_d cells along edge vector d with
+// w_d / M_d <= (w_d / 2 - rc) / 2 and |H_d| / M_d <= 1 A (w_d the face
+// distance); for an orthorhombic cell it equals fine_grid(L, rc).
+FineGrid fine_grid_cell(const CellInfo &c, double rc);
 
 // Packs pos [P][N][3] into out [N][P] (bead-minor), each atom on the fine
 // grid of its system.
@@ -185,8 +205,34 @@ void pack_positions(const double *pos, int P, int N, const int32_t *atom_sys, co
 // (10 bits per axis in w; unwrapped coordinates allowed) and the FP32
 // offset x - floor(x / h) h inside it; a non-finite coordinate gives a NaN
 // offset.
+__device__ __forceinline__ float4 pack_one_tri(const double *x3, const SysGeom &g)
+{
+    // fine-grid coordinates u_d = (x G)_d M_d, cell floor(u_d) mod M_d, and the
+    // Cartesian offset from the cell corner sum_d floor(u_d) H_d / M_d
+    double fl[3];
+    bool fin = isfinite(x3[0]) && isfinite(x3[1]) && isfinite(x3[2]);
+    int bits = 0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double u = x3[0] * g.GM[d] + x3[1] * g.GM[3 + d] + x3[2] * g.GM[6 + d];
+        double f = floor(u);
+        if (!isfinite(f)) f = 0.0;
+        fl[d] = f;
+        int ci = (int)(f - (double)g.M[d] * floor(f / (double)g.M[d]));
+        ci = ci < 0 ? 0 : (ci >= g.M[d] ? g.M[d] - 1 : ci);
+        bits |= ci << (10 * d);
+    }
+    float o[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        o[a] = (float)(x3[a] - (fl[0] * g.hvd[a] + fl[1] * g.hvd[3 + a] + fl[2] * g.hvd[6 + a]));
+    if (!fin) o[0] = __int_as_float(0x7fc00000);
+    return make_float4(o[0], o[1], o[2], __int_as_float(bits));
+}
+
 __device__ __forceinline__ float4 pack_one(const double *x3, const SysGeom &g)
 {
+    if (g.tri) return pack_one_tri(x3, g);
     float o[3];
     int bits = 0;
     bool fin = true;
@@ -233,6 +279,68 @@ __device__ __forceinline__ void packed_pair(const float4 &pj, const float4 &pi, 
     dz = fmaf(h[2], cz, pj.z - pi.z);
 }
 
+// r_j - r_i from packed positions in a general cell: the offset difference
+// plus sum_d wrap(c_j,d - c_i,d) H_d / M_d.
+__device__ __forceinline__ void packed_pair_tri(const float4 &pj, const float4 &pi, const int M[3], const float hv[9],
+                                                float &dx, float &dy, float &dz)
+{
+    const int wj = __float_as_int(pj.w), wi = __float_as_int(pi.w);
+    const float c0 = wrap_cell_f((wj & 1023) - (wi & 1023), (float)M[0], 1.0f / (float)M[0]);
+    const float c1 = wrap_cell_f(((wj >> 10) & 1023) - ((wi >> 10) & 1023), (float)M[1], 1.0f / (float)M[1]);
+    const float c2 = wrap_cell_f(((wj >> 20) & 1023) - ((wi >> 20) & 1023), (float)M[2], 1.0f / (float)M[2]);
+    dx = fmaf(hv[6], c2, fmaf(hv[3], c1, fmaf(hv[0], c0, pj.x - pi.x)));
+    dy = fmaf(hv[7], c2, fmaf(hv[4], c1, fmaf(hv[1], c0, pj.y - pi.y)));
+    dz = fmaf(hv[8], c2, fmaf(hv[5], c1, fmaf(hv[2], c0, pj.z - pi.z)));
+}
+
+// Exact FP64 minimum-image squared distance in a general cell, the literal
+// expression (no contraction; every step antisymmetric in i and j)
+//   s_c = (d_x G_xc + d_y G_yc) + d_z G_zc;  f_c = s_c - rint(s_c);
+//   e_a = (f_0 H_0a + f_1 H_1a) + f_2 H_2a;  (e_x^2 + e_y^2) + e_z^2
+__device__ __forceinline__ double mic_r2_exact_tri(const double *ri, const double *rj, const double H[9],
+                                                   const double G[9])
+{
+#pragma clang fp contract(off)
+    const double d[3] = {rj[0] - ri[0], rj[1] - ri[1], rj[2] - ri[2]};
+    double f[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double sc = (d[0] * G[c] + d[1] * G[3 + c]) + d[2] * G[6 + c];
+        f[c] = sc - rint(sc);
+    }
+    double e2[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double e = (f[0] * H[a] + f[1] * H[3 + a]) + f[2] * H[6 + a];
+        e2[a] = e * e;
+    }
+    return (e2[0] + e2[1]) + e2[2];
+}
+
+// Minimum-image vector in place (FP64; cell-list and centroid distances).
+__device__ __forceinline__ void mic_vec(double d[3], const SysGeom &g)
+{
+    if (!g.tri) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) d[a] -= g.L[a] * rint(d[a] * g.invL[a]);
+        return;
+    }
+    double f[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double sc = d[0] * g.G[c] + d[1] * g.G[3 + c] + d[2] * g.G[6 + c];
+        f[c] = sc - rint(sc);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = f[0] * g.H[a] + f[1] * g.H[3 + a] + f[2] * g.H[6 + a];
+}
+
+// Fractional coordinate d of a point (cell lists).
+__device__ __forceinline__ double frac_coord(const double x[3], const SysGeom &g, int d)
+{
+    return g.tri ? x[0] * g.G[d] + x[1] * g.G[3 + d] + x[2] * g.G[6 + d] : x[d] * g.invL[d];
+}
+
 // Exact FP64 minimum-image squared distance, the literal expression
 //   d = r_j - r_i;  d -= L rint(d / L);  (dx*dx + dy*dy) + dz*dz
 // without contraction.  The division is replaced by a multiply with 1/L
@@ -266,16 +374,21 @@ struct CutTest {
     float rc2f, margin;
     double rc2;
 };
-struct BoxD {
-    double L[3], invL[3];
-};
 __device__ __forceinline__ bool pair_within(float r2f, const CutTest &c, const double *__restrict__ pos, int i, int j,
-                                            const BoxD &box)
+                                            const SysGeom &g)
 {
     if (fabsf(r2f - c.rc2f) > c.margin) return r2f < c.rc2f;
     const double ri[3] = {pos[3 * (size_t)i], pos[3 * (size_t)i + 1], pos[3 * (size_t)i + 2]};
     const double rj[3] = {pos[3 * (size_t)j], pos[3 * (size_t)j + 1], pos[3 * (size_t)j + 2]};
-    return mic_r2_exact(ri, rj, box.L, box.invL) < c.rc2;
+    return (g.tri ? mic_r2_exact_tri(ri, rj, g.H, g.G) : mic_r2_exact(ri, rj, g.L, g.invL)) < c.rc2;
+}
+
+// r_j - r_i from packed positions of the system's fine grid.
+__device__ __forceinline__ void packed_pair_g(const float4 &pj, const float4 &pi, const SysGeom &g, float &dx,
+                                              float &dy, float &dz)
+{
+    if (g.tri) packed_pair_tri(pj, pi, g.M, g.hv, dx, dy, dz);
+    else packed_pair(pj, pi, g.M, g.h, dx, dy, dz);
 }
 
 // Lanes per atom: the beads of one atom occupy G = 2^lg consecutive lanes of
@@ -291,7 +404,8 @@ inline int lanes_log2(int P)
 // refreshes the per-system geometry of the list handle (synchronous upload
 // when a box changed).  margin: decision margin of the FP32 pre-test, about
 // 30x the packed error bound.
-int32_t update_geometry(const nep_model *m, nep_nlist *nl, const double *boxes, bool &changed, float &margin);
+int32_t update_geometry(const nep_model *m, nep_nlist *nl, const double *boxes, bool &changed, float &margin,
+                        bool &tri_changed);
 
 // Kernel timing (hipEvents around launches on the caller's stream), off by default.
 enum KernelId {

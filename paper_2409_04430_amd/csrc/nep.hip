@@ -889,12 +889,11 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
     }
     if (!pos || !types || !F) return fail(NEP_ERR_INVALID_ARG, "nep_compute: null array");
     if (!nl->built) return fail(NEP_ERR_INVALID_ARG, "nep_compute: the neighbour lists were never built");
-    for (int sy = 0; sy < nsys; ++sy) {
-        double L[3];
-        if (!box_lengths(boxes + 9 * sy, L)) return fail(NEP_ERR_UNSUPPORTED, "nep_compute: only orthorhombic cells");
-        if (L[0] != nl->boxL[3 * sy] || L[1] != nl->boxL[3 * sy + 1] || L[2] != nl->boxL[3 * sy + 2])
-            return fail(NEP_ERR_INVALID_ARG, "nep_compute: box of system %d differs from the last neighbor_build", sy);
-    }
+    for (int sy = 0; sy < nsys; ++sy)
+        for (int k = 0; k < 9; ++k)
+            if (boxes[9 * sy + k] != nl->boxL[9 * sy + k])
+                return fail(NEP_ERR_INVALID_ARG, "nep_compute: box of system %d differs from the last neighbor_build",
+                            sy);
     const nep_hparams &h = m->hp;
     NepArgs a{};
     // packed positions of the last neighbor_build (the same positions, see the header)

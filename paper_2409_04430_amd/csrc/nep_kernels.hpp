@@ -47,6 +47,8 @@ struct LaneMap {
     bool valid;      // a real (atom, bead)
     int M[3];
     float h[3];
+    int tri;         // general cell: pair vectors through the step vectors hv
+    float hv[9];
 };
 __device__ __forceinline__ LaneMap lane_map(const NepArgs &a)
 {
@@ -64,6 +66,9 @@ __device__ __forceinline__ LaneMap lane_map(const NepArgs &a)
         m.M[d] = g.M[d];
         m.h[d] = g.h[d];
     }
+    m.tri = g.tri;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m.hv[k] = g.hv[k];
     return m;
 }
 
@@ -78,7 +83,8 @@ __device__ __forceinline__ void block_range(const int32_t *uend, int i, int t, i
 __device__ __forceinline__ void pair_vec(const float4 &pj, const float4 &pi, const LaneMap &lm, float &dx, float &dy,
                                          float &dz)
 {
-    packed_pair(pj, pi, lm.M, lm.h, dx, dy, dz);
+    if (lm.tri) packed_pair_tri(pj, pi, lm.M, lm.hv, dx, dy, dz);   // wave-uniform branch
+    else packed_pair(pj, pi, lm.M, lm.h, dx, dy, dz);
 }
 
 __device__ __forceinline__ double wave_sum(double v)

@@ -61,9 +61,8 @@ __device__ __forceinline__ const DevSys *dev_sys(const uint32_t *grid, int s)
     return reinterpret_cast<const DevSys *>(grid + 16) + s;
 }
 
-__device__ __forceinline__ int cell_axis(double x, double L, double invL, int nc)
+__device__ __forceinline__ int cell_axis(double s, int nc)
 {
-    double s = x * invL;
     s = s - floor(s);
     if (!(s >= 0.0) || !(s < 1.0)) s = 0.0;   // NaN / Inf, or s rounded up to 1
     int c = (int)(s * nc);
@@ -140,7 +139,8 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
             const DevSys *ds = dev_sys(grid, sy);
             double lam[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) lam[a] = ds->Lb[a] > 0.0 ? geom[sy].L[a] / ds->Lb[a] : 1.0;
+            for (int a = 0; a < 3; ++a)
+                lam[a] = (!geom[sy].tri && ds->Lb[a] > 0.0) ? geom[sy].L[a] / ds->Lb[a] : 1.0;   // a changed general cell rebuilds
             const double dx = c[0] - lam[0] * cen_ref[3 * i], dy = c[1] - lam[1] * cen_ref[3 * i + 1],
                          dz = c[2] - lam[2] * cen_ref[3 * i + 2];
             const double d2 = dx * dx + dy * dy + dz * dz;
@@ -204,7 +204,7 @@ __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double
     for (int s = 0; s < nsys; ++s) {
         const DevSys *ds = dev_sys(grid, s);
         for (int a = 0; a < 3; ++a)
-            if (ds->Lb[a] > 0.0) lam_min = fmin(lam_min, geom[s].L[a] / ds->Lb[a]);
+            if (!geom[s].tri && ds->Lb[a] > 0.0) lam_min = fmin(lam_min, geom[s].L[a] / ds->Lb[a]);
     }
     const double reach = 2.0 * (double)spread + 2.0 * (double)disp, d0 = 2.0 * (double)dg->d_build;
     const double needR = (rcR + reach) / lam_min - rcR - d0, needA = (rcA + reach) / lam_min - rcA - d0;
@@ -217,7 +217,7 @@ __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double
             int ncell = 1;
             DevSys *ds = dev_sys(grid, s);
             for (int a = 0; a < 3; ++a) {
-                int nc = (int)floor(geom[s].L[a] / (R * (1.0 + 1e-9)));
+                int nc = (int)floor(geom[s].w[a] / (R * (1.0 + 1e-9)));
                 nc = nc < 1 ? 1 : (nc > geom[s].nc_cap[a] ? geom[s].nc_cap[a] : nc);
                 ds->nc[a] = nc;
                 ds->Lb[a] = geom[s].L[a];
@@ -248,9 +248,10 @@ __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double
 // Global cell of atom i's centroid (system s).
 __device__ __forceinline__ int atom_cell(const double *__restrict__ cen, int i, const SysGeom &g, const DevSys &ds)
 {
-    const int cx = cell_axis(cen[3 * i], g.L[0], g.invL[0], ds.nc[0]);
-    const int cy = cell_axis(cen[3 * i + 1], g.L[1], g.invL[1], ds.nc[1]);
-    const int cz = cell_axis(cen[3 * i + 2], g.L[2], g.invL[2], ds.nc[2]);
+    const double c[3] = {cen[3 * i], cen[3 * i + 1], cen[3 * i + 2]};
+    const int cx = cell_axis(frac_coord(c, g, 0), ds.nc[0]);
+    const int cy = cell_axis(frac_coord(c, g, 1), ds.nc[1]);
+    const int cz = cell_axis(frac_coord(c, g, 2), ds.nc[2]);
     return g.cell_base + (cz * ds.nc[1] + cy) * ds.nc[0] + cx;
 }
 
@@ -418,13 +419,9 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
                     w = (tj >= 0 && tj < S) ? ((j << 2) | tj) : -1;
                 }
                 if (w >= 0 && (w >> 2) != i) {
-                    double r2 = 0.0;
-#pragma unroll
-                    for (int e = 0; e < 3; ++e) {
-                        double d = p[e] - ci[e];
-                        d -= g.L[e] * rint(d * g.invL[e]);
-                        r2 += d * d;
-                    }
+                    double d[3] = {p[0] - ci[0], p[1] - ci[1], p[2] - ci[2]};
+                    mic_vec(d, g);
+                    const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
                     okR = r2 < R2;
                     okA = r2 < RA2;
                 }
@@ -572,7 +569,6 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
     const float4 pi = pos4[(size_t)i * P + bb];
     const double *pb = pos + (size_t)bb * N * 3;
     const SysGeom &g = geom[atom_sys[i]];
-    const BoxD box{{g.L[0], g.L[1], g.L[2]}, {g.invL[0], g.invL[1], g.invL[2]}};
     const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
     const uint64_t full = (P == 64) ? ~0ull : ((1ull << P) - 1ull);
     const double ci0 = cen[3 * (size_t)i], ci1 = cen[3 * (size_t)i + 1], ci2 = cen[3 * (size_t)i + 2];
@@ -593,11 +589,9 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
             const int k = kb + lane;
             const bool kin = k < k1;
             const int j = kin ? row[k] >> 2 : i;
-            double dx = cen[3 * (size_t)j] - ci0, dy = cen[3 * (size_t)j + 1] - ci1, dz = cen[3 * (size_t)j + 2] - ci2;
-            dx -= box.L[0] * rint(dx * box.invL[0]);
-            dy -= box.L[1] * rint(dy * box.invL[1]);
-            dz -= box.L[2] * rint(dz * box.invL[2]);
-            const double d = sqrt(dx * dx + dy * dy + dz * dz);
+            double dv[3] = {cen[3 * (size_t)j] - ci0, cen[3 * (size_t)j + 1] - ci1, cen[3 * (size_t)j + 2] - ci2};
+            mic_vec(dv, g);
+            const double d = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
             const double sp = si + (double)spr[j];
             const bool all_in = kin && d + sp < rc - kShellEps;
             const bool shell = kin && !all_in && !(d - sp > rc + kShellEps);
@@ -615,9 +609,9 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
                 }
                 const int jq = __shfl(j, my, 64);
                 float ex, ey, ez;
-                packed_pair(pos4[(size_t)jq * P + bb], pi, g.M, g.h, ex, ey, ez);
+                packed_pair_g(pos4[(size_t)jq * P + bb], pi, g, ex, ey, ez);
                 const float r2f = ex * ex + ey * ey + ez * ez;
-                const bool in = cg < nq && bead_ok && pair_within(r2f, c, pb, i, jq, box);
+                const bool in = cg < nq && bead_ok && pair_within(r2f, c, pb, i, jq, g);
                 const uint64_t m = __ballot(in);
                 for (int q = 0; q < nq; ++q) {
                     const int sq = __builtin_ctzll(take);
@@ -664,7 +658,6 @@ __global__ __launch_bounds__(256) void k_materialize(const double *__restrict__ 
     const float4 pi = pos4[(size_t)i * P + b];
     const double *pb = pos + (size_t)b * N * 3;
     const SysGeom &g = geom[atom_sys[i]];
-    const BoxD box{{g.L[0], g.L[1], g.L[2]}, {g.invL[0], g.invL[1], g.invL[2]}};
     for (int kind = 0; kind < 2; ++kind) {
         const int cap = kind ? capA : capR, out = kind ? outA : outR;
         const int32_t *row = (kind ? candA : candR) + (size_t)i * cap;
@@ -675,8 +668,8 @@ __global__ __launch_bounds__(256) void k_materialize(const double *__restrict__ 
         for (int k = 0; k < n; ++k) {
             const int j = row[k] >> 2;
             float dx, dy, dz;
-            packed_pair(pos4[(size_t)j * P + b], pi, g.M, g.h, dx, dy, dz);
-            if (pair_within(dx * dx + dy * dy + dz * dz, c, pb, i, j, box)) {
+            packed_pair_g(pos4[(size_t)j * P + b], pi, g, dx, dy, dz);
+            if (pair_within(dx * dx + dy * dy + dz * dz, c, pb, i, j, g)) {
                 if (cnt < out) nb[(size_t)cnt * N] = j;
                 ++cnt;
             }
@@ -688,41 +681,64 @@ __global__ __launch_bounds__(256) void k_materialize(const double *__restrict__ 
 // Checks the boxes of a batch and refreshes the per-system geometry (fine
 // grids, cell bounds, cell ranges).  The device copy is rewritten, with a
 // synchronous copy, only when a box changed; `changed` reports that.
-int32_t update_geometry(const nep_model *m, nep_nlist *nl, const double *boxes, bool &changed, float &margin)
+int32_t update_geometry(const nep_model *m, nep_nlist *nl, const double *boxes, bool &changed, float &margin,
+                        bool &tri_changed)
 {
     const double rc = std::max(m->hp.rc_radial, m->hp.rc_angular);
     std::vector<SysGeom> G(nl->nsys);
     int cell_total = 0;
     double hmax = 0.0;
     changed = false;
+    tri_changed = false;
     for (int s = 0; s < nl->nsys; ++s) {
         SysGeom &g = G[s];
-        double L[3];
-        if (!box_lengths(boxes + 9 * s, L)) return fail(NEP_ERR_UNSUPPORTED, "system %d: only orthorhombic cells", s);
-        for (int a = 0; a < 3; ++a) {
-            if (!(L[a] > 0.0) || !std::isfinite(L[a]))
-                return fail(NEP_ERR_INVALID_ARG, "system %d: bad box edge %g", s, L[a]);
-            if (L[a] < 2.0 * rc)
-                return fail(NEP_ERR_BOX_TOO_SMALL, "system %d: box edge %g is shorter than twice the cutoff %g", s,
-                            L[a], rc);
-        }
-        const FineGrid fg = fine_grid(L, rc);
+        const double *box = boxes + 9 * s;
+        CellInfo ci;
+        if (!cell_info(box, ci))
+            return fail(NEP_ERR_INVALID_ARG, "system %d: singular, left-handed or non-finite cell", s);
+        for (int a = 0; a < 3; ++a)
+            if (ci.w[a] < 2.0 * rc)
+                return fail(NEP_ERR_BOX_TOO_SMALL,
+                            "system %d: the cell's faces %d lie %g apart, less than twice the cutoff %g", s, a,
+                            ci.w[a], rc);
+        const FineGrid fg = fine_grid_cell(ci, rc);
         if (!fg.exact)
-            return fail(NEP_ERR_BOX_TOO_SMALL, "system %d: box edges %g %g %g leave no margin over twice the cutoff",
-                        s, L[0], L[1], L[2]);
+            return fail(NEP_ERR_BOX_TOO_SMALL, "system %d: face distances %g %g %g leave no margin over twice the "
+                                               "cutoff", s, ci.w[0], ci.w[1], ci.w[2]);
+        g.tri = ci.tri;
+        bool diff = false;
+        for (int k = 0; k < 9; ++k) {
+            g.H[k] = ci.H[k];
+            g.G[k] = ci.G[k];
+            if (nl->boxL[9 * s + k] != box[k]) diff = true;
+        }
         int ncap = 1;
         for (int a = 0; a < 3; ++a) {
-            g.L[a] = L[a];
-            g.invL[a] = 1.0 / L[a];
+            g.L[a] = ci.tri ? 1.0 : ci.H[4 * a];
+            g.invL[a] = 1.0 / g.L[a];
+            g.w[a] = ci.w[a];
             g.hd[a] = fg.hd[a];
             g.Minv[a] = fg.Minv[a];
             g.h[a] = fg.h[a];
             g.M[a] = fg.M[a];
-            const int nc = (int)std::floor(L[a] / (rc * (1.0 + 1e-9)));
+            const int nc = (int)std::floor(ci.w[a] / (rc * (1.0 + 1e-9)));
             g.nc_cap[a] = nc < 1 ? 1 : (nc > 64 ? 64 : nc);
             ncap *= g.nc_cap[a];
             hmax = std::max(hmax, fg.hd[a]);
-            if (nl->boxL[3 * s + a] != L[a]) changed = true;
+        }
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                g.GM[3 * r + c] = ci.G[3 * r + c] * g.M[c];
+                g.hvd[3 * r + c] = ci.H[3 * r + c] / g.M[r];
+                g.hv[3 * r + c] = (float)g.hvd[3 * r + c];
+            }
+        if (ci.tri) hmax = std::max(hmax, fg.hd[0] + fg.hd[1] + fg.hd[2]);   // offsets span the skewed fine cell
+        if (diff) {
+            changed = true;
+            // the scaled skin test covers per-axis scaling of orthorhombic cells only
+            bool was_tri = false;
+            for (int k : {1, 2, 3, 5, 6, 7}) was_tri = was_tri || nl->boxL[9 * s + k] != 0.0;
+            if (ci.tri || was_tri) tri_changed = true;
         }
         g.cell_base = cell_total;
         cell_total += ncap;
@@ -730,6 +746,7 @@ int32_t update_geometry(const nep_model *m, nep_nlist *nl, const double *boxes, 
         g.atom1 = nl->off[s + 1];
     }
     margin = (float)(1e-3 * std::max(1.0, hmax * hmax) * std::max(1.0, rc * rc / 36.0));
+    nl->margin = margin;
     if (!changed) return NEP_OK;
     if (cell_total > nl->ncell_alloc) {
         for (int32_t **p : {&nl->cell_cnt, &nl->cell_start, &nl->cell_sys}) {
@@ -753,7 +770,7 @@ int32_t update_geometry(const nep_model *m, nep_nlist *nl, const double *boxes, 
     NEP_HIP(hipMemcpy(nl->geom, G.data(), sizeof(SysGeom) * G.size(), hipMemcpyHostToDevice));
     nl->ncell_total = cell_total;
     for (int s = 0; s < nl->nsys; ++s)
-        for (int a = 0; a < 3; ++a) nl->boxL[3 * s + a] = G[s].L[a];
+        for (int k = 0; k < 9; ++k) nl->boxL[9 * s + k] = boxes[9 * s + k];
     return NEP_OK;
 }
 
@@ -770,11 +787,12 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
                     nl->P, nl->N);
     if (P == 0 || N == 0) return NEP_OK;
     if (!pos || !types) return fail(NEP_ERR_INVALID_ARG, "neighbor_build: null array");
-    bool changed = false;
+    bool changed = false, tri_changed = false;
     float margin = 0.0f;
-    const int32_t rc_ = update_geometry(m, nl, boxes, changed, margin);
+    const int32_t rc_ = update_geometry(m, nl, boxes, changed, margin, tri_changed);
     if (rc_ != NEP_OK) return rc_;
-    const bool force = !nl->built;   // a changed box is covered by the device-side skin test
+    // a per-axis scaling of an orthorhombic cell is covered by the device-side skin test
+    const bool force = !nl->built || tri_changed;
     pack_positions(pos, P, N, nl->atom_sys, nl->geom, reinterpret_cast<float4 *>(nl->pos4), s);
     const dim3 g1(div_up(N, kBlock));
     const dim3 gw(div_up(N, kBlock / 64));
@@ -843,17 +861,12 @@ extern "C" int32_t nep_nlist_materialize(const nep_model *m, const nep_nlist *nl
     if (P == 0 || N == 0) return NEP_OK;
     if (!pos || !nbrR || !cntR || !nbrA || !cntA) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_materialize: null array");
     if (!nl->built) return fail(NEP_ERR_INVALID_ARG, "nep_nlist_materialize: no neighbor_build yet");
-    for (int sy = 0; sy < nl->nsys; ++sy) {
-        double L[3];
-        if (!box_lengths(boxes + 9 * sy, L) || L[0] != nl->boxL[3 * sy] || L[1] != nl->boxL[3 * sy + 1] ||
-            L[2] != nl->boxL[3 * sy + 2])
-            return fail(NEP_ERR_INVALID_ARG, "nep_nlist_materialize: box of system %d differs from the last build", sy);
-    }
-    const double rc = std::max(m->hp.rc_radial, m->hp.rc_angular);
-    double hmax = 0.0;
     for (int sy = 0; sy < nl->nsys; ++sy)
-        for (int a = 0; a < 3; ++a) hmax = std::max(hmax, fine_grid(&nl->boxL[3 * sy], rc).hd[a]);
-    const float margin = (float)(1e-3 * std::max(1.0, hmax * hmax) * std::max(1.0, rc * rc / 36.0));
+        for (int k = 0; k < 9; ++k)
+            if (boxes[9 * sy + k] != nl->boxL[9 * sy + k])
+                return fail(NEP_ERR_INVALID_ARG, "nep_nlist_materialize: box of system %d differs from the last build",
+                            sy);
+    const float margin = nl->margin;
     const double rR2 = m->hp.rc_radial * m->hp.rc_radial, rA2 = m->hp.rc_angular * m->hp.rc_angular;
     const CutTest cR{(float)rR2, margin, rR2};
     const CutTest cA{(float)rA2, margin, rA2};

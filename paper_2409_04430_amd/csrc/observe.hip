@@ -36,12 +36,19 @@ __global__ void k_beads_minor(const double *__restrict__ pos, double *__restrict
 // batches whose loads are in flight together, keeps the entries whose bead
 // mask holds its bead, and counts the pair's bin in the workgroup's LDS
 // histogram; the workgroup then adds its non-zero bins to the global 64-bit
-// histogram.  The image shift is rint(x (1/L)): every listed pair is closer
-// than the cutoff, far from the half-integer points where it could differ
-// from rint(x / L), so the distance is the same double as with the division.
+// histogram.  Orthorhombic cells: the image shift is rint(x (1/L)); every
+// listed pair is closer than the cutoff, far from the half-integer points
+// where it could differ from rint(x / L), so the distance is the same double
+// as with the division.  General cells: the fractional difference reduced by
+// rint and mapped back, in the same order of operations as the list test.
+struct RdfCell {
+    double L[3], iL[3];     // orthorhombic: edges and their inverses
+    double H[9], G[9];      // general: edge vectors as rows and H^-1
+    int tri;
+};
+
 __global__ __launch_bounds__(kRdfBlock) void k_rdf(const double *__restrict__ posT, const int32_t *__restrict__ types,
-                                                   int P, int N, int S, int lg, double Lx, double Ly, double Lz,
-                                                   double iLx, double iLy, double iLz,
+                                                   int P, int N, int S, int lg, RdfCell cell,
                                                    double inv, int nbins, const int32_t *__restrict__ uni,
                                                    const uint64_t *__restrict__ um, const int32_t *__restrict__ uend,
                                                    int cap, unsigned long long *__restrict__ hist)
@@ -52,7 +59,6 @@ __global__ __launch_bounds__(kRdfBlock) void k_rdf(const double *__restrict__ po
     __syncthreads();
     const int G = 1 << lg;
     const int64_t lanes = (int64_t)N << lg;
-    const double L[3] = {Lx, Ly, Lz}, iL[3] = {iLx, iLy, iLz};
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < lanes; t += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(t >> lg), b = (int)(t & (G - 1));
         if (b >= P) continue;
@@ -87,11 +93,24 @@ __global__ __launch_bounds__(kRdfBlock) void k_rdf(const double *__restrict__ po
                     if (!in[u]) continue;
                     const double xv[3] = {xj[u][0] - xi0, xj[u][1] - xi1, xj[u][2] - xi2};
                     double d[3];
+                    if (cell.tri) {
+                        // fractional difference reduced by rint, mapped back
+                        double f[3];
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        const double k = rint(xv[a] * iL[a]);
-                        const double sh = L[a] * k;
-                        d[a] = xv[a] - sh;
+                        for (int c = 0; c < 3; ++c) {
+                            const double sc = (xv[0] * cell.G[c] + xv[1] * cell.G[3 + c]) + xv[2] * cell.G[6 + c];
+                            f[c] = sc - rint(sc);
+                        }
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            d[a] = (f[0] * cell.H[a] + f[1] * cell.H[3 + a]) + f[2] * cell.H[6 + a];
+                    } else {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const double k = rint(xv[a] * cell.iL[a]);
+                            const double sh = cell.L[a] * k;
+                            d[a] = xv[a] - sh;
+                        }
                     }
                     const double xx = d[0] * d[0], yy = d[1] * d[1], zz = d[2] * d[2];
                     const double r2 = (xx + yy) + zz;
@@ -134,11 +153,11 @@ extern "C" int32_t nep_rdf_accumulate(const nep_model *m, nep_nlist *nl, const d
     if (!(rmax > 0.0) || !(rmax <= rcR * (1.0 - 1e-9)))
         return fail(NEP_ERR_INVALID_ARG, "nep_rdf_accumulate: rmax %g must lie in (0, rc_radial (1 - 1e-9)], "
                                          "rc_radial = %g", rmax, rcR);
-    double L[3];
-    if (!box_lengths(box, L)) return fail(NEP_ERR_UNSUPPORTED, "nep_rdf_accumulate: only orthorhombic cells");
-    for (int a = 0; a < 3; ++a)
-        if (L[a] != nl->boxL[a])
+    for (int k = 0; k < 9; ++k)
+        if (box[k] != nl->boxL[k])
             return fail(NEP_ERR_INVALID_ARG, "nep_rdf_accumulate: box differs from the last neighbor_build");
+    CellInfo ci;
+    if (!cell_info(box, ci)) return fail(NEP_ERR_INVALID_ARG, "nep_rdf_accumulate: bad cell");
     if (!nl->built) return fail(NEP_ERR_INVALID_ARG, "nep_rdf_accumulate: lists not built");
     if (!hist) return fail(NEP_ERR_INVALID_ARG, "nep_rdf_accumulate: null histogram");
     if (P == 0 || N == 0) return NEP_OK;
@@ -152,9 +171,18 @@ extern "C" int32_t nep_rdf_accumulate(const nep_model *m, nep_nlist *nl, const d
     ProfScope ps_(K_RDF, s);
     const int64_t PN = (int64_t)P * N;
     hipLaunchKernelGGL(k_beads_minor, dim3((unsigned)((PN + 255) / 256)), dim3(256), 0, s, pos, nl->posT, P, N);
-    hipLaunchKernelGGL(k_rdf, dim3(groups), dim3(kRdfBlock), lds, s, nl->posT, types, P, N, S, lg, L[0], L[1], L[2],
-                       1.0 / L[0], 1.0 / L[1], 1.0 / L[2], nbins / rmax, nbins, nl->uniR, nl->umR, nl->uendR,
-                       nl->capR, reinterpret_cast<unsigned long long *>(hist));
+    RdfCell cell{};
+    cell.tri = ci.tri;
+    for (int k = 0; k < 9; ++k) {
+        cell.H[k] = ci.H[k];
+        cell.G[k] = ci.G[k];
+    }
+    for (int a = 0; a < 3; ++a) {
+        cell.L[a] = ci.H[4 * a];
+        cell.iL[a] = 1.0 / ci.H[4 * a];
+    }
+    hipLaunchKernelGGL(k_rdf, dim3(groups), dim3(kRdfBlock), lds, s, nl->posT, types, P, N, S, lg, cell, nbins / rmax,
+                       nbins, nl->uniR, nl->umR, nl->uendR, nl->capR, reinterpret_cast<unsigned long long *>(hist));
     NEP_HIP(hipGetLastError());
     return NEP_OK;
 }

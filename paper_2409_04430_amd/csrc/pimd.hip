@@ -329,26 +329,41 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+struct ObsCell {
+    double L[3];          // orthorhombic edges
+    double H[9], G[9];    // general cell: edge vectors as rows and H^-1
+    int tri;
+};
+
 __global__ __launch_bounds__(kObsBlock) void k_obs_partial(const double *__restrict__ pos, const float *__restrict__ F,
-                                                           int N, int P, int lg, double Lx, double Ly, double Lz,
+                                                           int N, int P, int lg, ObsCell cell,
                                                            double *__restrict__ part)
 {
     const int G = 1 << lg;
     const int t = blockIdx.x * kObsBlock + threadIdx.x;
     const int i = t >> lg, b = t & (G - 1);
     const bool valid = i < N && b < P;
-    const double L[3] = {Lx, Ly, Lz};
     double rel[3] = {0.0, 0.0, 0.0}, f[3] = {0.0, 0.0, 0.0};
     if (valid) {
         const double *r = pos + ((size_t)b * N + i) * 3;
         const double *r1 = pos + (size_t)i * 3;
         const float *fb = F + ((size_t)b * N + i) * 3;
+        const double d[3] = {r[0] - r1[0], r[1] - r1[1], r[2] - r1[2]};
+        if (cell.tri) {
+            double fr[3];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const double d = r[a] - r1[a];
-            rel[a] = d - L[a] * rint(d / L[a]);
-            f[a] = (double)fb[a];
+            for (int c = 0; c < 3; ++c) {
+                const double sc = d[0] * cell.G[c] + d[1] * cell.G[3 + c] + d[2] * cell.G[6 + c];
+                fr[c] = sc - rint(sc);
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) rel[a] = fr[0] * cell.H[a] + fr[1] * cell.H[3 + a] + fr[2] * cell.H[6 + a];
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) rel[a] = d[a] - cell.L[a] * rint(d[a] / cell.L[a]);
         }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) f[a] = (double)fb[a];
     }
     // mean over the atom's beads (lanes b >= P hold zeros)
     double dr[3];
@@ -627,15 +642,21 @@ extern "C" int32_t pimd_observables(const pimd_ctx *c, const double *pos, const 
     if (!c || !box) return fail(NEP_ERR_INVALID_ARG, "pimd_observables: null argument");
     if ((c->N > 0 && (!pos || !F)) || !W_bead || !E_bead || !out)
         return fail(NEP_ERR_INVALID_ARG, "pimd_observables: null array");
-    double L[3];
-    if (!box_lengths(box, L)) return fail(NEP_ERR_UNSUPPORTED, "pimd_observables: only orthorhombic cells");
-    if (!(L[0] > 0.0 && L[1] > 0.0 && L[2] > 0.0)) return fail(NEP_ERR_INVALID_ARG, "pimd_observables: bad box");
+    CellInfo ci;
+    if (!cell_info(box, ci)) return fail(NEP_ERR_INVALID_ARG, "pimd_observables: singular, left-handed or non-finite cell");
+    ObsCell cell{};
+    cell.tri = ci.tri;
+    for (int k = 0; k < 9; ++k) {
+        cell.H[k] = ci.H[k];
+        cell.G[k] = ci.G[k];
+    }
+    for (int a = 0; a < 3; ++a) cell.L[a] = ci.H[4 * a];
     int lg = 0;
     while ((1 << lg) < c->P) ++lg;
     const int nblk = c->obs_blocks;
     ProfScope ps_(K_OBS, s);
     if (nblk > 0)
-        hipLaunchKernelGGL(k_obs_partial, dim3(nblk), dim3(kObsBlock), 0, s, pos, F, c->N, c->P, lg, L[0], L[1], L[2],
+        hipLaunchKernelGGL(k_obs_partial, dim3(nblk), dim3(kObsBlock), 0, s, pos, F, c->N, c->P, lg, cell,
                            c->obs_part);
     ObsFinal a;
     a.part = c->obs_part;
@@ -645,7 +666,7 @@ extern "C" int32_t pimd_observables(const pimd_ctx *c, const double *pos, const 
     a.P = c->P;
     a.N = c->N;
     a.NkT = c->N * kKB * c->prm.T_K;
-    a.inv_vol_gpa = ev_a3_gpa() / (L[0] * L[1] * L[2]);
+    a.inv_vol_gpa = ev_a3_gpa() / ci.vol;
     a.out = out;
     hipLaunchKernelGGL(k_obs_final, dim3(1), dim3(kObsBlock), 0, s, a);
     NEP_HIP(hipGetLastError());

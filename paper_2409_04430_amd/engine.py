@@ -84,8 +84,7 @@ class NepPimd:
         self.W = torch.zeros(eshape + (9,), dtype=torch.float64, device=dev)
         self.E_atom = torch.zeros((self.P, self.N), dtype=torch.float32, device=dev) if want_atom else None
         self.W_atom = torch.zeros((self.P, self.N, 9), dtype=torch.float32, device=dev) if want_atom else None
-        vol = sum(float(np.prod(np.asarray(s.box, np.float64).reshape(-1)[[0, 4, 8]] if np.asarray(s.box).size == 9
-                                 else np.asarray(s.box, np.float64))) for s in systems)
+        vol = sum(I.cell_volume(s.box) for s in systems)
         dens = self.N / vol
         self.density = dens
         S = self.model.n_species
@@ -197,8 +196,9 @@ class NepPimd:
             mu = self.mu.cpu().numpy()     # the next neighbour build needs the new cell
             if not (np.all(np.isfinite(mu)) and np.all(mu > 0.0)):
                 raise lib.NepError(6, f"barostat scaling factors {mu}")
+            # every Cartesian component a of the positions and of the edge vectors scales by mu_a
             box = np.asarray(self.box, np.float64)
-            self.box = box * mu if box.shape == (3,) else (box.reshape(3, 3) * mu[:, None]).reshape(box.shape)
+            self.box = box * mu if box.shape == (3,) else (box.reshape(3, 3) * mu[None, :]).reshape(box.shape)
 
     def step(self):
         """One full step: forces at the advanced positions, then POST(n) + PRE(n+1)."""
@@ -274,8 +274,7 @@ class NepPimd:
         counts = self.rdf_hist.cpu().numpy().astype(np.uint64)
         types = self.types.cpu().numpy()
         n_sp = [int((types == a).sum()) for a in range(self.model.n_species)]
-        box = np.asarray(self.box, np.float64).reshape(-1)
-        vol = float(np.prod(box[[0, 4, 8]] if box.size == 9 else box))
+        vol = I.cell_volume(self.box)
         r, g = rdf_normalise(counts, n_sp, vol, float(self.rdf_cfg["rmax"]), self.rdf_frames, self.P)
         return r, g, counts
 

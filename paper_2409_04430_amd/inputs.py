@@ -65,6 +65,23 @@ def rocksalt(ncell: int, a: float):
 WATER_VOLUME_PER_MOLECULE = 18.01528 / 6.02214076e23 * 1e24   # A^3 at 1.0 g/cm^3
 
 
+def fcc_primitive(n: int, a: float):
+    """FCC crystal in an n x n x n supercell of the rhombohedral primitive cell
+    (edge vectors a/2 (0,1,1), a/2 (1,0,1), a/2 (1,1,0)): a triclinic cell of
+    n^3 atoms.  Returns (pos [n^3, 3], types zeros, cell [3, 3] with the
+    edge vectors as rows)."""
+    prim = 0.5 * a * np.array([[0.0, 1.0, 1.0], [1.0, 0.0, 1.0], [1.0, 1.0, 0.0]])
+    idx = np.arange(n)
+    frac = np.stack(np.meshgrid(idx, idx, idx, indexing="ij"), axis=-1).reshape(-1, 3).astype(np.float64)
+    return frac @ prim, np.zeros(n ** 3, np.int32), n * prim
+
+
+def cell_volume(box) -> float:
+    """Volume of a cell given as edge lengths [3] or edge vectors [3, 3] (rows)."""
+    b = np.asarray(box, np.float64)
+    return float(np.prod(b)) if b.shape == (3,) else float(abs(np.linalg.det(b.reshape(3, 3))))
+
+
 def water_box(n_mol: int, rng: np.random.Generator, oh: float = 0.96,
               hoh_deg: float = 104.5, min_oo: float = 2.5):
     """n_mol rigid-geometry water molecules at 1.0 g/cm^3 in a cubic box.
@@ -323,7 +340,7 @@ class System:
     vel: np.ndarray        # [P, N, 3] float64, A/fs
     types: np.ndarray      # [N] int32
     masses: np.ndarray     # [N] float64, amu
-    box: np.ndarray        # [3] float64, orthorhombic edge lengths, A
+    box: np.ndarray        # [3] orthorhombic edge lengths, or [3, 3] edge vectors as rows, A
 
     @property
     def P(self):

@@ -122,7 +122,7 @@ class StudentTrainer:
         self.val = np.sort(order[:n_val])
         self.train = np.sort(order[n_val:]) if n_val < len(store) else order
         self.rng = rng
-        dens = self.N / float(np.prod(self.box if self.box.size == 3 else np.diag(self.box.reshape(3, 3))))
+        dens = self.N / I.cell_volume(self.box)
         caps = (default_capacity(self.model.rc_radial + skin + 1.0, dens, 1),
                 default_capacity(self.model.rc_angular + skin + 1.0, dens, 1))
         self.nl = lib.fitted_neighbor_list(self.model, store.pos[0], self.box, self.types, *caps, skin=skin)

@@ -290,9 +290,13 @@ def test_nep_edge_cases(torch, L, tmpdir_session):
     with pytest.raises(L.NepError) as e:
         nl.build(tpos, [9.0, 12.15, 12.15], ttyp)
     assert e.value.code == 4
+    # a left-handed cell, and a sheared cell whose opposite faces lie closer than twice the cutoff
     with pytest.raises(L.NepError) as e:
-        nl.build(tpos, np.array([[12.15, 0.1, 0], [0, 12.15, 0], [0, 0, 12.15]]), ttyp)
-    assert e.value.code == 3
+        nl.build(tpos, np.array([[12.15, 0, 0], [0, 12.15, 0], [0, 0, -12.15]]), ttyp)
+    assert e.value.code == 1
+    with pytest.raises(L.NepError) as e:
+        nl.build(tpos, np.array([[12.15, 0, 0], [12.0, 5.0, 0], [0, 0, 12.15]]), ttyp)
+    assert e.value.code == 4
     # capacity overflow is flagged and the lists stay within bounds
     for caps in ((10, 4), (96, 4), (10, 48)):
         small = L.NeighborList(m, 2, 108, *caps)

@@ -122,10 +122,10 @@ def test_observables_rejects_bad_arguments(torch, L):
     W = torch.zeros((P, 9), dtype=torch.float64, device=dev)
     E = torch.zeros(P, dtype=torch.float64, device=dev)
     out = torch.zeros(L.OBS_COUNT, dtype=torch.float64, device=dev)
-    tri = np.array([[10.0, 0, 0], [1.0, 10.0, 0], [0, 0, 10.0]])
+    left = np.array([[10.0, 0, 0], [0, 10.0, 0], [0, 0, -10.0]])   # left-handed
     with pytest.raises(L.NepError) as e:
-        pimd.observables(z, z.float(), W, E, tri, out)
-    assert e.value.code == 3
+        pimd.observables(z, z.float(), W, E, left, out)
+    assert e.value.code == 1
     mu = torch.zeros(3, dtype=torch.float64, device=dev)
     for kw in (dict(beta=-1.0, tau_p=100.0), dict(beta=0.01, tau_p=0.0), dict(beta=float("nan"), tau_p=10.0)):
         with pytest.raises(L.NepError):
