@@ -84,6 +84,7 @@ struct nep_nlist {
     std::vector<int> off;         // host [nsys+1]
     std::vector<double> boxL;     // host [nsys][9] cells of the last build (0: none yet)
     float margin = 0.0f;          // FP32 pre-test margin of the last build's geometry
+    int any_tri = 0;              // some system of the last build has a general (triclinic) cell
     nep::SysGeom *geom = nullptr; // [nsys]
     int32_t *atom_sys = nullptr;  // [N]
     int32_t *cell_sys = nullptr;  // [ncell_alloc]
@@ -318,9 +319,11 @@ __device__ __forceinline__ double mic_r2_exact_tri(const double *ri, const doubl
 }
 
 // Minimum-image vector in place (FP64; cell-list and centroid distances).
-__device__ __forceinline__ void mic_vec(double d[3], const SysGeom &g)
+// tri: the cell is a general one (g.tri; a compile-time false removes the
+// general branch from orthorhombic-only kernels).
+__device__ __forceinline__ void mic_vec(double d[3], const SysGeom &g, bool tri)
 {
-    if (!g.tri) {
+    if (!tri) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) d[a] -= g.L[a] * rint(d[a] * g.invL[a]);
         return;
@@ -375,19 +378,19 @@ struct CutTest {
     double rc2;
 };
 __device__ __forceinline__ bool pair_within(float r2f, const CutTest &c, const double *__restrict__ pos, int i, int j,
-                                            const SysGeom &g)
+                                            const SysGeom &g, bool tri)
 {
     if (fabsf(r2f - c.rc2f) > c.margin) return r2f < c.rc2f;
     const double ri[3] = {pos[3 * (size_t)i], pos[3 * (size_t)i + 1], pos[3 * (size_t)i + 2]};
     const double rj[3] = {pos[3 * (size_t)j], pos[3 * (size_t)j + 1], pos[3 * (size_t)j + 2]};
-    return (g.tri ? mic_r2_exact_tri(ri, rj, g.H, g.G) : mic_r2_exact(ri, rj, g.L, g.invL)) < c.rc2;
+    return (tri ? mic_r2_exact_tri(ri, rj, g.H, g.G) : mic_r2_exact(ri, rj, g.L, g.invL)) < c.rc2;
 }
 
-// r_j - r_i from packed positions of the system's fine grid.
-__device__ __forceinline__ void packed_pair_g(const float4 &pj, const float4 &pi, const SysGeom &g, float &dx,
-                                              float &dy, float &dz)
+// r_j - r_i from packed positions of the system's fine grid (tri as for mic_vec).
+__device__ __forceinline__ void packed_pair_g(const float4 &pj, const float4 &pi, const SysGeom &g, bool tri,
+                                              float &dx, float &dy, float &dz)
 {
-    if (g.tri) packed_pair_tri(pj, pi, g.M, g.hv, dx, dy, dz);
+    if (tri) packed_pair_tri(pj, pi, g.M, g.hv, dx, dy, dz);
     else packed_pair(pj, pi, g.M, g.h, dx, dy, dz);
 }
 

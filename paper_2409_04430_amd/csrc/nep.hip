@@ -166,7 +166,7 @@ constexpr int kNetGlobal = 0, kNetLds = 1, kNetBf16 = 2;
 
 // ----------------------------------------------------------- pass 1 ---
 
-template <int NR1, int NA1, int KR1, int KA1, bool FOUR, int NET>
+template <int NR1, int NA1, int KR1, int KA1, bool FOUR, int NET, bool TRI>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void k_descriptor(NepArgs a, const float *__restrict__ prm)
 {
@@ -244,7 +244,7 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                 for (int u = 0; u < kBatch; ++u) {
                     if (in[u]) {
                         float dx, dy, dz;
-                        pair_vec(pj[u], pi, lm, dx, dy, dz);
+                        pair_vec<TRI>(pj[u], pi, lm, dx, dy, dz);
                         const float r2 = dx * dx + dy * dy + dz * dz;
                         {
                             // sk[0] collects f_c, sk[k > 0] collects f_c T_k
@@ -306,7 +306,7 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                 }
                 if (!inc) continue;
                 float dx, dy, dz;
-                pair_vec(pc, pi, lm, dx, dy, dz);
+                pair_vec<TRI>(pc, pi, lm, dx, dy, dz);
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 const float rinv = __builtin_amdgcn_rsqf(r2);
                 const float r = r2 * rinv;
@@ -504,7 +504,7 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
 // past their atom's last candidate or outside the cutoff compute on a dummy
 // pair and contribute nothing; a candidate outside for every lane is
 // skipped.
-template <int NA1, int KA1, bool BREG>
+template <int NA1, int KA1, bool BREG, bool TRI>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void k_force_ang(NepArgs a, const float *__restrict__ prm)
 {
@@ -569,7 +569,7 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
                 }
                 if (__ballot(act) == 0) continue;
                 float dx, dy, dz;
-                pair_vec(pj, pi, lm, dx, dy, dz);
+                pair_vec<TRI>(pj, pi, lm, dx, dy, dz);
                 if (!act) {
                     dx = 1.0f;
                     dy = 0.0f;
@@ -664,7 +664,7 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
 // bead-minor), then the reverse angular terms -dU_j/dr_ji that the angular
 // pass deposited at this atom's slots, then the angular own part.  Force and
 // per-atom virial sums are kept in FP64.
-template <int KR1>
+template <int KR1, bool TRI>
 __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
 {
     const LaneMap lm = lane_map(a);
@@ -717,7 +717,7 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
                 for (int u = 0; u < kBatch; ++u) {
                     if (in[u]) {
                         float dx, dy, dz;
-                        pair_vec(pj[u], pi, lm, dx, dy, dz);
+                        pair_vec<TRI>(pj[u], pi, lm, dx, dy, dz);
                         const float r2 = dx * dx + dy * dy + dz * dz;
                         const float rinv = __builtin_amdgcn_rsqf(r2);
                         const float r = r2 * rinv;
@@ -771,7 +771,7 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
                 for (int u = 0; u < kBatch; ++u) {
                     if (!in[u]) continue;
                     float dx, dy, dz;
-                    pair_vec(p4[(size_t)(rowA[kk[u]] >> 2) * P + b], pi, lm, dx, dy, dz);
+                    pair_vec<TRI>(p4[(size_t)(rowA[kk[u]] >> 2) * P + b], pi, lm, dx, dy, dz);
                     const float4 dd = d[u];
                     // reverse half of the per-atom split: +1/2 r_ij (x) dU_j/dr_ji
                     const float hx = 0.5f * dx, hy = 0.5f * dy, hz = 0.5f * dz;
@@ -839,8 +839,8 @@ __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partE
 
 constexpr size_t kNetLdsMax = 60 * 1024;   // bytes of LDS for the staged network weights
 
-template <int NR1, int NA1, bool FOUR, bool MF = false>
-static void launch(const NepArgs &a, const float *prm, int nblk, int wpb, hipStream_t s)
+template <int NR1, int NA1, bool FOUR, bool MF, bool TRI>
+static void launch_t(const NepArgs &a, const float *prm, int nblk, int wpb, hipStream_t s)
 {
     const dim3 g(nblk);
     const dim3 blk(64 * wpb);
@@ -849,21 +849,30 @@ static void launch(const NepArgs &a, const float *prm, int nblk, int wpb, hipStr
         constexpr int D = Dims<NR1, NA1, FOUR>::D, DP = (D + 3) & ~3;
         const size_t net = sizeof(float) * (size_t)a.S * a.H * (DP + 2);
         if constexpr (MF)   // BF16 weights of the student
-            hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetBf16>), g, blk,
+            hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetBf16, TRI>), g, blk,
                                sizeof(float) * kMfWave * wpb, s, a, prm);
         else if (net <= kNetLdsMax)   // network weights staged in LDS
-            hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetLds>), g, blk, net, s, a, prm);
+            hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetLds, TRI>), g, blk, net, s, a, prm);
         else
-            hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetGlobal>), g, blk, 0, s, a, prm);
+            hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetGlobal, TRI>), g, blk, 0, s, a, prm);
     }
     {
         ProfScope ps_(K_FORCE_ANG, s);
-        hipLaunchKernelGGL((k_force_ang<NA1, 9, (NA1 <= 5)>), g, blk, 0, s, a, prm);
+        hipLaunchKernelGGL((k_force_ang<NA1, 9, (NA1 <= 5), TRI>), g, blk, 0, s, a, prm);
     }
     {
         ProfScope ps_(K_FORCE, s);
-        hipLaunchKernelGGL((k_force_rad<9>), g, blk, 0, s, a);
+        hipLaunchKernelGGL((k_force_rad<9, TRI>), g, blk, 0, s, a);
     }
+}
+
+// General (triclinic) cells get the kernels with the general pair vector;
+// orthorhombic-only lists the ones without it.
+template <int NR1, int NA1, bool FOUR, bool MF = false>
+static void launch(const NepArgs &a, const float *prm, int nblk, int wpb, bool tri, hipStream_t s)
+{
+    if (tri) launch_t<NR1, NA1, FOUR, MF, true>(a, prm, nblk, wpb, s);
+    else launch_t<NR1, NA1, FOUR, MF, false>(a, prm, nblk, wpb, s);
 }
 
 }  // namespace nep
@@ -919,19 +928,19 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
         return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");
     switch (key) {
     case 440:
-        if (mf) launch<5, 5, false, true>(a, m->dev, ws->nblk, ws->wpb, s);
-        else launch<5, 5, false>(a, m->dev, ws->nblk, ws->wpb, s);
+        if (mf) launch<5, 5, false, true>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s);
+        else launch<5, 5, false>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s);
         break;
     case 441:
-        if (mf) launch<5, 5, true, true>(a, m->dev, ws->nblk, ws->wpb, s);
-        else launch<5, 5, true>(a, m->dev, ws->nblk, ws->wpb, s);
+        if (mf) launch<5, 5, true, true>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s);
+        else launch<5, 5, true>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s);
         break;
     case 640:
-        if (mf) launch<7, 5, false, true>(a, m->dev, ws->nblk, ws->wpb, s);
-        else launch<7, 5, false>(a, m->dev, ws->nblk, ws->wpb, s);
+        if (mf) launch<7, 5, false, true>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s);
+        else launch<7, 5, false>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s);
         break;
-    case 860: launch<9, 7, false>(a, m->dev, ws->nblk, ws->wpb, s); break;
-    case 881: launch<9, 9, true>(a, m->dev, ws->nblk, ws->wpb, s); break;
+    case 860: launch<9, 7, false>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s); break;
+    case 881: launch<9, 9, true>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s); break;
     default: return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");
     }
     {

@@ -80,10 +80,14 @@ __device__ __forceinline__ void block_range(const int32_t *uend, int i, int t, i
 }
 
 // Pair vector r_j - r_i from packed positions (see FineGrid).
+// TRI: the launch covers general (triclinic) cells, each lane's system
+// choosing its form (a uniform branch); orthorhombic-only launches take
+// TRI = false and carry no general-cell code.
+template <bool TRI>
 __device__ __forceinline__ void pair_vec(const float4 &pj, const float4 &pi, const LaneMap &lm, float &dx, float &dy,
                                          float &dz)
 {
-    if (lm.tri) packed_pair_tri(pj, pi, lm.M, lm.hv, dx, dy, dz);   // wave-uniform branch
+    if (TRI && lm.tri) packed_pair_tri(pj, pi, lm.M, lm.hv, dx, dy, dz);
     else packed_pair(pj, pi, lm.M, lm.h, dx, dy, dz);
 }
 

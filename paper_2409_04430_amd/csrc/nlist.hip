@@ -420,7 +420,7 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
                 }
                 if (w >= 0 && (w >> 2) != i) {
                     double d[3] = {p[0] - ci[0], p[1] - ci[1], p[2] - ci[2]};
-                    mic_vec(d, g);
+                    mic_vec(d, g, g.tri);
                     const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
                     okR = r2 < R2;
                     okA = r2 < RA2;
@@ -525,6 +525,7 @@ __global__ __launch_bounds__(256) void k_sort_rows(const uint32_t *__restrict__ 
 // appended with one ballot-ranked store per lane.
 constexpr double kShellEps = 1e-3;   // A; far above the rounding of d and s
 
+template <bool TRI>
 __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, const float4 *__restrict__ pos4,
                                                const double *__restrict__ cen, const float *__restrict__ spr, int P,
                                                int N, int S, int lg, const int32_t *__restrict__ atom_sys,
@@ -569,6 +570,7 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
     const float4 pi = pos4[(size_t)i * P + bb];
     const double *pb = pos + (size_t)bb * N * 3;
     const SysGeom &g = geom[atom_sys[i]];
+    const bool tri = TRI && g.tri;   // orthorhombic-only launches carry no general-cell code
     const uint64_t gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
     const uint64_t full = (P == 64) ? ~0ull : ((1ull << P) - 1ull);
     const double ci0 = cen[3 * (size_t)i], ci1 = cen[3 * (size_t)i + 1], ci2 = cen[3 * (size_t)i + 2];
@@ -590,7 +592,7 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
             const bool kin = k < k1;
             const int j = kin ? row[k] >> 2 : i;
             double dv[3] = {cen[3 * (size_t)j] - ci0, cen[3 * (size_t)j + 1] - ci1, cen[3 * (size_t)j + 2] - ci2};
-            mic_vec(dv, g);
+            mic_vec(dv, g, tri);
             const double d = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
             const double sp = si + (double)spr[j];
             const bool all_in = kin && d + sp < rc - kShellEps;
@@ -609,9 +611,9 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
                 }
                 const int jq = __shfl(j, my, 64);
                 float ex, ey, ez;
-                packed_pair_g(pos4[(size_t)jq * P + bb], pi, g, ex, ey, ez);
+                packed_pair_g(pos4[(size_t)jq * P + bb], pi, g, tri, ex, ey, ez);
                 const float r2f = ex * ex + ey * ey + ez * ez;
-                const bool in = cg < nq && bead_ok && pair_within(r2f, c, pb, i, jq, g);
+                const bool in = cg < nq && bead_ok && pair_within(r2f, c, pb, i, jq, g, tri);
                 const uint64_t m = __ballot(in);
                 for (int q = 0; q < nq; ++q) {
                     const int sq = __builtin_ctzll(take);
@@ -668,8 +670,8 @@ __global__ __launch_bounds__(256) void k_materialize(const double *__restrict__ 
         for (int k = 0; k < n; ++k) {
             const int j = row[k] >> 2;
             float dx, dy, dz;
-            packed_pair_g(pos4[(size_t)j * P + b], pi, g, dx, dy, dz);
-            if (pair_within(dx * dx + dy * dy + dz * dz, c, pb, i, j, g)) {
+            packed_pair_g(pos4[(size_t)j * P + b], pi, g, g.tri, dx, dy, dz);
+            if (pair_within(dx * dx + dy * dy + dz * dz, c, pb, i, j, g, g.tri)) {
                 if (cnt < out) nb[(size_t)cnt * N] = j;
                 ++cnt;
             }
@@ -747,6 +749,8 @@ int32_t update_geometry(const nep_model *m, nep_nlist *nl, const double *boxes, 
     }
     margin = (float)(1e-3 * std::max(1.0, hmax * hmax) * std::max(1.0, rc * rc / 36.0));
     nl->margin = margin;
+    nl->any_tri = 0;
+    for (int s = 0; s < nl->nsys; ++s) nl->any_tri |= G[s].tri;
     if (!changed) return NEP_OK;
     if (cell_total > nl->ncell_alloc) {
         for (int32_t **p : {&nl->cell_cnt, &nl->cell_start, &nl->cell_sys}) {
@@ -834,7 +838,8 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
         const double rR2 = m->hp.rc_radial * m->hp.rc_radial, rA2 = m->hp.rc_angular * m->hp.rc_angular;
         const CutTest cR{(float)rR2, margin, rR2};
         const CutTest cA{(float)rA2, margin, rA2};
-        hipLaunchKernelGGL(k_union, dim3(div_up(N, kBlock / 64), 2), dim3(kBlock), 0, s, pos,
+        auto kern = nl->any_tri ? k_union<true> : k_union<false>;
+        hipLaunchKernelGGL(kern, dim3(div_up(N, kBlock / 64), 2), dim3(kBlock), 0, s, pos,
                            reinterpret_cast<const float4 *>(nl->pos4), nl->cen, nl->spr, P, N, nl->S, lg, nl->atom_sys, nl->geom, cR,
                            cA, nl->candR, nl->offR, nl->candA, nl->offA, nl->capR, nl->capA, nl->uniR, nl->umR,
                            nl->uendR, nl->uniA, nl->umA, nl->uendA, nl->status, nl->grid, types, nl->revA);

@@ -161,7 +161,7 @@ void k_train_jvp(NepArgs a, TrainArgs ta, const float *__restrict__ prm)
                 if (!((mR[s] >> b) & 1u)) continue;
                 const int j = uR[s];
                 float dx, dy, dz;
-                pair_vec(p4[(size_t)j * P + b], pi, lm, dx, dy, dz);
+                pair_vec<true>(p4[(size_t)j * P + b], pi, lm, dx, dy, dz);
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 const float rinv = __builtin_amdgcn_rsqf(r2);
                 const float r = r2 * rinv;
@@ -209,7 +209,7 @@ void k_train_jvp(NepArgs a, TrainArgs ta, const float *__restrict__ prm)
                 if (!((mA[s] >> b) & 1u)) continue;
                 const int j = rowA[uA[s]] >> 2;
                 float dx, dy, dz;
-                pair_vec(p4[(size_t)j * P + b], pi, lm, dx, dy, dz);
+                pair_vec<true>(p4[(size_t)j * P + b], pi, lm, dx, dy, dz);
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 const float rinv = __builtin_amdgcn_rsqf(r2);
                 const float r = r2 * rinv;
@@ -347,7 +347,7 @@ void k_train_jvp(NepArgs a, TrainArgs ta, const float *__restrict__ prm)
                     if (!((mA[s] >> b) & 1u)) continue;
                     const int j = rowA[uA[s]] >> 2;
                     float dx, dy, dz;
-                    pair_vec(p4[(size_t)j * P + b], pi, lm, dx, dy, dz);
+                    pair_vec<true>(p4[(size_t)j * P + b], pi, lm, dx, dy, dz);
                     const float r2 = dx * dx + dy * dy + dz * dz;
                     const float rinv = __builtin_amdgcn_rsqf(r2);
                     const float r = r2 * rinv;
