@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--no-profile", action="store_true", help="do not bracket kernels with timing events")
     ap.add_argument("--no-student", action="store_true", help="skip the learned-student leg")
     ap.add_argument("--no-npt", action="store_true", help="skip the barostat (NPT) leg")
+    ap.add_argument("--no-triclinic", action="store_true", help="skip the general-cell leg")
     ap.add_argument("--npt-steps", type=int, default=50, help="timed steps of the NPT leg")
     ap.add_argument("--student-only", action="store_true",
                     help="run only the learned-student leg (prints its JSON object)")
@@ -205,6 +206,43 @@ def npt_leg(args, torch, lib, w, model_path, s, NepPimd, nvt_ms: float):
                                        "bytes_per_launch": int(per * units), "avg_us": round(kernels[name], 2)}
     del eng
     return out
+
+
+def triclinic_leg(args, torch, lib, w, model_path, s, NepPimd, nvt_ms: float):
+    """The same periodic system described by the sheared cell (a + b, b, c + a)
+    of its own lattice: the general-cell kernels on the same work."""
+    import dataclasses
+    H = np.array([[1.0, 1.0, 0.0], [0.0, 1.0, 0.0], [1.0, 0.0, 1.0]]) @ np.diag(np.asarray(s.box, np.float64))
+    st = dataclasses.replace(s, box=H)
+    eng = NepPimd(model_path, st, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=0)
+    eng.run(5)
+    eng.check()
+    kernels = {}
+    if not args.no_profile:
+        lib.profile_read(reset=True)
+        lib.profile_enable(True)
+        eng.run(10)
+        torch.cuda.synchronize()
+        lib.profile_enable(False)
+        kt = lib.profile_read(reset=True)
+        kernels = {k: round(1e3 * v[0] / v[1], 2) for k, v in kt.items() if v[1]}
+    rb_prof = int(eng.nl.status(clear=True)["rebuilds"])
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    n = max(20, min(100, args.steps))
+    torch.cuda.synchronize()
+    e0.record(stream)
+    eng.run(n)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    eng.check()
+    ms = e0.elapsed_time(e1) / n
+    rb = int(eng.nl.status(clear=True)["rebuilds"])
+    del eng
+    return {"cell_rows_A": H.round(6).tolist(), "steps": n, "ms_per_step": round(ms, 4),
+            "value": round(s.N * s.P / (ms * 1e-3), 1), "vs_orthorhombic_step": round(ms / nvt_ms, 3),
+            "rebuilds_timed": rb, "rebuilds_in_profiled_steps": rb_prof, "kernels_us": kernels}
 
 
 def student_leg(args, torch, lib, configs, I):
@@ -410,6 +448,9 @@ def main():
     npt = None
     if not args.no_npt:
         npt = npt_leg(args, torch, lib, w, model_path, s, NepPimd, gpu_ms / args.steps)
+    tri = None
+    if not args.no_triclinic:
+        tri = triclinic_leg(args, torch, lib, w, model_path, s, NepPimd, gpu_ms / args.steps)
     stu = None
     if not args.no_student:
         del eng
@@ -441,6 +482,7 @@ def main():
         "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
         "cpu_baseline": cpu,
         "npt": npt,
+        "triclinic": tri,
         "student_vs_teacher": stu,
     }
     print(json.dumps(out), flush=True)

@@ -320,13 +320,16 @@ __global__ void k_cell_fill(const double *__restrict__ cen, int N, const int32_t
 }
 
 
-// Candidate rows.  One workgroup per cell; the centroids of its stencil
-// cells (3 x 3 x 3, fewer along an axis with fewer than 3 cells) are staged
-// in LDS when they fit, and each wavefront takes one atom of the cell at a
-// time, its lanes testing 64 stencil atoms at once and appending the
-// accepted ones by ballot + prefix popcount (stencil order; sorted later).
-// A stencil too large for LDS is read from global memory instead.
+// Candidate rows.  gridDim.y workgroups per cell, each taking every
+// gridDim.y-th group of the cell's atoms (small or skewed cells have few
+// cells with large stencils); the centroids of the cell's stencil cells
+// (3 x 3 x 3, fewer along an axis with fewer than 3 cells) are staged in
+// LDS when they fit, and each wavefront takes one atom at a time, its lanes
+// testing 64 stencil atoms at once and appending the accepted ones by
+// ballot + prefix popcount (stencil order; sorted later).  A stencil too
+// large for LDS is read from global memory instead.
 constexpr int kStage = 2048;
+constexpr int kCandSplitMax = 16;   // workgroups per cell at most
 __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ cen, const int32_t *__restrict__ types,
                                                     int N, int S, const SysGeom *__restrict__ geom,
                                                     const int32_t *__restrict__ cell_sys, uint32_t *__restrict__ grid,
@@ -347,7 +350,7 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
     const DevSys ds = *dev_sys(grid, sy_);
     const int c = blockIdx.x - g.cell_base;   // cell within its system
     if (!dg->rebuild || c >= ds.ncell) return;   // whole workgroup
-    if (threadIdx.x == 0) cell_cnt[blockIdx.x] = 0;   // counts start from zero at the next rebuild
+    if (threadIdx.x == 0 && blockIdx.y == 0) cell_cnt[blockIdx.x] = 0;   // counts start from zero at the next rebuild
     const int nc0 = ds.nc[0], nc1 = ds.nc[1], nc2 = ds.nc[2];
     const double R2 = dg->R2, RA2 = dg->RA2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -378,11 +381,15 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
     __syncthreads();
     const int nr = nrange, total = rp[nr];
     const bool staged = total <= kStage;
-    // flat stencil position q -> index into cell_atoms
+    // flat stencil position q -> index into cell_atoms (the last range starting at or before q)
     auto at = [&](int q) {
-        int r = 0;
-        while (r + 1 < nr && rp[r + 1] <= q) ++r;
-        return rs[r] + (q - rp[r]);
+        int lo = 0, hi = nr - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rp[mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        return rs[lo] + (q - rp[lo]);
     };
     if (staged) {
         for (int q = threadIdx.x; q < total; q += blockDim.x) {
@@ -397,7 +404,8 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
     __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int a0 = cell_start[blockIdx.x], a1 = cell_start[blockIdx.x + 1];
-    for (int a = a0 + wv; a < a1; a += blockDim.x >> 6) {
+    const int waves = blockDim.x >> 6;
+    for (int a = a0 + blockIdx.y * waves + wv; a < a1; a += gridDim.y * waves) {
         const int i = cell_atoms[a];
         const double ci[3] = {cen[3 * i], cen[3 * i + 1], cen[3 * i + 2]};
         int32_t *rowR = candR + (size_t)i * capR;
@@ -800,7 +808,8 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
     pack_positions(pos, P, N, nl->atom_sys, nl->geom, reinterpret_cast<float4 *>(nl->pos4), s);
     const dim3 g1(div_up(N, kBlock));
     const dim3 gw(div_up(N, kBlock / 64));
-    const dim3 gc(nl->ncell_total);
+    // enough workgroups for the candidate search even when the cells are few
+    const dim3 gc(nl->ncell_total, std::min(kCandSplitMax, std::max(1, div_up(1024, nl->ncell_total))));
     {
         ProfScope ps_(K_CENTROID, s);
         hipLaunchKernelGGL(k_centroid, g1, dim3(kBlock), 0, s, pos, types, nl->atom_sys, P, N, nl->S, nl->cen, nl->spr,
