@@ -318,8 +318,10 @@ __global__ void k_step_advance(int64_t *step) { *step += 1; }
 // centroid is taken through the periodic boundaries: each bead is brought to
 // the image nearest the atom's first bead, r~_j = r_1 + mic(r_j - r_1), and
 // dr_j = r~_j - mean_k r~_k.  Each workgroup reduces its lanes' dr (x) F to
-// nine FP64 partial sums in a fixed order; one workgroup then reduces the
-// partials in a fixed order and forms the outputs (bitwise reproducible).
+// nine FP64 partial sums in a fixed order; a second launch of one workgroup
+// reduces the partials in a fixed order and forms the outputs (bitwise
+// reproducible).  A last-workgroup ticket in one launch was slower: the
+// device-scope fence each workgroup then needs costs more than a launch.
 
 constexpr int kObsBlock = 256;
 
@@ -333,6 +335,15 @@ struct ObsCell {
     double L[3];          // orthorhombic edges
     double H[9], G[9];    // general cell: edge vectors as rows and H^-1
     int tri;
+};
+
+struct ObsFinal {
+    const double *part;        // [nblk][9] partial sums
+    int nblk;
+    const double *Wb, *Eb;
+    int P, N;
+    double NkT, inv_vol_gpa;   // N kB T (eV); 1 / V in GPa per eV
+    double *out;
 };
 
 __global__ __launch_bounds__(kObsBlock) void k_obs_partial(const double *__restrict__ pos, const float *__restrict__ F,
@@ -388,31 +399,31 @@ __global__ __launch_bounds__(kObsBlock) void k_obs_partial(const double *__restr
         for (int k = 0; k < kObsBlock / 64; ++k) acc += red[k][threadIdx.x];
         part[(size_t)blockIdx.x * 9 + threadIdx.x] = acc;
     }
-}
 
-struct ObsFinal {
-    const double *part, *Wb, *Eb;
-    int nblk, P, N;
-    double NkT, inv_vol_gpa;   // N kB T (eV); 1 / V in GPa per eV
-    double *out;
-};
+}
 
 __global__ __launch_bounds__(kObsBlock) void k_obs_final(ObsFinal a)
 {
-    __shared__ double red[kObsBlock];
+    // nine running sums per thread over the partials, then one LDS tree
+    __shared__ double tree[9][kObsBlock];
     __shared__ double wcv[9];
-    for (int e = 0; e < 9; ++e) {
-        double acc = 0.0;
-        for (int k = threadIdx.x; k < a.nblk; k += kObsBlock) acc += a.part[(size_t)k * 9 + e];
-        red[threadIdx.x] = acc;
-        __syncthreads();
-        for (int h = kObsBlock / 2; h > 0; h >>= 1) {
-            if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) wcv[e] = red[0];
+    {
+        double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int k = threadIdx.x; k < a.nblk; k += kObsBlock)
+#pragma unroll
+            for (int e = 0; e < 9; ++e) acc[e] += a.part[(size_t)k * 9 + e];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) tree[e][threadIdx.x] = acc[e];
+    }
+    __syncthreads();
+    for (int h = kObsBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+#pragma unroll
+            for (int e = 0; e < 9; ++e) tree[e][threadIdx.x] += tree[e][threadIdx.x + h];
         __syncthreads();
     }
+    if (threadIdx.x < 9) wcv[threadIdx.x] = tree[threadIdx.x][0];
+    __syncthreads();
     if (threadIdx.x == 0) {
         double Ep = 0.0, Wp[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
         for (int j = 0; j < a.P; ++j) {
@@ -660,9 +671,9 @@ extern "C" int32_t pimd_observables(const pimd_ctx *c, const double *pos, const 
                            c->obs_part);
     ObsFinal a;
     a.part = c->obs_part;
+    a.nblk = nblk;
     a.Wb = W_bead;
     a.Eb = E_bead;
-    a.nblk = nblk;
     a.P = c->P;
     a.N = c->N;
     a.NkT = c->N * kKB * c->prm.T_K;
