@@ -138,8 +138,8 @@ struct nep_ws {
     int32_t *sys_tile0 = nullptr;   // [nsys + 1]
     float *B = nullptr;        // [N][P][NA1*24] angular adjoints dU_i/dA_nlm
     float *arad = nullptr;     // [N][S][P][12] radial adjoints sum_n dU_i/dq_n c_nk (9 used)
-    double *partE = nullptr;   // [nblk_cap][P]
-    double *partW = nullptr;   // [2][nblk_cap][P][9] (angular pass, radial pass)
+    double *partE = nullptr;   // [P][nblk] per-workgroup partial energies (bead-major)
+    double *partW = nullptr;   // angular pass [P][9][nblk], then radial pass [P][9][nblk] (room for nblk_cap)
     float *Fang = nullptr;     // [N][P][3] angular part of the forces
     uint32_t *flags = nullptr; // [1]
 };

@@ -488,7 +488,8 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
     if (valid && a.Eatom) a.Eatom[(size_t)b * a.N + i] = U;
     if (valid && !tok) atomicOr(a.flags, (uint32_t)NEP_FLAG_BAD_TYPE);
     __shared__ double lds[kBlock];
-    bead_block_sum(valid ? (double)U : 0.0, lds, P, a.lg, a.partE + (size_t)blockIdx.x * P, 1);
+    // partials bead-major, [P][workgroups]: the reduction reads them contiguously
+    bead_block_sum(valid ? (double)U : 0.0, lds, P, a.lg, a.partE + blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------ pass 2: angular, own ---
@@ -654,7 +655,8 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
     }
     __shared__ double lds[kBlock];
     for (int e = 0; e < 9; ++e)
-        bead_block_sum(valid ? (double)Wv[e] : 0.0, lds, P, a.lg, a.partWa + (size_t)blockIdx.x * P * 9 + e, 9);
+        bead_block_sum(valid ? (double)Wv[e] : 0.0, lds, P, a.lg, a.partWa + (size_t)e * gridDim.x + blockIdx.x,
+                       9 * gridDim.x);
 }
 
 // ----------------------------------------- pass 3: radial + combination ---
@@ -801,16 +803,20 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
     }
     __shared__ double lds[kBlock];
     for (int e = 0; e < 9; ++e)
-        bead_block_sum(valid ? (double)Wf[e] : 0.0, lds, P, a.lg, a.partWr + (size_t)blockIdx.x * P * 9 + e, 9);
+        bead_block_sum(valid ? (double)Wf[e] : 0.0, lds, P, a.lg, a.partWr + (size_t)e * gridDim.x + blockIdx.x,
+                       9 * gridDim.x);
 }
 
 // Per-(system, bead) totals from the per-workgroup partial sums of the
 // system's tiles.  One workgroup per (system, bead): thread t adds tiles
 // t, t + 256, ... in order, then a fixed-shape tree over the threads, so the
 // result is bitwise reproducible.  Component 0 is E, 1..9 the virial.
+// Per-bead energy and virial of each system from the workgroups' partials,
+// stored [P][nblk] (energy) and [P][9][nblk] (virial parts): one workgroup
+// per (system, bead), fixed order.
 __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partE, const double *__restrict__ partWa,
                                                 const double *__restrict__ partWr, const int32_t *__restrict__ sys_tile0,
-                                                int P, double *__restrict__ E, double *__restrict__ W)
+                                                int P, int nblk, double *__restrict__ E, double *__restrict__ W)
 {
     __shared__ double red[10][256];
     const int sb = blockIdx.x, sy = sb / P, b = sb - sy * P, t = threadIdx.x;
@@ -819,10 +825,12 @@ __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partE
 #pragma unroll
     for (int c = 0; c < 10; ++c) acc[c] = 0.0;
     for (int k = k0 + t; k < k1; k += blockDim.x) {
-        acc[0] += partE[(size_t)k * P + b];
-        const size_t o = ((size_t)k * P + b) * 9;
+        acc[0] += partE[(size_t)b * nblk + k];
 #pragma unroll
-        for (int c = 0; c < 9; ++c) acc[c + 1] += partWa[o + c] + partWr[o + c];
+        for (int c = 0; c < 9; ++c) {
+            const size_t o = ((size_t)b * 9 + c) * nblk + k;
+            acc[c + 1] += partWa[o] + partWr[o];
+        }
     }
 #pragma unroll
     for (int c = 0; c < 10; ++c) red[c][t] = acc[c];
@@ -946,7 +954,7 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
     {
         ProfScope ps_(K_REDUCE, s);
         hipLaunchKernelGGL(k_reduce, dim3(nsys * P), dim3(256), 0, s, ws->partE, a.partWa, a.partWr, ws->sys_tile0,
-                           P, E, W);
+                           P, ws->nblk, E, W);
     }
     NEP_HIP(hipGetLastError());
     return NEP_OK;

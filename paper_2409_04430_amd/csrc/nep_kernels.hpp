@@ -28,7 +28,7 @@ struct NepArgs {
     float *B;            // [N][P][NA1*24]
     float *arad;         // [N][S][P][kRadPad] radial adjoints, 9 used
     float *Fang;         // [N][P][3]
-    double *partE, *partWa, *partWr;   // [blocks][P], [blocks][P][9]
+    double *partE, *partWa, *partWr;   // [P][blocks], [P][9][blocks]
     uint32_t *flags;
     // outputs
     float *F;

@@ -39,7 +39,7 @@ struct DevGlobal {
     float d_build;          // D at the last rebuild
     uint32_t rows_overflow; // a candidate row of the last rebuild was truncated
     int rebuild;            // 1: rebuild the candidate rows in this call
-    uint32_t ticket;        // workgroups of k_centroid finished in this call (reset by the last)
+    uint32_t ticket;        // workgroups of k_cell_count finished in this call (reset by the last)
     double R2;              // radial candidate radius squared of the last rebuild
     double RA2;             // angular candidate radius squared
 };
@@ -96,6 +96,10 @@ __device__ __forceinline__ void raise_max(uint32_t *word, uint32_t v)
 __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double rcR, double rcA, double skin,
                               int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status);
 
+// Four lanes per atom (adjacent), each summing every fourth bead; the
+// atom's sums and the bead spread meet by shuffles, and the atom's first
+// lane writes its centroid and spread.
+constexpr int kCenLanes = 4;
 __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ pos, const int32_t *__restrict__ types,
                                                      const int32_t *__restrict__ atom_sys,
                                                      int P, int N, int S, double *__restrict__ cen,
@@ -104,26 +108,37 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
                                                      double rcA, double skin, int force, uint32_t *__restrict__ grid,
                                                      uint32_t *__restrict__ status)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = t / kCenLanes, q = t % kCenLanes;
+    const bool has = i < N;
     uint32_t f = 0;
     float spread = 0.0f, disp = 0.0f;
-    if (i < N) {
-        const size_t st = (size_t)N * 3;
-        double c[3] = {0.0, 0.0, 0.0};
-        for (int b = 0; b < P; ++b) {
+    const size_t st = (size_t)N * 3;
+    double c[3] = {0.0, 0.0, 0.0};
+    if (has)
+        for (int b = q; b < P; b += kCenLanes) {
             const double *p = pos + b * st + 3 * (size_t)i;
             c[0] += p[0];
             c[1] += p[1];
             c[2] += p[2];
         }
-        const double inv = 1.0 / P;
-        c[0] *= inv; c[1] *= inv; c[2] *= inv;
-        double m2 = 0.0;
-        for (int b = 0; b < P; ++b) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        c[a] += __shfl_xor(c[a], 1);
+        c[a] += __shfl_xor(c[a], 2);
+    }
+    const double inv = 1.0 / P;
+    c[0] *= inv; c[1] *= inv; c[2] *= inv;
+    double m2 = 0.0;
+    if (has)
+        for (int b = q; b < P; b += kCenLanes) {
             const double *p = pos + b * st + 3 * (size_t)i;
             const double dx = p[0] - c[0], dy = p[1] - c[1], dz = p[2] - c[2];
             m2 = fmax(m2, dx * dx + dy * dy + dz * dz);
         }
+    m2 = fmax(m2, __shfl_xor(m2, 1));
+    m2 = fmax(m2, __shfl_xor(m2, 2));
+    if (has && q == 0) {
         cen[3 * i] = c[0];
         cen[3 * i + 1] = c[1];
         cen[3 * i + 2] = c[2];
@@ -146,8 +161,8 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
             const double d2 = dx * dx + dy * dy + dz * dz;
             disp = isfinite(d2) ? (float)sqrt(d2) * 1.000001f + 1e-7f : 3.0e38f;
         }
-        const int t = types[i];
-        if (t < 0 || t >= S) f |= NEP_FLAG_BAD_TYPE;
+        const int ty = types[i];
+        if (ty < 0 || ty >= S) f |= NEP_FLAG_BAD_TYPE;
     }
     // one atomic per workgroup and word (same-address atomics serialise)
     __shared__ float red[2][kBlock / 64];
@@ -168,18 +183,14 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
         if (disp > 0.0f) atomicMax(&grid[1], __float_as_uint(disp));
     }
     if (f) atomicOr(&status[0], f);
+}
 
-    // the last workgroup to finish takes the rebuild decision (no waiting:
-    // every other workgroup has already retired its maxima when it counts)
-    __shared__ int last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&dev_global(grid)->ticket, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;   // whole workgroup
-    __threadfence();
+// The rebuild decision after every workgroup's maxima (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_decide(const SysGeom *__restrict__ geom, int nsys, double rcR,
+                                                   double rcA, double skin, int force, uint32_t *__restrict__ grid,
+                                                   uint32_t *__restrict__ status)
+{
     grid_decision(geom, nsys, rcR, rcA, skin, force, grid, status);
-    if (threadIdx.x == 0) dev_global(grid)->ticket = 0u;
 }
 
 // Rebuild decision and, on a rebuild, the grid and candidate radius from the
@@ -192,8 +203,9 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
 // bead pair inside the cutoff has |e| < rc + 2 D, so the rows stay complete
 // while (rc + 2 D + 2 max|dc|) / lambda_min - rc - 2 D0 <= skin for both
 // cutoffs (for an unchanged box: 2 (D - D0) + 2 max|dc| <= skin); otherwise
-// they are rebuilt.  Run by the last workgroup of k_centroid, after every
-// workgroup's maxima.
+// they are rebuilt.  Run by k_decide, one workgroup launched after
+// k_centroid (a last-workgroup ticket inside k_centroid cost more: every
+// workgroup then needs a device-scope fence).
 __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double rcR, double rcA, double skin,
                               int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status)
 {
@@ -812,10 +824,13 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
     const dim3 gc(nl->ncell_total, std::min(kCandSplitMax, std::max(1, div_up(1024, nl->ncell_total))));
     {
         ProfScope ps_(K_CENTROID, s);
-        hipLaunchKernelGGL(k_centroid, g1, dim3(kBlock), 0, s, pos, types, nl->atom_sys, P, N, nl->S, nl->cen, nl->spr,
+        hipLaunchKernelGGL(k_centroid, dim3(div_up(N * kCenLanes, kBlock)), dim3(kBlock), 0, s, pos, types,
+                           nl->atom_sys, P, N, nl->S, nl->cen, nl->spr,
                            nl->cen_ref,
                            nl->geom, nl->nsys, m->hp.rc_radial, m->hp.rc_angular, nl->skin, force ? 1 : 0, nl->grid,
                            nl->status);
+        hipLaunchKernelGGL(k_decide, dim3(1), dim3(kBlock), 0, s, nl->geom, nl->nsys, m->hp.rc_radial,
+                           m->hp.rc_angular, nl->skin, force ? 1 : 0, nl->grid, nl->status);
     }
     {
         ProfScope ps_(K_CELL_COUNT, s);
