@@ -332,14 +332,57 @@ __global__ void k_cell_fill(const double *__restrict__ cen, int N, const int32_t
 }
 
 
+// Sort one candidate row by (species, index) in place and record its species
+// block starts: rank sort by one wavefront (each element's position is the
+// number of smaller keys), reading the row from buf (rows up to kSortLds
+// entries, in LDS) or from the atom's row of a scratch array.
+constexpr int kSortLds = 512;
+__device__ void sort_row(int32_t *__restrict__ row, int n, int32_t *__restrict__ src, int S,
+                         int32_t *__restrict__ off)
+{
+    const int lane = threadIdx.x & 63;
+    for (int e = lane; e < n; e += 64) src[e] = row[e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // key: species above index; entries are distinct
+    auto key = [](int32_t w) { return ((uint32_t)(w & 3) << 29) | (uint32_t)(w >> 2); };
+    int cntS[kMaxSpecies] = {0, 0, 0, 0};
+    for (int e = lane; e < n; e += 64) {
+        const int32_t w = src[e];
+        const uint32_t kw = key(w);
+        int r = 0;
+        for (int f = 0; f < n; ++f) r += key(src[f]) < kw;
+        row[r] = w;
+#pragma unroll
+        for (int t = 0; t < kMaxSpecies; ++t) cntS[t] += (w & 3) == t;
+    }
+#pragma unroll
+    for (int t = 0; t < kMaxSpecies; ++t)
+        for (int o = 32; o > 0; o >>= 1) cntS[t] += __shfl_xor(cntS[t], o);
+    if (lane == 0) {
+        int run = 0;
+        for (int t = 0; t < S; ++t) {
+            off[t] = run;
+            run += cntS[t];
+        }
+        off[S] = run;
+    }
+    // the buffer is reused by the next row of this wavefront
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // Candidate rows.  gridDim.y workgroups per cell, each taking every
 // gridDim.y-th group of the cell's atoms (small or skewed cells have few
 // cells with large stencils); the centroids of the cell's stencil cells
 // (3 x 3 x 3, fewer along an axis with fewer than 3 cells) are staged in
 // LDS when they fit, and each wavefront takes one atom at a time, its lanes
 // testing 64 stencil atoms at once and appending the accepted ones by
-// ballot + prefix popcount (stencil order; sorted later).  A stencil too
-// large for LDS is read from global memory instead.
+// ballot + prefix popcount (stencil order).  A stencil too large for LDS is
+// read from global memory instead.  Then every wavefront sorts the rows it
+// wrote (sort_row), with the staging buffer as sort space.
 constexpr int kStage = 2048;
 constexpr int kCandSplitMax = 16;   // workgroups per cell at most
 __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ cen, const int32_t *__restrict__ types,
@@ -350,7 +393,9 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
                                                     int32_t *__restrict__ cell_cnt, int capR, int capA,
                                                     int32_t *__restrict__ candR, int32_t *__restrict__ lenR,
                                                     int32_t *__restrict__ candA, int32_t *__restrict__ lenA,
-                                                    double *__restrict__ cen_ref, uint32_t *__restrict__ status)
+                                                    double *__restrict__ cen_ref, uint32_t *__restrict__ status,
+                                                    int32_t *__restrict__ offR, int32_t *__restrict__ offA,
+                                                    int32_t *__restrict__ scratchR, int32_t *__restrict__ scratchA)
 {
     __shared__ double sx[kStage], sy[kStage], sz[kStage];
     __shared__ int32_t sw[kStage];
@@ -467,65 +512,21 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
             }
         }
     }
+    // sort the rows this wavefront wrote; the stencil staging is free once
+    // every wavefront of the workgroup has left its atom loop
+    static_assert(kStage >= (kBlock / 64) * kSortLds, "sort buffers exceed the staging space");
+    __syncthreads();
+    int32_t *sbuf = sw + wv * kSortLds;
+    for (int a = a0 + blockIdx.y * waves + wv; a < a1; a += gridDim.y * waves) {
+        const int i = cell_atoms[a];
+        const int nR = min(lenR[i], capR), nA = min(lenA[i], capA);
+        sort_row(candR + (size_t)i * capR, nR, nR <= kSortLds ? sbuf : scratchR + (size_t)i * capR, S,
+                 offR + (size_t)i * (kMaxSpecies + 1));
+        sort_row(candA + (size_t)i * capA, nA, nA <= kSortLds ? sbuf : scratchA + (size_t)i * capA, S,
+                 offA + (size_t)i * (kMaxSpecies + 1));
+    }
 }
 
-// Sort each candidate row by (species, index) and record the species block
-// starts.  One wavefront per atom: rank sort (each element's position is the
-// number of smaller keys), in LDS for rows up to kSortLds, otherwise through
-// the atom's reverse-slot row as scratch (it is rewritten afterwards).
-constexpr int kSortLds = 512;
-struct SortRows {
-    int capC;
-    int32_t *cand;
-    const int32_t *rowlen;
-    int32_t *off, *scratch;
-};
-__global__ __launch_bounds__(256) void k_sort_rows(const uint32_t *__restrict__ grid, int N, int S, SortRows r0,
-                                                   SortRows r1)
-{
-    if (!dev_global(grid)->rebuild) return;   // whole workgroup
-    const SortRows &r = blockIdx.y ? r1 : r0;   // radial or angular rows
-    const int capC = r.capC;
-    int32_t *__restrict__ cand = r.cand;
-    const int32_t *__restrict__ rowlen = r.rowlen;
-    int32_t *__restrict__ off = r.off;
-    int32_t *__restrict__ scratch = r.scratch;
-    __shared__ int32_t buf[kBlock / 64][kSortLds];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int i = blockIdx.x * (kBlock / 64) + wv;
-    if (i >= N) return;   // whole wavefront
-    const int n = min(rowlen[i], capC);
-    int32_t *row = cand + (size_t)i * capC;
-    const bool lds = n <= kSortLds;
-    int32_t *src = lds ? buf[wv] : scratch + (size_t)i * capC;
-    for (int e = lane; e < n; e += 64) src[e] = row[e];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    // key: species above index; entries are distinct
-    auto key = [](int32_t w) { return ((uint32_t)(w & 3) << 29) | (uint32_t)(w >> 2); };
-    int cntS[kMaxSpecies] = {0, 0, 0, 0};
-    for (int e = lane; e < n; e += 64) {
-        const int32_t w = src[e];
-        const uint32_t kw = key(w);
-        int r = 0;
-        for (int f = 0; f < n; ++f) r += key(src[f]) < kw;
-        row[r] = w;
-#pragma unroll
-        for (int t = 0; t < kMaxSpecies; ++t) cntS[t] += (w & 3) == t;
-    }
-#pragma unroll
-    for (int t = 0; t < kMaxSpecies; ++t)
-        for (int o = 32; o > 0; o >>= 1) cntS[t] += __shfl_xor(cntS[t], o);
-    if (lane == 0) {
-        int run = 0;
-        for (int t = 0; t < S; ++t) {
-            off[(size_t)i * (kMaxSpecies + 1) + t] = run;
-            run += cntS[t];
-        }
-        off[(size_t)i * (kMaxSpecies + 1) + S] = run;
-    }
-}
 
 
 // Union lists.  One wavefront per atom and list (grid.y picks the radial or
@@ -847,14 +848,7 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
         hipLaunchKernelGGL(k_candidates, gc, dim3(kBlock), 0, s, nl->cen, types, N, nl->S, nl->geom, nl->cell_sys,
                            nl->grid, nl->cell_start, nl->cell_atoms, nl->cell_cnt, nl->capR, nl->capA, nl->candR,
                            nl->lenR,
-                           nl->candA, nl->lenA, nl->cen_ref, nl->status);
-    }
-    {
-        // the union-list and reverse-slot arrays serve as sort scratch before they are filled
-        ProfScope ps_(K_SORT_ROWS, s);
-        const SortRows rr{nl->capR, nl->candR, nl->lenR, nl->offR, nl->uniR};
-        const SortRows ra{nl->capA, nl->candA, nl->lenA, nl->offA, nl->revA};
-        hipLaunchKernelGGL(k_sort_rows, dim3(gw.x, 2), dim3(kBlock), 0, s, nl->grid, N, nl->S, rr, ra);
+                           nl->candA, nl->lenA, nl->cen_ref, nl->status, nl->offR, nl->offA, nl->uniR, nl->revA);
     }
     {
         ProfScope ps_(K_NLIST, s);
