@@ -112,28 +112,6 @@ FineGrid fine_grid(const double L[3], double rc)
     return g;
 }
 
-// Per axis: fine cell c = floor(x / h) mod M and offset x - floor(x / h) h
-// (unwrapped coordinates allowed) on the fine grid of the atom's system;
-// non-finite input gives a NaN offset.  Reads pos [P][N][3], writes out
-// [N][P] (bead-minor).
-__global__ void k_pack(const double *__restrict__ pos, int P, int N, const int32_t *__restrict__ atom_sys,
-                       const SysGeom *__restrict__ geom, float4 *__restrict__ out)
-{
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (size_t)P * N) return;
-    const int b = (int)(e / (size_t)N), i = (int)(e - (size_t)b * N);
-    out[(size_t)i * P + b] = pack_one(pos + 3 * e, geom[atom_sys[i]]);
-}
-
-void pack_positions(const double *pos, int P, int N, const int32_t *atom_sys, const SysGeom *geom, float4 *out,
-                    hipStream_t s)
-{
-    const size_t n = (size_t)P * N;
-    if (n == 0) return;
-    ProfScope ps_(K_PACK, s);
-    hipLaunchKernelGGL(k_pack, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, pos, P, N, atom_sys,
-                       geom, out);
-}
 
 // ---------------------------------------------------------- profiling ---
 

@@ -197,10 +197,6 @@ FineGrid fine_grid(const double L[3], double rc);
 // distance); for an orthorhombic cell it equals fine_grid(L, rc).
 FineGrid fine_grid_cell(const CellInfo &c, double rc);
 
-// Packs pos [P][N][3] into out [N][P] (bead-minor), each atom on the fine
-// grid of its system.
-void pack_positions(const double *pos, int P, int N, const int32_t *atom_sys, const SysGeom *geom, float4 *out,
-                    hipStream_t s);
 
 // One packed position: per axis the fine cell c = floor(x / h) mod M
 // (10 bits per axis in w; unwrapped coordinates allowed) and the FP32

@@ -96,9 +96,10 @@ __device__ __forceinline__ void raise_max(uint32_t *word, uint32_t v)
 __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double rcR, double rcA, double skin,
                               int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status);
 
-// Four lanes per atom (adjacent), each summing every fourth bead; the
-// atom's sums and the bead spread meet by shuffles, and the atom's first
-// lane writes its centroid and spread.
+// Four lanes per atom (adjacent), each summing every fourth bead and
+// packing those beads' positions on the fine grid (the packed positions
+// [N][P] of the list); the atom's sums and the bead spread meet by
+// shuffles, and the atom's first lane writes its centroid and spread.
 constexpr int kCenLanes = 4;
 __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ pos, const int32_t *__restrict__ types,
                                                      const int32_t *__restrict__ atom_sys,
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
                                                      float *__restrict__ spr, const double *__restrict__ cen_ref,
                                                      const SysGeom *__restrict__ geom, int nsys, double rcR,
                                                      double rcA, double skin, int force, uint32_t *__restrict__ grid,
-                                                     uint32_t *__restrict__ status)
+                                                     uint32_t *__restrict__ status, float4 *__restrict__ pos4)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = t / kCenLanes, q = t % kCenLanes;
@@ -115,13 +116,16 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
     float spread = 0.0f, disp = 0.0f;
     const size_t st = (size_t)N * 3;
     double c[3] = {0.0, 0.0, 0.0};
-    if (has)
+    if (has) {
+        const SysGeom &g = geom[atom_sys[i]];
         for (int b = q; b < P; b += kCenLanes) {
             const double *p = pos + b * st + 3 * (size_t)i;
             c[0] += p[0];
             c[1] += p[1];
             c[2] += p[2];
+            pos4[(size_t)i * P + b] = pack_one(p, g);
         }
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         c[a] += __shfl_xor(c[a], 1);
@@ -818,7 +822,6 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
     if (rc_ != NEP_OK) return rc_;
     // a per-axis scaling of an orthorhombic cell is covered by the device-side skin test
     const bool force = !nl->built || tri_changed;
-    pack_positions(pos, P, N, nl->atom_sys, nl->geom, reinterpret_cast<float4 *>(nl->pos4), s);
     const dim3 g1(div_up(N, kBlock));
     const dim3 gw(div_up(N, kBlock / 64));
     // enough workgroups for the candidate search even when the cells are few
@@ -829,7 +832,7 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
                            nl->atom_sys, P, N, nl->S, nl->cen, nl->spr,
                            nl->cen_ref,
                            nl->geom, nl->nsys, m->hp.rc_radial, m->hp.rc_angular, nl->skin, force ? 1 : 0, nl->grid,
-                           nl->status);
+                           nl->status, reinterpret_cast<float4 *>(nl->pos4));
         hipLaunchKernelGGL(k_decide, dim3(1), dim3(kBlock), 0, s, nl->geom, nl->nsys, m->hp.rc_radial,
                            m->hp.rc_angular, nl->skin, force ? 1 : 0, nl->grid, nl->status);
     }
