@@ -39,7 +39,6 @@ struct DevGlobal {
     float d_build;          // D at the last rebuild
     uint32_t rows_overflow; // a candidate row of the last rebuild was truncated
     int rebuild;            // 1: rebuild the candidate rows in this call
-    uint32_t ticket;        // workgroups of k_cell_count finished in this call (reset by the last)
     double R2;              // radial candidate radius squared of the last rebuild
     double RA2;             // angular candidate radius squared
 };
@@ -189,13 +188,6 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
     if (f) atomicOr(&status[0], f);
 }
 
-// The rebuild decision after every workgroup's maxima (one workgroup).
-__global__ __launch_bounds__(kBlock) void k_decide(const SysGeom *__restrict__ geom, int nsys, double rcR,
-                                                   double rcA, double skin, int force, uint32_t *__restrict__ grid,
-                                                   uint32_t *__restrict__ status)
-{
-    grid_decision(geom, nsys, rcR, rcA, skin, force, grid, status);
-}
 
 // Rebuild decision and, on a rebuild, the grid and candidate radius from the
 // measured spread.  Rows built with radius rc + 2 D0 + skin on edges L0 hold
@@ -243,22 +235,24 @@ __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double
         }
     }
     __syncthreads();   // every thread has read the record of the last rebuild
-    if (threadIdx.x != 0) return;
-    dg->rebuild = rebuild;
-    atomicMax(&status[4], __float_as_uint(spread));
-    // the next call's maxima start from zero
-    dg->spread_bits = 0u;
-    dg->disp_bits = 0u;
-    if (!rebuild) {
-        // reused rows that were truncated keep the overflow flag raised
-        if (dg->rows_overflow) atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
-        return;
+    if (threadIdx.x == 0) {
+        dg->rebuild = rebuild;
+        atomicMax(&status[4], __float_as_uint(spread));
+        // the next call's maxima start from zero
+        dg->spread_bits = 0u;
+        dg->disp_bits = 0u;
+        if (!rebuild) {
+            // reused rows that were truncated keep the overflow flag raised
+            if (dg->rows_overflow) atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
+        } else {
+            dg->rows_overflow = 0;
+            dg->R2 = R * R;
+            dg->RA2 = RA * RA;
+            dg->d_build = spread;
+            atomicAdd(&status[5], 1u);
+        }
     }
-    dg->rows_overflow = 0;
-    dg->R2 = R * R;
-    dg->RA2 = RA * RA;
-    dg->d_build = spread;
-    atomicAdd(&status[5], 1u);
+    __syncthreads();   // the decision is visible to the whole workgroup
 }
 
 // Global cell of atom i's centroid (system s).
@@ -298,42 +292,37 @@ __device__ void cell_scan_block(int ncell, int32_t *__restrict__ cnt, int32_t *_
     if (t == nt - 1) st[ncell] = part[nt - 1];
 }
 
-__global__ __launch_bounds__(kBlock) void k_cell_count(const double *__restrict__ cen, int N,
-                                                       const int32_t *__restrict__ atom_sys,
-                                                       const SysGeom *__restrict__ geom, uint32_t *__restrict__ grid,
-                                                       int ncell, int32_t *__restrict__ cell_cnt,
-                                                       int32_t *__restrict__ cell_start)
+// The rebuild decision after every workgroup's maxima, and on a rebuild
+// the centroid cell list: cell populations, their exclusive prefix sums and
+// the atoms sorted into cells (one workgroup; the steps are separated by
+// workgroup barriers, so most steps, which keep their rows, cost one launch
+// instead of three).
+__global__ __launch_bounds__(kBlock) void k_decide(const SysGeom *__restrict__ geom, int nsys, double rcR,
+                                                   double rcA, double skin, int force, uint32_t *__restrict__ grid,
+                                                   uint32_t *__restrict__ status, const double *__restrict__ cen,
+                                                   int N, const int32_t *__restrict__ atom_sys, int ncell,
+                                                   int32_t *__restrict__ cell_cnt, int32_t *__restrict__ cell_start,
+                                                   int32_t *__restrict__ cell_atoms)
 {
-    if (!dev_global(grid)->rebuild) return;   // whole grid
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) {
+    grid_decision(geom, nsys, rcR, rcA, skin, force, grid, status);
+    // values written by other threads of the workgroup are read through L2
+    if (!__atomic_load_n(&dev_global(grid)->rebuild, __ATOMIC_RELAXED)) return;   // whole workgroup
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const int s = atom_sys[i];
         atomicAdd(&cell_cnt[atom_cell(cen, i, geom[s], *dev_sys(grid, s))], 1);
     }
-    // the last workgroup to finish scans the counts
-    __shared__ int last;
-    __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(&dev_global(grid)->ticket, 1u) == gridDim.x - 1;
+    cell_scan_block(ncell, cell_cnt, cell_start);   // leaves the counts at zero for the fill
     __syncthreads();
-    if (!last) return;   // whole workgroup
-    __threadfence();
-    cell_scan_block(ncell, cell_cnt, cell_start);
-    if (threadIdx.x == 0) dev_global(grid)->ticket = 0u;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int s = atom_sys[i];
+        const int c = atom_cell(cen, i, geom[s], *dev_sys(grid, s));
+        const int slot = atomicAdd(&cell_cnt[c], 1);
+        cell_atoms[__atomic_load_n(&cell_start[c], __ATOMIC_RELAXED) + slot] = i;
+    }
 }
 
-__global__ void k_cell_fill(const double *__restrict__ cen, int N, const int32_t *__restrict__ atom_sys,
-                            const SysGeom *__restrict__ geom, const uint32_t *__restrict__ grid,
-                            int32_t *__restrict__ cell_cnt, const int32_t *__restrict__ cell_start,
-                            int32_t *__restrict__ cell_atoms)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N || !dev_global(grid)->rebuild) return;
-    const int s = atom_sys[i];
-    const int c = atom_cell(cen, i, geom[s], *dev_sys(grid, s));
-    const int slot = atomicAdd(&cell_cnt[c], 1);
-    cell_atoms[cell_start[c] + slot] = i;
-}
+
 
 
 // Sort one candidate row by (species, index) in place and record its species
@@ -822,7 +811,6 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
     if (rc_ != NEP_OK) return rc_;
     // a per-axis scaling of an orthorhombic cell is covered by the device-side skin test
     const bool force = !nl->built || tri_changed;
-    const dim3 g1(div_up(N, kBlock));
     const dim3 gw(div_up(N, kBlock / 64));
     // enough workgroups for the candidate search even when the cells are few
     const dim3 gc(nl->ncell_total, std::min(kCandSplitMax, std::max(1, div_up(1024, nl->ncell_total))));
@@ -834,17 +822,8 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
                            nl->geom, nl->nsys, m->hp.rc_radial, m->hp.rc_angular, nl->skin, force ? 1 : 0, nl->grid,
                            nl->status, reinterpret_cast<float4 *>(nl->pos4));
         hipLaunchKernelGGL(k_decide, dim3(1), dim3(kBlock), 0, s, nl->geom, nl->nsys, m->hp.rc_radial,
-                           m->hp.rc_angular, nl->skin, force ? 1 : 0, nl->grid, nl->status);
-    }
-    {
-        ProfScope ps_(K_CELL_COUNT, s);
-        hipLaunchKernelGGL(k_cell_count, g1, dim3(kBlock), 0, s, nl->cen, N, nl->atom_sys, nl->geom, nl->grid,
-                           nl->ncell_total, nl->cell_cnt, nl->cell_start);
-    }
-    {
-        ProfScope ps_(K_CELL_FILL, s);
-        hipLaunchKernelGGL(k_cell_fill, g1, dim3(kBlock), 0, s, nl->cen, N, nl->atom_sys, nl->geom, nl->grid,
-                           nl->cell_cnt, nl->cell_start, nl->cell_atoms);
+                           m->hp.rc_angular, nl->skin, force ? 1 : 0, nl->grid, nl->status, nl->cen, N, nl->atom_sys,
+                           nl->ncell_total, nl->cell_cnt, nl->cell_start, nl->cell_atoms);
     }
     {
         ProfScope ps_(K_CANDIDATES, s);
