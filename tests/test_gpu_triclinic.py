@@ -221,3 +221,60 @@ def test_npt_anisotropic_triclinic_matches_oracle(torch, L, orc, tmpdir_session)
     assert dbox <= np.abs(box).max() * mu_bound and dp < 1e-6
     st = eng.nl.status(clear=True)
     assert st["flags"] == 0
+
+
+def test_batch_mixing_cubic_and_sheared_cells(torch, L, orc, tmpdir_session):
+    """One batch holding a cubic and a sheared cell: the general-cell kernels
+    take each system's own form.  Both systems match the oracle, and the cubic
+    one agrees with its single-system (orthorhombic-kernel) evaluation."""
+    w = configs.WORKLOADS["rocksalt4096"]
+    path = write_model(tmpdir_session, "tri_batch", w.model())
+    P = 4
+    pos_s, typ_s, H, _ = sheared_rocksalt(P, 41)
+    p0, t0, b0 = I.rocksalt(4, 4.2)                  # 512 atoms, 16.8 A cube
+    rng = np.random.default_rng(42)
+    base = I.displace(p0, 0.08, rng)
+    pos_c = base[None] + rng.normal(0.0, 0.03, (P,) + base.shape)
+    parts = [(pos_c, np.asarray(t0, np.int32), np.diag(b0)), (pos_s, typ_s, H)]
+    m = L.Model(path)
+    off = np.array([0, pos_c.shape[1], pos_c.shape[1] + pos_s.shape[1]], np.int32)
+    N = int(off[-1])
+    dev = torch.device("cuda")
+    pos = torch.tensor(np.concatenate([pos_c, pos_s], axis=1), dtype=torch.float64, device=dev)
+    typ = torch.tensor(np.concatenate([parts[0][1], typ_s]), dtype=torch.int32, device=dev)
+    boxes = np.stack([parts[0][2], H])
+    say(f"[triclinic batch] cubic {pos_c.shape[1]} + sheared {pos_s.shape[1]} atoms x {P} beads")
+    nl = L.fitted_neighbor_list(m, pos, boxes, typ, 160, 96, offsets=off)
+    ws = L.Workspace(m, P, N, offsets=off)
+    E = torch.zeros((2, P), dtype=torch.float64, device=dev)
+    W = torch.zeros((2, P, 9), dtype=torch.float64, device=dev)
+    F = torch.zeros((P, N, 3), dtype=torch.float32, device=dev)
+    nl.build(pos, boxes, typ)
+    ws.compute(nl, pos, boxes, typ, E, F, W)
+    torch.cuda.synchronize()
+    flags, _, _ = nl.poll()
+    assert flags == 0 and ws.poll() == 0
+    E, W, F = E.cpu().numpy(), W.cpu().numpy(), F.cpu().numpy().astype(np.float64)
+    M = orc.Model(path)
+    for s, b in ((0, 0), (0, 3), (1, 1), (1, 2)):
+        p, t, box = parts[s]
+        ref = M.config(p[b], t, box)
+        n = p.shape[1]
+        dE = abs(E[s, b] - ref["E"]) / n
+        dF = np.abs(F[b, off[s]:off[s + 1]] - ref["F"]).max() / np.abs(ref["F"]).max()
+        dW = np.abs(W[s, b].reshape(3, 3) - ref["W"]).max() / np.abs(ref["W"]).max()
+        say(f"  system {s} bead {b}: dE/N {dE:.2e}  dF/Fmax {dF:.2e}  dW/Wmax {dW:.2e}")
+        assert dE <= E_TOL and dF <= F_TOL and dW <= W_TOL
+    one, _, _ = evaluate(torch, L, path, pos_c, parts[0][1], parts[0][2])
+    rel = np.abs(one[1] - F[:, :off[1]]).max() / np.abs(one[1]).max()
+    assert rel <= 1e-6, rel
+    # per-bead lists of the sheared system against the oracle's brute force
+    lists = nl.to_host(pos, boxes, 160, 96)
+    for kind, rc in (("radial", m.rc_radial), ("angular", m.rc_angular)):
+        for b in (0, 3):
+            oc, oi = orc.neighbors(pos_s[b], H, rc, cap=1024)
+            for i in range(0, pos_s.shape[1], 9):
+                gi = off[1] + i
+                c = lists["cnt_" + kind][b, gi]
+                assert c == oc[i]
+                np.testing.assert_array_equal(np.sort(lists["nbr_" + kind][b, :c, gi]) - off[1], oi[i, :oc[i]])
