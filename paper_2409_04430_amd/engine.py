@@ -2,7 +2,10 @@
 
 One stream, no per-step host synchronisation: the sticky device flags of
 the neighbour lists and of the force workspace are polled every
-`check_every` steps.  The step is the paper's workflow (Sec. II.A): thermostat,
+`check_every` steps.  Each successful poll keeps a device snapshot of the
+state; a candidate-row overflow found by a poll grows the rows, rolls back
+to the snapshot and replays the steps (the noise is counter-based, so the
+replay is the trajectory that larger rows would have given).  The step is the paper's workflow (Sec. II.A): thermostat,
 half kick, free ring-polymer step, forces, half kick, thermostat; the two
 integrator halves around consecutive force evaluations run as one fused
 launch.  Optional: the ring-polymer observables (centroid virial kinetic
@@ -121,7 +124,11 @@ class NepPimd:
         self.dump_log = []
         if self.dump_every and self.batched:
             raise ValueError("velocity dumps need a single system")
+        self.rollbacks = 0
+        self._snap = None
+        self._finished = False   # the last call was finish() (closing half without the next opening half)
         self._fit_capacity()
+        self._snapshot()
         self.tile = None
         if autotune:
             self.tile = self.ws.autotune(self.nl, self.pos, self.box, self.types, self.E, self.F, self.W)
@@ -130,11 +137,13 @@ class NepPimd:
     def _fit_capacity(self):
         """Size the candidate rows to the starting configuration, with room for
         the ring polymers to spread: the rows are at least as long as a uniform
-        system of the same density needs for radius rc + skin + 1 A."""
+        system of the same density needs for radius rc + skin + 2 A (the ring
+        polymers spread and the local density fluctuates during a run; a row
+        that still overflows is grown by `check`)."""
         self.nl = lib.fitted_neighbor_list(self.model, self.pos, self.box, self.types, *self.caps, skin=self.skin,
                                            offsets=self.offsets if self.batched else None)
-        floor = (default_capacity(self.model.rc_radial + self.skin + 1.0, self.density, 1, slack=1.3),
-                 default_capacity(self.model.rc_angular + self.skin + 1.0, self.density, 1, slack=1.3))
+        floor = (default_capacity(self.model.rc_radial + self.skin + 2.0, self.density, 1, slack=1.3),
+                 default_capacity(self.model.rc_angular + self.skin + 2.0, self.density, 1, slack=1.3))
         caps = tuple(max(a, b) for a, b in zip(self.nl.caps, floor))
         if caps != tuple(self.nl.caps):
             self.nl = lib.NeighborList(self.model, self.P, self.N, *caps,
@@ -149,18 +158,69 @@ class NepPimd:
         self.ws.compute(self.nl, self.pos, self.box, self.types, self.E, self.F, self.W, self.E_atom, self.W_atom)
 
     def check(self):
-        """Poll the sticky flags (synchronises); raise on overflow or non-finite values."""
-        st = self.nl.status(clear=True)
-        flags, mr, ma = st["flags"], st["max_union_radial"], st["max_union_angular"]
-        if flags & lib.FLAG_NEIGHBOR_OVERFLOW:
-            raise lib.NepError(5, f"candidate overflow: rows {st['max_cand_radial']}/{st['max_cand_angular']}, "
-                                  f"capacities {self.caps}")
-        wf = self.ws.poll(clear=True)
+        """Poll the sticky flags (synchronises).  A candidate-row overflow since
+        the last poll grows the rows, rolls back to the last poll's snapshot and
+        replays the steps; non-finite values or bad species raise."""
+        for _ in range(8):
+            st = self.nl.status(clear=True)
+            flags, mr, ma = st["flags"], st["max_union_radial"], st["max_union_angular"]
+            wf = self.ws.poll(clear=True)
+            if not (flags & lib.FLAG_NEIGHBOR_OVERFLOW):
+                break
+            self._grow_and_replay(st)
+        else:
+            raise lib.NepError(5, f"candidate overflow persists: capacities {self.caps}")
         if (flags | wf) & lib.FLAG_NONFINITE:
             raise lib.NepError(6, "non-finite force or position")
         if (flags | wf) & lib.FLAG_BAD_TYPE:
             raise lib.NepError(1, "species index outside the model's range")
+        self._snapshot()
         return mr, ma
+
+    def _snapshot(self):
+        """Device copy of the state at a verified point (positions, velocities,
+        cell, step, recorded observables)."""
+        self._snap = dict(step_no=self.step_no, started=self.started, pos=self.pos.clone(), vel=self.vel.clone(),
+                          box=np.array(self.box, dtype=np.float64, copy=True), obs_n=len(self.obs_log),
+                          dump_n=len(self.dump_log), rdf_frames=self.rdf_frames,
+                          rdf=None if self.rdf_hist is None else self.rdf_hist.clone())
+
+    def _grow_and_replay(self, st):
+        # rows found after an overflow may come from a state that truncated forces
+        # spoiled: grow by at most 2x (a replay that still overflows grows again)
+        need = (int(np.ceil(st["max_cand_radial"] * 1.25)) + 8, int(np.ceil(st["max_cand_angular"] * 1.25)) + 8)
+        self.caps = tuple(max(a + 1, min(b, 2 * a)) for a, b in zip(self.caps, need))
+        self.nl = lib.NeighborList(self.model, self.P, self.N, *self.caps,
+                                   offsets=self.offsets if self.batched else None)
+        self.nl.set_skin(self.skin)
+        had_graph = self.graph is not None
+        self.graph = None
+        target = self.step_no
+        s = self._snap
+        self.pos.copy_(s["pos"])
+        self.vel.copy_(s["vel"])
+        self.box = s["box"].copy()
+        self.step_no, self.started = s["step_no"], s["started"]
+        del self.obs_log[s["obs_n"]:]
+        del self.dump_log[s["dump_n"]:]
+        self.rdf_frames = s["rdf_frames"]
+        if self.rdf_hist is not None:
+            self.rdf_hist.copy_(s["rdf"])
+        self.rollbacks += 1
+        # replay the same calls: steps, then finish() or a fresh capture (whose
+        # own eager step is the last one) where the original sequence had them
+        finished = self._finished
+        last = target - 1 if (finished or had_graph) else target
+        every, self.check_every = self.check_every, 0   # the caller's poll verifies the replay
+        try:
+            while self.step_no < last:
+                self.step()
+            if finished:
+                self.finish()
+            elif had_graph:
+                self.capture()
+        finally:
+            self.check_every = every
 
     def start(self):
         self.forces()
@@ -202,6 +262,7 @@ class NepPimd:
 
     def step(self):
         """One full step: forces at the advanced positions, then POST(n) + PRE(n+1)."""
+        self._finished = False
         if self.graph is not None:
             self.graph.replay()
         else:
@@ -263,6 +324,7 @@ class NepPimd:
         self._after_post(self.step_no)
         self.started = False
         self.step_no += 1
+        self._finished = True
 
     def rdf(self):
         """Partial radial distribution functions from the accumulated counts

@@ -172,3 +172,35 @@ def test_graph_replay_matches_eager(torch, tmpdir_session):
     fa, _, _ = a.nl.poll()
     fb, _, _ = b.nl.poll()
     assert fa == 0 and fb == 0
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_overflow_rollback_replays_the_same_trajectory(torch, tmpdir_session, graph):
+    """Candidate rows far too short for the run overflow at once; the next poll
+    grows them, rolls back to the last verified state and replays, so the
+    final state equals bit for bit that of an engine whose rows were large
+    enough from the start (the integrator's noise is counter-based)."""
+    from paper_2409_04430_amd import lib
+    from paper_2409_04430_amd.engine import NepPimd
+    w = configs.WORKLOADS["fcc108"]
+    path = write_model(tmpdir_session, "rollback", w.model())
+    s = w.systems()[0]
+    kw = dict(dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=5, skin=0.3)
+    ref = NepPimd(path, s, **kw)
+    eng = NepPimd(path, s, **kw)
+    eng.caps = (30, 10)
+    eng.nl = lib.NeighborList(eng.model, s.P, s.N, *eng.caps)
+    eng.nl.set_skin(0.3)
+    if graph:
+        ref.capture()
+        eng.capture()
+    ref.run(17)
+    eng.run(17)
+    for e in (ref, eng):
+        e.finish()
+        e.check()
+    torch.cuda.synchronize()
+    say(f"  [rollback graph={graph}] rollbacks {eng.rollbacks}, capacities {eng.caps}")
+    assert eng.rollbacks >= 1 and eng.caps[0] > 30 and ref.rollbacks == 0
+    assert eng.step_no == ref.step_no == 18 + int(graph)   # capture() runs one eager step
+    assert torch.equal(eng.pos, ref.pos) and torch.equal(eng.vel, ref.vel)
