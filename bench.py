@@ -422,6 +422,7 @@ def main():
         mr, ma = eng.check()
         if eng.rollbacks == rb0:
             break   # else rows overflowed inside the region: they were grown, time again
+    regrowths = eng.rollbacks
     gpu_ms = ev0.elapsed_time(ev1)
     elapsed = max(gpu_ms / 1e3, 1e-12)
     value = s.N * s.P * args.steps / elapsed
@@ -486,7 +487,7 @@ def main():
                                  "pair terms FP32",
                    "wall_s": round(wall, 4), "launch": "hipGraph replay" if args.graph else "eager",
                    "eager_ms_per_step": round(eager_ms, 4), "candidate_rebuilds_timed": rebuilds,
-                   "capacity_regrowths": eng.rollbacks},
+                   "capacity_regrowths": regrowths},
         "roofline": roof,
         "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
         "cpu_baseline": cpu,
