@@ -451,6 +451,25 @@ def main():
             if rec and rec.get("source_hash") == source_hash():
                 roof["traffic"] = rec["bytes_per_launch"]
 
+    # every timed kernel against the VALU roofline (where its flops are counted)
+    # and the HBM roofline (its algorithmic bytes), and the whole step's
+    # algorithmic bytes against the step time
+    per_kernel = {}
+    for k, v in kernels.items():
+        sec = v["avg_us"] * 1e-6
+        row = {"avg_us": round(v["avg_us"], 2)}
+        if k in flops:
+            t = flops[k] * units / sec / 1e12
+            row.update({"TFLOP/s": round(t, 3), "valu_frac": round(t / PEAK_FP32_VALU_TFLOPS, 4)})
+        if k in byts:
+            gb = byts[k] * units / sec / 1e9
+            row.update({"GB/s": round(gb, 1), "hbm_frac": round(gb / PEAK_HBM_GBS, 4)})
+        per_kernel[k] = row
+    step_bytes = sum(byts.values()) * units
+    step_gbs = step_bytes / (gpu_ms / args.steps * 1e-3) / 1e9
+    step_hbm = {"algorithmic_bytes": int(step_bytes), "GB/s": round(step_gbs, 1),
+                "hbm_frac": round(step_gbs / PEAK_HBM_GBS, 4)}
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, model_path, s, args.cpu_beads)
@@ -489,6 +508,8 @@ def main():
                    "eager_ms_per_step": round(eager_ms, 4), "candidate_rebuilds_timed": rebuilds,
                    "capacity_regrowths": regrowths},
         "roofline": roof,
+        "kernels_roofline": per_kernel,
+        "step_hbm": step_hbm,
         "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
         "cpu_baseline": cpu,
         "npt": npt,
