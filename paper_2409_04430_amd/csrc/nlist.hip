@@ -267,9 +267,11 @@ __device__ __forceinline__ int atom_cell(const double *__restrict__ cen, int i, 
 
 // Cell populations, then (last workgroup) their exclusive prefix sums, the
 // counts reset for use as fill counters.
+constexpr int kDecideBlock = 1024;   // threads of the decision / cell-list workgroup
+
 __device__ void cell_scan_block(int ncell, int32_t *__restrict__ cnt, int32_t *__restrict__ st)
 {
-    __shared__ int32_t part[kBlock];
+    __shared__ int32_t part[kDecideBlock];
     const int t = threadIdx.x, nt = blockDim.x;
     const int per = (ncell + nt - 1) / nt;
     const int c0 = min(t * per, ncell), c1 = min(c0 + per, ncell);
@@ -292,12 +294,15 @@ __device__ void cell_scan_block(int ncell, int32_t *__restrict__ cnt, int32_t *_
     if (t == nt - 1) st[ncell] = part[nt - 1];
 }
 
+constexpr int kCellLds = 8192;   // cells whose counts the decision kernel keeps in LDS
+
 // The rebuild decision after every workgroup's maxima, and on a rebuild
 // the centroid cell list: cell populations, their exclusive prefix sums and
 // the atoms sorted into cells (one workgroup; the steps are separated by
 // workgroup barriers, so most steps, which keep their rows, cost one launch
-// instead of three).
-__global__ __launch_bounds__(kBlock) void k_decide(const SysGeom *__restrict__ geom, int nsys, double rcR,
+// instead of three).  Up to kCellLds cells the counts and the fill slots are
+// LDS atomics; larger grids use global ones.
+__global__ __launch_bounds__(kDecideBlock) void k_decide(const SysGeom *__restrict__ geom, int nsys, double rcR,
                                                    double rcA, double skin, int force, uint32_t *__restrict__ grid,
                                                    uint32_t *__restrict__ status, const double *__restrict__ cen,
                                                    int N, const int32_t *__restrict__ atom_sys, int ncell,
@@ -307,6 +312,46 @@ __global__ __launch_bounds__(kBlock) void k_decide(const SysGeom *__restrict__ g
     grid_decision(geom, nsys, rcR, rcA, skin, force, grid, status);
     // values written by other threads of the workgroup are read through L2
     if (!__atomic_load_n(&dev_global(grid)->rebuild, __ATOMIC_RELAXED)) return;   // whole workgroup
+    if (ncell <= kCellLds) {
+        // counts in LDS; after the scan each counter holds its cell's start and
+        // an LDS atomic on it hands out the atom's slot
+        __shared__ int32_t lc[kCellLds];
+        __shared__ int32_t part[kDecideBlock];
+        for (int c = threadIdx.x; c < ncell; c += blockDim.x) lc[c] = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            const int s = atom_sys[i];
+            atomicAdd(&lc[atom_cell(cen, i, geom[s], *dev_sys(grid, s))], 1);
+        }
+        __syncthreads();
+        const int t = threadIdx.x, nt = blockDim.x;
+        const int per = (ncell + nt - 1) / nt;
+        const int c0 = min(t * per, ncell), c1 = min(c0 + per, ncell);
+        int sum = 0;
+        for (int c = c0; c < c1; ++c) sum += lc[c];
+        part[t] = sum;
+        __syncthreads();
+        for (int off = 1; off < nt; off <<= 1) {
+            const int v = (t >= off) ? part[t - off] : 0;
+            __syncthreads();
+            part[t] += v;
+            __syncthreads();
+        }
+        int run = part[t] - sum;
+        for (int c = c0; c < c1; ++c) {
+            const int n = lc[c];
+            cell_start[c] = run;
+            lc[c] = run;
+            run += n;
+        }
+        if (t == nt - 1) cell_start[ncell] = part[nt - 1];
+        __syncthreads();
+        for (int i = threadIdx.x; i < N; i += blockDim.x) {
+            const int s = atom_sys[i];
+            cell_atoms[atomicAdd(&lc[atom_cell(cen, i, geom[s], *dev_sys(grid, s))], 1)] = i;
+        }
+        return;
+    }
     for (int i = threadIdx.x; i < N; i += blockDim.x) {
         const int s = atom_sys[i];
         atomicAdd(&cell_cnt[atom_cell(cen, i, geom[s], *dev_sys(grid, s))], 1);
@@ -367,15 +412,37 @@ __device__ void sort_row(int32_t *__restrict__ row, int n, int32_t *__restrict__
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Sort every candidate row (rebuild calls only): one wavefront per atom and
+// row kind (blockIdx.y: radial, angular), so the quadratic rank sort of the
+// longer rows spreads over the whole chip.
+__global__ __launch_bounds__(kBlock) void k_sort_rows(const uint32_t *__restrict__ grid, int N, int S, int capR,
+                                                      int32_t *__restrict__ candR, const int32_t *__restrict__ lenR,
+                                                      int32_t *__restrict__ offR, int32_t *__restrict__ scratchR,
+                                                      int capA, int32_t *__restrict__ candA,
+                                                      const int32_t *__restrict__ lenA, int32_t *__restrict__ offA,
+                                                      int32_t *__restrict__ scratchA)
+{
+    if (!dev_global(grid)->rebuild) return;   // whole workgroup
+    __shared__ int32_t buf[kBlock / 64][kSortLds];
+    const int wv = threadIdx.x >> 6;
+    const int i = blockIdx.x * (kBlock / 64) + wv;
+    if (i >= N) return;   // whole wavefront
+    const bool ang = blockIdx.y != 0;
+    const int cap = ang ? capA : capR;
+    const int n = min((ang ? lenA : lenR)[i], cap);
+    int32_t *row = (ang ? candA : candR) + (size_t)i * cap;
+    sort_row(row, n, n <= kSortLds ? buf[wv] : (ang ? scratchA : scratchR) + (size_t)i * cap, S,
+             (ang ? offA : offR) + (size_t)i * (kMaxSpecies + 1));
+}
+
 // Candidate rows.  gridDim.y workgroups per cell, each taking every
 // gridDim.y-th group of the cell's atoms (small or skewed cells have few
 // cells with large stencils); the centroids of the cell's stencil cells
 // (3 x 3 x 3, fewer along an axis with fewer than 3 cells) are staged in
 // LDS when they fit, and each wavefront takes one atom at a time, its lanes
 // testing 64 stencil atoms at once and appending the accepted ones by
-// ballot + prefix popcount (stencil order).  A stencil too large for LDS is
-// read from global memory instead.  Then every wavefront sorts the rows it
-// wrote (sort_row), with the staging buffer as sort space.
+// ballot + prefix popcount (stencil order; sorted by k_sort_rows).  A
+// stencil too large for LDS is read from global memory instead.
 constexpr int kStage = 2048;
 constexpr int kCandSplitMax = 16;   // workgroups per cell at most
 __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ cen, const int32_t *__restrict__ types,
@@ -386,9 +453,7 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
                                                     int32_t *__restrict__ cell_cnt, int capR, int capA,
                                                     int32_t *__restrict__ candR, int32_t *__restrict__ lenR,
                                                     int32_t *__restrict__ candA, int32_t *__restrict__ lenA,
-                                                    double *__restrict__ cen_ref, uint32_t *__restrict__ status,
-                                                    int32_t *__restrict__ offR, int32_t *__restrict__ offA,
-                                                    int32_t *__restrict__ scratchR, int32_t *__restrict__ scratchA)
+                                                    double *__restrict__ cen_ref, uint32_t *__restrict__ status)
 {
     __shared__ double sx[kStage], sy[kStage], sz[kStage];
     __shared__ int32_t sw[kStage];
@@ -504,19 +569,6 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
                 atomicOr(&dg->rows_overflow, 1u);
             }
         }
-    }
-    // sort the rows this wavefront wrote; the stencil staging is free once
-    // every wavefront of the workgroup has left its atom loop
-    static_assert(kStage >= (kBlock / 64) * kSortLds, "sort buffers exceed the staging space");
-    __syncthreads();
-    int32_t *sbuf = sw + wv * kSortLds;
-    for (int a = a0 + blockIdx.y * waves + wv; a < a1; a += gridDim.y * waves) {
-        const int i = cell_atoms[a];
-        const int nR = min(lenR[i], capR), nA = min(lenA[i], capA);
-        sort_row(candR + (size_t)i * capR, nR, nR <= kSortLds ? sbuf : scratchR + (size_t)i * capR, S,
-                 offR + (size_t)i * (kMaxSpecies + 1));
-        sort_row(candA + (size_t)i * capA, nA, nA <= kSortLds ? sbuf : scratchA + (size_t)i * capA, S,
-                 offA + (size_t)i * (kMaxSpecies + 1));
     }
 }
 
@@ -821,7 +873,7 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
                            nl->cen_ref,
                            nl->geom, nl->nsys, m->hp.rc_radial, m->hp.rc_angular, nl->skin, force ? 1 : 0, nl->grid,
                            nl->status, reinterpret_cast<float4 *>(nl->pos4));
-        hipLaunchKernelGGL(k_decide, dim3(1), dim3(kBlock), 0, s, nl->geom, nl->nsys, m->hp.rc_radial,
+        hipLaunchKernelGGL(k_decide, dim3(1), dim3(kDecideBlock), 0, s, nl->geom, nl->nsys, m->hp.rc_radial,
                            m->hp.rc_angular, nl->skin, force ? 1 : 0, nl->grid, nl->status, nl->cen, N, nl->atom_sys,
                            nl->ncell_total, nl->cell_cnt, nl->cell_start, nl->cell_atoms);
     }
@@ -830,7 +882,15 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
         hipLaunchKernelGGL(k_candidates, gc, dim3(kBlock), 0, s, nl->cen, types, N, nl->S, nl->geom, nl->cell_sys,
                            nl->grid, nl->cell_start, nl->cell_atoms, nl->cell_cnt, nl->capR, nl->capA, nl->candR,
                            nl->lenR,
-                           nl->candA, nl->lenA, nl->cen_ref, nl->status, nl->offR, nl->offA, nl->uniR, nl->revA);
+                           nl->candA, nl->lenA, nl->cen_ref, nl->status);
+    }
+    {
+        // one wavefront per (atom, row kind); the union-list and reverse-slot
+        // arrays serve as sort scratch for long rows before they are filled
+        ProfScope ps_(K_SORT_ROWS, s);
+        hipLaunchKernelGGL(k_sort_rows, dim3(div_up(N, kBlock / 64), 2), dim3(kBlock), 0, s, nl->grid, N, nl->S,
+                           nl->capR, nl->candR, nl->lenR, nl->offR, nl->uniR, nl->capA, nl->candA, nl->lenA,
+                           nl->offA, nl->revA);
     }
     {
         ProfScope ps_(K_NLIST, s);
