@@ -95,11 +95,11 @@ __device__ __forceinline__ void raise_max(uint32_t *word, uint32_t v)
 __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double rcR, double rcA, double skin,
                               int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status);
 
-// Four lanes per atom (adjacent), each summing every fourth bead and
-// packing those beads' positions on the fine grid (the packed positions
+// kCenLanes lanes per atom (adjacent), each summing every kCenLanes-th bead
+// and packing those beads' positions on the fine grid (the packed positions
 // [N][P] of the list); the atom's sums and the bead spread meet by
 // shuffles, and the atom's first lane writes its centroid and spread.
-constexpr int kCenLanes = 4;
+constexpr int kCenLanes = 16;   // a power of two dividing 64
 __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ pos, const int32_t *__restrict__ types,
                                                      const int32_t *__restrict__ atom_sys,
                                                      int P, int N, int S, double *__restrict__ cen,
@@ -127,8 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        c[a] += __shfl_xor(c[a], 1);
-        c[a] += __shfl_xor(c[a], 2);
+        for (int o = 1; o < kCenLanes; o <<= 1) c[a] += __shfl_xor(c[a], o);
     }
     const double inv = 1.0 / P;
     c[0] *= inv; c[1] *= inv; c[2] *= inv;
@@ -139,8 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
             const double dx = p[0] - c[0], dy = p[1] - c[1], dz = p[2] - c[2];
             m2 = fmax(m2, dx * dx + dy * dy + dz * dz);
         }
-    m2 = fmax(m2, __shfl_xor(m2, 1));
-    m2 = fmax(m2, __shfl_xor(m2, 2));
+    for (int o = 1; o < kCenLanes; o <<= 1) m2 = fmax(m2, __shfl_xor(m2, o));
     if (has && q == 0) {
         cen[3 * i] = c[0];
         cen[3 * i + 1] = c[1];
