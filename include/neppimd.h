@@ -194,9 +194,11 @@ int32_t neighbor_build(const nep_model *model, nep_nlist *nl, const double *pos,
 
 /* Reuse of the candidate rows (a Verlet skin on the centroid search): with
  * skin > 0 the rows are built with radius rc + 2 D + skin and kept while
- * (rc + 2 D + 2 max_i |c_i - lambda c_i,build|) / lambda_min - rc - 2 D_build
- * <= skin for both cutoffs, lambda = L / L_build per axis of the box (so
- * 2 (D - D_build) + 2 max_i |c_i - c_i,build| <= skin for an unchanged box),
+ * (rc + 2 max_i (D_i + |c_i - lambda c_i,build|)) / lambda_min - rc
+ * - 2 D_build <= skin for both cutoffs, D_i the largest bead distance from
+ * atom i's centroid, D = max_i D_i, lambda = L / L_build per axis of the box
+ * (so 2 max_i (D_i + |c_i - c_i,build|) - 2 D_build <= skin for an
+ * unchanged box),
  * which keeps them a superset of every bead pair within the cutoffs
  * (triangle inequality, any periodic image); the decision is taken on the
  * device, without a host round trip.  A box scaled by a barostat therefore

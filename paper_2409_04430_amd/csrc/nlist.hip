@@ -35,7 +35,7 @@ namespace nep {
 // decision of this call.
 struct DevGlobal {
     uint32_t spread_bits;   // D of this call (float bits, atomicMax)
-    uint32_t disp_bits;     // largest centroid displacement since the rebuild (float bits)
+    uint32_t reach_bits;    // largest D_i + |dc_i| of this call (float bits): spread plus displacement
     float d_build;          // D at the last rebuild
     uint32_t rows_overflow; // a candidate row of the last rebuild was truncated
     int rebuild;            // 1: rebuild the candidate rows in this call
@@ -90,8 +90,9 @@ __device__ __forceinline__ void raise_max(uint32_t *word, uint32_t v)
     if (v > __atomic_load_n(word, __ATOMIC_RELAXED)) atomicMax(word, v);
 }
 
-// Centroid of each atom's ring polymer, its largest bead distance and its
-// displacement from the centroid of the last rebuild (both rounded up).
+// Centroid of each atom's ring polymer, its largest bead distance D_i and
+// its displacement |dc_i| from the centroid of the last rebuild (both
+// rounded up); the maxima of D_i and of D_i + |dc_i| go to the skin test.
 __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double rcR, double rcA, double skin,
                               int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status);
 
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
     const int i = t / kCenLanes, q = t % kCenLanes;
     const bool has = i < N;
     uint32_t f = 0;
-    float spread = 0.0f, disp = 0.0f;
+    float spread = 0.0f, reach = 0.0f;
     const size_t st = (size_t)N * 3;
     double c[3] = {0.0, 0.0, 0.0};
     if (has) {
@@ -148,7 +149,8 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
         if (!finite) {
             f |= NEP_FLAG_NONFINITE;
         } else {
-            spread = (float)sqrt(m2) * 1.000001f + 1e-7f;   // rounded up
+            const double di = sqrt(m2);
+            spread = (float)di * 1.000001f + 1e-7f;   // rounded up
             // displacement from the build centroid carried along with the box:
             // c - lambda c_build, lambda = L / L_build per axis (1 for an unchanged box)
             const int sy = atom_sys[i];
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
             const double dx = c[0] - lam[0] * cen_ref[3 * i], dy = c[1] - lam[1] * cen_ref[3 * i + 1],
                          dz = c[2] - lam[2] * cen_ref[3 * i + 2];
             const double d2 = dx * dx + dy * dy + dz * dz;
-            disp = isfinite(d2) ? (float)sqrt(d2) * 1.000001f + 1e-7f : 3.0e38f;
+            reach = isfinite(d2) ? (float)(di + sqrt(d2)) * 1.000001f + 1e-7f : 3.0e38f;
         }
         const int ty = types[i];
         if (ty < 0 || ty >= S) f |= NEP_FLAG_BAD_TYPE;
@@ -168,20 +170,20 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
     // one atomic per workgroup and word (same-address atomics serialise)
     __shared__ float red[2][kBlock / 64];
     spread = wave_max_f(spread);
-    disp = wave_max_f(disp);
+    reach = wave_max_f(reach);
     const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         red[0][wv] = spread;
-        red[1][wv] = disp;
+        red[1][wv] = reach;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
             spread = fmaxf(spread, red[0][w]);
-            disp = fmaxf(disp, red[1][w]);
+            reach = fmaxf(reach, red[1][w]);
         }
         if (spread > 0.0f) atomicMax(&grid[0], __float_as_uint(spread));
-        if (disp > 0.0f) atomicMax(&grid[1], __float_as_uint(disp));
+        if (reach > 0.0f) atomicMax(&grid[1], __float_as_uint(reach));
     }
     if (f) atomicOr(&status[0], f);
 }
@@ -193,26 +195,30 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
 // box now L = lambda L0 (per axis) and e = c_j - c_i + n L a minimum-image
 // centroid vector, e0 = c0_j - c0_i + n L0 satisfies
 //   lambda (x) e0 = e - (dc_j - dc_i),  dc = c - lambda (x) c0,
-// so |e0| <= (|e| + 2 max|dc|) / lambda_min, whatever the image n.  Every
-// bead pair inside the cutoff has |e| < rc + 2 D, so the rows stay complete
-// while (rc + 2 D + 2 max|dc|) / lambda_min - rc - 2 D0 <= skin for both
-// cutoffs (for an unchanged box: 2 (D - D0) + 2 max|dc| <= skin); otherwise
-// they are rebuilt.  Run by k_decide, one workgroup launched after
-// k_centroid (a last-workgroup ticket inside k_centroid cost more: every
-// workgroup then needs a device-scope fence).
+// so |e0| <= (|e| + |dc_i| + |dc_j|) / lambda_min, whatever the image n.
+// A bead pair inside the cutoff has |e| < rc + D_i + D_j (D_i: largest bead
+// distance from atom i's centroid), so |e0| < (rc + 2 max_k (D_k + |dc_k|))
+// / lambda_min and the rows stay complete while
+// (rc + 2 max_k (D_k + |dc_k|)) / lambda_min - rc - 2 D0 <= skin for both
+// cutoffs (for an unchanged box: 2 max_k (D_k + |dc_k|) - 2 D0 <= skin);
+// otherwise they are rebuilt.  Pairing each atom's spread with its own
+// displacement keeps the rows longer than the separate maxima would.  Run
+// by k_decide, one workgroup launched after k_centroid (a last-workgroup
+// ticket inside k_centroid cost more: every workgroup then needs a
+// device-scope fence).
 __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double rcR, double rcA, double skin,
                               int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status)
 {
     DevGlobal *dg = dev_global(grid);
     const float spread = __uint_as_float(__atomic_load_n(&dg->spread_bits, __ATOMIC_RELAXED));
-    const float disp = __uint_as_float(__atomic_load_n(&dg->disp_bits, __ATOMIC_RELAXED));
+    const float reach1 = __uint_as_float(__atomic_load_n(&dg->reach_bits, __ATOMIC_RELAXED));
     double lam_min = 1.0;
     for (int s = 0; s < nsys; ++s) {
         const DevSys *ds = dev_sys(grid, s);
         for (int a = 0; a < 3; ++a)
             if (!geom[s].tri && ds->Lb[a] > 0.0) lam_min = fmin(lam_min, geom[s].L[a] / ds->Lb[a]);
     }
-    const double reach = 2.0 * (double)spread + 2.0 * (double)disp, d0 = 2.0 * (double)dg->d_build;
+    const double reach = 2.0 * (double)reach1, d0 = 2.0 * (double)dg->d_build;
     const double needR = (rcR + reach) / lam_min - rcR - d0, needA = (rcA + reach) / lam_min - rcA - d0;
     const int rebuild = force || !(needR <= skin && needA <= skin);
     const double rc = rcR > rcA ? rcR : rcA;
@@ -238,7 +244,7 @@ __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double
         atomicMax(&status[4], __float_as_uint(spread));
         // the next call's maxima start from zero
         dg->spread_bits = 0u;
-        dg->disp_bits = 0u;
+        dg->reach_bits = 0u;
         if (!rebuild) {
             // reused rows that were truncated keep the overflow flag raised
             if (dg->rows_overflow) atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
