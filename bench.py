@@ -21,6 +21,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import tempfile
 import time
@@ -62,11 +63,36 @@ def parse():
     return ap.parse_args()
 
 
-def source_hash() -> str:
+# source file of each timed kernel (the stored HBM traffic of a kernel stays
+# valid while the files it is compiled from and the build flags are unchanged)
+KERNEL_SOURCES = {"descriptor": "nep.hip", "force_ang": "nep.hip", "force": "nep.hip", "reduce": "nep.hip",
+                  "nlist": "nlist.hip", "centroid": "nlist.hip", "candidates": "nlist.hip",
+                  "sort_rows": "nlist.hip", "trpmd": "pimd.hip"}
+
+
+def kernel_source_hash(kernel: str) -> str:
+    """Hash of a kernel's .hip file, every header it includes (transitively)
+    and the build script that sets the compiler flags."""
+    pkg = os.path.join(ROOT, "paper_2409_04430_amd")
+    dirs = (os.path.join(pkg, "csrc"), os.path.join(ROOT, "include"))
+
+    def path(f):
+        for d in dirs:
+            if os.path.exists(os.path.join(d, f)):
+                return os.path.join(d, f)
+        raise FileNotFoundError(f)
+
+    seen, todo = set(), [KERNEL_SOURCES[kernel]]
+    while todo:
+        f = todo.pop()
+        if f in seen:
+            continue
+        seen.add(f)
+        with open(path(f), "rb") as fh:
+            todo += [m.decode() for m in re.findall(rb'#include "([^"]+)"', fh.read())]
     h = hashlib.sha256()
-    d = os.path.join(ROOT, "paper_2409_04430_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        with open(os.path.join(d, f), "rb") as fh:
+    for f in sorted(seen) + ["build.py"]:
+        with open(path(f) if f != "build.py" else os.path.join(pkg, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
@@ -448,7 +474,7 @@ def main():
         if os.path.exists(tr_path):
             tr = json.load(open(tr_path))
             rec = tr.get(args.workload, {}).get(dom)
-            if rec and rec.get("source_hash") == source_hash():
+            if rec and dom in KERNEL_SOURCES and rec.get("source_hash") == kernel_source_hash(dom):
                 roof["traffic"] = rec["bytes_per_launch"]
 
     # every timed kernel against the VALU roofline (where its flops are counted)
