@@ -63,24 +63,52 @@ __device__ __forceinline__ void philox4x32_10(uint32_t k0, uint32_t k1, uint32_t
     }
 }
 
-// Standard normal e4 (0..3) of block kb of component a of atom i: the
-// block's Philox output gives two Box-Muller pairs (uniforms (x + 1) 2^-32),
-// normals 0, 1 from the first pair (cosine, sine) and 2, 3 from the second.
-// Each lane evaluates only its own pair (kept out of line: one copy of the
-// FP64 Box-Muller code).
-__device__ __noinline__ double normal1(uint64_t seed, uint64_t step, int stage, int i, int a, int nb, int kb, int e4)
+// Philox block kb of component a of atom i for (step, stage).
+__device__ __forceinline__ void noise_block(uint64_t seed, uint64_t step, int stage, int i, int a, int nb, int kb,
+                                            uint32_t (&c)[4])
 {
-    uint32_t c[4] = {(uint32_t)i, (uint32_t)(a * nb + kb), (uint32_t)step,
-                     (uint32_t)((step >> 32) * 2u + (uint64_t)stage)};
+    c[0] = (uint32_t)i;
+    c[1] = (uint32_t)(a * nb + kb);
+    c[2] = (uint32_t)step;
+    c[3] = (uint32_t)((step >> 32) * 2u + (uint64_t)stage);
     philox4x32_10((uint32_t)seed, (uint32_t)(seed >> 32), c);
+}
+
+// Box-Muller pair from two Philox words (uniforms (x + 1) 2^-32).
+__device__ __forceinline__ void box_muller(uint32_t x0, uint32_t x1, double &zc, double &zs)
+{
     const double s = 1.0 / 4294967296.0;
-    const bool second = e4 >= 2;
-    const double u0 = ((double)(second ? c[2] : c[0]) + 1.0) * s;
-    const double u1 = ((double)(second ? c[3] : c[1]) + 1.0) * s;
+    const double u0 = ((double)x0 + 1.0) * s;
+    const double u1 = ((double)x1 + 1.0) * s;
     const double rad = sqrt(-2.0 * log(u0));
     double sn, cs;
     sincos(2.0 * M_PI * u1, &sn, &cs);
-    return rad * ((e4 & 1) ? sn : cs);
+    zc = rad * cs;
+    zs = rad * sn;
+}
+
+// Standard normal e4 (0..3) of block kb of component a of atom i: the
+// block's Philox output gives two Box-Muller pairs, normals 0, 1 from the
+// first pair (cosine, sine) and 2, 3 from the second.  Each lane evaluates
+// only its own pair (kept out of line: one copy of the FP64 Box-Muller code).
+__device__ __noinline__ double normal1(uint64_t seed, uint64_t step, int stage, int i, int a, int nb, int kb, int e4)
+{
+    uint32_t c[4];
+    noise_block(seed, step, stage, i, a, nb, kb, c);
+    const bool second = e4 >= 2;
+    double zc, zs;
+    box_muller(second ? c[2] : c[0], second ? c[3] : c[1], zc, zs);
+    return (e4 & 1) ? zs : zc;
+}
+
+// All four normals of block kb (the values normal1 returns for e4 = 0..3).
+__device__ __noinline__ void normal4(uint64_t seed, uint64_t step, int stage, int i, int a, int nb, int kb,
+                                     double (&z)[4])
+{
+    uint32_t c[4];
+    noise_block(seed, step, stage, i, a, nb, kb, c);
+    box_muller(c[0], c[1], z[0], z[1]);
+    box_muller(c[2], c[3], z[2], z[3]);
 }
 
 struct StepArgs {
@@ -212,8 +240,12 @@ __global__ __launch_bounds__(kStepBlock) void k_trpmd(StepArgs a, const double *
 // elements of one bead per lane group), the per-mode update runs on the
 // result tile (lane j + 16 g holds modes g, g + 4, g + 8, g + 12 of the tile
 // for element j), the new mode vectors of all mode tiles meet in LDS, and
-// each wavefront back-transforms one 16-bead tile.  FP64 fragment layout: A(i, k) in lane i + 16 k, B(k, j)
-// in lane j + 16 k, result (i, j) in lane j + 16 (i % 4), slot i / 4.
+// each wavefront back-transforms one 16-bead tile.  The tile's thermostat
+// normals (16 elements x 16 modes, 16 x 4 Philox blocks per draw) are drawn
+// once each: lane j + 16 g draws block 4 mt + g of element j and leaves its
+// four normals in LDS for the lanes that hold those modes.  FP64 fragment
+// layout: A(i, k) in lane i + 16 k, B(k, j) in lane j + 16 k, result (i, j)
+// in lane j + 16 (i % 4), slot i / 4.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 // Workgroup: ET element tiles x MT mode tiles, one wavefront each (4 or 3).
 template <int P> constexpr int step_mf_et() { return P == 48 ? 1 : 64 / P; }
@@ -224,6 +256,7 @@ __global__ __launch_bounds__(64 * 4) void k_trpmd_mf(StepArgs a, const double *_
     static_assert(P % 16 == 0 && P <= 64, "matrix-core stage needs P = 16, 32, 48 or 64");
     constexpr int MT = P / 16, KS = P / 4, ET = step_mf_et<P>();
     __shared__ double xt[ET][2][P][16];   // new mode vectors v~, q~ of each element tile
+    __shared__ double zn[ET * MT][2][16][16];   // thermostat normals [wavefront][draw][mode in tile][element]
     const PimdLayout Lo(P);
     const int M = 3 * a.N;
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lg = l >> 4;
@@ -256,6 +289,18 @@ __global__ __launch_bounds__(64 * 4) void k_trpmd_mf(StepArgs a, const double *_
     const double hk = 0.5 * a.dt / (m * a.conv);
     const double sig = sqrt(a.kTP / (m * a.conv));
     const int NB = (P + 3) / 4;
+    const bool fused = a.stage == PIMD_STAGE_FUSED;
+    if (a.noise) {
+        // draw 0: (step, closing half, or the stage's own half); the fused
+        // stage's draw 1: (step + 1, opening half)
+        for (int d = 0; d < (fused ? 2 : 1); ++d) {
+            double z4[4];
+            normal4(a.seed, (uint64_t)step + (uint64_t)d, fused ? 1 - d : (post ? 1 : 0), i, comp, NB, 4 * mt + lg, z4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) zn[wv][d][4 * lg + q][lr] = z4[q];
+        }
+    }
+    __syncthreads();   // the normals of the tile are in LDS
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
         const int k = 16 * mt + lg + 4 * s4;
@@ -267,15 +312,10 @@ __global__ __launch_bounds__(64 * 4) void k_trpmd_mf(StepArgs a, const double *_
             beta = c1 * c1 + 1.0;
         }
         if (a.noise && ok) {
-            const int kb = k >> 2, e4 = k & 3;
+            // normal k & 3 of block k >> 2: mode k - 16 mt = lg + 4 s4 of the tile
             const double gs = sig * cst[Lo.sc2 + k];
-            if (a.stage == PIMD_STAGE_FUSED) {
-                const double z1 = normal1(a.seed, (uint64_t)step, 1, i, comp, NB, kb, e4);
-                const double z0 = normal1(a.seed, (uint64_t)(step + 1), 0, i, comp, NB, kb, e4);
-                gamma = gs * (c1 * z1 + z0);
-            } else {
-                gamma = gs * normal1(a.seed, (uint64_t)step, post ? 1 : 0, i, comp, NB, kb, e4);
-            }
+            const double z1 = zn[wv][0][lg + 4 * s4][lr];
+            gamma = fused ? gs * (c1 * z1 + zn[wv][1][lg + 4 * s4][lr]) : gs * z1;
         }
         const double v1 = alpha * vt[s4] + gamma + beta * (hk * ft[s4]);
         double vn = v1, qn = 0.0;
