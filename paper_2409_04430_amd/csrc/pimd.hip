@@ -102,7 +102,7 @@ __device__ __noinline__ double normal1(uint64_t seed, uint64_t step, int stage, 
 }
 
 // All four normals of block kb (the values normal1 returns for e4 = 0..3).
-__device__ __noinline__ void normal4(uint64_t seed, uint64_t step, int stage, int i, int a, int nb, int kb,
+__device__ __forceinline__ void normal4(uint64_t seed, uint64_t step, int stage, int i, int a, int nb, int kb,
                                      double (&z)[4])
 {
     uint32_t c[4];
@@ -268,31 +268,39 @@ __global__ __launch_bounds__(64 * 4) void k_trpmd_mf(StepArgs a, const double *_
     const int64_t step = a.step_dev ? *a.step_dev : a.step;
     const double *C = cst + Lo.C;   // C[b * P + k]
 
-    // forward, modes 16 mt .. 16 mt + 15: v~ = C^T v, f~ = C^T F, q~ = C^T q
-    f64x4 vt = {0.0, 0.0, 0.0, 0.0}, ft = {0.0, 0.0, 0.0, 0.0}, qt = {0.0, 0.0, 0.0, 0.0};
+    // bead values of the element tile, all loads in flight at once (lanes
+    // past the last element read element 0 and drop it) and issued before
+    // the noise draws, which do not depend on them
+    double xv[KS], xq[KS], cf[KS], cb[KS];
+    float xf[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-        const int b = 4 * ks + lg;
-        const size_t at = (size_t)b * M + (ok ? e : 0);
-        const double xv = ok ? a.vel[at] : 0.0;
-        const double xf = ok ? (double)a.F[at] : 0.0;
-        const double xq = (ok && pre) ? a.pos[at] : 0.0;
-        const double cA = C[(size_t)b * P + 16 * mt + lr];   // C^T(mode 16 mt + lr, bead b)
-        vt = __builtin_amdgcn_mfma_f64_16x16x4f64(cA, xv, vt, 0, 0, 0);
-        ft = __builtin_amdgcn_mfma_f64_16x16x4f64(cA, xf, ft, 0, 0, 0);
-        if (pre) qt = __builtin_amdgcn_mfma_f64_16x16x4f64(cA, xq, qt, 0, 0, 0);
+        const size_t at = (size_t)(4 * ks + lg) * M + (ok ? e : 0);
+        xv[ks] = a.vel[at];
+        xf[ks] = a.F[at];
+        xq[ks] = pre ? a.pos[at] : 0.0;
+        cf[ks] = C[(size_t)(4 * ks + lg) * P + 16 * mt + lr];   // C^T(mode 16 mt + lr, bead 4 ks + lg)
+        cb[ks] = C[(size_t)(16 * mt + lr) * P + 4 * ks + lg];   // C(bead 16 mt + lr, mode 4 ks + lg)
     }
-
-    // per (mode, element): thermostat, kicks and the Cayley map
     const int i = e / 3, comp = e - 3 * i;
-    const double m = ok ? a.mass[i] : 1.0;
-    const double hk = 0.5 * a.dt / (m * a.conv);
-    const double sig = sqrt(a.kTP / (m * a.conv));
+    const double mi = a.mass[ok ? i : 0];
+    // per-mode constants of this lane's four modes k = 16 mt + lg + 4 s4
+    double kc1[4], ksc2[4], kcq[4], kqv[4], kvq[4];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+        const int k = 16 * mt + lg + 4 * s4;
+        kc1[s4] = cst[Lo.c1 + k];
+        ksc2[s4] = cst[Lo.sc2 + k];
+        kcq[s4] = pre ? cst[Lo.cq + k] : 0.0;
+        kqv[s4] = pre ? cst[Lo.qv + k] : 0.0;
+        kvq[s4] = pre ? cst[Lo.vq + k] : 0.0;
+    }
     const int NB = (P + 3) / 4;
     const bool fused = a.stage == PIMD_STAGE_FUSED;
     if (a.noise) {
         // draw 0: (step, closing half, or the stage's own half); the fused
         // stage's draw 1: (step + 1, opening half)
+#pragma unroll 1
         for (int d = 0; d < (fused ? 2 : 1); ++d) {
             double z4[4];
             normal4(a.seed, (uint64_t)step + (uint64_t)d, fused ? 1 - d : (post ? 1 : 0), i, comp, NB, 4 * mt + lg, z4);
@@ -301,10 +309,24 @@ __global__ __launch_bounds__(64 * 4) void k_trpmd_mf(StepArgs a, const double *_
         }
     }
     __syncthreads();   // the normals of the tile are in LDS
+
+    // forward, modes 16 mt .. 16 mt + 15: v~ = C^T v, f~ = C^T F, q~ = C^T q
+    f64x4 vt = {0.0, 0.0, 0.0, 0.0}, ft = {0.0, 0.0, 0.0, 0.0}, qt = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        vt = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[ks], ok ? xv[ks] : 0.0, vt, 0, 0, 0);
+        ft = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[ks], ok ? (double)xf[ks] : 0.0, ft, 0, 0, 0);
+        if (pre) qt = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[ks], ok ? xq[ks] : 0.0, qt, 0, 0, 0);
+    }
+
+    // per (mode, element): thermostat, kicks and the Cayley map
+    const double m = ok ? mi : 1.0;
+    const double hk = 0.5 * a.dt / (m * a.conv);
+    const double sig = sqrt(a.kTP / (m * a.conv));
 #pragma unroll
     for (int s4 = 0; s4 < 4; ++s4) {
         const int k = 16 * mt + lg + 4 * s4;
-        const double c1 = cst[Lo.c1 + k];
+        const double c1 = kc1[s4];
         double alpha = c1, beta = 1.0, gamma = 0.0;
         if (a.stage == PIMD_STAGE_POST) beta = c1;
         if (a.stage == PIMD_STAGE_FUSED) {
@@ -313,16 +335,15 @@ __global__ __launch_bounds__(64 * 4) void k_trpmd_mf(StepArgs a, const double *_
         }
         if (a.noise && ok) {
             // normal k & 3 of block k >> 2: mode k - 16 mt = lg + 4 s4 of the tile
-            const double gs = sig * cst[Lo.sc2 + k];
+            const double gs = sig * ksc2[s4];
             const double z1 = zn[wv][0][lg + 4 * s4][lr];
             gamma = fused ? gs * (c1 * z1 + zn[wv][1][lg + 4 * s4][lr]) : gs * z1;
         }
         const double v1 = alpha * vt[s4] + gamma + beta * (hk * ft[s4]);
         double vn = v1, qn = 0.0;
         if (pre) {
-            const double cq = cst[Lo.cq + k], qv = cst[Lo.qv + k], vq = cst[Lo.vq + k];
-            qn = cq * qt[s4] + qv * v1;
-            vn = cq * v1 - vq * qt[s4];
+            qn = kcq[s4] * qt[s4] + kqv[s4] * v1;
+            vn = kcq[s4] * v1 - kvq[s4] * qt[s4];
         }
         xt[et][0][k][lr] = vn;
         xt[et][1][k][lr] = qn;
@@ -334,9 +355,8 @@ __global__ __launch_bounds__(64 * 4) void k_trpmd_mf(StepArgs a, const double *_
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const int k = 4 * ks + lg;
-        const double cA = C[(size_t)(16 * mt + lr) * P + k];   // C(bead 16 mt + lr, mode k)
-        vb = __builtin_amdgcn_mfma_f64_16x16x4f64(cA, xt[et][0][k][lr], vb, 0, 0, 0);
-        if (pre) qb = __builtin_amdgcn_mfma_f64_16x16x4f64(cA, xt[et][1][k][lr], qb, 0, 0, 0);
+        vb = __builtin_amdgcn_mfma_f64_16x16x4f64(cb[ks], xt[et][0][k][lr], vb, 0, 0, 0);
+        if (pre) qb = __builtin_amdgcn_mfma_f64_16x16x4f64(cb[ks], xt[et][1][k][lr], qb, 0, 0, 0);
     }
     if (ok) {
 #pragma unroll
