@@ -233,13 +233,20 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                 int jj[kBatch];
                 bool in[kBatch];
                 float4 pj[kBatch];
+                // every load unconditional (slots past the block end reread
+                // its last entry, masked off) so that the batch's loads are
+                // in flight together
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
-                    const bool ok = sb + u < s1;
-                    jj[u] = ok ? uR[sb + u] : i;
-                    in[u] = ok && ((mR[ok ? sb + u : 0] >> b) & 1u);
-                    pj[u] = p4[(size_t)jj[u] * P + b];
+                    const int su = min(sb + u, s1 - 1);
+                    jj[u] = uR[su];
+                    const uint64_t mu = mR[su];
+                    in[u] = (sb + u < s1) & (((mu >> b) & 1u) != 0);
                 }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) pj[u] = p4[(size_t)jj[u] * P + b];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) keep(pj[u]);
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
                     if (in[u]) {
@@ -283,7 +290,7 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
         for (int t = 0; t < S; ++t) {
             int s0, s1;
             block_range(a.uendA, i, t, s0, s1);
-            const float *c = prm + a.oA + (tc * S + t) * NA1 * KA1;
+            const float *c = prm + __builtin_amdgcn_readfirstlane(a.oA + (tc * S + t) * NA1 * KA1);   // uniform
             // g_n = f_c / 2 (cs_n + sum_{k>0} c_nk T_k), cs_n = c_n0 + sum_k c_nk
             float cs[NA1];
 #pragma unroll
@@ -293,36 +300,50 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                 for (int q2 = 0; q2 < KA1; ++q2) acc += c[n * KA1 + q2];
                 cs[n] = acc;
             }
-            int jn = s0 < s1 ? (rowA[uA[s0]] >> 2) : i;
-            bool inn = s0 < s1 && ((mA[s0 < s1 ? s0 : 0] >> b) & 1u);
-            float4 pn = p4[(size_t)jn * P + b];
-            for (int sn = s0; sn < s1; ++sn) {
-                const float4 pc = pn;
-                const bool inc = inn;
-                if (sn + 1 < s1) {
-                    jn = rowA[uA[sn + 1]] >> 2;
-                    inn = (mA[sn + 1] >> b) & 1u;
-                    pn = p4[(size_t)jn * P + b];
+            // batches of kBatch entries: slots, then partners, then their
+            // positions, each level's loads in flight together (slots past
+            // the block end reread its last entry, masked off)
+            for (int sb = s0; sb < s1; sb += kBatch) {
+                // coefficients through scalar loads, which do not wait on the gathers
+                const cf32p cl = launder(c), shl = launder(shc);
+                int kq[kBatch];
+                bool in[kBatch];
+                float4 pj[kBatch];
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    const int su = min(sb + u, s1 - 1);
+                    kq[u] = uA[su];
+                    const uint64_t mu = mA[su];
+                    in[u] = (sb + u < s1) & (((mu >> b) & 1u) != 0);
                 }
-                if (!inc) continue;
-                float dx, dy, dz;
-                pair_vec<TRI>(pc, pi, lm, dx, dy, dz);
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                const float rinv = __builtin_amdgcn_rsqf(r2);
-                const float r = r2 * rinv;
-                float fc, T[KA1];
-                cheb_t<KA1>(r, a.rcAinv, fc, T);
-                const float hf = 0.5f * fc;
-                float Y[kNumSH];
-                sh_eval(dx * rinv, dy * rinv, dz * rinv, shc, Y);
 #pragma unroll
-                for (int n = 0; n < NA1; ++n) {
-                    float g = cs[n];
+                for (int u = 0; u < kBatch; ++u) kq[u] = rowA[kq[u]] >> 2;
 #pragma unroll
-                    for (int q2 = 1; q2 < KA1; ++q2) g = fmaf(c[n * KA1 + q2], T[q2], g);
-                    g *= hf;
+                for (int u = 0; u < kBatch; ++u) pj[u] = p4[(size_t)kq[u] * P + b];
 #pragma unroll
-                    for (int m = 0; m < kNumSH; ++m) A[n][m] += g * Y[m];
+                for (int u = 0; u < kBatch; ++u) keep(pj[u]);
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
+                    if (!in[u]) continue;
+                    float dx, dy, dz;
+                    pair_vec<TRI>(pj[u], pi, lm, dx, dy, dz);
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const float rinv = __builtin_amdgcn_rsqf(r2);
+                    const float r = r2 * rinv;
+                    float fc, T[KA1];
+                    cheb_t<KA1>(r, a.rcAinv, fc, T);
+                    const float hf = 0.5f * fc;
+                    float Y[kNumSH];
+                    sh_eval(dx * rinv, dy * rinv, dz * rinv, shl, Y);
+#pragma unroll
+                    for (int n = 0; n < NA1; ++n) {
+                        float g = cs[n];
+#pragma unroll
+                        for (int q2 = 1; q2 < KA1; ++q2) g = fmaf(cl[n * KA1 + q2], T[q2], g);
+                        g *= hf;
+#pragma unroll
+                        for (int m = 0; m < kNumSH; ++m) A[n][m] += g * Y[m];
+                    }
                 }
             }
         }
@@ -558,7 +579,7 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
             int jn = cnt > 0 ? (rowA[kn] >> 2) : i;
             bool inn = cnt > 0 && ((mA[cnt > 0 ? s0 : 0] >> b) & 1u);
             for (int sc = 0; sc < cmax; ++sc) {
-                const float *cij_l = launder(cij), *shc_l = launder(shc);
+                const cf32p cij_l = launder(cij), shc_l = launder(shc);
                 const int j = jn, kc = kn;
                 const bool act = inn;
                 const float4 pj = p4[(size_t)j * P + b];
@@ -707,14 +728,21 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
                 bool in[kBatch];
                 float4 pj[kBatch];
                 float aj[kBatch][KR1];
+                // unconditional loads, as in the descriptor's radial batches
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
-                    const bool ok = sb + u < s1;
-                    jj[u] = ok ? uR[sb + u] : i;
-                    in[u] = ok && ((mR[ok ? sb + u : 0] >> b) & 1u);
+                    const int su = min(sb + u, s1 - 1);
+                    jj[u] = uR[su];
+                    const uint64_t mu = mR[su];
+                    in[u] = (sb + u < s1) & (((mu >> b) & 1u) != 0);
+                }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) {
                     pj[u] = p4[(size_t)jj[u] * P + b];
                     load_a(jj[u], ti, aj[u]);
                 }
+#pragma unroll
+                for (int u = 0; u < kBatch; ++u) keep(pj[u]);
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
                     if (in[u]) {
@@ -757,12 +785,19 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
             int kk[kBatch];
             bool in[kBatch];
             float4 d[kBatch];
+            // unconditional loads (slots past the list end reread its last
+            // entry; values outside the bead mask are dropped)
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
-                const bool ok = sb + u < nA;
-                kk[u] = ok ? uA[sb + u] : 0;
-                in[u] = ok && ((mA[ok ? sb + u : 0] >> b) & 1u);
-                d[u] = in[u] ? pbuf[(size_t)kk[u] * P] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                const int su = min(sb + u, nA - 1);
+                kk[u] = uA[su];
+                const uint64_t mu = mA[su];
+                in[u] = (sb + u < nA) & (((mu >> b) & 1u) != 0);
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const float4 v = pbuf[(size_t)kk[u] * P];
+                d[u] = in[u] ? v : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {

@@ -116,10 +116,26 @@ constexpr int kBatch = 4;   // neighbours whose index and position are loaded to
 // Hide a uniform pointer from loop-invariant code motion, so that the model
 // coefficients it addresses are re-read through the scalar cache inside a
 // neighbour loop instead of being hoisted into (scarce) vector registers.
-__device__ __forceinline__ const float *launder(const float *p)
+// Pins a gathered value at this point: without it the compiler sinks a
+// load that only a masked branch uses into that branch, where it waits for
+// the loads issued before it, so a batch's gathers run one after another.
+__device__ __forceinline__ void keep(float4 &v)
+{
+    asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w));
+}
+
+// Model coefficients (read-only during a launch) through the constant
+// address space: loads at a wave-uniform address become scalar loads, which
+// do not wait on the vector gathers in flight.
+typedef const float __attribute__((address_space(4))) *cf32p;
+
+// A uniform coefficient pointer re-materialised in SGPRs at its point of use
+// (keeps the compiler from hoisting every coefficient out of a loop into
+// VGPRs), returned in the constant address space.
+__device__ __forceinline__ cf32p launder(const float *p)
 {
     asm volatile("" : "+s"(p));
-    return p;
+    return (cf32p)p;
 }
 
 }  // namespace nep

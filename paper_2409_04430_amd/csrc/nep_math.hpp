@@ -135,8 +135,9 @@ __device__ __forceinline__ void cheb_fd(float r, float rcinv, float *f, float *f
 }
 
 // Real spherical harmonics l = 1..4 (m = -l..l) at unit vector (x, y, z);
-// c holds the normalisations.
-__device__ __forceinline__ void sh_eval(float x, float y, float z, const float *__restrict__ c, float *Y)
+// c holds the normalisations (a generic or constant-space pointer).
+template <typename CP>
+__device__ __forceinline__ void sh_eval(float x, float y, float z, CP c, float *Y)
 {
     const float x2 = x * x, y2 = y * y, z2 = z * z;
     Y[0] = c[0] * y;
@@ -168,7 +169,8 @@ __device__ __forceinline__ void sh_eval(float x, float y, float z, const float *
 // sY = sum_m bp_m Y_m(u);  g = sum_m b_m grad p_m(u), where Y_m = c_m p_m and
 // the polynomial p_m is differentiated as a function on R^3 (the tangential
 // projection is applied by the caller).
-__device__ __forceinline__ void sh_contract(float x, float y, float z, const float *__restrict__ c, const float *b,
+template <typename CP>
+__device__ __forceinline__ void sh_contract(float x, float y, float z, CP c, const float *b,
                                             const float *bp, float &sY, float &gx, float &gy, float &gz)
 {
     float Y[kNumSH];
@@ -221,8 +223,8 @@ __device__ __forceinline__ void sh_contract(float x, float y, float z, const flo
 // time so that no per-m array stays live:
 //   sY = sum_m (sum_n B_nm g'_n) Y_m(u),  grad = sum_m (sum_n B_nm g_n) c_m grad p_m(u)
 // (p_m the polynomial of Y_m = c_m p_m, differentiated on R^3).
-template <int NA1>
-__device__ __forceinline__ void adjoint_contract(float x, float y, float z, const float *__restrict__ c,
+template <int NA1, typename CP>
+__device__ __forceinline__ void adjoint_contract(float x, float y, float z, CP c,
                                                  const float (*B)[kNumSH], const float *g, const float *gp, float &sY,
                                                  float &gx, float &gy, float &gz)
 {
