@@ -526,6 +526,8 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
 // past their atom's last candidate or outside the cutoff compute on a dummy
 // pair and contribute nothing; a candidate outside for every lane is
 // skipped.
+constexpr int kBatchAng = 4;   // angular entries whose loads are issued together
+
 template <int NA1, int KA1, bool BREG, bool TRI>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void k_force_ang(NepArgs a, const float *__restrict__ prm)
@@ -575,23 +577,40 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
             for (int o = 32; o > 0; o >>= 1) cmax = max(cmax, __shfl_xor(cmax, o));
             cmax = __builtin_amdgcn_readfirstlane(cmax);
             const float *cij = prm + a.oA + (tc * S + t) * NA1 * KA1;
-            int kn = cnt > 0 ? uA[s0] : 0;
-            int jn = cnt > 0 ? (rowA[kn] >> 2) : i;
-            bool inn = cnt > 0 && ((mA[cnt > 0 ? s0 : 0] >> b) & 1u);
-            for (int sc = 0; sc < cmax; ++sc) {
-                const cf32p cij_l = launder(cij), shc_l = launder(shc);
-                const int j = jn, kc = kn;
-                const bool act = inn;
-                const float4 pj = p4[(size_t)j * P + b];
-                inn = false;
-                if (sc + 1 < cnt) {
-                    kn = uA[s0 + sc + 1];
-                    inn = (mA[s0 + sc + 1] >> b) & 1u;
-                    jn = rowA[kn] >> 2;
+            for (int sb = 0; sb < cmax; sb += kBatchAng) {
+                // the batch's slots, partners, positions and reverse slots,
+                // each level's loads in flight together: every index is
+                // clamped into the row (a lane with an empty block reads its
+                // row's first entry) and its value selected after the load
+                int kq[kBatchAng], jq[kBatchAng], rq[kBatchAng];
+                bool aq[kBatchAng];
+                float4 pq[kBatchAng];
+#pragma unroll
+                for (int u = 0; u < kBatchAng; ++u) {
+                    const int su = min(s0 + max(min(sb + u, cnt - 1), 0), a.capA - 1);
+                    const int k0 = uA[su];
+                    const uint64_t mu = mA[su];
+                    kq[u] = cnt > 0 ? k0 : 0;
+                    aq[u] = (sb + u < cnt) & (((mu >> b) & 1u) != 0);
                 }
+#pragma unroll
+                for (int u = 0; u < kBatchAng; ++u) {
+                    const int r0 = rowA[kq[u]];
+                    rq[u] = rvA[kq[u]];
+                    jq[u] = cnt > 0 ? (r0 >> 2) : i;
+                }
+#pragma unroll
+                for (int u = 0; u < kBatchAng; ++u) pq[u] = p4[(size_t)jq[u] * P + b];
+#pragma unroll
+                for (int u = 0; u < kBatchAng; ++u) keep(pq[u]);
+#pragma unroll
+                for (int u = 0; u < kBatchAng; ++u) {
+                const cf32p cij_l = launder(cij), shc_l = launder(shc);
+                const int j = jq[u];
+                const bool act = aq[u];
                 if (__ballot(act) == 0) continue;
                 float dx, dy, dz;
-                pair_vec<TRI>(pj, pi, lm, dx, dy, dz);
+                pair_vec<TRI>(pq[u], pi, lm, dx, dy, dz);
                 if (!act) {
                     dx = 1.0f;
                     dy = 0.0f;
@@ -651,12 +670,13 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
                 const float py = sY * uy + (gy - uy * ug) * rinv;
                 const float pz = sY * uz + (gz - uz * ug) * rinv;
                 if (act) {
-                    const int rk = rvA[kc];
+                    const int rk = rq[u];
                     if (rk >= 0) a.pairbuf[((size_t)j * a.capA + rk) * P + b] = make_float4(px, py, pz, 0.0f);
                     Fx += px; Fy += py; Fz += pz;
                     Wv[0] = fmaf(-dx, px, Wv[0]); Wv[1] = fmaf(-dx, py, Wv[1]); Wv[2] = fmaf(-dx, pz, Wv[2]);
                     Wv[3] = fmaf(-dy, px, Wv[3]); Wv[4] = fmaf(-dy, py, Wv[4]); Wv[5] = fmaf(-dy, pz, Wv[5]);
                     Wv[6] = fmaf(-dz, px, Wv[6]); Wv[7] = fmaf(-dz, py, Wv[7]); Wv[8] = fmaf(-dz, pz, Wv[8]);
+                }
                 }
             }
         }
