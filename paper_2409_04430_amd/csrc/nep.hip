@@ -229,26 +229,26 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             float sk[KR1];
 #pragma unroll
             for (int k = 0; k < KR1; ++k) sk[k] = 0.0f;
-            for (int sb = s0; sb < s1; sb += kBatch) {
-                int jj[kBatch];
-                bool in[kBatch];
-                float4 pj[kBatch];
+            for (int sb = s0; sb < s1; sb += kBatchR) {
+                int jj[kBatchR];
+                bool in[kBatchR];
+                float4 pj[kBatchR];
                 // every load unconditional (slots past the block end reread
                 // its last entry, masked off) so that the batch's loads are
                 // in flight together
 #pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
+                for (int u = 0; u < kBatchR; ++u) {
                     const int su = min(sb + u, s1 - 1);
                     jj[u] = uR[su];
                     const uint64_t mu = mR[su];
                     in[u] = (sb + u < s1) & (((mu >> b) & 1u) != 0);
                 }
 #pragma unroll
-                for (int u = 0; u < kBatch; ++u) pj[u] = p4[(size_t)jj[u] * P + b];
+                for (int u = 0; u < kBatchR; ++u) pj[u] = p4[(size_t)jj[u] * P + b];
 #pragma unroll
-                for (int u = 0; u < kBatch; ++u) keep(pj[u]);
+                for (int u = 0; u < kBatchR; ++u) keep(pj[u]);
 #pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
+                for (int u = 0; u < kBatchR; ++u) {
                     if (in[u]) {
                         float dx, dy, dz;
                         pair_vec<TRI>(pj[u], pi, lm, dx, dy, dz);

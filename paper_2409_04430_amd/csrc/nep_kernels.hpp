@@ -111,7 +111,8 @@ __device__ __forceinline__ void bead_block_sum(double v, double *lds, int P, int
     __syncthreads();
 }
 
-constexpr int kBatch = 4;   // neighbours whose index and position are loaded together
+constexpr int kBatch = 4;    // neighbours whose index and position are loaded together
+constexpr int kBatchR = 8;   // the same for the descriptor's radial loop
 
 // Hide a uniform pointer from loop-invariant code motion, so that the model
 // coefficients it addresses are re-read through the scalar cache inside a
