@@ -815,9 +815,11 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
                 in[u] = (sb + u < nA) & (((mu >> b) & 1u) != 0);
             }
 #pragma unroll
+            for (int u = 0; u < kBatch; ++u) d[u] = pbuf[(size_t)kk[u] * P];
+#pragma unroll
             for (int u = 0; u < kBatch; ++u) {
-                const float4 v = pbuf[(size_t)kk[u] * P];
-                d[u] = in[u] ? v : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                keep(d[u]);
+                if (!in[u]) d[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
