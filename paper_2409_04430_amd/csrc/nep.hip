@@ -864,42 +864,38 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
                        9 * gridDim.x);
 }
 
-// Per-(system, bead) totals from the per-workgroup partial sums of the
-// system's tiles.  One workgroup per (system, bead): thread t adds tiles
+// Per-(system, bead) energy and virial from the per-workgroup partial sums
+// of the system's tiles, stored [P][nblk] (energy) and [P][9][nblk] (virial
+// parts).  One workgroup per (system, bead, component): thread t adds tiles
 // t, t + 256, ... in order, then a fixed-shape tree over the threads, so the
 // result is bitwise reproducible.  Component 0 is E, 1..9 the virial.
-// Per-bead energy and virial of each system from the workgroups' partials,
-// stored [P][nblk] (energy) and [P][9][nblk] (virial parts): one workgroup
-// per (system, bead), fixed order.
 __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partE, const double *__restrict__ partWa,
                                                 const double *__restrict__ partWr, const int32_t *__restrict__ sys_tile0,
                                                 int P, int nblk, double *__restrict__ E, double *__restrict__ W)
 {
-    __shared__ double red[10][256];
-    const int sb = blockIdx.x, sy = sb / P, b = sb - sy * P, t = threadIdx.x;
+    // one workgroup per (system, bead) and component c (0: E, 1..9: W)
+    __shared__ double red[256];
+    const int sb = blockIdx.x, sy = sb / P, b = sb - sy * P, t = threadIdx.x, c = blockIdx.y;
     const int k0 = sys_tile0[sy], k1 = sys_tile0[sy + 1];
-    double acc[10];
-#pragma unroll
-    for (int c = 0; c < 10; ++c) acc[c] = 0.0;
-    for (int k = k0 + t; k < k1; k += blockDim.x) {
-        acc[0] += partE[(size_t)b * nblk + k];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) {
-            const size_t o = ((size_t)b * 9 + c) * nblk + k;
-            acc[c + 1] += partWa[o] + partWr[o];
+    double acc = 0.0;
+    if (c == 0) {
+        for (int k = k0 + t; k < k1; k += blockDim.x) acc += partE[(size_t)b * nblk + k];
+    } else {
+        for (int k = k0 + t; k < k1; k += blockDim.x) {
+            const size_t o = ((size_t)b * 9 + (c - 1)) * nblk + k;
+            acc += partWa[o] + partWr[o];
         }
     }
-#pragma unroll
-    for (int c = 0; c < 10; ++c) red[c][t] = acc[c];
+    red[t] = acc;
     __syncthreads();
     for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
-        if (t < w)
-#pragma unroll
-            for (int c = 0; c < 10; ++c) red[c][t] += red[c][t + w];
+        if (t < w) red[t] += red[t + w];
         __syncthreads();
     }
-    if (t == 0) E[sb] = red[0][0];
-    if (t >= 1 && t <= 9) W[(size_t)sb * 9 + (t - 1)] = red[t][0];
+    if (t == 0) {
+        if (c == 0) E[sb] = red[0];
+        else W[(size_t)sb * 9 + (c - 1)] = red[0];
+    }
 }
 
 constexpr size_t kNetLdsMax = 60 * 1024;   // bytes of LDS for the staged network weights
@@ -1010,7 +1006,7 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
     }
     {
         ProfScope ps_(K_REDUCE, s);
-        hipLaunchKernelGGL(k_reduce, dim3(nsys * P), dim3(256), 0, s, ws->partE, a.partWa, a.partWr, ws->sys_tile0,
+        hipLaunchKernelGGL(k_reduce, dim3(nsys * P, 10), dim3(256), 0, s, ws->partE, a.partWa, a.partWr, ws->sys_tile0,
                            P, ws->nblk, E, W);
     }
     NEP_HIP(hipGetLastError());
