@@ -97,6 +97,8 @@ struct nep_nlist {
     float *spr = nullptr;         // [N] largest bead distance from the centroid (rounded up) of this call
     double *cen_ref = nullptr;    // [N][3] centroids at the last rebuild
     int32_t *candR = nullptr;     // [N][capR] entries (j << 2) | species(j), sorted by (species, j)
+    int32_t *candRs = nullptr;    // [N][capR] the same rows unsorted, as the candidate search leaves them
+    int32_t *candAs = nullptr;    // [N][capA] the angular rows unsorted
     int32_t *lenR = nullptr;      // [N] candidates found (may exceed capR: overflow)
     int32_t *offR = nullptr;      // [N][5] species block starts, [S] = row length
     int32_t *candA = nullptr;     // [N][capA] the same for the angular radius

@@ -374,28 +374,36 @@ __global__ __launch_bounds__(kDecideBlock) void k_decide(const SysGeom *__restri
 
 
 
-// Sort one candidate row by (species, index) in place and record its species
+// One candidate row sorted by (species, index) into dst, with its species
 // block starts: rank sort by one wavefront (each element's position is the
-// number of smaller keys), reading the row from buf (rows up to kSortLds
-// entries, in LDS) or from the atom's row of a scratch array.
+// number of smaller keys), reading the unsorted row from lds (rows up to
+// kSortLds entries, copied there first) or straight from src.  src is not
+// modified, so other wavefronts may read it meanwhile.
 constexpr int kSortLds = 512;
-__device__ void sort_row(int32_t *__restrict__ row, int n, int32_t *__restrict__ src, int S,
-                         int32_t *__restrict__ off)
+__device__ __forceinline__ uint32_t cand_key(int32_t w)
+{
+    return ((uint32_t)(w & 3) << 29) | (uint32_t)(w >> 2);   // species above index; entries are distinct
+}
+
+__device__ void sort_row_into(int32_t *__restrict__ dst, int n, const int32_t *__restrict__ src,
+                              int32_t *__restrict__ lds, int S, int32_t *__restrict__ off)
 {
     const int lane = threadIdx.x & 63;
-    for (int e = lane; e < n; e += 64) src[e] = row[e];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    // key: species above index; entries are distinct
-    auto key = [](int32_t w) { return ((uint32_t)(w & 3) << 29) | (uint32_t)(w >> 2); };
+    const int32_t *from = src;
+    if (n <= kSortLds) {
+        for (int e = lane; e < n; e += 64) lds[e] = src[e];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        from = lds;
+    }
     int cntS[kMaxSpecies] = {0, 0, 0, 0};
     for (int e = lane; e < n; e += 64) {
-        const int32_t w = src[e];
-        const uint32_t kw = key(w);
+        const int32_t w = from[e];
+        const uint32_t kw = cand_key(w);
         int r = 0;
-        for (int f = 0; f < n; ++f) r += key(src[f]) < kw;
-        row[r] = w;
+        for (int f = 0; f < n; ++f) r += cand_key(from[f]) < kw;
+        dst[r] = w;
 #pragma unroll
         for (int t = 0; t < kMaxSpecies; ++t) cntS[t] += (w & 3) == t;
     }
@@ -410,33 +418,11 @@ __device__ void sort_row(int32_t *__restrict__ row, int n, int32_t *__restrict__
         }
         off[S] = run;
     }
-    // the buffer is reused by the next row of this wavefront
+    // the sorted row, its block starts and the buffer are read next by
+    // every lane of this wavefront
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
-
-// Sort every candidate row (rebuild calls only): one wavefront per atom and
-// row kind (blockIdx.y: radial, angular), so the quadratic rank sort of the
-// longer rows spreads over the whole chip.
-__global__ __launch_bounds__(kBlock) void k_sort_rows(const uint32_t *__restrict__ grid, int N, int S, int capR,
-                                                      int32_t *__restrict__ candR, const int32_t *__restrict__ lenR,
-                                                      int32_t *__restrict__ offR, int32_t *__restrict__ scratchR,
-                                                      int capA, int32_t *__restrict__ candA,
-                                                      const int32_t *__restrict__ lenA, int32_t *__restrict__ offA,
-                                                      int32_t *__restrict__ scratchA)
-{
-    if (!dev_global(grid)->rebuild) return;   // whole workgroup
-    __shared__ int32_t buf[kBlock / 64][kSortLds];
-    const int wv = threadIdx.x >> 6;
-    const int i = blockIdx.x * (kBlock / 64) + wv;
-    if (i >= N) return;   // whole wavefront
-    const bool ang = blockIdx.y != 0;
-    const int cap = ang ? capA : capR;
-    const int n = min((ang ? lenA : lenR)[i], cap);
-    int32_t *row = (ang ? candA : candR) + (size_t)i * cap;
-    sort_row(row, n, n <= kSortLds ? buf[wv] : (ang ? scratchA : scratchR) + (size_t)i * cap, S,
-             (ang ? offA : offR) + (size_t)i * (kMaxSpecies + 1));
 }
 
 // Candidate rows.  gridDim.y workgroups per cell, each taking every
@@ -445,8 +431,9 @@ __global__ __launch_bounds__(kBlock) void k_sort_rows(const uint32_t *__restrict
 // (3 x 3 x 3, fewer along an axis with fewer than 3 cells) are staged in
 // LDS when they fit, and each wavefront takes one atom at a time, its lanes
 // testing 64 stencil atoms at once and appending the accepted ones by
-// ballot + prefix popcount (stencil order; sorted by k_sort_rows).  A
-// stencil too large for LDS is read from global memory instead.
+// ballot + prefix popcount (stencil order, into the unsorted staging rows,
+// which k_union sorts).  A stencil too large for LDS is read from global
+// memory instead.
 constexpr int kStage = 2048;
 constexpr int kCandSplitMax = 16;   // workgroups per cell at most
 __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ cen, const int32_t *__restrict__ types,
@@ -600,8 +587,10 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
                                                const double *__restrict__ cen, const float *__restrict__ spr, int P,
                                                int N, int S, int lg, const int32_t *__restrict__ atom_sys,
                                                const SysGeom *__restrict__ geom, CutTest cR, CutTest cA,
-                                               const int32_t *__restrict__ candR, const int32_t *__restrict__ offR,
-                                               const int32_t *__restrict__ candA, const int32_t *__restrict__ offA,
+                                               int32_t *__restrict__ candR, int32_t *__restrict__ offR,
+                                               int32_t *__restrict__ candA, int32_t *__restrict__ offA,
+                                               const int32_t *__restrict__ candRs, const int32_t *__restrict__ candAs,
+                                               const int32_t *__restrict__ lenR, const int32_t *__restrict__ lenA,
                                                int capR, int capA, int32_t *__restrict__ uniR,
                                                uint64_t *__restrict__ umR, int32_t *__restrict__ uendR,
                                                int32_t *__restrict__ uniA, uint64_t *__restrict__ umA,
@@ -613,25 +602,37 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
     const int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int kind = blockIdx.y;   // 0: radial list, 1: angular list
     if (i >= N) return;            // whole wavefront
-    if (kind == 1 && dev_global(grid)->rebuild) {
-        // rows rebuilt in this call: reverse slot of every angular candidate, i.e.
-        // for candidate j of i (slot k) the slot of i in j's row, by binary search
-        // in the species block of i (ordered by index); -1 if i is missing (only
-        // when j's row overflowed)
-        const int ti = types[i] & 3;
-        const int S1 = kMaxSpecies + 1;
-        const int n = min(offA[(size_t)i * S1 + S], capA);
-        for (int k = lane; k < n; k += 64) {
-            const int j = candA[(size_t)i * capA + k] >> 2;
-            const int32_t *rj = candA + (size_t)j * capA;
-            const int hi0 = min(offA[(size_t)j * S1 + ti + 1], capA);
-            int lo = min(offA[(size_t)j * S1 + ti], capA), hi = hi0;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if ((rj[mid] >> 2) < i) lo = mid + 1;
-                else hi = mid;
+    if (dev_global(grid)->rebuild) {
+        // rows rebuilt in this call: this wavefront's row, left unsorted in
+        // the staging array by the candidate search, sorted into the list
+        __shared__ int32_t sbuf[4][kSortLds];   // one buffer per wavefront of the 256-lane workgroup
+        const int cap = kind ? capA : capR;
+        const int n = min((kind ? lenA : lenR)[i], cap);
+        int32_t *srow = (kind ? candA : candR) + (size_t)i * cap;
+        sort_row_into(srow, n, (kind ? candAs : candRs) + (size_t)i * cap, sbuf[threadIdx.x >> 6], S,
+                      (kind ? offA : offR) + (size_t)i * (kMaxSpecies + 1));
+        if (kind == 1) {
+            // reverse slot of every angular candidate: for candidate j of i
+            // (slot k) the slot of i in j's sorted row, i.e. the number of
+            // smaller keys in j's row, counted in its unsorted staging copy
+            // (no other row need be sorted yet); -1 if i is missing (only
+            // when j's row overflowed)
+            const int ti = types[i] & 3;
+            const int32_t wi = (int32_t)(((uint32_t)i << 2) | (uint32_t)ti);
+            const uint32_t ki = cand_key(wi);
+            for (int k = lane; k < n; k += 64) {
+                const int j = srow[k] >> 2;
+                const int nj = min(lenA[j], capA);
+                const int32_t *rj = candAs + (size_t)j * capA;
+                int r = 0;
+                bool found = false;
+                for (int f = 0; f < nj; ++f) {
+                    const int32_t w = rj[f];
+                    r += cand_key(w) < ki;
+                    found |= w == wi;
+                }
+                revA[(size_t)i * capA + k] = found ? r : -1;
             }
-            revA[(size_t)i * capA + k] = (lo < hi0 && (rj[lo] >> 2) == i) ? lo : -1;
         }
     }
     const int cg = lane >> lg, b = lane & (G - 1);
@@ -884,17 +885,9 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
     {
         ProfScope ps_(K_CANDIDATES, s);
         hipLaunchKernelGGL(k_candidates, gc, dim3(kBlock), 0, s, nl->cen, types, N, nl->S, nl->geom, nl->cell_sys,
-                           nl->grid, nl->cell_start, nl->cell_atoms, nl->cell_cnt, nl->capR, nl->capA, nl->candR,
+                           nl->grid, nl->cell_start, nl->cell_atoms, nl->cell_cnt, nl->capR, nl->capA, nl->candRs,
                            nl->lenR,
-                           nl->candA, nl->lenA, nl->cen_ref, nl->status);
-    }
-    {
-        // one wavefront per (atom, row kind); the union-list and reverse-slot
-        // arrays serve as sort scratch for long rows before they are filled
-        ProfScope ps_(K_SORT_ROWS, s);
-        hipLaunchKernelGGL(k_sort_rows, dim3(div_up(N, kBlock / 64), 2), dim3(kBlock), 0, s, nl->grid, N, nl->S,
-                           nl->capR, nl->candR, nl->lenR, nl->offR, nl->uniR, nl->capA, nl->candA, nl->lenA,
-                           nl->offA, nl->revA);
+                           nl->candAs, nl->lenA, nl->cen_ref, nl->status);
     }
     {
         ProfScope ps_(K_NLIST, s);
@@ -905,7 +898,8 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
         auto kern = nl->any_tri ? k_union<true> : k_union<false>;
         hipLaunchKernelGGL(kern, dim3(div_up(N, kBlock / 64), 2), dim3(kBlock), 0, s, pos,
                            reinterpret_cast<const float4 *>(nl->pos4), nl->cen, nl->spr, P, N, nl->S, lg, nl->atom_sys, nl->geom, cR,
-                           cA, nl->candR, nl->offR, nl->candA, nl->offA, nl->capR, nl->capA, nl->uniR, nl->umR,
+                           cA, nl->candR, nl->offR, nl->candA, nl->offA, nl->candRs, nl->candAs, nl->lenR, nl->lenA,
+                           nl->capR, nl->capA, nl->uniR, nl->umR,
                            nl->uendR, nl->uniA, nl->umA, nl->uendA, nl->status, nl->grid, types, nl->revA);
     }
     NEP_HIP(hipGetLastError());
