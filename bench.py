@@ -66,8 +66,7 @@ def parse():
 # source file of each timed kernel (the stored HBM traffic of a kernel stays
 # valid while the files it is compiled from and the build flags are unchanged)
 KERNEL_SOURCES = {"descriptor": "nep.hip", "force_ang": "nep.hip", "force": "nep.hip", "reduce": "nep.hip",
-                  "nlist": "nlist.hip", "centroid": "nlist.hip", "candidates": "nlist.hip",
-                  "sort_rows": "nlist.hip", "trpmd": "pimd.hip"}
+                  "nlist": "nlist.hip", "centroid": "nlist.hip", "candidates": "nlist.hip", "trpmd": "pimd.hip"}
 
 
 def kernel_source_hash(kernel: str) -> str:

@@ -115,10 +115,9 @@ FineGrid fine_grid(const double L[3], double rc)
 
 // ---------------------------------------------------------- profiling ---
 
-static const char *kKernelNames[K_NUM] = {"fill", "pack", "centroid", "grid", "cell_count", "cell_scan", "cell_fill",
-                                          "cell_sort", "candidates", "sort_rows", "reverse", "nlist",
-                                          "materialize", "descriptor", "force_ang", "force", "reduce", "trpmd", "modes",
-                                          "observables", "barostat", "rdf"};
+static const char *kKernelNames[K_NUM] = {"fill",   "centroid", "candidates", "nlist",       "materialize",
+                                          "descriptor", "force_ang", "force", "reduce",   "trpmd",
+                                          "modes", "observables", "barostat", "rdf"};
 static std::atomic<int> g_prof_on{0};
 static std::atomic<int> g_prof_only{-1};   // -1: every kind
 static std::mutex g_prof_mu;

@@ -410,8 +410,7 @@ int32_t update_geometry(const nep_model *m, nep_nlist *nl, const double *boxes, 
 
 // Kernel timing (hipEvents around launches on the caller's stream), off by default.
 enum KernelId {
-    K_FILL = 0, K_PACK, K_CENTROID, K_GRID, K_CELL_COUNT, K_CELL_SCAN, K_CELL_FILL, K_CELL_SORT, K_CANDIDATES,
-    K_SORT_ROWS, K_REVERSE, K_NLIST, K_MATERIALIZE,
+    K_FILL = 0, K_CENTROID, K_CANDIDATES, K_NLIST, K_MATERIALIZE,
     K_DESCRIPTOR, K_FORCE_ANG, K_FORCE, K_REDUCE, K_TRPMD, K_MODES, K_OBS, K_BARO, K_RDF, K_NUM
 };
 struct ProfScope {
