@@ -527,6 +527,7 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
 // pair and contribute nothing; a candidate outside for every lane is
 // skipped.
 constexpr int kBatchAng = 4;   // angular entries whose loads are issued together
+constexpr int kBatchRev = 8;   // reverse angular terms read together by the radial force kernel
 
 template <int NA1, int KA1, bool BREG, bool TRI>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
@@ -801,33 +802,33 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
         const float4 *pbuf = a.pairbuf + (size_t)i * a.capA * P + b;
         const int nA = a.uendA[(size_t)i * kMaxSpecies + S - 1];
         float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-        for (int sb = 0; sb < nA; sb += kBatch) {
-            int kk[kBatch];
-            bool in[kBatch];
-            float4 d[kBatch];
+        for (int sb = 0; sb < nA; sb += kBatchRev) {
+            int kk[kBatchRev];
+            bool in[kBatchRev];
+            float4 d[kBatchRev];
             // unconditional loads (slots past the list end reread its last
             // entry; values outside the bead mask are dropped)
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
+            for (int u = 0; u < kBatchRev; ++u) {
                 const int su = min(sb + u, nA - 1);
                 kk[u] = uA[su];
                 const uint64_t mu = mA[su];
                 in[u] = (sb + u < nA) & (((mu >> b) & 1u) != 0);
             }
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) d[u] = pbuf[(size_t)kk[u] * P];
+            for (int u = 0; u < kBatchRev; ++u) d[u] = pbuf[(size_t)kk[u] * P];
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
+            for (int u = 0; u < kBatchRev; ++u) {
                 keep(d[u]);
                 if (!in[u]) d[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
 #pragma unroll
-            for (int u = 0; u < kBatch; ++u) {
+            for (int u = 0; u < kBatchRev; ++u) {
                 gx -= d[u].x; gy -= d[u].y; gz -= d[u].z;
             }
             if (a.Watom) {
 #pragma unroll
-                for (int u = 0; u < kBatch; ++u) {
+                for (int u = 0; u < kBatchRev; ++u) {
                     if (!in[u]) continue;
                     float dx, dy, dz;
                     pair_vec<TRI>(p4[(size_t)(rowA[kk[u]] >> 2) * P + b], pi, lm, dx, dy, dz);
