@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-student", action="store_true", help="skip the learned-student leg")
     ap.add_argument("--no-npt", action="store_true", help="skip the barostat (NPT) leg")
     ap.add_argument("--no-triclinic", action="store_true", help="skip the general-cell leg")
+    ap.add_argument("--no-full-run", action="store_true", help="skip the configured-length run record")
+    ap.add_argument("--no-legs", action="store_true", help="skip the legs of the other configurations")
     ap.add_argument("--npt-steps", type=int, default=50, help="timed steps of the NPT leg")
     ap.add_argument("--student-only", action="store_true",
                     help="run only the learned-student leg (prints its JSON object)")
@@ -125,6 +127,39 @@ def flops_per_atom(hp: dict, nR: float, nA: float) -> dict:
     return {"descriptor": desc, "force_ang": force_ang, "force": force}
 
 
+def flops_per_atom_reference(hp: dict, nR: float, nA: float) -> dict:
+    """Algorithmic flops per (bead, atom) by the plain method's count, per
+    neighbour of the straightforward evaluation (basis contracted with the
+    coefficients per neighbour, L = 24 spherical harmonics):
+      radial energy   2 (n_R+1)(K_R+1) + 4 (K_R+1) + 20
+      radial force    2 [2 (n_R+1)(K_R+1) + 6 (K_R+1)] + 4 (n_R+1) + 30
+      angular energy  2 (n_A+1)(K_A+1) + 4 (K_A+1) + 3 L + 2 (n_A+1) L
+      angular force   2 [4 (n_A+1)(K_A+1) + 10 L + 8 (n_A+1) L]
+      network         4 D H
+    The descriptor kernel does the energy terms and the network, the angular
+    force kernel the angular force terms, the radial force kernel the radial
+    force terms."""
+    NR1, NA1 = hp["n_max_radial"] + 1, hp["n_max_angular"] + 1
+    KR1, KA1, H, D = hp["basis_radial"] + 1, hp["basis_angular"] + 1, hp["hidden"], hp["dim"]
+    L = 24
+    rad_e = 2 * NR1 * KR1 + 4 * KR1 + 20
+    rad_f = 2 * (2 * NR1 * KR1 + 6 * KR1) + 4 * NR1 + 30
+    ang_e = 2 * NA1 * KA1 + 4 * KA1 + 3 * L + 2 * NA1 * L
+    ang_f = 2 * (4 * NA1 * KA1 + 10 * L + 8 * NA1 * L)
+    return {"descriptor": nR * rad_e + nA * ang_e + 4 * D * H, "force_ang": nA * ang_f, "force": nR * rad_f}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def bytes_per_atom(hp: dict, nR: float, nA: float, P: int, cR: float = 0.0, cA: float = 0.0) -> dict:
     """Minimum HBM bytes per (bead, atom): every array read or written once.
 
@@ -165,10 +200,28 @@ def cpu_baseline(w, model_path, system, nb_req: int):
                        step=1, stage=oracle.FUSED)
     t_int = time.perf_counter() - t0
     t_step = t_nep / nb * P + t_int
-    return {"value": N * P / t_step, "unit": UNIT, "cores": oracle.num_threads(), "kind": "oracle",
+    threads = oracle.num_threads()
+    # the same sample on one core: two beads and the integrator stage
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        M.beads(system.pos[:2], system.types, system.box)
+        t1_nep = (time.perf_counter() - t0) / 2
+        pos, vel = system.pos.copy(), system.vel.copy()
+        t0 = time.perf_counter()
+        oracle.trpmd_stage(pos, vel, F, system.masses, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed,
+                           step=1, stage=oracle.FUSED)
+        t1_int = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(threads)
+    t1_step = t1_nep * P + t1_int
+    return {"value": N * P / t_step, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": len(os.sched_getaffinity(0)),
+            "value_1_core": N * P / t1_step,
             "sample": f"NEP energy/forces/virial (brute-force neighbours) of {nb} of {P} beads x {N} atoms "
                       f"({t_nep:.1f} s) plus one fused integrator stage over all beads ({t_int:.2f} s); "
-                      f"step time = per-bead NEP time x {P} + integrator time"}
+                      f"step time = per-bead NEP time x {P} + integrator time; one core: 2 beads "
+                      f"({2 * t1_nep:.1f} s) and the integrator stage ({t1_int:.2f} s)"}
 
 
 def npt_leg(args, torch, lib, w, model_path, s, NepPimd, nvt_ms: float):
@@ -350,6 +403,161 @@ def hp_S(eng) -> int:
     return int(eng.model.hp["n_species"])
 
 
+def list_stats(eng):
+    """Mean per-bead neighbour counts (radial, angular) and mean candidate-row lengths."""
+    lst = eng.nl.to_host(eng.pos, eng.box, eng.caps[0], eng.caps[1])
+    S = hp_S(eng)
+    return (float(lst["cnt_radial"].mean()), float(lst["cnt_angular"].mean()),
+            float(lst["cand_off_radial"][:, S].mean()), float(lst["cand_off_angular"][:, S].mean()))
+
+
+def kernel_profile(torch, lib, eng, steps: int) -> dict:
+    """Average duration (us) and launch count of every library kernel over `steps` steps."""
+    lib.profile_read(reset=True)
+    lib.profile_enable(True)
+    eng.run(steps)
+    torch.cuda.synchronize()
+    lib.profile_enable(False)
+    kt = lib.profile_read(reset=True)
+    return {k: {"avg_us": 1e3 * v[0] / v[1], "launches": v[1]} for k, v in kt.items() if v[1]}
+
+
+def dominant_kernel_time(torch, lib, eng, dom: str, steps: int) -> float:
+    """Average launch duration (us) of kernel `dom`, HIP events on its launch stream, over `steps` steps."""
+    lib.profile_read(reset=True)
+    lib.profile_enable(True, only=dom)
+    eng.run(steps)
+    torch.cuda.synchronize()
+    lib.profile_enable(False)
+    lib.profile_enable(False, only=None)
+    v = lib.profile_read(reset=True)[dom]
+    return 1e3 * v[0] / v[1] if v[1] else None
+
+
+def roofline(dom, avg_us, hp, nR, nA, units, byts):
+    """The dominant kernel against its roofline: VALU-bound kernels by the
+    plain method's flop count (and by this implementation's own count),
+    HBM-bound ones by their algorithmic bytes."""
+    if not dom or not avg_us:
+        return None
+    sec = avg_us * 1e-6
+    ref = flops_per_atom_reference(hp, nR, nA)
+    own = flops_per_atom(hp, nR, nA)
+    if dom in ref:
+        ach = ref[dom] * units / sec / 1e12
+        ach_own = own[dom] * units / sec / 1e12
+        return {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None, "kernel": dom,
+                "avg_us": round(avg_us, 2), "flop_per_atom_bead": round(ref[dom], 1), "units_per_launch": units,
+                "flop_count": "plain method, per neighbour",
+                "frac_own_count": round(ach_own / PEAK_FP32_VALU_TFLOPS, 4),
+                "flop_per_atom_bead_own_count": round(own[dom], 1),
+                "frac_of_non_packed_fp32": round(ach / (PEAK_FP32_VALU_TFLOPS / 2), 4)}
+    ach = byts.get(dom, 0.0) * units / sec / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": dom, "avg_us": round(avg_us, 2)}
+
+
+def timed_steps(torch, eng, steps: int, graph: bool):
+    """(GPU ms per step, wall s, candidate rebuilds) of `steps` whole steps with
+    inputs resident, bracketed by synchronisations; the polls before and after
+    verify the lists (an overflow inside the region grows the rows, and the
+    region is timed again)."""
+    stream = torch.cuda.current_stream()
+    if graph and eng.graph is None:
+        eng.capture()
+    for _attempt in range(3):
+        eng.check()
+        rb0 = eng.rollbacks
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        eng.run(steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        rebuilds = int(eng.nl.status(clear=False)["rebuilds"])
+        mr, ma = eng.check()
+        if eng.rollbacks == rb0:
+            break
+    return ev0.elapsed_time(ev1) / steps, wall, rebuilds, (mr, ma)
+
+
+def full_run_leg(torch, lib, w, model_path, s, NepPimd):
+    """The configured run length from the initial structure: polls every 50
+    steps, mean ms per step over the whole run (polls included), candidate
+    rebuilds, capacity regrowths, neighbour counts at the start and the end
+    and the centroid mean squared displacement."""
+    eng = NepPimd(model_path, s, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=50,
+                  regrow_budget_s=120.0)
+    eng.forces()
+    nR0, nA0, _, _ = list_stats(eng)
+    c0 = eng.pos.mean(dim=0)
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    eng.run(w.steps)
+    ev1.record(stream)
+    eng.check()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    msd = float(((eng.pos.mean(dim=0) - c0) ** 2).sum(dim=1).mean())
+    nR1, nA1, _, _ = list_stats(eng)
+    ms = ev0.elapsed_time(ev1) / w.steps
+    out = {"steps": w.steps, "ms_per_step": round(ms, 4), "value": round(s.N * s.P / (ms * 1e-3), 1),
+           "wall_s": round(wall, 3), "candidate_rebuilds": eng.rebuilds_total, "capacity_regrowths": eng.rollbacks,
+           "mean_neighbours_start": [round(nR0, 2), round(nA0, 2)],
+           "mean_neighbours_end": [round(nR1, 2), round(nA1, 2)],
+           "centroid_msd_A2": round(msd, 5), "polls_every": 50}
+    del eng
+    return out
+
+
+def workload_leg(args, torch, lib, configs, I, NepPimd, name: str, steps: int, graph: bool):
+    """Another configuration timed like the headline: warm-up with polls, then
+    `steps` eager steps (and graph replays), per-kernel times and the dominant
+    kernel's roofline."""
+    w = configs.WORKLOADS[name]
+    systems = w.systems()
+    sysarg = systems if len(systems) > 1 else systems[0]
+    tmp = tempfile.mkdtemp(prefix="neppimd_")
+    path = os.path.join(tmp, f"{name}.nep")
+    I.write_model(path, w.model())
+    eng = NepPimd(path, sysarg, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=50,
+                  autotune=len(systems) > 1)
+    eng.run(args.warmup)
+    eng.check()
+    eng.check_every = 0
+    N, P = eng.N, eng.P
+    units = N * P
+    nR, nA, cR, cA = list_stats(eng)
+    hp = eng.model.hp
+    kernels = kernel_profile(torch, lib, eng, 5) if not args.no_profile else {}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"]) if kernels else None
+    dom_us = dominant_kernel_time(torch, lib, eng, dom, 10) if dom else None
+    ms, wall, rb, _ = timed_steps(torch, eng, steps, False)
+    out = {"workload": f"{name}_p{P}", "systems": len(systems), "atoms": N, "beads": P, "steps": steps,
+           "ms_per_step": round(ms, 4), "value": round(units / (ms * 1e-3), 1), "rebuilds_timed": rb,
+           "mean_neighbours": [round(nR, 2), round(nA, 2)],
+           "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
+           "roofline": roofline(dom, dom_us, hp, nR, nA, units, bytes_per_atom(hp, nR, nA, P, cR, cA))}
+    if eng.tile is not None:
+        out["autotuned_waves_per_group"] = eng.tile[0]
+        out["autotune_ms"] = {str(k): round(v, 4) for k, v in eng.tile[1].items()}
+    if graph:
+        gms, _, grb, _ = timed_steps(torch, eng, steps, True)
+        out["graph_ms_per_step"] = round(gms, 4)
+        out["graph_value"] = round(units / (gms * 1e-3), 1)
+        out["graph_rebuilds_timed"] = grb
+        eng.release()
+    del eng
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -382,93 +590,33 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    eng = NepPimd(model_path, s, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=0)
+    # warm-up polled every 50 steps (an overflow replays one window at most);
+    # no polls inside the timed region
+    eng = NepPimd(model_path, s, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=50)
     eng.run(args.warmup)
     eng.check()
-    lst = eng.nl.to_host(eng.pos, eng.box, eng.caps[0], eng.caps[1])
-    nR = float(lst["cnt_radial"].mean())
-    nA = float(lst["cnt_angular"].mean())
-    cR = float(lst["cand_off_radial"][:, hp_S(eng)].mean())
-    cA = float(lst["cand_off_angular"][:, hp_S(eng)].mean())
+    eng.check_every = 0
+    nR, nA, cR, cA = list_stats(eng)
     hp = eng.model.hp
 
     # per-kernel breakdown: a short pass with every library kernel bracketed
     # by events, outside the timed region
-    kernels = {}
-    if not args.no_profile:
-        lib.profile_read(reset=True)
-        lib.profile_enable(True)
-        eng.run(max(5, min(20, args.steps // 10)))
-        torch.cuda.synchronize()
-        lib.profile_enable(False)
-        kt = lib.profile_read(reset=True)
-        kernels = {k: {"avg_us": 1e3 * v[0] / v[1], "launches": v[1]} for k, v in kt.items() if v[1]}
+    kernels = kernel_profile(torch, lib, eng, max(5, min(20, args.steps // 10))) if not args.no_profile else {}
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"]) if kernels else None
-
     # eager pass: the dominant kernel bracketed by events on its launch stream
-    eager_steps = max(10, min(50, args.steps))
-    if dom:
-        lib.profile_read(reset=True)
-        lib.profile_enable(True, only=dom)
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    eng.run(eager_steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    lib.profile_enable(False)
-    lib.profile_enable(False, only=None)
-    eager_ms = e0.elapsed_time(e1) / eager_steps
-    dom_avg_us = None
-    if dom:
-        v = lib.profile_read(reset=True)[dom]
-        dom_avg_us = 1e3 * v[0] / v[1] if v[1] else None
+    dom_avg_us = dominant_kernel_time(torch, lib, eng, dom, max(10, min(50, args.steps))) if dom else None
 
+    # the other launch mode in the same process, for comparison
+    other = timed_steps(torch, eng, max(20, min(100, args.steps)), not args.graph)[0]
+    eng.release()
     # timed region: K whole steps (eager launches, or graph replays with --graph)
-    if args.graph:
-        eng.capture()
-    for _attempt in range(3):
-        # a poll before the region verifies the state and clears the counters, so
-        # the rebuild count below covers the timed steps only
-        eng.check()
-        rb0 = eng.rollbacks
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ev0.record(stream)
-        eng.run(args.steps)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        rebuilds = int(eng.nl.status(clear=False)["rebuilds"])
-        mr, ma = eng.check()
-        if eng.rollbacks == rb0:
-            break   # else rows overflowed inside the region: they were grown, time again
+    ms, wall, rebuilds, (mr, ma) = timed_steps(torch, eng, args.steps, args.graph)
     regrowths = eng.rollbacks
-    gpu_ms = ev0.elapsed_time(ev1)
-    elapsed = max(gpu_ms / 1e3, 1e-12)
-    value = s.N * s.P * args.steps / elapsed
-
-    flops = flops_per_atom(hp, nR, nA)
-    byts = bytes_per_atom(hp, nR, nA, s.P, cR, cA)
+    value = s.N * s.P / (ms * 1e-3)
     units = s.N * s.P
-    roof = None
-    if dom and dom_avg_us:
-        avg_s = dom_avg_us * 1e-6
-        if dom in flops:
-            ach = flops[dom] * units / avg_s / 1e12
-            roof = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_FP32_VALU_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(ach / PEAK_FP32_VALU_TFLOPS, 4), "traffic": None,
-                    "kernel": dom, "avg_us": round(dom_avg_us, 2),
-                    "flop_per_atom_bead": round(flops[dom], 1), "units_per_launch": units}
-        else:
-            ach = byts.get(dom, 0.0) * units / avg_s / 1e9
-            roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": dom,
-                    "avg_us": round(dom_avg_us, 2)}
+    byts = bytes_per_atom(hp, nR, nA, s.P, cR, cA)
+    roof = roofline(dom, dom_avg_us, hp, nR, nA, units, byts)
+    if roof:
         tr_path = os.path.join(ROOT, "profiles", "traffic.json")
         if os.path.exists(tr_path):
             tr = json.load(open(tr_path))
@@ -479,34 +627,40 @@ def main():
     # every timed kernel against the VALU roofline (where its flops are counted)
     # and the HBM roofline (its algorithmic bytes), and the whole step's
     # algorithmic bytes against the step time
+    ref = flops_per_atom_reference(hp, nR, nA)
     per_kernel = {}
     for k, v in kernels.items():
         sec = v["avg_us"] * 1e-6
         row = {"avg_us": round(v["avg_us"], 2)}
-        if k in flops:
-            t = flops[k] * units / sec / 1e12
+        if k in ref:
+            t = ref[k] * units / sec / 1e12
             row.update({"TFLOP/s": round(t, 3), "valu_frac": round(t / PEAK_FP32_VALU_TFLOPS, 4)})
         if k in byts:
             gb = byts[k] * units / sec / 1e9
             row.update({"GB/s": round(gb, 1), "hbm_frac": round(gb / PEAK_HBM_GBS, 4)})
         per_kernel[k] = row
     step_bytes = sum(byts.values()) * units
-    step_gbs = step_bytes / (gpu_ms / args.steps * 1e-3) / 1e9
+    step_gbs = step_bytes / (ms * 1e-3) / 1e9
     step_hbm = {"algorithmic_bytes": int(step_bytes), "GB/s": round(step_gbs, 1),
                 "hbm_frac": round(step_gbs / PEAK_HBM_GBS, 4)}
+    del eng
 
+    full = None if args.no_full_run else full_run_leg(torch, lib, w, model_path, s, NepPimd)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, model_path, s, args.cpu_beads)
+    legs = {}
+    if not args.no_legs:
+        for name, st in (("fcc108", 100), ("water16", 50), ("porous13824", 20)):
+            legs[name] = workload_leg(args, torch, lib, configs, I, NepPimd, name, st, graph=True)
     npt = None
     if not args.no_npt:
-        npt = npt_leg(args, torch, lib, w, model_path, s, NepPimd, gpu_ms / args.steps)
+        npt = npt_leg(args, torch, lib, w, model_path, s, NepPimd, ms)
     tri = None
     if not args.no_triclinic:
-        tri = triclinic_leg(args, torch, lib, w, model_path, s, NepPimd, gpu_ms / args.steps)
+        tri = triclinic_leg(args, torch, lib, w, model_path, s, NepPimd, ms)
     stu = None
     if not args.no_student:
-        del eng
         stu = student_leg(args, torch, lib, configs, I)
 
     out = {
@@ -516,7 +670,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(gpu_ms / args.steps, 4),
+        "ms_per_step": round(ms, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -525,18 +679,21 @@ def main():
         "config": {"workload": f"{w.name}_p{s.P}", "atoms": s.N, "beads": s.P, "species": hp["n_species"],
                    "cutoffs_A": [hp["rc_radial"], hp["rc_angular"]],
                    "n_max": [hp["n_max_radial"], hp["n_max_angular"]], "l_max": hp["l_max"],
-                   "hidden": hp["hidden"], "mode": w.mode, "dt_fs": w.dt, "T_K": w.T,
+                   "hidden": hp["hidden"], "mode": w.mode, "dt_fs": w.dt, "T_K": w.T, "seed": w.seed,
+                   "e_scale": round(w.e_scale, 6),
                    "mean_neighbours": [round(nR, 2), round(nA, 2)], "max_block_neighbours": [mr, ma],
                    "arithmetic": "positions, integrator, force/energy/virial sums FP64; descriptors, network, "
                                  "pair terms FP32",
                    "wall_s": round(wall, 4), "launch": "hipGraph replay" if args.graph else "eager",
-                   "eager_ms_per_step": round(eager_ms, 4), "candidate_rebuilds_timed": rebuilds,
-                   "capacity_regrowths": regrowths},
+                   ("eager_ms_per_step" if args.graph else "graph_ms_per_step"): round(other, 4),
+                   "candidate_rebuilds_timed": rebuilds, "capacity_regrowths": regrowths},
         "roofline": roof,
         "kernels_roofline": per_kernel,
         "step_hbm": step_hbm,
         "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
+        "full_run": full,
         "cpu_baseline": cpu,
+        "legs": legs,
         "npt": npt,
         "triclinic": tri,
         "student_vs_teacher": stu,

@@ -76,7 +76,9 @@ enum nep_status {
 enum nep_flag_bits {
     NEP_FLAG_NEIGHBOR_OVERFLOW = 1u,  /* some list held more neighbours than its capacity */
     NEP_FLAG_NONFINITE = 2u,          /* a force or a position was NaN or Inf */
-    NEP_FLAG_BAD_TYPE = 4u            /* a species index was outside 0..n_species-1 */
+    NEP_FLAG_BAD_TYPE = 4u,           /* a species index was outside 0..n_species-1 */
+    NEP_FLAG_CELL_TOO_SMALL = 8u      /* a general (triclinic) cell's smallest face distance is not above
+                                         the candidate radius rc + 2 D + skin: the lists may miss pairs */
 };
 
 /* Thread-local message describing the last error of the calling thread. */
@@ -188,7 +190,13 @@ int32_t neighbor_build_batched(const nep_model *model, nep_nlist *nl, const doub
  * positions: w/2 - rc must exceed 2 w/1023, w the face distance),
  * NEP_ERR_HIP, NEP_ERR_NOMEM.  A candidate row longer than its capacity
  * sets NEP_FLAG_NEIGHBOR_OVERFLOW (the row is then truncated and the
- * results of nep_compute are not valid). */
+ * results of nep_compute are not valid).  In a general cell the centroid
+ * search takes nearest-image distances from the fractional reduction and,
+ * for vectors at least half the smallest face distance w_min long, from the
+ * 26 neighbouring images as well, which is exact below w_min; when the
+ * candidate radius rc + 2 D + skin (rc the larger cutoff) is not below w_min
+ * the call sets NEP_FLAG_CELL_TOO_SMALL and the lists are not valid (a
+ * larger cell, less spread beads or a smaller skin avoid it). */
 int32_t neighbor_build(const nep_model *model, nep_nlist *nl, const double *pos, const double box[9],
                        const int32_t *types, int32_t P, int32_t N, hipStream_t stream);
 
@@ -223,8 +231,13 @@ int32_t nep_nlist_invalidate(nep_nlist *nl);
  *       are inside rc_radial for at least one bead of the last build;
  *   union_radial_end [N][4] int32: end of species block t in that list;
  *   union_angular, union_angular_end: the same for the angular cutoff,
- *       holding slots k of the angular row instead of atom indices.
- * Entries past a row's length are not written. */
+ *       holding slots k of the angular row instead of atom indices;
+ *   union_radial_mask [N][cap_radial] uint64: for entry e of atom i's radial
+ *       union list, bit b set iff the pair is inside rc_radial in bead b
+ *       (the exact per-bead decision the force kernels apply);
+ *   union_angular_mask: the same for the angular union list.
+ * The per-bead set of bead b and atom i is therefore {union entry e : bit b
+ * of mask e}.  Entries past a row's length are not written. */
 typedef struct nep_nlist_layout {
     int32_t P, N, n_species, cap_radial, cap_angular;
     const int32_t *cand_radial;
@@ -236,6 +249,8 @@ typedef struct nep_nlist_layout {
     const int32_t *union_radial_end;
     const int32_t *union_angular;
     const int32_t *union_angular_end;
+    const uint64_t *union_radial_mask;
+    const uint64_t *union_angular_mask;
 } nep_nlist_layout;
 int32_t nep_nlist_view(const nep_nlist *nl, nep_nlist_layout *out);
 

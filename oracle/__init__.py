@@ -53,9 +53,13 @@ def lib():
         L.or_model_dims.argtypes = [vp, ip, dp]
         L.or_neighbors.argtypes = [dp, C.c_int, dp, C.c_double, C.c_int, ip, ip]
         L.or_neighbors.restype = C.c_int
+        L.or_neighbors_of.argtypes = [dp, C.c_int, dp, C.c_double, C.c_int, ip, C.c_int, ip, ip]
+        L.or_neighbors_of.restype = C.c_int
         L.or_nep_config.argtypes = [vp, dp, ip, C.c_int, dp, C.c_int, dp, dp, dp, dp, dp, dp]
         L.or_nep_beads.argtypes = [vp, dp, ip, C.c_int, C.c_int, dp, C.c_int, dp, dp, dp, dp, dp]
         L.or_num_threads.restype = C.c_int
+        L.or_set_num_threads.argtypes = [C.c_int]
+        L.or_set_num_threads.restype = None
         u32p = C.POINTER(C.c_uint32)
         u64p = C.POINTER(C.c_uint64)
         L.or_philox4x32.argtypes = [u32p, u32p, u32p]
@@ -113,6 +117,11 @@ def _i32(a):
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads used by the oracle's parallel loops from now on."""
+    lib().or_set_num_threads(int(n))
 
 
 # ---------------------------------------------------------------- NEP ---
@@ -199,6 +208,22 @@ def neighbors(pos, box, rc: float, cap: int = 512):
     cnt = np.zeros(N, np.int32)
     idx = np.full((N, cap), -1, np.int32)
     mx = lib().or_neighbors(_d(pos), N, _d(box), float(rc), cap, _i(cnt), _i(idx))
+    if mx > cap:
+        raise RuntimeError(f"oracle: neighbour capacity {cap} < {mx}")
+    return cnt, idx
+
+
+def neighbors_of(pos, box, rc: float, atoms, cap: int = 512):
+    """Brute-force minimum-image neighbours of the selected atoms only.
+
+    Returns (cnt [M], idx [M,cap] with ascending indices, -1 padded) for
+    atoms [M] (indices into pos [N,3])."""
+    pos = _f64(pos); box = _cell9(box)
+    at = _i32(atoms)
+    M = len(at)
+    cnt = np.zeros(M, np.int32)
+    idx = np.full((M, cap), -1, np.int32)
+    mx = lib().or_neighbors_of(_d(pos), len(pos), _d(box), float(rc), M, _i(at), cap, _i(cnt), _i(idx))
     if mx > cap:
         raise RuntimeError(f"oracle: neighbour capacity {cap} < {mx}")
     return cnt, idx

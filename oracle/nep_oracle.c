@@ -275,6 +275,32 @@ int or_neighbors(const double *pos, int N, const double *box, double rc, int cap
     return mx;
 }
 
+/* The same brute-force search for M selected atoms only (sampled checks of
+ * large systems): row r holds the neighbours of atom atoms[r], ascending. */
+int or_neighbors_of(const double *pos, int N, const double *box, double rc, int M, const int *atoms, int cap,
+                    int *cnt, int *idx)
+{
+    double rc2 = rc * rc;
+    int mx = 0;
+#pragma omp parallel for schedule(static) reduction(max : mx)
+    for (int r = 0; r < M; ++r) {
+        const int i = atoms[r];
+        int c = 0;
+        for (int j = 0; j < N; ++j) {
+            if (j == i) continue;
+            double d[3], r2;
+            mic(pos + 3 * i, pos + 3 * j, box, d, &r2);
+            if (r2 < rc2) {
+                if (c < cap) idx[(size_t)r * cap + c] = j;
+                ++c;
+            }
+        }
+        cnt[r] = c;
+        if (c > mx) mx = c;
+    }
+    return mx;
+}
+
 /* ------------------------------------------------------------------ */
 /* basis functions                                                     */
 /* ------------------------------------------------------------------ */
@@ -562,6 +588,9 @@ int or_nep_beads(const or_model *m, const double *pos, const int *types, int P, 
     }
     return 0;
 }
+
+/* Threads of the oracle's parallel loops (timing on one core). */
+void or_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
 
 int or_num_threads(void)
 {

@@ -565,6 +565,7 @@ extern "C" int32_t nep_nlist_view(const nep_nlist *nl, nep_nlist_layout *out)
     out->cand_angular = nl->candA; out->cand_angular_off = nl->offA; out->cand_angular_rev = nl->revA;
     out->union_radial = nl->uniR; out->union_radial_end = nl->uendR;
     out->union_angular = nl->uniA; out->union_angular_end = nl->uendA;
+    out->union_radial_mask = nl->umR; out->union_angular_mask = nl->umA;
     return NEP_OK;
 }
 

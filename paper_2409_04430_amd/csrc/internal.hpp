@@ -316,9 +316,16 @@ __device__ __forceinline__ double mic_r2_exact_tri(const double *ri, const doubl
     return (e2[0] + e2[1]) + e2[2];
 }
 
-// Minimum-image vector in place (FP64; cell-list and centroid distances).
+// Nearest-image vector in place (FP64; cell-list and centroid distances).
 // tri: the cell is a general one (g.tri; a compile-time false removes the
-// general branch from orthorhombic-only kernels).
+// general branch from orthorhombic-only kernels).  In a general cell the
+// fractional reduction f - rint(f) gives a vector e; every other image is
+// e + v with v a non-zero lattice vector, |v| >= w_min (the smallest face
+// distance), so e is the nearest image when |e| < w_min / 2.  Otherwise the
+// 26 neighbouring images are compared as well, which finds the nearest one
+// whenever it is shorter than w_min (its fractional coordinates then differ
+// from those of e by at most 1 per axis).  Callers need distances below
+// w_min only (candidate radii; the list build flags larger ones).
 __device__ __forceinline__ void mic_vec(double d[3], const SysGeom &g, bool tri)
 {
     if (!tri) {
@@ -334,6 +341,23 @@ __device__ __forceinline__ void mic_vec(double d[3], const SysGeom &g, bool tri)
     }
 #pragma unroll
     for (int a = 0; a < 3; ++a) d[a] = f[0] * g.H[a] + f[1] * g.H[3 + a] + f[2] * g.H[6 + a];
+    const double wmin = fmin(g.w[0], fmin(g.w[1], g.w[2]));
+    double best = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (!(best >= 0.25 * wmin * wmin)) return;   // nearest already (or non-finite)
+    double e0 = d[0], e1 = d[1], e2 = d[2];
+    for (int n0 = -1; n0 <= 1; ++n0)
+        for (int n1 = -1; n1 <= 1; ++n1)
+            for (int n2 = -1; n2 <= 1; ++n2) {
+                const double x = d[0] + n0 * g.H[0] + n1 * g.H[3] + n2 * g.H[6];
+                const double y = d[1] + n0 * g.H[1] + n1 * g.H[4] + n2 * g.H[7];
+                const double z = d[2] + n0 * g.H[2] + n1 * g.H[5] + n2 * g.H[8];
+                const double r2 = x * x + y * y + z * z;
+                if (r2 < best) {
+                    best = r2;
+                    e0 = x; e1 = y; e2 = z;
+                }
+            }
+    d[0] = e0; d[1] = e1; d[2] = e2;
 }
 
 // Fractional coordinate d of a point (cell lists).

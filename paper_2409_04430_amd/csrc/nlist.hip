@@ -224,6 +224,9 @@ __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double
     const double rc = rcR > rcA ? rcR : rcA;
     const double R = rc + 2.0 * (double)spread + skin + 1e-9 * (1.0 + rc);
     const double RA = rcA + 2.0 * (double)spread + skin + 1e-9 * (1.0 + rcA);
+    const double R_rows = rebuild ? R : sqrt(dg->R2);   // radius of the rows this call uses
+    // every thread has read the records (lambda_min, the last build) before any is rewritten
+    __syncthreads();
     if (rebuild) {
         for (int s = threadIdx.x; s < nsys; s += blockDim.x) {
             int ncell = 1;
@@ -241,6 +244,14 @@ __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double
     __syncthreads();   // every thread has read the record of the last rebuild
     if (threadIdx.x == 0) {
         dg->rebuild = rebuild;
+        // general cells: centroid distances are nearest-image distances only
+        // below the smallest face distance (mic_vec), and every candidate
+        // pair must lie there (rows of radius R_rows)
+        for (int s = 0; s < nsys; ++s) {
+            if (!geom[s].tri) continue;
+            const double wmin = fmin(geom[s].w[0], fmin(geom[s].w[1], geom[s].w[2]));
+            if (!(R_rows < wmin)) atomicOr(&status[0], (uint32_t)NEP_FLAG_CELL_TOO_SMALL);
+        }
         atomicMax(&status[4], __float_as_uint(spread));
         // the next call's maxima start from zero
         dg->spread_bits = 0u;
@@ -575,7 +586,8 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
 // centroids: with d the minimum-image centroid distance and s = s_i + s_j
 // the two atoms' largest bead distances from their centroids, every bead
 // pair lies within [d - s, d + s] (the minimum image is the shortest image),
-// so d + s < rc - eps keeps all beads and d - s > rc + eps none.  Only the
+// so d + s < rc - eps keeps all beads and d - s > rc + eps none (d is the
+// nearest-image distance, also in general cells: mic_vec).  Only the
 // remaining shell candidates are tested bead by bead (the exact test of the
 // per-bead lists), their G lanes per candidate holding the beads; each mask
 // is written back to its candidate's lane, and the kept candidates are

@@ -5,7 +5,10 @@ the neighbour lists and of the force workspace are polled every
 `check_every` steps.  Each successful poll keeps a device snapshot of the
 state; a candidate-row overflow found by a poll grows the rows, rolls back
 to the snapshot and replays the steps (the noise is counter-based, so the
-replay is the trajectory that larger rows would have given).  The step is the paper's workflow (Sec. II.A): thermostat,
+replay is the trajectory that larger rows would have given).  Regrowth is
+bounded: at most `max_regrow` rounds and `regrow_budget_s` seconds per poll,
+after which the poll raises with the capacities and the step reached.  The
+step is the paper's workflow (Sec. II.A): thermostat,
 half kick, free ring-polymer step, forces, half kick, thermostat; the two
 integrator halves around consecutive force evaluations run as one fused
 launch.  Optional: the ring-polymer observables (centroid virial kinetic
@@ -19,7 +22,8 @@ of every k-th force call.
 from __future__ import annotations
 
 import math
-from typing import Optional
+import time
+from typing import Callable, List, Optional
 
 import numpy as np
 
@@ -60,7 +64,8 @@ class NepPimd:
     def __init__(self, model_path: str, system, *, dt: float, T: float, tau: float = 100.0,
                  mode: str = "trpmd", seed: int = 0, caps: Optional[tuple] = None, check_every: int = 50,
                  want_atom: bool = False, skin: float = 0.5, autotune: bool = False, obs_every: int = 0,
-                 barostat: Optional[dict] = None, rdf: Optional[dict] = None, dump_every: int = 0):
+                 barostat: Optional[dict] = None, rdf: Optional[dict] = None, dump_every: int = 0,
+                 max_regrow: int = 8, regrow_budget_s: float = 300.0):
         import torch
         self.torch = torch
         dev = torch.device("cuda")
@@ -125,6 +130,17 @@ class NepPimd:
         if self.dump_every and self.batched:
             raise ValueError("velocity dumps need a single system")
         self.rollbacks = 0
+        self.rebuilds_total = 0      # candidate-row rebuilds counted by the successful polls
+        self.max_regrow = int(max_regrow)
+        self.regrow_budget_s = float(regrow_budget_s)
+        # Owners of extra per-step state (a student driver, snapshot recording):
+        # on_forces(n) runs after the forces of step n (eager steps, replays
+        # included); snapshot_hooks are (save() -> token, restore(token)) pairs
+        # taken with every device snapshot and restored on a rollback;
+        # replay_step, if set, replays one step instead of self.step.
+        self.on_forces: Optional[Callable[[int], None]] = None
+        self.snapshot_hooks: List[tuple] = []
+        self.replay_step: Optional[Callable[[], None]] = None
         self._snap = None
         self._finished = False   # the last call was finish() (closing half without the next opening half)
         self._fit_capacity()
@@ -160,20 +176,33 @@ class NepPimd:
     def check(self):
         """Poll the sticky flags (synchronises).  A candidate-row overflow since
         the last poll grows the rows, rolls back to the last poll's snapshot and
-        replays the steps; non-finite values or bad species raise."""
-        for _ in range(8):
+        replays the steps, at most `max_regrow` times and for at most
+        `regrow_budget_s` seconds; non-finite values, bad species or a general
+        cell too small for the bead spread raise."""
+        t0 = time.perf_counter()
+        rounds = 0
+        while True:
             st = self.nl.status(clear=True)
             flags, mr, ma = st["flags"], st["max_union_radial"], st["max_union_angular"]
             wf = self.ws.poll(clear=True)
             if not (flags & lib.FLAG_NEIGHBOR_OVERFLOW):
+                self.rebuilds_total += int(st["rebuilds"])
                 break
+            spent = time.perf_counter() - t0
+            if rounds >= self.max_regrow or spent > self.regrow_budget_s:
+                raise lib.NepError(5, f"candidate rows still overflow at step {self.step_no} after {rounds} "
+                                      f"regrowths in {spent:.1f} s: capacities {self.caps}, longest rows "
+                                      f"({st['max_cand_radial']}, {st['max_cand_angular']}), snapshot at step "
+                                      f"{self._snap['step_no']}")
             self._grow_and_replay(st)
-        else:
-            raise lib.NepError(5, f"candidate overflow persists: capacities {self.caps}")
+            rounds += 1
         if (flags | wf) & lib.FLAG_NONFINITE:
             raise lib.NepError(6, "non-finite force or position")
         if (flags | wf) & lib.FLAG_BAD_TYPE:
             raise lib.NepError(1, "species index outside the model's range")
+        if flags & lib.FLAG_CELL_TOO_SMALL:
+            raise lib.NepError(4, "general cell: the smallest face distance is below the candidate radius "
+                                  "rc + 2 D + skin")
         self._snapshot()
         return mr, ma
 
@@ -183,7 +212,8 @@ class NepPimd:
         self._snap = dict(step_no=self.step_no, started=self.started, pos=self.pos.clone(), vel=self.vel.clone(),
                           box=np.array(self.box, dtype=np.float64, copy=True), obs_n=len(self.obs_log),
                           dump_n=len(self.dump_log), rdf_frames=self.rdf_frames,
-                          rdf=None if self.rdf_hist is None else self.rdf_hist.clone())
+                          rdf=None if self.rdf_hist is None else self.rdf_hist.clone(),
+                          extra=[save() for save, _ in self.snapshot_hooks])
 
     def _grow_and_replay(self, st):
         # rows found after an overflow may come from a state that truncated forces
@@ -206,15 +236,18 @@ class NepPimd:
         self.rdf_frames = s["rdf_frames"]
         if self.rdf_hist is not None:
             self.rdf_hist.copy_(s["rdf"])
+        for (_, restore), tok in zip(self.snapshot_hooks, s["extra"]):
+            restore(tok)
         self.rollbacks += 1
         # replay the same calls: steps, then finish() or a fresh capture (whose
         # own eager step is the last one) where the original sequence had them
         finished = self._finished
         last = target - 1 if (finished or had_graph) else target
         every, self.check_every = self.check_every, 0   # the caller's poll verifies the replay
+        one = self.replay_step or self.step
         try:
             while self.step_no < last:
-                self.step()
+                one()
             if finished:
                 self.finish()
             elif had_graph:
@@ -270,6 +303,8 @@ class NepPimd:
                 self.start()
             self.forces()
             n = self.step_no
+            if self.on_forces is not None:
+                self.on_forces(n)
             self._after_forces(n)
             if self._split():
                 self.pimd.step(self.pos, self.vel, self.F, n, lib.POST)

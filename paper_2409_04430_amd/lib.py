@@ -24,7 +24,7 @@ _lib = C.CDLL(LIB_PATH)
 NEP_OK = 0
 ERRORS = {1: "INVALID_ARG", 2: "PARAMS_FILE", 3: "UNSUPPORTED", 4: "BOX_TOO_SMALL", 5: "NEIGHBOR_OVERFLOW",
           6: "NONFINITE", 7: "HIP", 8: "NOMEM"}
-FLAG_NEIGHBOR_OVERFLOW, FLAG_NONFINITE, FLAG_BAD_TYPE = 1, 2, 4
+FLAG_NEIGHBOR_OVERFLOW, FLAG_NONFINITE, FLAG_BAD_TYPE, FLAG_CELL_TOO_SMALL = 1, 2, 4, 8
 MODE = {"pimd": 0, "pile": 0, "trpmd": 1, "rpmd": 2}
 PRE, POST, FUSED = 0, 1, 2
 
@@ -47,7 +47,8 @@ class NlistLayout(C.Structure):
                 ("cap_angular", C.c_int32), ("cand_radial", C.c_void_p), ("cand_radial_off", C.c_void_p),
                 ("cand_angular", C.c_void_p), ("cand_angular_off", C.c_void_p), ("cand_angular_rev", C.c_void_p),
                 ("union_radial", C.c_void_p), ("union_radial_end", C.c_void_p), ("union_angular", C.c_void_p),
-                ("union_angular_end", C.c_void_p)]
+                ("union_angular_end", C.c_void_p), ("union_radial_mask", C.c_void_p),
+                ("union_angular_mask", C.c_void_p)]
 
 
 class NlistStatus(C.Structure):
@@ -339,15 +340,16 @@ class NeighborList:
         lay = self.view()
         N = lay.N
         out = {"n_species": lay.n_species}
-        for kind, cap, cand, off, uni, uend in (
+        for kind, cap, cand, off, uni, uend, um in (
                 ("radial", lay.cap_radial, lay.cand_radial, lay.cand_radial_off, lay.union_radial,
-                 lay.union_radial_end),
+                 lay.union_radial_end, lay.union_radial_mask),
                 ("angular", lay.cap_angular, lay.cand_angular, lay.cand_angular_off, lay.union_angular,
-                 lay.union_angular_end)):
+                 lay.union_angular_end, lay.union_angular_mask)):
             out["cand_" + kind] = device_to_host(cand, (N, cap), np.int32)
             out["cand_off_" + kind] = device_to_host(off, (N, 5), np.int32)
             out["union_" + kind] = device_to_host(uni, (N, cap), np.int32)
             out["union_end_" + kind] = device_to_host(uend, (N, 4), np.int32)
+            out["union_mask_" + kind] = device_to_host(um, (N, cap), np.uint64)
         out["cand_rev_angular"] = device_to_host(lay.cand_angular_rev, (N, lay.cap_angular), np.int32)
         if pos is not None:
             cr = cap_radial or lay.cap_radial
@@ -386,6 +388,8 @@ def fitted_neighbor_list(model: "Model", pos, box, types, cap_radial: int = 96, 
         st = nl.status(clear=True)
         if st["flags"] & FLAG_BAD_TYPE:
             raise NepError(1, "species index outside the model's range")
+        if st["flags"] & FLAG_CELL_TOO_SMALL:
+            raise NepError(4, "general cell: the smallest face distance is below the candidate radius")
         need = [int(np.ceil(v * slack)) + 8 for v in (st["max_cand_radial"], st["max_cand_angular"])]
         if not (st["flags"] & FLAG_NEIGHBOR_OVERFLOW) and all(2 * n >= c for n, c in zip(need, caps)):
             return nl

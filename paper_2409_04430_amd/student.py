@@ -68,12 +68,17 @@ class SnapshotStore:
 
 def teacher_snapshots(teacher_path: str, make_system, temperatures: Sequence[float], *, steps: int, every: int,
                       warmup: int, dt: float, mode: str = "trpmd", tau: float = 100.0, seed: int = 0,
-                      store: Optional[SnapshotStore] = None, skin: float = 0.5) -> SnapshotStore:
+                      store: Optional[SnapshotStore] = None, skin: float = 0.5, check_every: int = 50,
+                      prepare=None) -> SnapshotStore:
     """Teacher NEP-PIMD at each temperature; keep every `every`-th step after `warmup`.
 
     make_system(T) returns the starting `inputs.System` (P beads) at T.  A
     kept snapshot is the positions at which the step evaluated its forces,
-    with the teacher's E [P], F [P,N,3] and W [P,9] there."""
+    with the teacher's E [P], F [P,N,3] and W [P,9] there.  Snapshots of a
+    poll window are staged and enter the store only once the engine's poll
+    at the end of the window has verified the lists; a window replayed after
+    a row overflow records its snapshots again from the replay.  prepare(eng),
+    if given, is applied to each engine before its first step."""
     per_T = (steps + every - 1) // every
     for k, T in enumerate(temperatures):
         system = make_system(T)
@@ -81,15 +86,38 @@ def teacher_snapshots(teacher_path: str, make_system, temperatures: Sequence[flo
             store = SnapshotStore(per_T * len(temperatures), system.P, system.N)
         eng = NepPimd(teacher_path, system, dt=dt, T=T, tau=tau, mode=mode, seed=seed + 7919 * k,
                       check_every=0, skin=skin)
+        pending: list = []
+        committed = [0]
+
+        def record(n, eng=eng, pending=pending):
+            if n >= warmup and (n - warmup) % every == 0:
+                pending.append((eng.pos.clone(), eng.E.clone(), eng.F.clone(), eng.W.clone()))
+
+        def save(pending=pending, committed=committed):
+            return committed[0] + len(pending)
+
+        def restore(tok, pending=pending, committed=committed):
+            del pending[tok - committed[0]:]
+
+        def commit(T=T, pending=pending, committed=committed):
+            for x, E, F, W in pending:
+                store.add(x, E, F, W, T)
+            committed[0] += len(pending)
+            pending.clear()
+
+        eng.on_forces = record
+        eng.snapshot_hooks.append((save, restore))
+        if prepare is not None:
+            prepare(eng)
+        eng._snapshot()
         eng.start()
         for s in range(warmup + steps):
-            x = eng.pos.clone() if s >= warmup and (s - warmup) % every == 0 else None
             eng.step()
-            if x is not None:
-                store.add(x, eng.E, eng.F, eng.W, T)
-            if (s + 1) % 50 == 0:
+            if (s + 1) % check_every == 0:
                 eng.check()
+                commit()
         eng.check()
+        commit()
     return store
 
 
@@ -231,6 +259,18 @@ class StudentPimd:
         self.on_student = True
         self.fallback_step: Optional[int] = None
         self.history: List[tuple] = []
+        # a replay after a row overflow goes through the judged step, and the
+        # judge's state rolls back with the engine's snapshot
+        e.replay_step = self._advance
+        e.snapshot_hooks.append((self._save, self._restore))
+        e._snapshot()
+
+    def _save(self):
+        return (self.on_student, self.fallback_step, len(self.history))
+
+    def _restore(self, tok):
+        self.on_student, self.fallback_step, n = tok
+        del self.history[n:]
 
     @property
     def step_no(self):
@@ -271,14 +311,18 @@ class StudentPimd:
         if self.tws.poll(clear=True):
             raise lib.NepError(6, "teacher evaluation raised device flags")
 
-    def step(self):
+    def _advance(self):
+        """One judged step without a poll (also the engine's replay step)."""
         e = self.eng
         if not e.started:
             self.start()
         self.forces()
         e.pimd.step(e.pos, e.vel, e.F, e.step_no, lib.FUSED)
         e.step_no += 1
-        if self.check_every and e.step_no % self.check_every == 0:
+
+    def step(self):
+        self._advance()
+        if self.check_every and self.eng.step_no % self.check_every == 0:
             self.check()
 
     def run(self, n: int):

@@ -18,6 +18,7 @@ pytestmark = pytest.mark.gpu
 E_TOL = 1e-6      # eV/atom
 F_TOL = 1e-5      # relative to the largest force of the bead
 W_TOL = 1e-5      # relative to the largest virial component of the bead
+WATOM_TOL = 1e-5  # per-atom virial, relative to the largest entry of the bead
 
 
 def say(*a):
@@ -81,17 +82,29 @@ def gpu_nep(torch, L, path, pos, types, box, capR, capA, atom=True):
     return out
 
 
-def check_lists(orc, lists, pos, box, rc_r, rc_a, beads=None, atoms=None, types=None):
+def check_lists(orc, lists, pos, box, rc_r, rc_a, beads=None, atoms=None, types=None, sample=None):
     """Per-bead neighbour lists equal the oracle's sets, in (species, index)
-    order; candidate rows, reverse slots and union lists are consistent."""
+    order; candidate rows, reverse slots and union lists are consistent, and
+    the union lists' bead masks (the decision the force kernels apply) give
+    the same per-bead sets.
+
+    sample: {bead: atoms} checks those (bead, atom) pairs only, against the
+    oracle's brute-force search over all atoms of that bead."""
     P, N = pos.shape[:2]
-    all_beads = beads is None
-    beads = range(P) if beads is None else beads
-    sel = range(N) if atoms is None else atoms
+    if sample is None:
+        beads = range(P) if beads is None else beads
+        sel = np.arange(N) if atoms is None else np.asarray(atoms)
+        sample = {b: sel for b in beads}
+    first = np.asarray(next(iter(sample.values())))
+    all_beads = sorted(sample) == list(range(P)) and all(np.array_equal(np.asarray(v), first)
+                                                          for v in sample.values())
     S = lists["n_species"]
+    checked = 0
     for kind, rc in (("radial", rc_r), ("angular", rc_a)):
         cand, coff = lists["cand_" + kind], lists["cand_off_" + kind][:, :S + 1]
-        for i in sel:
+        uni, uend, um = lists["union_" + kind], lists["union_end_" + kind], lists["union_mask_" + kind]
+        row_atoms = np.unique(np.concatenate([np.asarray(v) for v in sample.values()]))
+        for i in row_atoms:
             n = coff[i, S]
             row = cand[i, :n]
             assert coff[i, 0] == 0 and np.all(np.diff(coff[i]) >= 0), (kind, i)
@@ -107,23 +120,39 @@ def check_lists(orc, lists, pos, box, rc_r, rc_a, beads=None, atoms=None, types=
                                               err_msg=f"reverse slots {i}")
         nbr, cnt = lists["nbr_" + kind], lists["cnt_" + kind]
         sets = {}
-        for b in beads:
-            oc, oi = orc.neighbors(pos[b], box, rc, cap=1024)
-            for i in sel:
+        for b, sel in sample.items():
+            sel = np.asarray(sel)
+            oc, oi = orc.neighbors_of(pos[b], box, rc, sel, cap=1024)
+            for r, i in enumerate(sel):
                 got = nbr[b, :cnt[b, i], i]
-                assert cnt[b, i] == oc[i], (kind, b, i)
+                assert cnt[b, i] == oc[r], (kind, b, i)
                 if types is not None:
                     tj = np.asarray(types)[got]
                     assert np.all(np.diff(tj) >= 0), (kind, b, i)
-                np.testing.assert_array_equal(np.sort(got), oi[i, :oc[i]], err_msg=f"{kind} bead {b} atom {i}")
+                ref = oi[r, :oc[r]]
+                np.testing.assert_array_equal(np.sort(got), ref, err_msg=f"{kind} bead {b} atom {i}")
+                # the force path's own per-bead set: union entries with bit b
+                m = uend[i, S - 1]
+                e = uni[i, :m]
+                j = e if kind == "radial" else cand[i, e] >> 2
+                bit = ((um[i, :m] >> np.uint64(b)) & np.uint64(1)).astype(bool)
+                np.testing.assert_array_equal(np.sort(j[bit]), ref, err_msg=f"{kind} mask bead {b} atom {i}")
                 sets.setdefault(i, set()).update(got.tolist())
+                checked += 1
         if all_beads:
             # union lists: every candidate inside for at least one bead, in row order
-            uni, uend = lists["union_" + kind], lists["union_end_" + kind]
-            for i in sel:
+            for i in sets:
                 m = uend[i, S - 1]
                 j = uni[i, :m] if kind == "radial" else cand[i, uni[i, :m]] >> 2
                 assert set(j.tolist()) == sets[i] and len(j) == len(sets[i]), (kind, i)
+    return checked // 2
+
+
+def sampled_pairs(P, N, n, seed):
+    """About n (bead, atom) pairs spread over every bead: {bead: atoms}."""
+    rng = np.random.default_rng(seed)
+    per = -(-n // P)
+    return {b: np.sort(rng.choice(N, per, replace=False)) for b in range(P)}
 
 
 def check_nep(ref, got, beads, N, atom=True):
@@ -139,9 +168,12 @@ def check_nep(ref, got, beads, N, atom=True):
         assert dW <= W_TOL * wmax
         if atom:
             # U_i is one FP32 value: the bar is FP32 precision relative to the largest |U_i|
-            assert np.abs(got["U"][b] - ref["U"][k]).max() <= F_TOL * np.abs(ref["U"][k]).max()
+            du = np.abs(got["U"][b] - ref["U"][k]).max() / np.abs(ref["U"][k]).max()
             wa = np.abs(ref["Wat"][k]).max()
-            assert np.abs(got["Wat"][b] - ref["Wat"][k]).max() <= 10 * W_TOL * wa
+            dwa = np.abs(got["Wat"][b] - ref["Wat"][k]).max() / wa
+            say(f"          dU/Umax={du:.2e} dWatom/Watom_max={dwa:.2e}")
+            assert du <= F_TOL
+            assert dwa <= WATOM_TOL
 
 
 def oracle_beads(orc, path, pos, types, box, beads):
@@ -192,17 +224,21 @@ def test_nep_parity_water_boxes(torch, L, orc, tmpdir_session):
                   pos.shape[1])
 
 
-def test_nep_parity_porous_one_bead(torch, L, orc, tmpdir_session):
-    say("[nep parity] porous framework, 13824 atoms, four species")
+def test_nep_porous_p64_sampled(torch, L, orc, tmpdir_session):
+    """Porous framework at its full size, 13,824 atoms x 64 beads in one
+    launch: 10,240 sampled (bead, atom) neighbour lists against brute force,
+    E/F/W of the first and last bead against the oracle."""
+    say("[nep parity] porous framework 13824 x 64 beads, sampled lists")
     w = configs.WORKLOADS["porous13824"]
     path = write_model(tmpdir_session, "porous", w.model())
-    pos, types, box = beads_of("porous13824", 1, extra_sigma=0.05, seed=3)
-    got = gpu_nep(torch, L, path, pos, types, box, 96, 48)
-    rng = np.random.default_rng(0)
-    check_lists(orc, got["lists"], pos, box, 6.0, 4.0, atoms=rng.choice(pos.shape[1], 500, replace=False),
-                types=types)
-    ref = oracle_beads(orc, path, pos, types, box, [0])
-    check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"], U=ref["U"], Wat=ref["Wat"]), got, [0], pos.shape[1])
+    pos, types, box = beads_of("porous13824", 64, extra_sigma=0.05, seed=3)
+    got = gpu_nep(torch, L, path, pos, types, box, 96, 48, atom=False)
+    n = check_lists(orc, got["lists"], pos, box, 6.0, 4.0, types=types,
+                    sample=sampled_pairs(64, pos.shape[1], 10240, 0))
+    say(f"  {n} (bead, atom) lists checked")
+    assert n >= 10000
+    ref = oracle_beads(orc, path, pos, types, box, [0, 63])
+    check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"]), got, [0, 63], pos.shape[1], atom=False)
 
 
 def test_nep_full_size_rocksalt_sampled_beads(torch, L, orc, tmpdir_session):
@@ -223,17 +259,98 @@ def test_nep_full_size_rocksalt_sampled_beads(torch, L, orc, tmpdir_session):
     assert np.abs(Wt - Wt.transpose(0, 2, 1)).max() <= 1e-4 * np.abs(Wt).max()
 
 
-def test_nep_fcc32000_teacher_one_bead(torch, L, orc, tmpdir_session):
-    say("[nep parity] teacher with four-body terms, 32000 atoms")
+def test_nep_fcc32000_teacher_p32(torch, L, orc, tmpdir_session):
+    """The teacher (four-body terms, 100 hidden units) at its full size,
+    32,000 atoms x 32 beads in one launch: 10,240 sampled (bead, atom)
+    neighbour lists against brute force, E/F/W of beads 0 and 31 against
+    the oracle."""
+    say("[nep parity] teacher with four-body terms, 32000 atoms x 32 beads")
     w = configs.WORKLOADS["fcc32000"]
     path = write_model(tmpdir_session, "teacher", w.model())
-    pos, types, box = beads_of("fcc32000", 1, extra_sigma=0.02, seed=5)
+    pos, types, box = beads_of("fcc32000", 32, extra_sigma=0.02, seed=5)
     got = gpu_nep(torch, L, path, pos, types, box, 96, 72, atom=False)
-    rng = np.random.default_rng(1)
-    check_lists(orc, got["lists"], pos, box, 6.0, 5.0, atoms=rng.choice(pos.shape[1], 300, replace=False),
-                types=types)
-    ref = oracle_beads(orc, path, pos, types, box, [0])
-    check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"]), got, [0], pos.shape[1], atom=False)
+    n = check_lists(orc, got["lists"], pos, box, 6.0, 5.0, types=types,
+                    sample=sampled_pairs(32, pos.shape[1], 10240, 1))
+    say(f"  {n} (bead, atom) lists checked")
+    assert n >= 10000
+    ref = oracle_beads(orc, path, pos, types, box, [0, 31])
+    check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"]), got, [0, 31], pos.shape[1], atom=False)
+
+
+def edge_configuration(rcR, rcA, P=8, L=40.0):
+    """Pairs placed exactly at a cutoff and one FP64 step to either side of
+    it, per bead, for both cutoffs: along each axis, along (3, 4, 0) and
+    across the periodic boundary; plus a small cluster for non-zero forces.
+    The partner coordinate of bead b is x + rc moved by 0, -1 or +1 ulp (or
+    by -+1e-7 A); coordinate differences are exact in FP64 (Sterbenz), so the
+    oracle sees r = rc exactly or one rounding step off."""
+    moves = [lambda x: x, lambda x: np.nextafter(x, -np.inf), lambda x: np.nextafter(x, np.inf), lambda x: x,
+             lambda x: x - 1e-7, lambda x: x + 1e-7, lambda x: np.nextafter(x, np.inf),
+             lambda x: np.nextafter(x, -np.inf)]
+    base = [np.array([x, y, z]) for x in (9.0, 29.0) for y in (9.0, 29.0) for z in (9.0, 29.0)]
+    pos = []
+    k = 0
+    for rc in (rcR, rcA):
+        for ax in range(3):
+            a = np.broadcast_to(base[k], (P, 3)).copy()
+            bb = a.copy()
+            for q in range(P):
+                bb[q, ax] = moves[q % len(moves)](base[k][ax] + rc)
+            pos += [a, bb]
+            k += 1
+        if rc == 5.0:
+            # r = 5 from the integer components (3, 4, 0), the x coordinate moved per bead
+            a = np.broadcast_to(base[k], (P, 3)).copy()
+            bj = base[k] + np.array([3.0, 4.0, 0.0])
+            bb = np.broadcast_to(bj, (P, 3)).copy()
+            for q in range(P):
+                bb[q, 0] = moves[q % 3](bj[0])
+            pos += [a, bb]
+            k += 1
+    # across the periodic boundary: x = 1.5 and x = 1.5 - rc + L
+    for rc, y in ((rcR, 19.0), (rcA, 3.0)):
+        a = np.broadcast_to(np.array([1.5, y, 20.0]), (P, 3)).copy()
+        bb = a.copy()
+        for q in range(P):
+            bb[q, 0] = moves[q % 3](1.5 - rc + L)
+        pos += [a, bb]
+    rng = np.random.default_rng(17)
+    c0 = np.array([20.0, 30.0, 12.0])
+    pts = [c0]
+    while len(pts) < 12:
+        p = c0 + rng.uniform(-3.0, 3.0, 3)
+        if min(np.linalg.norm(p - q) for q in pts) > 1.6:
+            pts.append(p)
+    for p in pts:
+        pos.append(np.broadcast_to(p, (P, 3)) + rng.normal(0, 0.02, (P, 3)))
+    pos = np.ascontiguousarray(np.stack(pos, axis=1))
+    return pos, np.zeros(pos.shape[1], np.int32), np.full(3, L)
+
+
+def test_nep_cutoff_edge(torch, L, orc, tmpdir_session):
+    """Pairs exactly at r_c and one FP64 step to either side, per bead, for
+    both cutoffs: the per-bead lists (materialised and the force path's bead
+    masks) equal the oracle's strict r^2 < r_c^2 sets, and E/F/W match."""
+    say("[nep parity] pairs at the cutoff edge")
+    w = configs.WORKLOADS["fcc108"]
+    path = write_model(tmpdir_session, "edge_rc", w.model())
+    rcR, rcA = w.hyper.rc_radial, w.hyper.rc_angular
+    pos, types, box = edge_configuration(rcR, rcA)
+    # the construction hits the edge: some pair is exactly at rc in FP64 for each cutoff
+    for rc in (rcR, rcA):
+        hit = 0
+        for b in range(pos.shape[0]):
+            d = pos[b][None, :, :] - pos[b][:, None, :]
+            d -= box * np.rint(d / box)
+            r2 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+            hit += int(np.sum(r2 == rc * rc))
+        assert hit > 0, rc
+    got = gpu_nep(torch, L, path, pos, types, box, 24, 24)
+    n = check_lists(orc, got["lists"], pos, box, rcR, rcA, types=types)
+    say(f"  {n} (bead, atom) lists checked")
+    ref = oracle_beads(orc, path, pos, types, box, range(pos.shape[0]))
+    check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"], U=ref["U"], Wat=ref["Wat"]), got, range(pos.shape[0]),
+              pos.shape[1])
 
 
 def test_nep_deterministic(torch, L, tmpdir_session):

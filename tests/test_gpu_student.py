@@ -231,3 +231,69 @@ def test_student_training_judge_and_gain(torch, L, tmpdir_session):
     mt, ms = ms_per_step(teacher), ms_per_step(student)
     say(f"[student] 2048 atoms x 32 beads: teacher {mt:.3f} ms/step, student {ms:.3f} ms/step, gain {mt / ms:.2f}x")
     assert ms < mt / 1.5
+
+
+# ------------------------------------------- replay after an overflow ---
+
+def _shrink_rows(L, eng, caps=(8, 4)):
+    """Replace the engine's candidate rows by rows far too short (a forced overflow)."""
+    eng.nl = L.NeighborList(eng.model, eng.P, eng.N, *caps)
+    eng.nl.set_skin(eng.skin)
+    eng.caps = caps
+
+
+def test_student_replay_after_fallback(torch, L, tmpdir_session):
+    """A row overflow found by the poll after a fallback replays the window
+    through the judged step: the replayed steps run on the teacher's forces,
+    the judge history is rolled back and re-recorded once, and the state
+    equals, bitwise, a run whose rows never overflowed."""
+    from paper_2409_04430_amd.student import StudentPimd
+    w = configs.WORKLOADS["fcc32000"]
+    tpath = write_model(tmpdir_session, "rp_teacher", w.model())
+    spath = write_model(tmpdir_session, "rp_student", w.model(student=True))
+    p0, t, b = I.fcc(4, 4.05)
+    sysT = I.make_system(p0, t, b, w.species_masses, 4, 500.0, 0.05, np.random.default_rng(21))
+    kw = dict(dt=w.dt, T=500.0, mode="trpmd", seed=5, judge_every=20, threshold=1e-9, check_every=30)
+    ref = StudentPimd(tpath, spath, sysT, **kw)
+    ref.run(30)
+    ref.check()
+    st = StudentPimd(tpath, spath, sysT, **kw)
+    _shrink_rows(L, st.eng)
+    st.eng._snapshot()
+    st.run(30)                 # the poll at step 30 finds the overflow, grows the rows and replays
+    st.check()
+    say(f"[student replay] rollbacks {st.eng.rollbacks}, caps {st.eng.caps}, history {st.history}")
+    assert st.eng.rollbacks >= 1
+    assert not st.on_student and st.fallback_step == 0
+    assert [h[0] for h in st.history] == [0] and st.history == ref.history
+    assert torch.equal(st.eng.pos, ref.eng.pos) and torch.equal(st.eng.vel, ref.eng.vel)
+    # the forces of the last replayed step are the teacher's
+    e = st.eng
+    Et, Ft, Wt = torch.zeros_like(e.E), torch.zeros_like(e.F), torch.zeros_like(e.W)
+    e.nl.build(e.pos, e.box, e.types)
+    st.tws.compute(e.nl, e.pos, e.box, e.types, Et, Ft, Wt)
+    st.forces(judge=False)
+    torch.cuda.synchronize()
+    assert torch.equal(e.F, Ft)
+
+
+def test_teacher_snapshots_replayed_window(torch, L, tmpdir_session):
+    """Snapshots of a window whose rows overflowed are dropped and recorded
+    again from the replay: the store equals, bitwise, that of a run whose
+    rows never overflowed."""
+    from paper_2409_04430_amd.student import teacher_snapshots
+    w = configs.WORKLOADS["fcc32000"]
+    tpath = write_model(tmpdir_session, "snap_teacher", w.model())
+
+    def make_system(T):
+        p0, t, b = I.fcc(4, 4.05)
+        return I.make_system(p0, t, b, w.species_masses, 4, T, 0.05, np.random.default_rng(int(T)))
+
+    kw = dict(steps=40, every=5, warmup=10, dt=w.dt, check_every=25)
+    ref = teacher_snapshots(tpath, make_system, [400.0], **kw)
+    got = teacher_snapshots(tpath, make_system, [400.0], prepare=lambda eng: _shrink_rows(L, eng), **kw)
+    say(f"[snapshots] {len(ref)} reference, {len(got)} after the replayed window")
+    assert len(got) == len(ref) == 8
+    for k in range(len(ref)):
+        assert torch.equal(got.pos[k], ref.pos[k]) and torch.equal(got.F[k], ref.F[k])
+        assert torch.equal(got.E[k], ref.E[k]) and torch.equal(got.W[k], ref.W[k])

@@ -278,3 +278,40 @@ def test_batch_mixing_cubic_and_sheared_cells(torch, L, orc, tmpdir_session):
                 c = lists["cnt_" + kind][b, gi]
                 assert c == oc[i]
                 np.testing.assert_array_equal(np.sort(lists["nbr_" + kind][b, :c, gi]) - off[1], oi[i, :oc[i]])
+
+
+def test_spread_beads_beyond_half_face_distance(torch, L, orc, tmpdir_session):
+    """Skewed cell whose half smallest face distance (6.06 A) lies just above
+    the 6 A cutoff, beads spread so that the candidate radius rc + 2 D
+    exceeds it: the centroid search must take nearest images beyond w_min/2,
+    and the per-bead lists still equal brute force.  Beads spread so far that
+    the radius exceeds w_min itself raise NEP_FLAG_CELL_TOO_SMALL."""
+    w = configs.WORKLOADS["rocksalt4096"]
+    path = write_model(tmpdir_session, "tri_spread", w.model())
+    m = L.Model(path)
+    p0, types, box = I.rocksalt(5, 4.2)
+    H = SHEAR @ np.diag(box)
+    wmin = np.linalg.det(H) / max(np.linalg.norm(np.cross(H[(a + 1) % 3], H[(a + 2) % 3])) for a in range(3))
+    rng = np.random.default_rng(41)
+    base = I.displace(p0, 0.05, rng)
+    P = 8
+    pos = base[None] + rng.normal(0.0, 0.35, (P,) + base.shape)
+    D = np.linalg.norm(pos - pos.mean(axis=0), axis=2).max()
+    say(f"[triclinic] w_min {wmin:.3f} A, bead spread D {D:.3f} A, rc + 2D = {6.0 + 2 * D:.3f} A")
+    assert 6.0 + 2 * D > 0.5 * wmin and 6.0 + 2 * D < wmin
+    dev = torch.device("cuda")
+    tpos = torch.tensor(pos, dtype=torch.float64, device=dev)
+    ttyp = torch.tensor(np.asarray(types, np.int32), device=dev)
+    nl = L.fitted_neighbor_list(m, tpos, H, ttyp, 400, 200)
+    nl.build(tpos, H, ttyp)
+    assert nl.status()["flags"] == 0
+    lists = nl.to_host(tpos, H, *nl.caps)
+    check_lists(orc, lists, pos, H, m.rc_radial, m.rc_angular, types=np.asarray(types, np.int32))
+    # beads spread beyond the smallest face distance: flagged, not silently wrong
+    far = base[None] + rng.normal(0.0, 1.6, (P,) + base.shape)
+    tfar = torch.tensor(far, dtype=torch.float64, device=dev)
+    big = L.NeighborList(m, P, len(base), 2048, 1024)
+    big.build(tfar, H, ttyp)
+    st = big.status()
+    say(f"  spread {np.linalg.norm(far - far.mean(axis=0), axis=2).max():.2f} A: flags {st['flags']:#x}")
+    assert st["flags"] & L.FLAG_CELL_TOO_SMALL

@@ -85,3 +85,20 @@ def test_workload_sizes():
     assert configs.WORKLOADS["fcc108"].hyper.dim == 25
     assert configs.WORKLOADS["rocksalt4096"].hyper.dim == 27
     assert configs.WORKLOADS["fcc32000"].hyper.dim == 9 + 36 + 9
+
+
+def test_energy_scale_gives_half_ev_per_angstrom(orc, tmp_path):
+    """Every workload's seeded model has an RMS force component of 0.5 eV/A
+    on its initial displaced structure (all boxes of a batch together),
+    computed by the oracle."""
+    for name, w in configs.WORKLOADS.items():
+        path = str(tmp_path / (name + ".nep"))
+        I.write_model(path, w.model())
+        M = orc.Model(path)
+        F2, n = 0.0, 0
+        for s in w.systems(P=1):
+            F = M.config(s.pos[0], s.types, s.box)["F"]
+            F2 += float((F * F).sum())
+            n += F.size
+        rms = math.sqrt(F2 / n)
+        assert abs(rms / 0.5 - 1.0) < 1e-3, (name, rms)

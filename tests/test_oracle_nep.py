@@ -81,6 +81,27 @@ def test_neighbors_match_periodic_kdtree(orc):
         got = idx[i, :cnt[i]]
         assert list(got) == sorted(ref[i])
     assert np.all(np.diff(idx[0, :cnt[0]]) > 0)
+    # the sampled search (selected atoms only) against the same tree
+    sel = rng.choice(len(pos), 40, replace=False)
+    c2, i2 = orc.neighbors_of(pos, box, rc, sel, cap=256)
+    for r, i in enumerate(sel):
+        assert list(i2[r, :c2[r]]) == sorted(ref[i])
+
+
+def test_neighbors_at_the_cutoff_edge(orc):
+    """Strict r^2 < rc^2 in FP64: a pair exactly at rc is out, one ulp closer
+    is in, one ulp farther is out (also through the periodic image)."""
+    box = np.array([20.0, 20.0, 20.0])
+    rc = 6.0
+    x0 = 3.0
+    for xj, inside in ((x0 + rc, False), (np.nextafter(x0 + rc, -np.inf), True),
+                       (np.nextafter(x0 + rc, np.inf), False), (x0 - rc + 20.0, False),
+                       (np.nextafter(x0 - rc + 20.0, np.inf), True)):
+        pos = np.array([[x0, 1.0, 1.0], [xj, 1.0, 1.0]])
+        d = (xj - x0) - 20.0 * np.rint((xj - x0) / 20.0)
+        assert (d * d < rc * rc) == inside
+        cnt, _ = orc.neighbors(pos, box, rc, cap=4)
+        assert list(cnt) == ([1, 1] if inside else [0, 0]), (xj, inside)
 
 
 def test_neighbor_capacity_reported(orc):
