@@ -475,6 +475,23 @@ int32_t nep_rdf_accumulate(const nep_model *model, nep_nlist *nl, const double *
                            const int32_t *types, int32_t P, int32_t N, double rmax, int32_t nbins, uint64_t *hist,
                            hipStream_t stream);
 
+/* nep_rdf_accumulate for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments and the same histogram, but the bead-minor
+ * copy of the positions lives in a 24 MiB array of the library's device
+ * code object instead of a list-owned allocation, so the call allocates
+ * nothing (no device memory, no timing events; its kernels are not timed by
+ * nep_profile_*).  Limit: P N <= 1,048,576 (bead, atom) rows, else
+ * NEP_ERR_INVALID_ARG with the sizes in the message.  Each device holds one
+ * such array for the life of the process, shared by every call on that
+ * device: calls that overlap on one device (different streams, or threads)
+ * race and must be ordered by the caller.  Every call rewrites the part it
+ * uses before reading it.  Errors as nep_rdf_accumulate, and NEP_ERR_HIP if
+ * the array's device address cannot be obtained. */
+int32_t nep_rdf_accumulate_noalloc(const nep_model *model, nep_nlist *nl, const double *pos, const double box[9],
+                                   const int32_t *types, int32_t P, int32_t N, double rmax, int32_t nbins,
+                                   uint64_t *hist, hipStream_t stream);
+
 /* ------------------------------------------------------------------ */
 /* Training (gradient of an energy / force / virial loss, Adam)        */
 /* ------------------------------------------------------------------ */

@@ -143,6 +143,7 @@ static hipEvent_t prof_event()
 
 ProfScope::ProfScope(int kid, hipStream_t stream) : id(kid), s(stream)
 {
+    if (kid < 0 || kid >= K_NUM) return;   // untimed launches
     if (!g_prof_on.load(std::memory_order_relaxed)) return;
     const int only = g_prof_only.load(std::memory_order_relaxed);
     if (only >= 0 && only != kid) return;

@@ -7,10 +7,43 @@
 // and its bin as floor(r * nbins / rmax), each step rounded separately.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "internal.hpp"
 
 namespace nep {
+
+// Scratch of nep_rdf_accumulate_noalloc: the bead-minor position copy in a
+// file-scope device array instead of a list-owned allocation.  Each device
+// holds its own copy from the first use until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// device (kept per device in g_rdf_scratch), never through the array's name.
+constexpr size_t kRdfScratchBytes = (size_t)24 << 20;   // 24 MiB: P N <= 1,048,576 (bead, atom) rows
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) double scratch[kRdfScratchBytes / sizeof(double)];
+static double *g_rdf_scratch[kMaxDevices];
+static std::mutex g_rdf_scratch_mu;
+
+// Device address of `scratch` on device dev (looked up once per device, with
+// dev current); NEP_ERR_HIP if the lookup fails.
+static int32_t rdf_scratch(int dev, double **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(NEP_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_rdf_scratch_mu);
+    if (!g_rdf_scratch[dev]) {
+        int cur = 0;
+        NEP_HIP(hipGetDevice(&cur));
+        if (cur != dev) NEP_HIP(hipSetDevice(dev));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) NEP_HIP(hipSetDevice(cur));
+        if (e != hipSuccess || !p)
+            return fail(NEP_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_rdf_scratch[dev] = static_cast<double *>(p);
+    }
+    *out = g_rdf_scratch[dev];
+    return NEP_OK;
+}
 
 constexpr int kRdfBlock = 256;
 constexpr int kRdfMaxWords = 16384;   // S * S * nbins bins of 32-bit counts in LDS (64 KB)
@@ -138,13 +171,13 @@ __global__ void k_centroid_beads(const double *__restrict__ x, double *__restric
 
 using namespace nep;
 
-extern "C" int32_t nep_rdf_accumulate(const nep_model *m, nep_nlist *nl, const double *pos, const double box[9],
-                                      const int32_t *types, int32_t P, int32_t N, double rmax, int32_t nbins,
-                                      uint64_t *hist, hipStream_t s)
+// Argument checks and the launches of the pair histogram, with the
+// bead-minor copy of the positions at posT (null: the list's own copy,
+// allocated on the first call).
+static int32_t rdf_accumulate(const nep_model *m, nep_nlist *nl, const double *pos, const double box[9],
+                              const int32_t *types, int32_t P, int32_t N, double rmax, int32_t nbins, uint64_t *hist,
+                              double *posT, hipStream_t s)
 {
-    if (!m || !nl || !box) return fail(NEP_ERR_INVALID_ARG, "nep_rdf_accumulate: null argument");
-    if (P != nl->P || N != nl->N) return fail(NEP_ERR_INVALID_ARG, "nep_rdf_accumulate: P/N do not match the list");
-    if (nl->nsys != 1) return fail(NEP_ERR_UNSUPPORTED, "nep_rdf_accumulate: one system per list");
     const int S = nl->S;
     if (nbins < 1 || (int64_t)S * S * nbins > kRdfMaxWords)
         return fail(NEP_ERR_INVALID_ARG, "nep_rdf_accumulate: %d bins x %d species pairs exceed %d", nbins, S * S,
@@ -167,10 +200,15 @@ extern "C" int32_t nep_rdf_accumulate(const nep_model *m, nep_nlist *nl, const d
     const int64_t lanes = (int64_t)N << lg;
     const int groups = (int)std::min<int64_t>((lanes + kRdfBlock - 1) / kRdfBlock, kRdfMaxGroups);
     const size_t lds = sizeof(uint32_t) * (size_t)S * S * nbins;
-    if (!nl->posT) NEP_HIP(hipMalloc(&nl->posT, sizeof(double) * 3 * (size_t)N * P));   // first call only
-    ProfScope ps_(K_RDF, s);
+    const bool own = !posT;   // the library's own copy; timed when kernel timing is on
+    if (own) {
+        if (!nl->posT) NEP_HIP(hipMalloc(&nl->posT, sizeof(double) * 3 * (size_t)N * P));   // first call only
+        posT = nl->posT;
+    }
+    // the allocation-free form creates no timing events either
+    ProfScope ps_(own ? K_RDF : K_NUM, s);
     const int64_t PN = (int64_t)P * N;
-    hipLaunchKernelGGL(k_beads_minor, dim3((unsigned)((PN + 255) / 256)), dim3(256), 0, s, pos, nl->posT, P, N);
+    hipLaunchKernelGGL(k_beads_minor, dim3((unsigned)((PN + 255) / 256)), dim3(256), 0, s, pos, posT, P, N);
     RdfCell cell{};
     cell.tri = ci.tri;
     for (int k = 0; k < 9; ++k) {
@@ -181,10 +219,39 @@ extern "C" int32_t nep_rdf_accumulate(const nep_model *m, nep_nlist *nl, const d
         cell.L[a] = ci.H[4 * a];
         cell.iL[a] = 1.0 / ci.H[4 * a];
     }
-    hipLaunchKernelGGL(k_rdf, dim3(groups), dim3(kRdfBlock), lds, s, nl->posT, types, P, N, S, lg, cell, nbins / rmax,
+    hipLaunchKernelGGL(k_rdf, dim3(groups), dim3(kRdfBlock), lds, s, posT, types, P, N, S, lg, cell, nbins / rmax,
                        nbins, nl->uniR, nl->umR, nl->uendR, nl->capR, reinterpret_cast<unsigned long long *>(hist));
     NEP_HIP(hipGetLastError());
     return NEP_OK;
+}
+
+extern "C" int32_t nep_rdf_accumulate(const nep_model *m, nep_nlist *nl, const double *pos, const double box[9],
+                                      const int32_t *types, int32_t P, int32_t N, double rmax, int32_t nbins,
+                                      uint64_t *hist, hipStream_t s)
+{
+    if (!m || !nl || !box) return fail(NEP_ERR_INVALID_ARG, "nep_rdf_accumulate: null argument");
+    if (P != nl->P || N != nl->N) return fail(NEP_ERR_INVALID_ARG, "nep_rdf_accumulate: P/N do not match the list");
+    if (nl->nsys != 1) return fail(NEP_ERR_UNSUPPORTED, "nep_rdf_accumulate: one system per list");
+    return rdf_accumulate(m, nl, pos, box, types, P, N, rmax, nbins, hist, nullptr, s);
+}
+
+extern "C" int32_t nep_rdf_accumulate_noalloc(const nep_model *m, nep_nlist *nl, const double *pos,
+                                              const double box[9], const int32_t *types, int32_t P, int32_t N,
+                                              double rmax, int32_t nbins, uint64_t *hist, hipStream_t s)
+{
+    if (!m || !nl || !box) return fail(NEP_ERR_INVALID_ARG, "nep_rdf_accumulate_noalloc: null argument");
+    if (P != nl->P || N != nl->N)
+        return fail(NEP_ERR_INVALID_ARG, "nep_rdf_accumulate_noalloc: P/N do not match the list");
+    if (nl->nsys != 1) return fail(NEP_ERR_UNSUPPORTED, "nep_rdf_accumulate_noalloc: one system per list");
+    const size_t need = sizeof(double) * 3 * (size_t)P * (size_t)N;
+    if (need > kRdfScratchBytes)
+        return fail(NEP_ERR_INVALID_ARG, "nep_rdf_accumulate_noalloc: P N = %lld (bead, atom) rows need %zu bytes "
+                                         "of scratch, more than its %zu (at most %zu rows)",
+                    (long long)P * N, need, kRdfScratchBytes, kRdfScratchBytes / (3 * sizeof(double)));
+    double *posT = nullptr;
+    const int32_t rc = rdf_scratch(nl->device, &posT);
+    if (rc != NEP_OK) return rc;
+    return rdf_accumulate(m, nl, pos, box, types, P, N, rmax, nbins, hist, posT, s);
 }
 
 extern "C" int32_t pimd_centroid(const pimd_ctx *c, const double *x, double *out, hipStream_t s)

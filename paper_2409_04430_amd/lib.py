@@ -110,6 +110,8 @@ _sig = {
     "pimd_centroid": (_i32, [_vp, _vp, _vp, _vp]),
     "nep_rdf_accumulate": (_i32, [_vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, C.c_double, _i32, _vp,
                                   _vp]),
+    "nep_rdf_accumulate_noalloc": (_i32, [_vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, C.c_double, _i32,
+                                          _vp, _vp]),
     "nep_nlist_set_skin": (_i32, [_vp, C.c_double]),
     "nep_nlist_invalidate": (_i32, [_vp]),
     "nep_ws_set_tile": (_i32, [_vp, _i32]),
@@ -295,6 +297,18 @@ class NeighborList:
                                        _box9(box), _ptr(types, t.int32, (self.N,), "types"), self.P, self.N,
                                        float(rmax), int(hist.shape[2]), _ptr(hist, t.int64, None, "hist"),
                                        _stream()))
+
+    def rdf_accumulate_noalloc(self, pos, box, types, hist, rmax: float):
+        """nep_rdf_accumulate_noalloc: as rdf_accumulate, with the library's static
+        scratch instead of an allocation (P N <= 1,048,576)."""
+        t = _torch()
+        S = self.model.n_species
+        if hist.dim() != 3 or hist.shape[0] != S or hist.shape[1] != S:
+            raise ValueError(f"hist must have shape [{S}, {S}, nbins]")
+        _check(_lib.nep_rdf_accumulate_noalloc(self.model.handle, self._h,
+                                               _ptr(pos, t.float64, (self.P, self.N, 3), "pos"), _box9(box),
+                                               _ptr(types, t.int32, (self.N,), "types"), self.P, self.N, float(rmax),
+                                               int(hist.shape[2]), _ptr(hist, t.int64, None, "hist"), _stream()))
 
     def status(self, clear: bool = True) -> dict:
         """Sticky list status (synchronises the stream)."""
