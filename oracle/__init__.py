@@ -21,7 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = [os.path.join(_HERE, f) for f in ("nep_oracle.c", "pimd_oracle.c")]
+_SRC = [os.path.join(_HERE, f) for f in ("nep_oracle.c", "pimd_oracle.c", "d3_oracle.c")]
 
 
 def build(force: bool = False) -> str:
@@ -87,6 +87,20 @@ def lib():
         L.or_berendsen.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp, C.c_double, C.c_double, C.c_double, C.c_int,
                                    dp]
         L.or_berendsen.restype = None
+        L.or_d3_load.argtypes = [C.c_char_p, C.POINTER(vp)]
+        L.or_d3_load.restype = C.c_int
+        L.or_d3_free.argtypes = [vp]
+        L.or_d3_free.restype = None
+        L.or_d3_cn_term.argtypes = [vp, C.c_int, C.c_int, C.c_double, dp, dp]
+        L.or_d3_cn_term.restype = None
+        L.or_d3_c6.argtypes = [vp, C.c_int, C.c_int, C.c_double, C.c_double, dp, dp, dp]
+        L.or_d3_c6.restype = None
+        L.or_d3_cn.argtypes = [vp, dp, ip, C.c_int, dp, dp]
+        L.or_d3_cn.restype = None
+        L.or_d3_config.argtypes = [vp, dp, ip, C.c_int, dp, dp, dp, dp, dp, dp]
+        L.or_d3_config.restype = C.c_int
+        L.or_d3_beads.argtypes = [vp, dp, ip, C.c_int, C.c_int, dp, dp, dp, dp]
+        L.or_d3_beads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -183,6 +197,60 @@ class Model:
         if rc:
             raise RuntimeError(f"oracle: neighbour capacity {cap} too small")
         return dict(E=E, F=F, W=W.reshape(P, 3, 3), U=U, Wat=Wat.reshape(P, N, 3, 3))
+
+
+class D3:
+    """A D3 dispersion parameter file loaded into the oracle (see d3_oracle.c)."""
+
+    def __init__(self, path: str):
+        self._h = C.c_void_p()
+        rc = lib().or_d3_load(path.encode(), C.byref(self._h))
+        if rc:
+            raise ValueError(f"oracle: cannot load D3 parameter file {path} (code {rc})")
+
+    def __del__(self):
+        if getattr(self, "_h", None) and lib is not None:
+            try:
+                lib().or_d3_free(self._h)
+            except Exception:
+                pass
+            self._h = None
+
+    def cn_term(self, ti: int, tj: int, r: float):
+        """(c(r), dc/dr) of one coordination-number term."""
+        c, dc = np.zeros(1), np.zeros(1)
+        lib().or_d3_cn_term(self._h, int(ti), int(tj), float(r), _d(c), _d(dc))
+        return float(c[0]), float(dc[0])
+
+    def c6(self, ti: int, tj: int, cni: float, cnj: float):
+        """(C6, dC6/dCN_i, dC6/dCN_j) of a species pair."""
+        out = np.zeros(3)
+        lib().or_d3_c6(self._h, int(ti), int(tj), float(cni), float(cnj), _d(out[0:]), _d(out[1:]), _d(out[2:]))
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def cn(self, pos, types, box):
+        pos = _f64(pos); types = _i32(types); box = _cell9(box)
+        out = np.zeros(len(pos))
+        lib().or_d3_cn(self._h, _d(pos), _i(types), len(pos), _d(box), _d(out))
+        return out
+
+    def config(self, pos, types, box):
+        """E, F [N,3], W [3,3], CN [N], U [N] of one configuration."""
+        pos = _f64(pos); types = _i32(types); box = _cell9(box)
+        N = len(pos)
+        E = np.zeros(1); F = np.zeros((N, 3)); W = np.zeros(9); cn = np.zeros(N); U = np.zeros(N)
+        if lib().or_d3_config(self._h, _d(pos), _i(types), N, _d(box), _d(E), _d(F), _d(W), _d(cn), _d(U)):
+            raise RuntimeError("oracle: D3 evaluation failed")
+        return dict(E=float(E[0]), F=F, W=W.reshape(3, 3), CN=cn, U=U)
+
+    def beads(self, pos, types, box):
+        """All beads: pos [P,N,3] -> E [P], F [P,N,3], W [P,3,3]."""
+        pos = _f64(pos); types = _i32(types); box = _cell9(box)
+        P, N = pos.shape[:2]
+        E = np.zeros(P); F = np.zeros((P, N, 3)); W = np.zeros((P, 9))
+        if lib().or_d3_beads(self._h, _d(pos), _i(types), P, N, _d(box), _d(E), _d(F), _d(W)):
+            raise RuntimeError("oracle: D3 evaluation failed")
+        return dict(E=E, F=F, W=W.reshape(P, 3, 3))
 
 
 def force_rmse(Fa, Fb) -> float:

@@ -234,7 +234,9 @@ def random_model(h: NepHyper, rng: np.random.Generator, density: float,
 
 
 def _fmt(v) -> str:
-    return repr(float(np.float32(v))) if np.float32(v) == v else repr(float(v))
+    """Shortest text of an FP32 value when v is one, else of the double v."""
+    x = float(v)
+    return repr(float(np.float32(x))) if float(np.float32(x)) == x else repr(x)
 
 
 def write_model(path: str, m: dict) -> None:
@@ -358,3 +360,73 @@ def make_system(pos0, types, box, species_masses: Sequence[float], P: int, T: fl
     pos = replicate_beads(pos0, P)
     vel = bead_velocities(P, masses, T, rng)
     return System(pos, vel, types.astype(np.int32), masses, np.asarray(box, np.float64))
+
+
+# --------------------------------------------------------------------------
+# D3 dispersion parameters (synthetic, seeded).
+# --------------------------------------------------------------------------
+
+D3_MAGIC = "nep_d3_params"
+D3_MAX_REF = 5
+
+
+def random_d3(n_species: int, rng: np.random.Generator, rc: float = 12.0, rc_cn: float = 6.0) -> dict:
+    """Seeded synthetic D3 reference tables in eV and Angstrom.
+
+    The element tables of the published D3 are not available here, so every
+    table is drawn from a seed: covalent radii R ~ U(0.6, 1.4) A, the C8/C6
+    factors q ~ U(1.5, 3.5) A, 2..5 reference coordination numbers per
+    species (the first 0, the others ~ U(0.5, 5), sorted), reference C6 ~
+    U(5, 60) eV A^6 (symmetric under exchanging the two atoms with their
+    references), damping s6 = 1, s8 ~ U(0.5, 1.5), a1 ~ U(0.3, 0.6),
+    a2 ~ U(2, 3) A.  k1 = 16, k2 = 4/3 and k3 = 4 are the constants of the
+    published functional form.  Cutoffs 12 A (dispersion) and 6 A
+    (coordination number).  All values are FP32-representable."""
+    S = n_species
+    nref = rng.integers(2, D3_MAX_REF + 1, S)
+    cnref = np.zeros((S, D3_MAX_REF))
+    for s in range(S):
+        cnref[s, 1:nref[s]] = np.sort(rng.uniform(0.5, 5.0, nref[s] - 1))
+    c6 = np.zeros((S, S, D3_MAX_REF, D3_MAX_REF))
+    for si in range(S):
+        for sj in range(si, S):
+            blk = rng.uniform(5.0, 60.0, (D3_MAX_REF, D3_MAX_REF))
+            if si == sj:
+                blk = np.triu(blk) + np.triu(blk, 1).T
+            c6[si, sj] = blk
+            c6[sj, si] = blk.T
+    return dict(S=S, rc=float(rc), rc_cn=float(rc_cn), s6=1.0, s8=_f32(rng.uniform(0.5, 1.5)),
+                a1=_f32(rng.uniform(0.3, 0.6)), a2=_f32(rng.uniform(2.0, 3.0)),
+                k1=16.0, k2=_f32(4.0 / 3.0), k3=4.0, rcov=_f32(rng.uniform(0.6, 1.4, S)),
+                q=_f32(rng.uniform(1.5, 3.5, S)), nref=nref.astype(int), cnref=_f32(cnref), c6ref=_f32(c6))
+
+
+def write_d3(path: str, d: dict) -> None:
+    """Write the plain-text D3 parameter file read by the library and the oracle.
+
+    Layout (whitespace separated):
+      nep_d3_params 1
+      species S
+      cutoff rc rc_cn
+      damping s6 s8 a1 a2
+      constants k1 k2 k3
+      rcov S values;  q S values;  nref S integers
+      cnref      per species its nref values
+      c6ref      for si, sj: nref[si] x nref[sj] values (row = reference of si)
+    """
+    S = d["S"]
+    L = [f"{D3_MAGIC} 1", f"species {S}", f"cutoff {_fmt(d['rc'])} {_fmt(d['rc_cn'])}",
+         "damping " + " ".join(_fmt(d[k]) for k in ("s6", "s8", "a1", "a2")),
+         "constants " + " ".join(_fmt(d[k]) for k in ("k1", "k2", "k3")),
+         "rcov " + " ".join(_fmt(v) for v in d["rcov"]),
+         "q " + " ".join(_fmt(v) for v in d["q"]),
+         "nref " + " ".join(str(int(n)) for n in d["nref"]), "cnref"]
+    for s in range(S):
+        L.append(" ".join(_fmt(v) for v in d["cnref"][s, :d["nref"][s]]))
+    L.append("c6ref")
+    for si in range(S):
+        for sj in range(S):
+            blk = d["c6ref"][si, sj, :d["nref"][si], :d["nref"][sj]]
+            L.append(" ".join(_fmt(v) for v in blk.ravel()))
+    with open(path, "w") as f:
+        f.write("\n".join(L) + "\n")
