@@ -105,14 +105,28 @@ void or_d3_cn_term(const or_d3 *d, int ti, int tj, double r, double *c, double *
 }
 
 /* C6 of a species pair at coordination numbers (cni, cnj), with its
- * derivatives: the weighted mean of the reference values. */
+ * derivatives: the weighted mean of the reference values.  The mean does
+ * not change when every weight is multiplied by one factor, so the weights
+ * are taken relative to the largest, exp(-k3 (D_ab - D_min)) with
+ * D_ab = (cni - CNref_a)^2 + (cnj - CNref_b)^2: far from every reference
+ * the plain weights would all underflow (0/0), while the mean tends to the
+ * nearest reference's C6.  The factor depends on the coordination numbers
+ * but drops out of the derivative of the mean as well, so the weights'
+ * derivatives are taken at a fixed factor. */
 void or_d3_c6(const or_d3 *d, int ti, int tj, double cni, double cnj, double *c6, double *dc6i, double *dc6j)
 {
     double Z = 0.0, W = 0.0, dZi = 0.0, dWi = 0.0, dZj = 0.0, dWj = 0.0;
+    double Dmin = INFINITY;
     for (int a = 0; a < d->nref[ti]; ++a)
         for (int b = 0; b < d->nref[tj]; ++b) {
             const double xi = cni - d->cnref[ti][a], xj = cnj - d->cnref[tj][b];
-            const double L = exp(-d->k3 * (xi * xi + xj * xj));
+            const double D = xi * xi + xj * xj;
+            if (D < Dmin) Dmin = D;
+        }
+    for (int a = 0; a < d->nref[ti]; ++a)
+        for (int b = 0; b < d->nref[tj]; ++b) {
+            const double xi = cni - d->cnref[ti][a], xj = cnj - d->cnref[tj][b];
+            const double L = exp(-d->k3 * ((xi * xi + xj * xj) - Dmin));
             const double c = d->c6ref[ti][tj][a][b];
             Z += c * L;
             W += L;

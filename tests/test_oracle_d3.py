@@ -63,6 +63,12 @@ def test_c6_interpolation_closed_forms(orc, tmp_path):
     assert abs(c6 - 0.5 * (7.0 + 13.0)) < 1e-12
     c6, dci, _ = D.c6(0, 0, 0.5, 0.5)
     assert abs(c6 - 0.25 * (10.0 + 20.0 + 20.0 + 40.0)) < 1e-12
+    # far from every reference the mean tends to the nearest reference's C6
+    # (the plain weights would all underflow there)
+    c6, _, _ = D.c6(0, 0, 30.0, 31.0)
+    assert abs(c6 - 40.0) < 1e-12
+    c6, _, _ = D.c6(0, 1, -25.0, 40.0)
+    assert abs(c6 - 100.0) < 1e-12
     # symmetric in the two atoms
     a = D.c6(0, 1, 0.3, 2.2)
     b = D.c6(1, 0, 2.2, 0.3)
