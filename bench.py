@@ -558,6 +558,51 @@ def workload_leg(args, torch, lib, configs, I, NepPimd, name: str, steps: int, g
     return out
 
 
+def d3_flops(nR: float, nC: float) -> float:
+    """FP64 operations per (bead, atom) of the D3 passes (own count; an exp
+    counts 1): per dispersion pair the minimum image and distance (14), the
+    partner's five reference weights (25), the C6 interpolation and its
+    derivative (76), the damped terms and their derivatives (22) and the
+    sums (22); per coordination pair the term (20) and its force and virial
+    through the coordination numbers (45)."""
+    return 159.0 * nR + 65.0 * nC
+
+
+def d3_leg(args, torch, lib, configs, I, NepPimd, steps: int):
+    """NEP-D3 on the porous framework (13,824 atoms x 64 beads): the NEP of
+    the workload plus D3 dispersion with seeded synthetic tables, timed like
+    the headline; the D3 kernels against the FP64 vector peak."""
+    w = configs.WORKLOADS["porous13824"]
+    s = w.systems()[0]
+    tmp = tempfile.mkdtemp(prefix="neppimd_d3_")
+    mpath, dpath = os.path.join(tmp, "porous.nep"), os.path.join(tmp, "porous.d3")
+    I.write_model(mpath, w.model())
+    I.write_d3(dpath, I.random_d3(w.hyper.n_species, np.random.default_rng(w.seed)))
+    eng = NepPimd(mpath, s, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=50, d3=dpath)
+    eng.run(args.warmup)
+    eng.check()
+    eng.check_every = 0
+    kernels = kernel_profile(torch, lib, eng, 5) if not args.no_profile else {}
+    ms, _, rb, _ = timed_steps(torch, eng, steps, False)
+    lst = eng.d3_nl.to_host(eng.pos, eng.box, eng.d3_caps[0], eng.d3_caps[1])
+    nR, nC = float(lst["cnt_radial"].mean()), float(lst["cnt_angular"].mean())
+    units = s.N * s.P
+    out = {"workload": f"porous13824_p{s.P}_nep_d3", "steps": steps, "ms_per_step": round(ms, 4),
+           "value": round(units / (ms * 1e-3), 1), "rebuilds_timed": rb,
+           "d3_mean_neighbours": [round(nR, 2), round(nC, 2)], "cutoffs_A": [eng.d3.rc, eng.d3.rc_cn],
+           "tables": "seeded synthetic (no published element tables)",
+           "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()}}
+    d3k = [k for k in ("d3_cn", "d3_pair", "d3_cnforce") if k in kernels]
+    if d3k:
+        us = sum(kernels[k]["avg_us"] for k in d3k)
+        tf = d3_flops(nR, nC) * units / (us * 1e-6) / 1e12
+        out["d3_roofline"] = {"bound": "alu", "achieved": round(tf, 3), "peak": 78.6, "unit": "TFLOP/s (FP64)",
+                              "frac": round(tf / 78.6, 4), "avg_us": round(us, 2),
+                              "flop_per_atom_bead": round(d3_flops(nR, nC), 1)}
+    del eng
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -653,6 +698,7 @@ def main():
     if not args.no_legs:
         for name, st in (("fcc108", 100), ("water16", 50), ("porous13824", 20)):
             legs[name] = workload_leg(args, torch, lib, configs, I, NepPimd, name, st, graph=True)
+        legs["porous13824_nep_d3"] = d3_leg(args, torch, lib, configs, I, NepPimd, 20)
     npt = None
     if not args.no_npt:
         npt = npt_leg(args, torch, lib, w, model_path, s, NepPimd, ms)

@@ -311,7 +311,8 @@ void nep_ws_destroy(nep_ws *ws);
  * about 1e-6 A); the rest is FP32 arithmetic with FP64 accumulation of
  * forces, energies and virials.
  * The summation order is fixed, so repeated calls give identical bits.
- * Errors: NEP_ERR_INVALID_ARG (sizes differ from the handles'), NEP_ERR_HIP.
+ * Errors: NEP_ERR_INVALID_ARG (sizes differ from the handles', lists built
+ * with other cutoffs than the model's), NEP_ERR_HIP.
  * Non-finite forces set NEP_FLAG_NONFINITE in the workspace. */
 int32_t nep_compute(const nep_model *model, nep_nlist *nl, nep_ws *ws, const double *pos,
                     const double box[9], const int32_t *types, int32_t P, int32_t N, double *E, float *F,
@@ -491,6 +492,60 @@ int32_t nep_rdf_accumulate(const nep_model *model, nep_nlist *nl, const double *
 int32_t nep_rdf_accumulate_noalloc(const nep_model *model, nep_nlist *nl, const double *pos, const double box[9],
                                    const int32_t *types, int32_t P, int32_t N, double rmax, int32_t nbins,
                                    uint64_t *hist, hipStream_t stream);
+
+/* ------------------------------------------------------------------ */
+/* D3 dispersion of NEP-D3 (Sec. II.C, the MOF model)                  */
+/* ------------------------------------------------------------------ */
+
+typedef struct nep_d3 nep_d3;
+typedef struct nep_d3_ws nep_d3_ws;
+
+/* Parse a D3 parameter file (host) and upload its tables to the current
+ * device.  The paper adds D3 dispersion with Becke-Johnson damping to its
+ * MOF model, with a 12 A dispersion cutoff and a 6 A coordination-number
+ * cutoff; the form is the published D3 one, in eV and A:
+ *   CN_i  = sum_{j, r < rc_cn} 1 / (1 + exp(-k1 (k2 (R_i + R_j) / r - 1)))
+ *   C6_ij = sum_ab C6ref_ij(a,b) L_ab / sum_ab L_ab,
+ *           L_ab = exp(-k3 [(CN_i - CNref_i,a)^2 + (CN_j - CNref_j,b)^2])
+ *   C8_ij = 3 C6_ij q_i q_j,  f_ij = a1 sqrt(C8_ij / C6_ij) + a2
+ *   E     = -1/2 sum_i sum_{j, r < rc} [s6 C6_ij / (r^6 + f^6) + s8 C8_ij / (r^8 + f^8)]
+ * with hard cutoffs (strict r^2 < rc^2).  File layout: "nep_d3_params 1",
+ * "species S" (1..4), "cutoff rc rc_cn" (rc_cn <= rc), "damping s6 s8 a1
+ * a2", "constants k1 k2 k3", then "rcov", "q", "nref" (1..5 references)
+ * per species, "cnref" (each species' references) and "c6ref" (for every
+ * species pair, nref_i x nref_j values, eV A^6).  Errors:
+ * NEP_ERR_PARAMS_FILE, NEP_ERR_UNSUPPORTED, NEP_ERR_HIP, NEP_ERR_NOMEM.
+ * Released with nep_d3_destroy. */
+int32_t nep_d3_load(const char *path, nep_d3 **out);
+void nep_d3_destroy(nep_d3 *d3);
+
+/* The cutoff descriptor of the D3 lists: a model handle (owned by d3, not
+ * to be destroyed) whose radial cutoff is rc and angular cutoff rc_cn, for
+ * nep_nlist_create / neighbor_build only (it has no network: the NEP
+ * entry points reject it).  The D3 lists are a neighbour handle of their
+ * own, built on the same positions as the NEP lists. */
+int32_t nep_d3_list_model(const nep_d3 *d3, const nep_model **out);
+
+/* Workspace for P beads of N atoms (coordination numbers, dE/dCN, direct
+ * forces, partial sums).  Errors: NEP_ERR_INVALID_ARG, NEP_ERR_NOMEM. */
+int32_t nep_d3_ws_create(const nep_d3 *d3, int32_t P, int32_t N, nep_d3_ws **out);
+void nep_d3_ws_destroy(nep_d3_ws *ws);
+
+/* D3 energy, forces and virial of every bead from lists built by
+ * neighbor_build with the model of nep_d3_list_model on the same
+ * positions (one system per list).  F_i = -dE/dr_i through the explicit
+ * distances and through CN_i and CN_j; W_ab = -sum over ordered pairs of
+ * r_ij^a (dE/dr_ij)^b (the convention of nep_compute).  With accumulate != 0
+ * the results are added to E [P], F [P][N][3] and W [P][9] (dev; e.g. after
+ * nep_compute, giving NEP-D3), else they overwrite them.  FP64 arithmetic
+ * throughout (the pair terms of a near-perfect crystal nearly cancel, so
+ * FP32 pair terms would cost their net force its relative accuracy); fixed
+ * sum order.  Errors: NEP_ERR_INVALID_ARG (sizes, lists built with other
+ * cutoffs, box differing from the last build), NEP_ERR_UNSUPPORTED (a
+ * batched list), NEP_ERR_HIP. */
+int32_t nep_d3_compute(const nep_d3 *d3, nep_nlist *nl, nep_d3_ws *ws, const double *pos, const double box[9],
+                       const int32_t *types, int32_t P, int32_t N, double *E, float *F, double *W,
+                       int32_t accumulate, hipStream_t stream);
 
 /* ------------------------------------------------------------------ */
 /* Training (gradient of an energy / force / virial loss, Adam)        */

@@ -22,7 +22,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libneppimd.so")
 ARCH = os.environ.get("NEPPIMD_ARCH", "gfx950")
 
-SOURCES = ["core.hip", "nlist.hip", "nep.hip", "pimd.hip", "train.hip", "observe.hip"]
+SOURCES = ["core.hip", "nlist.hip", "nep.hip", "pimd.hip", "train.hip", "observe.hip", "d3.hip"]
 EXTRA = {"nlist.hip": ["-ffp-contract=off"], "observe.hip": ["-ffp-contract=off"]}
 
 

@@ -117,7 +117,8 @@ FineGrid fine_grid(const double L[3], double rc)
 
 static const char *kKernelNames[K_NUM] = {"fill",   "centroid", "candidates", "nlist",       "materialize",
                                           "descriptor", "force_ang", "force", "reduce",   "trpmd",
-                                          "modes", "observables", "barostat", "rdf"};
+                                          "modes", "observables", "barostat", "rdf", "d3_cn", "d3_pair",
+                                          "d3_cnforce", "d3_reduce"};
 static std::atomic<int> g_prof_on{0};
 static std::atomic<int> g_prof_only{-1};   // -1: every kind
 static std::mutex g_prof_mu;
@@ -409,7 +410,7 @@ extern "C" int32_t nep_model_info(const nep_model *m, nep_hparams *out)
 
 extern "C" void nep_model_destroy(nep_model *m)
 {
-    if (!m) return;
+    if (!m || m->cutoffs_only) return;   // a descriptor owned by its D3 handle
     if (m->dev) (void)hipFree(m->dev);
     if (m->w0b) (void)hipFree(m->w0b);
     delete m;
@@ -436,6 +437,7 @@ __global__ void k_w0_bf16(const float *__restrict__ W0, int S, int H, int D, uin
 extern "C" int32_t nep_model_set_mlp(nep_model *m, int32_t mode, hipStream_t s)
 {
     if (!m) return fail(NEP_ERR_INVALID_ARG, "nep_model_set_mlp: null model");
+    if (m->cutoffs_only) return fail(NEP_ERR_INVALID_ARG, "nep_model_set_mlp: a list cutoff descriptor has no network");
     if (mode == NEP_MLP_FP32) {
         m->mlp = mode;
         return NEP_OK;
@@ -645,6 +647,7 @@ extern "C" int32_t nep_ws_create_batched(const nep_model *m, int32_t P, int32_t 
                                          nep_ws **out)
 {
     if (!m || !out) return fail(NEP_ERR_INVALID_ARG, "nep_ws_create: null argument");
+    if (m->cutoffs_only) return fail(NEP_ERR_INVALID_ARG, "nep_ws_create: a list cutoff descriptor has no network");
     const int32_t rc0 = check_offsets(nsys, off, "nep_ws_create");
     if (rc0 != NEP_OK) return rc0;
     const int32_t N = off[nsys];

@@ -1,0 +1,565 @@
+// D3 dispersion with Becke-Johnson damping, the dispersion term of NEP-D3
+// (the paper's MOF model, Sec. II.C: 12 A dispersion cutoff, 6 A
+// coordination-number cutoff), for every bead of a ring polymer on gfx950.
+//
+// Published D3 form (Grimme et al. 2010: coordination numbers and the C6
+// interpolation; Grimme, Ehrlich and Goerigk 2011: the damping), eV and A:
+//   CN_i  = sum_{j, r < rc_cn} 1 / (1 + exp(-k1 (k2 (R_i + R_j) / r - 1)))
+//   C6_ij = sum_ab C6ref(a, b) L_i,a L_j,b / (sum_a L_i,a sum_b L_j,b),
+//           L_i,a = exp(-k3 (CN_i - CNref_i,a)^2)
+//   C8_ij = 3 C6_ij q_i q_j,  f_ij = a1 sqrt(3 q_i q_j) + a2
+//   E     = -1/2 sum_i sum_{j, r < rc} [s6 C6 / (r^6 + f^6) + s8 C8 / (r^8 + f^8)]
+// The weights of one atom share the factor exp(-k3 m_i), m_i the smallest
+// squared distance to a reference, which cancels in C6 and its derivative;
+// dividing it out keeps the largest weight at 1 (far from every reference
+// the plain weights underflow).  FP64 throughout: pair vectors from a
+// bead-minor FP64 copy of the positions with the minimum image of the list
+// test, FP64 weights and sums (the many pair terms of a near-perfect
+// crystal nearly cancel, which FP32 terms would not resolve).
+//
+// Lists: a neighbour handle built with the cutoff descriptor of the D3
+// parameters (dispersion cutoff as its radial cutoff, coordination cutoff as
+// its angular one), so the per-bead pair sets are the exact FP64 decisions
+// of the union lists' bead masks.  Passes, one lane per (atom, bead), the
+// beads of an atom in adjacent lanes, gathers only (no atomics):
+//   k_d3_cn       CN_i over the coordination list;
+//   k_d3_pair     site energy, direct forces and virial over the dispersion
+//                 list, and dE/dCN_i = -sum_j (de_ij/dC6) dC6_ij/dCN_i;
+//   k_d3_cnforce  forces (dE/dCN_i + dE/dCN_j) c'(r) u_ij and virial
+//                 -dE/dCN_i c'(r) r_ij (x) u_ij through the coordination
+//                 numbers, the total force written (or added);
+//   k_d3_reduce   per-bead energy and virial from per-workgroup partial sums
+//                 in a fixed order.
+#include <cmath>
+#include <fstream>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "nep_kernels.hpp"
+
+namespace nep {
+
+constexpr int kD3Ref = 5;
+// table: rcov [4], q [4], cnref [4][5], c6ref [4][4][5][5], f^6 [4][4], f^8 [4][4], 3 q_i q_j [4][4]
+constexpr int kTRcov = 0, kTQ = 4, kTCn = 8, kTC6 = kTCn + kMaxSpecies * kD3Ref,
+              kTF6 = kTC6 + kMaxSpecies * kMaxSpecies * kD3Ref * kD3Ref, kTF8 = kTF6 + 16, kTQQ = kTF8 + 16,
+              kTab = kTQQ + 16;
+constexpr double kD3PadCn = 1.0e4;   // reference slots past a species' count: weight exp(-k3 1e8) = 0
+
+struct D3Args {
+    const double *posT;   // [N][P][3] FP64 positions, bead-minor
+    const int32_t *types;
+    int N, P, lg, S;
+    const SysGeom *geom;
+    const int32_t *candA, *uniR, *uendR, *uniA, *uendA;
+    const uint64_t *umR, *umA;
+    int capR, capA;
+    const double *tab;
+    double s6, s8, k1, k2, k3;
+    double *cn, *dedcn, *fdir;   // [N][P], [N][P], [N][P][3]
+    double *partE, *partW0, *partW1;   // [P][nblk], [P][9][nblk] twice
+    float *F;
+    int accumulate;
+};
+
+// (atom, bead) of this lane: 2^lg lanes per atom, 256 >> lg atoms per workgroup.
+__device__ __forceinline__ bool d3_lane(const D3Args &a, int &i, int &b)
+{
+    const int G = 1 << a.lg;
+    i = blockIdx.x * (256 >> a.lg) + ((int)threadIdx.x >> a.lg);
+    b = threadIdx.x & (G - 1);
+    const bool ok = i < a.N && b < a.P;
+    i = i < a.N ? i : a.N - 1;
+    b = b < a.P ? b : a.P - 1;
+    return ok;
+}
+
+__device__ __forceinline__ void load_tab(const D3Args &a, double *t)
+{
+    for (int x = threadIdx.x; x < kTab; x += blockDim.x) t[x] = a.tab[x];
+    __syncthreads();
+}
+
+// Bead-minor FP64 copy of the positions: the beads of a neighbour are one
+// contiguous run for the lanes that gather them.
+__global__ void k_d3_beads_minor(const double *__restrict__ pos, double *__restrict__ posT, int P, int N)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // (i, b) with b fastest
+    if (e >= (int64_t)N * P) return;
+    const int i = (int)(e / P), b = (int)(e - (int64_t)i * P);
+    const double *src = pos + ((size_t)b * N + i) * 3;
+    double *dst = posT + (size_t)e * 3;
+    dst[0] = src[0];
+    dst[1] = src[1];
+    dst[2] = src[2];
+}
+
+// Minimum-image vector r_j - r_i in FP64 (every listed pair is closer than
+// half the smallest face distance, so the rint reduction gives the nearest
+// image, as in the list test).
+__device__ __forceinline__ void d3_pair_vec(const double *rj, const double *ri, const SysGeom &g, double &dx,
+                                            double &dy, double &dz)
+{
+    double d[3] = {rj[0] - ri[0], rj[1] - ri[1], rj[2] - ri[2]};
+    if (!g.tri) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) d[c] -= g.L[c] * rint(d[c] * g.invL[c]);
+    } else {
+        double f[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const double sc = d[0] * g.G[c] + d[1] * g.G[3 + c] + d[2] * g.G[6 + c];
+            f[c] = sc - rint(sc);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) d[c] = f[0] * g.H[c] + f[1] * g.H[3 + c] + f[2] * g.H[6 + c];
+    }
+    dx = d[0];
+    dy = d[1];
+    dz = d[2];
+}
+
+// Reference weights of one atom at coordination number cn, divided by
+// exp(-k3 m), m the smallest squared distance to a reference (the factor
+// cancels in C6 and in its derivative), with their derivatives at a fixed
+// factor; returns the sums.
+__device__ __forceinline__ void ref_weights(const double *t, int ty, double cn, double k3, double (&L)[kD3Ref],
+                                            double (&dL)[kD3Ref], double &sL, double &sdL)
+{
+    double x[kD3Ref], m = 1.0e300;
+#pragma unroll
+    for (int r = 0; r < kD3Ref; ++r) {
+        x[r] = cn - t[kTCn + ty * kD3Ref + r];
+        m = fmin(m, x[r] * x[r]);
+    }
+    sL = 0.0;
+    sdL = 0.0;
+#pragma unroll
+    for (int r = 0; r < kD3Ref; ++r) {
+        L[r] = exp(-k3 * (x[r] * x[r] - m));
+        dL[r] = -2.0 * k3 * x[r] * L[r];
+        sL += L[r];
+        sdL += dL[r];
+    }
+}
+
+// ------------------------------------------------ coordination numbers ---
+
+__global__ __launch_bounds__(256) void k_d3_cn(D3Args a)
+{
+    __shared__ double t[kTab];
+    load_tab(a, t);
+    int i, b;
+    const bool ok = d3_lane(a, i, b);
+    if (!ok) return;
+    const SysGeom &g = a.geom[0];
+    const int P = a.P, ti = a.types[i] & 3;
+    const double *ri = a.posT + ((size_t)i * P + b) * 3;
+    const int32_t *uA = a.uniA + (size_t)i * a.capA;
+    const uint64_t *mA = a.umA + (size_t)i * a.capA;
+    const int32_t *row = a.candA + (size_t)i * a.capA;
+    const int n = a.uendA[(size_t)i * kMaxSpecies + a.S - 1];
+    const double Ri = t[kTRcov + ti], kk = a.k1 * a.k2;
+    double cn = 0.0;
+    for (int e = 0; e < n; ++e) {
+        if (!((mA[e] >> b) & 1u)) continue;
+        const int w = row[uA[e]];
+        const int j = w >> 2, tj = w & 3;
+        double dx, dy, dz;
+        d3_pair_vec(a.posT + ((size_t)j * P + b) * 3, ri, g, dx, dy, dz);
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        cn += 1.0 / (1.0 + exp(a.k1 - kk * (Ri + t[kTRcov + tj]) / r));
+    }
+    a.cn[(size_t)i * P + b] = cn;
+}
+
+// ------------------------------------------- dispersion pairs, dE/dCN ---
+
+__global__ __launch_bounds__(256) void k_d3_pair(D3Args a)
+{
+    __shared__ double t[kTab];
+    __shared__ double lds[256];
+    load_tab(a, t);
+    int i, b;
+    const bool ok = d3_lane(a, i, b);
+    const SysGeom &g = a.geom[0];
+    const int P = a.P, S = a.S, ti = a.types[i] & 3;
+    const double *ri = a.posT + ((size_t)i * P + b) * 3;
+    double Li[kD3Ref], dLi[kD3Ref], sLi, sdLi;
+    ref_weights(t, ti, a.cn[(size_t)i * P + b], a.k3, Li, dLi, sLi, sdLi);
+    double U = 0.0, dE = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    double Wv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // xx yy zz xy xz yz (symmetric)
+    const int32_t *uR = a.uniR + (size_t)i * a.capR;
+    const uint64_t *mR = a.umR + (size_t)i * a.capR;
+    for (int tj = 0; tj < S && ok; ++tj) {
+        int s0, s1;
+        block_range(a.uendR, i, tj, s0, s1);
+        const double *c6 = t + kTC6 + (ti * kMaxSpecies + tj) * kD3Ref * kD3Ref;
+        const double f6 = t[kTF6 + ti * 4 + tj], f8 = t[kTF8 + ti * 4 + tj], qq = t[kTQQ + ti * 4 + tj];
+        for (int e = s0; e < s1; ++e) {
+            if (!((mR[e] >> b) & 1u)) continue;
+            const int j = uR[e];
+            double dx, dy, dz;
+            d3_pair_vec(a.posT + ((size_t)j * P + b) * 3, ri, g, dx, dy, dz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            double Lj[kD3Ref], dLj[kD3Ref], sLj, sdLj;
+            ref_weights(t, tj, a.cn[(size_t)j * P + b], a.k3, Lj, dLj, sLj, sdLj);
+            double Z = 0.0, dZ = 0.0;
+#pragma unroll
+            for (int ra = 0; ra < kD3Ref; ++ra) {
+                double sa = 0.0;
+#pragma unroll
+                for (int rb = 0; rb < kD3Ref; ++rb) sa = fma(c6[ra * kD3Ref + rb], Lj[rb], sa);
+                Z = fma(Li[ra], sa, Z);
+                dZ = fma(dLi[ra], sa, dZ);
+            }
+            const double Winv = 1.0 / (sLi * sLj);
+            const double C6 = Z * Winv;
+            const double dC6 = (dZ - C6 * sdLi * sLj) * Winv;
+            const double r6 = r2 * r2 * r2, r8 = r6 * r2;
+            const double d6inv = 1.0 / (r6 + f6), d8inv = 1.0 / (r8 + f8);
+            const double e6 = a.s6 * C6 * d6inv, e8 = a.s8 * qq * C6 * d8inv;
+            // de/dr / r = -(6 e6 r^6 / (r^6 + f^6) + 8 e8 r^8 / (r^8 + f^8)) / r^2
+            const double dedr_r = -(6.0 * e6 * r6 * d6inv + 8.0 * e8 * r8 * d8inv) / r2;
+            const double dedc6 = a.s6 * d6inv + a.s8 * qq * d8inv;
+            U -= 0.5 * (e6 + e8);
+            dE -= dedc6 * dC6;
+            // F_i = -sum_j e' u_ij;  W += 1/2 e' r_ij (x) u_ij
+            fx -= dedr_r * dx;
+            fy -= dedr_r * dy;
+            fz -= dedr_r * dz;
+            const double hw = 0.5 * dedr_r;
+            Wv[0] += hw * dx * dx; Wv[1] += hw * dy * dy; Wv[2] += hw * dz * dz;
+            Wv[3] += hw * dx * dy; Wv[4] += hw * dx * dz; Wv[5] += hw * dy * dz;
+        }
+    }
+    if (ok) {
+        a.dedcn[(size_t)i * P + b] = dE;
+        double *fo = a.fdir + ((size_t)i * P + b) * 3;
+        fo[0] = fx;
+        fo[1] = fy;
+        fo[2] = fz;
+    }
+    const int nblk = gridDim.x;
+    bead_block_sum(ok ? U : 0.0, lds, P, a.lg, a.partE + blockIdx.x, nblk);
+    const int comp[9] = {0, 3, 4, 3, 1, 5, 4, 5, 2};
+    for (int c = 0; c < 9; ++c)
+        bead_block_sum(ok ? Wv[comp[c]] : 0.0, lds, P, a.lg, a.partW0 + (size_t)c * nblk + blockIdx.x, 9 * nblk);
+}
+
+// ------------------------------------ forces through the coordination ---
+
+__global__ __launch_bounds__(256) void k_d3_cnforce(D3Args a)
+{
+    __shared__ double t[kTab];
+    __shared__ double lds[256];
+    load_tab(a, t);
+    int i, b;
+    const bool ok = d3_lane(a, i, b);
+    const SysGeom &g = a.geom[0];
+    const int P = a.P, ti = a.types[i] & 3;
+    const double *ri = a.posT + ((size_t)i * P + b) * 3;
+    const double dEi = a.dedcn[(size_t)i * P + b];
+    const int32_t *uA = a.uniA + (size_t)i * a.capA;
+    const uint64_t *mA = a.umA + (size_t)i * a.capA;
+    const int32_t *row = a.candA + (size_t)i * a.capA;
+    const int n = ok ? a.uendA[(size_t)i * kMaxSpecies + a.S - 1] : 0;
+    const double Ri = t[kTRcov + ti], kk = a.k1 * a.k2;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    double Wv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int e = 0; e < n; ++e) {
+        if (!((mA[e] >> b) & 1u)) continue;
+        const int w = row[uA[e]];
+        const int j = w >> 2, tj = w & 3;
+        double dx, dy, dz;
+        d3_pair_vec(a.posT + ((size_t)j * P + b) * 3, ri, g, dx, dy, dz);
+        const double r2 = dx * dx + dy * dy + dz * dz;
+        const double r = sqrt(r2);
+        const double R = Ri + t[kTRcov + tj];
+        const double ex = exp(a.k1 - kk * R / r);
+        const double den = 1.0 + ex;
+        // c'(r) / r = -ex k1 k2 R / (r^3 (1 + ex)^2)
+        const double dc_r = -ex * kk * R / (r2 * r * den * den);
+        const double sum = (dEi + a.dedcn[(size_t)j * P + b]) * dc_r;
+        fx += sum * dx;
+        fy += sum * dy;
+        fz += sum * dz;
+        const double hw = -dEi * dc_r;
+        Wv[0] += hw * dx * dx; Wv[1] += hw * dy * dy; Wv[2] += hw * dz * dz;
+        Wv[3] += hw * dx * dy; Wv[4] += hw * dx * dz; Wv[5] += hw * dy * dz;
+    }
+    if (ok) {
+        const double *fd = a.fdir + ((size_t)i * P + b) * 3;
+        float *fo = a.F + ((size_t)b * a.N + i) * 3;
+        const double gx = fx + fd[0], gy = fy + fd[1], gz = fz + fd[2];
+        if (a.accumulate) {
+            fo[0] = (float)((double)fo[0] + gx);
+            fo[1] = (float)((double)fo[1] + gy);
+            fo[2] = (float)((double)fo[2] + gz);
+        } else {
+            fo[0] = (float)gx;
+            fo[1] = (float)gy;
+            fo[2] = (float)gz;
+        }
+    }
+    const int nblk = gridDim.x;
+    const int comp[9] = {0, 3, 4, 3, 1, 5, 4, 5, 2};
+    for (int c = 0; c < 9; ++c)
+        bead_block_sum(ok ? Wv[comp[c]] : 0.0, lds, P, a.lg, a.partW1 + (size_t)c * nblk + blockIdx.x, 9 * nblk);
+}
+
+// One workgroup per (bead, component c): c = 0 energy, 1..9 virial; partial
+// sums added in a fixed order.
+__global__ __launch_bounds__(256) void k_d3_reduce(const double *__restrict__ partE, const double *__restrict__ partW0,
+                                                   const double *__restrict__ partW1, int nblk, int accumulate,
+                                                   double *__restrict__ E, double *__restrict__ W)
+{
+    __shared__ double red[256];
+    const int b = blockIdx.x, c = blockIdx.y, t = threadIdx.x;
+    double acc = 0.0;
+    if (c == 0) {
+        for (int k = t; k < nblk; k += blockDim.x) acc += partE[(size_t)b * nblk + k];
+    } else {
+        const size_t o = ((size_t)b * 9 + (c - 1)) * nblk;
+        for (int k = t; k < nblk; k += blockDim.x) acc += partW0[o + k] + partW1[o + k];
+    }
+    red[t] = acc;
+    __syncthreads();
+    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        double *out = c == 0 ? E + b : W + (size_t)b * 9 + (c - 1);
+        *out = accumulate ? *out + red[0] : red[0];
+    }
+}
+
+}  // namespace nep
+
+using namespace nep;
+
+struct nep_d3 {
+    nep_model lists;            // cutoff descriptor of the neighbour lists (no weights)
+    int S = 0;
+    double rc = 0.0, rcn = 0.0;
+    double s6 = 0, s8 = 0, a1 = 0, a2 = 0, k1 = 0, k2 = 0, k3 = 0;
+    std::vector<double> host;   // the kTab table
+    double *dev = nullptr;
+    int device = 0;
+};
+
+struct nep_d3_ws {
+    int P = 0, N = 0, nblk = 0, lg = 0;
+    int device = 0;
+    double *posT = nullptr;                      // [N][P][3] bead-minor positions
+    double *cn = nullptr, *dedcn = nullptr, *fdir = nullptr;
+    double *partE = nullptr, *partW = nullptr;   // [P][nblk], 2 x [P][9][nblk]
+};
+
+extern "C" int32_t nep_d3_load(const char *path, nep_d3 **out)
+{
+    if (!path || !out) return fail(NEP_ERR_INVALID_ARG, "nep_d3_load: null argument");
+    *out = nullptr;
+    std::ifstream f(path);
+    if (!f) return fail(NEP_ERR_PARAMS_FILE, "nep_d3_load: cannot open %s", path);
+    auto word = [&](const char *w) {
+        std::string s;
+        return (f >> s) && s == w;
+    };
+    int ver = 0, S = 0;
+    double rc = 0, rcn = 0, s6, s8, a1, a2, k1, k2, k3;
+    if (!word("nep_d3_params") || !(f >> ver) || ver != 1 || !word("species") || !(f >> S) || !word("cutoff") ||
+        !(f >> rc >> rcn) || !word("damping") || !(f >> s6 >> s8 >> a1 >> a2) || !word("constants") ||
+        !(f >> k1 >> k2 >> k3))
+        return fail(NEP_ERR_PARAMS_FILE, "nep_d3_load: %s: malformed header", path);
+    if (S < 1 || S > kMaxSpecies) return fail(NEP_ERR_UNSUPPORTED, "nep_d3_load: %d species (1..4)", S);
+    if (!(rc > 0.0) || !(rcn > 0.0) || rcn > rc || !(k3 > 0.0) || !(a1 >= 0.0) || !(a2 >= 0.0) || !(k1 > 0.0) ||
+        !(k2 > 0.0))
+        return fail(NEP_ERR_PARAMS_FILE, "nep_d3_load: %s: bad cutoffs or constants", path);
+    double rcov[kMaxSpecies] = {0}, q[kMaxSpecies] = {0};
+    int nref[kMaxSpecies] = {0};
+    bool okr = word("rcov");
+    for (int s = 0; s < S && okr; ++s) okr = okr && (f >> rcov[s]) && rcov[s] > 0.0;
+    okr = okr && word("q");
+    for (int s = 0; s < S && okr; ++s) okr = okr && (f >> q[s]) && q[s] > 0.0;
+    okr = okr && word("nref");
+    for (int s = 0; s < S && okr; ++s) okr = okr && (f >> nref[s]) && nref[s] >= 1 && nref[s] <= kD3Ref;
+    if (!okr) return fail(NEP_ERR_PARAMS_FILE, "nep_d3_load: %s: bad species tables", path);
+    nep_d3 *d = new (std::nothrow) nep_d3;
+    if (!d) return fail(NEP_ERR_NOMEM, "host allocation failed");
+    d->host.assign(kTab, 0.0);
+    double *t = d->host.data();
+    bool ok = word("cnref");
+    for (int s = 0; s < S; ++s)
+        for (int r = 0; r < kD3Ref; ++r) {
+            double v = kD3PadCn;
+            if (r < nref[s]) ok = ok && (f >> v);
+            t[kTCn + s * kD3Ref + r] = v;
+        }
+    ok = ok && word("c6ref");
+    for (int si = 0; si < S; ++si)
+        for (int sj = 0; sj < S; ++sj)
+            for (int ra = 0; ra < nref[si]; ++ra)
+                for (int rb = 0; rb < nref[sj]; ++rb) {
+                    double v = 0.0;
+                    ok = ok && (f >> v) && v >= 0.0;
+                    t[kTC6 + ((si * kMaxSpecies + sj) * kD3Ref + ra) * kD3Ref + rb] = v;
+                }
+    if (!ok) {
+        delete d;
+        return fail(NEP_ERR_PARAMS_FILE, "nep_d3_load: %s: bad reference tables", path);
+    }
+    for (int s = 0; s < S; ++s) {
+        t[kTRcov + s] = rcov[s];
+        t[kTQ + s] = q[s];
+    }
+    for (int si = 0; si < S; ++si)
+        for (int sj = 0; sj < S; ++sj) {
+            const double qq = 3.0 * q[si] * q[sj];
+            const double fd = a1 * std::sqrt(qq) + a2;
+            const double f2 = fd * fd;
+            t[kTF6 + si * 4 + sj] = f2 * f2 * f2;
+            t[kTF8 + si * 4 + sj] = f2 * f2 * f2 * f2;
+            t[kTQQ + si * 4 + sj] = qq;
+        }
+    d->S = S;
+    d->rc = rc;
+    d->rcn = rcn;
+    d->s6 = s6; d->s8 = s8; d->a1 = a1; d->a2 = a2;
+    d->k1 = k1; d->k2 = k2; d->k3 = k3;
+    d->lists.hp = nep_hparams{};
+    d->lists.cutoffs_only = true;
+    d->lists.hp.n_species = S;
+    d->lists.hp.rc_radial = rc;
+    d->lists.hp.rc_angular = rcn;
+    hipError_t e = hipGetDevice(&d->device);
+    if (e == hipSuccess) e = hipMalloc((void **)&d->dev, sizeof(double) * kTab);
+    if (e == hipSuccess) e = hipMemcpy(d->dev, t, sizeof(double) * kTab, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (d->dev) (void)hipFree(d->dev);
+        delete d;
+        return fail(e == hipErrorOutOfMemory ? NEP_ERR_NOMEM : NEP_ERR_HIP, "nep_d3_load: %s", hipGetErrorString(e));
+    }
+    *out = d;
+    return NEP_OK;
+}
+
+extern "C" void nep_d3_destroy(nep_d3 *d)
+{
+    if (!d) return;
+    if (d->dev) (void)hipFree(d->dev);
+    delete d;
+}
+
+extern "C" int32_t nep_d3_list_model(const nep_d3 *d, const nep_model **out)
+{
+    if (!d || !out) return fail(NEP_ERR_INVALID_ARG, "nep_d3_list_model: null argument");
+    *out = &d->lists;
+    return NEP_OK;
+}
+
+extern "C" int32_t nep_d3_ws_create(const nep_d3 *d, int32_t P, int32_t N, nep_d3_ws **out)
+{
+    if (!d || !out) return fail(NEP_ERR_INVALID_ARG, "nep_d3_ws_create: null argument");
+    if (P < 0 || P > kMaxBeads || N < 0) return fail(NEP_ERR_INVALID_ARG, "nep_d3_ws_create: bad sizes P=%d N=%d", P, N);
+    *out = nullptr;
+    nep_d3_ws *w = new (std::nothrow) nep_d3_ws;
+    if (!w) return fail(NEP_ERR_NOMEM, "host allocation failed");
+    w->P = P;
+    w->N = N;
+    w->lg = lanes_log2(P > 0 ? P : 1);
+    w->nblk = div_up(N > 0 ? N : 1, 256 >> w->lg);
+    const size_t PN = (size_t)(P > 0 ? P : 1) * (N > 0 ? N : 1), Pp = P > 0 ? P : 1;
+    hipError_t e = hipGetDevice(&w->device);
+    if (e == hipSuccess) e = hipMalloc((void **)&w->posT, sizeof(double) * 3 * PN);
+    if (e == hipSuccess) e = hipMalloc((void **)&w->cn, sizeof(double) * PN);
+    if (e == hipSuccess) e = hipMalloc((void **)&w->dedcn, sizeof(double) * PN);
+    if (e == hipSuccess) e = hipMalloc((void **)&w->fdir, sizeof(double) * 3 * PN);
+    if (e == hipSuccess) e = hipMalloc((void **)&w->partE, sizeof(double) * Pp * w->nblk);
+    if (e == hipSuccess) e = hipMalloc((void **)&w->partW, sizeof(double) * 2 * 9 * Pp * w->nblk);
+    if (e != hipSuccess) {
+        for (void *p : {(void *)w->posT, (void *)w->cn, (void *)w->dedcn, (void *)w->fdir, (void *)w->partE,
+                        (void *)w->partW})
+            if (p) (void)hipFree(p);
+        delete w;
+        return fail(e == hipErrorOutOfMemory ? NEP_ERR_NOMEM : NEP_ERR_HIP, "nep_d3_ws_create: %s",
+                    hipGetErrorString(e));
+    }
+    *out = w;
+    return NEP_OK;
+}
+
+extern "C" void nep_d3_ws_destroy(nep_d3_ws *w)
+{
+    if (!w) return;
+    for (void *p : {(void *)w->posT, (void *)w->cn, (void *)w->dedcn, (void *)w->fdir, (void *)w->partE,
+                    (void *)w->partW})
+        if (p) (void)hipFree(p);
+    delete w;
+}
+
+extern "C" int32_t nep_d3_compute(const nep_d3 *d, nep_nlist *nl, nep_d3_ws *w, const double *pos, const double box[9],
+                                  const int32_t *types, int32_t P, int32_t N, double *E, float *F, double *W,
+                                  int32_t accumulate, hipStream_t s)
+{
+    if (!d || !nl || !w || !box) return fail(NEP_ERR_INVALID_ARG, "nep_d3_compute: null argument");
+    if (nl->P != P || nl->N != N || w->P != P || w->N != N || nl->S != d->S)
+        return fail(NEP_ERR_INVALID_ARG, "nep_d3_compute: P=%d N=%d do not match the list/workspace handles", P, N);
+    if (nl->nsys != 1) return fail(NEP_ERR_UNSUPPORTED, "nep_d3_compute: one system per list");
+    if (P == 0) return NEP_OK;
+    if (!E || !W) return fail(NEP_ERR_INVALID_ARG, "nep_d3_compute: null E or W");
+    if (N == 0) {
+        if (!accumulate) {
+            fill_u32(reinterpret_cast<uint32_t *>(E), 0u, (size_t)P * 2, s);
+            fill_u32(reinterpret_cast<uint32_t *>(W), 0u, (size_t)P * 18, s);
+        }
+        NEP_HIP(hipGetLastError());
+        return NEP_OK;
+    }
+    if (!pos || !types || !F) return fail(NEP_ERR_INVALID_ARG, "nep_d3_compute: null array");
+    if (!nl->built) return fail(NEP_ERR_INVALID_ARG, "nep_d3_compute: the neighbour lists were never built");
+    if (nl->rc_built[0] != d->rc || nl->rc_built[1] != d->rcn)
+        return fail(NEP_ERR_INVALID_ARG, "nep_d3_compute: the lists were built for cutoffs %g/%g, D3 needs %g/%g "
+                                         "(build them with the model of nep_d3_list_model)",
+                    nl->rc_built[0], nl->rc_built[1], d->rc, d->rcn);
+    for (int k = 0; k < 9; ++k)
+        if (box[k] != nl->boxL[k]) return fail(NEP_ERR_INVALID_ARG, "nep_d3_compute: box differs from the last build");
+    D3Args a{};
+    a.posT = w->posT;
+    a.types = types;
+    a.N = N; a.P = P; a.lg = w->lg; a.S = d->S;
+    a.geom = nl->geom;
+    a.candA = nl->candA; a.uniR = nl->uniR; a.uendR = nl->uendR; a.uniA = nl->uniA; a.uendA = nl->uendA;
+    a.umR = nl->umR; a.umA = nl->umA; a.capR = nl->capR; a.capA = nl->capA;
+    a.tab = d->dev;
+    a.s6 = d->s6; a.s8 = d->s8; a.k1 = d->k1; a.k2 = d->k2; a.k3 = d->k3;
+    a.cn = w->cn; a.dedcn = w->dedcn; a.fdir = w->fdir;
+    a.partE = w->partE; a.partW0 = w->partW; a.partW1 = w->partW + (size_t)9 * P * w->nblk;
+    a.F = F;
+    a.accumulate = accumulate ? 1 : 0;
+    const dim3 grid(w->nblk), block(256);
+    {
+        ProfScope ps_(K_D3_CN, s);
+        const int64_t PN = (int64_t)P * N;
+        hipLaunchKernelGGL(k_d3_beads_minor, dim3((unsigned)((PN + 255) / 256)), dim3(256), 0, s, pos, w->posT, P, N);
+        hipLaunchKernelGGL(k_d3_cn, grid, block, 0, s, a);
+    }
+    {
+        ProfScope ps_(K_D3_PAIR, s);
+        hipLaunchKernelGGL(k_d3_pair, grid, block, 0, s, a);
+    }
+    {
+        ProfScope ps_(K_D3_CNFORCE, s);
+        hipLaunchKernelGGL(k_d3_cnforce, grid, block, 0, s, a);
+    }
+    {
+        ProfScope ps_(K_D3_REDUCE, s);
+        hipLaunchKernelGGL(k_d3_reduce, dim3(P, 10), dim3(256), 0, s, w->partE, w->partW,
+                           w->partW + (size_t)9 * P * w->nblk, w->nblk, a.accumulate, E, W);
+    }
+    NEP_HIP(hipGetLastError());
+    return NEP_OK;
+}

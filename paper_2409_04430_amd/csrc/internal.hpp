@@ -45,6 +45,7 @@ struct nep_model {
     int device = 0;
     int mlp = 0;               // NEP_MLP_FP32 or NEP_MLP_BF16_MFMA
     uint16_t *w0b = nullptr;   // BF16 W0 per species: [S][2][32][32], layouts [mu][v] and [v][mu]
+    bool cutoffs_only = false; // a cutoff descriptor for neighbour lists (no weights; owned by another handle)
 };
 
 namespace nep {
@@ -120,6 +121,7 @@ struct nep_nlist {
     // Centroid cell list (grown on demand): cell_cnt [ncell], cell_start [ncell+1], cell_atoms [N].
     int ncell_alloc = 0, ncell_total = 0;
     int32_t *cell_cnt = nullptr, *cell_start = nullptr, *cell_atoms = nullptr;
+    double rc_built[2] = {0.0, 0.0};   // cutoffs (radial, angular) of the last neighbor_build
     uint32_t *grid = nullptr;     // device-chosen grid record: 16 global words + kDevSysWords per system
     uint32_t *status = nullptr;   // [0] flags, [1] max radial union, [2] max angular union,
                                   // [3] max radial candidates, [4] spread (float bits), [5] rebuilds,
@@ -435,7 +437,8 @@ int32_t update_geometry(const nep_model *m, nep_nlist *nl, const double *boxes, 
 // Kernel timing (hipEvents around launches on the caller's stream), off by default.
 enum KernelId {
     K_FILL = 0, K_CENTROID, K_CANDIDATES, K_NLIST, K_MATERIALIZE,
-    K_DESCRIPTOR, K_FORCE_ANG, K_FORCE, K_REDUCE, K_TRPMD, K_MODES, K_OBS, K_BARO, K_RDF, K_NUM
+    K_DESCRIPTOR, K_FORCE_ANG, K_FORCE, K_REDUCE, K_TRPMD, K_MODES, K_OBS, K_BARO, K_RDF, K_D3_CN, K_D3_PAIR,
+    K_D3_CNFORCE, K_D3_REDUCE, K_NUM
 };
 struct ProfScope {
     int id;

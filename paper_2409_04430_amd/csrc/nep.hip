@@ -946,6 +946,7 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
                                        float *F, double *W, float *E_atom, float *W_atom, hipStream_t s)
 {
     if (!m || !nl || !ws || !boxes) return fail(NEP_ERR_INVALID_ARG, "nep_compute: null argument");
+    if (m->cutoffs_only) return fail(NEP_ERR_INVALID_ARG, "nep_compute: a list cutoff descriptor has no network");
     if (nl->P != P || nl->N != N || ws->P != P || ws->N != N || nl->S != m->hp.n_species || ws->S != m->hp.n_species ||
         ws->NA1 != m->hp.n_max_angular + 1 || nl->off != ws->off)
         return fail(NEP_ERR_INVALID_ARG, "nep_compute: P=%d N=%d do not match the list/workspace handles", P, N);
@@ -960,6 +961,9 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
     }
     if (!pos || !types || !F) return fail(NEP_ERR_INVALID_ARG, "nep_compute: null array");
     if (!nl->built) return fail(NEP_ERR_INVALID_ARG, "nep_compute: the neighbour lists were never built");
+    if (nl->rc_built[0] != m->hp.rc_radial || nl->rc_built[1] != m->hp.rc_angular)
+        return fail(NEP_ERR_INVALID_ARG, "nep_compute: the lists were built for cutoffs %g/%g, the model has %g/%g",
+                    nl->rc_built[0], nl->rc_built[1], m->hp.rc_radial, m->hp.rc_angular);
     for (int sy = 0; sy < nsys; ++sy)
         for (int k = 0; k < 9; ++k)
             if (boxes[9 * sy + k] != nl->boxL[9 * sy + k])

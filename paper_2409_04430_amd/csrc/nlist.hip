@@ -916,6 +916,8 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
     }
     NEP_HIP(hipGetLastError());
     nl->built = 1;
+    nl->rc_built[0] = m->hp.rc_radial;
+    nl->rc_built[1] = m->hp.rc_angular;
     return NEP_OK;
 }
 

@@ -509,6 +509,7 @@ struct nep_train_ws {
 extern "C" int32_t nep_train_ws_create(const nep_model *m, int32_t P, int32_t N, nep_train_ws **out)
 {
     if (!m || !out) return fail(NEP_ERR_INVALID_ARG, "nep_train_ws_create: null argument");
+    if (m->cutoffs_only) return fail(NEP_ERR_INVALID_ARG, "nep_train_ws_create: a list cutoff descriptor has no network");
     if (P < 1 || P > kMaxBeads || N < 1) return fail(NEP_ERR_INVALID_ARG, "nep_train_ws_create: bad sizes");
     const nep_hparams &h = m->hp;
     if (h.four_body) return fail(NEP_ERR_UNSUPPORTED, "nep_train_ws_create: four-body models are not trainable");
@@ -567,6 +568,7 @@ extern "C" int32_t nep_param_grad(const nep_model *m, nep_nlist *nl, nep_ws *ws,
 {
     if (!m || !nl || !ws || !tw || !lambda || !grad || !loss || !E_ref || !F_ref || !W_ref)
         return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: null argument");
+    if (m->cutoffs_only) return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: a list cutoff descriptor has no network");
     if (tw->P != P || tw->N != N || nl->nsys != 1)
         return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: sizes do not match the training workspace");
     if (m->mlp != NEP_MLP_FP32)
@@ -609,6 +611,7 @@ extern "C" int32_t nep_param_grad(const nep_model *m, nep_nlist *nl, nep_ws *ws,
 extern "C" int32_t nep_model_params(nep_model *m, float **params, int32_t *count, nep_param_offsets *off)
 {
     if (!m || !params || !count) return fail(NEP_ERR_INVALID_ARG, "nep_model_params: null argument");
+    if (m->cutoffs_only) return fail(NEP_ERR_INVALID_ARG, "nep_model_params: a list cutoff descriptor has no network");
     *params = m->dev;
     *count = m->off.total;
     if (off) {

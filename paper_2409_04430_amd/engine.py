@@ -65,7 +65,7 @@ class NepPimd:
                  mode: str = "trpmd", seed: int = 0, caps: Optional[tuple] = None, check_every: int = 50,
                  want_atom: bool = False, skin: float = 0.5, autotune: bool = False, obs_every: int = 0,
                  barostat: Optional[dict] = None, rdf: Optional[dict] = None, dump_every: int = 0,
-                 max_regrow: int = 8, regrow_budget_s: float = 300.0):
+                 max_regrow: int = 8, regrow_budget_s: float = 300.0, d3: Optional[str] = None):
         import torch
         self.torch = torch
         dev = torch.device("cuda")
@@ -129,6 +129,16 @@ class NepPimd:
         self.dump_log = []
         if self.dump_every and self.batched:
             raise ValueError("velocity dumps need a single system")
+        # D3 dispersion (NEP-D3): its own lists (dispersion / coordination cutoffs) on the same positions
+        self.d3 = lib.D3(d3) if d3 else None
+        self.d3_nl = None
+        self.d3_caps = None
+        if self.d3 is not None:
+            if self.batched:
+                raise ValueError("the D3 term needs a single system")
+            if self.d3.n_species != self.model.n_species:
+                raise ValueError("the D3 parameters and the model have different species counts")
+            self.d3_ws = self.d3.workspace(self.P, self.N)
         self.rollbacks = 0
         self.rebuilds_total = 0      # candidate-row rebuilds counted by the successful polls
         self.max_regrow = int(max_regrow)
@@ -167,11 +177,33 @@ class NepPimd:
             self.nl.set_skin(self.skin)
             self.nl.build(self.pos, self.box, self.types)
         self.caps = caps
+        if self.d3 is not None:
+            lm = self.d3.list_model
+            guess = (default_capacity(lm.rc_radial + self.skin + 1.0, self.density, 1),
+                     default_capacity(lm.rc_angular + self.skin + 1.0, self.density, 1))
+            self.d3_nl = lib.fitted_neighbor_list(lm, self.pos, self.box, self.types, *guess, skin=self.skin)
+            floor = (default_capacity(lm.rc_radial + self.skin + 2.0, self.density, 1, slack=1.3),
+                     default_capacity(lm.rc_angular + self.skin + 2.0, self.density, 1, slack=1.3))
+            d3c = tuple(max(a, b) for a, b in zip(self.d3_nl.caps, floor))
+            if d3c != tuple(self.d3_nl.caps):
+                self.d3_nl = self._d3_list(d3c)
+            self.d3_caps = d3c
+
+    def _d3_list(self, caps):
+        nl = lib.NeighborList(self.d3.list_model, self.P, self.N, *caps)
+        nl.set_skin(self.skin)
+        nl.build(self.pos, self.box, self.types)
+        return nl
 
     def forces(self):
-        """Neighbour lists + NEP energy, forces and virial at the current positions."""
+        """Neighbour lists + NEP energy, forces and virial at the current positions
+        (plus the D3 dispersion term when the engine has one)."""
         self.nl.build(self.pos, self.box, self.types)
         self.ws.compute(self.nl, self.pos, self.box, self.types, self.E, self.F, self.W, self.E_atom, self.W_atom)
+        if self.d3 is not None:
+            self.d3_nl.build(self.pos, self.box, self.types)
+            self.d3.compute(self.d3_nl, self.d3_ws, self.pos, self.box, self.types, self.E, self.F, self.W,
+                            accumulate=True)
 
     def check(self):
         """Poll the sticky flags (synchronises).  A candidate-row overflow since
@@ -185,16 +217,21 @@ class NepPimd:
             st = self.nl.status(clear=True)
             flags, mr, ma = st["flags"], st["max_union_radial"], st["max_union_angular"]
             wf = self.ws.poll(clear=True)
-            if not (flags & lib.FLAG_NEIGHBOR_OVERFLOW):
+            st3 = self.d3_nl.status(clear=True) if self.d3_nl is not None else None
+            if st3 is not None:
+                flags |= st3["flags"] & ~lib.FLAG_NEIGHBOR_OVERFLOW
+            over = bool(st["flags"] & lib.FLAG_NEIGHBOR_OVERFLOW)
+            over3 = st3 is not None and bool(st3["flags"] & lib.FLAG_NEIGHBOR_OVERFLOW)
+            if not (over or over3):
                 self.rebuilds_total += int(st["rebuilds"])
                 break
             spent = time.perf_counter() - t0
             if rounds >= self.max_regrow or spent > self.regrow_budget_s:
                 raise lib.NepError(5, f"candidate rows still overflow at step {self.step_no} after {rounds} "
-                                      f"regrowths in {spent:.1f} s: capacities {self.caps}, longest rows "
-                                      f"({st['max_cand_radial']}, {st['max_cand_angular']}), snapshot at step "
-                                      f"{self._snap['step_no']}")
-            self._grow_and_replay(st)
+                                      f"regrowths in {spent:.1f} s: capacities {self.caps} (D3 {self.d3_caps}), "
+                                      f"longest rows ({st['max_cand_radial']}, {st['max_cand_angular']}), "
+                                      f"snapshot at step {self._snap['step_no']}")
+            self._grow_and_replay(st if over else None, st3 if over3 else None)
             rounds += 1
         if (flags | wf) & lib.FLAG_NONFINITE:
             raise lib.NepError(6, "non-finite force or position")
@@ -215,14 +252,23 @@ class NepPimd:
                           rdf=None if self.rdf_hist is None else self.rdf_hist.clone(),
                           extra=[save() for save, _ in self.snapshot_hooks])
 
-    def _grow_and_replay(self, st):
+    @staticmethod
+    def _grown(caps, st):
         # rows found after an overflow may come from a state that truncated forces
         # spoiled: grow by at most 2x (a replay that still overflows grows again)
         need = (int(np.ceil(st["max_cand_radial"] * 1.25)) + 8, int(np.ceil(st["max_cand_angular"] * 1.25)) + 8)
-        self.caps = tuple(max(a + 1, min(b, 2 * a)) for a, b in zip(self.caps, need))
-        self.nl = lib.NeighborList(self.model, self.P, self.N, *self.caps,
-                                   offsets=self.offsets if self.batched else None)
-        self.nl.set_skin(self.skin)
+        return tuple(max(a + 1, min(b, 2 * a)) for a, b in zip(caps, need))
+
+    def _grow_and_replay(self, st, st3=None):
+        if st is not None:
+            self.caps = self._grown(self.caps, st)
+            self.nl = lib.NeighborList(self.model, self.P, self.N, *self.caps,
+                                       offsets=self.offsets if self.batched else None)
+            self.nl.set_skin(self.skin)
+        if st3 is not None:
+            self.d3_caps = self._grown(self.d3_caps, st3)
+            self.d3_nl = lib.NeighborList(self.d3.list_model, self.P, self.N, *self.d3_caps)
+            self.d3_nl.set_skin(self.skin)
         had_graph = self.graph is not None
         self.graph = None
         target = self.step_no
@@ -338,8 +384,7 @@ class NepPimd:
         t.cuda.synchronize()
         g = t.cuda.CUDAGraph()
         with t.cuda.graph(g):
-            self.nl.build(self.pos, self.box, self.types)
-            self.ws.compute(self.nl, self.pos, self.box, self.types, self.E, self.F, self.W, self.E_atom, self.W_atom)
+            self.forces()
             self.pimd.step_dev(self.pos, self.vel, self.F, self.step_dev, lib.FUSED)
         t.cuda.synchronize()
         # capture does not execute: the counter and the state are unchanged

@@ -125,6 +125,12 @@ _sig = {
                               C.POINTER(C.c_double), _vp, _vp, _vp]),
     "nep_adam_step": (_i32, [_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, _i32,
                              _vp]),
+    "nep_d3_load": (_i32, [C.c_char_p, C.POINTER(_vp)]),
+    "nep_d3_destroy": (None, [_vp]),
+    "nep_d3_list_model": (_i32, [_vp, C.POINTER(_vp)]),
+    "nep_d3_ws_create": (_i32, [_vp, _i32, _i32, C.POINTER(_vp)]),
+    "nep_d3_ws_destroy": (None, [_vp]),
+    "nep_d3_compute": (_i32, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, _vp, _vp, _vp, _i32, _vp]),
     "nep_profile_enable": (_i32, [_i32]),
     "nep_profile_select": (_i32, [_i32]),
     "nep_profile_num_kernels": (_i32, []),
@@ -587,6 +593,73 @@ class Trainer:
         h = getattr(self, "_h", None)
         if h and _lib is not None:
             _lib.nep_train_ws_destroy(h)
+            self._h = None
+
+
+class _ListModel:
+    """The cutoff descriptor of a D3 handle, usable where a NeighborList needs a model."""
+
+    def __init__(self, handle, owner, n_species: int, rc_radial: float, rc_angular: float):
+        self._h, self._owner = handle, owner
+        self.n_species, self.rc_radial, self.rc_angular = n_species, rc_radial, rc_angular
+        self.hp = {"n_species": n_species, "rc_radial": rc_radial, "rc_angular": rc_angular}
+
+    @property
+    def handle(self):
+        return self._h
+
+
+class D3:
+    """nep_d3_load / nep_d3_list_model / nep_d3_ws_create / nep_d3_compute."""
+
+    def __init__(self, path: str):
+        self._h = _vp()
+        _check(_lib.nep_d3_load(path.encode(), C.byref(self._h)))
+        mh = _vp()
+        _check(_lib.nep_d3_list_model(self._h, C.byref(mh)))
+        hp = HParams()
+        _check(_lib.nep_model_info(mh, C.byref(hp)))
+        self.list_model = _ListModel(mh, self, hp.n_species, hp.rc_radial, hp.rc_angular)
+        self.n_species, self.rc, self.rc_cn = hp.n_species, hp.rc_radial, hp.rc_angular
+        self.path = path
+
+    def workspace(self, P: int, N: int) -> "D3Workspace":
+        return D3Workspace(self, P, N)
+
+    def compute(self, nl: "NeighborList", ws: "D3Workspace", pos, box, types, E, F, W, accumulate: bool = False):
+        """E [P], F [P, N, 3], W [P, 9] (written, or added with accumulate) from lists nl of list_model."""
+        t = _torch()
+        P, N = ws.P, ws.N
+        _check(_lib.nep_d3_compute(self._h, nl.handle, ws.handle, _ptr(pos, t.float64, (P, N, 3), "pos"), _box9(box),
+                                   _ptr(types, t.int32, (N,), "types"), P, N, _ptr(E, t.float64, (P,), "E"),
+                                   _ptr(F, t.float32, (P, N, 3), "F"), _ptr(W, t.float64, (P, 9), "W"),
+                                   int(bool(accumulate)), _stream()))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.nep_d3_destroy(h)
+            self._h = None
+
+
+class D3Workspace:
+    def __init__(self, d3: D3, P: int, N: int):
+        self._h = _vp()
+        _check(_lib.nep_d3_ws_create(d3.handle, int(P), int(N), C.byref(self._h)))
+        self.d3, self.P, self.N = d3, int(P), int(N)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.nep_d3_ws_destroy(h)
             self._h = None
 
 
