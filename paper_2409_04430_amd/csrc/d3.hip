@@ -22,7 +22,8 @@
 // its angular one), so the per-bead pair sets are the exact FP64 decisions
 // of the union lists' bead masks.  Passes, one lane per (atom, bead), the
 // beads of an atom in adjacent lanes, gathers only (no atomics):
-//   k_d3_cn       CN_i over the coordination list;
+//   k_d3_cn       CN_i over the coordination list, and the atom's reference
+//                 weights, which its partners gather in the next pass;
 //   k_d3_pair     site energy, direct forces and virial over the dispersion
 //                 list, and dE/dCN_i = -sum_j (de_ij/dC6) dC6_ij/dCN_i;
 //   k_d3_cnforce  forces (dE/dCN_i + dE/dCN_j) c'(r) u_ij and virial
@@ -59,6 +60,7 @@ struct D3Args {
     const double *tab;
     double s6, s8, k1, k2, k3;
     double *cn, *dedcn, *fdir;   // [N][P], [N][P], [N][P][3]
+    double *wts;                 // [N][P][8]: reference weights L_0..4, their sum, its derivative (see ref_weights)
     double *partE, *partW0, *partW1;   // [P][nblk], [P][9][nblk] twice
     float *F;
     int accumulate;
@@ -173,6 +175,14 @@ __global__ __launch_bounds__(256) void k_d3_cn(D3Args a)
         cn += 1.0 / (1.0 + exp(a.k1 - kk * (Ri + t[kTRcov + tj]) / r));
     }
     a.cn[(size_t)i * P + b] = cn;
+    // this atom's reference weights, gathered by every partner in the pair pass
+    double L[kD3Ref], dL[kD3Ref], sL, sdL;
+    ref_weights(t, ti, cn, a.k3, L, dL, sL, sdL);
+    double2 *wo = reinterpret_cast<double2 *>(a.wts + ((size_t)i * P + b) * 8);
+    wo[0] = make_double2(L[0], L[1]);
+    wo[1] = make_double2(L[2], L[3]);
+    wo[2] = make_double2(L[4], sL);
+    wo[3] = make_double2(sdL, 0.0);
 }
 
 // ------------------------------------------- dispersion pairs, dE/dCN ---
@@ -188,7 +198,7 @@ __global__ __launch_bounds__(256) void k_d3_pair(D3Args a)
     const int P = a.P, S = a.S, ti = a.types[i] & 3;
     const double *ri = a.posT + ((size_t)i * P + b) * 3;
     double Li[kD3Ref], dLi[kD3Ref], sLi, sdLi;
-    ref_weights(t, ti, a.cn[(size_t)i * P + b], a.k3, Li, dLi, sLi, sdLi);
+    ref_weights(t, ti, a.cn[(size_t)i * P + b], a.k3, Li, dLi, sLi, sdLi);   // with derivatives (once per lane)
     double U = 0.0, dE = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
     double Wv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // xx yy zz xy xz yz (symmetric)
     const int32_t *uR = a.uniR + (size_t)i * a.capR;
@@ -204,8 +214,12 @@ __global__ __launch_bounds__(256) void k_d3_pair(D3Args a)
             double dx, dy, dz;
             d3_pair_vec(a.posT + ((size_t)j * P + b) * 3, ri, g, dx, dy, dz);
             const double r2 = dx * dx + dy * dy + dz * dz;
-            double Lj[kD3Ref], dLj[kD3Ref], sLj, sdLj;
-            ref_weights(t, tj, a.cn[(size_t)j * P + b], a.k3, Lj, dLj, sLj, sdLj);
+            // the partner's weights from the coordination pass (the same
+            // arithmetic as ref_weights here; its derivative is not needed)
+            const double2 *wj = reinterpret_cast<const double2 *>(a.wts + ((size_t)j * P + b) * 8);
+            const double2 w01 = wj[0], w23 = wj[1], w4s = wj[2];
+            const double Lj[kD3Ref] = {w01.x, w01.y, w23.x, w23.y, w4s.x};
+            const double sLj = w4s.y;
             double Z = 0.0, dZ = 0.0;
 #pragma unroll
             for (int ra = 0; ra < kD3Ref; ++ra) {
@@ -355,6 +369,7 @@ struct nep_d3_ws {
     int P = 0, N = 0, nblk = 0, lg = 0;
     int device = 0;
     double *posT = nullptr;                      // [N][P][3] bead-minor positions
+    double *wts = nullptr;                       // [N][P][8] reference weights of each (atom, bead)
     double *cn = nullptr, *dedcn = nullptr, *fdir = nullptr;
     double *partE = nullptr, *partW = nullptr;   // [P][nblk], 2 x [P][9][nblk]
 };
@@ -475,14 +490,15 @@ extern "C" int32_t nep_d3_ws_create(const nep_d3 *d, int32_t P, int32_t N, nep_d
     const size_t PN = (size_t)(P > 0 ? P : 1) * (N > 0 ? N : 1), Pp = P > 0 ? P : 1;
     hipError_t e = hipGetDevice(&w->device);
     if (e == hipSuccess) e = hipMalloc((void **)&w->posT, sizeof(double) * 3 * PN);
+    if (e == hipSuccess) e = hipMalloc((void **)&w->wts, sizeof(double) * 8 * PN);
     if (e == hipSuccess) e = hipMalloc((void **)&w->cn, sizeof(double) * PN);
     if (e == hipSuccess) e = hipMalloc((void **)&w->dedcn, sizeof(double) * PN);
     if (e == hipSuccess) e = hipMalloc((void **)&w->fdir, sizeof(double) * 3 * PN);
     if (e == hipSuccess) e = hipMalloc((void **)&w->partE, sizeof(double) * Pp * w->nblk);
     if (e == hipSuccess) e = hipMalloc((void **)&w->partW, sizeof(double) * 2 * 9 * Pp * w->nblk);
     if (e != hipSuccess) {
-        for (void *p : {(void *)w->posT, (void *)w->cn, (void *)w->dedcn, (void *)w->fdir, (void *)w->partE,
-                        (void *)w->partW})
+        for (void *p : {(void *)w->posT, (void *)w->wts, (void *)w->cn, (void *)w->dedcn, (void *)w->fdir,
+                        (void *)w->partE, (void *)w->partW})
             if (p) (void)hipFree(p);
         delete w;
         return fail(e == hipErrorOutOfMemory ? NEP_ERR_NOMEM : NEP_ERR_HIP, "nep_d3_ws_create: %s",
@@ -495,8 +511,8 @@ extern "C" int32_t nep_d3_ws_create(const nep_d3 *d, int32_t P, int32_t N, nep_d
 extern "C" void nep_d3_ws_destroy(nep_d3_ws *w)
 {
     if (!w) return;
-    for (void *p : {(void *)w->posT, (void *)w->cn, (void *)w->dedcn, (void *)w->fdir, (void *)w->partE,
-                    (void *)w->partW})
+    for (void *p : {(void *)w->posT, (void *)w->wts, (void *)w->cn, (void *)w->dedcn, (void *)w->fdir,
+                    (void *)w->partE, (void *)w->partW})
         if (p) (void)hipFree(p);
     delete w;
 }
@@ -536,7 +552,7 @@ extern "C" int32_t nep_d3_compute(const nep_d3 *d, nep_nlist *nl, nep_d3_ws *w, 
     a.umR = nl->umR; a.umA = nl->umA; a.capR = nl->capR; a.capA = nl->capA;
     a.tab = d->dev;
     a.s6 = d->s6; a.s8 = d->s8; a.k1 = d->k1; a.k2 = d->k2; a.k3 = d->k3;
-    a.cn = w->cn; a.dedcn = w->dedcn; a.fdir = w->fdir;
+    a.cn = w->cn; a.dedcn = w->dedcn; a.fdir = w->fdir; a.wts = w->wts;
     a.partE = w->partE; a.partW0 = w->partW; a.partW1 = w->partW + (size_t)9 * P * w->nblk;
     a.F = F;
     a.accumulate = accumulate ? 1 : 0;
