@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--cpu-beads", type=int, default=0, help="oracle sample size in beads (0: auto)")
     ap.add_argument("--graph", action="store_true",
                     help="time replays of the captured step graph instead of eager launches")
+    ap.add_argument("--graph-steps", type=int, default=10, help="steps captured per graph replay (even)")
+    ap.add_argument("--mlp", default="auto", choices=["auto", "fp32", "fp32_mfma"],
+                    help="network arithmetic of the timed model: FP32 vector units, FP32 weights as three "
+                         "BF16 terms on the matrix cores, or the library's choice for the model's shape")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--no-profile", action="store_true", help="do not bracket kernels with timing events")
@@ -375,6 +379,8 @@ def student_leg(args, torch, lib, configs, I):
     teacher.run(5)
     ms_t = timed(teacher, max(10, n // 2))
     teacher.check()
+    teacher_net = {"fp32": "FP32 network on the vector units",
+                   "fp32_mfma": "FP32 network (weights as three BF16 terms) on the matrix cores"}[teacher.mlp]
     del teacher
     student = StudentPimd(tpath, trained, big, dt=w.dt, T=T, tau=w.tau_T, mode=w.mode, seed=w.seed,
                           judge_every=50, threshold=0.020)
@@ -385,7 +391,7 @@ def student_leg(args, torch, lib, configs, I):
     return {
         "workload": f"fcc32000_p{P}", "atoms": big.N, "beads": P, "T_K": T, "mode": w.mode, "dt_fs": w.dt,
         "teacher": {"value": round(units / (ms_t * 1e-3), 1), "ms_per_step": round(ms_t, 4),
-                    "model": "n_max 8/8, l_max 4 + four-body, 100 hidden, FP32 network"},
+                    "model": "n_max 8/8, l_max 4 + four-body, 100 hidden, " + teacher_net},
         "student": {"value": round(units / (ms_s * 1e-3), 1), "ms_per_step": round(ms_s, 4),
                     "model": "n_max 4/4, l_max 4, 30 hidden, BF16 MFMA network",
                     "judge_every": 50, "threshold_meV_A": 20.0,
@@ -458,6 +464,9 @@ def roofline(dom, avg_us, hp, nR, nA, units, byts):
             "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "kernel": dom, "avg_us": round(avg_us, 2)}
 
 
+GRAPH_STEPS = 10   # steps per graph replay (set from --graph-steps)
+
+
 def timed_steps(torch, eng, steps: int, graph: bool):
     """(GPU ms per step, wall s, candidate rebuilds) of `steps` whole steps with
     inputs resident, bracketed by synchronisations; the polls before and after
@@ -465,7 +474,7 @@ def timed_steps(torch, eng, steps: int, graph: bool):
     region is timed again)."""
     stream = torch.cuda.current_stream()
     if graph and eng.graph is None:
-        eng.capture()
+        eng.capture(GRAPH_STEPS)
     for _attempt in range(3):
         eng.check()
         rb0 = eng.rollbacks
@@ -485,13 +494,13 @@ def timed_steps(torch, eng, steps: int, graph: bool):
     return ev0.elapsed_time(ev1) / steps, wall, rebuilds, (mr, ma)
 
 
-def full_run_leg(torch, lib, w, model_path, s, NepPimd):
+def full_run_leg(torch, lib, w, model_path, s, NepPimd, mlp="fp32"):
     """The configured run length from the initial structure: polls every 50
     steps, mean ms per step over the whole run (polls included), candidate
     rebuilds, capacity regrowths, neighbour counts at the start and the end
     and the centroid mean squared displacement."""
     eng = NepPimd(model_path, s, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=50,
-                  regrow_budget_s=120.0)
+                  regrow_budget_s=120.0, mlp=mlp)
     eng.forces()
     nR0, nA0, _, _ = list_stats(eng)
     c0 = eng.pos.mean(dim=0)
@@ -542,7 +551,7 @@ def workload_leg(args, torch, lib, configs, I, NepPimd, name: str, steps: int, g
     ms, wall, rb, _ = timed_steps(torch, eng, steps, False)
     out = {"workload": f"{name}_p{P}", "systems": len(systems), "atoms": N, "beads": P, "steps": steps,
            "ms_per_step": round(ms, 4), "value": round(units / (ms * 1e-3), 1), "rebuilds_timed": rb,
-           "mean_neighbours": [round(nR, 2), round(nA, 2)],
+           "mean_neighbours": [round(nR, 2), round(nA, 2)], "network": eng.mlp,
            "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
            "roofline": roofline(dom, dom_us, hp, nR, nA, units, bytes_per_atom(hp, nR, nA, P, cR, cA))}
     if eng.tile is not None:
@@ -551,6 +560,7 @@ def workload_leg(args, torch, lib, configs, I, NepPimd, name: str, steps: int, g
     if graph:
         gms, _, grb, _ = timed_steps(torch, eng, steps, True)
         out["graph_ms_per_step"] = round(gms, 4)
+        out["graph_steps_per_replay"] = GRAPH_STEPS
         out["graph_value"] = round(units / (gms * 1e-3), 1)
         out["graph_rebuilds_timed"] = grb
         eng.release()
@@ -604,7 +614,9 @@ def d3_leg(args, torch, lib, configs, I, NepPimd, steps: int):
 
 
 def main():
+    global GRAPH_STEPS
     args = parse()
+    GRAPH_STEPS = args.graph_steps
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding is a "
               f"design note, not an implementation", file=sys.stderr)
@@ -637,7 +649,8 @@ def main():
 
     # warm-up polled every 50 steps (an overflow replays one window at most);
     # no polls inside the timed region
-    eng = NepPimd(model_path, s, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=50)
+    eng = NepPimd(model_path, s, dt=w.dt, T=w.T, tau=w.tau_T, mode=w.mode, seed=w.seed, check_every=50,
+                  mlp=args.mlp)
     eng.run(args.warmup)
     eng.check()
     eng.check_every = 0
@@ -688,9 +701,18 @@ def main():
     step_gbs = step_bytes / (ms * 1e-3) / 1e9
     step_hbm = {"algorithmic_bytes": int(step_bytes), "GB/s": round(step_gbs, 1),
                 "hbm_frac": round(step_gbs / PEAK_HBM_GBS, 4)}
+    # the other network arithmetic on the same engine and steps
+    timed_mlp = eng.mlp
+    other_mlp = "fp32_mfma" if timed_mlp == "fp32" else "fp32"
+    eng.model.set_mlp(lib.MLP_MODES[other_mlp])
+    ok_ = kernel_profile(torch, lib, eng, 5) if not args.no_profile else {}
+    oms = timed_steps(torch, eng, max(20, min(100, args.steps)), False)[0]
+    net_cmp = {"mlp": other_mlp, "ms_per_step": round(oms, 4), "value": round(s.N * s.P / (oms * 1e-3), 1),
+               "descriptor_us": round(ok_["descriptor"]["avg_us"], 2) if "descriptor" in ok_ else None,
+               "vs_timed": round(oms / ms, 4)}
     del eng
 
-    full = None if args.no_full_run else full_run_leg(torch, lib, w, model_path, s, NepPimd)
+    full = None if args.no_full_run else full_run_leg(torch, lib, w, model_path, s, NepPimd, args.mlp)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, model_path, s, args.cpu_beads)
@@ -732,11 +754,13 @@ def main():
                                  "pair terms FP32",
                    "wall_s": round(wall, 4), "launch": "hipGraph replay" if args.graph else "eager",
                    ("eager_ms_per_step" if args.graph else "graph_ms_per_step"): round(other, 4),
+                   "graph_steps_per_replay": args.graph_steps,
                    "candidate_rebuilds_timed": rebuilds, "capacity_regrowths": regrowths},
         "roofline": roof,
         "kernels_roofline": per_kernel,
         "step_hbm": step_hbm,
         "kernels_us": {k: round(v["avg_us"], 2) for k, v in kernels.items()},
+        "network_arithmetic": {"asked": args.mlp, "timed": timed_mlp, "other": net_cmp},
         "full_run": full,
         "cpu_baseline": cpu,
         "legs": legs,

@@ -121,21 +121,35 @@ void nep_model_destroy(nep_model *model);
 /* Arithmetic of the per-atom network (Sec. II.C) in nep_compute. */
 enum nep_mlp_mode {
     NEP_MLP_FP32 = 0,       /* FP32 vector arithmetic (default) */
-    NEP_MLP_BF16_MFMA = 1   /* BF16 weights on the matrix cores, FP32 accumulate */
+    NEP_MLP_BF16_MFMA = 1,  /* BF16 weights on the matrix cores, FP32 accumulate */
+    NEP_MLP_FP32_MFMA = 2,  /* FP32 weights as three BF16 terms on the matrix cores, FP32 accumulate */
+    NEP_MLP_FP32_AUTO = 3   /* FP32 accuracy, the faster of the two forms for this model's shape */
 };
 
-/* Select the network arithmetic used by nep_compute.  NEP_MLP_BF16_MFMA
- * evaluates the hidden layer and its adjoint as [64 x D] x [D x H] and
- * [64 x H] x [H x D] matrix-core products per wavefront of (atom, bead)
- * rows: W0 is rounded to the nearest BF16 value (ties to even) from the
- * model's FP32 weights, activations enter exactly (each as a sum of three
- * BF16 terms), products accumulate in FP32.  It needs D <= 32 and H <= 32
- * (NEP_ERR_UNSUPPORTED otherwise).  The BF16 copy is taken now, on
- * `stream`, from the current device weights: call again after the weights
- * change (nep_adam_step).  Not for concurrent use with nep_compute on
- * another stream.  Errors: NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED,
- * NEP_ERR_HIP. */
+/* Select the network arithmetic used by nep_compute (Sec. II.C network,
+ * batched over the (atom, bead) rows of a wavefront as [64 x D] x [D x H]
+ * and [64 x H] x [H x D] products on the matrix cores, 16 x 16 x 32 BF16
+ * tiles with FP32 accumulation; activations enter exactly, each as a sum
+ * of three BF16 terms).  NEP_MLP_BF16_MFMA: W0 rounded to the nearest BF16
+ * value (ties to even).  NEP_MLP_FP32_MFMA: W0 as three BF16 terms whose sum
+ * is the FP32 weight exactly; of the nine term products the six largest are
+ * kept (each dropped one is below 2^-22 of its full product), so the result
+ * has FP32 accuracy.  Both need D <= 64 and H <= 128 (NEP_ERR_UNSUPPORTED
+ * otherwise).  NEP_MLP_FP32_AUTO resolves, from the shape alone, to
+ * NEP_MLP_FP32_MFMA for models with more than five angular radial functions
+ * (n_max_angular >= 5) whose network fits the tiles, and to NEP_MLP_FP32
+ * otherwise: with at most five, nep_compute keeps the angular sums A_nlm in
+ * registers through a vector-unit network, which the matrix-core network
+ * cannot afford.  The operand copy is taken now, on `stream`, from the
+ * current device weights: call again after the weights change
+ * (nep_adam_step).  Not for concurrent use with nep_compute on another
+ * stream.  Errors: NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED, NEP_ERR_HIP. */
 int32_t nep_model_set_mlp(nep_model *model, int32_t mode, hipStream_t stream);
+
+/* The network arithmetic in use (*mode, host): NEP_MLP_FP32,
+ * NEP_MLP_BF16_MFMA or NEP_MLP_FP32_MFMA, never NEP_MLP_FP32_AUTO.  Errors:
+ * NEP_ERR_INVALID_ARG. */
+int32_t nep_model_mlp(const nep_model *model, int32_t *mode);
 
 /* ------------------------------------------------------------------ */
 /* Neighbour lists (per bead, minimum image, cell list)                */
@@ -390,12 +404,16 @@ int32_t rp_normal_modes(const pimd_ctx *ctx, int32_t dir, const double *in, doub
 int32_t trpmd_step(const pimd_ctx *ctx, double *pos, double *vel, const float *F, int64_t step, int32_t stage,
                    hipStream_t stream);
 
-/* trpmd_step with the step number read from device memory (*step, int64)
- * at launch time; after a POST or FUSED stage the counter is advanced by one
- * on the stream.  For graph capture: a captured step replays with fresh
- * noise.  Errors as trpmd_step, and NEP_ERR_INVALID_ARG for a null counter. */
-int32_t trpmd_step_dev(const pimd_ctx *ctx, double *pos, double *vel, const float *F, int64_t *step,
-                       int32_t stage, hipStream_t stream);
+/* trpmd_step with the step number read from device memory (*step_in, int64)
+ * by the launch itself; a POST or FUSED stage also writes step + 1 to
+ * *step_out (dev int64, another word than step_in: the launch's workgroups
+ * all read step_in), so consecutive steps alternate two counters and no
+ * extra launch advances them.  For graph capture: captured steps replay with
+ * fresh noise (an even number of captured steps returns the count to the
+ * first counter).  step_out is ignored for PRE.  Errors as trpmd_step, and
+ * NEP_ERR_INVALID_ARG for a null counter or step_out == step_in. */
+int32_t trpmd_step_dev(const pimd_ctx *ctx, double *pos, double *vel, const float *F, const int64_t *step_in,
+                       int64_t *step_out, int32_t stage, hipStream_t stream);
 
 /* ------------------------------------------------------------------ */
 /* Observables and pressure control (Sec. II.A, Sec. II.D)             */
@@ -582,7 +600,7 @@ void nep_train_ws_destroy(nep_train_ws *tw);
  * c_radial and c_angular (other entries untouched); loss [4] (device) is
  * accumulated: total, energy, force and virial parts.  The force and virial
  * parts enter as mixed derivatives through a forward-mode pass of the
- * descriptor along the residual field.  The model must use the FP32 network
+ * descriptor along the residual field.  The model must use FP32 weights
  * (NEP_ERR_INVALID_ARG after nep_model_set_mlp(NEP_MLP_BF16_MFMA)).  Errors
  * as nep_compute. */
 int32_t nep_param_grad(const nep_model *model, nep_nlist *nl, nep_ws *ws, nep_train_ws *tw, const double *pos,

@@ -416,43 +416,104 @@ extern "C" void nep_model_destroy(nep_model *m)
     delete m;
 }
 
-// BF16 copies of the first-layer weights for the matrix-core network: each
-// FP32 weight rounded to the nearest BF16 value (ties to even mantissa),
-// zero-padded to 32 x 32 per species, once as [mu][v] (operand of the
-// forward product) and once as [v][mu] (operand of the adjoint product).
-__global__ void k_w0_bf16(const float *__restrict__ W0, int S, int H, int D, uint16_t *__restrict__ out)
+// First-layer weights as matrix-core operand fragments (16 x 16 x 32 BF16
+// tiles; see mlp_frag_layout).  NEP_MLP_BF16_MFMA: one term per weight, the
+// FP32 weight rounded to the nearest BF16 value (ties to even).
+// NEP_MLP_FP32_MFMA: three terms whose sum is the FP32 weight exactly (the
+// top 8 significant bits by truncation, then the top 8 of the remainder,
+// then the rest, at most 8 bits).  Entry (species, term, block, lane, e):
+//   forward block (ht, kc): W0[16 ht + lane % 16][32 kc + 8 (lane / 16) + e]
+//   adjoint block (dt, hc): W0[mu][16 dt + lane % 16] with
+//       mu = 32 hc + 4 (lane / 16) + e (e < 4), 32 hc + 16 + 4 (lane / 16) + e - 4 (e >= 4)
+// zero outside the model's H x D weights.
+__device__ __forceinline__ uint16_t bf16_term(float x, int term, int wt)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= S * 1024) return;
-    const int s = t >> 10, mu = (t >> 5) & 31, v = t & 31;
-    uint16_t r = 0;
-    if (mu < H && v < D) {
-        const uint32_t u = __float_as_uint(W0[(size_t)s * H * D + mu * D + v]);
-        r = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+    if (wt == 1) {
+        const uint32_t u = __float_as_uint(x);
+        return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
     }
-    out[(size_t)s * 2048 + mu * 32 + v] = r;
-    out[(size_t)s * 2048 + 1024 + v * 32 + mu] = r;
+    float r = x;
+    uint32_t part = 0;
+    for (int k = 0; k <= term; ++k) {
+        part = __float_as_uint(r) & 0xffff0000u;
+        r -= __uint_as_float(part);
+    }
+    return (uint16_t)(part >> 16);
+}
+
+__global__ void k_w0_frag(const float *__restrict__ W0, int S, int H, int D, int wt, MlpFrag fl,
+                          uint16_t *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int per_term = fl.fwd_blocks + fl.adj_blocks;
+    const int64_t total = (int64_t)S * wt * per_term * 512;
+    if (t >= total) return;
+    const int e = (int)(t & 7), lane = (int)((t >> 3) & 63);
+    int64_t rest = t >> 9;
+    const int blk = (int)(rest % per_term);
+    rest /= per_term;
+    const int term = (int)(rest % wt), s = (int)(rest / wt);
+    int mu, v;
+    if (blk < fl.fwd_blocks) {
+        const int ht = blk / fl.KC, kc = blk - ht * fl.KC;
+        mu = 16 * ht + (lane & 15);
+        v = 32 * kc + 8 * (lane >> 4) + e;
+    } else {
+        const int b2 = blk - fl.fwd_blocks, dt = b2 / fl.HC, hc = b2 - dt * fl.HC;
+        const int g = lane >> 4;
+        mu = 32 * hc + (e < 4 ? 4 * g + e : 16 + 4 * g + e - 4);
+        v = 16 * dt + (lane & 15);
+    }
+    const float w = (mu < H && v < D) ? W0[(size_t)s * H * D + (size_t)mu * D + v] : 0.0f;
+    out[t] = bf16_term(w, term, wt);
 }
 
 extern "C" int32_t nep_model_set_mlp(nep_model *m, int32_t mode, hipStream_t s)
 {
     if (!m) return fail(NEP_ERR_INVALID_ARG, "nep_model_set_mlp: null model");
     if (m->cutoffs_only) return fail(NEP_ERR_INVALID_ARG, "nep_model_set_mlp: a list cutoff descriptor has no network");
+    const nep_hparams &h = m->hp;
+    if (mode == NEP_MLP_FP32_AUTO) {
+        // k_descriptor keeps the angular sums of up to five radial functions
+        // in registers through a vector-unit network; the matrix-core network
+        // needs those registers and parks the sums in memory, which pays only
+        // where they are parked either way
+        const bool fits = h.dim <= 64 && h.hidden <= 128;
+        mode = (fits && h.n_max_angular + 1 > 5) ? NEP_MLP_FP32_MFMA : NEP_MLP_FP32;
+    }
     if (mode == NEP_MLP_FP32) {
         m->mlp = mode;
         return NEP_OK;
     }
-    if (mode != NEP_MLP_BF16_MFMA) return fail(NEP_ERR_INVALID_ARG, "nep_model_set_mlp: unknown mode %d", mode);
-    const nep_hparams &h = m->hp;
-    if (h.dim > 32 || h.hidden > 32)
-        return fail(NEP_ERR_UNSUPPORTED, "nep_model_set_mlp: the matrix-core network needs D <= 32 and H <= 32 "
+    if (mode != NEP_MLP_BF16_MFMA && mode != NEP_MLP_FP32_MFMA)
+        return fail(NEP_ERR_INVALID_ARG, "nep_model_set_mlp: unknown mode %d", mode);
+    if (h.dim > 64 || h.hidden > 128)
+        return fail(NEP_ERR_UNSUPPORTED, "nep_model_set_mlp: the matrix-core network needs D <= 64 and H <= 128 "
                                          "(model has D = %d, H = %d)", h.dim, h.hidden);
-    if (!m->w0b) NEP_HIP(hipMalloc(&m->w0b, sizeof(uint16_t) * 2048 * (size_t)h.n_species));
-    const int n = h.n_species * 1024;
-    hipLaunchKernelGGL(k_w0_bf16, dim3((n + 255) / 256), dim3(256), 0, s, m->dev + m->off.W0, h.n_species, h.hidden,
-                       h.dim, m->w0b);
+    const int wt = mode == NEP_MLP_FP32_MFMA ? 3 : 1;
+    const MlpFrag fl = mlp_frag_layout(h.dim, h.hidden, wt);
+    const size_t n = (size_t)h.n_species * fl.species_stride;
+    if (m->w0b && m->w0b_len < n) {
+        (void)hipFree(m->w0b);
+        m->w0b = nullptr;
+        m->w0b_len = 0;
+    }
+    if (!m->w0b) {
+        NEP_HIP(hipMalloc(&m->w0b, sizeof(uint16_t) * n));
+        m->w0b_len = n;
+    }
+    hipLaunchKernelGGL(k_w0_frag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, m->dev + m->off.W0,
+                       h.n_species, h.hidden, h.dim, wt, fl, m->w0b);
     NEP_HIP(hipGetLastError());
     m->mlp = mode;
+    return NEP_OK;
+}
+
+extern "C" int32_t nep_model_mlp(const nep_model *m, int32_t *mode)
+{
+    if (!m || !mode) return fail(NEP_ERR_INVALID_ARG, "nep_model_mlp: null argument");
+    if (m->cutoffs_only) return fail(NEP_ERR_INVALID_ARG, "nep_model_mlp: a list cutoff descriptor has no network");
+    *mode = m->mlp;
     return NEP_OK;
 }
 

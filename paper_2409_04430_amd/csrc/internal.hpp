@@ -44,9 +44,38 @@ struct nep_model {
     float *dev = nullptr;      // device copy
     int device = 0;
     int mlp = 0;               // NEP_MLP_FP32 or NEP_MLP_BF16_MFMA
-    uint16_t *w0b = nullptr;   // BF16 W0 per species: [S][2][32][32], layouts [mu][v] and [v][mu]
+    uint16_t *w0b = nullptr;   // W0 as matrix-core operand fragments (nep::MlpFrag layout), BF16 terms
+    size_t w0b_len = 0;        // elements allocated at w0b
     bool cutoffs_only = false; // a cutoff descriptor for neighbour lists (no weights; owned by another handle)
 };
+
+namespace nep {
+// Fragment layout of the matrix-core network's first-layer weights, per
+// species and BF16 term: forward blocks (ht, kc) for ht < HT = 2 HC and
+// kc < KC = DP / 32, then adjoint blocks (dt, hc) for dt < DT = DP / 16 and
+// hc < HC = ceil(H / 32); 512 entries (64 lanes x 8) per block.  DP = 32
+// for D <= 32, else 64.
+struct MlpFrag {
+    int DP, KC, DT, HC, HT, wt;
+    int fwd_blocks, adj_blocks;
+    int term_stride, species_stride;   // entries
+};
+__host__ __device__ inline MlpFrag mlp_frag_layout(int D, int H, int wt)
+{
+    MlpFrag f;
+    f.DP = D <= 32 ? 32 : 64;
+    f.KC = f.DP / 32;
+    f.DT = f.DP / 16;
+    f.HC = (H + 31) / 32;
+    f.HT = 2 * f.HC;
+    f.wt = wt;
+    f.fwd_blocks = f.HT * f.KC;
+    f.adj_blocks = f.DT * f.HC;
+    f.term_stride = (f.fwd_blocks + f.adj_blocks) * 512;
+    f.species_stride = wt * f.term_stride;
+    return f;
+}
+}  // namespace nep
 
 namespace nep {
 // Geometry of one system of a batch (device copy in the list handle).

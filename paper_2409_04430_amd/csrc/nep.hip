@@ -29,8 +29,6 @@ namespace nep {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-constexpr int kMfLd = 36;                       // LDS row stride (floats) of the staged tiles
-constexpr int kMfWave = 2 * 64 * kMfLd;         // floats of LDS per wavefront
 
 // Orders this wavefront's LDS writes before its later LDS reads (LDS
 // operations of one wavefront complete in issue order).
@@ -44,9 +42,8 @@ __device__ __forceinline__ void wave_lds_sync()
 // Eight FP32 values as three BF16 vectors whose sum is exact: truncation
 // keeps the top 8 significant bits, the remainder's top 8 bits follow, and
 // the last remainder has at most 8 significant bits left.
-__device__ __forceinline__ void split3(const float4 x0, const float4 x1, bf16x8 &hi, bf16x8 &mid, bf16x8 &lo)
+__device__ __forceinline__ void split3(const float (&x)[8], bf16x8 &hi, bf16x8 &mid, bf16x8 &lo)
 {
-    const float x[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const uint32_t u0 = __float_as_uint(x[e]) & 0xffff0000u;
@@ -59,110 +56,187 @@ __device__ __forceinline__ void split3(const float4 x0, const float4 x1, bf16x8 
     }
 }
 
-__device__ __forceinline__ f32x4 mfma3(const bf16x8 &hi, const bf16x8 &mid, const bf16x8 &lo, const bf16x8 &w, f32x4 c)
+// C += A B over the BF16 terms of both operands: A (weights) with WT terms,
+// B (activations) with three.  WT = 1: the three products; WT = 3: the six
+// products of term indices i + j <= 2 (a dropped product is below 2^-22 of
+// the full one).
+template <int WT>
+__device__ __forceinline__ f32x4 mfma_terms(const bf16x8 (&a)[WT], const bf16x8 (&b)[3], f32x4 c)
 {
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi, w, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mid, w, c, 0, 0, 0);
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, w, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], c, 0, 0, 0);
+    if constexpr (WT == 3) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], c, 0, 0, 0);
+    }
     return c;
 }
 
-// The network of the wavefront's 64 (atom, bead) rows on the matrix cores
-// (16 x 16 x 32 BF16 tiles, FP32 accumulate):
-//   Z = Qh W0^T,  h = tanh(Z - b0),  U = h w1 - b1,  G = (w1 (1 - h^2)) W0,
-// with Qh the scaled descriptors of each lane's own row (zero rows for lanes
-// outside the current species) and W0 the BF16 copy [S][2][32][32].  Tile
-// layout: operand element (row r, k) in lane r + 16 (k / 8), slot k % 8;
-// result (row r, col c) in lane c + 16 (r / 4), slot r % 4.  X and Y are
-// this wavefront's two 64 x kMfLd LDS tiles.  Returns U of the lane's row,
-// G (without the descriptor scale) in G[0..D).
-template <int D>
-__device__ float mlp_mfma(const float (&qh)[D], bool mine, const uint16_t *__restrict__ w0b, const float *b0,
-                          const float *w1, float b1, int H, float *X, float *Y, float (&G)[D])
+// tanh and its slope, both to a few units in the last place over the whole
+// range.  With a = |z| and r = 2 / (exp(2 a) + 1) in (0, 1]:
+// |tanh z| = 1 - r and 1 - tanh^2 z = r (2 - r), free of cancellation for
+// a >= 1/2 (r <= 0.54) and, for the slope, everywhere (exp saturates to inf
+// for large a, so r = 0).  Below a = 1/2, tanh z = z f(z^2) with f the
+// Maclaurin series of tanh(z) / z, whose coefficients are
+// 2^2k (2^2k - 1) B_2k / (2k)! (B the Bernoulli numbers); through z^15 the
+// series is exact to 1e-8 relative there.
+__device__ __forceinline__ void tanh_and_slope(float z, float &h, float &dh)
 {
-    const int l = threadIdx.x & 63, lr = l & 15, lk = (l >> 4) * 8;
+    const float a = fabsf(z);
+    const float r = 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * a) + 1.0f);
+    dh = r * (2.0f - r);
+    const float t = z * z;
+    float f = -929569.0f / 638512875.0f;
+    f = fmaf(f, t, 21844.0f / 6081075.0f);
+    f = fmaf(f, t, -1382.0f / 155925.0f);
+    f = fmaf(f, t, 62.0f / 2835.0f);
+    f = fmaf(f, t, -17.0f / 315.0f);
+    f = fmaf(f, t, 2.0f / 15.0f);
+    f = fmaf(f, t, -1.0f / 3.0f);
+    f = fmaf(f, t, 1.0f);
+    h = a < 0.5f ? z * f : copysignf(1.0f - r, z);
+}
+
+// The network of the wavefront's 64 (atom, bead) rows on the matrix cores,
+// as transposed products: Z^T = W0 Qh^T (A operand = weights, rows = hidden
+// units; B operand = the scaled descriptors, columns = rows of the batch),
+// h = tanh(Z - b0), U = w1 . h - b1, and G^T = W0^T (w1 (1 - h^2))^T.  The
+// hidden units of a forward result tile sit in the lanes exactly where the
+// adjoint product takes them as its B operand (its K order is permuted to
+// match, in the weight fragments), so the hidden layer never leaves
+// registers.  Qh is staged once in this wavefront's LDS tile X (64 rows of
+// XS floats); each row's G and U are written back over it.  Zero rows for
+// lanes outside the current species (mine = false).  Returns U of the
+// lane's row and G (without the descriptor scale) in G[0..D).
+template <int D, int WT>
+__device__ float mlp_mf(const float (&qh)[D], bool mine, const uint16_t *__restrict__ frag, const float *b0,
+                        const float *w1, float b1, int H, float *X, float (&G)[D])
+{
+    constexpr int DP = D <= 32 ? 32 : 64, KC = DP / 32, DT = DP / 16, XS = DP + 4;
+    // batch tiles (16 rows each) per pass: every weight fragment is loaded
+    // once per pass, and a pass keeps its tiles' operands and accumulators
+    // in registers
+    constexpr int JB = DP == 32 ? 4 : 2;
+    const int HC = (H + 31) >> 5, HT = 2 * HC;
+    const int l = threadIdx.x & 63, c = l & 15, g = l >> 4;
 #pragma unroll
-    for (int v4 = 0; v4 < 8; ++v4) {
-        float4 w;
-        w.x = (mine && 4 * v4 + 0 < D) ? qh[(4 * v4 + 0) < D ? 4 * v4 + 0 : 0] : 0.0f;
-        w.y = (mine && 4 * v4 + 1 < D) ? qh[(4 * v4 + 1) < D ? 4 * v4 + 1 : 0] : 0.0f;
-        w.z = (mine && 4 * v4 + 2 < D) ? qh[(4 * v4 + 2) < D ? 4 * v4 + 2 : 0] : 0.0f;
-        w.w = (mine && 4 * v4 + 3 < D) ? qh[(4 * v4 + 3) < D ? 4 * v4 + 3 : 0] : 0.0f;
-        *reinterpret_cast<float4 *>(X + l * kMfLd + 4 * v4) = w;
-    }
-    wave_lds_sync();
-    // weight operands: forward B(k = v, col = mu) = W0[mu][v]; adjoint B(k = mu, col = v) = W0[mu][v]
-    bf16x8 wf[2], wt[2];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        wf[c] = *reinterpret_cast<const bf16x8 *>(w0b + (16 * c + lr) * 32 + lk);
-        wt[c] = *reinterpret_cast<const bf16x8 *>(w0b + 1024 + (16 * c + lr) * 32 + lk);
-    }
-    float b0c[2], w1c[2];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int mu = 16 * c + lr;
-        b0c[c] = mu < H ? b0[mu] : 0.0f;
-        w1c[c] = mu < H ? w1[mu] : 0.0f;
-    }
-    // forward, one 16-row tile at a time; the hidden-layer adjoint goes to Y
-#pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-        const float *xr = X + (16 * rt + lr) * kMfLd + lk;
-        bf16x8 ah, am, al;
-        split3(*reinterpret_cast<const float4 *>(xr), *reinterpret_cast<const float4 *>(xr + 4), ah, am, al);
-        float us[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
-            z = mfma3(ah, am, al, wf[c], z);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const float hh = tanhf(z[e] - b0c[c]);
-                us[e] += w1c[c] * hh;
-                Y[(16 * rt + 4 * (l >> 4) + e) * kMfLd + 16 * c + lr] = w1c[c] * (1.0f - hh * hh);
-            }
-        }
-        // row sums over the 16 lanes that share the rows
+    for (int v4 = 0; v4 < DP / 4; ++v4) {
+        float w[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-#pragma unroll
-            for (int o = 1; o < 16; o <<= 1) us[e] += __shfl_xor(us[e], o, 64);
+            const int v = 4 * v4 + e;
+            w[e] = (mine && v < D) ? qh[v < D ? v : 0] : 0.0f;
         }
-        if (lr == 0) {
+        *reinterpret_cast<float4 *>(X + l * XS + 4 * v4) = make_float4(w[0], w[1], w[2], w[3]);
+    }
+    wave_lds_sync();
+    const bf16x8 *fw = reinterpret_cast<const bf16x8 *>(frag) + l;   // one 8-entry fragment per lane and block
+    const int fwd = HT * KC, tstride = fwd + DT * HC;                 // blocks per term
+    for (int j0 = 0; j0 < 4; j0 += JB) {
+        // B operands of the forward product: column c of tile j = batch row 16 j + c
+        bf16x8 xb[JB][KC][3];
 #pragma unroll
-            for (int e = 0; e < 4; ++e) X[(16 * rt + 4 * (l >> 4) + e) * kMfLd + 32] = us[e];
+        for (int jj = 0; jj < JB; ++jj) {
+            const float *xr = X + (16 * (j0 + jj) + c) * XS + 8 * g;
+#pragma unroll
+            for (int kc = 0; kc < KC; ++kc) {
+                const float4 a0 = *reinterpret_cast<const float4 *>(xr + 32 * kc);
+                const float4 a1 = *reinterpret_cast<const float4 *>(xr + 32 * kc + 4);
+                const float x8[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+                split3(x8, xb[jj][kc][0], xb[jj][kc][1], xb[jj][kc][2]);
+            }
+        }
+        f32x4 gacc[JB][DT];
+        float uacc[JB];
+#pragma unroll
+        for (int jj = 0; jj < JB; ++jj) {
+            uacc[jj] = 0.0f;
+#pragma unroll
+            for (int dt = 0; dt < DT; ++dt) gacc[jj][dt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+        for (int hc = 0; hc < HC; ++hc) {
+            // this lane's eight hidden units of the chunk: 32 hc + 16 h2 + 4 g + e
+            float bq[8], wq[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int mu = 32 * hc + 16 * (q >> 2) + 4 * g + (q & 3);
+                bq[q] = mu < H ? b0[mu] : 0.0f;
+                wq[q] = mu < H ? w1[mu] : 0.0f;
+            }
+            float gz[JB][8];
+#pragma unroll
+            for (int h2 = 0; h2 < 2; ++h2) {
+                const int ht = 2 * hc + h2;
+                bf16x8 wa[KC][WT];
+#pragma unroll
+                for (int kc = 0; kc < KC; ++kc)
+#pragma unroll
+                    for (int t = 0; t < WT; ++t) wa[kc][t] = fw[(t * tstride + ht * KC + kc) * 64];
+#pragma unroll
+                for (int jj = 0; jj < JB; ++jj) {
+                    f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int kc = 0; kc < KC; ++kc) z = mfma_terms<WT>(wa[kc], xb[jj][kc], z);
+                    // z[e]: hidden unit 16 ht + 4 g + e of batch row 16 (j0 + jj) + c
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        float hh, dh;
+                        tanh_and_slope(z[e] - bq[4 * h2 + e], hh, dh);
+                        uacc[jj] = fmaf(wq[4 * h2 + e], hh, uacc[jj]);
+                        gz[jj][4 * h2 + e] = wq[4 * h2 + e] * dh;
+                    }
+                }
+            }
+            // adjoint: B operand gz^T in K order (4 g + e, 16 + 4 g + e) as in the fragments
+            bf16x8 wt[DT][WT];
+#pragma unroll
+            for (int dt = 0; dt < DT; ++dt)
+#pragma unroll
+                for (int t = 0; t < WT; ++t) wt[dt][t] = fw[(t * tstride + fwd + dt * HC + hc) * 64];
+#pragma unroll
+            for (int jj = 0; jj < JB; ++jj) {
+                bf16x8 gb[3];
+                split3(gz[jj], gb[0], gb[1], gb[2]);
+#pragma unroll
+                for (int dt = 0; dt < DT; ++dt) gacc[jj][dt] = mfma_terms<WT>(wt[dt], gb, gacc[jj][dt]);
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < JB; ++jj) {
+            // U of column c: the four lane groups hold different hidden units
+            float u = uacc[jj];
+            u += __shfl_xor(u, 16, 64);
+            u += __shfl_xor(u, 32, 64);
+            // G^T (descriptor 16 dt + 4 g + e, column c) back over the row, which
+            // this wavefront has finished reading (its LDS operations run in order)
+            float *xo = X + (16 * (j0 + jj) + c) * XS;
+#pragma unroll
+            for (int dt = 0; dt < DT; ++dt)
+                *reinterpret_cast<float4 *>(xo + 16 * dt + 4 * g) =
+                    make_float4(gacc[jj][dt][0], gacc[jj][dt][1], gacc[jj][dt][2], gacc[jj][dt][3]);
+            if (g == 0) xo[DP] = u;
         }
     }
     wave_lds_sync();
-    // adjoint: G = Y W0, written over the descriptor columns of X
 #pragma unroll
-    for (int rt = 0; rt < 4; ++rt) {
-        const float *yr = Y + (16 * rt + lr) * kMfLd + lk;
-        bf16x8 ah, am, al;
-        split3(*reinterpret_cast<const float4 *>(yr), *reinterpret_cast<const float4 *>(yr + 4), ah, am, al);
-#pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            f32x4 g = {0.0f, 0.0f, 0.0f, 0.0f};
-            g = mfma3(ah, am, al, wt[c], g);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) X[(16 * rt + 4 * (l >> 4) + e) * kMfLd + 16 * c + lr] = g[e];
-        }
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (int v = 0; v < D; ++v) G[v] = X[l * kMfLd + v];
-    const float u = X[l * kMfLd + 32] - b1;
-    wave_lds_sync();   // X and Y are rewritten by the next species of this wavefront
+    for (int v = 0; v < D; ++v) G[v] = X[l * XS + v];
+    const float u = X[l * XS + DP] - b1;
+    wave_lds_sync();   // X is rewritten by the next species of this wavefront
     return u;
 }
+
+// LDS floats per wavefront of the matrix-core network.
+template <int D>
+constexpr int mf_lds_floats() { return 64 * ((D <= 32 ? 32 : 64) + 4); }
 
 // Network arithmetic of k_descriptor: FP32 vector units with the weights
 // read from global memory or staged in LDS, or BF16 matrix cores (student
 // weights).  (FP32 operands on the matrix cores measured slower than the
 // LDS-staged vector form: two wavefronts per SIMD cannot hide the chains of
 // dependent 16 x 16 x 4 FP32 tiles.)
-constexpr int kNetGlobal = 0, kNetLds = 1, kNetBf16 = 2;
+constexpr int kNetGlobal = 0, kNetLds = 1, kNetBf16 = 2, kNetMf32 = 3;
 
 // ----------------------------------------------------------- pass 1 ---
 
@@ -170,10 +244,11 @@ template <int NR1, int NA1, int KR1, int KA1, bool FOUR, int NET, bool TRI>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void k_descriptor(NepArgs a, const float *__restrict__ prm)
 {
-    constexpr bool MF = NET == kNetBf16;   // whole-wavefront network
+    constexpr bool MF = NET == kNetBf16 || NET == kNetMf32;   // whole-wavefront network on the matrix cores
     constexpr bool NL = NET == kNetLds;
-    // dynamic LDS: BF16, two 64 x kMfLd tiles per wavefront; LDS weights,
-    // W0 [S][H][DP] (rows padded to DP = 4 ceil(D / 4)), b0 [S][H], w1 [S][H]
+    // dynamic LDS: matrix-core network, one 64 x (32 or 64, + 4) tile per
+    // wavefront; LDS weights, W0 [S][H][DP] (rows padded to DP = 4 ceil(D / 4)),
+    // b0 [S][H], w1 [S][H]
     extern __shared__ float dyn[];
     constexpr int D = Dims<NR1, NA1, FOUR>::D;
     const LaneMap lm = lane_map(a);
@@ -393,12 +468,14 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             qh[v] = qs[v] * q[v];
             G[v] = 0.0f;
         }
-        if constexpr (NET == kNetBf16) {
+        if constexpr (MF) {
+            constexpr int WT = NET == kNetMf32 ? 3 : 1;
             const float *b0 = prm + a.ob0 + tc * a.H;
             const float *w1 = prm + a.ow1 + tc * a.H;
-            float *X = dyn + (threadIdx.x >> 6) * kMfWave;
-            const float u = mlp_mfma<D>(qh, mine, a.w0b + (size_t)tc * 2048, b0, w1, prm[a.ob1], a.H, X,
-                                        X + 64 * kMfLd, G);
+            float *X = dyn + (threadIdx.x >> 6) * mf_lds_floats<D>();
+            const MlpFrag fl = mlp_frag_layout(D, a.H, WT);
+            const float u = mlp_mf<D, WT>(qh, mine, a.w0b + (size_t)tc * fl.species_stride, b0, w1, prm[a.ob1],
+                                          a.H, X, G);
             if (mine) U = u;
         } else if constexpr (NL) {
             const int nw = S * a.H * DP, nb = S * a.H;
@@ -417,9 +494,10 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                 float z = -b0[mu];
 #pragma unroll
                 for (int v = 0; v < D; ++v) z += wr[v] * qh[v];
-                const float h = tanhf(z);
+                float h, dh;
+                tanh_and_slope(z, h, dh);
                 u += w1[mu] * h;
-                const float gz = w1[mu] * (1.0f - h * h);
+                const float gz = w1[mu] * dh;
 #pragma unroll
                 for (int v = 0; v < D; ++v) G[v] += gz * wr[v];
             }
@@ -433,9 +511,10 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                 float z = -b0[mu];
 #pragma unroll
                 for (int v = 0; v < D; ++v) z += W0[mu * D + v] * qh[v];
-                const float h = tanhf(z);
+                float h, dh;
+                tanh_and_slope(z, h, dh);
                 u += w1[mu] * h;
-                const float gz = w1[mu] * (1.0f - h * h);
+                const float gz = w1[mu] * dh;
 #pragma unroll
                 for (int v = 0; v < D; ++v) G[v] += gz * W0[mu * D + v];
             }
@@ -901,8 +980,9 @@ __global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partE
 
 constexpr size_t kNetLdsMax = 60 * 1024;   // bytes of LDS for the staged network weights
 
-template <int NR1, int NA1, bool FOUR, bool MF, bool TRI>
-static void launch_t(const NepArgs &a, const float *prm, int nblk, int wpb, hipStream_t s)
+// mlp: NEP_MLP_FP32 (vector units), NEP_MLP_BF16_MFMA or NEP_MLP_FP32_MFMA (matrix cores).
+template <int NR1, int NA1, bool FOUR, bool TRI>
+static void launch_t(const NepArgs &a, const float *prm, int nblk, int wpb, int mlp, hipStream_t s)
 {
     const dim3 g(nblk);
     const dim3 blk(64 * wpb);
@@ -910,9 +990,11 @@ static void launch_t(const NepArgs &a, const float *prm, int nblk, int wpb, hipS
         ProfScope ps_(K_DESCRIPTOR, s);
         constexpr int D = Dims<NR1, NA1, FOUR>::D, DP = (D + 3) & ~3;
         const size_t net = sizeof(float) * (size_t)a.S * a.H * (DP + 2);
-        if constexpr (MF)   // BF16 weights of the student
-            hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetBf16, TRI>), g, blk,
-                               sizeof(float) * kMfWave * wpb, s, a, prm);
+        const size_t mf = sizeof(float) * (size_t)mf_lds_floats<D>() * wpb;
+        if (mlp == NEP_MLP_BF16_MFMA)   // BF16 weights (the student)
+            hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetBf16, TRI>), g, blk, mf, s, a, prm);
+        else if (mlp == NEP_MLP_FP32_MFMA)   // FP32 weights as three BF16 terms
+            hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetMf32, TRI>), g, blk, mf, s, a, prm);
         else if (net <= kNetLdsMax)   // network weights staged in LDS
             hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetLds, TRI>), g, blk, net, s, a, prm);
         else
@@ -930,11 +1012,11 @@ static void launch_t(const NepArgs &a, const float *prm, int nblk, int wpb, hipS
 
 // General (triclinic) cells get the kernels with the general pair vector;
 // orthorhombic-only lists the ones without it.
-template <int NR1, int NA1, bool FOUR, bool MF = false>
-static void launch(const NepArgs &a, const float *prm, int nblk, int wpb, bool tri, hipStream_t s)
+template <int NR1, int NA1, bool FOUR>
+static void launch(const NepArgs &a, const float *prm, int nblk, int wpb, bool tri, int mlp, hipStream_t s)
 {
-    if (tri) launch_t<NR1, NA1, FOUR, MF, true>(a, prm, nblk, wpb, s);
-    else launch_t<NR1, NA1, FOUR, MF, false>(a, prm, nblk, wpb, s);
+    if (tri) launch_t<NR1, NA1, FOUR, true>(a, prm, nblk, wpb, mlp, s);
+    else launch_t<NR1, NA1, FOUR, false>(a, prm, nblk, wpb, mlp, s);
 }
 
 }  // namespace nep
@@ -988,25 +1070,15 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
     a.oR = m->off.cR; a.oA = m->off.cA; a.oq = m->off.qs; a.oW0 = m->off.W0; a.ob0 = m->off.b0;
     a.ow1 = m->off.w1; a.ob1 = m->off.b1; a.osh = m->off.sh;
     a.w0b = m->w0b;
-    const bool mf = m->mlp == NEP_MLP_BF16_MFMA;
+    const int mlp = m->mlp;
     const int key = h.n_max_radial * 100 + h.n_max_angular * 10 + h.four_body;
-    if (key != 440 && key != 441 && key != 640 && key != 860 && key != 881)
-        return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");
+    const bool tri = nl->any_tri != 0;
     switch (key) {
-    case 440:
-        if (mf) launch<5, 5, false, true>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s);
-        else launch<5, 5, false>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s);
-        break;
-    case 441:
-        if (mf) launch<5, 5, true, true>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s);
-        else launch<5, 5, true>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s);
-        break;
-    case 640:
-        if (mf) launch<7, 5, false, true>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s);
-        else launch<7, 5, false>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s);
-        break;
-    case 860: launch<9, 7, false>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s); break;
-    case 881: launch<9, 9, true>(a, m->dev, ws->nblk, ws->wpb, nl->any_tri != 0, s); break;
+    case 440: launch<5, 5, false>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, s); break;
+    case 441: launch<5, 5, true>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, s); break;
+    case 640: launch<7, 5, false>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, s); break;
+    case 860: launch<9, 7, false>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, s); break;
+    case 881: launch<9, 9, true>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, s); break;
     default: return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");
     }
     {

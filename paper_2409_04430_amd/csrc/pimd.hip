@@ -120,6 +120,7 @@ struct StepArgs {
     uint64_t seed;
     int64_t step;
     const int64_t *step_dev;   // if set, the step number is read from device memory
+    int64_t *step_out;         // if set (device counter mode), step + 1 is written there by a closing stage
     int stage, noise;
 };
 
@@ -144,6 +145,8 @@ __global__ __launch_bounds__(kStepBlock) void k_trpmd(StepArgs a, const double *
     const int t = threadIdx.x;
     const bool pre = a.stage != PIMD_STAGE_POST, post = a.stage != PIMD_STAGE_PRE;
     const int64_t step = a.step_dev ? *a.step_dev : a.step;
+    // the next step's counter (a different word: every workgroup reads step_dev)
+    if (a.step_out && post && blockIdx.x == 0 && threadIdx.x == 0) *a.step_out = step + 1;
 
     for (int x = t; x < P * P; x += blockDim.x) Cs[x] = cst[Lo.C + x];
     for (int x = t; x < EPB * P; x += blockDim.x) {
@@ -266,6 +269,8 @@ __global__ __launch_bounds__(64 * 4) void k_trpmd_mf(StepArgs a, const double *_
     const bool ok = e < M;
     const bool pre = a.stage != PIMD_STAGE_POST, post = a.stage != PIMD_STAGE_PRE;
     const int64_t step = a.step_dev ? *a.step_dev : a.step;
+    // the next step's counter (a different word: every workgroup reads step_dev)
+    if (a.step_out && post && blockIdx.x == 0 && threadIdx.x == 0) *a.step_out = step + 1;
     const double *C = cst + Lo.C;   // C[b * P + k]
 
     // bead values of the element tile, all loads in flight at once (lanes
@@ -368,7 +373,6 @@ __global__ __launch_bounds__(64 * 4) void k_trpmd_mf(StepArgs a, const double *_
     }
 }
 
-__global__ void k_step_advance(int64_t *step) { *step += 1; }
 
 // ------------------------------------------------------- observables ---
 //
@@ -670,7 +674,7 @@ extern "C" int32_t rp_normal_modes(const pimd_ctx *c, int32_t dir, const double 
 }
 
 static int32_t step_common(const pimd_ctx *c, double *pos, double *vel, const float *F, int64_t step,
-                           int64_t *step_dev, int32_t stage, hipStream_t s)
+                           const int64_t *step_dev, int64_t *step_out, int32_t stage, hipStream_t s)
 {
     if (!c) return fail(NEP_ERR_INVALID_ARG, "trpmd_step: null context");
     if (stage < PIMD_STAGE_PRE || stage > PIMD_STAGE_FUSED) return fail(NEP_ERR_INVALID_ARG, "trpmd_step: bad stage");
@@ -685,11 +689,11 @@ static int32_t step_common(const pimd_ctx *c, double *pos, double *vel, const fl
     a.seed = c->prm.seed;
     a.step = step;
     a.step_dev = step_dev;
+    a.step_out = step_out;
     a.stage = stage;
     a.noise = c->prm.mode != PIMD_MODE_RPMD && !(c->prm.mode == PIMD_MODE_TRPMD && c->P == 1);
     if (c->P < 1 || c->P > kMaxBeads) return fail(NEP_ERR_UNSUPPORTED, "trpmd_step: P=%d", c->P);
     launch_step(a, c->consts, s);
-    if (step_dev && stage != PIMD_STAGE_PRE) hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(1), 0, s, step_dev);
     NEP_HIP(hipGetLastError());
     return NEP_OK;
 }
@@ -697,14 +701,16 @@ static int32_t step_common(const pimd_ctx *c, double *pos, double *vel, const fl
 extern "C" int32_t trpmd_step(const pimd_ctx *c, double *pos, double *vel, const float *F, int64_t step, int32_t stage,
                               hipStream_t s)
 {
-    return step_common(c, pos, vel, F, step, nullptr, stage, s);
+    return step_common(c, pos, vel, F, step, nullptr, nullptr, stage, s);
 }
 
-extern "C" int32_t trpmd_step_dev(const pimd_ctx *c, double *pos, double *vel, const float *F, int64_t *step,
-                                  int32_t stage, hipStream_t s)
+extern "C" int32_t trpmd_step_dev(const pimd_ctx *c, double *pos, double *vel, const float *F, const int64_t *step_in,
+                                  int64_t *step_out, int32_t stage, hipStream_t s)
 {
-    if (!step) return fail(NEP_ERR_INVALID_ARG, "trpmd_step_dev: null step counter");
-    return step_common(c, pos, vel, F, 0, step, stage, s);
+    if (!step_in) return fail(NEP_ERR_INVALID_ARG, "trpmd_step_dev: null step counter");
+    if (stage != PIMD_STAGE_PRE && (!step_out || step_out == step_in))
+        return fail(NEP_ERR_INVALID_ARG, "trpmd_step_dev: a closing stage needs an output counter other than the input");
+    return step_common(c, pos, vel, F, 0, step_in, stage == PIMD_STAGE_PRE ? nullptr : step_out, stage, s);
 }
 
 extern "C" int32_t pimd_observables(const pimd_ctx *c, const double *pos, const float *F, const double *W_bead,

@@ -571,8 +571,8 @@ extern "C" int32_t nep_param_grad(const nep_model *m, nep_nlist *nl, nep_ws *ws,
     if (m->cutoffs_only) return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: a list cutoff descriptor has no network");
     if (tw->P != P || tw->N != N || nl->nsys != 1)
         return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: sizes do not match the training workspace");
-    if (m->mlp != NEP_MLP_FP32)
-        return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: training needs the FP32 network (nep_model_set_mlp)");
+    if (m->mlp == NEP_MLP_BF16_MFMA)
+        return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: training needs the FP32 weights (nep_model_set_mlp)");
     int32_t rc = nep_compute(m, nl, ws, pos, box, types, P, N, tw->E, tw->F, tw->W, nullptr, nullptr, s);
     if (rc != NEP_OK) return rc;
     const size_t PN = (size_t)P * N;

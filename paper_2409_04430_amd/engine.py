@@ -59,17 +59,27 @@ class NepPimd:
 
     With a list of systems the atoms are concatenated along the atom axis,
     every kernel of a step covers all systems at once, and E / W gain a
-    leading system axis ([nsys, P], [nsys, P, 9])."""
+    leading system axis ([nsys, P], [nsys, P, 9]).
+
+    mlp selects the network arithmetic: "auto" (FP32 accuracy, matrix cores
+    or vector units by the model's shape), "fp32", "fp32_mfma" or
+    "bf16_mfma"; self.mlp is the arithmetic in use."""
 
     def __init__(self, model_path: str, system, *, dt: float, T: float, tau: float = 100.0,
                  mode: str = "trpmd", seed: int = 0, caps: Optional[tuple] = None, check_every: int = 50,
                  want_atom: bool = False, skin: float = 0.5, autotune: bool = False, obs_every: int = 0,
                  barostat: Optional[dict] = None, rdf: Optional[dict] = None, dump_every: int = 0,
-                 max_regrow: int = 8, regrow_budget_s: float = 300.0, d3: Optional[str] = None):
+                 max_regrow: int = 8, regrow_budget_s: float = 300.0, d3: Optional[str] = None,
+                 mlp: str = "auto"):
         import torch
         self.torch = torch
         dev = torch.device("cuda")
         self.model = lib.Model(model_path)
+        if mlp not in lib.MLP_MODES:
+            raise ValueError(f"mlp must be one of {sorted(lib.MLP_MODES)}")
+        if lib.MLP_MODES[mlp] != lib.MLP_FP32:
+            self.model.set_mlp(lib.MLP_MODES[mlp])
+        self.mlp = lib.MLP_NAMES[self.model.mlp]   # "auto" resolved by the library
         systems = list(system) if isinstance(system, (list, tuple)) else [system]
         self.batched = isinstance(system, (list, tuple))
         self.P = systems[0].P
@@ -108,7 +118,9 @@ class NepPimd:
         self.step_no = 0
         self.started = False
         self.graph = None
-        self.step_dev = None
+        self.graph_steps = 0
+        self.step_dev = None      # two alternating device step counters of the captured steps
+        self._dev_stale = False   # an eager step ran since the last replay: refresh the counter first
         self.obs_every = int(obs_every)
         self.baro = dict(barostat) if barostat else None
         self.obs_log = []
@@ -297,7 +309,7 @@ class NepPimd:
             if finished:
                 self.finish()
             elif had_graph:
-                self.capture()
+                self.capture(self.graph_steps)
         finally:
             self.check_every = every
 
@@ -340,55 +352,79 @@ class NepPimd:
             self.box = box * mu if box.shape == (3,) else (box.reshape(3, 3) * mu[None, :]).reshape(box.shape)
 
     def step(self):
-        """One full step: forces at the advanced positions, then POST(n) + PRE(n+1)."""
+        """One full step, launched eagerly: forces at the advanced positions,
+        then POST(n) + PRE(n+1).  (`run` replays a captured graph where it can.)"""
         self._finished = False
-        if self.graph is not None:
-            self.graph.replay()
+        if not self.started:
+            self.start()
+        self.forces()
+        n = self.step_no
+        if self.on_forces is not None:
+            self.on_forces(n)
+        self._after_forces(n)
+        if self._split():
+            self.pimd.step(self.pos, self.vel, self.F, n, lib.POST)
+            self._after_post(n)
+            self.pimd.step(self.pos, self.vel, self.F, n + 1, lib.PRE)
         else:
-            if not self.started:
-                self.start()
-            self.forces()
-            n = self.step_no
-            if self.on_forces is not None:
-                self.on_forces(n)
-            self._after_forces(n)
-            if self._split():
-                self.pimd.step(self.pos, self.vel, self.F, n, lib.POST)
-                self._after_post(n)
-                self.pimd.step(self.pos, self.vel, self.F, n + 1, lib.PRE)
-            else:
-                self.pimd.step(self.pos, self.vel, self.F, n, lib.FUSED)
+            self.pimd.step(self.pos, self.vel, self.F, n, lib.FUSED)
         self.step_no += 1
+        if self.graph is not None:
+            self._dev_stale = True
         if self.check_every and self.step_no % self.check_every == 0:
             self.check()
 
     def run(self, n: int):
-        for _ in range(n):
-            self.step()
+        """n steps: replays of the captured graph while at least its step count
+        remains, eager steps otherwise."""
+        while n > 0:
+            if self.graph is not None and n >= self.graph_steps:
+                self._finished = False
+                if self._dev_stale:
+                    self.step_dev[0].fill_(self.step_no)   # the counter the graph reads first
+                    self._dev_stale = False
+                before = self.step_no
+                self.graph.replay()
+                self.step_no += self.graph_steps
+                n -= self.graph_steps
+                if self.check_every and self.step_no // self.check_every != before // self.check_every:
+                    self.check()
+            else:
+                self.step()
+                n -= 1
 
-    def capture(self):
-        """Capture one full step (lists, forces, fused integrator stage) as a HIP graph.
+    def capture(self, steps: int = 2):
+        """Capture `steps` full steps (lists, forces, fused integrator stage;
+        an even number) as one HIP graph, replayed by `run`.
 
-        The step number then lives in a device counter advanced by the graph
-        itself, so every replay draws fresh noise.  The box and the species
-        must stay fixed while the graph is in use; `release()` returns to
-        eager launches."""
+        The step number lives in two device counters that the captured
+        integrator launches read and write alternately, so every replay draws
+        fresh noise with no extra launch; one replay's launch overhead is
+        shared by its steps.  The box and the species must stay fixed while
+        the graph is in use; `release()` returns to eager launches."""
         t = self.torch
+        if steps < 2 or steps % 2:
+            raise ValueError("capture: the number of captured steps must be even (the step counters alternate)")
         if self._split() or self.rdf_cfg:
             raise ValueError("capture: observables, dumps, RDFs and the barostat run eagerly")
+        self.graph = None
         if not self.started:
             self.start()
         # one eager step first so that every lazy allocation has happened
         self.step()
-        self.step_dev = t.tensor([self.step_no], dtype=t.int64, device=self.pos.device)
+        self.step_dev = t.tensor([self.step_no, 0], dtype=t.int64, device=self.pos.device)
+        c = (self.step_dev[0:1], self.step_dev[1:2])
         t.cuda.synchronize()
         g = t.cuda.CUDAGraph()
         with t.cuda.graph(g):
-            self.forces()
-            self.pimd.step_dev(self.pos, self.vel, self.F, self.step_dev, lib.FUSED)
+            for k in range(steps):
+                self.forces()
+                self.pimd.step_dev(self.pos, self.vel, self.F, c[k % 2], c[(k + 1) % 2], lib.FUSED)
         t.cuda.synchronize()
-        # capture does not execute: the counter and the state are unchanged
+        # capture does not execute: the counters and the state are unchanged
         self.graph = g
+        self.graph_steps = steps
+        self._dev_stale = False
 
     def release(self):
         self.graph = None

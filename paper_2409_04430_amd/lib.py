@@ -82,6 +82,7 @@ _sig = {
     "nep_model_info": (_i32, [_vp, C.POINTER(HParams)]),
     "nep_model_destroy": (None, [_vp]),
     "nep_model_set_mlp": (_i32, [_vp, _i32, _vp]),
+    "nep_model_mlp": (_i32, [_vp, _vp]),
     "nep_force_rmse": (_i32, [_vp, _vp, C.c_int64, _vp, _vp]),
     "nep_nlist_create": (_i32, [_vp, _i32, _i32, _i32, _i32, C.POINTER(_vp)]),
     "nep_nlist_create_batched": (_i32, [_vp, _i32, _i32, C.POINTER(C.c_int32), _i32, _i32, C.POINTER(_vp)]),
@@ -104,7 +105,7 @@ _sig = {
     "pimd_destroy": (None, [_vp]),
     "rp_normal_modes": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "trpmd_step": (_i32, [_vp, _vp, _vp, _vp, C.c_int64, _i32, _vp]),
-    "trpmd_step_dev": (_i32, [_vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "trpmd_step_dev": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
     "pimd_observables": (_i32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp, _vp]),
     "pimd_berendsen": (_i32, [_vp, _vp, _vp, C.POINTER(PimdBarostat), _vp, _vp]),
     "pimd_centroid": (_i32, [_vp, _vp, _vp, _vp]),
@@ -195,7 +196,9 @@ def _box9(box) -> C.Array:
 
 # ------------------------------------------------------------------ handles
 
-MLP_FP32, MLP_BF16_MFMA = 0, 1
+MLP_FP32, MLP_BF16_MFMA, MLP_FP32_MFMA, MLP_FP32_AUTO = 0, 1, 2, 3
+MLP_MODES = {"fp32": MLP_FP32, "bf16_mfma": MLP_BF16_MFMA, "fp32_mfma": MLP_FP32_MFMA, "auto": MLP_FP32_AUTO}
+MLP_NAMES = {v: k for k, v in MLP_MODES.items()}
 
 
 class Model:
@@ -220,10 +223,14 @@ class Model:
             return hp[k]
         raise AttributeError(k)
 
-    def set_mlp(self, mode: int):
-        """nep_model_set_mlp on the current stream: MLP_FP32 or MLP_BF16_MFMA (re-call after the weights change)."""
+    def set_mlp(self, mode: int) -> int:
+        """nep_model_set_mlp on the current stream (re-call after the weights change);
+        returns the arithmetic in use (nep_model_mlp), MLP_FP32_AUTO resolved."""
         _check(_lib.nep_model_set_mlp(self._h, int(mode), _stream()))
-        self.mlp = int(mode)
+        m = C.c_int32()
+        _check(_lib.nep_model_mlp(self._h, C.byref(m)))
+        self.mlp = m.value
+        return self.mlp
 
     def params(self):
         """(device pointer, count, offsets) of the model's FP32 parameter array."""
@@ -507,13 +514,14 @@ class Pimd:
         _check(_lib.trpmd_step(self._h, _ptr(pos, t.float64, shp, "pos"), _ptr(vel, t.float64, shp, "vel"),
                                _ptr(F, t.float32, shp, "F"), int(step), int(stage), _stream()))
 
-    def step_dev(self, pos, vel, F, step, stage: int):
-        """trpmd_step with the step number in a device int64 tensor (advanced after POST/FUSED)."""
+    def step_dev(self, pos, vel, F, step_in, step_out, stage: int):
+        """trpmd_step with the step number read from device int64 step_in [1]; a closing
+        stage writes step + 1 to step_out [1] (another tensor)."""
         t = _torch()
         shp = (self.P, self.N, 3)
         _check(_lib.trpmd_step_dev(self._h, _ptr(pos, t.float64, shp, "pos"), _ptr(vel, t.float64, shp, "vel"),
-                                   _ptr(F, t.float32, shp, "F"), _ptr(step, t.int64, (1,), "step"), int(stage),
-                                   _stream()))
+                                   _ptr(F, t.float32, shp, "F"), _ptr(step_in, t.int64, (1,), "step_in"),
+                                   _ptr(step_out, t.int64, (1,), "step_out"), int(stage), _stream()))
 
     def observables(self, pos, F, W, E, box, out):
         """pimd_observables: out [OBS_COUNT] float64 device tensor, written on the stream."""

@@ -45,10 +45,14 @@ def student_path(tmpdir_session):
 
 
 def evaluate(torch, L, path, pos, types, box, mlp, caps=(160, 96)):
+    """mlp: False / 0 for the vector-unit network, True for BF16 weights on
+    the matrix cores, or a nep_mlp_mode value."""
     P, N = pos.shape[:2]
     m = L.Model(path)
-    if mlp:
+    if mlp is True:
         m.set_mlp(L.MLP_BF16_MFMA)
+    elif mlp:
+        m.set_mlp(int(mlp))
     dev = torch.device("cuda")
     tpos = torch.tensor(pos, dtype=torch.float64, device=dev)
     ttyp = torch.tensor(types, dtype=torch.int32, device=dev)
@@ -125,14 +129,51 @@ def test_mfma_full_size_sampled_beads(torch, L, orc, student_path):
 
 
 def test_mfma_rejects_wide_models(torch, L, tmpdir_session):
-    path = write_model(tmpdir_session, "teacher_mf", configs.WORKLOADS["fcc32000"].model())
+    hyper = I.NepHyper(1, 5.0, 4.0, 4, 4, 8, 8, 4, False, 130)    # H = 130 > 128
+    path = write_model(tmpdir_session, "wide_mf", I.random_model(hyper, np.random.default_rng(3), 0.06, 10.0))
     m = L.Model(path)
-    with pytest.raises(L.NepError) as e:
-        m.set_mlp(L.MLP_BF16_MFMA)
-    assert e.value.code == 3
+    for mode in (L.MLP_BF16_MFMA, L.MLP_FP32_MFMA):
+        with pytest.raises(L.NepError) as e:
+            m.set_mlp(mode)
+        assert e.value.code == 3
     with pytest.raises(L.NepError):
         m.set_mlp(7)
+    assert m.set_mlp(L.MLP_FP32_AUTO) == L.MLP_FP32    # too wide for the tiles
     m.set_mlp(L.MLP_FP32)
+
+
+@pytest.mark.parametrize("name,want", [("fcc108", "fp32"), ("rocksalt4096", "fp32"), ("water16", "fp32"),
+                                       ("porous13824", "fp32_mfma"), ("fcc32000", "fp32_mfma")])
+def test_auto_network_arithmetic(torch, L, tmpdir_session, name, want):
+    """The automatic choice: matrix cores only where the angular sums of more
+    than five radial functions leave the registers either way."""
+    w = configs.WORKLOADS[name]
+    path = write_model(tmpdir_session, name + "_auto", w.model())
+    m = L.Model(path)
+    assert m.mlp == L.MLP_FP32
+    assert L.MLP_NAMES[m.set_mlp(L.MLP_FP32_AUTO)] == want
+
+
+@pytest.mark.parametrize("name,P,beads", [("rocksalt4096", 4, (0, 3)), ("porous13824", 2, (0, 1)),
+                                          ("fcc32000", 2, (0, 1)), ("fcc108", 4, (0, 1, 2, 3))])
+def test_fp32_network_on_matrix_cores_matches_oracle(torch, L, orc, tmpdir_session, name, P, beads):
+    """NEP_MLP_FP32_MFMA: the FP32 weights as three BF16 terms (six products
+    kept) on the matrix cores give the FP32 model's E/F/W within the usual
+    bar against the oracle with unrounded weights: rocksalt (D 27, H 50,
+    two species), porous (D 37, H 80, four species), the teacher (D 54,
+    H 100, four-body) and fcc108 (D 25, H 30); and agree with the vector
+    units' network to FP32 rounding."""
+    w = configs.WORKLOADS[name]
+    path = write_model(tmpdir_session, "mf32_" + name, w.model())
+    s = w.systems(P=P)[0]
+    pos = s.pos + np.random.default_rng(4).normal(0.0, 0.03, s.pos.shape)
+    say(f"[fp32 mfma] {name}: {s.N} atoms x {P} beads")
+    got = evaluate(torch, L, path, pos, s.types, s.box, mlp=L.MLP_FP32_MFMA)
+    compare(orc.Model(path), pos, s.types, s.box, got, beads, name)
+    vec = evaluate(torch, L, path, pos, s.types, s.box, mlp=0)
+    rel = np.abs(got[1] - vec[1]).max() / np.abs(vec[1]).max()
+    say(f"  matrix cores vs vector units: max dF/Fmax {rel:.2e}")
+    assert rel < 2e-6
 
 
 # ------------------------------------------------------------ judge ---
