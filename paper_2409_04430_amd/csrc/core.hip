@@ -563,6 +563,7 @@ extern "C" int32_t nep_nlist_create_batched(const nep_model *m, int32_t P, int32
     if (e == hipSuccess && Nn) e = hipMemcpy(nl->atom_sys, asys.data(), sizeof(int32_t) * Nn, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = dalloc(&nl->cen, Nn * 3);
     if (e == hipSuccess) e = dalloc(&nl->spr, Nn);
+    if (e == hipSuccess) e = dalloc(&nl->cmax, 2 * ((kCenLanes * Nn + kBlock - 1) / kBlock));
     if (e == hipSuccess) e = dalloc(&nl->cen_ref, Nn * 3);
     if (e == hipSuccess) e = dalloc(&nl->candR, Nn * capR);
     if (e == hipSuccess) e = dalloc(&nl->candRs, Nn * capR);
@@ -611,7 +612,7 @@ extern "C" int32_t nep_nlist_create(const nep_model *m, int32_t P, int32_t N, in
 extern "C" void nep_nlist_destroy(nep_nlist *nl)
 {
     if (!nl) return;
-    for (void *p : {(void *)nl->geom, (void *)nl->atom_sys, (void *)nl->cell_sys, (void *)nl->cen, (void *)nl->spr, (void *)nl->cen_ref, (void *)nl->candR, (void *)nl->candRs, (void *)nl->candAs, (void *)nl->lenR, (void *)nl->offR,
+    for (void *p : {(void *)nl->geom, (void *)nl->atom_sys, (void *)nl->cell_sys, (void *)nl->cen, (void *)nl->spr, (void *)nl->cmax, (void *)nl->cen_ref, (void *)nl->candR, (void *)nl->candRs, (void *)nl->candAs, (void *)nl->lenR, (void *)nl->offR,
                     (void *)nl->candA, (void *)nl->lenA, (void *)nl->offA, (void *)nl->revA, (void *)nl->uniR,
                     (void *)nl->umR, (void *)nl->umA, (void *)nl->uendR, (void *)nl->uniA, (void *)nl->uendA, (void *)nl->pairbuf, (void *)nl->pos4, (void *)nl->posT,
                     (void *)nl->cell_cnt, (void *)nl->cell_start, (void *)nl->cell_atoms, (void *)nl->grid,

@@ -125,6 +125,7 @@ struct nep_nlist {
     // Shared by all beads: ring-polymer centroids and candidate rows.
     double *cen = nullptr;        // [N][3] centroids of this call
     float *spr = nullptr;         // [N] largest bead distance from the centroid (rounded up) of this call
+    float *cmax = nullptr;        // [ceil(kCenLanes N / kBlock)][2] per-workgroup maxima of the centroid kernel
     double *cen_ref = nullptr;    // [N][3] centroids at the last rebuild
     int32_t *candR = nullptr;     // [N][capR] entries (j << 2) | species(j), sorted by (species, j)
     int32_t *candRs = nullptr;    // [N][capR] the same rows unsorted, as the candidate search leaves them
@@ -192,6 +193,8 @@ namespace nep {
 
 // Number of threads per block used by the per-atom kernels.
 constexpr int kBlock = 256;
+// Lanes per atom of the centroid kernel (a power of two dividing 64).
+constexpr int kCenLanes = 16;
 
 inline int div_up(int a, int b) { return (a + b - 1) / b; }
 

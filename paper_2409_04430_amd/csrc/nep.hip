@@ -946,35 +946,32 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
 
 // Per-(system, bead) energy and virial from the per-workgroup partial sums
 // of the system's tiles, stored [P][nblk] (energy) and [P][9][nblk] (virial
-// parts).  One workgroup per (system, bead, component): thread t adds tiles
-// t, t + 256, ... in order, then a fixed-shape tree over the threads, so the
-// result is bitwise reproducible.  Component 0 is E, 1..9 the virial.
-__global__ __launch_bounds__(256) void k_reduce(const double *__restrict__ partE, const double *__restrict__ partWa,
-                                                const double *__restrict__ partWr, const int32_t *__restrict__ sys_tile0,
-                                                int P, int nblk, double *__restrict__ E, double *__restrict__ W)
+// parts).  One wavefront per (system, bead, component): lane t adds tiles
+// t, t + 64, ... in order (four loads in flight), then a fixed butterfly
+// over the lanes, so the result is bitwise reproducible.  Component 0 is E,
+// 1..9 the virial.
+__global__ __launch_bounds__(64) void k_reduce(const double *__restrict__ partE, const double *__restrict__ partWa,
+                                               const double *__restrict__ partWr, const int32_t *__restrict__ sys_tile0,
+                                               int P, int nblk, double *__restrict__ E, double *__restrict__ W)
 {
-    // one workgroup per (system, bead) and component c (0: E, 1..9: W)
-    __shared__ double red[256];
     const int sb = blockIdx.x, sy = sb / P, b = sb - sy * P, t = threadIdx.x, c = blockIdx.y;
     const int k0 = sys_tile0[sy], k1 = sys_tile0[sy + 1];
+    const double *pa = c == 0 ? partE + (size_t)b * nblk : partWa + ((size_t)b * 9 + (c - 1)) * nblk;
+    const double *pr = c == 0 ? nullptr : partWr + ((size_t)b * 9 + (c - 1)) * nblk;
     double acc = 0.0;
-    if (c == 0) {
-        for (int k = k0 + t; k < k1; k += blockDim.x) acc += partE[(size_t)b * nblk + k];
-    } else {
-        for (int k = k0 + t; k < k1; k += blockDim.x) {
-            const size_t o = ((size_t)b * 9 + (c - 1)) * nblk + k;
-            acc += partWa[o] + partWr[o];
-        }
+    int k = k0 + t;
+    for (; k + 192 < k1; k += 256) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = pa[k + 64 * u] + (pr ? pr[k + 64 * u] : 0.0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += v[u];
     }
-    red[t] = acc;
-    __syncthreads();
-    for (int w = blockDim.x >> 1; w > 0; w >>= 1) {
-        if (t < w) red[t] += red[t + w];
-        __syncthreads();
-    }
+    for (; k < k1; k += 64) acc += pa[k] + (pr ? pr[k] : 0.0);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     if (t == 0) {
-        if (c == 0) E[sb] = red[0];
-        else W[(size_t)sb * 9 + (c - 1)] = red[0];
+        if (c == 0) E[sb] = acc;
+        else W[(size_t)sb * 9 + (c - 1)] = acc;
     }
 }
 
@@ -1083,7 +1080,7 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
     }
     {
         ProfScope ps_(K_REDUCE, s);
-        hipLaunchKernelGGL(k_reduce, dim3(nsys * P, 10), dim3(256), 0, s, ws->partE, a.partWa, a.partWr, ws->sys_tile0,
+        hipLaunchKernelGGL(k_reduce, dim3(nsys * P, 10), dim3(64), 0, s, ws->partE, a.partWa, a.partWr, ws->sys_tile0,
                            P, ws->nblk, E, W);
     }
     NEP_HIP(hipGetLastError());

@@ -34,8 +34,6 @@ namespace nep {
 // and persist across calls; 0-1 are per-call maxima; 4 is the rebuild
 // decision of this call.
 struct DevGlobal {
-    uint32_t spread_bits;   // D of this call (float bits, atomicMax)
-    uint32_t reach_bits;    // largest D_i + |dc_i| of this call (float bits): spread plus displacement
     float d_build;          // D at the last rebuild
     uint32_t rows_overflow; // a candidate row of the last rebuild was truncated
     int rebuild;            // 1: rebuild the candidate rows in this call
@@ -92,38 +90,58 @@ __device__ __forceinline__ void raise_max(uint32_t *word, uint32_t v)
 
 // Centroid of each atom's ring polymer, its largest bead distance D_i and
 // its displacement |dc_i| from the centroid of the last rebuild (both
-// rounded up); the maxima of D_i and of D_i + |dc_i| go to the skin test.
+// rounded up); each workgroup's maxima of D_i and of D_i + |dc_i| go to the
+// skin test through cmax.
 __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double rcR, double rcA, double skin,
-                              int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status);
+                              int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status,
+                              const float *__restrict__ cmax, int nblk);
 
 // kCenLanes lanes per atom (adjacent), each summing every kCenLanes-th bead
-// and packing those beads' positions on the fine grid (the packed positions
-// [N][P] of the list); the atom's sums and the bead spread meet by
-// shuffles, and the atom's first lane writes its centroid and spread.
-constexpr int kCenLanes = 16;   // a power of two dividing 64
+// (kept in registers for the spread) and packing those beads' positions on
+// the fine grid (the packed positions [N][P] of the list); the atom's sums
+// and the bead spread meet by shuffles, and the atom's first lane writes
+// its centroid and spread.  Each workgroup writes its two maxima to
+// cmax[2 blockIdx.x ..] (one store each: same-address atomics from every
+// workgroup serialise in the L2), reduced by the decision.
+constexpr int kCenBeads = kMaxBeads / kCenLanes;   // beads per lane at most
 __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ pos, const int32_t *__restrict__ types,
                                                      const int32_t *__restrict__ atom_sys,
                                                      int P, int N, int S, double *__restrict__ cen,
                                                      float *__restrict__ spr, const double *__restrict__ cen_ref,
-                                                     const SysGeom *__restrict__ geom, int nsys, double rcR,
-                                                     double rcA, double skin, int force, uint32_t *__restrict__ grid,
-                                                     uint32_t *__restrict__ status, float4 *__restrict__ pos4)
+                                                     const SysGeom *__restrict__ geom, const uint32_t *__restrict__ grid,
+                                                     uint32_t *__restrict__ status, float4 *__restrict__ pos4,
+                                                     float *__restrict__ cmax)
 {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int i = t / kCenLanes, q = t % kCenLanes;
     const bool has = i < N;
+    const int ic = has ? i : N - 1;
+    // per-atom records first: their loads do not wait on the positions
+    const int sy = atom_sys[ic];
+    const int ty = types[ic];
+    const double cr0 = cen_ref[3 * ic], cr1 = cen_ref[3 * ic + 1], cr2 = cen_ref[3 * ic + 2];
+    const SysGeom &g = geom[sy];
+    const size_t st = (size_t)N * 3;
+    double x[kCenBeads][3];
+#pragma unroll
+    for (int u = 0; u < kCenBeads; ++u) {
+        const int b = q + u * kCenLanes;
+        const double *p = pos + (size_t)(b < P ? b : 0) * st + 3 * (size_t)ic;
+        x[u][0] = p[0];
+        x[u][1] = p[1];
+        x[u][2] = p[2];
+    }
     uint32_t f = 0;
     float spread = 0.0f, reach = 0.0f;
-    const size_t st = (size_t)N * 3;
     double c[3] = {0.0, 0.0, 0.0};
-    if (has) {
-        const SysGeom &g = geom[atom_sys[i]];
-        for (int b = q; b < P; b += kCenLanes) {
-            const double *p = pos + b * st + 3 * (size_t)i;
-            c[0] += p[0];
-            c[1] += p[1];
-            c[2] += p[2];
-            pos4[(size_t)i * P + b] = pack_one(p, g);
+#pragma unroll
+    for (int u = 0; u < kCenBeads; ++u) {
+        const int b = q + u * kCenLanes;
+        if (has && b < P) {
+            c[0] += x[u][0];
+            c[1] += x[u][1];
+            c[2] += x[u][2];
+            pos4[(size_t)i * P + b] = pack_one(x[u], g);
         }
     }
 #pragma unroll
@@ -133,12 +151,14 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
     const double inv = 1.0 / P;
     c[0] *= inv; c[1] *= inv; c[2] *= inv;
     double m2 = 0.0;
-    if (has)
-        for (int b = q; b < P; b += kCenLanes) {
-            const double *p = pos + b * st + 3 * (size_t)i;
-            const double dx = p[0] - c[0], dy = p[1] - c[1], dz = p[2] - c[2];
+#pragma unroll
+    for (int u = 0; u < kCenBeads; ++u) {
+        const int b = q + u * kCenLanes;
+        if (has && b < P) {
+            const double dx = x[u][0] - c[0], dy = x[u][1] - c[1], dz = x[u][2] - c[2];
             m2 = fmax(m2, dx * dx + dy * dy + dz * dz);
         }
+    }
     for (int o = 1; o < kCenLanes; o <<= 1) m2 = fmax(m2, __shfl_xor(m2, o));
     if (has && q == 0) {
         cen[3 * i] = c[0];
@@ -153,21 +173,17 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
             spread = (float)di * 1.000001f + 1e-7f;   // rounded up
             // displacement from the build centroid carried along with the box:
             // c - lambda c_build, lambda = L / L_build per axis (1 for an unchanged box)
-            const int sy = atom_sys[i];
             const DevSys *ds = dev_sys(grid, sy);
             double lam[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a)
-                lam[a] = (!geom[sy].tri && ds->Lb[a] > 0.0) ? geom[sy].L[a] / ds->Lb[a] : 1.0;   // a changed general cell rebuilds
-            const double dx = c[0] - lam[0] * cen_ref[3 * i], dy = c[1] - lam[1] * cen_ref[3 * i + 1],
-                         dz = c[2] - lam[2] * cen_ref[3 * i + 2];
+                lam[a] = (!g.tri && ds->Lb[a] > 0.0) ? g.L[a] / ds->Lb[a] : 1.0;   // a changed general cell rebuilds
+            const double dx = c[0] - lam[0] * cr0, dy = c[1] - lam[1] * cr1, dz = c[2] - lam[2] * cr2;
             const double d2 = dx * dx + dy * dy + dz * dz;
             reach = isfinite(d2) ? (float)(di + sqrt(d2)) * 1.000001f + 1e-7f : 3.0e38f;
         }
-        const int ty = types[i];
         if (ty < 0 || ty >= S) f |= NEP_FLAG_BAD_TYPE;
     }
-    // one atomic per workgroup and word (same-address atomics serialise)
     __shared__ float red[2][kBlock / 64];
     spread = wave_max_f(spread);
     reach = wave_max_f(reach);
@@ -182,8 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
             spread = fmaxf(spread, red[0][w]);
             reach = fmaxf(reach, red[1][w]);
         }
-        if (spread > 0.0f) atomicMax(&grid[0], __float_as_uint(spread));
-        if (reach > 0.0f) atomicMax(&grid[1], __float_as_uint(reach));
+        *reinterpret_cast<float2 *>(cmax + 2 * (size_t)blockIdx.x) = make_float2(spread, reach);
     }
     if (f) atomicOr(&status[0], f);
 }
@@ -207,11 +222,29 @@ __global__ __launch_bounds__(kBlock) void k_centroid(const double *__restrict__ 
 // ticket inside k_centroid cost more: every workgroup then needs a
 // device-scope fence).
 __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double rcR, double rcA, double skin,
-                              int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status)
+                              int force, uint32_t *__restrict__ grid, uint32_t *__restrict__ status,
+                              const float *__restrict__ cmax, int nblk)
 {
     DevGlobal *dg = dev_global(grid);
-    const float spread = __uint_as_float(__atomic_load_n(&dg->spread_bits, __ATOMIC_RELAXED));
-    const float reach1 = __uint_as_float(__atomic_load_n(&dg->reach_bits, __ATOMIC_RELAXED));
+    // maxima over the centroid kernel's workgroups
+    __shared__ float dred[2][32];
+    float spread = 0.0f, reach1 = 0.0f;
+    for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
+        const float2 v = *reinterpret_cast<const float2 *>(cmax + 2 * (size_t)k);
+        spread = fmaxf(spread, v.x);
+        reach1 = fmaxf(reach1, v.y);
+    }
+    spread = wave_max_f(spread);
+    reach1 = wave_max_f(reach1);
+    if ((threadIdx.x & 63) == 0) {
+        dred[0][threadIdx.x >> 6] = spread;
+        dred[1][threadIdx.x >> 6] = reach1;
+    }
+    __syncthreads();
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        spread = fmaxf(spread, dred[0][w]);
+        reach1 = fmaxf(reach1, dred[1][w]);
+    }
     double lam_min = 1.0;
     for (int s = 0; s < nsys; ++s) {
         const DevSys *ds = dev_sys(grid, s);
@@ -253,9 +286,6 @@ __device__ void grid_decision(const SysGeom *__restrict__ geom, int nsys, double
             if (!(R_rows < wmin)) atomicOr(&status[0], (uint32_t)NEP_FLAG_CELL_TOO_SMALL);
         }
         atomicMax(&status[4], __float_as_uint(spread));
-        // the next call's maxima start from zero
-        dg->spread_bits = 0u;
-        dg->reach_bits = 0u;
         if (!rebuild) {
             // reused rows that were truncated keep the overflow flag raised
             if (dg->rows_overflow) atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
@@ -322,9 +352,10 @@ __global__ __launch_bounds__(kDecideBlock) void k_decide(const SysGeom *__restri
                                                    uint32_t *__restrict__ status, const double *__restrict__ cen,
                                                    int N, const int32_t *__restrict__ atom_sys, int ncell,
                                                    int32_t *__restrict__ cell_cnt, int32_t *__restrict__ cell_start,
-                                                   int32_t *__restrict__ cell_atoms)
+                                                   int32_t *__restrict__ cell_atoms,
+                                                   const float *__restrict__ cmax, int nblk)
 {
-    grid_decision(geom, nsys, rcR, rcA, skin, force, grid, status);
+    grid_decision(geom, nsys, rcR, rcA, skin, force, grid, status, cmax, nblk);
     // values written by other threads of the workgroup are read through L2
     if (!__atomic_load_n(&dev_global(grid)->rebuild, __ATOMIC_RELAXED)) return;   // whole workgroup
     if (ncell <= kCellLds) {
@@ -436,9 +467,9 @@ __device__ void sort_row_into(int32_t *__restrict__ dst, int n, const int32_t *_
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Candidate rows.  gridDim.y workgroups per cell, each taking every
-// gridDim.y-th group of the cell's atoms (small or skewed cells have few
-// cells with large stencils); the centroids of the cell's stencil cells
+// Candidate rows.  `split` work items per cell, each taking every
+// split-th group of the cell's atoms (small or skewed cells have few
+// cells with large stencils), looped over by a capped grid; the centroids of the cell's stencil cells
 // (3 x 3 x 3, fewer along an axis with fewer than 3 cells) are staged in
 // LDS when they fit, and each wavefront takes one atom at a time, its lanes
 // testing 64 stencil atoms at once and appending the accepted ones by
@@ -446,7 +477,8 @@ __device__ void sort_row_into(int32_t *__restrict__ dst, int n, const int32_t *_
 // which k_union sorts).  A stencil too large for LDS is read from global
 // memory instead.
 constexpr int kStage = 2048;
-constexpr int kCandSplitMax = 16;   // workgroups per cell at most
+constexpr int kCandSplitMax = 16;   // work items per cell at most
+constexpr int kCandGrid = 256;      // workgroups of the candidate search
 __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ cen, const int32_t *__restrict__ types,
                                                     int N, int S, const SysGeom *__restrict__ geom,
                                                     const int32_t *__restrict__ cell_sys, uint32_t *__restrict__ grid,
@@ -455,122 +487,129 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
                                                     int32_t *__restrict__ cell_cnt, int capR, int capA,
                                                     int32_t *__restrict__ candR, int32_t *__restrict__ lenR,
                                                     int32_t *__restrict__ candA, int32_t *__restrict__ lenA,
-                                                    double *__restrict__ cen_ref, uint32_t *__restrict__ status)
+                                                    double *__restrict__ cen_ref, uint32_t *__restrict__ status,
+                                                    int ncell_total, int split)
 {
     __shared__ double sx[kStage], sy[kStage], sz[kStage];
     __shared__ int32_t sw[kStage];
     __shared__ int32_t rs[28], rp[28];
     __shared__ int nrange;
     DevGlobal *dg = dev_global(grid);
-    const int sy_ = cell_sys[blockIdx.x];
-    const SysGeom &g = geom[sy_];
-    const DevSys ds = *dev_sys(grid, sy_);
-    const int c = blockIdx.x - g.cell_base;   // cell within its system
-    if (!dg->rebuild || c >= ds.ncell) return;   // whole workgroup
-    if (threadIdx.x == 0 && blockIdx.y == 0) cell_cnt[blockIdx.x] = 0;   // counts start from zero at the next rebuild
-    const int nc0 = ds.nc[0], nc1 = ds.nc[1], nc2 = ds.nc[2];
+    if (!dg->rebuild) return;   // whole workgroup: most calls keep their rows
     const double R2 = dg->R2, RA2 = dg->RA2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (threadIdx.x == 0) {
-        const int cx = c % nc0, cy = (c / nc0) % nc1, cz = c / (nc0 * nc1);
-        const int oz_n = nc2 >= 3 ? 3 : nc2, oy_n = nc1 >= 3 ? 3 : nc1, ox_n = nc0 >= 3 ? 3 : nc0;
-        int nr = 0, tot = 0;
-        for (int oz = 0; oz < oz_n; ++oz) {
-            int z = nc2 >= 3 ? cz + oz - 1 : oz;
-            z = z < 0 ? z + nc2 : (z >= nc2 ? z - nc2 : z);
-            for (int oy = 0; oy < oy_n; ++oy) {
-                int y = nc1 >= 3 ? cy + oy - 1 : oy;
-                y = y < 0 ? y + nc1 : (y >= nc1 ? y - nc1 : y);
-                for (int ox = 0; ox < ox_n; ++ox) {
-                    int x = nc0 >= 3 ? cx + ox - 1 : ox;
-                    x = x < 0 ? x + nc0 : (x >= nc0 ? x - nc0 : x);
-                    const int cc = g.cell_base + (z * nc1 + y) * nc0 + x;
-                    rs[nr] = cell_start[cc];
-                    rp[nr] = tot;
-                    tot += cell_start[cc + 1] - cell_start[cc];
-                    ++nr;
-                }
-            }
-        }
-        rp[nr] = tot;
-        nrange = nr;
-    }
-    __syncthreads();
-    const int nr = nrange, total = rp[nr];
-    const bool staged = total <= kStage;
-    // flat stencil position q -> index into cell_atoms (the last range starting at or before q)
-    auto at = [&](int q) {
-        int lo = 0, hi = nr - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (rp[mid] <= q) lo = mid;
-            else hi = mid - 1;
-        }
-        return rs[lo] + (q - rp[lo]);
-    };
-    if (staged) {
-        for (int q = threadIdx.x; q < total; q += blockDim.x) {
-            const int j = cell_atoms[at(q)];
-            const int tj = types[j];
-            sx[q] = cen[3 * j];
-            sy[q] = cen[3 * j + 1];
-            sz[q] = cen[3 * j + 2];
-            sw[q] = (tj >= 0 && tj < S) ? ((j << 2) | tj) : -1;
-        }
-    }
-    __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int a0 = cell_start[blockIdx.x], a1 = cell_start[blockIdx.x + 1];
     const int waves = blockDim.x >> 6;
-    for (int a = a0 + blockIdx.y * waves + wv; a < a1; a += gridDim.y * waves) {
-        const int i = cell_atoms[a];
-        const double ci[3] = {cen[3 * i], cen[3 * i + 1], cen[3 * i + 2]};
-        int32_t *rowR = candR + (size_t)i * capR;
-        int32_t *rowA = candA + (size_t)i * capA;
-        int cR = 0, cA = 0;
-        for (int q0 = 0; q0 < total; q0 += 64) {
-            const int q = q0 + lane;
-            bool okR = false, okA = false;
-            int w = -1;
-            if (q < total) {
-                double p[3];
-                if (staged) {
-                    p[0] = sx[q]; p[1] = sy[q]; p[2] = sz[q];
-                    w = sw[q];
-                } else {
-                    const int j = cell_atoms[at(q)];
-                    const int tj = types[j];
-                    p[0] = cen[3 * j]; p[1] = cen[3 * j + 1]; p[2] = cen[3 * j + 2];
-                    w = (tj >= 0 && tj < S) ? ((j << 2) | tj) : -1;
-                }
-                if (w >= 0 && (w >> 2) != i) {
-                    double d[3] = {p[0] - ci[0], p[1] - ci[1], p[2] - ci[2]};
-                    mic_vec(d, g, g.tri);
-                    const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-                    okR = r2 < R2;
-                    okA = r2 < RA2;
+    // work items (cell, part), part = which of the cell's atoms
+    for (int item = blockIdx.x; item < ncell_total * split; item += gridDim.x) {
+        const int cell = item / split, part = item - cell * split;
+        const int sy_ = cell_sys[cell];
+        const SysGeom &g = geom[sy_];
+        const DevSys ds = *dev_sys(grid, sy_);
+        const int c = cell - g.cell_base;   // cell within its system
+        if (c >= ds.ncell) continue;        // whole workgroup
+        if (threadIdx.x == 0 && part == 0) cell_cnt[cell] = 0;   // counts start from zero at the next rebuild
+        const int nc0 = ds.nc[0], nc1 = ds.nc[1], nc2 = ds.nc[2];
+        if (threadIdx.x == 0) {
+            const int cx = c % nc0, cy = (c / nc0) % nc1, cz = c / (nc0 * nc1);
+            const int oz_n = nc2 >= 3 ? 3 : nc2, oy_n = nc1 >= 3 ? 3 : nc1, ox_n = nc0 >= 3 ? 3 : nc0;
+            int nr = 0, tot = 0;
+            for (int oz = 0; oz < oz_n; ++oz) {
+                int z = nc2 >= 3 ? cz + oz - 1 : oz;
+                z = z < 0 ? z + nc2 : (z >= nc2 ? z - nc2 : z);
+                for (int oy = 0; oy < oy_n; ++oy) {
+                    int y = nc1 >= 3 ? cy + oy - 1 : oy;
+                    y = y < 0 ? y + nc1 : (y >= nc1 ? y - nc1 : y);
+                    for (int ox = 0; ox < ox_n; ++ox) {
+                        int x = nc0 >= 3 ? cx + ox - 1 : ox;
+                        x = x < 0 ? x + nc0 : (x >= nc0 ? x - nc0 : x);
+                        const int cc = g.cell_base + (z * nc1 + y) * nc0 + x;
+                        rs[nr] = cell_start[cc];
+                        rp[nr] = tot;
+                        tot += cell_start[cc + 1] - cell_start[cc];
+                        ++nr;
+                    }
                 }
             }
-            const uint64_t mR = __ballot(okR), mA = __ballot(okA);
-            const int pR = cR + __popcll(mR & below), pA = cA + __popcll(mA & below);
-            if (okR && pR < capR) rowR[pR] = w;
-            if (okA && pA < capA) rowA[pA] = w;
-            cR += __popcll(mR);
-            cA += __popcll(mA);
+            rp[nr] = tot;
+            nrange = nr;
         }
-        if (lane == 0) {
-            lenR[i] = cR;
-            lenA[i] = cA;
-            cen_ref[3 * i] = ci[0];
-            cen_ref[3 * i + 1] = ci[1];
-            cen_ref[3 * i + 2] = ci[2];
-            raise_max(&status[3], (uint32_t)cR);
-            raise_max(&status[6], (uint32_t)cA);
-            if (cR > capR || cA > capA) {
-                atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
-                atomicOr(&dg->rows_overflow, 1u);
+        __syncthreads();
+        const int nr = nrange, total = rp[nr];
+        const bool staged = total <= kStage;
+        // flat stencil position q -> index into cell_atoms (the last range starting at or before q)
+        auto at = [&](int q) {
+            int lo = 0, hi = nr - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (rp[mid] <= q) lo = mid;
+                else hi = mid - 1;
+            }
+            return rs[lo] + (q - rp[lo]);
+        };
+        if (staged) {
+            for (int q = threadIdx.x; q < total; q += blockDim.x) {
+                const int j = cell_atoms[at(q)];
+                const int tj = types[j];
+                sx[q] = cen[3 * j];
+                sy[q] = cen[3 * j + 1];
+                sz[q] = cen[3 * j + 2];
+                sw[q] = (tj >= 0 && tj < S) ? ((j << 2) | tj) : -1;
             }
         }
+        __syncthreads();
+        const int a0 = cell_start[cell], a1 = cell_start[cell + 1];
+        for (int a = a0 + part * waves + wv; a < a1; a += split * waves) {
+            const int i = cell_atoms[a];
+            const double ci[3] = {cen[3 * i], cen[3 * i + 1], cen[3 * i + 2]};
+            int32_t *rowR = candR + (size_t)i * capR;
+            int32_t *rowA = candA + (size_t)i * capA;
+            int cR = 0, cA = 0;
+            for (int q0 = 0; q0 < total; q0 += 64) {
+                const int q = q0 + lane;
+                bool okR = false, okA = false;
+                int w = -1;
+                if (q < total) {
+                    double p[3];
+                    if (staged) {
+                        p[0] = sx[q]; p[1] = sy[q]; p[2] = sz[q];
+                        w = sw[q];
+                    } else {
+                        const int j = cell_atoms[at(q)];
+                        const int tj = types[j];
+                        p[0] = cen[3 * j]; p[1] = cen[3 * j + 1]; p[2] = cen[3 * j + 2];
+                        w = (tj >= 0 && tj < S) ? ((j << 2) | tj) : -1;
+                    }
+                    if (w >= 0 && (w >> 2) != i) {
+                        double d[3] = {p[0] - ci[0], p[1] - ci[1], p[2] - ci[2]};
+                        mic_vec(d, g, g.tri);
+                        const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+                        okR = r2 < R2;
+                        okA = r2 < RA2;
+                    }
+                }
+                const uint64_t mR = __ballot(okR), mA = __ballot(okA);
+                const int pR = cR + __popcll(mR & below), pA = cA + __popcll(mA & below);
+                if (okR && pR < capR) rowR[pR] = w;
+                if (okA && pA < capA) rowA[pA] = w;
+                cR += __popcll(mR);
+                cA += __popcll(mA);
+            }
+            if (lane == 0) {
+                lenR[i] = cR;
+                lenA[i] = cA;
+                cen_ref[3 * i] = ci[0];
+                cen_ref[3 * i + 1] = ci[1];
+                cen_ref[3 * i + 2] = ci[2];
+                raise_max(&status[3], (uint32_t)cR);
+                raise_max(&status[6], (uint32_t)cA);
+                if (cR > capR || cA > capA) {
+                    atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
+                    atomicOr(&dg->rows_overflow, 1u);
+                }
+            }
+        }
+        __syncthreads();   // the stencil records and staged centroids are rewritten by the next item
     }
 }
 
@@ -593,6 +632,7 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
 // is written back to its candidate's lane, and the kept candidates are
 // appended with one ballot-ranked store per lane.
 constexpr double kShellEps = 1e-3;   // A; far above the rounding of d and s
+constexpr int kUnionRounds = 4;      // shell rounds whose partner loads are in flight together
 
 template <bool TRI>
 __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, const float4 *__restrict__ pos4,
@@ -676,35 +716,53 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
             const int j = kin ? row[k] >> 2 : i;
             double dv[3] = {cen[3 * (size_t)j] - ci0, cen[3 * (size_t)j + 1] - ci1, cen[3 * (size_t)j + 2] - ci2};
             mic_vec(dv, g, tri);
-            const double d = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+            // d + s < rc - eps and d - s > rc + eps, on squares
+            const double d2 = dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2];
             const double sp = si + (double)spr[j];
-            const bool all_in = kin && d + sp < rc - kShellEps;
-            const bool shell = kin && !all_in && !(d - sp > rc + kShellEps);
+            const double lo = rc - kShellEps - sp, hi = rc + kShellEps + sp;
+            const bool all_in = kin && lo > 0.0 && d2 < lo * lo;
+            const bool shell = kin && !all_in && !(d2 > hi * hi);
             int mlo = 0, mhi = 0;
             uint64_t rem = __ballot(shell);
             while (rem) {
-                // the next CPW shell candidates, one per group of G lanes
-                uint64_t take = rem;
-                int my = 0, nq = 0;
-                for (int q = 0; q < CPW && rem; ++q) {
-                    const int sq = __builtin_ctzll(rem);
-                    rem &= rem - 1;
-                    if (q == cg) my = sq;
-                    nq = q + 1;
+                // kUnionRounds rounds of the next CPW shell candidates (one
+                // per group of G lanes), their partners' positions loaded
+                // together; rounds past the last candidate load lane 0's
+                // partner and test nothing
+                uint64_t take[kUnionRounds];
+                int nq[kUnionRounds], jq[kUnionRounds];
+#pragma unroll
+                for (int u = 0; u < kUnionRounds; ++u) {
+                    take[u] = rem;
+                    int my = 0, n = 0;
+                    for (int q = 0; q < CPW && rem; ++q) {
+                        const int sq = __builtin_ctzll(rem);
+                        rem &= rem - 1;
+                        if (q == cg) my = sq;
+                        n = q + 1;
+                    }
+                    nq[u] = n;
+                    jq[u] = __shfl(j, my, 64);
                 }
-                const int jq = __shfl(j, my, 64);
-                float ex, ey, ez;
-                packed_pair_g(pos4[(size_t)jq * P + bb], pi, g, tri, ex, ey, ez);
-                const float r2f = ex * ex + ey * ey + ez * ez;
-                const bool in = cg < nq && bead_ok && pair_within(r2f, c, pb, i, jq, g, tri);
-                const uint64_t m = __ballot(in);
-                for (int q = 0; q < nq; ++q) {
-                    const int sq = __builtin_ctzll(take);
-                    take &= take - 1;
-                    const uint64_t gm = (m >> (q * G)) & gmask;
-                    if (lane == sq) {
-                        mlo = (int)(uint32_t)gm;
-                        mhi = (int)(uint32_t)(gm >> 32);
+                float4 pj[kUnionRounds];
+#pragma unroll
+                for (int u = 0; u < kUnionRounds; ++u) pj[u] = pos4[(size_t)jq[u] * P + bb];
+#pragma unroll
+                for (int u = 0; u < kUnionRounds; ++u) {
+                    float ex, ey, ez;
+                    packed_pair_g(pj[u], pi, g, tri, ex, ey, ez);
+                    const float r2f = ex * ex + ey * ey + ez * ez;
+                    const bool in = cg < nq[u] && bead_ok && pair_within(r2f, c, pb, i, jq[u], g, tri);
+                    const uint64_t m = __ballot(in);
+                    uint64_t tk = take[u];
+                    for (int q = 0; q < nq[u]; ++q) {
+                        const int sq = __builtin_ctzll(tk);
+                        tk &= tk - 1;
+                        const uint64_t gm = (m >> (q * G)) & gmask;
+                        if (lane == sq) {
+                            mlo = (int)(uint32_t)gm;
+                            mhi = (int)(uint32_t)(gm >> 32);
+                        }
                     }
                 }
             }
@@ -881,25 +939,27 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
     // a per-axis scaling of an orthorhombic cell is covered by the device-side skin test
     const bool force = !nl->built || tri_changed;
     const dim3 gw(div_up(N, kBlock / 64));
-    // enough workgroups for the candidate search even when the cells are few
-    const dim3 gc(nl->ncell_total, std::min(kCandSplitMax, std::max(1, div_up(1024, nl->ncell_total))));
+    // enough work items for the candidate search even when the cells are few;
+    // a grid of at most kCandGrid workgroups loops over them (on most calls
+    // the rows are kept and every workgroup returns at once)
+    const int split = std::min(kCandSplitMax, std::max(1, div_up(1024, nl->ncell_total)));
+    const dim3 gc(std::min(kCandGrid, nl->ncell_total * split));
     {
         ProfScope ps_(K_CENTROID, s);
-        hipLaunchKernelGGL(k_centroid, dim3(div_up(N * kCenLanes, kBlock)), dim3(kBlock), 0, s, pos, types,
-                           nl->atom_sys, P, N, nl->S, nl->cen, nl->spr,
-                           nl->cen_ref,
-                           nl->geom, nl->nsys, m->hp.rc_radial, m->hp.rc_angular, nl->skin, force ? 1 : 0, nl->grid,
-                           nl->status, reinterpret_cast<float4 *>(nl->pos4));
+        const int nblk = div_up(N * kCenLanes, kBlock);
+        hipLaunchKernelGGL(k_centroid, dim3(nblk), dim3(kBlock), 0, s, pos, types, nl->atom_sys, P, N, nl->S,
+                           nl->cen, nl->spr, nl->cen_ref, nl->geom, nl->grid, nl->status,
+                           reinterpret_cast<float4 *>(nl->pos4), nl->cmax);
         hipLaunchKernelGGL(k_decide, dim3(1), dim3(kDecideBlock), 0, s, nl->geom, nl->nsys, m->hp.rc_radial,
                            m->hp.rc_angular, nl->skin, force ? 1 : 0, nl->grid, nl->status, nl->cen, N, nl->atom_sys,
-                           nl->ncell_total, nl->cell_cnt, nl->cell_start, nl->cell_atoms);
+                           nl->ncell_total, nl->cell_cnt, nl->cell_start, nl->cell_atoms, nl->cmax, nblk);
     }
     {
         ProfScope ps_(K_CANDIDATES, s);
         hipLaunchKernelGGL(k_candidates, gc, dim3(kBlock), 0, s, nl->cen, types, N, nl->S, nl->geom, nl->cell_sys,
                            nl->grid, nl->cell_start, nl->cell_atoms, nl->cell_cnt, nl->capR, nl->capA, nl->candRs,
                            nl->lenR,
-                           nl->candAs, nl->lenA, nl->cen_ref, nl->status);
+                           nl->candAs, nl->lenA, nl->cen_ref, nl->status, nl->ncell_total, split);
     }
     {
         ProfScope ps_(K_NLIST, s);

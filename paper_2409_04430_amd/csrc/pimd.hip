@@ -82,7 +82,7 @@ __device__ __forceinline__ void box_muller(uint32_t x0, uint32_t x1, double &zc,
     const double u1 = ((double)x1 + 1.0) * s;
     const double rad = sqrt(-2.0 * log(u0));
     double sn, cs;
-    sincos(2.0 * M_PI * u1, &sn, &cs);
+    sincospi(2.0 * u1, &sn, &cs);   // the angle 2 pi u1, without a range reduction by pi
     zc = rad * cs;
     zs = rad * sn;
 }
@@ -238,32 +238,38 @@ __global__ __launch_bounds__(kStepBlock) void k_trpmd(StepArgs a, const double *
 // The same stage with the mode transforms on the matrix cores, for P a
 // multiple of 16: both transforms are products with the P x P matrix C over
 // a block of elements, (C^T X) and (C X~), done as 16 x 16 x 4 FP64 tiles.
-// One wavefront takes 16 elements and one 16-mode tile: the bead values
-// come straight from the bead-major arrays as B fragments (16 consecutive
-// elements of one bead per lane group), the per-mode update runs on the
-// result tile (lane j + 16 g holds modes g, g + 4, g + 8, g + 12 of the tile
-// for element j), the new mode vectors of all mode tiles meet in LDS, and
-// each wavefront back-transforms one 16-bead tile.  The tile's thermostat
-// normals (16 elements x 16 modes, 16 x 4 Philox blocks per draw) are drawn
-// once each: lane j + 16 g draws block 4 mt + g of element j and leaves its
-// four normals in LDS for the lanes that hold those modes.  FP64 fragment
-// layout: A(i, k) in lane i + 16 k, B(k, j) in lane j + 16 k, result (i, j)
-// in lane j + 16 (i % 4), slot i / 4.
+// A pair of wavefronts takes 16 elements and one 16-mode tile, each summing
+// over half of the beads (forward) and half of the modes (back): the bead
+// values come straight from the bead-major arrays as B fragments (16
+// consecutive elements of one bead per lane group); the second wavefront's
+// partial tiles meet the first's in LDS, in a fixed order; the per-mode
+// update runs on the result tile (lane j + 16 g holds modes g, g + 4, g + 8,
+// g + 12 of the tile for element j); the new mode vectors of all mode tiles
+// meet in LDS, and each pair back-transforms one 16-bead tile.  The tile's
+// thermostat normals (16 elements x 16 modes, 16 x 4 Philox blocks per
+// draw) are drawn once each, the two draws of the fused stage by the two
+// wavefronts of the pair: lane j + 16 g draws block 4 mt + g of element j
+// and leaves its four normals in LDS for the lanes that hold those modes.
+// FP64 fragment layout: A(i, k) in lane i + 16 k, B(k, j) in lane j + 16 k,
+// result (i, j) in lane j + 16 (i % 4), slot i / 4.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
-// Workgroup: ET element tiles x MT mode tiles, one wavefront each (4 or 3).
+// Workgroup: ET element tiles x MT mode tiles x 2 halves, one wavefront each (8 or 6).
 template <int P> constexpr int step_mf_et() { return P == 48 ? 1 : 64 / P; }
+constexpr int kStepHalves = 2;
 
 template <int P>
-__global__ __launch_bounds__(64 * 4) void k_trpmd_mf(StepArgs a, const double *__restrict__ cst)
+__global__ __launch_bounds__(64 * 8) void k_trpmd_mf(StepArgs a, const double *__restrict__ cst)
 {
     static_assert(P % 16 == 0 && P <= 64, "matrix-core stage needs P = 16, 32, 48 or 64");
-    constexpr int MT = P / 16, KS = P / 4, ET = step_mf_et<P>();
-    __shared__ double xt[ET][2][P][16];   // new mode vectors v~, q~ of each element tile
-    __shared__ double zn[ET * MT][2][16][16];   // thermostat normals [wavefront][draw][mode in tile][element]
+    constexpr int MT = P / 16, KS = P / 4, ET = step_mf_et<P>(), NT = ET * MT, KH = KS / kStepHalves;
+    __shared__ double xt[ET][2][P][16];        // new mode vectors v~, q~ of each element tile
+    __shared__ double zn[NT][2][16][16];       // thermostat normals [tile][draw][mode in tile][element]
+    __shared__ f64x4 part[NT][3][64];          // the second half's partial tiles (forward v, f, q; back v, q)
     const PimdLayout Lo(P);
     const int M = 3 * a.N;
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lg = l >> 4;
-    const int et = wv / MT, mt = wv - et * MT;   // this wavefront's element tile and 16-mode (16-bead) tile
+    const int tile = wv % NT, half = wv / NT;
+    const int et = tile / MT, mt = tile - et * MT;   // this pair's element tile and 16-mode (16-bead) tile
     const int e0 = (blockIdx.x * ET + et) * 16;
     const int e = e0 + lr;
     const bool ok = e < M;
@@ -272,98 +278,106 @@ __global__ __launch_bounds__(64 * 4) void k_trpmd_mf(StepArgs a, const double *_
     // the next step's counter (a different word: every workgroup reads step_dev)
     if (a.step_out && post && blockIdx.x == 0 && threadIdx.x == 0) *a.step_out = step + 1;
     const double *C = cst + Lo.C;   // C[b * P + k]
+    const int ks0 = half * KH;      // this wavefront's beads (forward) and modes (back): 4 ks + lg
 
     // bead values of the element tile, all loads in flight at once (lanes
     // past the last element read element 0 and drop it) and issued before
     // the noise draws, which do not depend on them
-    double xv[KS], xq[KS], cf[KS], cb[KS];
-    float xf[KS];
+    double xv[KH], xq[KH], cf[KH], cb[KH];
+    float xf[KH];
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
+    for (int h = 0; h < KH; ++h) {
+        const int ks = ks0 + h;
         const size_t at = (size_t)(4 * ks + lg) * M + (ok ? e : 0);
-        xv[ks] = a.vel[at];
-        xf[ks] = a.F[at];
-        xq[ks] = pre ? a.pos[at] : 0.0;
-        cf[ks] = C[(size_t)(4 * ks + lg) * P + 16 * mt + lr];   // C^T(mode 16 mt + lr, bead 4 ks + lg)
-        cb[ks] = C[(size_t)(16 * mt + lr) * P + 4 * ks + lg];   // C(bead 16 mt + lr, mode 4 ks + lg)
+        xv[h] = a.vel[at];
+        xf[h] = a.F[at];
+        xq[h] = pre ? a.pos[at] : 0.0;
+        cf[h] = C[(size_t)(4 * ks + lg) * P + 16 * mt + lr];   // C^T(mode 16 mt + lr, bead 4 ks + lg)
+        cb[h] = C[(size_t)(16 * mt + lr) * P + 4 * ks + lg];   // C(bead 16 mt + lr, mode 4 ks + lg)
     }
     const int i = e / 3, comp = e - 3 * i;
-    const double mi = a.mass[ok ? i : 0];
-    // per-mode constants of this lane's four modes k = 16 mt + lg + 4 s4
-    double kc1[4], ksc2[4], kcq[4], kqv[4], kvq[4];
-#pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-        const int k = 16 * mt + lg + 4 * s4;
-        kc1[s4] = cst[Lo.c1 + k];
-        ksc2[s4] = cst[Lo.sc2 + k];
-        kcq[s4] = pre ? cst[Lo.cq + k] : 0.0;
-        kqv[s4] = pre ? cst[Lo.qv + k] : 0.0;
-        kvq[s4] = pre ? cst[Lo.vq + k] : 0.0;
-    }
     const int NB = (P + 3) / 4;
     const bool fused = a.stage == PIMD_STAGE_FUSED;
-    if (a.noise) {
-        // draw 0: (step, closing half, or the stage's own half); the fused
-        // stage's draw 1: (step + 1, opening half)
-#pragma unroll 1
-        for (int d = 0; d < (fused ? 2 : 1); ++d) {
-            double z4[4];
-            normal4(a.seed, (uint64_t)step + (uint64_t)d, fused ? 1 - d : (post ? 1 : 0), i, comp, NB, 4 * mt + lg, z4);
+    if (a.noise && (fused || half == 0)) {
+        // draw 0 (first half): (step, closing half, or the stage's own half);
+        // the fused stage's draw 1 (second half): (step + 1, opening half)
+        const int d = half;
+        double z4[4];
+        normal4(a.seed, (uint64_t)step + (uint64_t)d, fused ? 1 - d : (post ? 1 : 0), i, comp, NB, 4 * mt + lg, z4);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) zn[wv][d][4 * lg + q][lr] = z4[q];
-        }
+        for (int q = 0; q < 4; ++q) zn[tile][d][4 * lg + q][lr] = z4[q];
     }
-    __syncthreads();   // the normals of the tile are in LDS
 
-    // forward, modes 16 mt .. 16 mt + 15: v~ = C^T v, f~ = C^T F, q~ = C^T q
+    // forward, modes 16 mt .. 16 mt + 15, this half's beads: v~ = C^T v, f~ = C^T F, q~ = C^T q
     f64x4 vt = {0.0, 0.0, 0.0, 0.0}, ft = {0.0, 0.0, 0.0, 0.0}, qt = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        vt = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[ks], ok ? xv[ks] : 0.0, vt, 0, 0, 0);
-        ft = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[ks], ok ? (double)xf[ks] : 0.0, ft, 0, 0, 0);
-        if (pre) qt = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[ks], ok ? xq[ks] : 0.0, qt, 0, 0, 0);
+    for (int h = 0; h < KH; ++h) {
+        vt = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[h], ok ? xv[h] : 0.0, vt, 0, 0, 0);
+        ft = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[h], ok ? (double)xf[h] : 0.0, ft, 0, 0, 0);
+        if (pre) qt = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[h], ok ? xq[h] : 0.0, qt, 0, 0, 0);
     }
+    if (half == 1) {
+        part[tile][0][l] = vt;
+        part[tile][1][l] = ft;
+        part[tile][2][l] = qt;
+    }
+    __syncthreads();   // the normals and the second half's partial tiles are in LDS
 
-    // per (mode, element): thermostat, kicks and the Cayley map
-    const double m = ok ? mi : 1.0;
-    const double hk = 0.5 * a.dt / (m * a.conv);
-    const double sig = sqrt(a.kTP / (m * a.conv));
+    if (half == 0) {
+        vt += part[tile][0][l];
+        ft += part[tile][1][l];
+        if (pre) qt += part[tile][2][l];
+        const double mi = a.mass[ok ? i : 0];
+        const double m = ok ? mi : 1.0;
+        const double hk = 0.5 * a.dt / (m * a.conv);
+        const double sig = sqrt(a.kTP / (m * a.conv));
+        // per (mode, element): thermostat, kicks and the Cayley map, for
+        // this lane's four modes k = 16 mt + lg + 4 s4
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-        const int k = 16 * mt + lg + 4 * s4;
-        const double c1 = kc1[s4];
-        double alpha = c1, beta = 1.0, gamma = 0.0;
-        if (a.stage == PIMD_STAGE_POST) beta = c1;
-        if (a.stage == PIMD_STAGE_FUSED) {
-            alpha = c1 * c1;
-            beta = c1 * c1 + 1.0;
+        for (int s4 = 0; s4 < 4; ++s4) {
+            const int k = 16 * mt + lg + 4 * s4;
+            const double c1 = cst[Lo.c1 + k];
+            double alpha = c1, beta = 1.0, gamma = 0.0;
+            if (a.stage == PIMD_STAGE_POST) beta = c1;
+            if (fused) {
+                alpha = c1 * c1;
+                beta = c1 * c1 + 1.0;
+            }
+            if (a.noise && ok) {
+                // normal k & 3 of block k >> 2: mode k - 16 mt = lg + 4 s4 of the tile
+                const double gs = sig * cst[Lo.sc2 + k];
+                const double z1 = zn[tile][0][lg + 4 * s4][lr];
+                gamma = fused ? gs * (c1 * z1 + zn[tile][1][lg + 4 * s4][lr]) : gs * z1;
+            }
+            const double v1 = alpha * vt[s4] + gamma + beta * (hk * ft[s4]);
+            double vn = v1, qn = 0.0;
+            if (pre) {
+                const double cq = cst[Lo.cq + k], qv = cst[Lo.qv + k], vq = cst[Lo.vq + k];
+                qn = cq * qt[s4] + qv * v1;
+                vn = cq * v1 - vq * qt[s4];
+            }
+            xt[et][0][k][lr] = vn;
+            xt[et][1][k][lr] = qn;
         }
-        if (a.noise && ok) {
-            // normal k & 3 of block k >> 2: mode k - 16 mt = lg + 4 s4 of the tile
-            const double gs = sig * ksc2[s4];
-            const double z1 = zn[wv][0][lg + 4 * s4][lr];
-            gamma = fused ? gs * (c1 * z1 + zn[wv][1][lg + 4 * s4][lr]) : gs * z1;
-        }
-        const double v1 = alpha * vt[s4] + gamma + beta * (hk * ft[s4]);
-        double vn = v1, qn = 0.0;
-        if (pre) {
-            qn = kcq[s4] * qt[s4] + kqv[s4] * v1;
-            vn = kcq[s4] * v1 - kvq[s4] * qt[s4];
-        }
-        xt[et][0][k][lr] = vn;
-        xt[et][1][k][lr] = qn;
     }
-    __syncthreads();   // every mode tile of the element tile is in LDS
+    __syncthreads();   // every mode tile of the element tile is in LDS; part is free
 
-    // back transform, beads 16 mt .. 16 mt + 15: v = C v~, q = C q~
+    // back transform, beads 16 mt .. 16 mt + 15, this half's modes: v = C v~, q = C q~
     f64x4 vb = {0.0, 0.0, 0.0, 0.0}, qb = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        const int k = 4 * ks + lg;
-        vb = __builtin_amdgcn_mfma_f64_16x16x4f64(cb[ks], xt[et][0][k][lr], vb, 0, 0, 0);
-        if (pre) qb = __builtin_amdgcn_mfma_f64_16x16x4f64(cb[ks], xt[et][1][k][lr], qb, 0, 0, 0);
+    for (int h = 0; h < KH; ++h) {
+        const int k = 4 * (ks0 + h) + lg;
+        vb = __builtin_amdgcn_mfma_f64_16x16x4f64(cb[h], xt[et][0][k][lr], vb, 0, 0, 0);
+        if (pre) qb = __builtin_amdgcn_mfma_f64_16x16x4f64(cb[h], xt[et][1][k][lr], qb, 0, 0, 0);
     }
-    if (ok) {
+    if (half == 1) {
+        part[tile][0][l] = vb;
+        part[tile][1][l] = qb;
+    }
+    __syncthreads();   // the second half's partial tiles are in LDS
+    if (half == 0 && ok) {
+        vb += part[tile][0][l];
+        if (pre) qb += part[tile][1][l];
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
             const size_t at = (size_t)(16 * mt + lg + 4 * s4) * M + e;
@@ -552,7 +566,7 @@ static void launch_step(const StepArgs &a, const double *cst, hipStream_t s)
 #define NEP_STEP_MF(PP)                                                                                     \
     case PP:                                                                                                \
         hipLaunchKernelGGL(k_trpmd_mf<PP>, dim3(div_up(3 * a.N, 16 * step_mf_et<PP>())),                    \
-                           dim3(64 * step_mf_et<PP>() * (PP / 16)), 0, s, a, cst);                          \
+                           dim3(64 * step_mf_et<PP>() * (PP / 16) * kStepHalves), 0, s, a, cst);            \
         return;
     switch (a.P) {   // matrix-core transforms where P is a multiple of 16
         NEP_STEP_MF(16) NEP_STEP_MF(32) NEP_STEP_MF(48) NEP_STEP_MF(64)
