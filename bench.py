@@ -17,6 +17,7 @@ dominant kernel from live hipEvent timings, oracle CPU baseline).
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import math
@@ -65,6 +66,8 @@ def parse():
     ap.add_argument("--student-only", action="store_true",
                     help="run only the learned-student leg (prints its JSON object)")
     ap.add_argument("--student-epochs", type=int, default=200)
+    ap.add_argument("--student-batch", type=int, default=8,
+                    help="labelled snapshots per gradient call (a batch of systems) and Adam step")
     ap.add_argument("--student-steps", type=int, default=100, help="timed steps of the student and teacher runs")
     return ap.parse_args()
 
@@ -331,10 +334,13 @@ def student_leg(args, torch, lib, configs, I):
     """Learned student against its teacher on the 32,000-atom FCC crystal x 32 beads.
 
     Teacher labels come from teacher NEP-PIMD of a 4x4x4-cell crystal
-    (256 atoms x 32 beads) at 300, 500 and 700 K; the student is trained on
-    them on the device, then both models drive NEP-PIMD of the large crystal
+    (256 atoms x 32 beads) at 300, 500 and 700 K, about 20,000 bead
+    snapshots; the student is trained on them on the device (energy, force
+    and virial loss), then both models drive NEP-PIMD of the large crystal
     at 500 K; the student run is judged by the teacher every 50 steps
-    (fallback above 20 meV/A), and its timed steps include the judgements."""
+    (fallback above 20 meV/A), and its timed steps include the judgements.
+    Held-out check: judged student runs of the large crystal at 300 and
+    700 K as well."""
     from paper_2409_04430_amd.engine import NepPimd
     from paper_2409_04430_amd.student import StudentPimd, StudentTrainer, teacher_snapshots
     w = configs.WORKLOADS["fcc32000"]
@@ -349,13 +355,14 @@ def student_leg(args, torch, lib, configs, I):
         return I.make_system(p0, t, b, w.species_masses, P, T, 0.05, np.random.default_rng(int(T)))
 
     t0 = time.perf_counter()
-    store = teacher_snapshots(tpath, small, [300.0, 500.0, 700.0], steps=120, every=6, warmup=30, dt=w.dt)
+    store = teacher_snapshots(tpath, small, [300.0, 500.0, 700.0], steps=1254, every=6, warmup=30, dt=w.dt)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     s0 = small(300.0)
-    tr = StudentTrainer(spath, store, s0.types, s0.box, lambdas=(0.1, 1.0, 0.0), holdout=0.15)
+    lambdas = (0.1, 1.0, 0.1)
+    tr = StudentTrainer(spath, store, s0.types, s0.box, lambdas=lambdas, holdout=0.15)
     t0 = time.perf_counter()
-    tr.fit(args.student_epochs, lr0=1e-2, lr1=3e-4, every=max(1, args.student_epochs))
+    tr.fit(args.student_epochs, lr0=2e-2, lr1=1e-4, batch=args.student_batch, every=max(1, args.student_epochs))
     t_train = time.perf_counter() - t0
     val = tr.log[-1].val_rmse_F
     trained = os.path.join(tmp, "student_trained.nep")
@@ -388,6 +395,17 @@ def student_leg(args, torch, lib, configs, I):
     ms_s = timed(student, n)
     student.check()
     units = big.N * P
+    # the other temperatures of the training data, on the large crystal
+    held_out = {}
+    for T2 in (300.0, 700.0):
+        big2 = dataclasses.replace(w, T=T2).systems(P=P)[0]
+        st2 = StudentPimd(tpath, trained, big2, dt=w.dt, T=T2, tau=w.tau_T, mode=w.mode, seed=w.seed,
+                          judge_every=50, threshold=0.020)
+        st2.run(110)
+        st2.check()
+        held_out[f"{int(T2)}K"] = {"judged_rmse_meV_A": [round(1e3 * r, 3) for _, r in st2.history],
+                                   "fallback_step": st2.fallback_step}
+        del st2
     return {
         "workload": f"fcc32000_p{P}", "atoms": big.N, "beads": P, "T_K": T, "mode": w.mode, "dt_fs": w.dt,
         "teacher": {"value": round(units / (ms_t * 1e-3), 1), "ms_per_step": round(ms_t, 4),
@@ -396,11 +414,13 @@ def student_leg(args, torch, lib, configs, I):
                     "model": "n_max 4/4, l_max 4, 30 hidden, BF16 MFMA network",
                     "judge_every": 50, "threshold_meV_A": 20.0,
                     "judged_rmse_meV_A": [round(1e3 * r, 3) for _, r in student.history],
-                    "fallback_step": student.fallback_step},
+                    "fallback_step": student.fallback_step, "other_temperatures": held_out},
         "gain": round(ms_t / ms_s, 3),
         "training": {"bead_snapshots": store.bead_snapshots(), "atoms": store.N, "temperatures_K": [300, 500, 700],
-                     "epochs": len(tr.log) and tr.log[-1].epoch, "seconds": round(t_train, 2),
+                     "epochs": len(tr.log) and tr.log[-1].epoch, "snapshots_per_step": args.student_batch,
+                     "seconds": round(t_train, 2),
                      "teacher_data_seconds": round(t_data, 2), "val_rmse_meV_A": round(1e3 * val, 3),
+                     "loss_weights_EFW": list(lambdas),
                      "trained": "W0, b0, w1, b1, c_radial, c_angular (Adam)"},
     }
 

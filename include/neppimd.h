@@ -589,6 +589,13 @@ typedef struct nep_train_ws nep_train_ws;
  * trainable (NEP_ERR_UNSUPPORTED).  Errors: NEP_ERR_INVALID_ARG,
  * NEP_ERR_UNSUPPORTED, NEP_ERR_NOMEM. */
 int32_t nep_train_ws_create(const nep_model *model, int32_t P, int32_t N, nep_train_ws **out);
+
+/* Training workspace for a batch of nsys systems (atoms [off[s], off[s+1])
+ * form system s, off host [nsys+1], as for nep_nlist_create_batched), P
+ * configurations each: one nep_param_grad_batched call then covers nsys
+ * independent labelled snapshots.  Errors as nep_train_ws_create. */
+int32_t nep_train_ws_create_batched(const nep_model *model, int32_t P, int32_t nsys, const int32_t *off,
+                                    nep_train_ws **out);
 void nep_train_ws_destroy(nep_train_ws *tw);
 
 /* Loss and parameter gradient for the P configurations pos [P][N][3] (the
@@ -607,6 +614,16 @@ int32_t nep_param_grad(const nep_model *model, nep_nlist *nl, nep_ws *ws, nep_tr
                        const double box[9], const int32_t *types, int32_t P, int32_t N, const double *E_ref,
                        const float *F_ref, const double *W_ref, const double lambda[3], float *grad, double *loss,
                        hipStream_t stream);
+
+/* nep_param_grad over a batch of systems: the list, the workspace and the
+ * training workspace hold the same partition; boxes [nsys][9] (host),
+ * E_ref [nsys][P], F_ref [P][N][3], W_ref [nsys][P][9] (device).  The loss
+ * is the sum of each system's loss above, N its own atom count.  Errors as
+ * nep_param_grad (NEP_ERR_INVALID_ARG when the partitions differ). */
+int32_t nep_param_grad_batched(const nep_model *model, nep_nlist *nl, nep_ws *ws, nep_train_ws *tw,
+                               const double *pos, const double *boxes, const int32_t *types, int32_t P, int32_t N,
+                               const double *E_ref, const float *F_ref, const double *W_ref,
+                               const double lambda[3], float *grad, double *loss, hipStream_t stream);
 
 /* One Adam step (Kingma and Ba, with bias correction) on the model's
  * parameters: theta -= lr mhat / (sqrt(vhat) + eps), for the parameter

@@ -526,7 +526,7 @@ static hipError_t dalloc(T **p, size_t n)
 }
 
 // Validates a batch partition: offsets [nsys+1], non-decreasing from 0.
-static int32_t check_offsets(int32_t nsys, const int32_t *off, const char *who)
+int32_t check_offsets(int32_t nsys, const int32_t *off, const char *who)
 {
     if (nsys < 1 || nsys > 4096 || !off) return fail(NEP_ERR_INVALID_ARG, "%s: bad system count %d", who, nsys);
     if (off[0] != 0) return fail(NEP_ERR_INVALID_ARG, "%s: offsets must start at 0", who);

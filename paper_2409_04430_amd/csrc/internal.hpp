@@ -105,6 +105,10 @@ struct CellInfo {
 bool cell_info(const double box[9], CellInfo &c);
 }  // namespace nep
 
+// Validates a batch partition: offsets [nsys+1], non-decreasing from 0
+// (NEP_OK, or the error code after fail()).
+int32_t check_offsets(int32_t nsys, const int32_t *off, const char *who);
+
 struct nep_nlist {
     int P = 0, N = 0, S = 0;
     int capR = 0, capA = 0;       // candidate row capacities per atom (radial, angular radius)

@@ -5,9 +5,11 @@
 // The NEP site-energy model is that of Sec. II.C of arXiv:2409.04430; the
 // paper fits its models by SNES, this library by gradients.
 //
-// For the P configurations of one call (the beads of a neighbour handle,
-// each with reference E, F, W) the loss is
-//   L = sum_b [ lE (dE_b / N)^2 + lF sum_i |dF_bi|^2 / (3 N) + lW sum_ab (dW_b,ab / N)^2 ].
+// For the P configurations of each system of one call (the beads of a
+// neighbour handle, each with reference E, F, W; a batch of systems is a
+// batch of independent snapshots) the loss is, summed over the systems,
+//   L = sum_b [ lE (dE_b / N)^2 + lF sum_i |dF_bi|^2 / (3 N) + lW sum_ab (dW_b,ab / N)^2 ]
+// with N the system's atom count.
 // Force and virial terms are derivatives of E, so their parameter gradient
 // is a mixed derivative.  With g_ij = dU_i/dr_ij and a per-pair field
 //   d_ij = -(2 lF / 3N) (dF_j - dF_i) - (2 lW / N^2) dW_b^T r_ij
@@ -24,8 +26,8 @@ namespace nep {
 
 struct TrainArgs {
     const float4 *dF;   // [N][P] scaled force residuals -2 lF/(3N) (F - F_ref), bead-minor
-    const float *cW;    // [P][9] -2 lW/N^2 (W - W_ref)
-    const float *eE;    // [P] 2 lE/N^2 (E - E_ref)
+    const float *cW;    // [nsys][P][9] -2 lW/N^2 (W - W_ref)
+    const float *eE;    // [nsys][P] 2 lE/N^2 (E - E_ref)
     float *rows;        // [N*P][RW] factor rows, row i * P + b
     int RW;
     float *xb;          // [N*P][2][NA1][24] scratch: X and B of the angular-coefficient pass
@@ -42,22 +44,27 @@ struct RowLayout {
     }
 };
 
-// Residuals: scaled force residuals per (atom, bead) and per-bead energy and
-// virial factors; loss parts accumulated into loss[1..3] (diagnostic).
+// Residuals: scaled force residuals per (atom, bead) and per-(system, bead)
+// energy and virial factors; loss parts accumulated into loss[1..3]
+// (diagnostic).  atom_sys [N] and sys_off [nsys+1] give each atom's system
+// and the systems' atom counts.
 __global__ void k_residual(const float *__restrict__ F, const float *__restrict__ Fref, const double *__restrict__ E,
                            const double *__restrict__ Eref, const double *__restrict__ W,
-                           const double *__restrict__ Wref, int P, int N, double lE, double lF, double lW,
-                           float4 *__restrict__ dF, float *__restrict__ cW, float *__restrict__ eE,
-                           double *__restrict__ loss)
+                           const double *__restrict__ Wref, int P, int N, int nsys,
+                           const int32_t *__restrict__ atom_sys, const int32_t *__restrict__ sys_off, double lE,
+                           double lF, double lW, float4 *__restrict__ dF, float *__restrict__ cW,
+                           float *__restrict__ eE, double *__restrict__ loss)
 {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     double lf = 0.0;
     if (e < (size_t)P * N) {
         const int b = (int)(e / (size_t)N), i = (int)(e - (size_t)b * N);
+        const int sy = atom_sys[i];
+        const double Ns = (double)(sys_off[sy + 1] - sys_off[sy]);
         const double dx = (double)F[3 * e] - Fref[3 * e], dy = (double)F[3 * e + 1] - Fref[3 * e + 1],
                      dz = (double)F[3 * e + 2] - Fref[3 * e + 2];
-        lf = lF * (dx * dx + dy * dy + dz * dz) / (3.0 * N);
-        const double cf = -2.0 * lF / (3.0 * N);
+        lf = lF * (dx * dx + dy * dy + dz * dz) / (3.0 * Ns);
+        const double cf = -2.0 * lF / (3.0 * Ns);
         dF[(size_t)i * P + b] = make_float4((float)(cf * dx), (float)(cf * dy), (float)(cf * dz), 0.0f);
     }
     // one pair of atomics per workgroup (same-address atomics serialise)
@@ -72,21 +79,28 @@ __global__ void k_residual(const float *__restrict__ F, const float *__restrict_
             atomicAdd(&loss[0], lf);
         }
     }
-    if (blockIdx.x == 0 && (int)threadIdx.x < P) {
-        const int b = threadIdx.x;
-        const double de = E[b] - Eref[b];
-        eE[b] = (float)(2.0 * lE * de / ((double)N * N));
-        atomicAdd(&loss[1], lE * (de / N) * (de / N));
-        atomicAdd(&loss[0], lE * (de / N) * (de / N));
-        double lw = 0.0;
-        for (int k = 0; k < 9; ++k) {
-            const double dw = W[9 * b + k] - Wref[9 * b + k];
-            cW[9 * b + k] = (float)(-2.0 * lW * dw / ((double)N * N));
-            lw += lW * (dw / N) * (dw / N);
+    if (blockIdx.x == 0)
+        for (int x = threadIdx.x; x < nsys * P; x += blockDim.x) {
+            const int sy = x / P;
+            const double Ns = (double)(sys_off[sy + 1] - sys_off[sy]);
+            if (!(Ns > 0.0)) {
+                eE[x] = 0.0f;
+                for (int k = 0; k < 9; ++k) cW[9 * x + k] = 0.0f;
+                continue;
+            }
+            const double de = E[x] - Eref[x];
+            eE[x] = (float)(2.0 * lE * de / (Ns * Ns));
+            atomicAdd(&loss[1], lE * (de / Ns) * (de / Ns));
+            atomicAdd(&loss[0], lE * (de / Ns) * (de / Ns));
+            double lw = 0.0;
+            for (int k = 0; k < 9; ++k) {
+                const double dw = W[9 * x + k] - Wref[9 * x + k];
+                cW[9 * x + k] = (float)(-2.0 * lW * dw / (Ns * Ns));
+                lw += lW * (dw / Ns) * (dw / Ns);
+            }
+            atomicAdd(&loss[3], lw);
+            atomicAdd(&loss[0], lw);
         }
-        atomicAdd(&loss[3], lw);
-        atomicAdd(&loss[0], lw);
-    }
 }
 
 // Descriptor, its derivative along the pair field d, and the network with
@@ -99,6 +113,7 @@ __global__ void k_residual(const float *__restrict__ F, const float *__restrict_
 // A_nlm + G_nl Adot_nlm).  B and X are parked in the row's scratch, then a
 // second pass over the angular neighbours (one n at a time) accumulates
 // f_k (X.Y + B.Ydot) + fdot_k (u.d) (B.Y) into the row.
+constexpr int kJvpGroup = 2;   // angular radial functions accumulated per neighbour pass
 template <int NR1, int NA1, int KR1, int KA1>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 void k_train_jvp(NepArgs a, TrainArgs ta, const float *__restrict__ prm)
@@ -112,9 +127,10 @@ void k_train_jvp(NepArgs a, TrainArgs ta, const float *__restrict__ prm)
     const float4 *p4 = a.p4;
     const float4 pi = p4[(size_t)i * P + b];
     const float4 di = ta.dF[(size_t)i * P + b];
+    const int sb = a.tile_sys[blockIdx.x] * P + b;   // (system, bead) of the lane
     float cw[9];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) cw[e] = ta.cW[9 * b + e];
+    for (int e = 0; e < 9; ++e) cw[e] = ta.cW[9 * sb + e];
     const float *shc = prm + a.osh;
     const RowLayout R(H, D, NR1, S, KR1, NA1, KA1);
     float *row = ta.rows + ((size_t)i * P + b) * ta.RW;
@@ -135,28 +151,28 @@ void k_train_jvp(NepArgs a, TrainArgs ta, const float *__restrict__ prm)
             ez = dj.z - di.z + cw[2] * dx + cw[5] * dy + cw[8] * dz;
         };
 
-        float q[D], qd[D];
+        // descriptors q and their derivatives along d go to the row, scaled,
+        // as soon as each is final (row[R.sq + v], row[R.sqd + v])
+        const float *qs = prm + a.oq;
+        float qr[NR1], qrd[NR1];
 #pragma unroll
-        for (int v = 0; v < D; ++v) {
-            q[v] = 0.0f;
-            qd[v] = 0.0f;
+        for (int n = 0; n < NR1; ++n) {
+            qr[n] = 0.0f;
+            qrd[n] = 0.0f;
         }
-        float sk[kMaxSpecies][KR1], skd[kMaxSpecies][KR1];
-#pragma unroll
-        for (int t = 0; t < kMaxSpecies; ++t)
-#pragma unroll
-            for (int k = 0; k < KR1; ++k) {
-                sk[t][k] = 0.0f;
-                skd[t][k] = 0.0f;
-            }
-        // radial
+        // radial: per neighbour species, the basis sums and their derivatives
+        // along d (written to the row at once), contracted with c
         const int32_t *uR = a.uniR + (size_t)i * a.capR;
         const uint64_t *mR = a.umR + (size_t)i * a.capR;
-#pragma unroll
-        for (int t = 0; t < kMaxSpecies; ++t) {
-            if (t >= S) break;
+        for (int t = 0; t < S; ++t) {
             int s0, s1;
             block_range(a.uendR, i, t, s0, s1);
+            float sk[KR1], skd[KR1];
+#pragma unroll
+            for (int k = 0; k < KR1; ++k) {
+                sk[k] = 0.0f;
+                skd[k] = 0.0f;
+            }
             for (int s = s0; s < s1; ++s) {
                 if (!((mR[s] >> b) & 1u)) continue;
                 const int j = uR[s];
@@ -172,112 +188,132 @@ void k_train_jvp(NepArgs a, TrainArgs ta, const float *__restrict__ prm)
                 cheb_fd<KR1>(r, a.rcRinv, f, fp);
 #pragma unroll
                 for (int k = 0; k < KR1; ++k) {
-                    sk[t][k] += f[k];
-                    skd[t][k] = fmaf(fp[k], rdot, skd[t][k]);
+                    sk[k] += f[k];
+                    skd[k] = fmaf(fp[k], rdot, skd[k]);
                 }
             }
             const float *c = prm + a.oR + (tc * S + t) * NR1 * KR1;
 #pragma unroll
             for (int n = 0; n < NR1; ++n) {
-                float acc = q[n], accd = qd[n];
+                float acc = qr[n], accd = qrd[n];
 #pragma unroll
                 for (int k = 0; k < KR1; ++k) {
-                    acc = fmaf(c[n * KR1 + k], sk[t][k], acc);
-                    accd = fmaf(c[n * KR1 + k], skd[t][k], accd);
+                    acc = fmaf(c[n * KR1 + k], sk[k], acc);
+                    accd = fmaf(c[n * KR1 + k], skd[k], accd);
                 }
-                q[n] = acc;
-                qd[n] = accd;
+                qr[n] = acc;
+                qrd[n] = accd;
+            }
+#pragma unroll
+            for (int k = 0; k < KR1; ++k) {
+                row[R.sk + t * KR1 + k] = sk[k];
+                row[R.skd + t * KR1 + k] = skd[k];
             }
         }
-        // angular: A_nlm and its derivative along d
-        float A[NA1][kNumSH], Ad[NA1][kNumSH];
 #pragma unroll
-        for (int n = 0; n < NA1; ++n)
-#pragma unroll
-            for (int m = 0; m < kNumSH; ++m) {
-                A[n][m] = 0.0f;
-                Ad[n][m] = 0.0f;
-            }
+        for (int n = 0; n < NR1; ++n) {
+            row[R.sq + n] = qs[n] * qr[n];
+            row[R.sqd + n] = qs[n] * qrd[n];
+        }
+        // angular: A_nlm and its derivative along d, kJvpGroup radial
+        // functions n per pass over the neighbours (their accumulators in
+        // registers), each group's q, qdot entries formed and its A, Adot
+        // parked (replaced by X and B once the network adjoints are known)
         const int32_t *uA = a.uniA + (size_t)i * a.capA;
         const uint64_t *mA = a.umA + (size_t)i * a.capA;
         const int32_t *rowA = a.candA + (size_t)i * a.capA;
-        for (int t = 0; t < S; ++t) {
-            int s0, s1;
-            block_range(a.uendA, i, t, s0, s1);
-            const float *c = prm + a.oA + (tc * S + t) * NA1 * KA1;
-            for (int s = s0; s < s1; ++s) {
-                if (!((mA[s] >> b) & 1u)) continue;
-                const int j = rowA[uA[s]] >> 2;
-                float dx, dy, dz;
-                pair_vec<true>(p4[(size_t)j * P + b], pi, lm, dx, dy, dz);
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                const float rinv = __builtin_amdgcn_rsqf(r2);
-                const float r = r2 * rinv;
-                const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
-                float ex, ey, ez;
-                field(ta.dF[(size_t)j * P + b], dx, dy, dz, ex, ey, ez);
-                const float rdot = ux * ex + uy * ey + uz * ez;
-                // du/de = (d - u (u . d)) / r
-                const float vx = (ex - ux * rdot) * rinv, vy = (ey - uy * rdot) * rinv, vz = (ez - uz * rdot) * rinv;
-                float f[KA1], fp[KA1];
-                cheb_fd<KA1>(r, a.rcAinv, f, fp);
-                float Y[kNumSH], Dm[kNumSH];
-                sh_eval(ux, uy, uz, shc, Y);
-                sh_dir(ux, uy, uz, vx, vy, vz, shc, Dm);
 #pragma unroll
-                for (int n = 0; n < NA1; ++n) {
-                    float g = 0.0f, gp = 0.0f;
+        for (int n0 = 0; n0 < NA1; n0 += kJvpGroup) {
+            float A[kJvpGroup][kNumSH], Ad[kJvpGroup][kNumSH];
 #pragma unroll
-                    for (int k = 0; k < KA1; ++k) {
-                        g = fmaf(c[n * KA1 + k], f[k], g);
-                        gp = fmaf(c[n * KA1 + k], fp[k], gp);
-                    }
-                    const float gpr = gp * rdot;
+            for (int g = 0; g < kJvpGroup; ++g)
 #pragma unroll
-                    for (int m = 0; m < kNumSH; ++m) {
-                        A[n][m] = fmaf(g, Y[m], A[n][m]);
-                        Ad[n][m] = fmaf(gpr, Y[m], fmaf(g, Dm[m], Ad[n][m]));
+                for (int m = 0; m < kNumSH; ++m) {
+                    A[g][m] = 0.0f;
+                    Ad[g][m] = 0.0f;
+                }
+            for (int t = 0; t < S; ++t) {
+                int s0, s1;
+                block_range(a.uendA, i, t, s0, s1);
+                const float *c = prm + a.oA + (tc * S + t) * NA1 * KA1;
+                for (int s = s0; s < s1; ++s) {
+                    if (!((mA[s] >> b) & 1u)) continue;
+                    const int j = rowA[uA[s]] >> 2;
+                    float dx, dy, dz;
+                    pair_vec<true>(p4[(size_t)j * P + b], pi, lm, dx, dy, dz);
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    const float rinv = __builtin_amdgcn_rsqf(r2);
+                    const float r = r2 * rinv;
+                    const float ux = dx * rinv, uy = dy * rinv, uz = dz * rinv;
+                    float ex, ey, ez;
+                    field(ta.dF[(size_t)j * P + b], dx, dy, dz, ex, ey, ez);
+                    const float rdot = ux * ex + uy * ey + uz * ez;
+                    // du/de = (d - u (u . d)) / r
+                    const float vx = (ex - ux * rdot) * rinv, vy = (ey - uy * rdot) * rinv,
+                                vz = (ez - uz * rdot) * rinv;
+                    float f[KA1], fp[KA1];
+                    cheb_fd<KA1>(r, a.rcAinv, f, fp);
+                    float Y[kNumSH], Dm[kNumSH];
+                    sh_eval(ux, uy, uz, shc, Y);
+                    sh_dir(ux, uy, uz, vx, vy, vz, shc, Dm);
+#pragma unroll
+                    for (int g = 0; g < kJvpGroup; ++g) {
+                        const int n = n0 + g;
+                        if (n >= NA1) break;
+                        float gn = 0.0f, gp = 0.0f;
+#pragma unroll
+                        for (int k = 0; k < KA1; ++k) {
+                            gn = fmaf(c[n * KA1 + k], f[k], gn);
+                            gp = fmaf(c[n * KA1 + k], fp[k], gp);
+                        }
+                        const float gpr = gp * rdot;
+#pragma unroll
+                        for (int m = 0; m < kNumSH; ++m) {
+                            A[g][m] = fmaf(gn, Y[m], A[g][m]);
+                            Ad[g][m] = fmaf(gpr, Y[m], fmaf(gn, Dm[m], Ad[g][m]));
+                        }
                     }
                 }
             }
+#pragma unroll
+            for (int g = 0; g < kJvpGroup; ++g) {
+                const int n = n0 + g;
+                if (n >= NA1) break;
+#pragma unroll
+                for (int l = 1; l <= kLmax; ++l) {
+                    float s2 = 0.0f, s2d = 0.0f;
+#pragma unroll
+                    for (int m = 0; m < kNumSH; ++m)
+                        if (sh_l(m) == l) {
+                            s2 = fmaf(A[g][m], A[g][m], s2);
+                            s2d = fmaf(2.0f * A[g][m], Ad[g][m], s2d);
+                        }
+                    const int vv = NR1 + (l - 1) * NA1 + n;
+                    row[R.sq + vv] = qs[vv] * s2;
+                    row[R.sqd + vv] = qs[vv] * s2d;
+                }
+#pragma unroll
+                for (int m = 0; m < kNumSH; ++m) {
+                    xb[n * kNumSH + m] = A[g][m];
+                    xb[(NA1 + n) * kNumSH + m] = Ad[g][m];
+                }
+            }
         }
-#pragma unroll
-        for (int n = 0; n < NA1; ++n)
-#pragma unroll
-            for (int l = 1; l <= kLmax; ++l) {
-                float s2 = 0.0f, s2d = 0.0f;
-#pragma unroll
-                for (int m = 0; m < kNumSH; ++m)
-                    if (sh_l(m) == l) {
-                        s2 = fmaf(A[n][m], A[n][m], s2);
-                        s2d = fmaf(2.0f * A[n][m], Ad[n][m], s2d);
-                    }
-                q[NR1 + (l - 1) * NA1 + n] = s2;
-                qd[NR1 + (l - 1) * NA1 + n] = s2d;
-            }
-        // park A and Adot (replaced by X and B once the network adjoints are known)
-#pragma unroll
-        for (int n = 0; n < NA1; ++n)
-#pragma unroll
-            for (int m = 0; m < kNumSH; ++m) {
-                xb[n * kNumSH + m] = A[n][m];
-                xb[(NA1 + n) * kNumSH + m] = Ad[n][m];
-            }
 
-        // network and its forward derivative
-        const float *qs = prm + a.oq;
+        // network and its forward derivative (the scaled descriptors read
+        // back from the row, written by this lane)
         float qh[D], qhd[D], G[D], Gd[D];
 #pragma unroll
         for (int v = 0; v < D; ++v) {
-            qh[v] = qs[v] * q[v];
-            qhd[v] = qs[v] * qd[v];
+            qh[v] = row[R.sq + v];
+            qhd[v] = row[R.sqd + v];
             G[v] = 0.0f;
             Gd[v] = 0.0f;
         }
         const float *W0 = prm + a.oW0 + tc * H * D;
         const float *b0 = prm + a.ob0 + tc * H;
         const float *w1 = prm + a.ow1 + tc * H;
-        const float eEb = ta.eE[b];
+        const float eEb = ta.eE[sb];
         for (int mu = 0; mu < H; ++mu) {
             float z = -b0[mu], zd = 0.0f;
 #pragma unroll
@@ -299,22 +335,11 @@ void k_train_jvp(NepArgs a, TrainArgs ta, const float *__restrict__ prm)
             row[R.gw1 + mu] = eEb * h + dh * zd;
         }
 #pragma unroll
-        for (int v = 0; v < D; ++v) {
-            row[R.sq + v] = qh[v];
-            row[R.sqd + v] = qhd[v];
-        }
-#pragma unroll
         for (int n = 0; n < NR1; ++n) {
             const float g = qs[n] * G[n], gd = qs[n] * Gd[n];
             row[R.gR + n] = eEb * g + gd;
             row[R.GR + n] = g;
         }
-        for (int t = 0; t < S; ++t)
-#pragma unroll
-            for (int k = 0; k < KR1; ++k) {
-                row[R.sk + t * KR1 + k] = sk[t][k];
-                row[R.skd + t * KR1 + k] = skd[t][k];
-            }
         row[R.eE] = eEb;
         row[0] = __int_as_float(tc);
 
@@ -443,16 +468,28 @@ __global__ __launch_bounds__(256) void k_grad_partial(const float *__restrict__ 
     }
 }
 
-// Sums the partials in block order and scatters them to the parameter layout.
-__global__ void k_grad_final(const float *__restrict__ part, int nblk, int S, int H, int D, int NR1, int KR1,
-                             int NA1, int KA1, ParamLayout off, float *__restrict__ grad)
+// Sums the partials and scatters them to the parameter layout.  A
+// workgroup takes 64 consecutive outputs (one per lane, coalesced reads);
+// its kGradWaves wavefronts take every kGradWaves-th block in order, and
+// the wavefronts' sums are added in wavefront order (fixed order).
+constexpr int kGradWaves = 16;
+__global__ __launch_bounds__(64 * kGradWaves) void k_grad_final(const float *__restrict__ part, int nblk, int S, int H,
+                                                                int D, int NR1, int KR1, int NA1, int KA1,
+                                                                ParamLayout off, float *__restrict__ grad)
 {
     const int per = H * D + 2 * H + S * NR1 * KR1 + S * NA1 * KA1;
     const int nout = S * per + 1;
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= nout) return;
+    const int w = threadIdx.x >> 6;
+    const int o = blockIdx.x * 64 + (threadIdx.x & 63);
+    __shared__ double red[kGradWaves][64];
+    double acc = 0.0;
+    if (o < nout)
+        for (int k = w; k < nblk; k += kGradWaves) acc += part[(size_t)k * nout + o];
+    red[w][threadIdx.x & 63] = acc;
+    __syncthreads();
+    if (w != 0 || o >= nout) return;
     double s = 0.0;
-    for (int k = 0; k < nblk; ++k) s += part[(size_t)k * nout + o];
+    for (int v = 0; v < kGradWaves; ++v) s += red[v][threadIdx.x];
     int idx;
     if (o == nout - 1) {
         idx = off.b1;
@@ -493,11 +530,14 @@ static void launch_jvp(const NepArgs &a, const TrainArgs &t, const float *prm, i
 using namespace nep;
 
 struct nep_train_ws {
-    int P = 0, N = 0;
-    double *E = nullptr, *W = nullptr;   // [P], [P][9]
+    int P = 0, N = 0, nsys = 1;
+    std::vector<int> off;                // host [nsys+1]
+    int32_t *atom_sys = nullptr;         // [N] system of each atom
+    int32_t *sys_off = nullptr;          // [nsys+1]
+    double *E = nullptr, *W = nullptr;   // [nsys][P], [nsys][P][9]
     float *F = nullptr;                  // [P][N][3]
     float4 *dF = nullptr;                // [N][P]
-    float *cW = nullptr, *eE = nullptr;  // [P][9], [P]
+    float *cW = nullptr, *eE = nullptr;  // [nsys][P][9], [nsys][P]
     float *rows = nullptr;               // [N*P][RW]
     float *xb = nullptr;                 // [N*P][2][NA1][24]
     float *part = nullptr;               // [nblk][nout]
@@ -506,10 +546,14 @@ struct nep_train_ws {
     int ntrain_mask = -1;
 };
 
-extern "C" int32_t nep_train_ws_create(const nep_model *m, int32_t P, int32_t N, nep_train_ws **out)
+extern "C" int32_t nep_train_ws_create_batched(const nep_model *m, int32_t P, int32_t nsys, const int32_t *off,
+                                               nep_train_ws **out)
 {
     if (!m || !out) return fail(NEP_ERR_INVALID_ARG, "nep_train_ws_create: null argument");
     if (m->cutoffs_only) return fail(NEP_ERR_INVALID_ARG, "nep_train_ws_create: a list cutoff descriptor has no network");
+    const int32_t rc0 = check_offsets(nsys, off, "nep_train_ws_create");
+    if (rc0 != NEP_OK) return rc0;
+    const int32_t N = off[nsys];
     if (P < 1 || P > kMaxBeads || N < 1) return fail(NEP_ERR_INVALID_ARG, "nep_train_ws_create: bad sizes");
     const nep_hparams &h = m->hp;
     if (h.four_body) return fail(NEP_ERR_UNSUPPORTED, "nep_train_ws_create: four-body models are not trainable");
@@ -525,6 +569,11 @@ extern "C" int32_t nep_train_ws_create(const nep_model *m, int32_t P, int32_t N,
     nep_train_ws *w = new (std::nothrow) nep_train_ws;
     if (!w) return fail(NEP_ERR_NOMEM, "host allocation failed");
     w->P = P; w->N = N; w->RW = R.RW; w->nout = nout;
+    w->nsys = nsys;
+    w->off.assign(off, off + nsys + 1);
+    std::vector<int32_t> asys((size_t)N);
+    for (int sy = 0; sy < nsys; ++sy)
+        for (int i = off[sy]; i < off[sy + 1]; ++i) asys[i] = sy;
     const size_t PN = (size_t)P * N;
     // enough workgroups to fill the chip for a single snapshot, at most 512 rows each
     w->rows_per_block = (int)std::min<size_t>(512, std::max<size_t>(kRowChunk, (PN + 1023) / 1024));
@@ -533,12 +582,16 @@ extern "C" int32_t nep_train_ws_create(const nep_model *m, int32_t P, int32_t N,
     auto al = [&](void **p, size_t bytes) {
         if (e == hipSuccess) e = hipMalloc(p, bytes ? bytes : 4);
     };
-    al((void **)&w->E, sizeof(double) * P);
-    al((void **)&w->W, sizeof(double) * 9 * P);
+    al((void **)&w->atom_sys, sizeof(int32_t) * N);
+    al((void **)&w->sys_off, sizeof(int32_t) * (nsys + 1));
+    if (e == hipSuccess) e = hipMemcpy(w->atom_sys, asys.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(w->sys_off, off, sizeof(int32_t) * (nsys + 1), hipMemcpyHostToDevice);
+    al((void **)&w->E, sizeof(double) * nsys * P);
+    al((void **)&w->W, sizeof(double) * 9 * nsys * P);
     al((void **)&w->F, sizeof(float) * 3 * PN);
     al((void **)&w->dF, sizeof(float4) * PN);
-    al((void **)&w->cW, sizeof(float) * 9 * P);
-    al((void **)&w->eE, sizeof(float) * P);
+    al((void **)&w->cW, sizeof(float) * 9 * nsys * P);
+    al((void **)&w->eE, sizeof(float) * nsys * P);
     al((void **)&w->rows, sizeof(float) * PN * R.RW);
     al((void **)&w->xb, sizeof(float) * PN * 2 * NA1 * kNumSH);
     al((void **)&w->part, sizeof(float) * (size_t)w->nblk * nout);
@@ -555,29 +608,38 @@ extern "C" int32_t nep_train_ws_create(const nep_model *m, int32_t P, int32_t N,
 extern "C" void nep_train_ws_destroy(nep_train_ws *w)
 {
     if (!w) return;
-    for (void *p : {(void *)w->E, (void *)w->W, (void *)w->F, (void *)w->dF, (void *)w->cW, (void *)w->eE,
+    for (void *p : {(void *)w->atom_sys, (void *)w->sys_off, (void *)w->E, (void *)w->W, (void *)w->F, (void *)w->dF, (void *)w->cW, (void *)w->eE,
                     (void *)w->rows, (void *)w->xb, (void *)w->part, (void *)w->trainable})
         if (p) (void)hipFree(p);
     delete w;
 }
 
-extern "C" int32_t nep_param_grad(const nep_model *m, nep_nlist *nl, nep_ws *ws, nep_train_ws *tw, const double *pos,
-                                  const double box[9], const int32_t *types, int32_t P, int32_t N,
-                                  const double *E_ref, const float *F_ref, const double *W_ref,
-                                  const double lambda[3], float *grad, double *loss, hipStream_t s)
+extern "C" int32_t nep_train_ws_create(const nep_model *m, int32_t P, int32_t N, nep_train_ws **out)
+{
+    if (N < 1) return fail(NEP_ERR_INVALID_ARG, "nep_train_ws_create: bad sizes");
+    const int32_t off[2] = {0, N};
+    return nep_train_ws_create_batched(m, P, 1, off, out);
+}
+
+extern "C" int32_t nep_param_grad_batched(const nep_model *m, nep_nlist *nl, nep_ws *ws, nep_train_ws *tw,
+                                          const double *pos, const double *boxes, const int32_t *types, int32_t P,
+                                          int32_t N, const double *E_ref, const float *F_ref, const double *W_ref,
+                                          const double lambda[3], float *grad, double *loss, hipStream_t s)
 {
     if (!m || !nl || !ws || !tw || !lambda || !grad || !loss || !E_ref || !F_ref || !W_ref)
         return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: null argument");
     if (m->cutoffs_only) return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: a list cutoff descriptor has no network");
-    if (tw->P != P || tw->N != N || nl->nsys != 1)
-        return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: sizes do not match the training workspace");
+    if (tw->P != P || tw->N != N || nl->nsys != tw->nsys || ws->nsys != tw->nsys || nl->off != tw->off ||
+        ws->off != tw->off)
+        return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: sizes or systems do not match the training workspace");
     if (m->mlp == NEP_MLP_BF16_MFMA)
         return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: training needs the FP32 weights (nep_model_set_mlp)");
-    int32_t rc = nep_compute(m, nl, ws, pos, box, types, P, N, tw->E, tw->F, tw->W, nullptr, nullptr, s);
+    int32_t rc = nep_compute_batched(m, nl, ws, pos, boxes, types, P, N, tw->E, tw->F, tw->W, nullptr, nullptr, s);
     if (rc != NEP_OK) return rc;
     const size_t PN = (size_t)P * N;
     hipLaunchKernelGGL(k_residual, dim3((unsigned)((PN + 255) / 256)), dim3(256), 0, s, tw->F, F_ref, tw->E, E_ref,
-                       tw->W, W_ref, P, N, lambda[0], lambda[1], lambda[2], tw->dF, tw->cW, tw->eE, loss);
+                       tw->W, W_ref, P, N, tw->nsys, tw->atom_sys, tw->sys_off, lambda[0], lambda[1], lambda[2],
+                       tw->dF, tw->cW, tw->eE, loss);
     const nep_hparams &h = m->hp;
     NepArgs a{};
     a.p4 = reinterpret_cast<const float4 *>(nl->pos4); a.pos = pos; a.types = types; a.N = N; a.S = h.n_species;
@@ -602,10 +664,20 @@ extern "C" int32_t nep_param_grad(const nep_model *m, nep_nlist *nl, nep_ws *ws,
     const int NA1 = h.n_max_angular + 1, KA1 = h.basis_angular + 1;
     hipLaunchKernelGGL(k_grad_partial, dim3(tw->nblk), dim3(256), sizeof(float) * kRowChunk * tw->RW, s, tw->rows,
                        PN, tw->RW, S, H, D, NR1, KR1, NA1, KA1, tw->rows_per_block, tw->part);
-    hipLaunchKernelGGL(k_grad_final, dim3((tw->nout + 255) / 256), dim3(256), 0, s, tw->part, tw->nblk, S, H, D, NR1,
-                       KR1, NA1, KA1, m->off, grad);
+    hipLaunchKernelGGL(k_grad_final, dim3((tw->nout + 63) / 64), dim3(64 * kGradWaves), 0, s, tw->part, tw->nblk, S,
+                       H, D, NR1, KR1, NA1, KA1, m->off, grad);
     NEP_HIP(hipGetLastError());
     return NEP_OK;
+}
+
+extern "C" int32_t nep_param_grad(const nep_model *m, nep_nlist *nl, nep_ws *ws, nep_train_ws *tw, const double *pos,
+                                  const double box[9], const int32_t *types, int32_t P, int32_t N,
+                                  const double *E_ref, const float *F_ref, const double *W_ref,
+                                  const double lambda[3], float *grad, double *loss, hipStream_t s)
+{
+    if ((nl && nl->nsys != 1) || (tw && tw->nsys != 1))
+        return fail(NEP_ERR_INVALID_ARG, "nep_param_grad: the list or workspace holds a batch of systems");
+    return nep_param_grad_batched(m, nl, ws, tw, pos, box, types, P, N, E_ref, F_ref, W_ref, lambda, grad, loss, s);
 }
 
 extern "C" int32_t nep_model_params(nep_model *m, float **params, int32_t *count, nep_param_offsets *off)

@@ -121,9 +121,12 @@ _sig = {
                             C.POINTER(C.c_float), C.POINTER(C.c_int32), _vp]),
     "nep_model_params": (_i32, [_vp, C.POINTER(_vp), C.POINTER(C.c_int32), C.POINTER(ParamOffsets)]),
     "nep_train_ws_create": (_i32, [_vp, _i32, _i32, C.POINTER(_vp)]),
+    "nep_train_ws_create_batched": (_i32, [_vp, _i32, _i32, C.POINTER(C.c_int32), C.POINTER(_vp)]),
     "nep_train_ws_destroy": (None, [_vp]),
     "nep_param_grad": (_i32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, _vp, _vp, _vp,
                               C.POINTER(C.c_double), _vp, _vp, _vp]),
+    "nep_param_grad_batched": (_i32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, _vp, _vp,
+                                      _vp, C.POINTER(C.c_double), _vp, _vp, _vp]),
     "nep_adam_step": (_i32, [_vp, _vp, _vp, _vp, _vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, _i32,
                              _vp]),
     "nep_d3_load": (_i32, [C.c_char_p, C.POINTER(_vp)]),
@@ -562,39 +565,71 @@ class Trainer:
     NETWORK, RADIAL, ANGULAR = 1, 2, 4
     ALL = 7
 
-    def __init__(self, model: Model, P: int, N: int):
+    def __init__(self, model: Model, P: int, N: int, sys_offsets=None, share: "Trainer" = None):
+        """sys_offsets: atom offsets [nsys+1] of a batch of systems (snapshots);
+        share: a Trainer of the same model whose gradient, Adam moments, loss
+        accumulator and step count this one uses (one optimiser, several batch
+        shapes)."""
         t = _torch()
         self.model, self.P, self.N = model, P, N
+        self.sys_offsets = None if sys_offsets is None else np.asarray(sys_offsets, np.int32)
         self._h = _vp()
-        _check(_lib.nep_train_ws_create(model.handle, P, N, C.byref(self._h)))
+        if self.sys_offsets is None:
+            _check(_lib.nep_train_ws_create(model.handle, P, N, C.byref(self._h)))
+        else:
+            o = (C.c_int32 * len(self.sys_offsets))(*self.sys_offsets.tolist())
+            _check(_lib.nep_train_ws_create_batched(model.handle, P, len(self.sys_offsets) - 1, o,
+                                                    C.byref(self._h)))
         _, cnt, self.offsets = model.params()
-        dev = t.device("cuda")
-        self.grad = t.zeros(cnt, dtype=t.float32, device=dev)
-        self.m1 = t.zeros(cnt, dtype=t.float32, device=dev)
-        self.m2 = t.zeros(cnt, dtype=t.float32, device=dev)
-        self.loss = t.zeros(4, dtype=t.float64, device=dev)
-        self.step_no = 0
+        self.share = share
+        if share is None:
+            dev = t.device("cuda")
+            self.grad = t.zeros(cnt, dtype=t.float32, device=dev)
+            self.m1 = t.zeros(cnt, dtype=t.float32, device=dev)
+            self.m2 = t.zeros(cnt, dtype=t.float32, device=dev)
+            self.loss = t.zeros(4, dtype=t.float64, device=dev)
+            self.step_no = 0
+        else:
+            if share.model is not model:
+                raise ValueError("a shared Trainer must belong to the same model")
+            self.grad, self.m1, self.m2, self.loss = share.grad, share.m1, share.m2, share.loss
 
     def zero(self):
         self.grad.zero_()
         self.loss.zero_()
 
+    @property
+    def nsys(self) -> int:
+        return 1 if self.sys_offsets is None else len(self.sys_offsets) - 1
+
     def accumulate(self, nl: NeighborList, ws: "Workspace", pos, box, types, E_ref, F_ref, W_ref, lambdas):
-        """grad += dL/dtheta and loss += (L, L_E, L_F, L_W) for the P configurations pos."""
+        """grad += dL/dtheta and loss += (L, L_E, L_F, L_W) for the P configurations pos
+        (of every system of a batch: box [nsys, 3 | 3, 3], E_ref [nsys, P], W_ref [nsys, P, 9])."""
         t = _torch()
-        P, N = self.P, self.N
+        P, N, S = self.P, self.N, self.nsys
         lam = (C.c_double * 3)(*[float(x) for x in lambdas])
-        _check(_lib.nep_param_grad(self.model.handle, nl.handle, ws.handle, self._h,
-                                   _ptr(pos, t.float64, (P, N, 3), "pos"), _box9(box),
-                                   _ptr(types, t.int32, (N,), "types"), P, N,
-                                   _ptr(E_ref, t.float64, (P,), "E_ref"), _ptr(F_ref, t.float32, (P, N, 3), "F_ref"),
-                                   _ptr(W_ref, t.float64, (P, 9), "W_ref"), lam, _ptr(self.grad, t.float32),
-                                   _ptr(self.loss, t.float64), _stream()))
+        if self.sys_offsets is None:
+            _check(_lib.nep_param_grad(self.model.handle, nl.handle, ws.handle, self._h,
+                                       _ptr(pos, t.float64, (P, N, 3), "pos"), _box9(box),
+                                       _ptr(types, t.int32, (N,), "types"), P, N,
+                                       _ptr(E_ref, t.float64, (P,), "E_ref"),
+                                       _ptr(F_ref, t.float32, (P, N, 3), "F_ref"),
+                                       _ptr(W_ref, t.float64, (P, 9), "W_ref"), lam, _ptr(self.grad, t.float32),
+                                       _ptr(self.loss, t.float64), _stream()))
+            return
+        _check(_lib.nep_param_grad_batched(self.model.handle, nl.handle, ws.handle, self._h,
+                                           _ptr(pos, t.float64, (P, N, 3), "pos"), _boxes(box, S),
+                                           _ptr(types, t.int32, (N,), "types"), P, N,
+                                           _ptr(E_ref, t.float64, (S, P), "E_ref"),
+                                           _ptr(F_ref, t.float32, (P, N, 3), "F_ref"),
+                                           _ptr(W_ref, t.float64, (S, P, 9), "W_ref"), lam,
+                                           _ptr(self.grad, t.float32), _ptr(self.loss, t.float64), _stream()))
 
     def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, mask: int = 7):
-        self.step_no += 1
+        owner = self.share if self.share is not None else self
+        owner.step_no += 1
         _check(_lib.nep_adam_step(self.model.handle, self._h, _ptr(self.grad, _torch().float32),
-                                  _ptr(self.m1, _torch().float32), _ptr(self.m2, _torch().float32), self.step_no,
+                                  _ptr(self.m1, _torch().float32), _ptr(self.m2, _torch().float32), owner.step_no,
                                   float(lr), float(beta1), float(beta2), float(eps), int(mask), _stream()))
 
     def __del__(self):

@@ -156,6 +156,8 @@ class StudentTrainer:
         self.nl = lib.fitted_neighbor_list(self.model, store.pos[0], self.box, self.types, *caps, skin=skin)
         self.ws = lib.Workspace(self.model, self.P, self.N)
         self.trainer = lib.Trainer(self.model, self.P, self.N)
+        self.skin = skin
+        self._groups = {}   # snapshots per call -> (lists, workspace, trainer, types) of that batch
         self.E = torch.zeros(self.P, dtype=torch.float64, device="cuda")
         self.F = torch.zeros((self.P, self.N, 3), dtype=torch.float32, device="cuda")
         self.W = torch.zeros((self.P, 9), dtype=torch.float64, device="cuda")
@@ -169,21 +171,58 @@ class StudentTrainer:
         if st["flags"] or self.ws.poll(clear=True):
             raise lib.NepError(6, f"student training: device flags {st['flags']:#x}")
 
+    def _group(self, B: int):
+        """Handles for B snapshots per gradient call (a batch of B systems of N atoms)."""
+        g = self._groups.get(B)
+        if g is None:
+            off = np.arange(B + 1, dtype=np.int32) * self.N
+            nl = lib.NeighborList(self.model, self.P, B * self.N, *self.nl.caps, offsets=off)
+            nl.set_skin(self.skin)
+            ws = lib.Workspace(self.model, self.P, B * self.N, offsets=off)
+            tr = lib.Trainer(self.model, self.P, B * self.N, sys_offsets=off, share=self.trainer)
+            g = (nl, ws, tr, self.types.repeat(B).contiguous(), np.stack([self.box] * B))
+            self._groups[B] = g
+        return g
+
+    def _check_groups(self):
+        for nl, ws, _, _, _ in self._groups.values():
+            st = nl.status(clear=True)
+            if st["flags"] & lib.FLAG_NEIGHBOR_OVERFLOW:
+                raise lib.NepError(5, "student training: candidate rows overflowed")
+            if st["flags"] or ws.poll(clear=True):
+                raise lib.NepError(6, f"student training: device flags {st['flags']:#x}")
+
     def epoch(self, lr: float, batch: int = 1) -> float:
-        """One pass over the training snapshots in random order; Adam step per `batch` snapshots.
-        Returns the mean loss per snapshot."""
+        """One pass over the training snapshots in random order; one gradient call
+        (the snapshots as a batch of systems) and one Adam step per `batch`
+        snapshots.  Returns the mean loss per snapshot."""
+        t = self.torch
         st = self.store
         idx = self.rng.permutation(self.train)
-        total = self.torch.zeros(4, dtype=self.torch.float64, device="cuda")
+        total = t.zeros(4, dtype=t.float64, device="cuda")
+        P, N = self.P, self.N
         for s in range(0, len(idx), batch):
+            ks = idx[s:s + batch]
             self.trainer.zero()
-            for k in idx[s:s + batch]:
+            if len(ks) == 1:
+                k = int(ks[0])
                 self.nl.build(st.pos[k], self.box, self.types)
                 self.trainer.accumulate(self.nl, self.ws, st.pos[k], self.box, self.types, st.E[k], st.F[k],
                                         st.W[k], self.lambdas)
+            else:
+                B = len(ks)
+                nl, ws, tr, types, boxes = self._group(B)
+                sel = t.as_tensor(ks, device="cuda")
+                # [B, P, N, 3] -> [P, B N, 3]: the snapshots side by side along the atom axis
+                pos = st.pos.index_select(0, sel).permute(1, 0, 2, 3).reshape(P, B * N, 3).contiguous()
+                F = st.F.index_select(0, sel).permute(1, 0, 2, 3).reshape(P, B * N, 3).contiguous()
+                nl.build(pos, boxes, types)
+                tr.accumulate(nl, ws, pos, boxes, types, st.E.index_select(0, sel).contiguous(), F,
+                              st.W.index_select(0, sel).contiguous(), self.lambdas)
             total += self.trainer.loss
             self.trainer.adam(lr, mask=self.mask)
         self._check_lists()
+        self._check_groups()
         return float(total[0]) / max(1, len(idx))
 
     def rmse(self, which: str = "val") -> float:

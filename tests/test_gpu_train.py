@@ -150,3 +150,74 @@ def test_adam_lowers_loss(torch, L, orc, tmpdir_session):
     tr.zero()
     tr.accumulate(nl, ws, tpos, box, ttyp, *refs, LAM)
     assert abs(float(tr.loss[0].item()) - L1) <= 1e-3 * L1
+
+
+def test_batched_gradient_is_the_sum_over_systems(torch, L, orc, tmpdir_session):
+    """Two labelled snapshots of different size in one call (a batch of
+    systems): the loss equals the sum of the oracle losses, the gradient the
+    sum of the two single-system gradients (each pinned to the oracle's
+    finite differences above)."""
+    h = I.NepHyper(1, 5.0, 4.0, 4, 4, 8, 8, 4, False, 12)
+    student = I.random_model(h, np.random.default_rng(5), 0.06, 10.0)
+    teacher = I.random_model(h, np.random.default_rng(6), 0.06, 10.0)
+    spath = write_model(tmpdir_session, "train_batch_student", student)
+    tpath = write_model(tmpdir_session, "train_batch_teacher", teacher)
+    P = 2
+    snaps = []
+    for k, (nc, a) in enumerate(((3, 4.05), (4, 4.10))):
+        p0, types, box = I.fcc(nc, a)
+        pos = I.replicate_beads(p0, P) + np.random.default_rng(20 + k).normal(0.0, 0.05, (P, len(types), 3))
+        r = orc.Model(tpath).beads(pos, types, box)
+        snaps.append((pos, np.asarray(types), np.asarray(box, np.float64), r))
+    dev = torch.device("cuda")
+    m = L.Model(spath)
+    # one system at a time
+    single = []
+    loss_or = 0.0
+    for pos, types, box, r in snaps:
+        N = pos.shape[1]
+        tpos = torch.tensor(pos, dtype=torch.float64, device=dev)
+        ttyp = torch.tensor(types, dtype=torch.int32, device=dev)
+        nl = L.fitted_neighbor_list(m, tpos, box, ttyp, 96, 48)
+        ws = L.Workspace(m, P, N)
+        tr = L.Trainer(m, P, N)
+        nl.build(tpos, box, ttyp)
+        tr.zero()
+        tr.accumulate(nl, ws, tpos, box, ttyp, torch.tensor(r["E"], dtype=torch.float64, device=dev),
+                      torch.tensor(r["F"], dtype=torch.float32, device=dev),
+                      torch.tensor(r["W"].reshape(P, 9), dtype=torch.float64, device=dev), LAM)
+        torch.cuda.synchronize()
+        single.append((tr.grad.cpu().numpy().astype(np.float64), tr.loss.cpu().numpy()))
+        r_st = orc.Model(spath).beads(pos, types, box)
+        loss_or += orc.train_loss(dict(E=r_st["E"], F=r_st["F"], W=r_st["W"]), dict(E=r["E"], F=r["F"], W=r["W"]),
+                                  LAM, N)[0]
+    # both in one call
+    sizes = [s[0].shape[1] for s in snaps]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    pos = np.concatenate([s[0] for s in snaps], axis=1)
+    types = np.concatenate([s[1] for s in snaps])
+    boxes = np.stack([s[2] for s in snaps])
+    N = int(off[-1])
+    tpos = torch.tensor(pos, dtype=torch.float64, device=dev)
+    ttyp = torch.tensor(types, dtype=torch.int32, device=dev)
+    nl = L.fitted_neighbor_list(m, tpos, boxes, ttyp, 96, 48, offsets=off)
+    ws = L.Workspace(m, P, N, offsets=off)
+    tr = L.Trainer(m, P, N, sys_offsets=off)
+    E = torch.tensor(np.stack([s[3]["E"] for s in snaps]), dtype=torch.float64, device=dev)
+    F = torch.tensor(np.concatenate([s[3]["F"] for s in snaps], axis=1), dtype=torch.float32, device=dev)
+    W = torch.tensor(np.stack([s[3]["W"].reshape(P, 9) for s in snaps]), dtype=torch.float64, device=dev)
+    nl.build(tpos, boxes, ttyp)
+    tr.zero()
+    tr.accumulate(nl, ws, tpos, boxes, ttyp, E, F, W, LAM)
+    torch.cuda.synchronize()
+    g = tr.grad.cpu().numpy().astype(np.float64)
+    loss = tr.loss.cpu().numpy()
+    gsum = single[0][0] + single[1][0]
+    say(f"[train batch] loss GPU {loss[0]:.6e} oracle {loss_or:.6e}; "
+        f"max |g - (g1 + g2)| / max|g| {np.abs(g - gsum).max() / np.abs(gsum).max():.2e}")
+    assert abs(loss[0] - loss_or) <= 1e-4 * loss_or
+    np.testing.assert_allclose(loss, single[0][1] + single[1][1], rtol=1e-9, atol=0.0)
+    assert np.abs(g - gsum).max() <= 1e-5 * np.abs(gsum).max()
+    # a batch whose partition differs from the lists' is refused
+    with pytest.raises(L.NepError):
+        L.Trainer(m, P, N, sys_offsets=[0, sizes[1], N]).accumulate(nl, ws, tpos, boxes, ttyp, E, F, W, LAM)
