@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one plain device copy of this size first (HBM counter calibration)")
     ap.add_argument("--no-profile", action="store_true", help="do not bracket kernels with timing events")
+    ap.add_argument("--no-mlp-compare", action="store_true",
+                    help="skip the comparison run with the other network arithmetic (profiler runs)")
     ap.add_argument("--no-student", action="store_true", help="skip the learned-student leg")
     ap.add_argument("--no-npt", action="store_true", help="skip the barostat (NPT) leg")
     ap.add_argument("--no-triclinic", action="store_true", help="skip the general-cell leg")
@@ -723,13 +725,15 @@ def main():
                 "hbm_frac": round(step_gbs / PEAK_HBM_GBS, 4)}
     # the other network arithmetic on the same engine and steps
     timed_mlp = eng.mlp
-    other_mlp = "fp32_mfma" if timed_mlp == "fp32" else "fp32"
-    eng.model.set_mlp(lib.MLP_MODES[other_mlp])
-    ok_ = kernel_profile(torch, lib, eng, 5) if not args.no_profile else {}
-    oms = timed_steps(torch, eng, max(20, min(100, args.steps)), False)[0]
-    net_cmp = {"mlp": other_mlp, "ms_per_step": round(oms, 4), "value": round(s.N * s.P / (oms * 1e-3), 1),
-               "descriptor_us": round(ok_["descriptor"]["avg_us"], 2) if "descriptor" in ok_ else None,
-               "vs_timed": round(oms / ms, 4)}
+    net_cmp = None
+    if not args.no_mlp_compare:
+        other_mlp = "fp32_mfma" if timed_mlp == "fp32" else "fp32"
+        eng.model.set_mlp(lib.MLP_MODES[other_mlp])
+        ok_ = kernel_profile(torch, lib, eng, 5) if not args.no_profile else {}
+        oms = timed_steps(torch, eng, max(20, min(100, args.steps)), False)[0]
+        net_cmp = {"mlp": other_mlp, "ms_per_step": round(oms, 4), "value": round(s.N * s.P / (oms * 1e-3), 1),
+                   "descriptor_us": round(ok_["descriptor"]["avg_us"], 2) if "descriptor" in ok_ else None,
+                   "vs_timed": round(oms / ms, 4)}
     del eng
 
     full = None if args.no_full_run else full_run_leg(torch, lib, w, model_path, s, NepPimd, args.mlp)

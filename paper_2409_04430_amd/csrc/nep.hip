@@ -237,6 +237,7 @@ constexpr int mf_lds_floats() { return 64 * ((D <= 32 ? 32 : 64) + 4); }
 // LDS-staged vector form: two wavefronts per SIMD cannot hide the chains of
 // dependent 16 x 16 x 4 FP32 tiles.)
 constexpr int kNetGlobal = 0, kNetLds = 1, kNetBf16 = 2, kNetMf32 = 3;
+constexpr int kNetRowRegs = 40;   // longest descriptor whose weight rows the LDS network holds in registers
 
 // ----------------------------------------------------------- pass 1 ---
 
@@ -353,27 +354,35 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             }
         }
 
-        // angular: A_nlm = sum_j g_n(r_ij) Y_lm(u_ij)
-        float A[NA1][kNumSH];
-#pragma unroll
-        for (int n = 0; n < NA1; ++n)
-#pragma unroll
-            for (int m = 0; m < kNumSH; ++m) A[n][m] = 0.0f;
+        // angular: A_nlm = sum_j g_n(r_ij) Y_lm(u_ij), NG radial functions n
+        // per pass over the neighbours (all of them when A stays in
+        // registers; in two passes when more than five are parked, so that
+        // the accumulators of one pass fit the registers), each pass's q
+        // entries formed and its A parked before the next
+        constexpr int NG = NA1 > 5 ? (NA1 + 2) / 3 : NA1;
         const int32_t *uA = a.uniA + (size_t)i * a.capA;
         const uint64_t *mA = a.umA + (size_t)i * a.capA;
         const int32_t *rowA = a.candA + (size_t)i * a.capA;
+#pragma unroll
+        for (int n0 = 0; n0 < NA1; n0 += NG) {
+        float A[NG][kNumSH];
+#pragma unroll
+        for (int g = 0; g < NG; ++g)
+#pragma unroll
+            for (int m = 0; m < kNumSH; ++m) A[g][m] = 0.0f;
         for (int t = 0; t < S; ++t) {
             int s0, s1;
             block_range(a.uendA, i, t, s0, s1);
             const float *c = prm + __builtin_amdgcn_readfirstlane(a.oA + (tc * S + t) * NA1 * KA1);   // uniform
             // g_n = f_c / 2 (cs_n + sum_{k>0} c_nk T_k), cs_n = c_n0 + sum_k c_nk
-            float cs[NA1];
+            float cs[NG];
 #pragma unroll
-            for (int n = 0; n < NA1; ++n) {
+            for (int g = 0; g < NG; ++g) {
+                const int n = n0 + g < NA1 ? n0 + g : NA1 - 1;
                 float acc = c[n * KA1];
 #pragma unroll
                 for (int q2 = 0; q2 < KA1; ++q2) acc += c[n * KA1 + q2];
-                cs[n] = acc;
+                cs[g] = acc;
             }
             // batches of kBatch entries: slots, then partners, then their
             // positions, each level's loads in flight together (slots past
@@ -411,30 +420,34 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                     float Y[kNumSH];
                     sh_eval(dx * rinv, dy * rinv, dz * rinv, shl, Y);
 #pragma unroll
-                    for (int n = 0; n < NA1; ++n) {
-                        float g = cs[n];
+                    for (int g = 0; g < NG; ++g) {
+                        const int n = n0 + g;
+                        if (n >= NA1) break;
+                        float gn = cs[g];
 #pragma unroll
-                        for (int q2 = 1; q2 < KA1; ++q2) g = fmaf(cl[n * KA1 + q2], T[q2], g);
-                        g *= hf;
+                        for (int q2 = 1; q2 < KA1; ++q2) gn = fmaf(cl[n * KA1 + q2], T[q2], gn);
+                        gn *= hf;
 #pragma unroll
-                        for (int m = 0; m < kNumSH; ++m) A[n][m] += g * Y[m];
+                        for (int m = 0; m < kNumSH; ++m) A[g][m] += gn * Y[m];
                     }
                 }
             }
         }
 #pragma unroll
-        for (int n = 0; n < NA1; ++n) {
+        for (int g = 0; g < NG; ++g) {
+            const int n = n0 + g;
+            if (n >= NA1) break;
 #pragma unroll
             for (int l = 1; l <= kLmax; ++l) {
                 float s2 = 0.0f;
 #pragma unroll
                 for (int m = 0; m < kNumSH; ++m)
-                    if (sh_l(m) == l) s2 += A[n][m] * A[n][m];
+                    if (sh_l(m) == l) s2 += A[g][m] * A[g][m];
                 q[NR1 + (l - 1) * NA1 + n] = s2;
             }
             if (FOUR) {
                 float M[5];
-                m_from_l2(&A[n][3], shc, M);
+                m_from_l2(&A[g][3], shc, M);
                 const float mxy = M[0], myz = M[1], mzz = M[2], mxz = M[3], dd = M[4];
                 const float mxx = 0.5f * (dd - mzz), myy = 0.5f * (-dd - mzz);
                 const float tr3 = mxx * mxx * mxx + myy * myy * myy + mzz * mzz * mzz +
@@ -442,22 +455,18 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                                   3.0f * mzz * (mxz * mxz + myz * myz) + 6.0f * mxy * myz * mxz;
                 q[NR1 + kLmax * NA1 + n] = a.kappa4 * tr3;
             }
-        }
-        if constexpr (PARK) {
-            // park A in this atom's adjoint row (overwritten with B below)
-#pragma unroll
-            for (int n = 0; n < NA1; ++n) {
+            if constexpr (PARK) {
+                // park A in this atom's adjoint row (overwritten with B below)
                 float4 *o4 = reinterpret_cast<float4 *>(Bo + n * kNumSH);
 #pragma unroll
                 for (int q4 = 0; q4 < kNumSH / 4; ++q4)
-                    o4[q4] = make_float4(A[n][4 * q4], A[n][4 * q4 + 1], A[n][4 * q4 + 2], A[n][4 * q4 + 3]);
+                    o4[q4] = make_float4(A[g][4 * q4], A[g][4 * q4 + 1], A[g][4 * q4 + 2], A[g][4 * q4 + 3]);
+            } else {
+#pragma unroll
+                for (int m = 0; m < kNumSH; ++m) Ar[PARK ? 0 : n][m] = A[g][m];
             }
-        } else {
-#pragma unroll
-            for (int n = 0; n < (PARK ? 1 : NA1); ++n)
-#pragma unroll
-                for (int m = 0; m < kNumSH; ++m) Ar[n][m] = A[n][m];
         }
+        }   // angular passes
         }   // descriptors of the lanes of species tc
 
         // network: U = sum_mu w1 tanh(sum_nu W0 s_nu q_nu - b0) - b1;  G_nu = dU/dq_nu
@@ -483,23 +492,55 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             const float *b0 = dyn + nw + tc * a.H;
             const float *w1 = dyn + nw + nb + tc * a.H;
             float u = -prm[a.ob1];
-            for (int mu = 0; mu < a.H; ++mu) {
-                const float4 *w4 = reinterpret_cast<const float4 *>(W0 + mu * DP);
-                float wr[DP];
+            if constexpr (D <= kNetRowRegs) {
+                for (int mu = 0; mu < a.H; ++mu) {
+                    // the weight row in registers, read from LDS once for both products
+                    const float4 *w4 = reinterpret_cast<const float4 *>(W0 + mu * DP);
+                    float wr[DP];
 #pragma unroll
-                for (int v4 = 0; v4 < DP / 4; ++v4) {
-                    const float4 t4 = w4[v4];
-                    wr[4 * v4] = t4.x; wr[4 * v4 + 1] = t4.y; wr[4 * v4 + 2] = t4.z; wr[4 * v4 + 3] = t4.w;
+                    for (int v4 = 0; v4 < DP / 4; ++v4) {
+                        const float4 t4 = w4[v4];
+                        wr[4 * v4] = t4.x; wr[4 * v4 + 1] = t4.y; wr[4 * v4 + 2] = t4.z; wr[4 * v4 + 3] = t4.w;
+                    }
+                    float z = -b0[mu];
+#pragma unroll
+                    for (int v = 0; v < D; ++v) z += wr[v] * qh[v];
+                    float h, dh;
+                    tanh_and_slope(z, h, dh);
+                    u += w1[mu] * h;
+                    const float gz = w1[mu] * dh;
+#pragma unroll
+                    for (int v = 0; v < D; ++v) G[v] += gz * wr[v];
                 }
-                float z = -b0[mu];
+            } else {
+                // long rows: read from LDS in 4-wide chunks for each product
+                // (broadcast reads), so the row takes no registers; one hidden
+                // unit per iteration (unrolling interleaves rows and spills)
+#pragma unroll 1
+                for (int mu = 0; mu < a.H; ++mu) {
+                    const float4 *w4 = reinterpret_cast<const float4 *>(W0 + mu * DP);
+                    float z = -b0[mu];
 #pragma unroll
-                for (int v = 0; v < D; ++v) z += wr[v] * qh[v];
-                float h, dh;
-                tanh_and_slope(z, h, dh);
-                u += w1[mu] * h;
-                const float gz = w1[mu] * dh;
+                    for (int v4 = 0; v4 < DP / 4; ++v4) {
+                        const float4 t4 = w4[v4];
+                        const float wq[4] = {t4.x, t4.y, t4.z, t4.w};
 #pragma unroll
-                for (int v = 0; v < D; ++v) G[v] += gz * wr[v];
+                        for (int e = 0; e < 4; ++e)
+                            if (4 * v4 + e < D) z += wq[e] * qh[4 * v4 + e < D ? 4 * v4 + e : 0];
+                    }
+                    float h, dh;
+                    tanh_and_slope(z, h, dh);
+                    u += w1[mu] * h;
+                    const float gz = w1[mu] * dh;
+#pragma unroll
+                    for (int v4 = 0; v4 < DP / 4; ++v4) {
+                        const float4 t4 = w4[v4];
+                        const float wq[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            if (4 * v4 + e < D) G[4 * v4 + e < D ? 4 * v4 + e : 0] += gz * wq[e];
+                    }
+                }
             }
             U = u;
         } else {
