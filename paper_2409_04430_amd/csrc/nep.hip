@@ -640,17 +640,22 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
 //   d_ij = sum_n sum_lm B^i_nlm d/dr_ij [ g^{ij}_n(r) Y_lm(u) ],
 // deposited where the partner j reads it back (its angular slot of i, same
 // bead), and summed into the angular force part F_i += d_ij and the virial
-// -r_ij (x) d_ij (the total needs no reverse terms).  BREG keeps B^i in
-// registers (small n_max); otherwise it is re-read from its L1-resident row.
+// -r_ij (x) d_ij (the total needs no reverse terms).  B^i stays in
+// registers for the whole neighbour walk; with more than five radial
+// functions that takes the register file of one wavefront per SIMD
+// (VGPRs and AGPRs): re-reading the row per neighbour instead streamed it
+// from memory, the rows of a CU's wavefronts being larger than its caches.
 // Control flow stays wave-uniform: lanes outside the current centre species,
 // past their atom's last candidate or outside the cutoff compute on a dummy
 // pair and contribute nothing; a candidate outside for every lane is
 // skipped.
 constexpr int kBatchAng = 4;   // angular entries whose loads are issued together
+// Wavefronts per SIMD of k_force_ang.
+template <int NA1> constexpr int kAngWaves() { return NA1 > 5 ? 1 : 2; }
 constexpr int kBatchRev = 8;   // reverse angular terms read together by the radial force kernel
 
-template <int NA1, int KA1, bool BREG, bool TRI>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+template <int NA1, int KA1, bool TRI>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kAngWaves<NA1>())))
 void k_force_ang(NepArgs a, const float *__restrict__ prm)
 {
     const LaneMap lm = lane_map(a);
@@ -679,17 +684,15 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
         todo &= ~__ballot(mine);
 
         const float4 *bi4 = reinterpret_cast<const float4 *>(a.B + ((size_t)i * P + b) * (NA1 * kNumSH));
-        float Bi[BREG ? NA1 : 1][kNumSH];
-        if (BREG) {
+        float Bi[NA1][kNumSH];
 #pragma unroll
-            for (int n = 0; n < (BREG ? NA1 : 1); ++n)
+        for (int n = 0; n < NA1; ++n)
 #pragma unroll
-                for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
-                    const float4 v4 = bi4[n * (kNumSH / 4) + q4];
-                    Bi[n][4 * q4] = v4.x; Bi[n][4 * q4 + 1] = v4.y;
-                    Bi[n][4 * q4 + 2] = v4.z; Bi[n][4 * q4 + 3] = v4.w;
-                }
-        }
+            for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
+                const float4 v4 = bi4[n * (kNumSH / 4) + q4];
+                Bi[n][4 * q4] = v4.x; Bi[n][4 * q4 + 1] = v4.y;
+                Bi[n][4 * q4 + 2] = v4.z; Bi[n][4 * q4 + 3] = v4.w;
+            }
         for (int t = 0; t < S; ++t) {
             int s0 = 0, s1 = 0;
             if (mine) block_range(a.uendA, i, t, s0, s1);
@@ -761,31 +764,7 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
                     }
                 }
                 float sY, gx, gy, gz;
-                if constexpr (BREG) {
-                    adjoint_contract<NA1>(ux, uy, uz, shc_l, Bi, gij, gpij, sY, gx, gy, gz);
-                } else {
-                    float beta[kNumSH], betap[kNumSH];
-#pragma unroll
-                    for (int m = 0; m < kNumSH; ++m) {
-                        beta[m] = 0.0f;
-                        betap[m] = 0.0f;
-                    }
-#pragma unroll
-                    for (int n = 0; n < NA1; ++n) {
-#pragma unroll
-                        for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
-                            const float4 x4 = bi4[n * (kNumSH / 4) + q4];
-                            const float bx[4] = {x4.x, x4.y, x4.z, x4.w};
-#pragma unroll
-                            for (int e = 0; e < 4; ++e) {
-                                const int m = 4 * q4 + e;
-                                beta[m] = fmaf(bx[e], gij[n], beta[m]);
-                                betap[m] = fmaf(bx[e], gpij[n], betap[m]);
-                            }
-                        }
-                    }
-                    sh_contract(ux, uy, uz, shc_l, beta, betap, sY, gx, gy, gz);
-                }
+                adjoint_contract<NA1>(ux, uy, uz, shc_l, Bi, gij, gpij, sY, gx, gy, gz);
                 const float ug = ux * gx + uy * gy + uz * gz;
                 const float px = sY * ux + (gx - ux * ug) * rinv;
                 const float py = sY * uy + (gy - uy * ug) * rinv;
@@ -1040,7 +1019,7 @@ static void launch_t(const NepArgs &a, const float *prm, int nblk, int wpb, int 
     }
     {
         ProfScope ps_(K_FORCE_ANG, s);
-        hipLaunchKernelGGL((k_force_ang<NA1, 9, (NA1 <= 5), TRI>), g, blk, 0, s, a, prm);
+        hipLaunchKernelGGL((k_force_ang<NA1, 9, TRI>), g, blk, 0, s, a, prm);
     }
     {
         ProfScope ps_(K_FORCE, s);

@@ -166,59 +166,6 @@ __device__ __forceinline__ void sh_eval(float x, float y, float z, CP c, float *
     Y[23] = c[23] * (x2 * (x2 - 3.0f * y2) - y2 * (3.0f * x2 - y2));
 }
 
-// sY = sum_m bp_m Y_m(u);  g = sum_m b_m grad p_m(u), where Y_m = c_m p_m and
-// the polynomial p_m is differentiated as a function on R^3 (the tangential
-// projection is applied by the caller).
-template <typename CP>
-__device__ __forceinline__ void sh_contract(float x, float y, float z, CP c, const float *b,
-                                            const float *bp, float &sY, float &gx, float &gy, float &gz)
-{
-    float Y[kNumSH];
-    sh_eval(x, y, z, c, Y);
-    float s = 0.0f;
-#pragma unroll
-    for (int m = 0; m < kNumSH; ++m) s += bp[m] * Y[m];
-    sY = s;
-    float w[kNumSH];
-#pragma unroll
-    for (int m = 0; m < kNumSH; ++m) w[m] = b[m] * c[m];
-    const float x2 = x * x, y2 = y * y, z2 = z * z;
-    const float xy = x * y, yz = y * z, xz = x * z;
-    float X = 0.0f, Yv = 0.0f, Z = 0.0f;
-    // l = 1
-    Yv += w[0];
-    Z += w[1];
-    X += w[2];
-    // l = 2
-    X += w[3] * y;  Yv += w[3] * x;
-    Yv += w[4] * z; Z += w[4] * y;
-    Z += w[5] * 6.0f * z;
-    X += w[6] * z;  Z += w[6] * x;
-    X += w[7] * 2.0f * x; Yv -= w[7] * 2.0f * y;
-    // l = 3
-    X += w[8] * 6.0f * xy;  Yv += w[8] * 3.0f * (x2 - y2);
-    X += w[9] * yz; Yv += w[9] * xz; Z += w[9] * xy;
-    Yv += w[10] * (5.0f * z2 - 1.0f); Z += w[10] * 10.0f * yz;
-    Z += w[11] * (15.0f * z2 - 3.0f);
-    X += w[12] * (5.0f * z2 - 1.0f); Z += w[12] * 10.0f * xz;
-    X += w[13] * 2.0f * xz; Yv -= w[13] * 2.0f * yz; Z += w[13] * (x2 - y2);
-    X += w[14] * 3.0f * (x2 - y2); Yv -= w[14] * 6.0f * xy;
-    // l = 4
-    X += w[15] * (3.0f * x2 * y - y2 * y); Yv += w[15] * (x2 * x - 3.0f * x * y2);
-    X += w[16] * 6.0f * xy * z; Yv += w[16] * 3.0f * z * (x2 - y2); Z += w[16] * (3.0f * x2 * y - y2 * y);
-    X += w[17] * y * (7.0f * z2 - 1.0f); Yv += w[17] * x * (7.0f * z2 - 1.0f); Z += w[17] * 14.0f * xy * z;
-    Yv += w[18] * z * (7.0f * z2 - 3.0f); Z += w[18] * y * (21.0f * z2 - 3.0f);
-    Z += w[19] * z * (140.0f * z2 - 60.0f);
-    X += w[20] * z * (7.0f * z2 - 3.0f); Z += w[20] * x * (21.0f * z2 - 3.0f);
-    X += w[21] * 2.0f * x * (7.0f * z2 - 1.0f); Yv -= w[21] * 2.0f * y * (7.0f * z2 - 1.0f);
-    Z += w[21] * 14.0f * z * (x2 - y2);
-    X += w[22] * 3.0f * z * (x2 - y2); Yv -= w[22] * 6.0f * xy * z; Z += w[22] * x * (x2 - 3.0f * y2);
-    X += w[23] * (4.0f * x2 * x - 12.0f * x * y2); Yv += w[23] * (4.0f * y2 * y - 12.0f * x2 * y);
-    gx = X;
-    gy = Yv;
-    gz = Z;
-}
-
 // Contraction of the own adjoints with the harmonics of one pair, one m at a
 // time so that no per-m array stays live:
 //   sY = sum_m (sum_n B_nm g'_n) Y_m(u),  grad = sum_m (sum_n B_nm g_n) c_m grad p_m(u)
