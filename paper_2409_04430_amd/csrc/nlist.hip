@@ -467,9 +467,9 @@ __device__ void sort_row_into(int32_t *__restrict__ dst, int n, const int32_t *_
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Candidate rows.  `split` work items per cell, each taking every
-// split-th group of the cell's atoms (small or skewed cells have few
-// cells with large stencils), looped over by a capped grid; the centroids of the cell's stencil cells
+// Candidate rows.  gridDim.y workgroups per cell, each taking every
+// gridDim.y-th group of the cell's atoms (small or skewed cells have few
+// cells with large stencils); the centroids of the cell's stencil cells
 // (3 x 3 x 3, fewer along an axis with fewer than 3 cells) are staged in
 // LDS when they fit, and each wavefront takes one atom at a time, its lanes
 // testing 64 stencil atoms at once and appending the accepted ones by
@@ -477,8 +477,7 @@ __device__ void sort_row_into(int32_t *__restrict__ dst, int n, const int32_t *_
 // which k_union sorts).  A stencil too large for LDS is read from global
 // memory instead.
 constexpr int kStage = 2048;
-constexpr int kCandSplitMax = 16;   // work items per cell at most
-constexpr int kCandGrid = 256;      // workgroups of the candidate search
+constexpr int kCandSplitMax = 16;   // workgroups per cell at most
 __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ cen, const int32_t *__restrict__ types,
                                                     int N, int S, const SysGeom *__restrict__ geom,
                                                     const int32_t *__restrict__ cell_sys, uint32_t *__restrict__ grid,
@@ -487,129 +486,122 @@ __global__ __launch_bounds__(256) void k_candidates(const double *__restrict__ c
                                                     int32_t *__restrict__ cell_cnt, int capR, int capA,
                                                     int32_t *__restrict__ candR, int32_t *__restrict__ lenR,
                                                     int32_t *__restrict__ candA, int32_t *__restrict__ lenA,
-                                                    double *__restrict__ cen_ref, uint32_t *__restrict__ status,
-                                                    int ncell_total, int split)
+                                                    double *__restrict__ cen_ref, uint32_t *__restrict__ status)
 {
     __shared__ double sx[kStage], sy[kStage], sz[kStage];
     __shared__ int32_t sw[kStage];
     __shared__ int32_t rs[28], rp[28];
     __shared__ int nrange;
     DevGlobal *dg = dev_global(grid);
-    if (!dg->rebuild) return;   // whole workgroup: most calls keep their rows
+    const int sy_ = cell_sys[blockIdx.x];
+    const SysGeom &g = geom[sy_];
+    const DevSys ds = *dev_sys(grid, sy_);
+    const int c = blockIdx.x - g.cell_base;   // cell within its system
+    if (!dg->rebuild || c >= ds.ncell) return;   // whole workgroup
+    if (threadIdx.x == 0 && blockIdx.y == 0) cell_cnt[blockIdx.x] = 0;   // counts start from zero at the next rebuild
+    const int nc0 = ds.nc[0], nc1 = ds.nc[1], nc2 = ds.nc[2];
     const double R2 = dg->R2, RA2 = dg->RA2;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (threadIdx.x == 0) {
+        const int cx = c % nc0, cy = (c / nc0) % nc1, cz = c / (nc0 * nc1);
+        const int oz_n = nc2 >= 3 ? 3 : nc2, oy_n = nc1 >= 3 ? 3 : nc1, ox_n = nc0 >= 3 ? 3 : nc0;
+        int nr = 0, tot = 0;
+        for (int oz = 0; oz < oz_n; ++oz) {
+            int z = nc2 >= 3 ? cz + oz - 1 : oz;
+            z = z < 0 ? z + nc2 : (z >= nc2 ? z - nc2 : z);
+            for (int oy = 0; oy < oy_n; ++oy) {
+                int y = nc1 >= 3 ? cy + oy - 1 : oy;
+                y = y < 0 ? y + nc1 : (y >= nc1 ? y - nc1 : y);
+                for (int ox = 0; ox < ox_n; ++ox) {
+                    int x = nc0 >= 3 ? cx + ox - 1 : ox;
+                    x = x < 0 ? x + nc0 : (x >= nc0 ? x - nc0 : x);
+                    const int cc = g.cell_base + (z * nc1 + y) * nc0 + x;
+                    rs[nr] = cell_start[cc];
+                    rp[nr] = tot;
+                    tot += cell_start[cc + 1] - cell_start[cc];
+                    ++nr;
+                }
+            }
+        }
+        rp[nr] = tot;
+        nrange = nr;
+    }
+    __syncthreads();
+    const int nr = nrange, total = rp[nr];
+    const bool staged = total <= kStage;
+    // flat stencil position q -> index into cell_atoms (the last range starting at or before q)
+    auto at = [&](int q) {
+        int lo = 0, hi = nr - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rp[mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        return rs[lo] + (q - rp[lo]);
+    };
+    if (staged) {
+        for (int q = threadIdx.x; q < total; q += blockDim.x) {
+            const int j = cell_atoms[at(q)];
+            const int tj = types[j];
+            sx[q] = cen[3 * j];
+            sy[q] = cen[3 * j + 1];
+            sz[q] = cen[3 * j + 2];
+            sw[q] = (tj >= 0 && tj < S) ? ((j << 2) | tj) : -1;
+        }
+    }
+    __syncthreads();
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int a0 = cell_start[blockIdx.x], a1 = cell_start[blockIdx.x + 1];
     const int waves = blockDim.x >> 6;
-    // work items (cell, part), part = which of the cell's atoms
-    for (int item = blockIdx.x; item < ncell_total * split; item += gridDim.x) {
-        const int cell = item / split, part = item - cell * split;
-        const int sy_ = cell_sys[cell];
-        const SysGeom &g = geom[sy_];
-        const DevSys ds = *dev_sys(grid, sy_);
-        const int c = cell - g.cell_base;   // cell within its system
-        if (c >= ds.ncell) continue;        // whole workgroup
-        if (threadIdx.x == 0 && part == 0) cell_cnt[cell] = 0;   // counts start from zero at the next rebuild
-        const int nc0 = ds.nc[0], nc1 = ds.nc[1], nc2 = ds.nc[2];
-        if (threadIdx.x == 0) {
-            const int cx = c % nc0, cy = (c / nc0) % nc1, cz = c / (nc0 * nc1);
-            const int oz_n = nc2 >= 3 ? 3 : nc2, oy_n = nc1 >= 3 ? 3 : nc1, ox_n = nc0 >= 3 ? 3 : nc0;
-            int nr = 0, tot = 0;
-            for (int oz = 0; oz < oz_n; ++oz) {
-                int z = nc2 >= 3 ? cz + oz - 1 : oz;
-                z = z < 0 ? z + nc2 : (z >= nc2 ? z - nc2 : z);
-                for (int oy = 0; oy < oy_n; ++oy) {
-                    int y = nc1 >= 3 ? cy + oy - 1 : oy;
-                    y = y < 0 ? y + nc1 : (y >= nc1 ? y - nc1 : y);
-                    for (int ox = 0; ox < ox_n; ++ox) {
-                        int x = nc0 >= 3 ? cx + ox - 1 : ox;
-                        x = x < 0 ? x + nc0 : (x >= nc0 ? x - nc0 : x);
-                        const int cc = g.cell_base + (z * nc1 + y) * nc0 + x;
-                        rs[nr] = cell_start[cc];
-                        rp[nr] = tot;
-                        tot += cell_start[cc + 1] - cell_start[cc];
-                        ++nr;
-                    }
+    for (int a = a0 + blockIdx.y * waves + wv; a < a1; a += gridDim.y * waves) {
+        const int i = cell_atoms[a];
+        const double ci[3] = {cen[3 * i], cen[3 * i + 1], cen[3 * i + 2]};
+        int32_t *rowR = candR + (size_t)i * capR;
+        int32_t *rowA = candA + (size_t)i * capA;
+        int cR = 0, cA = 0;
+        for (int q0 = 0; q0 < total; q0 += 64) {
+            const int q = q0 + lane;
+            bool okR = false, okA = false;
+            int w = -1;
+            if (q < total) {
+                double p[3];
+                if (staged) {
+                    p[0] = sx[q]; p[1] = sy[q]; p[2] = sz[q];
+                    w = sw[q];
+                } else {
+                    const int j = cell_atoms[at(q)];
+                    const int tj = types[j];
+                    p[0] = cen[3 * j]; p[1] = cen[3 * j + 1]; p[2] = cen[3 * j + 2];
+                    w = (tj >= 0 && tj < S) ? ((j << 2) | tj) : -1;
+                }
+                if (w >= 0 && (w >> 2) != i) {
+                    double d[3] = {p[0] - ci[0], p[1] - ci[1], p[2] - ci[2]};
+                    mic_vec(d, g, g.tri);
+                    const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
+                    okR = r2 < R2;
+                    okA = r2 < RA2;
                 }
             }
-            rp[nr] = tot;
-            nrange = nr;
+            const uint64_t mR = __ballot(okR), mA = __ballot(okA);
+            const int pR = cR + __popcll(mR & below), pA = cA + __popcll(mA & below);
+            if (okR && pR < capR) rowR[pR] = w;
+            if (okA && pA < capA) rowA[pA] = w;
+            cR += __popcll(mR);
+            cA += __popcll(mA);
         }
-        __syncthreads();
-        const int nr = nrange, total = rp[nr];
-        const bool staged = total <= kStage;
-        // flat stencil position q -> index into cell_atoms (the last range starting at or before q)
-        auto at = [&](int q) {
-            int lo = 0, hi = nr - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (rp[mid] <= q) lo = mid;
-                else hi = mid - 1;
-            }
-            return rs[lo] + (q - rp[lo]);
-        };
-        if (staged) {
-            for (int q = threadIdx.x; q < total; q += blockDim.x) {
-                const int j = cell_atoms[at(q)];
-                const int tj = types[j];
-                sx[q] = cen[3 * j];
-                sy[q] = cen[3 * j + 1];
-                sz[q] = cen[3 * j + 2];
-                sw[q] = (tj >= 0 && tj < S) ? ((j << 2) | tj) : -1;
+        if (lane == 0) {
+            lenR[i] = cR;
+            lenA[i] = cA;
+            cen_ref[3 * i] = ci[0];
+            cen_ref[3 * i + 1] = ci[1];
+            cen_ref[3 * i + 2] = ci[2];
+            raise_max(&status[3], (uint32_t)cR);
+            raise_max(&status[6], (uint32_t)cA);
+            if (cR > capR || cA > capA) {
+                atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
+                atomicOr(&dg->rows_overflow, 1u);
             }
         }
-        __syncthreads();
-        const int a0 = cell_start[cell], a1 = cell_start[cell + 1];
-        for (int a = a0 + part * waves + wv; a < a1; a += split * waves) {
-            const int i = cell_atoms[a];
-            const double ci[3] = {cen[3 * i], cen[3 * i + 1], cen[3 * i + 2]};
-            int32_t *rowR = candR + (size_t)i * capR;
-            int32_t *rowA = candA + (size_t)i * capA;
-            int cR = 0, cA = 0;
-            for (int q0 = 0; q0 < total; q0 += 64) {
-                const int q = q0 + lane;
-                bool okR = false, okA = false;
-                int w = -1;
-                if (q < total) {
-                    double p[3];
-                    if (staged) {
-                        p[0] = sx[q]; p[1] = sy[q]; p[2] = sz[q];
-                        w = sw[q];
-                    } else {
-                        const int j = cell_atoms[at(q)];
-                        const int tj = types[j];
-                        p[0] = cen[3 * j]; p[1] = cen[3 * j + 1]; p[2] = cen[3 * j + 2];
-                        w = (tj >= 0 && tj < S) ? ((j << 2) | tj) : -1;
-                    }
-                    if (w >= 0 && (w >> 2) != i) {
-                        double d[3] = {p[0] - ci[0], p[1] - ci[1], p[2] - ci[2]};
-                        mic_vec(d, g, g.tri);
-                        const double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-                        okR = r2 < R2;
-                        okA = r2 < RA2;
-                    }
-                }
-                const uint64_t mR = __ballot(okR), mA = __ballot(okA);
-                const int pR = cR + __popcll(mR & below), pA = cA + __popcll(mA & below);
-                if (okR && pR < capR) rowR[pR] = w;
-                if (okA && pA < capA) rowA[pA] = w;
-                cR += __popcll(mR);
-                cA += __popcll(mA);
-            }
-            if (lane == 0) {
-                lenR[i] = cR;
-                lenA[i] = cA;
-                cen_ref[3 * i] = ci[0];
-                cen_ref[3 * i + 1] = ci[1];
-                cen_ref[3 * i + 2] = ci[2];
-                raise_max(&status[3], (uint32_t)cR);
-                raise_max(&status[6], (uint32_t)cA);
-                if (cR > capR || cA > capA) {
-                    atomicOr(&status[0], (uint32_t)NEP_FLAG_NEIGHBOR_OVERFLOW);
-                    atomicOr(&dg->rows_overflow, 1u);
-                }
-            }
-        }
-        __syncthreads();   // the stencil records and staged centroids are rewritten by the next item
     }
 }
 
@@ -939,11 +931,8 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
     // a per-axis scaling of an orthorhombic cell is covered by the device-side skin test
     const bool force = !nl->built || tri_changed;
     const dim3 gw(div_up(N, kBlock / 64));
-    // enough work items for the candidate search even when the cells are few;
-    // a grid of at most kCandGrid workgroups loops over them (on most calls
-    // the rows are kept and every workgroup returns at once)
-    const int split = std::min(kCandSplitMax, std::max(1, div_up(1024, nl->ncell_total)));
-    const dim3 gc(std::min(kCandGrid, nl->ncell_total * split));
+    // enough workgroups for the candidate search even when the cells are few
+    const dim3 gc(nl->ncell_total, std::min(kCandSplitMax, std::max(1, div_up(1024, nl->ncell_total))));
     {
         ProfScope ps_(K_CENTROID, s);
         const int nblk = div_up(N * kCenLanes, kBlock);
@@ -959,7 +948,7 @@ extern "C" int32_t neighbor_build_batched(const nep_model *m, nep_nlist *nl, con
         hipLaunchKernelGGL(k_candidates, gc, dim3(kBlock), 0, s, nl->cen, types, N, nl->S, nl->geom, nl->cell_sys,
                            nl->grid, nl->cell_start, nl->cell_atoms, nl->cell_cnt, nl->capR, nl->capA, nl->candRs,
                            nl->lenR,
-                           nl->candAs, nl->lenA, nl->cen_ref, nl->status, nl->ncell_total, split);
+                           nl->candAs, nl->lenA, nl->cen_ref, nl->status);
     }
     {
         ProfScope ps_(K_NLIST, s);
