@@ -578,7 +578,9 @@ def workload_leg(args, torch, lib, configs, I, NepPimd, name: str, steps: int, g
            "roofline": roofline(dom, dom_us, hp, nR, nA, units, bytes_per_atom(hp, nR, nA, P, cR, cA))}
     if eng.tile is not None:
         out["autotuned_waves_per_group"] = eng.tile[0]
-        out["autotune_ms"] = {str(k): round(v, 4) for k, v in eng.tile[1].items()}
+        out["autotuned_weights"] = "lds" if eng.tile[1] == lib.WEIGHTS_LDS else "global"
+        out["autotune_ms"] = {f"{w}w_{'lds' if st == lib.WEIGHTS_LDS else 'global'}": round(v, 4)
+                              for (w, st), v in eng.tile[2].items()}
     if graph:
         gms, _, grb, _ = timed_steps(torch, eng, steps, True)
         out["graph_ms_per_step"] = round(gms, 4)

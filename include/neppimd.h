@@ -345,11 +345,26 @@ int32_t nep_compute_batched(const nep_model *model, nep_nlist *nl, nep_ws *ws, c
 int32_t nep_ws_set_tile(nep_ws *ws, int32_t waves_per_group);
 int32_t nep_ws_get_tile(const nep_ws *ws, int32_t *waves_per_group);
 
+/* Where the FP32 network's weights are read from in nep_compute (vector-
+ * unit network): staged in LDS once per workgroup (default; used only where
+ * S H (D + 2) floats fit 60 KiB, else global) or read from global memory.
+ * Both evaluate the same products in the same order, so E, F and W are
+ * bitwise the same; only the speed differs.  No effect on the matrix-core
+ * networks.  Errors: NEP_ERR_INVALID_ARG. */
+enum nep_weight_staging { NEP_WEIGHTS_LDS = 0, NEP_WEIGHTS_GLOBAL = 1 };
+int32_t nep_ws_set_weight_staging(nep_ws *ws, int32_t staging);
+int32_t nep_ws_get_weight_staging(const nep_ws *ws, int32_t *staging);
+
 /* Autotuner: times nep_compute_batched (one warm-up plus `reps` calls, HIP
- * events on `stream`) for every tile shape, keeps the fastest in the
- * workspace and reports it in *best (host), with the mean times in ms_out[3]
- * (host, for 1, 2 and 4 wavefronts; may be NULL).  E, F, W are overwritten.
- * Synchronises the stream.  Errors as nep_compute_batched. */
+ * events on `stream`) for every tile shape (1, 2, 4 wavefronts per
+ * workgroup) and weight staging (LDS, global; LDS only where the weights
+ * fit, and one staging for the matrix-core networks), keeps the fastest in
+ * the workspace and reports it in best[2] (host: wavefronts per workgroup,
+ * staging), with the mean times in ms_out[6] (host, entry 2 c + st for tile
+ * choice c and staging st, -1 where a staging does not apply; may be NULL).
+ * Forces and virials do not depend on either knob (energies regroup per
+ * tile).  E, F, W are overwritten.  Synchronises the stream.  Errors as
+ * nep_compute_batched. */
 int32_t nep_autotune(const nep_model *model, nep_nlist *nl, nep_ws *ws, const double *pos, const double *boxes,
                      const int32_t *types, int32_t P, int32_t N, double *E, float *F, double *W, int32_t reps,
                      float *ms_out, int32_t *best, hipStream_t stream);

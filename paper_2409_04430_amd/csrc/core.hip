@@ -705,6 +705,22 @@ extern "C" int32_t nep_ws_get_tile(const nep_ws *w, int32_t *waves_per_group)
     return NEP_OK;
 }
 
+extern "C" int32_t nep_ws_set_weight_staging(nep_ws *w, int32_t staging)
+{
+    if (!w) return fail(NEP_ERR_INVALID_ARG, "nep_ws_set_weight_staging: null argument");
+    if (staging != NEP_WEIGHTS_LDS && staging != NEP_WEIGHTS_GLOBAL)
+        return fail(NEP_ERR_INVALID_ARG, "nep_ws_set_weight_staging: unknown staging %d", staging);
+    w->net_global = staging == NEP_WEIGHTS_GLOBAL;
+    return NEP_OK;
+}
+
+extern "C" int32_t nep_ws_get_weight_staging(const nep_ws *w, int32_t *staging)
+{
+    if (!w || !staging) return fail(NEP_ERR_INVALID_ARG, "nep_ws_get_weight_staging: null argument");
+    *staging = w->net_global ? NEP_WEIGHTS_GLOBAL : NEP_WEIGHTS_LDS;
+    return NEP_OK;
+}
+
 extern "C" int32_t nep_ws_create_batched(const nep_model *m, int32_t P, int32_t nsys, const int32_t *off,
                                          nep_ws **out)
 {

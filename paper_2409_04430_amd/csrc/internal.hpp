@@ -171,6 +171,7 @@ struct nep_ws {
     // Tiles: each workgroup of the NEP kernels takes up to 4 * 64 / G atoms
     // (all their beads) of one system.
     int wpb = 4;                    // wavefronts per workgroup (tile shape), set by nep_ws_set_tile / nep_autotune
+    int net_global = 0;             // 1: FP32 network weights read from global memory even where they fit LDS
     int nblk_cap = 0;               // tile capacity (the count for one wavefront per workgroup)
     int32_t *tile_atom0 = nullptr, *tile_atom1 = nullptr, *tile_sys = nullptr;   // [nblk_cap]
     int32_t *sys_tile0 = nullptr;   // [nsys + 1]

@@ -999,7 +999,7 @@ constexpr size_t kNetLdsMax = 60 * 1024;   // bytes of LDS for the staged networ
 
 // mlp: NEP_MLP_FP32 (vector units), NEP_MLP_BF16_MFMA or NEP_MLP_FP32_MFMA (matrix cores).
 template <int NR1, int NA1, bool FOUR, bool TRI>
-static void launch_t(const NepArgs &a, const float *prm, int nblk, int wpb, int mlp, hipStream_t s)
+static void launch_t(const NepArgs &a, const float *prm, int nblk, int wpb, int mlp, bool lds_net, hipStream_t s)
 {
     const dim3 g(nblk);
     const dim3 blk(64 * wpb);
@@ -1012,7 +1012,7 @@ static void launch_t(const NepArgs &a, const float *prm, int nblk, int wpb, int 
             hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetBf16, TRI>), g, blk, mf, s, a, prm);
         else if (mlp == NEP_MLP_FP32_MFMA)   // FP32 weights as three BF16 terms
             hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetMf32, TRI>), g, blk, mf, s, a, prm);
-        else if (net <= kNetLdsMax)   // network weights staged in LDS
+        else if (lds_net && net <= kNetLdsMax)   // network weights staged in LDS
             hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetLds, TRI>), g, blk, net, s, a, prm);
         else
             hipLaunchKernelGGL((k_descriptor<NR1, NA1, 9, 9, FOUR, kNetGlobal, TRI>), g, blk, 0, s, a, prm);
@@ -1030,10 +1030,11 @@ static void launch_t(const NepArgs &a, const float *prm, int nblk, int wpb, int 
 // General (triclinic) cells get the kernels with the general pair vector;
 // orthorhombic-only lists the ones without it.
 template <int NR1, int NA1, bool FOUR>
-static void launch(const NepArgs &a, const float *prm, int nblk, int wpb, bool tri, int mlp, hipStream_t s)
+static void launch(const NepArgs &a, const float *prm, int nblk, int wpb, bool tri, int mlp, bool lds_net,
+                   hipStream_t s)
 {
-    if (tri) launch_t<NR1, NA1, FOUR, true>(a, prm, nblk, wpb, mlp, s);
-    else launch_t<NR1, NA1, FOUR, false>(a, prm, nblk, wpb, mlp, s);
+    if (tri) launch_t<NR1, NA1, FOUR, true>(a, prm, nblk, wpb, mlp, lds_net, s);
+    else launch_t<NR1, NA1, FOUR, false>(a, prm, nblk, wpb, mlp, lds_net, s);
 }
 
 }  // namespace nep
@@ -1091,11 +1092,11 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
     const int key = h.n_max_radial * 100 + h.n_max_angular * 10 + h.four_body;
     const bool tri = nl->any_tri != 0;
     switch (key) {
-    case 440: launch<5, 5, false>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, s); break;
-    case 441: launch<5, 5, true>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, s); break;
-    case 640: launch<7, 5, false>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, s); break;
-    case 860: launch<9, 7, false>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, s); break;
-    case 881: launch<9, 9, true>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, s); break;
+    case 440: launch<5, 5, false>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, !ws->net_global, s); break;
+    case 441: launch<5, 5, true>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, !ws->net_global, s); break;
+    case 640: launch<7, 5, false>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, !ws->net_global, s); break;
+    case 860: launch<9, 7, false>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, !ws->net_global, s); break;
+    case 881: launch<9, 9, true>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, !ws->net_global, s); break;
     default: return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");
     }
     {
@@ -1122,37 +1123,52 @@ extern "C" int32_t nep_autotune(const nep_model *m, nep_nlist *nl, nep_ws *ws, c
     if (!m || !nl || !ws) return fail(NEP_ERR_INVALID_ARG, "nep_autotune: null argument");
     if (reps < 1 || reps > 100) return fail(NEP_ERR_INVALID_ARG, "nep_autotune: reps must be in 1..100");
     const int choices[3] = {1, 2, 4};
+    // the staging knob exists for the vector-unit network whose weights fit LDS
+    const nep_hparams &h = m->hp;
+    const size_t net = sizeof(float) * (size_t)h.n_species * h.hidden * (((h.dim + 3) & ~3) + 2);
+    const int nst = (m->mlp == NEP_MLP_FP32 && net <= kNetLdsMax) ? 2 : 1;
     float best_ms = 0.0f;
-    int best = 4;
+    int best = 4, best_st = NEP_WEIGHTS_LDS;
+    if (ms_out)
+        for (int k = 0; k < 6; ++k) ms_out[k] = -1.0f;
     hipEvent_t e0, e1;
     NEP_HIP(hipEventCreate(&e0));
     NEP_HIP(hipEventCreate(&e1));
     int32_t rc = NEP_OK;
-    for (int c = 0; c < 3 && rc == NEP_OK; ++c) {
-        rc = nep_ws_set_tile(ws, choices[c]);
-        if (rc != NEP_OK) break;
-        rc = nep_compute_batched(m, nl, ws, pos, boxes, types, P, N, E, F, W, nullptr, nullptr, s);   // warm-up
-        if (rc != NEP_OK) break;
-        if (hipEventRecord(e0, s) != hipSuccess) rc = fail(NEP_ERR_HIP, "nep_autotune: event record failed");
-        for (int r = 0; r < reps && rc == NEP_OK; ++r)
-            rc = nep_compute_batched(m, nl, ws, pos, boxes, types, P, N, E, F, W, nullptr, nullptr, s);
-        if (rc != NEP_OK) break;
-        float ms = 0.0f;
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            rc = fail(NEP_ERR_HIP, "nep_autotune: event timing failed");
-            break;
+    bool first = true;
+    for (int c = 0; c < 3 && rc == NEP_OK; ++c)
+        for (int st = 0; st < nst && rc == NEP_OK; ++st) {
+            rc = nep_ws_set_tile(ws, choices[c]);
+            if (rc == NEP_OK) rc = nep_ws_set_weight_staging(ws, st);
+            if (rc != NEP_OK) break;
+            rc = nep_compute_batched(m, nl, ws, pos, boxes, types, P, N, E, F, W, nullptr, nullptr, s);   // warm-up
+            if (rc != NEP_OK) break;
+            if (hipEventRecord(e0, s) != hipSuccess) rc = fail(NEP_ERR_HIP, "nep_autotune: event record failed");
+            for (int r = 0; r < reps && rc == NEP_OK; ++r)
+                rc = nep_compute_batched(m, nl, ws, pos, boxes, types, P, N, E, F, W, nullptr, nullptr, s);
+            if (rc != NEP_OK) break;
+            float ms = 0.0f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                rc = fail(NEP_ERR_HIP, "nep_autotune: event timing failed");
+                break;
+            }
+            ms /= (float)reps;
+            if (ms_out) ms_out[2 * c + st] = ms;
+            if (first || ms < best_ms) {
+                best_ms = ms;
+                best = choices[c];
+                best_st = st;
+                first = false;
+            }
         }
-        ms /= (float)reps;
-        if (ms_out) ms_out[c] = ms;
-        if (c == 0 || ms < best_ms) {
-            best_ms = ms;
-            best = choices[c];
-        }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != NEP_OK) return rc;
-    if (best_out) *best_out = best;
-    return nep_ws_set_tile(ws, best);
+    if (best_out) {
+        best_out[0] = best;
+        best_out[1] = best_st;
+    }
+    rc = nep_ws_set_weight_staging(ws, best_st);
+    return rc != NEP_OK ? rc : nep_ws_set_tile(ws, best);
 }

@@ -167,7 +167,7 @@ class NepPimd:
         self._finished = False   # the last call was finish() (closing half without the next opening half)
         self._fit_capacity()
         self._snapshot()
-        self.tile = None
+        self.tile = None   # autotuned (waves per group, weight staging, {(waves, staging): ms})
         if autotune:
             self.tile = self.ws.autotune(self.nl, self.pos, self.box, self.types, self.E, self.F, self.W)
 

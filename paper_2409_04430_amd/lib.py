@@ -117,6 +117,8 @@ _sig = {
     "nep_nlist_invalidate": (_i32, [_vp]),
     "nep_ws_set_tile": (_i32, [_vp, _i32]),
     "nep_ws_get_tile": (_i32, [_vp, C.POINTER(C.c_int32)]),
+    "nep_ws_set_weight_staging": (_i32, [_vp, _i32]),
+    "nep_ws_get_weight_staging": (_i32, [_vp, C.POINTER(C.c_int32)]),
     "nep_autotune": (_i32, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, _vp, _vp, _vp, _i32,
                             C.POINTER(C.c_float), C.POINTER(C.c_int32), _vp]),
     "nep_model_params": (_i32, [_vp, C.POINTER(_vp), C.POINTER(C.c_int32), C.POINTER(ParamOffsets)]),
@@ -199,6 +201,7 @@ def _box9(box) -> C.Array:
 
 # ------------------------------------------------------------------ handles
 
+WEIGHTS_LDS, WEIGHTS_GLOBAL = 0, 1
 MLP_FP32, MLP_BF16_MFMA, MLP_FP32_MFMA, MLP_FP32_AUTO = 0, 1, 2, 3
 MLP_MODES = {"fp32": MLP_FP32, "bf16_mfma": MLP_BF16_MFMA, "fp32_mfma": MLP_FP32_MFMA, "auto": MLP_FP32_AUTO}
 MLP_NAMES = {v: k for k, v in MLP_MODES.items()}
@@ -464,18 +467,29 @@ class Workspace:
         _check(_lib.nep_ws_get_tile(self._h, C.byref(v)))
         return v.value
 
+    def set_weight_staging(self, staging: int):
+        """WEIGHTS_LDS or WEIGHTS_GLOBAL (results are the same bit for bit)."""
+        _check(_lib.nep_ws_set_weight_staging(self._h, int(staging)))
+
+    def get_weight_staging(self) -> int:
+        v = C.c_int32()
+        _check(_lib.nep_ws_get_weight_staging(self._h, C.byref(v)))
+        return v.value
+
     def autotune(self, nl: NeighborList, pos, box, types, E, F, W, reps: int = 3):
-        """Time every tile shape, keep the fastest; returns (waves per group, {shape: ms})."""
+        """Time every tile shape and weight staging, keep the fastest; returns
+        (waves per group, staging, {(waves, staging): ms})."""
         t = _torch()
         P, N, S = self.P, self.N, self.nsys
         es, ws = ((P,), (P, 9)) if self.offsets is None else ((S, P), (S, P, 9))
-        ms = (C.c_float * 3)()
-        best = C.c_int32()
+        ms = (C.c_float * 6)()
+        best = (C.c_int32 * 2)()
         _check(_lib.nep_autotune(self.model.handle, nl.handle, self._h, _ptr(pos, t.float64, (P, N, 3), "pos"),
                                  _boxes(box, S), _ptr(types, t.int32, (N,), "types"), P, N,
                                  _ptr(E, t.float64, es, "E"), _ptr(F, t.float32, (P, N, 3), "F"),
-                                 _ptr(W, t.float64, ws, "W"), int(reps), ms, C.byref(best), _stream()))
-        return best.value, {1: ms[0], 2: ms[1], 4: ms[2]}
+                                 _ptr(W, t.float64, ws, "W"), int(reps), ms, best, _stream()))
+        times = {(w, st): ms[2 * c + st] for c, w in enumerate((1, 2, 4)) for st in (0, 1) if ms[2 * c + st] >= 0.0}
+        return best[0], best[1], times
 
     def poll(self, clear: bool = True) -> int:
         f = C.c_uint32()

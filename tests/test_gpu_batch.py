@@ -52,7 +52,7 @@ def water(tmpdir_session):
     return path, out
 
 
-def run(torch, L, path, parts, P, tile=None):
+def run(torch, L, path, parts, P, tile=None, staging=None):
     m = L.Model(path)
     sizes = [p[0].shape[1] for p in parts]
     off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
@@ -66,6 +66,8 @@ def run(torch, L, path, parts, P, tile=None):
     ws = L.Workspace(m, P, N, offsets=off if batched else None)
     if tile:
         ws.set_tile(tile)
+    if staging is not None:
+        ws.set_weight_staging(staging)
     es = (len(parts), P) if batched else (P,)
     E = torch.zeros(es, dtype=torch.float64, device=dev)
     W = torch.zeros(es + (9,), dtype=torch.float64, device=dev)
@@ -125,7 +127,8 @@ def test_batch_matches_oracle(torch, L, orc, water):
 
 
 def test_autotune_and_tiles_agree(torch, L, water):
-    """Every tile shape gives the same forces; the autotuner keeps the fastest."""
+    """Every tile shape and weight staging gives the same forces; the
+    autotuner keeps the fastest of the six configurations."""
     path, parts = water
     P = 32
     sub = parts[:6]
@@ -135,13 +138,19 @@ def test_autotune_and_tiles_agree(torch, L, water):
         np.testing.assert_array_equal(got["F"], ref["F"])
         # per-system sums regroup with the tile shape: equal to rounding
         np.testing.assert_allclose(got["E"], ref["E"], rtol=1e-13, atol=1e-10)
-    best, ms = ref["ws"].autotune(ref["nl"], ref["pos"], ref["boxes"], ref["typ"],
-                                  torch.zeros((6, P), dtype=torch.float64, device="cuda"),
-                                  torch.zeros((P, ref["pos"].shape[1], 3), dtype=torch.float32, device="cuda"),
-                                  torch.zeros((6, P, 9), dtype=torch.float64, device="cuda"))
-    say(f"[autotune] waves per workgroup -> ms: {ms}; chosen {best}")
-    assert best in (1, 2, 4) and ref["ws"].get_tile() == best
-    assert ms[best] == min(ms.values())
+    # network weights read from global memory instead of LDS: the same products in the same order
+    glob = run(torch, L, path, sub, P, tile=4, staging=L.WEIGHTS_GLOBAL)
+    np.testing.assert_array_equal(glob["F"], ref["F"])
+    np.testing.assert_array_equal(glob["E"], ref["E"])
+    np.testing.assert_array_equal(glob["W"], ref["W"])
+    best, st, ms = ref["ws"].autotune(ref["nl"], ref["pos"], ref["boxes"], ref["typ"],
+                                      torch.zeros((6, P), dtype=torch.float64, device="cuda"),
+                                      torch.zeros((P, ref["pos"].shape[1], 3), dtype=torch.float32, device="cuda"),
+                                      torch.zeros((6, P, 9), dtype=torch.float64, device="cuda"))
+    say(f"[autotune] (waves per workgroup, staging) -> ms: {ms}; chosen {best}, {st}")
+    assert len(ms) == 6
+    assert best in (1, 2, 4) and ref["ws"].get_tile() == best and ref["ws"].get_weight_staging() == st
+    assert ms[(best, st)] == min(ms.values())
 
 
 def test_batched_engine_runs(torch, tmpdir_session):
