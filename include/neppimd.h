@@ -146,9 +146,9 @@ enum nep_mlp_mode {
  * stream.  Errors: NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED, NEP_ERR_HIP. */
 int32_t nep_model_set_mlp(nep_model *model, int32_t mode, hipStream_t stream);
 
-/* The network arithmetic in use (*mode, host): NEP_MLP_FP32,
- * NEP_MLP_BF16_MFMA or NEP_MLP_FP32_MFMA, never NEP_MLP_FP32_AUTO.  Errors:
- * NEP_ERR_INVALID_ARG. */
+/* The arithmetic of the per-atom network (Sec. II.C) in use (*mode, host):
+ * NEP_MLP_FP32, NEP_MLP_BF16_MFMA or NEP_MLP_FP32_MFMA, never
+ * NEP_MLP_FP32_AUTO.  Errors: NEP_ERR_INVALID_ARG. */
 int32_t nep_model_mlp(const nep_model *model, int32_t *mode);
 
 /* ------------------------------------------------------------------ */
@@ -345,7 +345,8 @@ int32_t nep_compute_batched(const nep_model *model, nep_nlist *nl, nep_ws *ws, c
 int32_t nep_ws_set_tile(nep_ws *ws, int32_t waves_per_group);
 int32_t nep_ws_get_tile(const nep_ws *ws, int32_t *waves_per_group);
 
-/* Where the FP32 network's weights are read from in nep_compute (vector-
+/* Where the weights of the FP32 per-atom network (Sec. II.C) are read from
+ * in nep_compute (vector-
  * unit network): staged in LDS once per workgroup (default; used only where
  * S H (D + 2) floats fit 60 KiB, else global) or read from global memory.
  * Both evaluate the same products in the same order, so E, F and W are
@@ -605,7 +606,8 @@ typedef struct nep_train_ws nep_train_ws;
  * NEP_ERR_UNSUPPORTED, NEP_ERR_NOMEM. */
 int32_t nep_train_ws_create(const nep_model *model, int32_t P, int32_t N, nep_train_ws **out);
 
-/* Training workspace for a batch of nsys systems (atoms [off[s], off[s+1])
+/* Training workspace (the loss gradient above; the paper fits NEP models by
+ * SNES, Sec. II.C) for a batch of nsys systems (atoms [off[s], off[s+1])
  * form system s, off host [nsys+1], as for nep_nlist_create_batched), P
  * configurations each: one nep_param_grad_batched call then covers nsys
  * independent labelled snapshots.  Errors as nep_train_ws_create. */
