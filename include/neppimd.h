@@ -346,9 +346,9 @@ int32_t nep_ws_set_tile(nep_ws *ws, int32_t waves_per_group);
 int32_t nep_ws_get_tile(const nep_ws *ws, int32_t *waves_per_group);
 
 /* Where the weights of the FP32 per-atom network (Sec. II.C) are read from
- * in nep_compute (vector-
- * unit network): staged in LDS once per workgroup (default; used only where
- * S H (D + 2) floats fit 60 KiB, else global) or read from global memory.
+ * in nep_compute (vector-unit network): staged in LDS once per workgroup
+ * (default; used only where S H (D + 2) floats fit 60 KiB, else global) or
+ * read from global memory.
  * Both evaluate the same products in the same order, so E, F and W are
  * bitwise the same; only the speed differs.  No effect on the matrix-core
  * networks.  Errors: NEP_ERR_INVALID_ARG. */
