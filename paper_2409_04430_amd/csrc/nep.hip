@@ -389,7 +389,7 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             // the block end reread its last entry, masked off)
             for (int sb = s0; sb < s1; sb += kBatch) {
                 // coefficients through scalar loads, which do not wait on the gathers
-                const cf32p cl = launder(c), shl = launder(shc);
+                const cf32p cl = launder(c);
                 int kq[kBatch];
                 bool in[kBatch];
                 float4 pj[kBatch];
@@ -417,8 +417,9 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                     float fc, T[KA1];
                     cheb_t<KA1>(r, a.rcAinv, fc, T);
                     const float hf = 0.5f * fc;
+                    // bare polynomials: the normalisations c_m are applied to the sums below
                     float Y[kNumSH];
-                    sh_eval(dx * rinv, dy * rinv, dz * rinv, shl, Y);
+                    sh_eval(dx * rinv, dy * rinv, dz * rinv, UnitNorm{}, Y);
 #pragma unroll
                     for (int g = 0; g < NG; ++g) {
                         const int n = n0 + g;
@@ -437,6 +438,8 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
         for (int g = 0; g < NG; ++g) {
             const int n = n0 + g;
             if (n >= NA1) break;
+#pragma unroll
+            for (int m = 0; m < kNumSH; ++m) A[g][m] *= shc[m];   // A_nlm = c_m sum_j g_n p_m
 #pragma unroll
             for (int l = 1; l <= kLmax; ++l) {
                 float s2 = 0.0f;
@@ -602,6 +605,9 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                 Bn[6] += g4 * 6.0f * sxz / shc[6];
                 Bn[7] += g4 * 1.5f * (sxx - syy) / shc[7];
             }
+            // stored as B_nlm c_m, the factor the pair terms need with the bare polynomials
+#pragma unroll
+            for (int m = 0; m < kNumSH; ++m) Bn[m] *= shc[m];
 #pragma unroll
             for (int q4 = 0; q4 < kNumSH / 4; ++q4)
                 o4[q4] = make_float4(Bn[4 * q4], Bn[4 * q4 + 1], Bn[4 * q4 + 2], Bn[4 * q4 + 3]);
@@ -729,7 +735,7 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
                 for (int u = 0; u < kBatchAng; ++u) keep(pq[u]);
 #pragma unroll
                 for (int u = 0; u < kBatchAng; ++u) {
-                const cf32p cij_l = launder(cij), shc_l = launder(shc);
+                const cf32p cij_l = launder(cij);
                 const int j = jq[u];
                 const bool act = aq[u];
                 if (__ballot(act) == 0) continue;
@@ -764,7 +770,8 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
                     }
                 }
                 float sY, gx, gy, gz;
-                adjoint_contract<NA1>(ux, uy, uz, shc_l, Bi, gij, gpij, sY, gx, gy, gz);
+                // B^i is stored as B_nlm c_m: bare polynomials here
+                adjoint_contract<NA1>(ux, uy, uz, UnitNorm{}, Bi, gij, gpij, sY, gx, gy, gz);
                 const float ug = ux * gx + uy * gy + uz * gz;
                 const float px = sY * ux + (gx - ux * ug) * rinv;
                 const float py = sY * uy + (gy - uy * ug) * rinv;

@@ -134,8 +134,16 @@ __device__ __forceinline__ void cheb_fd(float r, float rcinv, float *f, float *f
     }
 }
 
+// Normalisations of 1 for sh_eval / adjoint_contract: the bare polynomials
+// p_m of Y_m = c_m p_m (the multiplications fold away), for sums that apply
+// c_m once after the neighbour loop.
+struct UnitNorm {
+    __device__ constexpr float operator[](int) const { return 1.0f; }
+};
+
 // Real spherical harmonics l = 1..4 (m = -l..l) at unit vector (x, y, z);
-// c holds the normalisations (a generic or constant-space pointer).
+// c holds the normalisations (a generic or constant-space pointer, or
+// UnitNorm for the bare polynomials).
 template <typename CP>
 __device__ __forceinline__ void sh_eval(float x, float y, float z, CP c, float *Y)
 {
