@@ -612,8 +612,9 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             for (int q4 = 0; q4 < kNumSH / 4; ++q4)
                 o4[q4] = make_float4(Bn[4 * q4], Bn[4 * q4 + 1], Bn[4 * q4 + 2], Bn[4 * q4 + 3]);
         }
-        // radial adjoints a_k(t) = sum_n G_n c^{tc t}_nk, [atom][species][bead][12]
-        static_assert(KR1 <= kRadPad, "radial basis exceeds the padded adjoint row");
+        // radial adjoints a_k(t) = sum_n G_n c^{tc t}_nk, [atom][species][bead][12],
+        // and in slot KR1 their sum over k >= 1 (the pair terms need it)
+        static_assert(KR1 < kRadPad, "radial basis exceeds the padded adjoint row");
         for (int t = 0; t < S; ++t) {
             const float *c = prm + a.oR + (tc * S + t) * NR1 * KR1;
             float acc[kRadPad];
@@ -625,6 +626,8 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                     for (int n = 0; n < NR1; ++n) acc[k] += G[n] * c[n * KR1 + k];
                 }
             }
+#pragma unroll
+            for (int k = 1; k < KR1; ++k) acc[KR1] += acc[k];
             float4 *ao = reinterpret_cast<float4 *>(a.arad + (((size_t)i * S + t) * P + b) * kRadPad);
 #pragma unroll
             for (int q4 = 0; q4 < kRadPad / 4; ++q4)
@@ -837,10 +840,10 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
 #pragma unroll
             for (int q4 = 0; q4 < kRadPad / 4; ++q4) {
                 const float4 v = p[q4];
-                if (4 * q4 < KR1) out[4 * q4] = v.x;
-                if (4 * q4 + 1 < KR1) out[4 * q4 + 1] = v.y;
-                if (4 * q4 + 2 < KR1) out[4 * q4 + 2] = v.z;
-                if (4 * q4 + 3 < KR1) out[4 * q4 + 3] = v.w;
+                if (4 * q4 <= KR1) out[4 * q4] = v.x;
+                if (4 * q4 + 1 <= KR1) out[4 * q4 + 1] = v.y;
+                if (4 * q4 + 2 <= KR1) out[4 * q4 + 2] = v.z;
+                if (4 * q4 + 3 <= KR1) out[4 * q4 + 3] = v.w;
             }
         };
         const int32_t *uR = a.uniR + (size_t)i * a.capR;
@@ -848,13 +851,13 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
         for (int t = 0; t < S; ++t) {
             int s0, s1;
             block_range(a.uendR, i, t, s0, s1);
-            float ai[KR1];
+            float ai[KR1 + 1];   // a_k and, last, their sum over k >= 1
             load_a(i, t, ai);
             for (int sb = s0; sb < s1; sb += kBatch) {
                 int jj[kBatch];
                 bool in[kBatch];
                 float4 pj[kBatch];
-                float aj[kBatch][KR1];
+                float aj[kBatch][KR1 + 1];
                 // unconditional loads, as in the descriptor's radial batches
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
@@ -870,6 +873,7 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
                 }
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) keep(pj[u]);
+                float bx = 0.0f, by = 0.0f, bz = 0.0f;   // the batch's force, FP32, into the FP64 sum once
 #pragma unroll
                 for (int u = 0; u < kBatch; ++u) {
                     if (in[u]) {
@@ -878,26 +882,28 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
                         const float r2 = dx * dx + dy * dy + dz * dz;
                         const float rinv = __builtin_amdgcn_rsqf(r2);
                         const float r = r2 * rinv;
-                        // sum_k A_k f_k' = (dx/dr f_c sum A_k T_k' + f_c' sum A_k (T_k + 1)) / 2
+                        // sum_k A_k f_k' = (dx/dr f_c sum A_k T_k' + f_c' sum A_k (T_k + 1)) / 2,
+                        // sum_{k>0} A_k (T_k + 1) = sum_{k>0} A_k T_k + (the stored sums of a_k)
                         float fc, fcp, dxdr, T[KR1], Tp[KR1];
                         cheb_td<KR1>(r, a.rcRinv, fc, fcp, dxdr, T, Tp);
-                        float s1 = 2.0f * (ai[0] + aj[u][0]), s2 = 0.0f;
+                        float s1 = 2.0f * (ai[0] + aj[u][0]) + (ai[KR1] + aj[u][KR1]), s2 = 0.0f;
 #pragma unroll
                         for (int q2 = 1; q2 < KR1; ++q2) {
                             const float A = ai[q2] + aj[u][q2];
-                            s1 = fmaf(A, T[q2] + 1.0f, s1);
+                            s1 = fmaf(A, T[q2], s1);
                             s2 = fmaf(A, Tp[q2], s2);
                         }
                         const float sc = 0.5f * fmaf(dxdr * fc, s2, fcp * s1);
                         const float w = sc * rinv;
                         const float qx = w * dx, qy = w * dy, qz = w * dz;
-                        Fx += qx; Fy += qy; Fz += qz;
+                        bx += qx; by += qy; bz += qz;
                         const float hx = -0.5f * dx, hy = -0.5f * dy, hz = -0.5f * dz;
                         Wf[0] = fmaf(hx, qx, Wf[0]); Wf[1] = fmaf(hx, qy, Wf[1]); Wf[2] = fmaf(hx, qz, Wf[2]);
                         Wf[3] = fmaf(hy, qx, Wf[3]); Wf[4] = fmaf(hy, qy, Wf[4]); Wf[5] = fmaf(hy, qz, Wf[5]);
                         Wf[6] = fmaf(hz, qx, Wf[6]); Wf[7] = fmaf(hz, qy, Wf[7]); Wf[8] = fmaf(hz, qz, Wf[8]);
                     }
                 }
+                Fx += (double)bx; Fy += (double)by; Fz += (double)bz;
             }
         }
 

@@ -26,7 +26,7 @@ struct NepArgs {
     float4 *pairbuf;     // [N][capA][P] dU_j/dr_ji at the receiving atom's angular slot of j
     // workspace
     float *B;            // [N][P][NA1*24]
-    float *arad;         // [N][S][P][kRadPad] radial adjoints, 9 used
+    float *arad;         // [N][S][P][kRadPad] radial adjoints a_k (k < 9) and, in slot 9, their sum over k >= 1
     float *Fang;         // [N][P][3]
     double *partE, *partWa, *partWr;   // [P][blocks], [P][9][blocks]
     uint32_t *flags;
