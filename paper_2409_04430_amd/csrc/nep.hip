@@ -7,8 +7,9 @@
 //                 over real orthonormal spherical harmonics, q_nl = sum_m A_nlm^2
 //                 (equal to the Legendre double sum by the addition theorem),
 //                 the optional (2,2,2) four-body invariant, the tanh network,
-//                 and the adjoints: B_nlm = dU_i/dA_nlm and the radial
-//                 a_k(t) = sum_n dU_i/dq_n c^{ti t}_nk;
+//                 and the adjoints: B_nlm = dU_i/dA_nlm (stored times the
+//                 harmonic's normalisation c_m) and the radial
+//                 a_k(t) = sum_n dU_i/dq_n c^{ti t}_nk (with their sum over k > 0);
 //   k_force_ang   angular pair terms d_ij = dU_i/dr_ij from the atom's own
 //                 adjoints, kept per (bead, atom, candidate slot);
 //   k_force_rad   radial pair terms (a^i_k(tj) + a^j_k(ti)) f'_k(r) u, the
@@ -232,10 +233,11 @@ template <int D>
 constexpr int mf_lds_floats() { return 64 * ((D <= 32 ? 32 : 64) + 4); }
 
 // Network arithmetic of k_descriptor: FP32 vector units with the weights
-// read from global memory or staged in LDS, or BF16 matrix cores (student
-// weights).  (FP32 operands on the matrix cores measured slower than the
-// LDS-staged vector form: two wavefronts per SIMD cannot hide the chains of
-// dependent 16 x 16 x 4 FP32 tiles.)
+// read from global memory or staged in LDS; BF16 matrix cores with BF16
+// weights (the student); or BF16 matrix cores with the FP32 weights as
+// three exact BF16 terms (FP32 accuracy).  (FP32 operands on the matrix
+// cores, 16 x 16 x 4 FP32 tiles, measured slower than the LDS-staged vector
+// form: two wavefronts per SIMD cannot hide their dependent chains.)
 constexpr int kNetGlobal = 0, kNetLds = 1, kNetBf16 = 2, kNetMf32 = 3;
 constexpr int kNetRowRegs = 40;   // longest descriptor whose weight rows the LDS network holds in registers
 
