@@ -586,6 +586,9 @@ extern "C" int32_t nep_nlist_create_batched(const nep_model *m, int32_t P, int32
     if (e == hipSuccess) e = dalloc(&nl->grid, 16 + kDevSysWords * (size_t)nsys);
     if (e == hipSuccess) e = dalloc(&nl->status, 8);
     if (e == hipSuccess) e = hipMemset(nl->status, 0, 8 * sizeof(uint32_t));
+    // pair terms start at zero: a slot that a step with truncated rows leaves
+    // unwritten then holds a finite stale value, never uninitialised bits
+    if (e == hipSuccess && PN) e = hipMemset(nl->pairbuf, 0, sizeof(float) * 4 * PN * capA);
     if (e == hipSuccess) e = hipMemset(nl->grid, 0, (16 + kDevSysWords * (size_t)nsys) * sizeof(uint32_t));
     if (e == hipSuccess && Nn) e = hipMemset(nl->offR, 0, sizeof(int32_t) * Nn * (kMaxSpecies + 1));
     if (e == hipSuccess && Nn) e = hipMemset(nl->offA, 0, sizeof(int32_t) * Nn * (kMaxSpecies + 1));

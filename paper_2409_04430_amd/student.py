@@ -310,6 +310,9 @@ class StudentPimd:
     def _restore(self, tok):
         self.on_student, self.fallback_step, n = tok
         del self.history[n:]
+        # flags the teacher raised in the discarded window (forces on
+        # truncated rows) do not outlive it; the replay raises its own
+        self.tws.poll(clear=True)
 
     @property
     def step_no(self):
