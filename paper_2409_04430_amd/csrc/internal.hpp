@@ -43,7 +43,7 @@ struct nep_model {
     std::vector<float> host;   // packed parameters (FP32)
     float *dev = nullptr;      // device copy
     int device = 0;
-    int mlp = 0;               // NEP_MLP_FP32 or NEP_MLP_BF16_MFMA
+    int mlp = 0;               // NEP_MLP_FP32, NEP_MLP_BF16_MFMA or NEP_MLP_FP32_MFMA (AUTO resolved)
     uint16_t *w0b = nullptr;   // W0 as matrix-core operand fragments (nep::MlpFrag layout), BF16 terms
     size_t w0b_len = 0;        // elements allocated at w0b
     bool cutoffs_only = false; // a cutoff descriptor for neighbour lists (no weights; owned by another handle)

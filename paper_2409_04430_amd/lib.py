@@ -432,7 +432,7 @@ def fitted_neighbor_list(model: "Model", pos, box, types, cap_radial: int = 96, 
 
 
 class Workspace:
-    """nep_ws_create / nep_compute / nep_poll_flags."""
+    """nep_ws_create / nep_compute / nep_poll_flags, tile shape and weight staging, autotuner."""
 
     def __init__(self, model: Model, P: int, N: int, offsets=None):
         self._h = _vp()
