@@ -106,11 +106,20 @@ typedef struct nep_hparams {
  * to the current device.  The file holds the hyperparameters, the radial
  * and angular Chebyshev coefficients c[ti][tj][n][k], one scale per
  * descriptor, per-species network weights W0[H][D], b0[H], w1[H] and the
- * shared output bias b1.  Supported shapes: l_max = 4, basis sizes 8,
- * (n_max_radial, n_max_angular, four_body) in {(4,4,0), (4,4,1), (6,4,0),
- * (8,6,0), (8,8,1)}, rc_angular <= rc_radial.  Errors: NEP_ERR_PARAMS_FILE,
- * NEP_ERR_UNSUPPORTED, NEP_ERR_HIP, NEP_ERR_NOMEM.  *out is owned by the
- * caller and released with nep_model_destroy. */
+ * shared output bias b1.  Supported shapes: l_max 1..4, basis sizes 1..8,
+ * n_max_radial and n_max_angular 0..8, four_body (needs l_max >= 2),
+ * 1..4 species, 1..512 hidden units, 0 < rc_angular <= rc_radial.  The
+ * kernels are compiled for (n_max_radial, n_max_angular, four_body) in
+ * {(4,4,0), (6,4,0), (4,4,1), (8,6,0), (8,8,1)} with basis sizes 8 and
+ * l_max = 4; a model of another shape runs on the first of these that
+ * contains it (listed by descriptor length), its parameters placed in that
+ * layout with zeros elsewhere, so every extra term is an exact zero and the
+ * results are those of the model itself, at the cost of the larger shape.
+ * nep_model_info reports the file's shape; the parameters of such an
+ * embedded model are not exposed (nep_model_params) or trainable
+ * (nep_train_ws_create), both NEP_ERR_UNSUPPORTED.  Errors:
+ * NEP_ERR_PARAMS_FILE, NEP_ERR_UNSUPPORTED, NEP_ERR_HIP, NEP_ERR_NOMEM.
+ * *out is owned by the caller and released with nep_model_destroy. */
 int32_t nep_load_params(const char *path, nep_model **out);
 
 /* Copy the hyperparameters of a model into *out (host). */
@@ -595,13 +604,15 @@ typedef struct nep_param_offsets {
 
 /* Device parameter array of a model (owned by the model; the NEP kernels
  * read it, so writing it changes the model), its length and block offsets.
- * Errors: NEP_ERR_INVALID_ARG. */
+ * Errors: NEP_ERR_INVALID_ARG, NEP_ERR_UNSUPPORTED (a model embedded in a
+ * larger kernel shape, nep_load_params). */
 int32_t nep_model_params(nep_model *model, float **params, int32_t *count, nep_param_offsets *offsets);
 
 typedef struct nep_train_ws nep_train_ws;
 
 /* Training workspace for P configurations of N atoms (the beads of a
- * neighbour handle of one system).  Models with the four-body term are not
+ * neighbour handle of one system).  Models with the four-body term, and
+ * models embedded in a larger kernel shape (nep_load_params), are not
  * trainable (NEP_ERR_UNSUPPORTED).  Errors: NEP_ERR_INVALID_ARG,
  * NEP_ERR_UNSUPPORTED, NEP_ERR_NOMEM. */
 int32_t nep_train_ws_create(const nep_model *model, int32_t P, int32_t N, nep_train_ws **out);

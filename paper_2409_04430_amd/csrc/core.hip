@@ -240,16 +240,93 @@ struct TokReader {
     }
 };
 
+// Kernel shapes compiled into the library, (n_max_radial, n_max_angular,
+// four_body) with basis sizes 8 and l_max = 4, in order of descriptor length.
+// A model of another shape runs on the first that contains it: its
+// Chebyshev coefficients and network columns sit in the kernel shape's
+// layout with zeros everywhere else, so every extra basis function, radial
+// function, angular order or four-body entry contributes an exact zero (a
+// zero coefficient times a finite basis value; a zero descriptor scale and
+// a zero weight column for the extra descriptors, whose adjoints are then
+// zero too).
+static const int kKernelShapes[][3] = {{4, 4, 0}, {6, 4, 0}, {4, 4, 1}, {8, 6, 0}, {8, 8, 1}};
+
+static int kernel_shape(const nep_hparams &h)
+{
+    for (int k = 0; k < (int)(sizeof kKernelShapes / sizeof kKernelShapes[0]); ++k) {
+        const int *s = kKernelShapes[k];
+        if (h.n_max_radial <= s[0] && h.n_max_angular <= s[1] && h.four_body <= s[2]) return k;
+    }
+    return -1;
+}
+
 static bool shape_supported(const nep_hparams &h)
 {
-    if (h.l_max != kLmax || h.basis_radial != 8 || h.basis_angular != 8) return false;
+    if (h.l_max < 1 || h.l_max > kLmax) return false;
+    if (h.basis_radial < 1 || h.basis_radial > 8 || h.basis_angular < 1 || h.basis_angular > 8) return false;
+    if (h.n_max_radial < 0 || h.n_max_angular < 0) return false;
+    if (h.four_body != 0 && h.four_body != 1) return false;
+    if (h.four_body && h.l_max < 2) return false;   // the four-body invariant couples l = 2 sums
     if (h.n_species < 1 || h.n_species > kMaxSpecies) return false;
     if (h.hidden < 1 || h.hidden > 512) return false;
     if (!(h.rc_angular > 0.0) || !(h.rc_radial >= h.rc_angular)) return false;
-    const int ok[][3] = {{4, 4, 0}, {4, 4, 1}, {6, 4, 0}, {8, 6, 0}, {8, 8, 1}};
-    for (auto &s : ok)
-        if (h.n_max_radial == s[0] && h.n_max_angular == s[1] && h.four_body == s[2]) return true;
-    return false;
+    return kernel_shape(h) >= 0;
+}
+
+static int descriptor_dim(const nep_hparams &h)
+{
+    return (h.n_max_radial + 1) + h.l_max * (h.n_max_angular + 1) + (h.four_body ? h.n_max_angular + 1 : 0);
+}
+
+// Offsets of the packed parameter blocks of a shape (the spherical-harmonic
+// normalisations last).
+static ParamLayout param_layout(const nep_hparams &h)
+{
+    const int S = h.n_species, H = h.hidden, D = descriptor_dim(h);
+    ParamLayout o;
+    int p = 0;
+    o.cR = p; p += S * S * (h.n_max_radial + 1) * (h.basis_radial + 1);
+    o.cA = p; p += S * S * (h.n_max_angular + 1) * (h.basis_angular + 1);
+    o.qs = p; p += D;
+    o.W0 = p; p += S * H * D;
+    o.b0 = p; p += S * H;
+    o.w1 = p; p += S * H;
+    o.b1 = p; p += 1;
+    o.sh = p; p += kNumSH;
+    o.total = p;
+    return o;
+}
+
+// Copy the parameters va of shape a (layout oa) into the zero-filled vb of
+// the containing shape b (layout ob).  Descriptor order in both: radial n,
+// then angular (l - 1)(n_max_angular + 1) + n, then four-body n.
+static void embed_params(const nep_hparams &a, const ParamLayout &oa, const std::vector<float> &va,
+                         const nep_hparams &b, const ParamLayout &ob, std::vector<float> &vb)
+{
+    const int S = a.n_species, H = a.hidden, Da = descriptor_dim(a), Db = descriptor_dim(b);
+    const int aR = a.n_max_radial + 1, aA = a.n_max_angular + 1, bR = b.n_max_radial + 1, bA = b.n_max_angular + 1;
+    vb.assign((size_t)ob.total, 0.0f);
+    auto coef = [&](int offa, int offb, int na, int nb, int ka, int kb) {
+        for (int tt = 0; tt < S * S; ++tt)
+            for (int n = 0; n < na; ++n)
+                for (int k = 0; k < ka; ++k) vb[offb + (tt * nb + n) * kb + k] = va[offa + (tt * na + n) * ka + k];
+    };
+    coef(oa.cR, ob.cR, aR, bR, a.basis_radial + 1, b.basis_radial + 1);
+    coef(oa.cA, ob.cA, aA, bA, a.basis_angular + 1, b.basis_angular + 1);
+    std::vector<int> col((size_t)Da);
+    for (int n = 0; n < aR; ++n) col[n] = n;
+    for (int l = 1; l <= a.l_max; ++l)
+        for (int n = 0; n < aA; ++n) col[aR + (l - 1) * aA + n] = bR + (l - 1) * bA + n;
+    if (a.four_body)
+        for (int n = 0; n < aA; ++n) col[aR + a.l_max * aA + n] = bR + b.l_max * bA + n;
+    for (int v = 0; v < Da; ++v) vb[ob.qs + col[v]] = va[oa.qs + v];
+    for (int sm = 0; sm < S * H; ++sm)
+        for (int v = 0; v < Da; ++v) vb[ob.W0 + sm * Db + col[v]] = va[oa.W0 + sm * Da + v];
+    for (int x = 0; x < S * H; ++x) {
+        vb[ob.b0 + x] = va[oa.b0 + x];
+        vb[ob.w1 + x] = va[oa.w1 + x];
+    }
+    vb[ob.b1] = va[oa.b1];
 }
 
 // Orthonormal real spherical harmonics l = 1..4 as constant x polynomial;
@@ -348,41 +425,51 @@ extern "C" int32_t nep_load_params(const char *path, nep_model **out)
                     h.basis_angular, h.l_max, h.four_body, h.hidden, h.rc_radial, h.rc_angular);
     const int S = h.n_species, NR1 = h.n_max_radial + 1, NA1 = h.n_max_angular + 1;
     const int KR1 = h.basis_radial + 1, KA1 = h.basis_angular + 1, H = h.hidden;
-    h.dim = NR1 + h.l_max * NA1 + (h.four_body ? NA1 : 0);
+    h.dim = descriptor_dim(h);
     const int D = h.dim;
+    // the kernel shape that runs this model (its own when compiled)
+    const int *ks = kKernelShapes[kernel_shape(h)];
+    nep_hparams hk = h;
+    hk.n_max_radial = ks[0];
+    hk.n_max_angular = ks[1];
+    hk.four_body = ks[2];
+    hk.basis_radial = hk.basis_angular = 8;
+    hk.l_max = kLmax;
+    hk.dim = descriptor_dim(hk);
+    const bool embedded = hk.n_max_radial != h.n_max_radial || hk.n_max_angular != h.n_max_angular ||
+                          hk.four_body != h.four_body || hk.basis_radial != h.basis_radial ||
+                          hk.basis_angular != h.basis_angular || hk.l_max != h.l_max;
 
     nep_model *m = new (std::nothrow) nep_model;
     if (!m) return fail(NEP_ERR_NOMEM, "host allocation failed");
-    m->hp = h;
-    ParamLayout &o = m->off;
-    int p = 0;
-    o.cR = p; p += S * S * NR1 * KR1;
-    o.cA = p; p += S * S * NA1 * KA1;
-    o.qs = p; p += D;
-    o.W0 = p; p += S * H * D;
-    o.b0 = p; p += S * H;
-    o.w1 = p; p += S * H;
-    o.b1 = p; p += 1;
-    o.sh = p; p += kNumSH;
-    o.total = p;
-    m->host.assign(p, 0.0f);
+    m->hp = hk;
+    m->own = h;
+    m->embedded = embedded;
+    const ParamLayout oo = param_layout(h);
+    std::vector<float> vo((size_t)oo.total, 0.0f);
     auto rd = [&](int off, int n) {
-        for (int i = 0; i < n; ++i) m->host[off + i] = (float)r.getd();
+        for (int i = 0; i < n; ++i) vo[off + i] = (float)r.getd();
     };
-    r.expect("c_radial"); rd(o.cR, S * S * NR1 * KR1);
-    r.expect("c_angular"); rd(o.cA, S * S * NA1 * KA1);
-    r.expect("q_scale"); rd(o.qs, D);
+    r.expect("c_radial"); rd(oo.cR, S * S * NR1 * KR1);
+    r.expect("c_angular"); rd(oo.cA, S * S * NA1 * KA1);
+    r.expect("q_scale"); rd(oo.qs, D);
     r.expect("ann");
     for (int s = 0; s < S; ++s) {
-        rd(o.W0 + s * H * D, H * D);
-        rd(o.b0 + s * H, H);
-        rd(o.w1 + s * H, H);
+        rd(oo.W0 + s * H * D, H * D);
+        rd(oo.b0 + s * H, H);
+        rd(oo.w1 + s * H, H);
     }
-    r.expect("b1"); rd(o.b1, 1);
+    r.expect("b1"); rd(oo.b1, 1);
     if (!r.ok) {
         delete m;
         return fail(NEP_ERR_PARAMS_FILE, "malformed or truncated parameter blocks in '%s'", path);
     }
+    m->off = param_layout(hk);
+    const ParamLayout &o = m->off;
+    if (embedded)
+        embed_params(h, oo, vo, hk, o, m->host);
+    else
+        m->host.swap(vo);
     double shc[kNumSH];
     sh_norms(shc);
     for (int i = 0; i < kNumSH; ++i) m->host[o.sh + i] = (float)shc[i];
@@ -404,7 +491,7 @@ extern "C" int32_t nep_load_params(const char *path, nep_model **out)
 extern "C" int32_t nep_model_info(const nep_model *m, nep_hparams *out)
 {
     if (!m || !out) return fail(NEP_ERR_INVALID_ARG, "nep_model_info: null argument");
-    *out = m->hp;
+    *out = m->embedded ? m->own : m->hp;
     return NEP_OK;
 }
 

@@ -38,7 +38,9 @@ struct ParamLayout {
 }  // namespace nep
 
 struct nep_model {
-    nep_hparams hp;
+    nep_hparams hp;            // the kernel shape: the model's own, or the compiled shape it is embedded in
+    nep_hparams own;           // the shape of the model file (equal to hp unless embedded)
+    bool embedded = false;     // parameters zero-padded into the larger kernel shape hp
     nep::ParamLayout off;
     std::vector<float> host;   // packed parameters (FP32)
     float *dev = nullptr;      // device copy

@@ -551,6 +551,8 @@ extern "C" int32_t nep_train_ws_create_batched(const nep_model *m, int32_t P, in
 {
     if (!m || !out) return fail(NEP_ERR_INVALID_ARG, "nep_train_ws_create: null argument");
     if (m->cutoffs_only) return fail(NEP_ERR_INVALID_ARG, "nep_train_ws_create: a list cutoff descriptor has no network");
+    if (m->embedded)
+        return fail(NEP_ERR_UNSUPPORTED, "nep_train_ws_create: a model embedded in a larger kernel shape is not trainable");
     const int32_t rc0 = check_offsets(nsys, off, "nep_train_ws_create");
     if (rc0 != NEP_OK) return rc0;
     const int32_t N = off[nsys];
@@ -684,6 +686,9 @@ extern "C" int32_t nep_model_params(nep_model *m, float **params, int32_t *count
 {
     if (!m || !params || !count) return fail(NEP_ERR_INVALID_ARG, "nep_model_params: null argument");
     if (m->cutoffs_only) return fail(NEP_ERR_INVALID_ARG, "nep_model_params: a list cutoff descriptor has no network");
+    if (m->embedded)
+        return fail(NEP_ERR_UNSUPPORTED, "nep_model_params: the parameters of a model embedded in a larger kernel "
+                                         "shape are not exposed");
     *params = m->dev;
     *count = m->off.total;
     if (off) {

@@ -54,13 +54,18 @@ def test_model_file_errors(L, tmp_path):
         L.Model(str(bad))
     assert e.value.code == 2
     from paper_2409_04430_amd import inputs as I
-    h = I.NepHyper(1, 5.0, 4.0, 5, 3, 8, 8, 4, False, 10)       # (5,3) is not a built shape
-    m = I.random_model(h, np.random.default_rng(0), 0.06)
-    p = tmp_path / "unsup.nep"
-    I.write_model(str(p), m)
-    with pytest.raises(L.NepError) as e:
-        L.Model(str(p))
-    assert e.value.code == 3
+    # shapes outside every compiled kernel shape or outside the model form
+    for k, h in enumerate([I.NepHyper(1, 5.0, 4.0, 9, 3, 8, 8, 4, False, 10),    # n_max_radial > 8
+                           I.NepHyper(1, 5.0, 4.0, 4, 4, 9, 8, 4, False, 10),    # basis > 8
+                           I.NepHyper(1, 5.0, 4.0, 4, 4, 8, 0, 4, False, 10),    # basis < 1
+                           I.NepHyper(1, 5.0, 4.0, 4, 4, 8, 8, 5, False, 10),    # l_max > 4
+                           I.NepHyper(1, 5.0, 4.0, 4, 4, 8, 8, 1, True, 10),     # four-body without l = 2
+                           I.NepHyper(1, 4.0, 5.0, 4, 4, 8, 8, 4, False, 10)]):  # rc_angular > rc_radial
+        p = tmp_path / f"unsup{k}.nep"
+        I.write_model(str(p), I.random_model(h, np.random.default_rng(0), 0.06))
+        with pytest.raises(L.NepError) as e:
+            L.Model(str(p))
+        assert e.value.code == 3, k
     # truncated weights
     good = tmp_path / "good.nep"
     I.write_model(str(good), I.random_model(I.NepHyper(1, 5.0, 4.0, 4, 4, 8, 8, 4, False, 10),

@@ -208,6 +208,46 @@ def test_nep_parity_four_body(torch, L, orc, tmpdir_session):
     check_nep(dict(E=ref["E"], F=ref["F"], W=ref["W"], U=ref["U"], Wat=ref["Wat"]), got, range(3), pos.shape[1])
 
 
+@pytest.mark.parametrize("shape", [
+    # (species, n_max radial/angular, basis radial/angular, l_max, four-body, hidden), none of them a
+    # compiled kernel shape: each runs embedded in the first compiled shape that contains it
+    (2, 5, 3, 6, 5, 3, False, 12),
+    (1, 7, 7, 8, 8, 4, True, 16),
+    (2, 2, 1, 4, 3, 2, True, 10),
+    (1, 0, 0, 1, 1, 1, False, 6),
+])
+def test_nep_parity_embedded_shapes(torch, L, orc, tmpdir_session, shape):
+    S, nR, nA, kR, kA, lmax, four, H = shape
+    say(f"[nep parity] embedded shape {shape} on FCC, P=2")
+    h = I.NepHyper(S, 5.0, 4.0, nR, nA, kR, kA, lmax, four, H)
+    m = I.random_model(h, np.random.default_rng(7), 0.06, 30.0)
+    path = write_model(tmpdir_session, "emb_" + "_".join(str(int(x)) for x in shape), m)
+    pos, types, box = beads_of("fcc108", 2, extra_sigma=0.08, seed=5)
+    if S == 2:
+        types = (np.arange(len(types)) % 2).astype(np.asarray(types).dtype)
+    capR, capA = oracle_caps(orc, pos, box, 5.0, 4.0)
+    got = gpu_nep(torch, L, path, pos, types, box, capR, capA)
+    model = got["model"]
+    assert (model.n_max_radial, model.n_max_angular, model.basis_radial, model.basis_angular, model.l_max,
+            model.four_body, model.dim) == (nR, nA, kR, kA, lmax, int(four), h.dim)
+    with pytest.raises(L.NepError) as e:
+        model.params()
+    assert e.value.code == 3
+    ref = oracle_beads(orc, path, pos, types, box, range(2))
+    ref = dict(E=ref["E"], F=ref["F"], W=ref["W"], U=ref["U"], Wat=ref["Wat"])
+    check_nep(ref, got, range(2), pos.shape[1])
+    # the same model with the network on the matrix cores at FP32 accuracy
+    assert model.set_mlp(L.MLP_FP32_MFMA) == L.MLP_FP32_MFMA
+    tpos, ttyp, E, F, W, Ea, Wa = got["tensors"]
+    got["ws"].compute(got["nl"], tpos, box, ttyp, E, F, W, Ea, Wa)
+    torch.cuda.synchronize()
+    assert got["ws"].poll() == 0
+    P = pos.shape[0]
+    mf = dict(E=E.cpu().numpy(), F=F.cpu().numpy().astype(np.float64), W=W.cpu().numpy().reshape(P, 3, 3),
+              U=Ea.cpu().numpy(), Wat=Wa.cpu().numpy().reshape(P, pos.shape[1], 3, 3))
+    check_nep(ref, mf, range(2), pos.shape[1])
+
+
 def test_nep_parity_water_boxes(torch, L, orc, tmpdir_session):
     """Two water boxes: 64 molecules (L = 12.4 A, two cells per edge) and
     512 molecules; ragged atom counts (192, 1536)."""
