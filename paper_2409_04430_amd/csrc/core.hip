@@ -768,6 +768,7 @@ static int32_t set_tiles(nep_ws *w, int wpb)
     }
     st[w->nsys] = (int32_t)t0.size();
     if ((int)t0.size() > std::max(w->nblk_cap, 1)) return fail(NEP_ERR_INVALID_ARG, "tile table overflow");
+    if (w->B && t0.size() * (size_t)wpb > w->B_waves) return fail(NEP_ERR_INVALID_ARG, "adjoint rows overflow");
     NEP_HIP(hipDeviceSynchronize());
     if (!t0.empty()) {
         NEP_HIP(hipMemcpy(w->tile_atom0, t0.data(), sizeof(int32_t) * t0.size(), hipMemcpyHostToDevice));
@@ -839,7 +840,12 @@ extern "C" int32_t nep_ws_create_batched(const nep_model *m, int32_t P, int32_t 
     if (e == hipSuccess) e = dalloc(&w->tile_sys, nb);
     if (e == hipSuccess) e = dalloc(&w->sys_tile0, (size_t)nsys + 1);
     if (e == hipSuccess && set_tiles(w, 4) != NEP_OK) e = hipErrorUnknown;
-    if (e == hipSuccess) e = dalloc(&w->B, PN * w->NA1 * kNumSH);
+    // adjoint rows, one per lane of a launch (wavefront-interleaved): with
+    // wpb wavefronts per workgroup a system takes at most wpb - 1 more
+    // wavefronts than its count at one per workgroup
+    w->B_waves = (size_t)cap + (size_t)3 * nsys;
+    if (e == hipSuccess) e = dalloc(&w->B, w->B_waves * 64 * w->NA1 * kNumSH);
+    if (e == hipSuccess) e = hipMemset(w->B, 0, sizeof(float) * w->B_waves * 64 * w->NA1 * kNumSH);
     if (e == hipSuccess) e = dalloc(&w->arad, PN * w->S * 12);
     if (e == hipSuccess) e = dalloc(&w->partE, (size_t)std::max(P, 1) * nb);
     if (e == hipSuccess) e = dalloc(&w->partW, (size_t)2 * std::max(P, 1) * nb * 9);

@@ -177,7 +177,9 @@ struct nep_ws {
     int nblk_cap = 0;               // tile capacity (the count for one wavefront per workgroup)
     int32_t *tile_atom0 = nullptr, *tile_atom1 = nullptr, *tile_sys = nullptr;   // [nblk_cap]
     int32_t *sys_tile0 = nullptr;   // [nsys + 1]
-    float *B = nullptr;        // [N][P][NA1*24] angular adjoints dU_i/dA_nlm times c_m (the harmonic's normalisation)
+    float *B = nullptr;        // angular adjoints dU_i/dA_nlm times c_m (the harmonic's normalisation), one
+                               // row of NA1*24 per lane of a launch, wavefront-interleaved (adj_rows)
+    size_t B_waves = 0;        // wavefronts whose rows B holds
     float *arad = nullptr;     // [N][S][P][12] radial adjoints sum_n dU_i/dq_n c_nk (9 used)
     double *partE = nullptr;   // [P][nblk] per-workgroup partial energies (bead-major)
     double *partW = nullptr;   // angular pass [P][9][nblk], then radial pass [P][9][nblk] (room for nblk_cap)

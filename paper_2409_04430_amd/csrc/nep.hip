@@ -291,7 +291,9 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
         float q[D];
 #pragma unroll
         for (int v = 0; v < D; ++v) q[v] = 0.0f;
-        float *Bo = a.B + ((size_t)i * P + b) * (NA1 * kNumSH);
+        // the wavefront's adjoint rows, interleaved (adj_rows): each float4
+        // store or load of the wavefront covers 1 KiB contiguously
+        const __amdgpu_buffer_rsrc_t Bo = adj_rows(a.B, NA1);
         // A stays in registers through the network for small angular sets;
         // otherwise it is parked in the atom's adjoint row and read back
         constexpr bool PARK = MF || NA1 > 5;
@@ -461,11 +463,11 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                 q[NR1 + kLmax * NA1 + n] = a.kappa4 * tr3;
             }
             if constexpr (PARK) {
-                // park A in this atom's adjoint row (overwritten with B below)
-                float4 *o4 = reinterpret_cast<float4 *>(Bo + n * kNumSH);
+                // park A in this lane's adjoint row (overwritten with B below)
 #pragma unroll
                 for (int q4 = 0; q4 < kNumSH / 4; ++q4)
-                    o4[q4] = make_float4(A[g][4 * q4], A[g][4 * q4 + 1], A[g][4 * q4 + 2], A[g][4 * q4 + 3]);
+                    adj_store(Bo, n * (kNumSH / 4) + q4,
+                              make_float4(A[g][4 * q4], A[g][4 * q4 + 1], A[g][4 * q4 + 2], A[g][4 * q4 + 3]));
             } else {
 #pragma unroll
                 for (int m = 0; m < kNumSH; ++m) Ar[PARK ? 0 : n][m] = A[g][m];
@@ -574,11 +576,10 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
 #pragma unroll
         for (int n = 0; n < NA1; ++n) {
             float An[kNumSH];
-            float4 *o4 = reinterpret_cast<float4 *>(Bo + n * kNumSH);
             if constexpr (PARK) {
 #pragma unroll
                 for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
-                    const float4 v4 = o4[q4];
+                    const float4 v4 = adj_load(Bo, n * (kNumSH / 4) + q4);
                     An[4 * q4] = v4.x; An[4 * q4 + 1] = v4.y; An[4 * q4 + 2] = v4.z; An[4 * q4 + 3] = v4.w;
                 }
             } else {
@@ -612,7 +613,7 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
             for (int m = 0; m < kNumSH; ++m) Bn[m] *= shc[m];
 #pragma unroll
             for (int q4 = 0; q4 < kNumSH / 4; ++q4)
-                o4[q4] = make_float4(Bn[4 * q4], Bn[4 * q4 + 1], Bn[4 * q4 + 2], Bn[4 * q4 + 3]);
+                adj_store(Bo, n * (kNumSH / 4) + q4, make_float4(Bn[4 * q4], Bn[4 * q4 + 1], Bn[4 * q4 + 2], Bn[4 * q4 + 3]));
         }
         // radial adjoints a_k(t) = sum_n G_n c^{tc t}_nk, [atom][species][bead][12],
         // and in slot KR1 their sum over k >= 1 (the pair terms need it)
@@ -694,13 +695,13 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
         const bool mine = valid && tok && ti == tc;
         todo &= ~__ballot(mine);
 
-        const float4 *bi4 = reinterpret_cast<const float4 *>(a.B + ((size_t)i * P + b) * (NA1 * kNumSH));
+        const __amdgpu_buffer_rsrc_t bi4 = adj_rows(a.B, NA1);
         float Bi[NA1][kNumSH];
 #pragma unroll
         for (int n = 0; n < NA1; ++n)
 #pragma unroll
             for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
-                const float4 v4 = bi4[n * (kNumSH / 4) + q4];
+                const float4 v4 = adj_load(bi4, n * (kNumSH / 4) + q4);
                 Bi[n][4 * q4] = v4.x; Bi[n][4 * q4 + 1] = v4.y;
                 Bi[n][4 * q4 + 2] = v4.z; Bi[n][4 * q4 + 3] = v4.w;
             }

@@ -111,6 +111,41 @@ __device__ __forceinline__ void bead_block_sum(double v, double *lds, int P, int
     __syncthreads();
 }
 
+// Adjoint rows B_i (and the angular sums parked in them) are stored
+// wavefront-interleaved: float4 q of the row of lane L of the launch's
+// wavefront w (w = workgroup index * wavefronts per workgroup + wavefront in
+// the workgroup) sits at float4 index (w * NA1 * 6 + q) * 64 + L, so that
+// one store or load of the wavefront's q-th float4 covers 1 KiB
+// contiguously (a row per lane would put every lane of it on another cache
+// line).  The kernels that write and read the rows share one launch shape,
+// the workspace's tile table; the array holds a row for every lane of a
+// launch, idle lanes included (never written; zero from creation).  The
+// accesses go through a buffer resource over the wavefront's rows: the
+// lane's byte offset in a vector register, the float4 index as a scalar
+// offset, so that no per-float4 64-bit address is kept in registers (the
+// rows of one lane span more than the immediate offset of a global access).
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+constexpr int kBufWord3 = 0x00020000;   // buffer resource word 3 of gfx9-family chips: 32-bit data format
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t adj_rows(float *B, int NA1)
+{
+    const uint32_t w = __builtin_amdgcn_readfirstlane((uint32_t)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    const int bytes = NA1 * (kNumSH / 4) * 64 * 16;
+    return __builtin_amdgcn_make_buffer_rsrc(B + (size_t)w * (bytes / 4), (short)0, bytes, kBufWord3);
+}
+
+__device__ __forceinline__ void adj_store(__amdgpu_buffer_rsrc_t r, int q, float4 v)
+{
+    const u32x4_t u = {__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z), __float_as_uint(v.w)};
+    __builtin_amdgcn_raw_buffer_store_b128(u, r, (int)(threadIdx.x & 63) * 16, q * 1024, 0);
+}
+
+__device__ __forceinline__ float4 adj_load(__amdgpu_buffer_rsrc_t r, int q)
+{
+    const u32x4_t u = __builtin_amdgcn_raw_buffer_load_b128(r, (int)(threadIdx.x & 63) * 16, q * 1024, 0);
+    return make_float4(__uint_as_float(u.x), __uint_as_float(u.y), __uint_as_float(u.z), __uint_as_float(u.w));
+}
+
 constexpr int kBatch = 4;    // neighbours whose index and position are loaded together
 constexpr int kBatchR = 8;   // the same for the descriptor's radial loop
 
