@@ -846,6 +846,10 @@ extern "C" int32_t nep_ws_create_batched(const nep_model *m, int32_t P, int32_t 
     w->B_waves = (size_t)cap + (size_t)3 * nsys;
     if (e == hipSuccess) e = dalloc(&w->B, w->B_waves * 64 * w->NA1 * kNumSH);
     if (e == hipSuccess) e = hipMemset(w->B, 0, sizeof(float) * w->B_waves * 64 * w->NA1 * kNumSH);
+    // descriptor adjoints beside parked angular sums, the same lanes (room for the four-body entries)
+    const size_t gq = (size_t)w->NA1 + (w->NA1 + 3) / 4;
+    if (e == hipSuccess) e = dalloc(&w->Gad, w->B_waves * 64 * gq * 4);
+    if (e == hipSuccess) e = hipMemset(w->Gad, 0, sizeof(float) * w->B_waves * 64 * gq * 4);
     if (e == hipSuccess) e = dalloc(&w->arad, PN * w->S * 12);
     if (e == hipSuccess) e = dalloc(&w->partE, (size_t)std::max(P, 1) * nb);
     if (e == hipSuccess) e = dalloc(&w->partW, (size_t)2 * std::max(P, 1) * nb * 9);
@@ -872,7 +876,7 @@ extern "C" int32_t nep_ws_create(const nep_model *m, int32_t P, int32_t N, nep_w
 extern "C" void nep_ws_destroy(nep_ws *w)
 {
     if (!w) return;
-    for (void *p : {(void *)w->B, (void *)w->arad, (void *)w->partE, (void *)w->partW, (void *)w->Fang,
+    for (void *p : {(void *)w->B, (void *)w->Gad, (void *)w->arad, (void *)w->partE, (void *)w->partW, (void *)w->Fang,
                     (void *)w->flags, (void *)w->tile_atom0, (void *)w->tile_atom1, (void *)w->tile_sys,
                     (void *)w->sys_tile0})
         if (p) (void)hipFree(p);

@@ -180,6 +180,8 @@ struct nep_ws {
     float *B = nullptr;        // angular adjoints dU_i/dA_nlm times c_m (the harmonic's normalisation), one
                                // row of NA1*24 per lane of a launch, wavefront-interleaved (adj_rows)
     size_t B_waves = 0;        // wavefronts whose rows B holds
+    float *Gad = nullptr;      // descriptor adjoints dU/dq_nl (and the four-body ones) per lane, for parked
+                               // angular sums (the angular force forms B from both), wavefront-interleaved
     float *arad = nullptr;     // [N][S][P][12] radial adjoints sum_n dU_i/dq_n c_nk (9 used)
     double *partE = nullptr;   // [P][nblk] per-workgroup partial energies (bead-major)
     double *partW = nullptr;   // angular pass [P][9][nblk], then radial pass [P][9][nblk] (room for nblk_cap)

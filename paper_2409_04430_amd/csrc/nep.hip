@@ -293,10 +293,10 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
         for (int v = 0; v < D; ++v) q[v] = 0.0f;
         // the wavefront's adjoint rows, interleaved (adj_rows): each float4
         // store or load of the wavefront covers 1 KiB contiguously
-        const __amdgpu_buffer_rsrc_t Bo = adj_rows(a.B, NA1);
+        const __amdgpu_buffer_rsrc_t Bo = adj_rows(a.B, NA1 * (kNumSH / 4));
         // A stays in registers through the network for small angular sets;
         // otherwise it is parked in the atom's adjoint row and read back
-        constexpr bool PARK = MF || NA1 > 5;
+        constexpr bool PARK = adj_parked(MF, NA1);
         float Ar[PARK ? 1 : NA1][kNumSH];
         if (MF ? mine : true) {
 
@@ -572,48 +572,39 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
         for (int v = 0; v < D; ++v) G[v] *= qs[v];
         if (MF ? !mine : false) continue;
 
-        // adjoints: B_nlm = dU/dA_nlm
+        // adjoints: B_nlm = dU/dA_nlm, formed here from the sums in
+        // registers, or, with the sums parked in the adjoint rows, by the
+        // angular force kernel from them and the descriptor adjoints stored
+        // here (no read-back of the parked sums)
+        if constexpr (PARK) {
+            const __amdgpu_buffer_rsrc_t go = adj_rows(a.Gad, gad_q(NA1, FOUR));
 #pragma unroll
-        for (int n = 0; n < NA1; ++n) {
-            float An[kNumSH];
-            if constexpr (PARK) {
+            for (int n = 0; n < NA1; ++n)
+                adj_store(go, n, make_float4(G[NR1 + n], G[NR1 + NA1 + n], G[NR1 + 2 * NA1 + n], G[NR1 + 3 * NA1 + n]));
+            if constexpr (FOUR) {
 #pragma unroll
-                for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
-                    const float4 v4 = adj_load(Bo, n * (kNumSH / 4) + q4);
-                    An[4 * q4] = v4.x; An[4 * q4 + 1] = v4.y; An[4 * q4 + 2] = v4.z; An[4 * q4 + 3] = v4.w;
+                for (int c4 = 0; c4 < (NA1 + 3) / 4; ++c4) {
+                    float g4[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int n = 4 * c4 + e;
+                        g4[e] = n < NA1 ? G[NR1 + kLmax * NA1 + (n < NA1 ? n : 0)] * a.kappa4 : 0.0f;
+                    }
+                    adj_store(go, NA1 + c4, make_float4(g4[0], g4[1], g4[2], g4[3]));
                 }
-            } else {
-#pragma unroll
-                for (int m = 0; m < kNumSH; ++m) An[m] = Ar[PARK ? 0 : n][m];
             }
-            float Bn[kNumSH];
+        } else {
 #pragma unroll
-            for (int m = 0; m < kNumSH; ++m) Bn[m] = 2.0f * G[NR1 + (sh_l(m) - 1) * NA1 + n] * An[m];
-            if (FOUR) {
-                float M[5];
-                m_from_l2(&An[3], shc, M);
-                const float mxy = M[0], myz = M[1], mzz = M[2], mxz = M[3], dd = M[4];
-                const float mxx = 0.5f * (dd - mzz), myy = 0.5f * (-dd - mzz);
-                // entries of M^2
-                const float sxx = mxx * mxx + mxy * mxy + mxz * mxz;
-                const float syy = mxy * mxy + myy * myy + myz * myz;
-                const float szz = mxz * mxz + myz * myz + mzz * mzz;
-                const float sxy = mxx * mxy + mxy * myy + mxz * myz;
-                const float syz = mxy * mxz + myy * myz + myz * mzz;
-                const float sxz = mxx * mxz + mxy * myz + mxz * mzz;
-                const float g4 = G[NR1 + kLmax * NA1 + n] * a.kappa4;
-                Bn[3] += g4 * 6.0f * sxy / shc[3];
-                Bn[4] += g4 * 6.0f * syz / shc[4];
-                Bn[5] += g4 * 3.0f * (szz - 0.5f * sxx - 0.5f * syy) / (3.0f * shc[5]);
-                Bn[6] += g4 * 6.0f * sxz / shc[6];
-                Bn[7] += g4 * 1.5f * (sxx - syy) / shc[7];
+            for (int n = 0; n < NA1; ++n) {
+                const float Gl[kLmax] = {G[NR1 + n], G[NR1 + NA1 + n], G[NR1 + 2 * NA1 + n], G[NR1 + 3 * NA1 + n]};
+                const float g4 = FOUR ? G[NR1 + kLmax * NA1 + n] * a.kappa4 : 0.0f;
+                float Bn[kNumSH];
+                form_adjoint<FOUR>(Ar[PARK ? 0 : n], Gl, g4, shc, Bn);
+#pragma unroll
+                for (int q4 = 0; q4 < kNumSH / 4; ++q4)
+                    adj_store(Bo, n * (kNumSH / 4) + q4,
+                              make_float4(Bn[4 * q4], Bn[4 * q4 + 1], Bn[4 * q4 + 2], Bn[4 * q4 + 3]));
             }
-            // stored as B_nlm c_m, the factor the pair terms need with the bare polynomials
-#pragma unroll
-            for (int m = 0; m < kNumSH; ++m) Bn[m] *= shc[m];
-#pragma unroll
-            for (int q4 = 0; q4 < kNumSH / 4; ++q4)
-                adj_store(Bo, n * (kNumSH / 4) + q4, make_float4(Bn[4 * q4], Bn[4 * q4 + 1], Bn[4 * q4 + 2], Bn[4 * q4 + 3]));
         }
         // radial adjoints a_k(t) = sum_n G_n c^{tc t}_nk, [atom][species][bead][12],
         // and in slot KR1 their sum over k >= 1 (the pair terms need it)
@@ -666,7 +657,7 @@ constexpr int kBatchAng = 4;   // angular entries whose loads are issued togethe
 template <int NA1> constexpr int kAngWaves() { return NA1 > 5 ? 1 : 2; }
 constexpr int kBatchRev = 8;   // reverse angular terms read together by the radial force kernel
 
-template <int NA1, int KA1, bool TRI>
+template <int NA1, int KA1, bool FOUR, bool PARKED, bool TRI>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kAngWaves<NA1>())))
 void k_force_ang(NepArgs a, const float *__restrict__ prm)
 {
@@ -695,16 +686,39 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
         const bool mine = valid && tok && ti == tc;
         todo &= ~__ballot(mine);
 
-        const __amdgpu_buffer_rsrc_t bi4 = adj_rows(a.B, NA1);
+        // B^i from the adjoint rows, or formed from the parked sums A^i and
+        // the descriptor adjoints (see the descriptor kernel): their loads
+        // are issued after the first neighbour batch's, so that the wait for
+        // them overlaps that batch's gathers
         float Bi[NA1][kNumSH];
+        bool formed = false;   // wave-uniform
+        auto get_adjoints = [&]() {
+            const __amdgpu_buffer_rsrc_t bi4 = adj_rows(a.B, NA1 * (kNumSH / 4));
 #pragma unroll
-        for (int n = 0; n < NA1; ++n)
+            for (int n = 0; n < NA1; ++n)
 #pragma unroll
-            for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
-                const float4 v4 = adj_load(bi4, n * (kNumSH / 4) + q4);
-                Bi[n][4 * q4] = v4.x; Bi[n][4 * q4 + 1] = v4.y;
-                Bi[n][4 * q4 + 2] = v4.z; Bi[n][4 * q4 + 3] = v4.w;
+                for (int q4 = 0; q4 < kNumSH / 4; ++q4) {
+                    const float4 v4 = adj_load(bi4, n * (kNumSH / 4) + q4);
+                    Bi[n][4 * q4] = v4.x; Bi[n][4 * q4 + 1] = v4.y;
+                    Bi[n][4 * q4 + 2] = v4.z; Bi[n][4 * q4 + 3] = v4.w;
+                }
+            if constexpr (PARKED) {
+                const __amdgpu_buffer_rsrc_t gi = adj_rows(a.Gad, gad_q(NA1, FOUR));
+                const float *shc = prm + a.osh;
+#pragma unroll
+                for (int n = 0; n < NA1; ++n) {
+                    const float4 gl = adj_load(gi, n);
+                    const float Gl[kLmax] = {gl.x, gl.y, gl.z, gl.w};
+                    float g4 = 0.0f;
+                    if constexpr (FOUR) {
+                        const float4 q = adj_load(gi, NA1 + n / 4);
+                        g4 = (n & 3) == 0 ? q.x : (n & 3) == 1 ? q.y : (n & 3) == 2 ? q.z : q.w;
+                    }
+                    form_adjoint<FOUR>(Bi[n], Gl, g4, shc, Bi[n]);
+                }
             }
+            formed = true;
+        };
         for (int t = 0; t < S; ++t) {
             int s0 = 0, s1 = 0;
             if (mine) block_range(a.uendA, i, t, s0, s1);
@@ -737,6 +751,7 @@ void k_force_ang(NepArgs a, const float *__restrict__ prm)
                 }
 #pragma unroll
                 for (int u = 0; u < kBatchAng; ++u) pq[u] = p4[(size_t)jq[u] * P + b];
+                if (!formed) get_adjoints();
 #pragma unroll
                 for (int u = 0; u < kBatchAng; ++u) keep(pq[u]);
 #pragma unroll
@@ -1035,7 +1050,10 @@ static void launch_t(const NepArgs &a, const float *prm, int nblk, int wpb, int 
     }
     {
         ProfScope ps_(K_FORCE_ANG, s);
-        hipLaunchKernelGGL((k_force_ang<NA1, 9, TRI>), g, blk, 0, s, a, prm);
+        if (adj_parked(mlp == NEP_MLP_BF16_MFMA || mlp == NEP_MLP_FP32_MFMA, NA1))
+            hipLaunchKernelGGL((k_force_ang<NA1, 9, FOUR, true, TRI>), g, blk, 0, s, a, prm);
+        else
+            hipLaunchKernelGGL((k_force_ang<NA1, 9, FOUR, false, TRI>), g, blk, 0, s, a, prm);
     }
     {
         ProfScope ps_(K_FORCE, s);
@@ -1097,7 +1115,7 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
     a.umR = nl->umR; a.umA = nl->umA;
     a.uendA = nl->uendA; a.capR = nl->capR; a.capA = nl->capA;
     a.pairbuf = reinterpret_cast<float4 *>(nl->pairbuf);
-    a.B = ws->B; a.arad = ws->arad; a.Fang = ws->Fang;
+    a.B = ws->B; a.Gad = ws->Gad; a.arad = ws->arad; a.Fang = ws->Fang;
     a.partE = ws->partE; a.partWa = ws->partW; a.partWr = ws->partW + (size_t)P * ws->nblk * 9;
     a.flags = ws->flags;
     a.F = F; a.Eatom = E_atom; a.Watom = W_atom;

@@ -25,7 +25,8 @@ struct NepArgs {
     int capR, capA;
     float4 *pairbuf;     // [N][capA][P] dU_j/dr_ji at the receiving atom's angular slot of j
     // workspace
-    float *B;            // [N][P][NA1*24]
+    float *B;            // adjoint rows B_nlm c_m, or the parked sums A_nlm, per lane (adj_rows)
+    float *Gad;          // with parked sums: dU/dq_nl per lane, l = 1..4 per float4, then kappa dU/dq4_n (adj_rows)
     float *arad;         // [N][S][P][kRadPad] radial adjoints a_k (k < 9) and, in slot 9, their sum over k >= 1
     float *Fang;         // [N][P][3]
     double *partE, *partWa, *partWr;   // [P][blocks], [P][9][blocks]
@@ -127,12 +128,24 @@ __device__ __forceinline__ void bead_block_sum(double v, double *lds, int P, int
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 constexpr int kBufWord3 = 0x00020000;   // buffer resource word 3 of gfx9-family chips: 32-bit data format
 
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t adj_rows(float *B, int NA1)
+// nq: float4 entries per lane.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t adj_rows(float *B, int nq)
 {
     const uint32_t w = __builtin_amdgcn_readfirstlane((uint32_t)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
-    const int bytes = NA1 * (kNumSH / 4) * 64 * 16;
+    const int bytes = nq * 64 * 16;
     return __builtin_amdgcn_make_buffer_rsrc(B + (size_t)w * (bytes / 4), (short)0, bytes, kBufWord3);
 }
+
+// Whether the descriptor kernel parks the angular sums A in the adjoint
+// rows (the matrix-core network needs their registers, and wide angular
+// sets do not fit beside the network): then it stores A there and the
+// descriptor adjoints dU/dq_nl in Gad, and the angular force forms B from
+// both; otherwise the descriptor stores B itself.
+constexpr bool adj_parked(bool matrix_core_net, int NA1) { return matrix_core_net || NA1 > 5; }
+
+// float4 entries per lane of Gad: one per radial function (l = 1..4), then
+// the four-body adjoints four to an entry.
+constexpr int gad_q(int NA1, bool four) { return NA1 + (four ? (NA1 + 3) / 4 : 0); }
 
 __device__ __forceinline__ void adj_store(__amdgpu_buffer_rsrc_t r, int q, float4 v)
 {

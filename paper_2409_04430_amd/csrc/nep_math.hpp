@@ -498,6 +498,41 @@ __device__ __forceinline__ void m_from_l2(const float *A2, const float *shc, flo
     M[4] = A2[4] / shc[7];
 }
 
+// Adjoint of one radial function n's angular sums, stored as B_nlm c_m:
+// B_nlm = dU/dA_nlm = 2 (dU/dq_nl) A_nlm, plus for the four-body invariant
+// q4_n = kappa tr(M_n^3) the derivative through M_n's l = 2 entries,
+// 3 kappa (dU/dq4_n) d tr(M^3)/dM = 3 g4 M^2 mapped back onto m = -2..2.
+// Gl[l - 1] = dU/dq_nl, g4 = kappa dU/dq4_n.  An and Bn may be the same
+// array (M is formed before any entry is written).
+template <bool FOUR>
+__device__ __forceinline__ void form_adjoint(const float *An, const float (&Gl)[kLmax], float g4,
+                                             const float *__restrict__ shc, float *Bn)
+{
+    float M[5] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (FOUR) m_from_l2(&An[3], shc, M);
+#pragma unroll
+    for (int m = 0; m < kNumSH; ++m) Bn[m] = 2.0f * Gl[sh_l(m) - 1] * An[m];
+    if (FOUR) {
+        const float mxy = M[0], myz = M[1], mzz = M[2], mxz = M[3], dd = M[4];
+        const float mxx = 0.5f * (dd - mzz), myy = 0.5f * (-dd - mzz);
+        // entries of M^2
+        const float sxx = mxx * mxx + mxy * mxy + mxz * mxz;
+        const float syy = mxy * mxy + myy * myy + myz * myz;
+        const float szz = mxz * mxz + myz * myz + mzz * mzz;
+        const float sxy = mxx * mxy + mxy * myy + mxz * myz;
+        const float syz = mxy * mxz + myy * myz + myz * mzz;
+        const float sxz = mxx * mxz + mxy * myz + mxz * mzz;
+        Bn[3] += g4 * 6.0f * sxy / shc[3];
+        Bn[4] += g4 * 6.0f * syz / shc[4];
+        Bn[5] += g4 * 3.0f * (szz - 0.5f * sxx - 0.5f * syy) / (3.0f * shc[5]);
+        Bn[6] += g4 * 6.0f * sxz / shc[6];
+        Bn[7] += g4 * 1.5f * (sxx - syy) / shc[7];
+    }
+    // stored as B_nlm c_m, the factor the pair terms need with the bare polynomials
+#pragma unroll
+    for (int m = 0; m < kNumSH; ++m) Bn[m] *= shc[m];
+}
+
 // Directional derivatives D_m = c_m grad p_m(u) . v of the 24 harmonics
 // (Y_m = c_m p_m) along v, p_m differentiated on R^3.
 __device__ __forceinline__ void sh_dir(float x, float y, float z, float vx, float vy, float vz,
