@@ -916,14 +916,18 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
                         const float qx = w * dx, qy = w * dy, qz = w * dz;
                         bx += qx; by += qy; bz += qz;
                         const float hx = -0.5f * dx, hy = -0.5f * dy, hz = -0.5f * dz;
+                        // a central pair term: r (x) q is symmetric, six entries
                         Wf[0] = fmaf(hx, qx, Wf[0]); Wf[1] = fmaf(hx, qy, Wf[1]); Wf[2] = fmaf(hx, qz, Wf[2]);
-                        Wf[3] = fmaf(hy, qx, Wf[3]); Wf[4] = fmaf(hy, qy, Wf[4]); Wf[5] = fmaf(hy, qz, Wf[5]);
-                        Wf[6] = fmaf(hz, qx, Wf[6]); Wf[7] = fmaf(hz, qy, Wf[7]); Wf[8] = fmaf(hz, qz, Wf[8]);
+                        Wf[4] = fmaf(hy, qy, Wf[4]); Wf[5] = fmaf(hy, qz, Wf[5]); Wf[8] = fmaf(hz, qz, Wf[8]);
                     }
                 }
                 Fx += (double)bx; Fy += (double)by; Fz += (double)bz;
             }
         }
+
+        Wf[3] = Wf[1];
+        Wf[6] = Wf[2];
+        Wf[7] = Wf[5];
 
         // reverse angular terms: F_i -= dU_j/dr_ji for every angular neighbour j
         const int32_t *uA = a.uniA + (size_t)i * a.capA;
