@@ -417,37 +417,72 @@ __global__ __launch_bounds__(kDecideBlock) void k_decide(const SysGeom *__restri
 
 
 // One candidate row sorted by (species, index) into dst, with its species
-// block starts: rank sort by one wavefront (each element's position is the
-// number of smaller keys), reading the unsorted row from lds (rows up to
-// kSortLds entries, copied there first) or straight from src.  src is not
-// modified, so other wavefronts may read it meanwhile.
-constexpr int kSortLds = 512;
+// block starts, by one wavefront.  Rows of up to kSortLds entries: the keys
+// go to lds, padded to a power of two with keys above every entry, and a
+// bitonic network sorts them there (log2(n) (log2(n) + 1) / 2 exchange
+// stages, n / 128 exchanges per lane each); longer rows: rank sort straight
+// from src (each element's position is the number of smaller keys).  src
+// is not modified, so other wavefronts may read it meanwhile.
+constexpr int kSortLds = 1024;
 __device__ __forceinline__ uint32_t cand_key(int32_t w)
 {
     return ((uint32_t)(w & 3) << 29) | (uint32_t)(w >> 2);   // species above index; entries are distinct
+}
+__device__ __forceinline__ int32_t cand_entry(uint32_t key)
+{
+    return (int32_t)(((key & 0x1fffffffu) << 2) | (key >> 29));
+}
+
+__device__ __forceinline__ void wave_lds_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
 __device__ void sort_row_into(int32_t *__restrict__ dst, int n, const int32_t *__restrict__ src,
                               int32_t *__restrict__ lds, int S, int32_t *__restrict__ off)
 {
     const int lane = threadIdx.x & 63;
-    const int32_t *from = src;
-    if (n <= kSortLds) {
-        for (int e = lane; e < n; e += 64) lds[e] = src[e];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        from = lds;
-    }
     int cntS[kMaxSpecies] = {0, 0, 0, 0};
-    for (int e = lane; e < n; e += 64) {
-        const int32_t w = from[e];
-        const uint32_t kw = cand_key(w);
-        int r = 0;
-        for (int f = 0; f < n; ++f) r += cand_key(from[f]) < kw;
-        dst[r] = w;
+    if (n <= kSortLds) {
+        uint32_t *key = reinterpret_cast<uint32_t *>(lds);
+        int np = 64;
+        while (np < n) np <<= 1;
+        for (int e = lane; e < np; e += 64) {
+            const int32_t w = e < n ? src[e] : 0;
+            key[e] = e < n ? cand_key(w) : 0xffffffffu;
+            if (e < n) {
 #pragma unroll
-        for (int t = 0; t < kMaxSpecies; ++t) cntS[t] += (w & 3) == t;
+                for (int t = 0; t < kMaxSpecies; ++t) cntS[t] += (w & 3) == t;
+            }
+        }
+        wave_lds_fence();
+        for (int size = 2; size <= np; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int t = lane; t < (np >> 1); t += 64) {
+                    const int lo = 2 * stride * (t / stride) + (t % stride), hi = lo + stride;
+                    const uint32_t a = key[lo], b = key[hi];
+                    const bool up = (lo & size) == 0;   // ascending block
+                    if ((a > b) == up) {
+                        key[lo] = b;
+                        key[hi] = a;
+                    }
+                }
+                wave_lds_fence();
+            }
+        }
+        for (int e = lane; e < n; e += 64) dst[e] = cand_entry(key[e]);
+    } else {
+        for (int e = lane; e < n; e += 64) {
+            const int32_t w = src[e];
+            const uint32_t kw = cand_key(w);
+            int r = 0;
+            for (int f = 0; f < n; ++f) r += cand_key(src[f]) < kw;
+            dst[r] = w;
+#pragma unroll
+            for (int t = 0; t < kMaxSpecies; ++t) cntS[t] += (w & 3) == t;
+        }
     }
 #pragma unroll
     for (int t = 0; t < kMaxSpecies; ++t)
@@ -462,9 +497,7 @@ __device__ void sort_row_into(int32_t *__restrict__ dst, int n, const int32_t *_
     }
     // the sorted row, its block starts and the buffer are read next by
     // every lane of this wavefront
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    wave_lds_fence();
 }
 
 // Candidate rows.  gridDim.y workgroups per cell, each taking every
@@ -660,22 +693,32 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
             // (slot k) the slot of i in j's sorted row, i.e. the number of
             // smaller keys in j's row, counted in its unsorted staging copy
             // (no other row need be sorted yet); -1 if i is missing (only
-            // when j's row overflowed)
+            // when j's row overflowed).  The whole wavefront scans each
+            // partner's row (contiguous loads), one candidate after another;
+            // lane k % 64 keeps slot k's result for one store per 64 slots.
             const int ti = types[i] & 3;
             const int32_t wi = (int32_t)(((uint32_t)i << 2) | (uint32_t)ti);
             const uint32_t ki = cand_key(wi);
-            for (int k = lane; k < n; k += 64) {
-                const int j = srow[k] >> 2;
-                const int nj = min(lenA[j], capA);
-                const int32_t *rj = candAs + (size_t)j * capA;
-                int r = 0;
-                bool found = false;
-                for (int f = 0; f < nj; ++f) {
-                    const int32_t w = rj[f];
-                    r += cand_key(w) < ki;
-                    found |= w == wi;
+            for (int k0 = 0; k0 < n; k0 += 64) {
+                const int kn = min(64, n - k0);
+                const int jl = lane < kn ? (srow[k0 + lane] >> 2) : i;   // the partners of these 64 slots
+                int res = -1;
+                for (int kk = 0; kk < kn; ++kk) {
+                    const int j = __builtin_amdgcn_readlane(jl, kk);
+                    const int nj = min(lenA[j], capA);
+                    const int32_t *rj = candAs + (size_t)j * capA;
+                    int r = 0;
+                    bool found = false;
+                    for (int f = lane; f < nj; f += 64) {
+                        const int32_t w = rj[f];
+                        r += cand_key(w) < ki;
+                        found |= w == wi;
+                    }
+                    for (int o = 32; o > 0; o >>= 1) r += __shfl_xor(r, o);
+                    const bool any = __ballot(found) != 0;
+                    if (lane == kk) res = any ? r : -1;
                 }
-                revA[(size_t)i * capA + k] = found ? r : -1;
+                if (lane < kn) revA[(size_t)i * capA + k0 + lane] = res;
             }
         }
     }
