@@ -29,6 +29,10 @@ class Workload:
     species_masses: List[float]
     e_scale: float = 30.0
     student: Optional[I.NepHyper] = None
+    # steps before any timing: the ring polymers start collapsed on their
+    # centroids, and those of light atoms (H) take a few hundred steps to
+    # reach their thermal spread, which sets the neighbour rows' radius
+    equilibrate: int = 0
 
     def systems(self, P: Optional[int] = None, scale: int = 1) -> List[I.System]:
         """Build the periodic system(s) for this workload (list, one per box)."""
@@ -99,11 +103,12 @@ WORKLOADS = {
     # Sixteen water boxes of 64..1024 molecules, 32 beads at 300 K.
     "water16": Workload("water16", 4433, P=32, T=300.0, dt=0.5, mode="trpmd", steps=100, tau_T=100.0,
                         hyper=I.NepHyper(2, 6.0, 4.0, 4, 4, 8, 8, 4, False, 50),
-                        species_masses=[16.0, 1.008], e_scale=3.344848202322741),
+                        species_masses=[16.0, 1.008], e_scale=3.344848202322741, equilibrate=300),
     # Porous four-species framework, 13,824 atoms, 64 beads at 300 K.
     "porous13824": Workload("porous13824", 4484, P=64, T=300.0, dt=0.5, mode="trpmd", steps=50,
                             tau_T=100.0, hyper=I.NepHyper(4, 6.0, 4.0, 8, 6, 8, 8, 4, False, 80),
-                            species_masses=[65.38, 16.0, 12.011, 1.008], e_scale=0.5454022746326813),
+                            species_masses=[65.38, 16.0, 12.011, 1.008], e_scale=0.5454022746326813,
+                            equilibrate=300),
     # Large FCC crystal: teacher with four-body terms and a small student.
     "fcc32000": Workload("fcc32000", 4435, P=32, T=300.0, dt=1.0, mode="trpmd", steps=100, tau_T=100.0,
                          hyper=I.NepHyper(1, 6.0, 5.0, 8, 8, 8, 8, 4, True, 100),
