@@ -295,7 +295,8 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
         // store or load of the wavefront covers 1 KiB contiguously
         const __amdgpu_buffer_rsrc_t Bo = adj_rows(a.B, NA1 * (kNumSH / 4));
         // A stays in registers through the network for small angular sets;
-        // otherwise it is parked in the atom's adjoint row and read back
+        // otherwise it is parked in the lane's adjoint row, where the
+        // angular force kernel reads it
         constexpr bool PARK = adj_parked(MF, NA1);
         float Ar[PARK ? 1 : NA1][kNumSH];
         if (MF ? mine : true) {
@@ -360,7 +361,7 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
 
         // angular: A_nlm = sum_j g_n(r_ij) Y_lm(u_ij), NG radial functions n
         // per pass over the neighbours (all of them when A stays in
-        // registers; in two passes when more than five are parked, so that
+        // registers; in three passes when more than five are parked, so that
         // the accumulators of one pass fit the registers), each pass's q
         // entries formed and its A parked before the next
         constexpr int NG = NA1 > 5 ? (NA1 + 2) / 3 : NA1;
@@ -463,7 +464,7 @@ void k_descriptor(NepArgs a, const float *__restrict__ prm)
                 q[NR1 + kLmax * NA1 + n] = a.kappa4 * tr3;
             }
             if constexpr (PARK) {
-                // park A in this lane's adjoint row (overwritten with B below)
+                // park A in this lane's adjoint row (the angular force kernel forms B from it)
 #pragma unroll
                 for (int q4 = 0; q4 < kNumSH / 4; ++q4)
                     adj_store(Bo, n * (kNumSH / 4) + q4,
