@@ -742,13 +742,18 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
     int32_t *uend = (kind ? uendA : uendR) + (size_t)i * kMaxSpecies;
     const CutTest c = kind ? cA : cR;
     const double rc = sqrt(c.rc2);
+    // batches of 64 row entries run across the species blocks (the row is
+    // sorted by species, so the kept entries stay in blocks); each species'
+    // kept count gives the block ends
     int cnt = 0;   // wave-uniform
-    for (int t = 0; t < S; ++t) {
-        const int k0 = min(o[t], cap), k1 = min(o[t + 1], cap);
-        for (int kb = k0; kb < k1; kb += 64) {
+    int cntS[kMaxSpecies] = {0, 0, 0, 0};
+    const int kend = min(o[S], cap);
+    {
+        for (int kb = 0; kb < kend; kb += 64) {
             const int k = kb + lane;
-            const bool kin = k < k1;
-            const int j = kin ? row[k] >> 2 : i;
+            const bool kin = k < kend;
+            const int32_t wrow = kin ? row[k] : 0;
+            const int j = kin ? wrow >> 2 : i;
             double dv[3] = {cen[3 * (size_t)j] - ci0, cen[3 * (size_t)j + 1] - ci1, cen[3 * (size_t)j + 2] - ci2};
             mic_vec(dv, g, tri);
             // d + s < rc - eps and d - s > rc + eps, on squares
@@ -811,10 +816,17 @@ __global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, c
                 um[cnt + rank] = mask;
             }
             cnt += __popcll(bal);
+            for (int t = 0; t < S; ++t) cntS[t] += __popcll(__ballot(keep && (wrow & 3) == t));
         }
-        if (lane == 0) uend[t] = cnt;
     }
-    if (lane == 0) raise_max(&status[1 + kind], (uint32_t)cnt);
+    if (lane == 0) {
+        int run = 0;
+        for (int t = 0; t < S; ++t) {
+            run += cntS[t];
+            uend[t] = run;
+        }
+        raise_max(&status[1 + kind], (uint32_t)cnt);
+    }
 }
 
 // Per-bead lists written out for tests and analysis: one lane per (bead,
