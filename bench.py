@@ -625,12 +625,16 @@ def workload_leg(args, torch, lib, configs, I, NepPimd, name: str, steps: int, g
 
 
 def d3_flops(nR: float, nC: float) -> float:
-    """FP64 operations per (bead, atom) of the D3 passes (own count; an exp
-    counts 1): per dispersion pair the minimum image and distance (14), the
-    partner's five reference weights (25), the C6 interpolation and its
-    derivative (76), the damped terms and their derivatives (22) and the
-    sums (22); per coordination pair the term (20) and its force and virial
-    through the coordination numbers (45)."""
+    """FP64 operations per (bead, atom) of the D3 passes, counted for the
+    plain form of the method (an exp counts 1): per dispersion pair the
+    minimum image and distance (14), the partner's five reference weights
+    (25), the C6 interpolation over the 5 x 5 references and its derivative
+    (76), the damped terms and their derivatives (22) and the sums (22); per
+    coordination pair the term (20) and its force and virial through the
+    coordination numbers (45).  The kernels execute fewer: the partner's
+    weights come precomputed, and the C6 sum is contracted with the lane's
+    own weights once per partner species, leaving two 5-term dot products
+    per pair."""
     return 159.0 * nR + 65.0 * nC
 
 

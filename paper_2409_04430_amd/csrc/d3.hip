@@ -23,9 +23,14 @@
 // of the union lists' bead masks.  Passes, one lane per (atom, bead), the
 // beads of an atom in adjacent lanes, gathers only (no atomics):
 //   k_d3_cn       CN_i over the coordination list, and the atom's reference
-//                 weights, which its partners gather in the next pass;
+//                 weights divided by their sum, w_i,a = L_i,a / sum_a L_i,a,
+//                 which its partners gather in the next pass;
 //   k_d3_pair     site energy, direct forces and virial over the dispersion
-//                 list, and dE/dCN_i = -sum_j (de_ij/dC6) dC6_ij/dCN_i;
+//                 list, and dE/dCN_i = -sum_j (de_ij/dC6) dC6_ij/dCN_i.
+//                 C6_ij = sum_b V_i,b w_j,b with V_i,b = sum_a w_i,a
+//                 C6ref(a, b) formed once per (lane, partner species), and
+//                 dC6_ij/dCN_i = sum_b V'_i,b w_j,b with V' built from
+//                 dw_i,a/dCN_i: two 5-term dot products per pair;
 //   k_d3_cnforce  forces (dE/dCN_i + dE/dCN_j) c'(r) u_ij and virial
 //                 -dE/dCN_i c'(r) r_ij (x) u_ij through the coordination
 //                 numbers, the total force written (or added);
@@ -43,10 +48,13 @@
 namespace nep {
 
 constexpr int kD3Ref = 5;
-// table: rcov [4], q [4], cnref [4][5], c6ref [4][4][5][5], f^6 [4][4], f^8 [4][4], 3 q_i q_j [4][4]
+// table: rcov [4], q [4], cnref [4][5], c6ref [4][4][5][5], f^6 [4][4], f^8 [4][4], 3 q_i q_j [4][4],
+// reference counts [4]
 constexpr int kTRcov = 0, kTQ = 4, kTCn = 8, kTC6 = kTCn + kMaxSpecies * kD3Ref,
               kTF6 = kTC6 + kMaxSpecies * kMaxSpecies * kD3Ref * kD3Ref, kTF8 = kTF6 + 16, kTQQ = kTF8 + 16,
-              kTab = kTQQ + 16;
+              kTNref = kTQQ + 16, kTab = kTNref + kMaxSpecies;
+constexpr int kD3Batch = 4;       // list entries whose loads are issued together (coordination passes)
+constexpr int kD3PairBatch = 2;   // the same in the dispersion pass (FP64 registers)
 constexpr double kD3PadCn = 1.0e4;   // reference slots past a species' count: weight exp(-k3 1e8) = 0
 
 struct D3Args {
@@ -60,17 +68,26 @@ struct D3Args {
     const double *tab;
     double s6, s8, k1, k2, k3;
     double *cn, *dedcn, *fdir;   // [N][P], [N][P], [N][P][3]
-    double *wts;                 // [N][P][8]: reference weights L_0..4, their sum, its derivative (see ref_weights)
+    double *wts;                 // [5][N][P]: normalised reference weights w_0..4, one plane per reference
     double *partE, *partW0, *partW1;   // [P][nblk], [P][9][nblk] twice
     float *F;
     int accumulate;
 };
 
-// (atom, bead) of this lane: 2^lg lanes per atom, 256 >> lg atoms per workgroup.
+// (atom, bead) of this lane: 2^lg lanes per atom, 256 >> lg atoms per
+// workgroup.  Workgroups go to the 8 XCDs round-robin; when their number is
+// a multiple of 8 the atom blocks are permuted so that each XCD works through
+// one contiguous run of atoms, whose partners (neighbouring atom indices)
+// then stay in that XCD's L2 (XCD = true: the dispersion pass, whose 12 A
+// partner data is the largest; the 6 A passes measured slower with it).
+template <bool XCD = false>
 __device__ __forceinline__ bool d3_lane(const D3Args &a, int &i, int &b)
 {
     const int G = 1 << a.lg;
-    i = blockIdx.x * (256 >> a.lg) + ((int)threadIdx.x >> a.lg);
+    const int nb = gridDim.x;
+    int blk = blockIdx.x;
+    if (XCD && (nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
+    i = blk * (256 >> a.lg) + ((int)threadIdx.x >> a.lg);
     b = threadIdx.x & (G - 1);
     const bool ok = i < a.N && b < a.P;
     i = i < a.N ? i : a.N - 1;
@@ -101,11 +118,13 @@ __global__ void k_d3_beads_minor(const double *__restrict__ pos, double *__restr
 // Minimum-image vector r_j - r_i in FP64 (every listed pair is closer than
 // half the smallest face distance, so the rint reduction gives the nearest
 // image, as in the list test).
-__device__ __forceinline__ void d3_pair_vec(const double *rj, const double *ri, const SysGeom &g, double &dx,
-                                            double &dy, double &dz)
+// TRI = false: launches on orthorhombic cells only, no general-cell code.
+template <bool TRI>
+__device__ __forceinline__ void d3_pair_vec(const double *rj, double xi, double yi, double zi, const SysGeom &g,
+                                            double &dx, double &dy, double &dz)
 {
-    double d[3] = {rj[0] - ri[0], rj[1] - ri[1], rj[2] - ri[2]};
-    if (!g.tri) {
+    double d[3] = {rj[0] - xi, rj[1] - yi, rj[2] - zi};
+    if (!TRI || !g.tri) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) d[c] -= g.L[c] * rint(d[c] * g.invL[c]);
     } else {
@@ -149,6 +168,7 @@ __device__ __forceinline__ void ref_weights(const double *t, int ty, double cn, 
 
 // ------------------------------------------------ coordination numbers ---
 
+template <bool TRI>
 __global__ __launch_bounds__(256) void k_d3_cn(D3Args a)
 {
     __shared__ double t[kTab];
@@ -163,92 +183,161 @@ __global__ __launch_bounds__(256) void k_d3_cn(D3Args a)
     const uint64_t *mA = a.umA + (size_t)i * a.capA;
     const int32_t *row = a.candA + (size_t)i * a.capA;
     const int n = a.uendA[(size_t)i * kMaxSpecies + a.S - 1];
+    const double xi = ri[0], yi = ri[1], zi = ri[2];
     const double Ri = t[kTRcov + ti], kk = a.k1 * a.k2;
     double cn = 0.0;
-    for (int e = 0; e < n; ++e) {
-        if (!((mA[e] >> b) & 1u)) continue;
-        const int w = row[uA[e]];
-        const int j = w >> 2, tj = w & 3;
-        double dx, dy, dz;
-        d3_pair_vec(a.posT + ((size_t)j * P + b) * 3, ri, g, dx, dy, dz);
-        const double r = sqrt(dx * dx + dy * dy + dz * dz);
-        cn += 1.0 / (1.0 + exp(a.k1 - kk * (Ri + t[kTRcov + tj]) / r));
+    // entries four at a time: every load of a batch issued before its arithmetic
+    for (int e0 = 0; e0 < n; e0 += kD3Batch) {
+        uint64_t mm[kD3Batch];
+        int w[kD3Batch];
+#pragma unroll
+        for (int k = 0; k < kD3Batch; ++k) {
+            const int e = min(e0 + k, n - 1);
+            const uint64_t m = mA[e];
+            mm[k] = e0 + k < n ? m : 0ull;
+            w[k] = uA[e];
+        }
+#pragma unroll
+        for (int k = 0; k < kD3Batch; ++k) w[k] = row[w[k]];
+        double pj[kD3Batch][3];
+#pragma unroll
+        for (int k = 0; k < kD3Batch; ++k) {
+            const double *q = a.posT + ((size_t)(w[k] >> 2) * P + b) * 3;
+            pj[k][0] = q[0];
+            pj[k][1] = q[1];
+            pj[k][2] = q[2];
+        }
+#pragma unroll
+        for (int k = 0; k < kD3Batch; ++k) {
+            double dx, dy, dz;
+            d3_pair_vec<TRI>(pj[k], xi, yi, zi, g, dx, dy, dz);
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double c = 1.0 / (1.0 + exp(a.k1 - kk * (Ri + t[kTRcov + (w[k] & 3)]) / r));
+            cn += ((mm[k] >> b) & 1u) ? c : 0.0;
+        }
     }
     a.cn[(size_t)i * P + b] = cn;
-    // this atom's reference weights, gathered by every partner in the pair pass
+    // this atom's normalised reference weights, gathered by every partner in the pair pass
     double L[kD3Ref], dL[kD3Ref], sL, sdL;
     ref_weights(t, ti, cn, a.k3, L, dL, sL, sdL);
-    double2 *wo = reinterpret_cast<double2 *>(a.wts + ((size_t)i * P + b) * 8);
-    wo[0] = make_double2(L[0], L[1]);
-    wo[1] = make_double2(L[2], L[3]);
-    wo[2] = make_double2(L[4], sL);
-    wo[3] = make_double2(sdL, 0.0);
+    const double is = 1.0 / sL;
+    const size_t PN = (size_t)a.N * P;
+#pragma unroll
+    for (int r = 0; r < kD3Ref; ++r) a.wts[r * PN + (size_t)i * P + b] = L[r] * is;
 }
 
 // ------------------------------------------- dispersion pairs, dE/dCN ---
 
+template <bool TRI>
 __global__ __launch_bounds__(256) void k_d3_pair(D3Args a)
 {
     __shared__ double t[kTab];
     __shared__ double lds[256];
     load_tab(a, t);
     int i, b;
-    const bool ok = d3_lane(a, i, b);
+    const bool ok = d3_lane<true>(a, i, b);
     const SysGeom &g = a.geom[0];
     const int P = a.P, S = a.S, ti = a.types[i] & 3;
     const double *ri = a.posT + ((size_t)i * P + b) * 3;
-    double Li[kD3Ref], dLi[kD3Ref], sLi, sdLi;
-    ref_weights(t, ti, a.cn[(size_t)i * P + b], a.k3, Li, dLi, sLi, sdLi);   // with derivatives (once per lane)
+    const double xi = ri[0], yi = ri[1], zi = ri[2];
+    // this lane's normalised weights w_a and their derivatives
+    // dw_a/dCN = (dL_a - w_a sum dL) / sum L, parked in LDS (column per
+    // lane) until each partner species block forms its V and V'
+    __shared__ double wsh[2 * kD3Ref][256];
+    {
+        double L[kD3Ref], dL[kD3Ref], sL, sdL;
+        ref_weights(t, ti, a.cn[(size_t)i * P + b], a.k3, L, dL, sL, sdL);
+        const double is = 1.0 / sL;
+#pragma unroll
+        for (int r = 0; r < kD3Ref; ++r) {
+            const double w = L[r] * is;
+            wsh[r][threadIdx.x] = w;
+            wsh[kD3Ref + r][threadIdx.x] = (dL[r] - w * sdL) * is;
+        }
+    }
     double U = 0.0, dE = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-    double Wv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // xx yy zz xy xz yz (symmetric)
+    double Wv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // xx yy zz xy xz yz (symmetric), halved at the end
     const int32_t *uR = a.uniR + (size_t)i * a.capR;
     const uint64_t *mR = a.umR + (size_t)i * a.capR;
+    const size_t PN = (size_t)a.N * P;
     for (int tj = 0; tj < S && ok; ++tj) {
         int s0, s1;
         block_range(a.uendR, i, tj, s0, s1);
+        if (s1 <= s0) continue;
+        // V_b = sum_a w_i,a C6ref(a, b) and its CN_i derivative for this partner species
         const double *c6 = t + kTC6 + (ti * kMaxSpecies + tj) * kD3Ref * kD3Ref;
-        const double f6 = t[kTF6 + ti * 4 + tj], f8 = t[kTF8 + ti * 4 + tj], qq = t[kTQQ + ti * 4 + tj];
-        for (int e = s0; e < s1; ++e) {
-            if (!((mR[e] >> b) & 1u)) continue;
-            const int j = uR[e];
-            double dx, dy, dz;
-            d3_pair_vec(a.posT + ((size_t)j * P + b) * 3, ri, g, dx, dy, dz);
-            const double r2 = dx * dx + dy * dy + dz * dz;
-            // the partner's weights from the coordination pass (the same
-            // arithmetic as ref_weights here; its derivative is not needed)
-            const double2 *wj = reinterpret_cast<const double2 *>(a.wts + ((size_t)j * P + b) * 8);
-            const double2 w01 = wj[0], w23 = wj[1], w4s = wj[2];
-            const double Lj[kD3Ref] = {w01.x, w01.y, w23.x, w23.y, w4s.x};
-            const double sLj = w4s.y;
-            double Z = 0.0, dZ = 0.0;
+        double V[kD3Ref], dV[kD3Ref];
+#pragma unroll
+        for (int rb = 0; rb < kD3Ref; ++rb) {
+            double v = 0.0, dv = 0.0;
 #pragma unroll
             for (int ra = 0; ra < kD3Ref; ++ra) {
-                double sa = 0.0;
-#pragma unroll
-                for (int rb = 0; rb < kD3Ref; ++rb) sa = fma(c6[ra * kD3Ref + rb], Lj[rb], sa);
-                Z = fma(Li[ra], sa, Z);
-                dZ = fma(dLi[ra], sa, dZ);
+                v = fma(wsh[ra][threadIdx.x], c6[ra * kD3Ref + rb], v);
+                dv = fma(wsh[kD3Ref + ra][threadIdx.x], c6[ra * kD3Ref + rb], dv);
             }
-            const double Winv = 1.0 / (sLi * sLj);
-            const double C6 = Z * Winv;
-            const double dC6 = (dZ - C6 * sdLi * sLj) * Winv;
-            const double r6 = r2 * r2 * r2, r8 = r6 * r2;
-            const double d6inv = 1.0 / (r6 + f6), d8inv = 1.0 / (r8 + f8);
-            const double e6 = a.s6 * C6 * d6inv, e8 = a.s8 * qq * C6 * d8inv;
-            // de/dr / r = -(6 e6 r^6 / (r^6 + f^6) + 8 e8 r^8 / (r^8 + f^8)) / r^2
-            const double dedr_r = -(6.0 * e6 * r6 * d6inv + 8.0 * e8 * r8 * d8inv) / r2;
-            const double dedc6 = a.s6 * d6inv + a.s8 * qq * d8inv;
-            U -= 0.5 * (e6 + e8);
-            dE -= dedc6 * dC6;
-            // F_i = -sum_j e' u_ij;  W += 1/2 e' r_ij (x) u_ij
-            fx -= dedr_r * dx;
-            fy -= dedr_r * dy;
-            fz -= dedr_r * dz;
-            const double hw = 0.5 * dedr_r;
-            Wv[0] += hw * dx * dx; Wv[1] += hw * dy * dy; Wv[2] += hw * dz * dz;
-            Wv[3] += hw * dx * dy; Wv[4] += hw * dx * dz; Wv[5] += hw * dy * dz;
+            V[rb] = v;
+            dV[rb] = dv;
+        }
+        const int nr = (int)t[kTNref + tj];   // the partner's weight planes past its reference count are 0
+        const double f6 = t[kTF6 + ti * 4 + tj], f8 = t[kTF8 + ti * 4 + tj];
+        const double s6 = a.s6, s8q = a.s8 * t[kTQQ + ti * 4 + tj];
+        for (int e0 = s0; e0 < s1; e0 += kD3PairBatch) {
+            uint64_t mm[kD3PairBatch];
+            int jj[kD3PairBatch];
+#pragma unroll
+            for (int k = 0; k < kD3PairBatch; ++k) {
+                const int e = min(e0 + k, s1 - 1);
+                const uint64_t m = mR[e];
+                mm[k] = e0 + k < s1 ? m : 0ull;
+                jj[k] = uR[e];
+            }
+            double pj[kD3PairBatch][3], wj[kD3PairBatch][kD3Ref];
+#pragma unroll
+            for (int k = 0; k < kD3PairBatch; ++k) {
+                const size_t o = (size_t)jj[k] * P + b;
+                const double *q = a.posT + o * 3;
+                pj[k][0] = q[0];
+                pj[k][1] = q[1];
+                pj[k][2] = q[2];
+#pragma unroll
+                for (int r = 0; r < kD3Ref; ++r) wj[k][r] = r < nr ? a.wts[r * PN + o] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < kD3PairBatch; ++k) {
+                double dx, dy, dz;
+                d3_pair_vec<TRI>(pj[k], xi, yi, zi, g, dx, dy, dz);
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                double C6 = 0.0, dC6 = 0.0;
+#pragma unroll
+                for (int r = 0; r < kD3Ref; ++r) {
+                    C6 = fma(V[r], wj[k][r], C6);
+                    dC6 = fma(dV[r], wj[k][r], dC6);
+                }
+                const double r6 = r2 * r2 * r2, r8 = r6 * r2;
+                const double a6 = r6 + f6, a8 = r8 + f8;
+                // one division for 1/a6, 1/a8 and 1/r2
+                const double inv = 1.0 / (a6 * a8 * r2);
+                const double a8r = a8 * r2, a6r = a6 * r2;
+                const double d6inv = a8r * inv, d8inv = a6r * inv, ir2 = a6 * a8 * inv;
+                const double e6 = s6 * C6 * d6inv, e8 = s8q * C6 * d8inv;
+                // de/dr / r = -(6 e6 r^6 / (r^6 + f^6) + 8 e8 r^8 / (r^8 + f^8)) / r^2
+                const double on = ((mm[k] >> b) & 1u) ? 1.0 : 0.0;
+                const double dedr_r = -on * (6.0 * e6 * r6 * d6inv + 8.0 * e8 * r8 * d8inv) * ir2;
+                const double dedc6 = on * (s6 * d6inv + s8q * d8inv);
+                U += on * (e6 + e8);
+                dE -= dedc6 * dC6;
+                // F_i = -sum_j e' u_ij;  W += 1/2 e' r_ij (x) u_ij
+                fx -= dedr_r * dx;
+                fy -= dedr_r * dy;
+                fz -= dedr_r * dz;
+                Wv[0] += dedr_r * dx * dx; Wv[1] += dedr_r * dy * dy; Wv[2] += dedr_r * dz * dz;
+                Wv[3] += dedr_r * dx * dy; Wv[4] += dedr_r * dx * dz; Wv[5] += dedr_r * dy * dz;
+            }
         }
     }
+    U *= -0.5;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) Wv[c] *= 0.5;
     if (ok) {
         a.dedcn[(size_t)i * P + b] = dE;
         double *fo = a.fdir + ((size_t)i * P + b) * 3;
@@ -265,6 +354,7 @@ __global__ __launch_bounds__(256) void k_d3_pair(D3Args a)
 
 // ------------------------------------ forces through the coordination ---
 
+template <bool TRI>
 __global__ __launch_bounds__(256) void k_d3_cnforce(D3Args a)
 {
     __shared__ double t[kTab];
@@ -275,6 +365,7 @@ __global__ __launch_bounds__(256) void k_d3_cnforce(D3Args a)
     const SysGeom &g = a.geom[0];
     const int P = a.P, ti = a.types[i] & 3;
     const double *ri = a.posT + ((size_t)i * P + b) * 3;
+    const double xi = ri[0], yi = ri[1], zi = ri[2];
     const double dEi = a.dedcn[(size_t)i * P + b];
     const int32_t *uA = a.uniA + (size_t)i * a.capA;
     const uint64_t *mA = a.umA + (size_t)i * a.capA;
@@ -283,26 +374,48 @@ __global__ __launch_bounds__(256) void k_d3_cnforce(D3Args a)
     const double Ri = t[kTRcov + ti], kk = a.k1 * a.k2;
     double fx = 0.0, fy = 0.0, fz = 0.0;
     double Wv[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int e = 0; e < n; ++e) {
-        if (!((mA[e] >> b) & 1u)) continue;
-        const int w = row[uA[e]];
-        const int j = w >> 2, tj = w & 3;
-        double dx, dy, dz;
-        d3_pair_vec(a.posT + ((size_t)j * P + b) * 3, ri, g, dx, dy, dz);
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        const double r = sqrt(r2);
-        const double R = Ri + t[kTRcov + tj];
-        const double ex = exp(a.k1 - kk * R / r);
-        const double den = 1.0 + ex;
-        // c'(r) / r = -ex k1 k2 R / (r^3 (1 + ex)^2)
-        const double dc_r = -ex * kk * R / (r2 * r * den * den);
-        const double sum = (dEi + a.dedcn[(size_t)j * P + b]) * dc_r;
-        fx += sum * dx;
-        fy += sum * dy;
-        fz += sum * dz;
-        const double hw = -dEi * dc_r;
-        Wv[0] += hw * dx * dx; Wv[1] += hw * dy * dy; Wv[2] += hw * dz * dz;
-        Wv[3] += hw * dx * dy; Wv[4] += hw * dx * dz; Wv[5] += hw * dy * dz;
+    for (int e0 = 0; e0 < n; e0 += kD3Batch) {
+        uint64_t mm[kD3Batch];
+        int w[kD3Batch];
+#pragma unroll
+        for (int k = 0; k < kD3Batch; ++k) {
+            const int e = min(e0 + k, n - 1);
+            const uint64_t m = mA[e];
+            mm[k] = e0 + k < n ? m : 0ull;
+            w[k] = uA[e];
+        }
+#pragma unroll
+        for (int k = 0; k < kD3Batch; ++k) w[k] = row[w[k]];
+        double pj[kD3Batch][3], dEj[kD3Batch];
+#pragma unroll
+        for (int k = 0; k < kD3Batch; ++k) {
+            const size_t o = (size_t)(w[k] >> 2) * P + b;
+            const double *q = a.posT + o * 3;
+            pj[k][0] = q[0];
+            pj[k][1] = q[1];
+            pj[k][2] = q[2];
+            dEj[k] = a.dedcn[o];
+        }
+#pragma unroll
+        for (int k = 0; k < kD3Batch; ++k) {
+            double dx, dy, dz;
+            d3_pair_vec<TRI>(pj[k], xi, yi, zi, g, dx, dy, dz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double r = sqrt(r2);
+            const double R = Ri + t[kTRcov + (w[k] & 3)];
+            const double ex = exp(a.k1 - kk * R / r);
+            const double den = 1.0 + ex;
+            // c'(r) / r = -ex k1 k2 R / (r^3 (1 + ex)^2)
+            const double on = ((mm[k] >> b) & 1u) ? 1.0 : 0.0;
+            const double dc_r = -on * ex * kk * R / (r2 * r * den * den);
+            const double sum = (dEi + dEj[k]) * dc_r;
+            fx += sum * dx;
+            fy += sum * dy;
+            fz += sum * dz;
+            const double hw = -dEi * dc_r;
+            Wv[0] += hw * dx * dx; Wv[1] += hw * dy * dy; Wv[2] += hw * dz * dz;
+            Wv[3] += hw * dx * dy; Wv[4] += hw * dx * dz; Wv[5] += hw * dy * dz;
+        }
     }
     if (ok) {
         const double *fd = a.fdir + ((size_t)i * P + b) * 3;
@@ -369,7 +482,7 @@ struct nep_d3_ws {
     int P = 0, N = 0, nblk = 0, lg = 0;
     int device = 0;
     double *posT = nullptr;                      // [N][P][3] bead-minor positions
-    double *wts = nullptr;                       // [N][P][8] reference weights of each (atom, bead)
+    double *wts = nullptr;                       // [5][N][P] normalised reference weights of each (atom, bead)
     double *cn = nullptr, *dedcn = nullptr, *fdir = nullptr;
     double *partE = nullptr, *partW = nullptr;   // [P][nblk], 2 x [P][9][nblk]
 };
@@ -430,6 +543,7 @@ extern "C" int32_t nep_d3_load(const char *path, nep_d3 **out)
     for (int s = 0; s < S; ++s) {
         t[kTRcov + s] = rcov[s];
         t[kTQ + s] = q[s];
+        t[kTNref + s] = nref[s];
     }
     for (int si = 0; si < S; ++si)
         for (int sj = 0; sj < S; ++sj) {
@@ -490,7 +604,7 @@ extern "C" int32_t nep_d3_ws_create(const nep_d3 *d, int32_t P, int32_t N, nep_d
     const size_t PN = (size_t)(P > 0 ? P : 1) * (N > 0 ? N : 1), Pp = P > 0 ? P : 1;
     hipError_t e = hipGetDevice(&w->device);
     if (e == hipSuccess) e = hipMalloc((void **)&w->posT, sizeof(double) * 3 * PN);
-    if (e == hipSuccess) e = hipMalloc((void **)&w->wts, sizeof(double) * 8 * PN);
+    if (e == hipSuccess) e = hipMalloc((void **)&w->wts, sizeof(double) * kD3Ref * PN);
     if (e == hipSuccess) e = hipMalloc((void **)&w->cn, sizeof(double) * PN);
     if (e == hipSuccess) e = hipMalloc((void **)&w->dedcn, sizeof(double) * PN);
     if (e == hipSuccess) e = hipMalloc((void **)&w->fdir, sizeof(double) * 3 * PN);
@@ -557,19 +671,23 @@ extern "C" int32_t nep_d3_compute(const nep_d3 *d, nep_nlist *nl, nep_d3_ws *w, 
     a.F = F;
     a.accumulate = accumulate ? 1 : 0;
     const dim3 grid(w->nblk), block(256);
+    const bool tri = nl->any_tri != 0;
     {
         ProfScope ps_(K_D3_CN, s);
         const int64_t PN = (int64_t)P * N;
         hipLaunchKernelGGL(k_d3_beads_minor, dim3((unsigned)((PN + 255) / 256)), dim3(256), 0, s, pos, w->posT, P, N);
-        hipLaunchKernelGGL(k_d3_cn, grid, block, 0, s, a);
+        if (tri) hipLaunchKernelGGL(k_d3_cn<true>, grid, block, 0, s, a);
+        else hipLaunchKernelGGL(k_d3_cn<false>, grid, block, 0, s, a);
     }
     {
         ProfScope ps_(K_D3_PAIR, s);
-        hipLaunchKernelGGL(k_d3_pair, grid, block, 0, s, a);
+        if (tri) hipLaunchKernelGGL(k_d3_pair<true>, grid, block, 0, s, a);
+        else hipLaunchKernelGGL(k_d3_pair<false>, grid, block, 0, s, a);
     }
     {
         ProfScope ps_(K_D3_CNFORCE, s);
-        hipLaunchKernelGGL(k_d3_cnforce, grid, block, 0, s, a);
+        if (tri) hipLaunchKernelGGL(k_d3_cnforce<true>, grid, block, 0, s, a);
+        else hipLaunchKernelGGL(k_d3_cnforce<false>, grid, block, 0, s, a);
     }
     {
         ProfScope ps_(K_D3_REDUCE, s);
