@@ -383,6 +383,16 @@ int32_t nep_autotune(const nep_model *model, nep_nlist *nl, nep_ws *ws, const do
  * clear != 0, reset them.  Returns NEP_ERR_NONFINITE if that bit is set. */
 int32_t nep_poll_flags(nep_ws *ws, uint32_t *flags, int32_t clear, hipStream_t stream);
 
+/* Defer the per-bead energy and virial sums (Sec. II.A virial, Sec. II.C
+ * total energy) of the next nep_compute / nep_compute_batched call on ws:
+ * that call writes forces (and the per-atom arrays) as usual but leaves E
+ * and W to the next trpmd_step_nep call given ws, which completes them
+ * inside its integrator launch (one launch fewer per MD step).  Until then
+ * E and W hold stale values.  Host state only: arms that one call, which
+ * disarms it; a later nep_compute on ws without a deferral drops sums left
+ * pending.  Errors: NEP_ERR_INVALID_ARG (null ws). */
+int32_t nep_ws_defer_reduce(nep_ws *ws);
+
 /* ------------------------------------------------------------------ */
 /* Ring polymer (Sec. II.A, Eqs. (3)-(12))                             */
 /* ------------------------------------------------------------------ */
@@ -439,6 +449,20 @@ int32_t trpmd_step(const pimd_ctx *ctx, double *pos, double *vel, const float *F
  * NEP_ERR_INVALID_ARG for a null counter or step_out == step_in. */
 int32_t trpmd_step_dev(const pimd_ctx *ctx, double *pos, double *vel, const float *F, const int64_t *step_in,
                        int64_t *step_out, int32_t stage, hipStream_t stream);
+
+/* One integrator stage (Eqs. (3)-(12), as trpmd_step: step_in = NULL uses
+ * the host step number `step`; otherwise as trpmd_step_dev with the device
+ * counters step_in / step_out and `step` ignored) that also completes the
+ * per-bead energy and virial sums left pending in ws by a deferred
+ * nep_compute (nep_ws_defer_reduce), in the same launch: extra workgroups
+ * of the stage, one wavefront per (system, bead, component), the same
+ * fixed-order sums as nep_compute's own, so E and W are bitwise the same.
+ * With nothing pending it is the plain stage.  Call it on the stream of
+ * that nep_compute, before anything else overwrites ws.  ws must have the
+ * context's P and N.  Errors as trpmd_step / trpmd_step_dev, and
+ * NEP_ERR_INVALID_ARG for a null ws or mismatched sizes. */
+int32_t trpmd_step_nep(const pimd_ctx *ctx, double *pos, double *vel, const float *F, int64_t step,
+                       const int64_t *step_in, int64_t *step_out, int32_t stage, nep_ws *ws, hipStream_t stream);
 
 /* ------------------------------------------------------------------ */
 /* Observables and pressure control (Sec. II.A, Sec. II.D)             */

@@ -164,6 +164,17 @@ struct nep_nlist {
                                   // [6] max angular candidates
 };
 
+// Per-(system, bead) energy and virial sums over the force kernels'
+// per-workgroup partials: launched by nep_compute itself, or left pending by
+// a deferred call and carried out inside the next integrator launch.
+struct PendingReduce {
+    const double *partE = nullptr, *partWa = nullptr, *partWr = nullptr;
+    const int32_t *sys_tile0 = nullptr;
+    int P = 0, nblk = 0;
+    int nout = 0;              // outputs: systems x P x 10 (energy, 9 virial entries); 0 = nothing pending
+    double *E = nullptr, *W = nullptr;
+};
+
 struct nep_ws {
     int P = 0, N = 0, S = 0, nblk = 0;
     int device = 0;
@@ -187,6 +198,8 @@ struct nep_ws {
     double *partW = nullptr;   // angular pass [P][9][nblk], then radial pass [P][9][nblk] (room for nblk_cap)
     float *Fang = nullptr;     // [N][P][3] angular part of the forces
     uint32_t *flags = nullptr; // [1]
+    int defer_next = 0;        // the next nep_compute leaves its E/W sums pending (nep_ws_defer_reduce)
+    PendingReduce pending;     // sums of a deferred call, until an integrator launch completes them
 };
 
 struct pimd_ctx {
@@ -222,6 +235,34 @@ __device__ __forceinline__ void bead_tile(int &bead, int &tile)
     if ((total & 7) == 0) lin = (lin & 7) * (total >> 3) + (lin >> 3);
     bead = lin / nt;
     tile = lin - bead * nt;
+}
+
+// Output o of a pending reduction, o = (system * P + bead) * 10 + c (c = 0
+// energy, 1..9 virial), on one wavefront (lane t): lane t adds the system's
+// workgroup partials t, t + 64, ... in order (four loads in flight), then a
+// fixed butterfly over the lanes, so the result is bitwise reproducible
+// whichever launch carries it.
+__device__ __forceinline__ void reduce_output(const PendingReduce &r, int o, int t)
+{
+    const int sb = o / 10, c = o - sb * 10, sy = sb / r.P, b = sb - sy * r.P;
+    const int k0 = r.sys_tile0[sy], k1 = r.sys_tile0[sy + 1];
+    const double *pa = c == 0 ? r.partE + (size_t)b * r.nblk : r.partWa + ((size_t)b * 9 + (c - 1)) * r.nblk;
+    const double *pr = c == 0 ? nullptr : r.partWr + ((size_t)b * 9 + (c - 1)) * r.nblk;
+    double acc = 0.0;
+    int k = k0 + t;
+    for (; k + 192 < k1; k += 256) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = pa[k + 64 * u] + (pr ? pr[k + 64 * u] : 0.0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc += v[u];
+    }
+    for (; k < k1; k += 64) acc += pa[k] + (pr ? pr[k] : 0.0);
+    for (int s = 32; s > 0; s >>= 1) acc += __shfl_xor(acc, s);
+    if (t == 0) {
+        if (c == 0) r.E[sb] = acc;
+        else r.W[(size_t)sb * 9 + (c - 1)] = acc;
+    }
 }
 
 // Orthorhombic edge lengths from a row-vector cell; false if not orthorhombic.

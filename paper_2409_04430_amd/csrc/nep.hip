@@ -1002,33 +1002,11 @@ __global__ __launch_bounds__(kBlock) void k_force_rad(NepArgs a)
 
 // Per-(system, bead) energy and virial from the per-workgroup partial sums
 // of the system's tiles, stored [P][nblk] (energy) and [P][9][nblk] (virial
-// parts).  One wavefront per (system, bead, component): lane t adds tiles
-// t, t + 64, ... in order (four loads in flight), then a fixed butterfly
-// over the lanes, so the result is bitwise reproducible.  Component 0 is E,
-// 1..9 the virial.
-__global__ __launch_bounds__(64) void k_reduce(const double *__restrict__ partE, const double *__restrict__ partWa,
-                                               const double *__restrict__ partWr, const int32_t *__restrict__ sys_tile0,
-                                               int P, int nblk, double *__restrict__ E, double *__restrict__ W)
+// parts): one wavefront per (system, bead, component), in the fixed order of
+// reduce_output.
+__global__ __launch_bounds__(64) void k_reduce(PendingReduce r)
 {
-    const int sb = blockIdx.x, sy = sb / P, b = sb - sy * P, t = threadIdx.x, c = blockIdx.y;
-    const int k0 = sys_tile0[sy], k1 = sys_tile0[sy + 1];
-    const double *pa = c == 0 ? partE + (size_t)b * nblk : partWa + ((size_t)b * 9 + (c - 1)) * nblk;
-    const double *pr = c == 0 ? nullptr : partWr + ((size_t)b * 9 + (c - 1)) * nblk;
-    double acc = 0.0;
-    int k = k0 + t;
-    for (; k + 192 < k1; k += 256) {
-        double v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = pa[k + 64 * u] + (pr ? pr[k + 64 * u] : 0.0);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc += v[u];
-    }
-    for (; k < k1; k += 64) acc += pa[k] + (pr ? pr[k] : 0.0);
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-    if (t == 0) {
-        if (c == 0) E[sb] = acc;
-        else W[(size_t)sb * 9 + (c - 1)] = acc;
-    }
+    reduce_output(r, blockIdx.x, threadIdx.x);
 }
 
 constexpr size_t kNetLdsMax = 60 * 1024;   // bytes of LDS for the staged network weights
@@ -1089,6 +1067,10 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
     if (nl->P != P || nl->N != N || ws->P != P || ws->N != N || nl->S != m->hp.n_species || ws->S != m->hp.n_species ||
         ws->NA1 != m->hp.n_max_angular + 1 || nl->off != ws->off)
         return fail(NEP_ERR_INVALID_ARG, "nep_compute: P=%d N=%d do not match the list/workspace handles", P, N);
+    // a deferral applies to this call only; a new call drops sums left pending
+    const bool defer = ws->defer_next != 0;
+    ws->defer_next = 0;
+    ws->pending = PendingReduce{};
     if (P == 0) return NEP_OK;
     if (!E || !W) return fail(NEP_ERR_INVALID_ARG, "nep_compute: null E or W");
     const int nsys = nl->nsys;
@@ -1138,10 +1120,14 @@ extern "C" int32_t nep_compute_batched(const nep_model *m, nep_nlist *nl, nep_ws
     case 881: launch<9, 9, true>(a, m->dev, ws->nblk, ws->wpb, tri, mlp, !ws->net_global, s); break;
     default: return fail(NEP_ERR_UNSUPPORTED, "nep_compute: unsupported model shape");
     }
-    {
+    PendingReduce r;
+    r.partE = ws->partE; r.partWa = a.partWa; r.partWr = a.partWr; r.sys_tile0 = ws->sys_tile0;
+    r.P = P; r.nblk = ws->nblk; r.nout = nsys * P * 10; r.E = E; r.W = W;
+    if (defer) {   // completed by the next integrator launch (trpmd_step_nep)
+        ws->pending = r;
+    } else {
         ProfScope ps_(K_REDUCE, s);
-        hipLaunchKernelGGL(k_reduce, dim3(nsys * P, 10), dim3(64), 0, s, ws->partE, a.partWa, a.partWr, ws->sys_tile0,
-                           P, ws->nblk, E, W);
+        hipLaunchKernelGGL(k_reduce, dim3(r.nout), dim3(64), 0, s, r);
     }
     NEP_HIP(hipGetLastError());
     return NEP_OK;
@@ -1153,6 +1139,13 @@ extern "C" int32_t nep_compute(const nep_model *m, nep_nlist *nl, nep_ws *ws, co
 {
     if (nl && nl->nsys != 1) return fail(NEP_ERR_INVALID_ARG, "nep_compute: the list holds a batch of systems");
     return nep_compute_batched(m, nl, ws, pos, box, types, P, N, E, F, W, E_atom, W_atom, s);
+}
+
+extern "C" int32_t nep_ws_defer_reduce(nep_ws *ws)
+{
+    if (!ws) return fail(NEP_ERR_INVALID_ARG, "nep_ws_defer_reduce: null workspace");
+    ws->defer_next = 1;
+    return NEP_OK;
 }
 
 extern "C" int32_t nep_autotune(const nep_model *m, nep_nlist *nl, nep_ws *ws, const double *pos, const double *boxes,

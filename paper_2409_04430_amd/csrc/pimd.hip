@@ -122,7 +122,15 @@ struct StepArgs {
     const int64_t *step_dev;   // if set, the step number is read from device memory
     int64_t *step_out;         // if set (device counter mode), step + 1 is written there by a closing stage
     int stage, noise;
+    PendingReduce red;         // energy/virial sums completed by this launch (red.nout = 0: none)
+    int int_blocks = 0;        // workgroups of the integrator proper; later ones carry the sums
 };
+
+// The pending sums on their own launch (integrator forms without the fold).
+__global__ __launch_bounds__(64) void k_reduce_pending(PendingReduce r)
+{
+    reduce_output(r, blockIdx.x, threadIdx.x);
+}
 
 // One workgroup holds floor(512 / P) (atom, component) elements; lane
 // (element, k) works on normal mode k of its element (and bead k for the
@@ -265,6 +273,13 @@ __global__ __launch_bounds__(64 * 8) void k_trpmd_mf(StepArgs a, const double *_
     __shared__ double xt[ET][2][P][16];        // new mode vectors v~, q~ of each element tile
     __shared__ double zn[NT][2][16][16];       // thermostat normals [tile][draw][mode in tile][element]
     __shared__ f64x4 part[NT][3][64];          // the second half's partial tiles (forward v, f, q; back v, q)
+    if ((int)blockIdx.x >= a.int_blocks) {
+        // workgroups past the integrator's: one wavefront per output of the
+        // pending energy/virial sums (independent of the stage's data)
+        const int o = ((int)blockIdx.x - a.int_blocks) * ((int)blockDim.x >> 6) + ((int)threadIdx.x >> 6);
+        if (o < a.red.nout) reduce_output(a.red, o, threadIdx.x & 63);
+        return;
+    }
     const PimdLayout Lo(P);
     const int M = 3 * a.N;
     const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lg = l >> 4;
@@ -560,19 +575,23 @@ __global__ __launch_bounds__(256) void k_modes(const double *__restrict__ in, do
     }
 }
 
-static void launch_step(const StepArgs &a, const double *cst, hipStream_t s)
+static void launch_step(StepArgs a, const double *cst, hipStream_t s)
 {
     ProfScope ps_(K_TRPMD, s);
 #define NEP_STEP_MF(PP)                                                                                     \
-    case PP:                                                                                                \
-        hipLaunchKernelGGL(k_trpmd_mf<PP>, dim3(div_up(3 * a.N, 16 * step_mf_et<PP>())),                    \
-                           dim3(64 * step_mf_et<PP>() * (PP / 16) * kStepHalves), 0, s, a, cst);            \
-        return;
+    case PP: {                                                                                              \
+        constexpr int waves = step_mf_et<PP>() * (PP / 16) * kStepHalves;                                  \
+        a.int_blocks = div_up(3 * a.N, 16 * step_mf_et<PP>());                                             \
+        const int extra = div_up(a.red.nout, waves);                                                       \
+        hipLaunchKernelGGL(k_trpmd_mf<PP>, dim3(a.int_blocks + extra), dim3(64 * waves), 0, s, a, cst);    \
+        return;                                                                                             \
+    }
     switch (a.P) {   // matrix-core transforms where P is a multiple of 16
         NEP_STEP_MF(16) NEP_STEP_MF(32) NEP_STEP_MF(48) NEP_STEP_MF(64)
     default: break;
     }
 #undef NEP_STEP_MF
+    if (a.red.nout > 0) hipLaunchKernelGGL(k_reduce_pending, dim3(a.red.nout), dim3(64), 0, s, a.red);
     const int EPB = kStepBlock / a.P;
     const size_t lds = sizeof(double) * ((size_t)a.P * a.P + 3 * (size_t)EPB * a.P);
     hipLaunchKernelGGL(k_trpmd, dim3(div_up(3 * a.N, EPB)), dim3(kStepBlock), lds, s, a, cst);
@@ -688,7 +707,8 @@ extern "C" int32_t rp_normal_modes(const pimd_ctx *c, int32_t dir, const double 
 }
 
 static int32_t step_common(const pimd_ctx *c, double *pos, double *vel, const float *F, int64_t step,
-                           const int64_t *step_dev, int64_t *step_out, int32_t stage, hipStream_t s)
+                           const int64_t *step_dev, int64_t *step_out, int32_t stage, hipStream_t s,
+                           nep_ws *ws = nullptr)
 {
     if (!c) return fail(NEP_ERR_INVALID_ARG, "trpmd_step: null context");
     if (stage < PIMD_STAGE_PRE || stage > PIMD_STAGE_FUSED) return fail(NEP_ERR_INVALID_ARG, "trpmd_step: bad stage");
@@ -707,6 +727,10 @@ static int32_t step_common(const pimd_ctx *c, double *pos, double *vel, const fl
     a.stage = stage;
     a.noise = c->prm.mode != PIMD_MODE_RPMD && !(c->prm.mode == PIMD_MODE_TRPMD && c->P == 1);
     if (c->P < 1 || c->P > kMaxBeads) return fail(NEP_ERR_UNSUPPORTED, "trpmd_step: P=%d", c->P);
+    if (ws) {   // the sums are taken once, by this launch
+        a.red = ws->pending;
+        ws->pending = PendingReduce{};
+    }
     launch_step(a, c->consts, s);
     NEP_HIP(hipGetLastError());
     return NEP_OK;
@@ -725,6 +749,19 @@ extern "C" int32_t trpmd_step_dev(const pimd_ctx *c, double *pos, double *vel, c
     if (stage != PIMD_STAGE_PRE && (!step_out || step_out == step_in))
         return fail(NEP_ERR_INVALID_ARG, "trpmd_step_dev: a closing stage needs an output counter other than the input");
     return step_common(c, pos, vel, F, 0, step_in, stage == PIMD_STAGE_PRE ? nullptr : step_out, stage, s);
+}
+
+extern "C" int32_t trpmd_step_nep(const pimd_ctx *c, double *pos, double *vel, const float *F, int64_t step,
+                                  const int64_t *step_in, int64_t *step_out, int32_t stage, nep_ws *ws, hipStream_t s)
+{
+    if (!c || !ws) return fail(NEP_ERR_INVALID_ARG, "trpmd_step_nep: null context or workspace");
+    if (ws->pending.nout > 0 && (ws->P != c->P || ws->N != c->N))
+        return fail(NEP_ERR_INVALID_ARG, "trpmd_step_nep: workspace P=%d N=%d, integrator P=%d N=%d", ws->P, ws->N,
+                    c->P, c->N);
+    if (!step_in) return step_common(c, pos, vel, F, step, nullptr, nullptr, stage, s, ws);
+    if (stage != PIMD_STAGE_PRE && (!step_out || step_out == step_in))
+        return fail(NEP_ERR_INVALID_ARG, "trpmd_step_nep: a closing stage needs an output counter other than the input");
+    return step_common(c, pos, vel, F, 0, step_in, stage == PIMD_STAGE_PRE ? nullptr : step_out, stage, s, ws);
 }
 
 extern "C" int32_t pimd_observables(const pimd_ctx *c, const double *pos, const float *F, const double *W_bead,

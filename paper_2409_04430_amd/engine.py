@@ -207,10 +207,19 @@ class NepPimd:
         nl.build(self.pos, self.box, self.types)
         return nl
 
-    def forces(self):
+    def _fold(self) -> bool:
+        """Whether a step may leave the per-bead E/W sums to its integrator
+        launch: nothing reads E or W between the forces and the stage (no D3
+        term accumulating into them, no force hook, no observables)."""
+        return self.d3 is None and self.on_forces is None and not self._split()
+
+    def forces(self, defer: bool = False):
         """Neighbour lists + NEP energy, forces and virial at the current positions
-        (plus the D3 dispersion term when the engine has one)."""
+        (plus the D3 dispersion term when the engine has one).  defer: E and W
+        are completed by the next `pimd.step_nep` with this workspace."""
         self.nl.build(self.pos, self.box, self.types)
+        if defer:
+            self.ws.defer_reduce()
         self.ws.compute(self.nl, self.pos, self.box, self.types, self.E, self.F, self.W, self.E_atom, self.W_atom)
         if self.d3 is not None:
             self.d3_nl.build(self.pos, self.box, self.types)
@@ -357,7 +366,8 @@ class NepPimd:
         self._finished = False
         if not self.started:
             self.start()
-        self.forces()
+        fold = self._fold()
+        self.forces(defer=fold)
         n = self.step_no
         if self.on_forces is not None:
             self.on_forces(n)
@@ -366,6 +376,8 @@ class NepPimd:
             self.pimd.step(self.pos, self.vel, self.F, n, lib.POST)
             self._after_post(n)
             self.pimd.step(self.pos, self.vel, self.F, n + 1, lib.PRE)
+        elif fold:   # the E/W sums ride in the integrator launch
+            self.pimd.step_nep(self.pos, self.vel, self.F, n, lib.FUSED, self.ws)
         else:
             self.pimd.step(self.pos, self.vel, self.F, n, lib.FUSED)
         self.step_no += 1
@@ -416,10 +428,14 @@ class NepPimd:
         c = (self.step_dev[0:1], self.step_dev[1:2])
         t.cuda.synchronize()
         g = t.cuda.CUDAGraph()
+        fold = self._fold()
         with t.cuda.graph(g):
             for k in range(steps):
-                self.forces()
-                self.pimd.step_dev(self.pos, self.vel, self.F, c[k % 2], c[(k + 1) % 2], lib.FUSED)
+                self.forces(defer=fold)
+                if fold:
+                    self.pimd.step_nep(self.pos, self.vel, self.F, 0, lib.FUSED, self.ws, c[k % 2], c[(k + 1) % 2])
+                else:
+                    self.pimd.step_dev(self.pos, self.vel, self.F, c[k % 2], c[(k + 1) % 2], lib.FUSED)
         t.cuda.synchronize()
         # capture does not execute: the counters and the state are unchanged
         self.graph = g

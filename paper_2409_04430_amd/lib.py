@@ -101,11 +101,13 @@ _sig = {
     "nep_compute": (_i32, [_vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
                            _vp]),
     "nep_poll_flags": (_i32, [_vp, C.POINTER(C.c_uint32), _i32, _vp]),
+    "nep_ws_defer_reduce": (_i32, [_vp]),
     "pimd_create": (_i32, [_i32, _i32, C.POINTER(PimdParams), _vp, C.POINTER(_vp)]),
     "pimd_destroy": (None, [_vp]),
     "rp_normal_modes": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "trpmd_step": (_i32, [_vp, _vp, _vp, _vp, C.c_int64, _i32, _vp]),
     "trpmd_step_dev": (_i32, [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp]),
+    "trpmd_step_nep": (_i32, [_vp, _vp, _vp, _vp, C.c_int64, _vp, _vp, _i32, _vp, _vp]),
     "pimd_observables": (_i32, [_vp, _vp, _vp, _vp, _vp, C.POINTER(C.c_double), _vp, _vp]),
     "pimd_berendsen": (_i32, [_vp, _vp, _vp, C.POINTER(PimdBarostat), _vp, _vp]),
     "pimd_centroid": (_i32, [_vp, _vp, _vp, _vp]),
@@ -491,6 +493,10 @@ class Workspace:
         times = {(w, st): ms[2 * c + st] for c, w in enumerate((1, 2, 4)) for st in (0, 1) if ms[2 * c + st] >= 0.0}
         return best[0], best[1], times
 
+    def defer_reduce(self):
+        """nep_ws_defer_reduce: the next compute leaves E and W to Pimd.step_nep."""
+        _check(_lib.nep_ws_defer_reduce(self._h))
+
     def poll(self, clear: bool = True) -> int:
         f = C.c_uint32()
         rc = _lib.nep_poll_flags(self._h, C.byref(f), int(clear), _stream())
@@ -539,6 +545,17 @@ class Pimd:
         _check(_lib.trpmd_step_dev(self._h, _ptr(pos, t.float64, shp, "pos"), _ptr(vel, t.float64, shp, "vel"),
                                    _ptr(F, t.float32, shp, "F"), _ptr(step_in, t.int64, (1,), "step_in"),
                                    _ptr(step_out, t.int64, (1,), "step_out"), int(stage), _stream()))
+
+    def step_nep(self, pos, vel, F, step: int, stage: int, ws: "Workspace", step_in=None, step_out=None):
+        """trpmd_step_nep: the stage (host step number, or the device counters
+        step_in / step_out as in step_dev) plus the energy/virial sums that a
+        deferred Workspace.compute left pending in ws, in one launch."""
+        t = _torch()
+        shp = (self.P, self.N, 3)
+        si = _ptr(step_in, t.int64, (1,), "step_in") if step_in is not None else None
+        so = _ptr(step_out, t.int64, (1,), "step_out") if step_out is not None else None
+        _check(_lib.trpmd_step_nep(self._h, _ptr(pos, t.float64, shp, "pos"), _ptr(vel, t.float64, shp, "vel"),
+                                   _ptr(F, t.float32, shp, "F"), int(step), si, so, int(stage), ws._h, _stream()))
 
     def observables(self, pos, F, W, E, box, out):
         """pimd_observables: out [OBS_COUNT] float64 device tensor, written on the stream."""
