@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--no-triclinic", action="store_true", help="skip the general-cell leg")
     ap.add_argument("--no-full-run", action="store_true", help="skip the configured-length run record")
     ap.add_argument("--no-legs", action="store_true", help="skip the legs of the other configurations")
+    ap.add_argument("--legs", default="fcc108,water16,porous13824,porous13824_nep_d3",
+                    help="comma-separated legs to run (of fcc108, water16, porous13824, porous13824_nep_d3)")
     ap.add_argument("--npt-steps", type=int, default=50, help="timed steps of the NPT leg")
     ap.add_argument("--student-only", action="store_true",
                     help="run only the learned-student leg (prints its JSON object)")
@@ -786,9 +788,12 @@ def main():
         cpu = cpu_baseline(w, model_path, s, args.cpu_beads)
     legs = {}
     if not args.no_legs:
+        wanted = {x.strip() for x in args.legs.split(",") if x.strip()}
         for name, st in (("fcc108", 100), ("water16", 50), ("porous13824", 20)):
-            legs[name] = workload_leg(args, torch, lib, configs, I, NepPimd, name, st, graph=True)
-        legs["porous13824_nep_d3"] = d3_leg(args, torch, lib, configs, I, NepPimd, 20)
+            if name in wanted:
+                legs[name] = workload_leg(args, torch, lib, configs, I, NepPimd, name, st, graph=True)
+        if "porous13824_nep_d3" in wanted:
+            legs["porous13824_nep_d3"] = d3_leg(args, torch, lib, configs, I, NepPimd, 20)
     npt = None
     if not args.no_npt:
         npt = npt_leg(args, torch, lib, w, model_path, s, NepPimd, ms)
