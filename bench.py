@@ -82,6 +82,11 @@ KERNEL_SOURCES = {"descriptor": "nep.hip", "force_ang": "nep.hip", "force": "nep
                   "nlist": "nlist.hip", "centroid": "nlist.hip", "candidates": "nlist.hip", "trpmd": "pimd.hip"}
 
 
+def note(msg: str):
+    """A progress line on stderr (the result stays the one JSON line on stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_hash(kernel: str) -> str:
     """Hash of a kernel's .hip file, every header it includes (transitively)
     and the build script that sets the compiler flags."""
@@ -782,26 +787,33 @@ def main():
                    "vs_timed": round(oms / ms, 4)}
     del eng
 
+    note(f"timed region done: {ms:.4f} ms per step")
     full = None if args.no_full_run else full_run_leg(torch, lib, w, model_path, s, NepPimd, args.mlp)
     cpu = None
     if not args.no_cpu_baseline:
+        note("oracle CPU baseline")
         cpu = cpu_baseline(w, model_path, s, args.cpu_beads)
     legs = {}
     if not args.no_legs:
         wanted = {x.strip() for x in args.legs.split(",") if x.strip()}
         for name, st in (("fcc108", 100), ("water16", 50), ("porous13824", 20)):
             if name in wanted:
+                note(f"leg {name}")
                 legs[name] = workload_leg(args, torch, lib, configs, I, NepPimd, name, st, graph=True)
         if "porous13824_nep_d3" in wanted:
+            note("leg porous13824_nep_d3")
             legs["porous13824_nep_d3"] = d3_leg(args, torch, lib, configs, I, NepPimd, 20)
     npt = None
     if not args.no_npt:
+        note("NPT leg")
         npt = npt_leg(args, torch, lib, w, model_path, s, NepPimd, ms)
     tri = None
     if not args.no_triclinic:
+        note("general-cell leg")
         tri = triclinic_leg(args, torch, lib, w, model_path, s, NepPimd, ms)
     stu = None
     if not args.no_student:
+        note("student leg")
         stu = student_leg(args, torch, lib, configs, I)
 
     out = {
