@@ -660,7 +660,7 @@ constexpr double kShellEps = 1e-3;   // A; far above the rounding of d and s
 constexpr int kUnionRounds = 4;      // shell rounds whose partner loads are in flight together
 
 template <bool TRI>
-__global__ __launch_bounds__(256) void k_union(const double *__restrict__ pos, const float4 *__restrict__ pos4,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TRI ? 4 : 5))) void k_union(const double *__restrict__ pos, const float4 *__restrict__ pos4,
                                                const double *__restrict__ cen, const float *__restrict__ spr, int P,
                                                int N, int S, int lg, const int32_t *__restrict__ atom_sys,
                                                const SysGeom *__restrict__ geom, CutTest cR, CutTest cA,
