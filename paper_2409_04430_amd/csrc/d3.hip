@@ -229,7 +229,7 @@ __global__ __launch_bounds__(256) void k_d3_cn(D3Args a)
 // ------------------------------------------- dispersion pairs, dE/dCN ---
 
 template <bool TRI>
-__global__ __launch_bounds__(256) void k_d3_pair(D3Args a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_d3_pair(D3Args a)
 {
     __shared__ double t[kTab];
     __shared__ double lds[256];
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(256) void k_d3_pair(D3Args a)
 // ------------------------------------ forces through the coordination ---
 
 template <bool TRI>
-__global__ __launch_bounds__(256) void k_d3_cnforce(D3Args a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_d3_cnforce(D3Args a)
 {
     __shared__ double t[kTab];
     __shared__ double lds[256];
