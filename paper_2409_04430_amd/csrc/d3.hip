@@ -61,6 +61,7 @@ struct D3Args {
     const double *posT;   // [N][P][3] FP64 positions, bead-minor
     const int32_t *types;
     int N, P, lg, S;
+    int lgc;                     // dispersion pass: 2^lgc lanes per atom, one bead chunk each
     const SysGeom *geom;
     const int32_t *candA, *uniR, *uendR, *uniA, *uendA;
     const uint64_t *umR, *umA;
@@ -74,20 +75,14 @@ struct D3Args {
     int accumulate;
 };
 
-// (atom, bead) of this lane: 2^lg lanes per atom, 256 >> lg atoms per
-// workgroup.  Workgroups go to the 8 XCDs round-robin; when their number is
-// a multiple of 8 the atom blocks are permuted so that each XCD works through
-// one contiguous run of atoms, whose partners (neighbouring atom indices)
-// then stay in that XCD's L2 (XCD = true: the dispersion pass, whose 12 A
-// partner data is the largest; the 6 A passes measured slower with it).
-template <bool XCD = false>
+// (atom, bead) of this lane in the coordination passes: 2^lg lanes per
+// atom, 256 >> lg atoms per workgroup, in launch order (a permutation that
+// gives each XCD one contiguous run of atoms measured slower in these
+// passes).
 __device__ __forceinline__ bool d3_lane(const D3Args &a, int &i, int &b)
 {
     const int G = 1 << a.lg;
-    const int nb = gridDim.x;
-    int blk = blockIdx.x;
-    if (XCD && (nb & 7) == 0) blk = (blk & 7) * (nb >> 3) + (blk >> 3);
-    i = blk * (256 >> a.lg) + ((int)threadIdx.x >> a.lg);
+    i = blockIdx.x * (256 >> a.lg) + ((int)threadIdx.x >> a.lg);
     b = threadIdx.x & (G - 1);
     const bool ok = i < a.N && b < a.P;
     i = i < a.N ? i : a.N - 1;
@@ -166,6 +161,48 @@ __device__ __forceinline__ void ref_weights(const double *t, int ty, double cn, 
     }
 }
 
+// Lanes of the dispersion pass: 2^lgc <= 16 lanes per atom take one chunk
+// of 2^lgc beads, grid (atom blocks, bead chunks), so that the partner data
+// a workgroup gathers (positions and weights of its chunk of beads) is a
+// quarter of a 64-bead atom's and the run of atoms an XCD works through at
+// once keeps its partners in that XCD's L2.  Workgroups go to the 8 XCDs
+// round-robin; when their number is a multiple of 8 the linear workgroup id
+// (bead chunk slowest) is permuted so that each XCD works through one
+// contiguous run of it, i.e. a run of neighbouring atoms (whose partners
+// are nearby atom indices) for one bead chunk.  Returns the atom block in
+// blk and the chunk's first bead in b0.
+__device__ __forceinline__ bool d3_chunk_lane(const D3Args &a, int &i, int &b, int &blk, int &b0)
+{
+    const int Gc = 1 << a.lgc, nb = gridDim.x, total = nb * gridDim.y;
+    int lin = blockIdx.y * nb + blockIdx.x;
+    if ((total & 7) == 0) lin = (lin & 7) * (total >> 3) + (lin >> 3);
+    const int chunk = lin / nb;
+    blk = lin - chunk * nb;
+    b0 = chunk * Gc;
+    i = blk * (256 >> a.lgc) + ((int)threadIdx.x >> a.lgc);
+    b = b0 + ((int)threadIdx.x & (Gc - 1));
+    const bool ok = i < a.N && b < a.P;
+    i = i < a.N ? i : a.N - 1;
+    b = b < a.P ? b : a.P - 1;
+    return ok;
+}
+
+// Per-bead sums over a workgroup of the chunked pass: lane t < 2^lgc adds
+// lanes t, t + 2^lgc, ... in order and writes bead b0 + t at out[bead * stride].
+__device__ __forceinline__ void chunk_block_sum(double v, double *lds, int lgc, int b0, int P, double *out,
+                                                int stride)
+{
+    lds[threadIdx.x] = v;
+    __syncthreads();
+    const int t = threadIdx.x, Gc = 1 << lgc;
+    if (t < Gc && b0 + t < P) {
+        double s = 0.0;
+        for (int x = t; x < (int)blockDim.x; x += Gc) s += lds[x];
+        out[(size_t)(b0 + t) * stride] = s;
+    }
+    __syncthreads();
+}
+
 // ------------------------------------------------ coordination numbers ---
 
 template <bool TRI>
@@ -234,8 +271,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     __shared__ double t[kTab];
     __shared__ double lds[256];
     load_tab(a, t);
-    int i, b;
-    const bool ok = d3_lane<true>(a, i, b);
+    int i, b, blk, bc0;
+    const bool ok = d3_chunk_lane(a, i, b, blk, bc0);
     const SysGeom &g = a.geom[0];
     const int P = a.P, S = a.S, ti = a.types[i] & 3;
     const double *ri = a.posT + ((size_t)i * P + b) * 3;
@@ -345,11 +382,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         fo[1] = fy;
         fo[2] = fz;
     }
-    const int nblk = gridDim.x;
-    bead_block_sum(ok ? U : 0.0, lds, P, a.lg, a.partE + blockIdx.x, nblk);
+    const int nblk = gridDim.x;   // atom blocks of this pass
+    chunk_block_sum(ok ? U : 0.0, lds, a.lgc, bc0, P, a.partE + blk, nblk);
     const int comp[9] = {0, 3, 4, 3, 1, 5, 4, 5, 2};
     for (int c = 0; c < 9; ++c)
-        bead_block_sum(ok ? Wv[comp[c]] : 0.0, lds, P, a.lg, a.partW0 + (size_t)c * nblk + blockIdx.x, 9 * nblk);
+        chunk_block_sum(ok ? Wv[comp[c]] : 0.0, lds, a.lgc, bc0, P, a.partW0 + (size_t)c * nblk + blk, 9 * nblk);
 }
 
 // ------------------------------------ forces through the coordination ---
@@ -440,17 +477,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 // One workgroup per (bead, component c): c = 0 energy, 1..9 virial; partial
 // sums added in a fixed order.
 __global__ __launch_bounds__(256) void k_d3_reduce(const double *__restrict__ partE, const double *__restrict__ partW0,
-                                                   const double *__restrict__ partW1, int nblk, int accumulate,
+                                                   const double *__restrict__ partW1, int nblk0, int nblk, int accumulate,
                                                    double *__restrict__ E, double *__restrict__ W)
 {
     __shared__ double red[256];
     const int b = blockIdx.x, c = blockIdx.y, t = threadIdx.x;
     double acc = 0.0;
     if (c == 0) {
-        for (int k = t; k < nblk; k += blockDim.x) acc += partE[(size_t)b * nblk + k];
+        for (int k = t; k < nblk0; k += blockDim.x) acc += partE[(size_t)b * nblk0 + k];
     } else {
-        const size_t o = ((size_t)b * 9 + (c - 1)) * nblk;
-        for (int k = t; k < nblk; k += blockDim.x) acc += partW0[o + k] + partW1[o + k];
+        // the dispersion pass's partials (nblk0 atom blocks), then the coordination pass's (nblk)
+        const size_t o0 = ((size_t)b * 9 + (c - 1)) * nblk0, o = ((size_t)b * 9 + (c - 1)) * nblk;
+        for (int k = t; k < nblk0; k += blockDim.x) acc += partW0[o0 + k];
+        for (int k = t; k < nblk; k += blockDim.x) acc += partW1[o + k];
     }
     red[t] = acc;
     __syncthreads();
@@ -480,6 +519,7 @@ struct nep_d3 {
 
 struct nep_d3_ws {
     int P = 0, N = 0, nblk = 0, lg = 0;
+    int lgc = 0, nblkc = 0, nchunk = 1;           // the dispersion pass's lanes per atom, atom blocks, bead chunks
     int device = 0;
     double *posT = nullptr;                      // [N][P][3] bead-minor positions
     double *wts = nullptr;                       // [5][N][P] normalised reference weights of each (atom, bead)
@@ -601,6 +641,9 @@ extern "C" int32_t nep_d3_ws_create(const nep_d3 *d, int32_t P, int32_t N, nep_d
     w->N = N;
     w->lg = lanes_log2(P > 0 ? P : 1);
     w->nblk = div_up(N > 0 ? N : 1, 256 >> w->lg);
+    w->lgc = w->lg < 4 ? w->lg : 4;
+    w->nblkc = div_up(N > 0 ? N : 1, 256 >> w->lgc);
+    w->nchunk = div_up(P > 0 ? P : 1, 1 << w->lgc);
     const size_t PN = (size_t)(P > 0 ? P : 1) * (N > 0 ? N : 1), Pp = P > 0 ? P : 1;
     hipError_t e = hipGetDevice(&w->device);
     if (e == hipSuccess) e = hipMalloc((void **)&w->posT, sizeof(double) * 3 * PN);
@@ -608,8 +651,8 @@ extern "C" int32_t nep_d3_ws_create(const nep_d3 *d, int32_t P, int32_t N, nep_d
     if (e == hipSuccess) e = hipMalloc((void **)&w->cn, sizeof(double) * PN);
     if (e == hipSuccess) e = hipMalloc((void **)&w->dedcn, sizeof(double) * PN);
     if (e == hipSuccess) e = hipMalloc((void **)&w->fdir, sizeof(double) * 3 * PN);
-    if (e == hipSuccess) e = hipMalloc((void **)&w->partE, sizeof(double) * Pp * w->nblk);
-    if (e == hipSuccess) e = hipMalloc((void **)&w->partW, sizeof(double) * 2 * 9 * Pp * w->nblk);
+    if (e == hipSuccess) e = hipMalloc((void **)&w->partE, sizeof(double) * Pp * w->nblkc);
+    if (e == hipSuccess) e = hipMalloc((void **)&w->partW, sizeof(double) * 9 * Pp * (w->nblkc + w->nblk));
     if (e != hipSuccess) {
         for (void *p : {(void *)w->posT, (void *)w->wts, (void *)w->cn, (void *)w->dedcn, (void *)w->fdir,
                         (void *)w->partE, (void *)w->partW})
@@ -660,14 +703,14 @@ extern "C" int32_t nep_d3_compute(const nep_d3 *d, nep_nlist *nl, nep_d3_ws *w, 
     D3Args a{};
     a.posT = w->posT;
     a.types = types;
-    a.N = N; a.P = P; a.lg = w->lg; a.S = d->S;
+    a.N = N; a.P = P; a.lg = w->lg; a.lgc = w->lgc; a.S = d->S;
     a.geom = nl->geom;
     a.candA = nl->candA; a.uniR = nl->uniR; a.uendR = nl->uendR; a.uniA = nl->uniA; a.uendA = nl->uendA;
     a.umR = nl->umR; a.umA = nl->umA; a.capR = nl->capR; a.capA = nl->capA;
     a.tab = d->dev;
     a.s6 = d->s6; a.s8 = d->s8; a.k1 = d->k1; a.k2 = d->k2; a.k3 = d->k3;
     a.cn = w->cn; a.dedcn = w->dedcn; a.fdir = w->fdir; a.wts = w->wts;
-    a.partE = w->partE; a.partW0 = w->partW; a.partW1 = w->partW + (size_t)9 * P * w->nblk;
+    a.partE = w->partE; a.partW0 = w->partW; a.partW1 = w->partW + (size_t)9 * P * w->nblkc;
     a.F = F;
     a.accumulate = accumulate ? 1 : 0;
     const dim3 grid(w->nblk), block(256);
@@ -681,8 +724,9 @@ extern "C" int32_t nep_d3_compute(const nep_d3 *d, nep_nlist *nl, nep_d3_ws *w, 
     }
     {
         ProfScope ps_(K_D3_PAIR, s);
-        if (tri) hipLaunchKernelGGL(k_d3_pair<true>, grid, block, 0, s, a);
-        else hipLaunchKernelGGL(k_d3_pair<false>, grid, block, 0, s, a);
+        const dim3 gc(w->nblkc, w->nchunk);
+        if (tri) hipLaunchKernelGGL(k_d3_pair<true>, gc, block, 0, s, a);
+        else hipLaunchKernelGGL(k_d3_pair<false>, gc, block, 0, s, a);
     }
     {
         ProfScope ps_(K_D3_CNFORCE, s);
@@ -692,7 +736,7 @@ extern "C" int32_t nep_d3_compute(const nep_d3 *d, nep_nlist *nl, nep_d3_ws *w, 
     {
         ProfScope ps_(K_D3_REDUCE, s);
         hipLaunchKernelGGL(k_d3_reduce, dim3(P, 10), dim3(256), 0, s, w->partE, w->partW,
-                           w->partW + (size_t)9 * P * w->nblk, w->nblk, a.accumulate, E, W);
+                           w->partW + (size_t)9 * P * w->nblkc, w->nblkc, w->nblk, a.accumulate, E, W);
     }
     NEP_HIP(hipGetLastError());
     return NEP_OK;
