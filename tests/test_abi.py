@@ -88,3 +88,11 @@ def test_pimd_rejects_bad_sizes(L):
     assert L._lib.pimd_create(4, 0, C.byref(bad), None, C.byref(out)) == 1
     assert "dt" in L.last_error()
     assert L._lib.trpmd_step(None, None, None, None, 0, 0, None) == 1
+
+
+def test_deferred_sums_entry_points_reject_null_handles(L):
+    """Host-side errors of the integrator-carried energy/virial sums (no GPU call)."""
+    assert L._lib.nep_ws_defer_reduce(None) == 1
+    assert "null workspace" in L.last_error()
+    assert L._lib.trpmd_step_nep(None, None, None, None, 0, None, None, 2, None, None) == 1
+    assert "null context or workspace" in L.last_error()
