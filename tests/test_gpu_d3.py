@@ -117,8 +117,21 @@ def test_d3_porous_p64(torch, L, orc, tmpdir_session):
     lists = got["nl"].to_host(got["tensors"][0], box, *got["nl"].caps)
     n = check_lists(orc, lists, pos, box, 12.0, 6.0, types=types, sample=sampled_pairs(64, pos.shape[1], 2048, 3))
     say(f"  {n} (bead, atom) lists checked")
-    ref = orc.D3(path).beads(pos[[0, 63]], types, box)
-    compare(ref, got, [0, 63], pos.shape[1], "porous")
+    # beads 0, 17, 40, 63: one from each 16-bead chunk of the dispersion pass
+    ref = orc.D3(path).beads(pos[[0, 17, 40, 63]], types, box)
+    compare(ref, got, [0, 17, 40, 63], pos.shape[1], "porous")
+
+
+def test_d3_ragged_bead_chunks(torch, L, orc, tmpdir_session):
+    """P = 20: the dispersion pass takes the beads in chunks of 16, so its
+    second chunk holds 4 beads and 12 idle lanes per atom; E/F/W of every
+    bead against the oracle (rocksalt, 1728 atoms)."""
+    path = d3_file(tmpdir_session, "d3_rag", 2, 13)
+    pos, types, box = displaced("rocksalt4096", 20, cells=6, seed=5)
+    say(f"[d3] rocksalt {pos.shape[1]} atoms x 20 beads")
+    got = gpu_d3(torch, L, path, pos, types, box)
+    ref = orc.D3(path).beads(pos, types, box)
+    compare(ref, got, range(20), pos.shape[1], "ragged")
 
 
 def test_nep_d3_accumulates_onto_nep(torch, L, orc, tmpdir_session):
